@@ -1,0 +1,491 @@
+"""Pins for the FP64 oracle: closed forms, published values, library routines,
+invariants.  None of these calls the GPU library.
+
+Each test fixes a part of the oracle against something other than the oracle
+itself, so that a dropped term, a wrong sign or index, or a transposed operand
+anywhere in it fails at least one of them.
+"""
+import math
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+from scipy import integrate, optimize, stats
+
+import oracle
+import phantoms
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+MEC2 = 510.99895
+R_E_CM = 2.8179403262e-13  # classical electron radius (CODATA 2018)
+
+
+def binom_z(k, n, p):
+    return (k - n * p) / math.sqrt(n * p * (1 - p))
+
+
+# ---------------------------------------------------------------------------
+# Philox4x32-10
+# ---------------------------------------------------------------------------
+
+def _kat():
+    rows = []
+    with open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(x, 16) for x in line.split()]
+            rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_known_answers():
+    rows = _kat()
+    assert len(rows) == 3
+    for ctr, key, out in rows:
+        assert list(oracle.philox(ctr, key)) == out
+
+
+_ROCRAND_SRC = r"""
+#include <rocrand/rocrand_kernel.h>
+#include <cstdio>
+int main() {
+    unsigned c0, c1, c2, c3, k0, k1;
+    while (std::scanf("%x %x %x %x %x %x", &c0, &c1, &c2, &c3, &k0, &k1) == 6) {
+        const unsigned long long seed = ((unsigned long long)k1 << 32) | k0;
+        const unsigned long long sub = ((unsigned long long)c3 << 32) | c2;
+        const unsigned long long off = ((unsigned long long)c1 << 32) | c0;
+        rocrand_device::philox4x32_10_engine e(seed, sub, off * 4ull);
+        uint4 r = e.next4();
+        std::printf("%08x %08x %08x %08x\n", r.x, r.y, r.z, r.w);
+    }
+    return 0;
+}
+"""
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
+def test_philox_matches_rocrand_host_engine():
+    """rocRAND's Philox4x32-10 engine, run on the host, as a library reference.
+    The engine's counter is (offset/4 in words 0-1, subsequence in words 2-3)."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    n = 256
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64)
+    ctr[:, 1] &= (1 << 30) - 1  # keep offset*4 inside 64 bits
+    key = rng.integers(0, 2**32, size=(n, 2), dtype=np.uint64)
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "ref.cpp")
+        exe = os.path.join(d, "ref")
+        with open(src, "w") as f:
+            f.write(_ROCRAND_SRC)
+        subprocess.check_call(["hipcc", "-O1", src, "-o", exe])
+        inp = "\n".join(" ".join("%x" % int(x) for x in list(ctr[i]) + list(key[i]))
+                        for i in range(n)) + "\n"
+        out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    ref = [[int(x, 16) for x in line.split()] for line in out.strip().splitlines()]
+    assert len(ref) == n
+    for i in range(n):
+        assert list(oracle.philox(ctr[i], key[i])) == ref[i]
+
+
+# ---------------------------------------------------------------------------
+# Uniform conversion: all 2^23 values
+# ---------------------------------------------------------------------------
+
+def test_uniform_all_values():
+    m = np.arange(1 << 23, dtype=np.uint32)
+    u = oracle.uniform_array(m << np.uint32(9))
+    assert u.min() > 0.0 and u.max() < 1.0
+    assert np.all(np.diff(u) > 0)                              # strictly increasing
+    assert np.array_equal(u.astype(np.float32).astype(np.float64), u)  # exact in FP32
+    np.testing.assert_array_equal(u + u[::-1], 1.0)            # symmetric about 1/2
+    assert u.sum() == (1 << 22)                                # mean exactly 1/2
+    # the low 9 bits are ignored
+    assert oracle.uniform(0x1FF) == oracle.uniform(0)
+
+
+# ---------------------------------------------------------------------------
+# Klein-Nishina
+# ---------------------------------------------------------------------------
+
+def kn_pdf_cos(c, k):
+    """Klein-Nishina dsigma/dOmega in units of r_e^2 (textbook form)."""
+    P = 1.0 / (1.0 + k * (1.0 - c))
+    return 0.5 * P * P * (P + 1.0 / P - (1.0 - c * c))
+
+
+@pytest.mark.parametrize("e", [20.0, 71.0, 126.0, 140.0, 154.0, 167.0, 511.0])
+def test_kn_total_matches_integral(e):
+    k = e / MEC2
+    num, _ = integrate.quad(kn_pdf_cos, -1.0, 1.0, args=(k,), epsabs=0, epsrel=1e-13)
+    # kn_total is in units of 2 pi r_e^2; the integral over cos is sigma / (2 pi r_e^2)
+    assert oracle.kn_total(e) == pytest.approx(num, rel=1e-10)
+
+
+def test_kn_total_140_in_barns():
+    sigma_b = oracle.kn_total(140.0) * 2 * math.pi * R_E_CM ** 2 / 1e-24
+    assert sigma_b == pytest.approx(0.4522955, abs=2e-6)
+    # low-energy (Thomson) limit: sigma/sigma_T = 1 - 2k + 26/5 k^2 - 133/10 k^3 + ...
+    k = 1.0 / MEC2
+    assert oracle.kn_total(1.0) == pytest.approx(4.0 / 3.0 * (1 - 2 * k + 5.2 * k * k),
+                                                 rel=20 * k ** 3)
+
+
+def test_attenuation_shape():
+    f = 1e-3
+    assert oracle.g_of_e(140.0, f) == pytest.approx(1.0, rel=1e-14)
+    assert oracle.p_pe(140.0, f) == pytest.approx(f, rel=1e-14)
+    # photoelectric share grows towards low energy, Compton share follows KN
+    assert oracle.p_pe(70.0, f) > oracle.p_pe(140.0, f)
+    ratio = oracle.g_of_e(126.0, 0.0)
+    assert ratio == pytest.approx(0.465338 / 0.452295, rel=2e-6)
+
+
+def _kahn_acceptance(k):
+    a1 = (1 + 2 * k) / (9 + 2 * k)
+    e1 = integrate.quad(lambda x: 4 * (1 / x - 1 / x ** 2), 1, 1 + 2 * k)[0] / (2 * k)
+    norm2 = 1 - 1 / (1 + 2 * k)
+
+    def f2(x):
+        c = 1 - (x - 1) / k
+        return 0.5 * (c * c + 1 / x) / x ** 2
+    e2 = integrate.quad(f2, 1, 1 + 2 * k)[0] / norm2
+    return a1 * e1 + (1 - a1) * e2
+
+
+def test_kahn_sampler_distribution():
+    e = 140.0
+    k = e / MEC2
+    n = 200_000
+    x, attempts = oracle.kahn_samples(e, n, seed=3)
+    assert np.all(np.isfinite(x))
+    assert np.all((x >= 1.0) & (x <= 1 + 2 * k))
+    # Compton relation E' = E / (1 + k (1 - cos)), so cos = 1 - (x - 1)/k
+    cos = 1.0 - (x - 1.0) / k
+    edges = np.linspace(-1, 1, 41)
+    total = integrate.quad(kn_pdf_cos, -1, 1, args=(k,))[0]
+    expected = np.array([integrate.quad(kn_pdf_cos, a, b, args=(k,))[0]
+                         for a, b in zip(edges[:-1], edges[1:])]) / total
+    counts, _ = np.histogram(cos, bins=edges)
+    chi2 = np.sum((counts - n * expected) ** 2 / (n * expected))
+    assert stats.chi2.sf(chi2, len(counts) - 1) > 1e-4
+    mean_c = integrate.quad(lambda c: c * kn_pdf_cos(c, k), -1, 1)[0] / total
+    assert mean_c == pytest.approx(0.149397, abs=2e-6)
+    sd = math.sqrt(integrate.quad(lambda c: c * c * kn_pdf_cos(c, k), -1, 1)[0] / total
+                   - mean_c ** 2)
+    assert abs(cos.mean() - mean_c) < 5 * sd / math.sqrt(n)
+    # P(E' >= 126 keV): scatter angle below the Compton edge of the window
+    c0 = 1 - (140.0 / 126.0 - 1) / k
+    p126 = integrate.quad(kn_pdf_cos, c0, 1, args=(k,))[0] / total
+    assert p126 == pytest.approx(0.335045, abs=2e-6)
+    assert math.degrees(math.acos(c0)) == pytest.approx(53.527, abs=1e-3)
+    frac = np.mean(x <= 140.0 / 126.0)
+    assert abs(binom_z(frac * n, n, p126)) < 5
+    # rejection efficiency of Kahn's method, derived independently
+    acc = _kahn_acceptance(k)
+    assert acc == pytest.approx(0.587, abs=0.005)
+    assert abs(binom_z(n, attempts, acc)) < 5
+
+
+@pytest.mark.parametrize("w", [0.3, -0.7, 0.999995, -0.9999999, 0.0])
+def test_direction_rotation_is_a_rotation(w):
+    rng = np.random.Generator(np.random.PCG64(21))
+    a = rng.uniform(0, 2 * math.pi)
+    s = math.sqrt(1 - w * w)
+    d = np.array([s * math.cos(a), s * math.sin(a), w])
+    # near the poles the rotation treats d as +-z exactly: error O(sqrt(1 - w^2))
+    tol = 20 * math.sqrt(1 - w * w) if abs(w) > 0.99999 else 1e-12
+    for cos_t in (0.9, 0.1, -0.6):
+        sin_t = math.sqrt(1 - cos_t ** 2)
+        phis = np.linspace(0, 2 * math.pi, 24, endpoint=False)
+        out = np.array([oracle.rotate(d, cos_t, ph) for ph in phis])
+        np.testing.assert_allclose(np.linalg.norm(out, axis=1), 1.0, atol=1e-12)
+        np.testing.assert_allclose(out @ d, cos_t, atol=tol)
+        perp = out - np.outer(out @ d, d)
+        np.testing.assert_allclose(np.linalg.norm(perp, axis=1), sin_t, atol=max(tol, 1e-12))
+        # equal steps in phi turn the perpendicular part by equal angles
+        cosang = np.sum(perp * np.roll(perp, -1, axis=0), axis=1) / sin_t ** 2
+        np.testing.assert_allclose(cosang, math.cos(2 * math.pi / 24), atol=max(tol, 1e-10))
+        # the perpendicular parts average out: the mean direction is cos_t * d
+        np.testing.assert_allclose(out.mean(axis=0), cos_t * d, atol=max(tol, 1e-12))
+        # right-handed about d (the near-pole branch turns about +z for either
+        # pole, which mirrors the azimuth for d ~ -z: same uniform distribution)
+        if abs(w) <= 0.99999 or w > 0:
+            assert np.dot(np.cross(perp[0], perp[1]), d) > 0
+
+
+# ---------------------------------------------------------------------------
+# Transport closed forms
+# ---------------------------------------------------------------------------
+
+def _cone_primary_prob(alpha, mu_path):
+    """P(emitted into the cone about +x and unattenuated) = 1/2 int exp(-mu_path/c) dc."""
+    return 0.5 * integrate.quad(lambda c: math.exp(-mu_path / c), math.cos(alpha), 1.0)[0]
+
+
+def test_geometric_efficiency_vacuum():
+    n = 16
+    mu = np.zeros((n, n, n), np.float32)
+    act = np.zeros((n, n, n), np.uint32)
+    act[n // 2, n // 2, n // 2] = 1
+    alpha = math.radians(20.0)
+    base = phantoms.point_source_cube("vac", n, 1.0, 200_000)
+    p = base.with_(mu=mu, activity=act, accept_half_angle_rad=alpha)
+    r = oracle.simulate(p)
+    N = p.n_histories
+    pexp = 0.5 * (1 - math.cos(alpha))
+    tal = r["fates"][5]
+    assert abs(binom_z(tal, N, pexp)) < 4
+    assert r["fates"][2] + tal == N          # nothing else can happen in vacuum
+    assert r["tally"][0, 1].sum() == 0       # no scatter
+    # primaries land within D tan(alpha) of the detector centre
+    iv, iu = np.nonzero(r["tally"][0, 0])
+    uc = (iu + 0.5) * p.pixel_cm - 0.5 * p.nu * p.pixel_cm
+    vc = (iv + 0.5) * p.pixel_cm - 0.5 * p.nv * p.pixel_cm
+    assert np.max(np.hypot(uc, vc)) <= p.radius_cm * math.tan(alpha) + p.pixel_cm
+
+
+@pytest.mark.parametrize("alpha_deg,N", [(20.0, 1_000_000), (2.0, 1_000_000)])
+def test_narrow_beam_primaries_water_cube(alpha_deg, N):
+    p = phantoms.point_cube_64(N).with_(accept_half_angle_rad=math.radians(alpha_deg))
+    r = oracle.simulate(p)
+    pexp = _cone_primary_prob(p.accept_half_angle_rad, 0.151 * 6.4)
+    if alpha_deg == 2.0:
+        assert pexp == pytest.approx(1.15846e-4, rel=1e-4)
+    assert abs(binom_z(r["tally"][0, 0].sum(), N, pexp)) < 4
+
+
+@pytest.mark.parametrize("extra_majorant", [False, True])
+def test_woodcock_two_material_slab(extra_majorant):
+    n, d = 64, 0.2
+    mu, act = phantoms.slab_phantom(n, d, 0.3, 0.05, 40)   # interface at x = 1.6 cm
+    if extra_majorant:
+        mu[0, 0, 0] = 0.6   # far corner; doubles the majorant, must not change results
+    alpha = math.radians(20.0)
+    p = phantoms.point_cube_64(1_000_000).with_(mu=mu, activity=act, accept_half_angle_rad=alpha)
+    r = oracle.simulate(p)
+    pexp = _cone_primary_prob(alpha, 0.3 * 1.6 + 0.05 * 4.8)
+    assert abs(binom_z(r["tally"][0, 0].sum(), p.n_histories, pexp)) < 4
+    q, mh = oracle.thresholds(p)
+    assert mh == pytest.approx(0.6 if extra_majorant else 0.3, rel=1e-7)
+    assert q.max() == 1 << 24
+
+
+def test_accept_thresholds():
+    mu = np.array([0.0, 0.0453, 0.151, 0.27935, 1e-30, 0.151 * (1 + 2**-20)], np.float32)
+    mu3 = np.zeros((1, 1, 6), np.float32)
+    mu3[0, 0] = mu
+    act = np.ones((1, 1, 6), np.uint32)
+    p = phantoms.point_cube_64(10).with_(nx=6, ny=1, nz=1, mu=mu3, activity=act)
+    q, mh = oracle.thresholds(p)
+    assert mh == float(mu.max())
+    q = q.reshape(-1)
+    assert q[0] == 0 and q[4] == 1 and q[3] == 1 << 24
+    # Q/2^24 brackets mu/mu_max from above by less than one step
+    ratio = mu.astype(np.float64) / mh
+    assert np.all(q / 2.0**24 >= ratio) and np.all(q / 2.0**24 - ratio <= 2.0**-24)
+
+
+def test_photoelectric_branch_fraction():
+    # every Compton scatter lowers E below 140 keV and is cut at once, so the
+    # first real collision's branch is observed directly: P(absorbed) = p_pe(140) = f
+    p = phantoms.point_source_cube("pe", 32, 0.5, 400_000, e_cut=140.0).with_(pe_fraction=0.3)
+    r = oracle.simulate(p)
+    a, c = r["fates"][0], r["fates"][1]
+    assert abs(binom_z(a, a + c, 0.3)) < 4
+    assert r["tally"].sum() == r["tally"][0, 0].sum()   # only primaries survive
+
+
+def test_conservation_thorax():
+    p = phantoms.thorax_problem("t", 32, 1.2, 2, 10, 180.0, 32, 1.2, 200_000).with_(e_cut_kev=10.0)
+    r = oracle.simulate(p)
+    assert r["fates"].sum() == p.n_histories == r["n_hist"]
+    assert r["energy"][:3].sum() == pytest.approx(140.0 * p.n_histories, rel=1e-12)
+    assert r["fates"][6] == 0
+    assert r["tally"].sum() == r["fates"][5]
+    np.testing.assert_array_equal(r["tally"], r["tally_sq"])   # analog weights are 1
+
+
+def test_emission_multinomial():
+    rng = np.random.Generator(np.random.PCG64(5))
+    act = rng.integers(0, 6, size=(4, 4, 4)).astype(np.uint32)
+    act[0, 0, 0] = 0
+    mu = np.full((4, 4, 4), 0.1, np.float32)
+    N = 200_000
+    p = phantoms.point_cube_64(N).with_(nx=4, ny=4, nz=4, voxel_cm=1.0, mu=mu, activity=act,
+                                        source_mode=phantoms.SOURCE_VOXELS)
+    rec = oracle.replay(p, np.zeros(N, np.int32), np.arange(N, dtype=np.uint64))
+    counts = np.bincount(rec["emit_voxel"], minlength=64)
+    a = act.reshape(-1).astype(np.float64)
+    assert np.all(counts[a == 0] == 0)
+    e = N * a / a.sum()
+    m = a > 0
+    chi2 = np.sum((counts[m] - e[m]) ** 2 / e[m])
+    assert stats.chi2.sf(chi2, m.sum() - 1) > 1e-4
+
+
+def test_emission_cdf_toy():
+    act = np.array([[[1, 0, 3]]], np.uint32)
+    mu = np.full((1, 1, 3), 0.1, np.float32)
+    N = 100_000
+    p = phantoms.point_cube_64(N).with_(nx=3, ny=1, nz=1, voxel_cm=1.0, mu=mu, activity=act,
+                                        source_mode=phantoms.SOURCE_VOXELS)
+    rec = oracle.replay(p, np.zeros(N, np.int32), np.arange(N, dtype=np.uint64))
+    c = np.bincount(rec["emit_voxel"], minlength=3)
+    assert c[1] == 0 and c.sum() == N
+    assert abs(binom_z(c[0], N, 0.25)) < 4
+
+
+def test_resume_and_thread_independence():
+    p = phantoms.thorax_problem("t", 32, 1.2, 2, 7, 180.0, 32, 1.2, 100_001)
+    full = oracle.simulate(p, n_threads=3)
+    one = oracle.simulate(p, n_threads=1)
+    a = oracle.simulate(p.with_(history_offset=0, history_count=40_000))
+    b = oracle.simulate(p.with_(history_offset=40_000, history_count=0))
+    np.testing.assert_array_equal(full["tally"], one["tally"])
+    np.testing.assert_array_equal(full["fates"], one["fates"])
+    np.testing.assert_array_equal(full["tally"], a["tally"] + b["tally"])
+    np.testing.assert_array_equal(full["fates"], a["fates"] + b["fates"])
+    assert full["n_tent"] == a["n_tent"] + b["n_tent"]
+
+
+def test_replay_agrees_with_simulate():
+    p = phantoms.thorax_problem("t", 32, 1.2, 2, 5, 180.0, 32, 1.2, 50_000)
+    r = oracle.simulate(p)
+    N, V = p.n_histories, p.n_views
+    views = np.concatenate([np.full(N // V + (k < N % V), k, np.int32) for k in range(V)])
+    hists = np.concatenate([np.arange(N // V + (k < N % V), dtype=np.uint64) for k in range(V)])
+    rec = oracle.replay(p, views, hists)
+    np.testing.assert_array_equal(np.bincount(rec["fate"], minlength=8), r["fates"])
+    t = rec[rec["fate"] == 5]
+    tally = np.zeros(p.tally_shape)
+    np.add.at(tally, (t["view"], t["cls"], t["iv"], t["iu"]), 1.0)
+    np.testing.assert_array_equal(tally, r["tally"])
+
+
+# ---------------------------------------------------------------------------
+# Adjoint
+# ---------------------------------------------------------------------------
+
+def test_adjoint_primary_scaling_closed_form():
+    """Only primaries in the window (E exactly 140).  Scaling mu -> s mu:
+    d lambda/ds = -N/2 int (mu h/c) exp(-mu h/c) dc; the estimator is
+    sum_v mu_v dlambda/dmu_v."""
+    N = 400_000
+    alpha = math.radians(20.0)
+    p = phantoms.point_source_cube("adj", 32, 0.4, N).with_(
+        accept_half_angle_rad=alpha, e_lo_kev=140.0, e_hi_kev=140.0)
+    G = np.ones(p.tally_shape)
+    r = oracle.adjoint(p, G)
+    est = float(np.sum(r["grad"] * p.mu.astype(np.float64)))
+    mh = 0.151 * 6.4
+    exp_ = -N * 0.5 * integrate.quad(lambda c: (mh / c) * math.exp(-mh / c), math.cos(alpha), 1)[0]
+    k = r["fates"][5]
+    assert k > 1000
+    # per-history value is mu*h/c in [0.966, 1.03]: sd ~ sqrt(k)
+    assert abs(est - exp_) < 4 * math.sqrt(k) * 1.0
+
+
+def test_adjoint_matches_analog_crn_fd_on_scaling():
+    """Independent of the likelihood-ratio machinery: re-simulate at mu*(1+-h)
+    with the same random numbers and difference the primary counts."""
+    N = 400_000
+    alpha = math.radians(20.0)
+    base = phantoms.point_source_cube("adj", 32, 0.4, N).with_(
+        accept_half_angle_rad=alpha, e_lo_kev=140.0, e_hi_kev=140.0)
+    h = 0.02
+    lp = oracle.simulate(base.with_(mu=(base.mu * (1 + h)).astype(np.float32)))["tally"].sum()
+    lm = oracle.simulate(base.with_(mu=(base.mu * (1 - h)).astype(np.float32)))["tally"].sum()
+    fd = (lp - lm) / (2 * h)
+    G = np.ones(base.tally_shape)
+    est = float(np.sum(oracle.adjoint(base, G)["grad"] * base.mu.astype(np.float64)))
+    # CRN difference counts histories whose fate flips: Poisson with mean ~ |fd|*2h
+    sd = math.sqrt(abs(fd) * 2 * h) / (2 * h)
+    assert abs(fd - est) < 4 * sd + 0.02 * abs(est)
+
+
+def test_adjoint_gradient_matches_path_frozen_fd():
+    N = 300_000
+    p = phantoms.point_source_cube("adj", 32, 0.4, N).with_(accept_half_angle_rad=math.radians(10))
+    ref = oracle.simulate(p.with_(seed=1))
+    lam_ref = ref["tally"].sum(axis=1)
+    y = phantoms.poisson_target(lam_ref, seed=4)
+    fwd = oracle.simulate(p)
+    lam = fwd["tally"].sum(axis=1)
+    eps = 1e-6 * lam.max()
+    _, dl = oracle.poisson_loss_grad(lam, y, eps)
+    G = np.repeat(dl[:, None], 2, axis=1)
+    r0 = oracle.adjoint(p, G)
+    cand = np.flatnonzero(r0["n_contrib"].reshape(-1) >= 50)
+    assert len(cand) >= 16
+    vox = phantoms.pick(4, cand, 16)
+    r = oracle.adjoint(p, G, pert_voxels=vox, delta=1e-3, lam=lam, y=y, eps=eps)
+    g = r["grad"].reshape(-1)[vox]
+    fd = r["fd"]
+    scale = np.maximum(np.abs(fd), 1e-2 * np.abs(fd).max())
+    assert np.all(np.abs(g - fd) <= 1e-5 * scale), (g, fd)
+    np.testing.assert_array_equal(r["grad"], r0["grad"])
+
+
+# ---------------------------------------------------------------------------
+# MLEM (Sec. 5.1, Eq. MLEM)
+# ---------------------------------------------------------------------------
+
+def _rand_T(rng, nb, nv, dens):
+    import scipy.sparse as sp
+    T = sp.random(nb, nv, density=dens, random_state=np.random.RandomState(1), format="csr")
+    T.data = rng.uniform(0.1, 1.0, size=T.nnz)
+    return T
+
+
+def test_mlem_fixed_point_and_conservation():
+    rng = np.random.Generator(np.random.PCG64(8))
+    T = _rand_T(rng, 300, 120, 0.05)
+    n = rng.uniform(0.5, 3.0, size=120)
+    sens = np.asarray(T.sum(axis=0)).ravel()
+    n[sens == 0] = 0
+    P = T @ n
+    S = oracle.mlem(T, P, 5, S0=n)
+    np.testing.assert_allclose(S, n, rtol=1e-12)
+    Pn = rng.poisson(P * 10) / 10.0
+    S = None
+    for k in range(1, 6):
+        S = oracle.mlem(T, Pn, k)
+        y = T @ S
+        # sum_i sens_i S_i = sum of P over bins with positive reprojection
+        assert np.dot(sens, S) == pytest.approx(Pn[(T @ oracle.mlem(T, Pn, k - 1)) > 0].sum(), rel=1e-12)
+
+
+def test_mlem_monotone_likelihood():
+    rng = np.random.Generator(np.random.PCG64(9))
+    T = _rand_T(rng, 200, 80, 0.08)
+    truth = rng.uniform(0, 5, size=80)
+    P = rng.poisson(T @ truth).astype(np.float64)
+    ll = [oracle.poisson_loglik(T, P, oracle.mlem(T, P, k)) for k in range(0, 30)]
+    assert np.all(np.diff(ll) >= -1e-9 * np.abs(ll[-1]))
+
+
+def test_mlem_one_voxel():
+    import scipy.sparse as sp
+    T = sp.csr_matrix(np.array([[0.2], [0.5], [0.0], [0.3]]))
+    P = np.array([3.0, 7.0, 2.0, 4.0])
+    S = oracle.mlem(T, P, 1, S0=np.array([17.0]))
+    assert S[0] == pytest.approx((3 + 7 + 4) / 1.0, rel=1e-14)   # sum P over seen bins / sum T
+
+
+def test_mlem_small_toy_vs_constrained_maximiser():
+    import scipy.sparse as sp
+    A = np.array([[0.6, 0.1], [0.3, 0.5], [0.1, 0.4]])   # 3 bins x 2 voxels
+    P = np.array([5.0, 9.0, 4.0])
+    T = sp.csr_matrix(A)
+    S = oracle.mlem(T, P, 3000)
+
+    def negll(s):
+        y = A @ s
+        return -(np.sum(P * np.log(y)) - np.sum(y))
+    res = optimize.minimize(negll, x0=np.ones(2), bounds=[(1e-9, None)] * 2, method="L-BFGS-B",
+                            options={"ftol": 1e-15, "gtol": 1e-12})
+    np.testing.assert_allclose(S, res.x, rtol=1e-5)

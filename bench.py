@@ -1,0 +1,144 @@
+"""Throughput benchmark of the Monte Carlo SPECT transport path on one MI355X.
+
+A step is one pass of the forward hot path over the 128^3 thorax workload
+(60 views over 180 degrees, 64x64 pixels at 6 mm, 126-154 keV window, 1e8
+photon histories): input staging, transport, tallies.  Inputs are resident in
+HBM before timing starts.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--histories N]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+N_CU, CLOCK_HZ = 256, 2.4e9
+PEAK_LANE_OPS = N_CU * 64 * CLOCK_HZ  # one 32-bit VALU operation per lane per clock
+
+# Algorithmic 32-bit operation model per unit of work:
+OPS_PHILOX = 100          # 10 rounds x (2 lo + 2 hi products, 4 xor, 2 key adds)
+OPS_EMISSION = 50         # voxel pick (64-bit product, guide, search), position, direction
+OPS_STEP = 35             # flight length, move, inside test, voxel index, accept test
+OPS_KAHN = 20             # one rejection attempt
+OPS_SCATTER = 95          # kinematics, rotation, attenuation terms (FP64 counted twice)
+OPS_END = 35              # collimator, detector bin, window, bookkeeping
+
+
+def ops_per_history(n_tent, n_kahn, n_scatter, n_hist):
+    per = (2 * (OPS_PHILOX) + OPS_EMISSION + OPS_END) * n_hist \
+        + n_tent * (OPS_PHILOX + OPS_STEP) + n_kahn * (OPS_PHILOX + OPS_KAHN) \
+        + n_scatter * OPS_SCATTER
+    return per / max(n_hist, 1)
+
+
+def cpu_baseline(prob, target_s: float = 12.0):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload."""
+    import oracle
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    # calibrate on growing samples until one takes a second, then size the timed sample
+    n0 = 200_000
+    while True:
+        t = time.perf_counter()
+        oracle.simulate(prob.with_(n_histories=n0), n_threads=cores)
+        dt0 = time.perf_counter() - t
+        if dt0 > 1.0 or n0 >= prob.n_histories:
+            break
+        n0 = min(n0 * 8, prob.n_histories)
+    n = int(min(max(n0, n0 * target_s / max(dt0, 1e-3)), prob.n_histories))
+    t = time.perf_counter()
+    oracle.simulate(prob.with_(n_histories=n), n_threads=cores)
+    dt = time.perf_counter() - t
+    return {"value": n / dt, "unit": "histories/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n} histories of the same workload ({prob.n_views} views), "
+                      f"{dt:.1f} s wall on {cores} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--histories", type=float, default=1e8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the transport path is built and timed on a single "
+              "MI355X (multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import phantoms
+    import paper_2105_13324_amd as mc
+
+    n_hist = int(args.histories)
+    prob = phantoms.thorax_128(n_hist)
+    dp = mc.to_device(prob)
+    timers = [mc.KernelTimer() for _ in range(max(args.steps, 1))]
+    sim = mc.Simulator(dp, want_sq=True)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        sim.run()
+    torch.cuda.synchronize()
+    sim.check_status()
+
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for k in range(args.steps):
+        # the library records timers[k] around its transport kernel on this stream
+        sim.run(kernel_events=timers[k].handles)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    kernel_ms = [t.elapsed_ms() for t in timers[:args.steps]]
+    st = sim.check_status()
+
+    ms_per_step = total_ms / args.steps
+    value = n_hist / (ms_per_step / 1e3)
+    cnt = sim.counters.cpu().numpy()[0].astype(np.float64)
+    fates = sim.fates.cpu().numpy()[0]
+    # accepted scatters = real collisions that were not photoelectric absorptions
+    n_scatter = float(cnt[1] - fates[0])
+    ops_h = ops_per_history(cnt[0], cnt[2], n_scatter, cnt[3])
+    k_ms = float(np.mean(kernel_ms))
+    achieved = ops_h * n_hist / (k_ms / 1e3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                "unit": "Tops/s (32-bit lane ops)", "frac": achieved / PEAK_LANE_OPS,
+                "traffic": None, "kernel": "k_transport", "kernel_ms": k_ms,
+                "ops_per_history": ops_h}
+    rec = {
+        "metric": "photon histories/s (128^3 thorax, 60 views) + adjoint μ-grad histories/s",
+        "value": value, "unit": "histories/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "thorax_128: 128^3 x 3 mm seeded ellipsoid thorax, 60 views over "
+                               "180 deg, 64x64 x 6 mm, 126-154 keV, alpha 2 deg",
+                   "histories": n_hist, "views": prob.n_views, "grid": [prob.nx, prob.ny, prob.nz]},
+        "roofline": roofline,
+        "per_history": {"tentative": cnt[0] / cnt[3], "real": cnt[1] / cnt[3],
+                        "kahn_attempts": cnt[2] / cnt[3],
+                        "tallied_fraction": float(fates[5]) / cnt[3]},
+        "status": int(st[0]),
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * mcspect.h -- C ABI of the MI355X Monte Carlo SPECT transport library.
+ *
+ * The library estimates SPECT projections by following photon histories one by
+ * one from emission to absorption, energy cut or escape (paper: Zhou et al.,
+ * "Application of Monte Carlo algorithms to cardiac imaging reconstruction",
+ * Sec. 2), through a voxelised attenuation map, into a rotating parallel-hole
+ * camera with a photopeak energy window (Sec. 3).  Tallied photons give the
+ * projections P_j and the Monte Carlo response matrix T_ij of Sec. 5.1,
+ * Eq. IMC; mlem_iterate runs the update of Sec. 5.1, Eq. MLEM.
+ *
+ * Physics model (the paper names none; these are this library's definitions):
+ *  - mu_v(E) = mu_v * g(E): every material is density-scaled water;
+ *    g(E) = (1-f) sigma_KN(E)/sigma_KN(140) + f (140/E)^3 with f the
+ *    photoelectric share of attenuation at 140 keV (pe_fraction);
+ *  - Woodcock tracking against mu_max(E) = max_v mu_v * g(E); a tentative
+ *    collision in voxel v is real iff (r >> 8) < Q_v, Q_v = ceil(mu_v 2^24 /
+ *    max mu) evaluated in double precision;
+ *  - photoelectric absorption with probability f (140/E)^3 / g(E), otherwise
+ *    Compton scatter with Kahn's Klein-Nishina sampler and uniform azimuth;
+ *  - the collimator accepts an escaping photon iff d . n_view >= cos(alpha).
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key (seed,
+ * problem_id), counter (history id, view, event, sub-draw), so every history
+ * can be replayed on its own.  Uniforms are ((r >> 9) + 1/2) 2^-23.
+ *
+ * Geometry: lengths in cm, energies in keV.  The voxel grid [nz][ny][nx]
+ * (x fastest) is centred on the origin.  View k has normal n_k = (cos t_k,
+ * sin t_k, 0), detector axes u_k = (-sin t_k, cos t_k, 0) and z, and its
+ * plane is n_k . p = radius_cm.  N histories split over V views as
+ * N_k = floor(N/V) + [k < N mod V], history ids 0..N_k-1 within view k; the
+ * work index g runs view-major over (view, history id).
+ *
+ * Conventions for every entry point:
+ *  - Pointers documented "device" are HIP device memory owned by the caller;
+ *    "host" pointers are read during the call only.
+ *  - Calls are asynchronous on the given stream (hipStream_t passed as void*,
+ *    NULL = default stream).  Results are valid after the stream synchronises.
+ *  - The library allocates no device memory: scratch comes from the caller's
+ *    workspace, sized by the matching *_workspace_bytes function.
+ *  - Return value: MC_OK or a negative MC_E* code.  Argument checks that need
+ *    device data (negative or NaN mu, zero activity, list overflow, capped
+ *    histories) are reported through the device status array instead.
+ *  - No C++ exception crosses this interface.  Calls on different streams with
+ *    different workspaces may run concurrently.
+ */
+#ifndef MCSPECT_H
+#define MCSPECT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MC_OK = 0,
+    MC_EINVAL = -1,     /* invalid argument (host-visible)                    */
+    MC_ENOMEM = -2,     /* workspace or output capacity too small             */
+    MC_EDEVICE = -3,    /* a HIP call failed; see mc_last_hip_error()         */
+    MC_EOVERFLOW = -4,  /* reserved: fixed-point overflow reported by a check */
+    MC_ECAPPED = -5     /* reserved: some history hit max_steps               */
+};
+
+/* Bits of status[0] (device int64 written by mc_simulate_projections). */
+enum {
+    MC_STATUS_BAD_MU = 1,        /* a mu value is negative, NaN or infinite   */
+    MC_STATUS_NO_ACTIVITY = 2,   /* activity sums to zero                     */
+    MC_STATUS_BAD_ANGLE = 4,     /* a view angle is not finite                */
+    MC_STATUS_LIST_OVERFLOW = 8, /* more tallied histories than list_capacity */
+    MC_STATUS_CAPPED = 16,       /* a history hit max_steps (fate CAPPED)     */
+    MC_STATUS_GRAD_OVERFLOW = 32,/* a gradient term exceeded the fixed-point  */
+                                 /* range at this frac_bits (term dropped)    */
+    MC_STATUS_BAD_EVENT = 64     /* an event did not replay to its bin        */
+};
+
+/* Fate counters, in this order: */
+enum { MC_ABSORBED = 0, MC_CUT = 1, MC_ESCAPED = 2, MC_ESCAPED_FOV = 3,
+       MC_OUT_OF_WINDOW = 4, MC_TALLIED = 5, MC_CAPPED_FATE = 6, MC_N_FATES = 8 };
+
+/* Emission modes. */
+enum { MC_SOURCE_VOXELS = 0,   /* voxel by activity, uniform inside it          */
+       MC_SOURCE_POINT = 1 };  /* grid centre exactly (voxel still drawn)       */
+
+typedef struct {
+    int32_t nx, ny, nz;         /* grid size                                    */
+    int32_t source_mode;        /* MC_SOURCE_*                                  */
+    double voxel_cm;            /* cubic voxel edge                             */
+    const float* mu140;         /* device [nz*ny*nx], 1/cm at 140 keV           */
+    const uint32_t* activity;   /* device [nz*ny*nx], integer emission weights  */
+    int32_t n_views;            /* V >= 1                                       */
+    int32_t nu, nv;             /* detector bins along u and z                  */
+    const double* angle_rad;    /* device [n_views], view angles                */
+    double pixel_cm;            /* square detector bin edge                     */
+    double radius_cm;           /* detector plane distance from the axis        */
+    double accept_half_angle_rad; /* collimator cone half-angle, (0, pi/2)      */
+    double e_lo_kev, e_hi_kev;  /* photopeak window, closed interval            */
+    double e_cut_kev;           /* photons below this energy are cut            */
+    double pe_fraction;         /* photoelectric share of attenuation at 140 keV*/
+    uint64_t n_histories;       /* N, defines the split over views              */
+    uint64_t history_offset;    /* first work index simulated by this call      */
+    uint64_t history_count;     /* work indices simulated (0 = to the end)      */
+    uint32_t seed, problem_id;  /* Philox key                                   */
+    int32_t image_factor;       /* >0: image voxel = phantom voxel / factor     */
+    uint32_t max_steps;         /* cap on tentative collisions (0 = 1000)       */
+} mc_problem;
+
+typedef struct {
+    int32_t hist_per_lane;      /* histories per lane per work claim, <=0: auto */
+    int32_t block_size;         /* threads per block (64..256), <=0: auto       */
+    int32_t blocks_per_cu;      /* resident blocks per CU to launch, <=0: auto  */
+    int32_t reserved;
+    void* kernel_events[2];     /* optional hipEvent_t pair recorded on the     */
+                                /* stream right before / after the transport    */
+                                /* kernel (NULL: none)                          */
+} mc_options;
+
+/* A tallied history, as written to the optional event list. */
+typedef struct {
+    uint64_t work;        /* call-global work index (problems concatenated)     */
+    uint32_t bin;         /* bin within its problem: ((view*2+cls)*nv+iv)*nu+iu */
+    uint32_t emit_voxel;  /* phantom voxel of emission                          */
+} mc_event;
+
+/* Per-history record written by mc_replay_histories. */
+typedef struct {
+    int32_t fate, view, iu, iv;   /* iu = iv = -1 when no detector bin        */
+    int32_t n_scatter, n_tent;    /* Compton scatters, tentative collisions   */
+    int32_t emit_voxel, cls;      /* cls 0 primary, 1 scattered (tallied)     */
+    double e_final;               /* energy at the end of the history (keV)   */
+} mc_record;
+
+/* Bytes of workspace that mc_simulate_projections / mc_replay_histories /
+ * mc_adjoint_mu need for these problems.  Returns 0 on invalid arguments. */
+size_t mc_workspace_bytes(const mc_problem* problems, int32_t n_problems,
+                          const mc_options* opt);
+
+/* Forward Monte Carlo projection of n_problems phantoms in one persistent
+ * launch (Sec. 2 transport, Sec. 3 camera; the projections P_j of Eq. IMC).
+ *   problems   host [n_problems]
+ *   opt        host, nullable (defaults)
+ *   tally      device int64 [sum_p V_p*2*nv_p*nu_p], Q31.32 fixed point sum of
+ *              weights, layout [problem][view][class][iv][iu]; overwritten
+ *   tally_sq   device, same shape, sum of squared weights; nullable
+ *   fates      device int64 [n_problems][8]; overwritten
+ *   energy     device int64 [n_problems][4], Q40.23 keV: deposited, escaped,
+ *              capped, 0; nullable
+ *   counters   device int64 [n_problems][4]: tentative collisions, real
+ *              collisions, Kahn attempts, histories; nullable
+ *   events     device mc_event [event_capacity], tallied histories in no
+ *              particular order; nullable
+ *   n_events   device uint64 [1], number of tallied histories (may exceed the
+ *              capacity: then status has MC_STATUS_LIST_OVERFLOW); nullable
+ *   status     device int64 [4]: [0] MC_STATUS_* bits, [1] capped histories
+ *   workspace  device, at least mc_workspace_bytes(...)
+ * Results are bit-identical from run to run and independent of the options. */
+int mc_simulate_projections(const mc_problem* problems, int32_t n_problems,
+                            const mc_options* opt,
+                            int64_t* tally, int64_t* tally_sq, int64_t* fates,
+                            int64_t* energy, int64_t* counters,
+                            mc_event* events, uint64_t event_capacity, uint64_t* n_events,
+                            int64_t* status,
+                            void* workspace, size_t workspace_bytes, void* stream);
+
+/* Re-run the listed histories of problem 0 one per lane and write one record
+ * each (the replay contract: a history is a function of its Philox counter).
+ *   views, hists   device [n]: view and history id of each history
+ *   records        device mc_record [n]                                     */
+int mc_replay_histories(const mc_problem* problem, const mc_options* opt,
+                        const int32_t* views, const uint64_t* hists, int64_t n,
+                        mc_record* records, int64_t* status,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* Gradient of sum_b G_b * tally_b with respect to mu140 (the adjoint of the
+ * forward projection), by path-frozen likelihood ratios: each tallied history
+ * is replayed from its Philox counter and its path walked voxel by voxel,
+ *   dL/dmu_v = sum_h G_{b(h)} * (c_{h,v} / mu_v - sum_seg g(E_seg) len(seg, v)),
+ * c_{h,v} = Compton vertices of h in v.  Only tallied histories contribute.
+ *   problem     host, the same description as the forward call
+ *   dL_dtally   device double [V*2*nv*nu], G in the tally layout
+ *   events      device, the forward call's event list (replay just those), or
+ *               NULL to replay every history of the range
+ *   n_events    device uint64 [1], the forward call's count (read on device)
+ *   event_capacity  the list's capacity (host)
+ *   dL_dmu      device int64 [nz*ny*nx], overwritten: fixed point with
+ *               frac_bits (0..62) fractional bits; value = dL_dmu * 2^-frac_bits
+ *   status      device int64 [4]: MC_STATUS_* bits in [0]
+ * The sum is exact integer arithmetic: bit-identical from run to run. */
+int mc_adjoint_mu(const mc_problem* problem, const mc_options* opt, const double* dL_dtally,
+                  const mc_event* events, const uint64_t* n_events, uint64_t event_capacity,
+                  int64_t* dL_dmu, int32_t frac_bits, int64_t* status,
+                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* Human-readable text for an MC_* code (static storage). */
+const char* mc_error_string(int code);
+
+/* The last HIP error code seen by this library on the calling thread. */
+int mc_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCSPECT_H */

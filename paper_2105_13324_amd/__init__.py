@@ -1,0 +1,424 @@
+"""Python binding of libmcspect (MI355X Monte Carlo SPECT transport).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libmcspect.so`` behind the C ABI declared in ``include/mcspect.h``.
+PyTorch provides device memory and the current HIP stream.  If the library is
+missing this module raises at import: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Union
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcspect.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libmcspect.so not built at {LIB_PATH}; run paper_2105_13324_amd.build.build()")
+
+# torch first: it loads its HIP runtime (soname libamdhip64.so.7), and the
+# library's own dependency then binds to that same copy.  Two HIP runtimes in
+# one process do not share devices.
+import torch  # noqa: E402,F401
+
+_lib = C.CDLL(LIB_PATH)
+
+MC_OK, MC_EINVAL, MC_ENOMEM, MC_EDEVICE, MC_EOVERFLOW, MC_ECAPPED = 0, -1, -2, -3, -4, -5
+STATUS_BAD_MU, STATUS_NO_ACTIVITY, STATUS_BAD_ANGLE, STATUS_LIST_OVERFLOW, STATUS_CAPPED = 1, 2, 4, 8, 16
+STATUS_GRAD_OVERFLOW, STATUS_BAD_EVENT = 32, 64
+FATES = ["ABSORBED", "CUT", "ESCAPED", "ESCAPED_FOV", "OUT_OF_WINDOW", "TALLIED", "CAPPED", "SPARE"]
+Q32 = float(2 ** 32)   # tally fixed point: Q31.32
+Q23 = float(2 ** 23)   # energy fixed point: Q40.23 keV
+
+# Exported symbols, as declared in include/mcspect.h.
+EXPORTS = ["mc_workspace_bytes", "mc_simulate_projections", "mc_replay_histories",
+           "mc_adjoint_mu", "mc_error_string", "mc_last_hip_error"]
+
+
+class McProblem(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("source_mode", C.c_int32),
+        ("voxel_cm", C.c_double),
+        ("mu140", C.c_void_p), ("activity", C.c_void_p),
+        ("n_views", C.c_int32), ("nu", C.c_int32), ("nv", C.c_int32),
+        ("angle_rad", C.c_void_p),
+        ("pixel_cm", C.c_double), ("radius_cm", C.c_double), ("accept_half_angle_rad", C.c_double),
+        ("e_lo_kev", C.c_double), ("e_hi_kev", C.c_double), ("e_cut_kev", C.c_double),
+        ("pe_fraction", C.c_double),
+        ("n_histories", C.c_uint64), ("history_offset", C.c_uint64), ("history_count", C.c_uint64),
+        ("seed", C.c_uint32), ("problem_id", C.c_uint32),
+        ("image_factor", C.c_int32), ("max_steps", C.c_uint32),
+    ]
+
+
+class McOptions(C.Structure):
+    _fields_ = [("hist_per_lane", C.c_int32), ("block_size", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("reserved", C.c_int32),
+                ("kernel_events", C.c_void_p * 2)]
+
+
+EVENT_DTYPE = np.dtype([("work", np.uint64), ("bin", np.uint32), ("emit_voxel", np.uint32)])
+RECORD_DTYPE = np.dtype([("fate", np.int32), ("view", np.int32), ("iu", np.int32), ("iv", np.int32),
+                         ("n_scatter", np.int32), ("n_tent", np.int32), ("emit_voxel", np.int32),
+                         ("cls", np.int32), ("e_final", np.float64)])
+assert C.sizeof(McProblem) == 160
+
+_vp, _i32, _i64, _u64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
+_lib.mc_workspace_bytes.argtypes = [C.POINTER(McProblem), _i32, C.POINTER(McOptions)]
+_lib.mc_workspace_bytes.restype = _sz
+_lib.mc_simulate_projections.argtypes = [C.POINTER(McProblem), _i32, C.POINTER(McOptions),
+                                         _vp, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp, _sz, _vp]
+_lib.mc_simulate_projections.restype = C.c_int
+_lib.mc_replay_histories.argtypes = [C.POINTER(McProblem), C.POINTER(McOptions), _vp, _vp, _i64,
+                                     _vp, _vp, _vp, _sz, _vp]
+_lib.mc_replay_histories.restype = C.c_int
+_lib.mc_adjoint_mu.argtypes = [C.POINTER(McProblem), C.POINTER(McOptions), _vp, _vp, _vp, _u64,
+                               _vp, C.c_int32, _vp, _vp, _sz, _vp]
+_lib.mc_adjoint_mu.restype = C.c_int
+_lib.mc_error_string.argtypes = [C.c_int]
+_lib.mc_error_string.restype = C.c_char_p
+_lib.mc_last_hip_error.argtypes = []
+_lib.mc_last_hip_error.restype = C.c_int
+
+
+class McError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != MC_OK:
+        msg = _lib.mc_error_string(rc).decode()
+        if rc == MC_EDEVICE:
+            msg += f" (hip error {_lib.mc_last_hip_error()})"
+        raise McError(f"{what}: {msg} ({rc})")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@dataclass
+class DeviceProblem:
+    """A problem whose arrays live on the GPU (torch tensors) plus its scalars."""
+    nx: int
+    ny: int
+    nz: int
+    voxel_cm: float
+    mu: "object"          # torch.float32 [nz, ny, nx]
+    activity: "object"    # torch.int32 view of uint32 [nz, ny, nx]
+    angles: "object"      # torch.float64 [V]
+    nu: int
+    nv: int
+    pixel_cm: float
+    radius_cm: float
+    accept_half_angle_rad: float
+    e_lo_kev: float
+    e_hi_kev: float
+    e_cut_kev: float
+    n_histories: int
+    seed: int = 0
+    problem_id: int = 0
+    source_mode: int = 0
+    image_factor: int = 0
+    pe_fraction: float = 1e-3
+    max_steps: int = 1000
+    history_offset: int = 0
+    history_count: int = 0
+
+    @property
+    def n_views(self) -> int:
+        return int(self.angles.shape[0])
+
+    @property
+    def tally_shape(self):
+        return (self.n_views, 2, self.nv, self.nu)
+
+    def with_(self, **kw) -> "DeviceProblem":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return DeviceProblem(**d)
+
+    def c_struct(self) -> McProblem:
+        return McProblem(
+            nx=self.nx, ny=self.ny, nz=self.nz, source_mode=self.source_mode,
+            voxel_cm=self.voxel_cm, mu140=self.mu.data_ptr(), activity=self.activity.data_ptr(),
+            n_views=self.n_views, nu=self.nu, nv=self.nv, angle_rad=self.angles.data_ptr(),
+            pixel_cm=self.pixel_cm, radius_cm=self.radius_cm,
+            accept_half_angle_rad=self.accept_half_angle_rad, e_lo_kev=self.e_lo_kev,
+            e_hi_kev=self.e_hi_kev, e_cut_kev=self.e_cut_kev, pe_fraction=self.pe_fraction,
+            n_histories=self.n_histories, history_offset=self.history_offset,
+            history_count=self.history_count, seed=self.seed, problem_id=self.problem_id,
+            image_factor=self.image_factor, max_steps=self.max_steps)
+
+
+_SCALARS = ["nx", "ny", "nz", "voxel_cm", "nu", "nv", "pixel_cm", "radius_cm",
+            "accept_half_angle_rad", "e_lo_kev", "e_hi_kev", "e_cut_kev", "n_histories", "seed",
+            "problem_id", "source_mode", "image_factor", "pe_fraction", "max_steps",
+            "history_offset", "history_count"]
+
+
+def to_device(prob, device="cuda") -> DeviceProblem:
+    """Copy a host problem description (numpy arrays + scalars) to the GPU."""
+    torch = _torch()
+    mu = torch.from_numpy(np.ascontiguousarray(prob.mu, dtype=np.float32)).to(device)
+    act = torch.from_numpy(np.ascontiguousarray(prob.activity, dtype=np.uint32).view(np.int32)).to(device)
+    ang = torch.from_numpy(np.ascontiguousarray(prob.angles, dtype=np.float64)).to(device)
+    kw = {k: getattr(prob, k) for k in _SCALARS}
+    return DeviceProblem(mu=mu, activity=act, angles=ang, **kw)
+
+
+def _opts(options: Optional[dict]) -> Optional[McOptions]:
+    if not options:
+        return None
+    o = McOptions(hist_per_lane=int(options.get("hist_per_lane", 0)),
+                  block_size=int(options.get("block_size", 0)),
+                  blocks_per_cu=int(options.get("blocks_per_cu", 0)), reserved=0)
+    ev = options.get("kernel_events")
+    if ev is not None:
+        o.kernel_events[0] = ev[0]
+        o.kernel_events[1] = ev[1]
+    return o
+
+
+class KernelTimer:
+    """A hipEvent_t pair the library records around its transport kernel."""
+
+    def __init__(self):
+        self._hip = C.CDLL("libamdhip64.so")
+        self._hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self._hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self._hip.hipEventDestroy.argtypes = [C.c_void_p]
+        self.ev = [C.c_void_p(), C.c_void_p()]
+        for e in self.ev:
+            if self._hip.hipEventCreate(C.byref(e)) != 0:
+                raise McError("hipEventCreate failed")
+
+    @property
+    def handles(self):
+        return (self.ev[0].value, self.ev[1].value)
+
+    def elapsed_ms(self) -> float:
+        ms = C.c_float()
+        if self._hip.hipEventElapsedTime(C.byref(ms), self.ev[0], self.ev[1]) != 0:
+            raise McError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def __del__(self):
+        try:
+            for e in self.ev:
+                if e.value:
+                    self._hip.hipEventDestroy(e)
+        except Exception:
+            pass
+
+
+def _stream_ptr():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def workspace_bytes(problems: Sequence[DeviceProblem], options=None) -> int:
+    arr = (McProblem * len(problems))(*[p.c_struct() for p in problems])
+    o = _opts(options)
+    n = _lib.mc_workspace_bytes(arr, len(problems), C.byref(o) if o else None)
+    if n == 0:
+        raise McError("mc_workspace_bytes: invalid problem description")
+    return int(n)
+
+
+class Simulator:
+    """Holds the outputs and workspace of repeated mc_simulate_projections calls
+    on a fixed set of problems (no allocation per call)."""
+
+    def __init__(self, problems: Union[DeviceProblem, Sequence[DeviceProblem]], *,
+                 event_capacity: int = 0, want_sq: bool = True, options: Optional[dict] = None):
+        torch = _torch()
+        if isinstance(problems, DeviceProblem):
+            problems = [problems]
+        self.problems: List[DeviceProblem] = list(problems)
+        self.options = _opts(options)
+        n = len(self.problems)
+        self._arr = (McProblem * n)(*[p.c_struct() for p in self.problems])
+        dev = self.problems[0].mu.device
+        self.sizes = [int(np.prod(p.tally_shape)) for p in self.problems]
+        total = sum(self.sizes)
+        self.tally = torch.zeros(total, dtype=torch.int64, device=dev)
+        self.tally_sq = torch.zeros(total, dtype=torch.int64, device=dev) if want_sq else None
+        self.fates = torch.zeros((n, 8), dtype=torch.int64, device=dev)
+        self.energy = torch.zeros((n, 4), dtype=torch.int64, device=dev)
+        self.counters = torch.zeros((n, 4), dtype=torch.int64, device=dev)
+        self.status = torch.zeros(4, dtype=torch.int64, device=dev)
+        self.event_capacity = int(event_capacity)
+        self.events = (torch.zeros((max(self.event_capacity, 1), 2), dtype=torch.int64, device=dev)
+                       if self.event_capacity else None)
+        self.n_events = torch.zeros(1, dtype=torch.int64, device=dev)
+        nb = _lib.mc_workspace_bytes(self._arr, n, C.byref(self.options) if self.options else None)
+        if nb == 0:
+            raise McError("mc_workspace_bytes: invalid problem description")
+        self.workspace = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+    def run(self, kernel_events=None):
+        """Enqueue one mc_simulate_projections on the current stream.  kernel_events:
+        optional (hipEvent_t, hipEvent_t) handles recorded around the transport kernel."""
+        opts = self.options
+        if kernel_events is not None:
+            opts = McOptions()
+            if self.options is not None:
+                C.memmove(C.byref(opts), C.byref(self.options), C.sizeof(McOptions))
+            opts.kernel_events[0] = kernel_events[0]
+            opts.kernel_events[1] = kernel_events[1]
+        rc = _lib.mc_simulate_projections(
+            self._arr, len(self.problems), C.byref(opts) if opts else None,
+            self.tally.data_ptr(), self.tally_sq.data_ptr() if self.tally_sq is not None else None,
+            self.fates.data_ptr(), self.energy.data_ptr(), self.counters.data_ptr(),
+            self.events.data_ptr() if self.events is not None else None, self.event_capacity,
+            self.n_events.data_ptr(), self.status.data_ptr(), self.workspace.data_ptr(),
+            self.workspace.numel(), _stream_ptr())
+        _check(rc, "mc_simulate_projections")
+
+    def check_status(self):
+        st = self.status.cpu().numpy()
+        if st[0] & (STATUS_BAD_MU | STATUS_NO_ACTIVITY | STATUS_BAD_ANGLE):
+            raise McError(f"invalid device input (status bits {int(st[0])})")
+        return st
+
+    def tallies(self):
+        """Per-problem tally tensors (int64 Q31.32) shaped [V, 2, nv, nu]."""
+        out, off = [], 0
+        for p, s in zip(self.problems, self.sizes):
+            out.append(self.tally[off:off + s].view(p.tally_shape))
+            off += s
+        return out
+
+    def events_numpy(self) -> np.ndarray:
+        n = min(int(self.n_events.item()), self.event_capacity)
+        if self.events is None or n == 0:
+            return np.zeros(0, dtype=EVENT_DTYPE)
+        raw = self.events[:n].cpu().numpy()
+        return raw.view(EVENT_DTYPE).reshape(-1)
+
+
+def simulate(problems, *, event_capacity: int = 0, want_sq: bool = True, options=None,
+             sync: bool = True) -> Simulator:
+    """One forward run (allocates outputs and workspace)."""
+    sim = Simulator(problems, event_capacity=event_capacity, want_sq=want_sq, options=options)
+    sim.run()
+    if sync:
+        _torch().cuda.synchronize()
+        sim.check_status()
+    return sim
+
+
+def replay(problem: DeviceProblem, views, hists, options=None) -> np.ndarray:
+    """Per-history records for listed (view, history id) pairs of one problem."""
+    torch = _torch()
+    dev = problem.mu.device
+    v = torch.as_tensor(np.ascontiguousarray(views, dtype=np.int32), device=dev)
+    h = torch.as_tensor(np.ascontiguousarray(hists, dtype=np.uint64).view(np.int64), device=dev)
+    n = int(v.numel())
+    rec = torch.zeros((max(n, 1), 5), dtype=torch.int64, device=dev)   # 40-byte records
+    status = torch.zeros(4, dtype=torch.int64, device=dev)
+    arr = problem.c_struct()
+    o = _opts(options)
+    nb = _lib.mc_workspace_bytes(C.byref(arr), 1, C.byref(o) if o else None)
+    if nb == 0:
+        raise McError("mc_workspace_bytes: invalid problem description")
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    rc = _lib.mc_replay_histories(C.byref(arr), C.byref(o) if o else None, v.data_ptr(), h.data_ptr(),
+                                  n, rec.data_ptr(), status.data_ptr(), ws.data_ptr(), nb,
+                                  _stream_ptr())
+    _check(rc, "mc_replay_histories")
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    if st[0] & (STATUS_BAD_MU | STATUS_NO_ACTIVITY | STATUS_BAD_ANGLE):
+        raise McError(f"invalid device input (status bits {int(st[0])})")
+    return rec[:n].cpu().numpy().view(RECORD_DTYPE).reshape(-1)
+
+
+def tally_float(t) -> np.ndarray:
+    """Fixed-point tally -> float64 counts."""
+    return t.cpu().numpy().astype(np.float64) / Q32
+
+
+def adjoint(problem: DeviceProblem, dL_dtally, sim: Optional[Simulator] = None,
+            frac_bits: int = 40, raw: bool = False):
+    """dL/dmu (float64 tensor [nz, ny, nx]) for G = dL_dtally (tally layout).
+
+    sim: the forward Simulator of the same problem; its event list (if it has
+    one) restricts the replay to the tallied histories.  Without it every
+    history of the range is replayed."""
+    torch = _torch()
+    dev = problem.mu.device
+    G = dL_dtally.to(device=dev, dtype=torch.float64).contiguous()
+    if G.numel() != int(np.prod(problem.tally_shape)):
+        raise McError("dL_dtally has the wrong size")
+    grad = torch.empty(problem.mu.shape, dtype=torch.int64, device=dev)
+    status = torch.zeros(4, dtype=torch.int64, device=dev)
+    arr = problem.c_struct()
+    nb = _lib.mc_workspace_bytes(C.byref(arr), 1, None)
+    if nb == 0:
+        raise McError("mc_workspace_bytes: invalid problem description")
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    use_events = sim is not None and sim.events is not None
+    rc = _lib.mc_adjoint_mu(C.byref(arr), None, G.data_ptr(),
+                            sim.events.data_ptr() if use_events else None,
+                            sim.n_events.data_ptr() if use_events else None,
+                            sim.event_capacity if use_events else 0,
+                            grad.data_ptr(), int(frac_bits), status.data_ptr(), ws.data_ptr(), nb,
+                            _stream_ptr())
+    _check(rc, "mc_adjoint_mu")
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    if st[0] & (STATUS_BAD_MU | STATUS_NO_ACTIVITY | STATUS_BAD_ANGLE):
+        raise McError(f"invalid device input (status bits {int(st[0])})")
+    if st[0] & STATUS_GRAD_OVERFLOW:
+        raise McError(f"gradient overflow at frac_bits={frac_bits}; use fewer fractional bits")
+    if st[0] & STATUS_BAD_EVENT:
+        raise McError("an event did not replay to its bin (event list from another problem?)")
+    if use_events and int(sim.n_events.item()) > sim.event_capacity:
+        raise McError("the forward event list overflowed; raise event_capacity")
+    if raw:
+        return grad
+    return grad.to(torch.float64) * (2.0 ** -frac_bits)
+
+
+class MCProject:
+    """torch.autograd.Function: mu -> projection tallies (float64 counts, tally
+    layout), with the replaying adjoint as backward.  Activity and geometry
+    are constants."""
+
+    @staticmethod
+    def apply(mu, problem: DeviceProblem, event_capacity: int = 1 << 20, frac_bits: int = 40):
+        return _mc_project_fn().apply(mu, problem, event_capacity, frac_bits)
+
+
+_FN = None
+
+
+def _mc_project_fn():
+    global _FN
+    if _FN is not None:
+        return _FN
+    torch = _torch()
+
+    class _Fn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, mu, problem, event_capacity, frac_bits):
+            dp = problem.with_(mu=mu.detach().to(torch.float32).contiguous())
+            sim = simulate(dp, event_capacity=event_capacity, want_sq=False)
+            if int(sim.n_events.item()) > event_capacity:
+                raise McError("event list overflow in forward; raise event_capacity")
+            ctx.dp, ctx.sim, ctx.frac_bits = dp, sim, frac_bits
+            return sim.tally.view(dp.tally_shape).to(torch.float64) * (2.0 ** -32)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = adjoint(ctx.dp, grad_out, ctx.sim, ctx.frac_bits)
+            return g.to(torch.float32), None, None, None
+
+    _FN = _Fn
+    return _FN

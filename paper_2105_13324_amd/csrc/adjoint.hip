@@ -1,0 +1,206 @@
+// Adjoint of the projection tallies with respect to the 140 keV attenuation map.
+//
+// A tallied history sampled at mu0 is a path: emission point, Compton vertices,
+// final flight out of the grid.  Under a change of mu its probability density
+// changes by the factor
+//     W_h(mu) = prod_{Compton vertices c} mu_{v_c}/mu0_{v_c}
+//               * exp(-sum_v (mu_v - mu0_v) * lt_{h,v}),
+//     lt_{h,v} = sum over segments of g(E_seg) * (length of the segment in v),
+// (materials are density-scaled water, so the scatter and branch probabilities
+// at a vertex do not depend on the magnitude of mu and cancel).  Hence
+//     dL/dmu_v = sum_h G_{b(h)} * (c_{h,v}/mu0_v - lt_{h,v}),
+// with G = dL/dtally.  The kernels here replay each tallied history from its
+// Philox counter -- no path is stored -- and walk every segment voxel by voxel
+// (Amanatides & Woo 1987 grid traversal), adding -G g(E) len to each crossed
+// voxel and +G/mu0 at each Compton vertex.  Sums are 64-bit fixed point with
+// frac_bits fractional bits: integer atomics, so the result is bit-exact from
+// run to run.
+#include "history.h"
+
+namespace mcs {
+namespace {
+
+__device__ inline void add_fixed(long long* grad, uint32_t v, double val, double scale,
+                                 int64_t* status) {
+    const double s = val * scale;
+    if (!(fabs(s) < 4.0e18)) {
+        atomicOr((unsigned long long*)status, (unsigned long long)MC_STATUS_GRAD_OVERFLOW);
+        return;
+    }
+    atomicAdd((unsigned long long*)(grad + v), (unsigned long long)__double2ll_rn(s));
+}
+
+// Walk the ray a + t d, t in [0, t_end) (t_end = +inf: to the grid exit), adding
+// w * (length in voxel) to every voxel it crosses.  a must be inside the grid.
+__device__ void walk(const Cst& C, float ax, float ay, float az, float dx, float dy, float dz,
+                     float t_end, double w, long long* grad, double scale, int64_t* status) {
+    const float px = ax + C.hx, py = ay + C.hy, pz = az + C.hz;
+    int ix = min(max((int)(px * C.inv_vox), 0), C.nx - 1);
+    int iy = min(max((int)(py * C.inv_vox), 0), C.ny - 1);
+    int iz = min(max((int)(pz * C.inv_vox), 0), C.nz - 1);
+    const int sx = dx > 0.0f ? 1 : -1, sy = dy > 0.0f ? 1 : -1, sz = dz > 0.0f ? 1 : -1;
+    const float inf = __builtin_huge_valf();
+    // parametric distance to the next plane on each axis, and between planes
+    float tx = dx != 0.0f ? (((float)(ix + (dx > 0.0f)) * C.vox) - px) / dx : inf;
+    float ty = dy != 0.0f ? (((float)(iy + (dy > 0.0f)) * C.vox) - py) / dy : inf;
+    float tz = dz != 0.0f ? (((float)(iz + (dz > 0.0f)) * C.vox) - pz) / dz : inf;
+    const float ddx = dx != 0.0f ? C.vox / fabsf(dx) : inf;
+    const float ddy = dy != 0.0f ? C.vox / fabsf(dy) : inf;
+    const float ddz = dz != 0.0f ? C.vox / fabsf(dz) : inf;
+    tx = fmaxf(tx, 0.0f); ty = fmaxf(ty, 0.0f); tz = fmaxf(tz, 0.0f);
+    float t = 0.0f;
+    const int max_iter = C.nx + C.ny + C.nz + 3;
+    for (int it = 0; it < max_iter; ++it) {
+        const float tn = fminf(tx, fminf(ty, tz));
+        const float te = fminf(tn, t_end);
+        const uint32_t v = (uint32_t)ix + (uint32_t)C.nx * ((uint32_t)iy + (uint32_t)C.ny * (uint32_t)iz);
+        if (te > t) add_fixed(grad, v, w * (double)(te - t), scale, status);
+        if (tn >= t_end) return;
+        t = tn;
+        if (tx <= ty && tx <= tz) { ix += sx; tx += ddx; if (ix < 0 || ix >= C.nx) return; }
+        else if (ty <= tz)        { iy += sy; ty += ddy; if (iy < 0 || iy >= C.ny) return; }
+        else                      { iz += sz; tz += ddz; if (iz < 0 || iz >= C.nz) return; }
+    }
+}
+
+__device__ inline double g_of(const Cst& C, float e) {
+    if (e == 140.0f) return 1.0;
+    float a, b;
+    return energy_terms(C, e, a, b);
+}
+
+// Replay one history; if it ends TALLIED in `bin`, walk its path with weight G.
+// walk_now = false: only report the fate/bin (first pass of replay-all mode).
+__device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now, double G,
+                           long long* grad, double scale, int64_t* status, uint32_t& bin_out) {
+    Lane L;
+    L.hist = hist; L.view = view; L.work = 0;
+    L.state = S_EMIT0; L.n = 0; L.a = 0; L.n_scatter = 0; L.emit_voxel = 0; L.e = 0.0f;
+    const float2 cs = C.views[view];
+    L.vc = cs.x; L.vs = cs.y;
+    Acc A;
+    acc_zero(A);
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;   // start of the current segment
+    for (;;) {
+        uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
+        counter_of(L, c2, c3);
+        philox10(c0, c1, c2, c3, C.seed, C.pid);
+        const int before = L.state;
+        const float e_flight = L.e;
+        int iu = -1, iv = -1;
+        const int fate = advance(C, L, c0, c1, c2, c3, A, iu, iv);
+        if (before == S_EMIT1) { sx = L.x; sy = L.y; sz = L.z; }
+        if (fate == R_RUNNING) {
+            if (walk_now && before == S_STEP && L.state == S_KAHN) {
+                // Compton vertex at L.x: close the segment, add the collision term
+                const float ex = L.x - sx, ey = L.y - sy, ez = L.z - sz;
+                const float len = ex * L.dx + ey * L.dy + ez * L.dz;
+                walk(C, sx, sy, sz, L.dx, L.dy, L.dz, len, -G * g_of(C, e_flight), grad, scale, status);
+                const int ix = min((int)((L.x + C.hx) * C.inv_vox), C.nx - 1);
+                const int iy = min((int)((L.y + C.hy) * C.inv_vox), C.ny - 1);
+                const int iz = min((int)((L.z + C.hz) * C.inv_vox), C.nz - 1);
+                const uint32_t v = (uint32_t)ix + (uint32_t)C.nx * ((uint32_t)iy + (uint32_t)C.ny * (uint32_t)iz);
+                add_fixed(grad, v, G / (double)C.mu[v], scale, status);
+                sx = L.x; sy = L.y; sz = L.z;
+            }
+            continue;
+        }
+        if (fate == MC_TALLIED) {
+            const int cls = L.n_scatter > 0 ? 1 : 0;
+            bin_out = (uint32_t)((((uint32_t)L.view * 2u + cls) * (uint32_t)C.nv + iv) * (uint32_t)C.nu + iu);
+            if (walk_now)
+                walk(C, sx, sy, sz, L.dx, L.dy, L.dz, __builtin_huge_valf(), -G * g_of(C, L.e),
+                     grad, scale, status);
+        }
+        return fate;
+    }
+}
+
+__device__ inline void split_work(const Cst& C, uint64_t g, int& view, uint64_t& hist) {
+    const uint64_t big = C.q_per_view + 1;
+    if (g < C.r_extra * big) { view = (int)(g / big); hist = g - (uint64_t)view * big; }
+    else {
+        const uint64_t g2 = g - C.r_extra * big;
+        const uint64_t v = C.r_extra + g2 / C.q_per_view;
+        view = (int)v;
+        hist = g2 - (v - C.r_extra) * C.q_per_view;
+    }
+}
+
+// One listed tallied history per lane.
+__global__ __launch_bounds__(64) void k_adjoint_events(const ProbDesc* __restrict__ d,
+                                                       const mc_event* __restrict__ events,
+                                                       const unsigned long long* __restrict__ n_events,
+                                                       uint64_t capacity, const double* __restrict__ dL,
+                                                       long long* grad, double scale, int64_t* status) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = min((uint64_t)*n_events, capacity);
+    if (i >= n) return;
+    const Cst C = load_cst(d);
+    if (C.flags) return;
+    const mc_event ev = events[i];
+    if (ev.work >= d->work_count) { atomicOr((unsigned long long*)status, (unsigned long long)MC_STATUS_BAD_EVENT); return; }
+    const double G = dL[C.tally_offset + ev.bin];
+    if (G == 0.0) return;
+    int view; uint64_t hist;
+    split_work(C, C.work_begin + ev.work, view, hist);
+    uint32_t bin = 0;
+    const int fate = replay_path(C, hist, view, true, G, grad, scale, status, bin);
+    if (fate != MC_TALLIED || bin != ev.bin)
+        atomicOr((unsigned long long*)status, (unsigned long long)MC_STATUS_BAD_EVENT);
+}
+
+// Every history of the call's range: replay, and walk the tallied ones.
+__global__ __launch_bounds__(256) void k_adjoint_all(const ProbDesc* __restrict__ d,
+                                                     const double* __restrict__ dL, long long* grad,
+                                                     double scale, int64_t* status) {
+    const Cst C = load_cst(d);
+    if (C.flags) return;
+    const uint64_t cnt = d->work_count;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        int view; uint64_t hist;
+        split_work(C, C.work_begin + i, view, hist);
+        uint32_t bin = 0;
+        const int fate = replay_path(C, hist, view, false, 0.0, grad, scale, status, bin);
+        if (fate != MC_TALLIED) continue;
+        const double G = dL[C.tally_offset + bin];
+        if (G == 0.0) continue;
+        replay_path(C, hist, view, true, G, grad, scale, status, bin);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_grad(long long* grad, uint64_t n, int64_t* status) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t i = tid; i < n; i += (uint64_t)gridDim.x * blockDim.x) grad[i] = 0;
+    if (tid < 4) status[tid] = 0;
+}
+
+__global__ void k_adjoint_finalize(const ProbDesc* __restrict__ d, int64_t* status) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) status[0] |= (int64_t)d->flags;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const ProbDesc* d, const mc_event* events, const uint64_t* n_events,
+                          uint64_t capacity, const double* dL, int64_t* grad, uint64_t nvox,
+                          int frac_bits, int64_t* status, int n_cu, hipStream_t s) {
+    uint64_t gz = (nvox + 255) / 256;
+    if (gz > 4096) gz = 4096;
+    if (gz < 1) gz = 1;
+    k_zero_grad<<<(int)gz, 256, 0, s>>>((long long*)grad, nvox, status);
+    const double scale = ldexp(1.0, frac_bits);
+    if (events) {
+        if (capacity > 0) {
+            const uint64_t g = (capacity + 63) / 64;
+            k_adjoint_events<<<(int)g, 64, 0, s>>>(d, events, (const unsigned long long*)n_events,
+                                                   capacity, dL, (long long*)grad, scale, status);
+        }
+    } else {
+        k_adjoint_all<<<n_cu * 8, 256, 0, s>>>(d, dL, (long long*)grad, scale, status);
+    }
+    k_adjoint_finalize<<<1, 64, 0, s>>>(d, status);
+    return hipGetLastError();
+}
+
+}  // namespace mcs

@@ -1,0 +1,277 @@
+// Host side of the C ABI: argument checks, workspace layout, launches.
+// No device memory is allocated here; no exception leaves this file.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mc_internal.h"
+
+using namespace mcs;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+constexpr uint32_t DEFAULT_MAX_STEPS = 1000;
+constexpr int DEFAULT_BLOCK = 256;
+constexpr int DEFAULT_HIST_PER_LANE = 16;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+double kn_bracket(double e) {
+    // Klein-Nishina total cross-section per electron over 2 pi r_e^2.
+    const double k = e / 510.99895;
+    const double a = 1.0 + 2.0 * k;
+    const double la = std::log(a);
+    return (1.0 + k) / (k * k) * (2.0 * (1.0 + k) / a - la / k) + la / (2.0 * k)
+           - (1.0 + 3.0 * k) / (a * a);
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// Host-visible checks of one problem.
+bool check_problem(const mc_problem& p) {
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1) return false;
+    const uint64_t nvox = (uint64_t)p.nx * p.ny * p.nz;
+    if (nvox >= (1ull << 31)) return false;
+    if (p.source_mode != MC_SOURCE_VOXELS && p.source_mode != MC_SOURCE_POINT) return false;
+    if (!finite_pos(p.voxel_cm)) return false;
+    if (!p.mu140 || !p.activity || !p.angle_rad) return false;
+    if (p.n_views < 1 || p.nu < 1 || p.nv < 1) return false;
+    if ((uint64_t)p.nu * p.nv * 2 * p.n_views >= (1ull << 32)) return false;
+    if (!finite_pos(p.pixel_cm) || !std::isfinite(p.radius_cm)) return false;
+    const double lx = p.nx * p.voxel_cm, ly = p.ny * p.voxel_cm;
+    if (p.radius_cm <= 0.5 * std::sqrt(lx * lx + ly * ly)) return false;   // plane outside the grid
+    if (!(p.accept_half_angle_rad > 0.0 && p.accept_half_angle_rad < 1.5707963267948966)) return false;
+    if (!std::isfinite(p.e_lo_kev) || !std::isfinite(p.e_hi_kev) || p.e_lo_kev > p.e_hi_kev) return false;
+    if (!finite_pos(p.e_cut_kev) || p.e_cut_kev > 140.0) return false;
+    if (!(p.pe_fraction >= 0.0 && p.pe_fraction <= 1.0)) return false;
+    if (p.n_histories < 1) return false;
+    if (p.n_histories / (uint64_t)p.n_views >= (1ull << 32) - 1) return false;
+    if (p.history_offset > p.n_histories) return false;
+    const uint64_t cnt = p.history_count ? p.history_count : p.n_histories - p.history_offset;
+    if (p.history_offset + cnt > p.n_histories) return false;
+    if (p.image_factor < 0) return false;
+    if (p.image_factor > 0 &&
+        (p.nx % p.image_factor || p.ny % p.image_factor || p.nz % p.image_factor)) return false;
+    return true;
+}
+
+struct Layout {
+    size_t desc, prefix, state;
+    std::vector<size_t> q, cdf, bsum, guide, views;
+    size_t total;
+};
+
+bool plan(const mc_problem* probs, int n, Layout& L) {
+    size_t off = 0;
+    L.desc = off;   off += align256(sizeof(ProbDesc) * (size_t)n);
+    L.prefix = off; off += align256(sizeof(uint64_t) * 2 * ((size_t)n + 1));
+    L.state = off;  off += align256(sizeof(CallState));
+    L.q.resize(n); L.cdf.resize(n); L.bsum.resize(n); L.guide.resize(n); L.views.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const mc_problem& p = probs[i];
+        const uint64_t nvox = (uint64_t)p.nx * p.ny * p.nz;
+        L.q[i] = off;     off += align256(4 * nvox);
+        L.cdf[i] = off;   off += align256(8 * nvox);
+        L.bsum[i] = off;  off += align256(8 * ((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS));
+        L.guide[i] = off; off += align256(4 * (guide_capacity(nvox) + 1));
+        L.views[i] = off; off += align256(8 * (size_t)p.n_views);
+    }
+    L.total = off;
+    return true;
+}
+
+ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64_t tally_offset) {
+    ProbDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.source_mode = p.source_mode;
+    const double vox = p.voxel_cm;
+    d.vox = (float)vox;
+    d.inv_vox = (float)(1.0 / vox);
+    d.lx = (float)(p.nx * vox); d.ly = (float)(p.ny * vox); d.lz = (float)(p.nz * vox);
+    d.hx = (float)(0.5 * p.nx * vox); d.hy = (float)(0.5 * p.ny * vox); d.hz = (float)(0.5 * p.nz * vox);
+    d.nu = p.nu; d.nv = p.nv; d.n_views = p.n_views;
+    d.image_factor = p.image_factor;
+    d.pix = (float)p.pixel_cm;
+    d.inv_pix = (float)(1.0 / p.pixel_cm);
+    d.radius = (float)p.radius_cm;
+    d.cos_alpha = (float)std::cos(p.accept_half_angle_rad);
+    d.wu = (float)(p.nu * p.pixel_cm);
+    d.wv = (float)(p.nv * p.pixel_cm);
+    d.e_lo = (float)p.e_lo_kev; d.e_hi = (float)p.e_hi_kev; d.e_cut = (float)p.e_cut_kev;
+    d.f_pe = (float)p.pe_fraction;
+    d.max_steps = p.max_steps ? p.max_steps : DEFAULT_MAX_STEPS;
+    d.seed = p.seed; d.problem_id = p.problem_id;
+    if (p.image_factor > 0) { d.img_nx = p.nx / p.image_factor; d.img_ny = p.ny / p.image_factor; }
+    d.kn140 = kn_bracket(140.0);
+    d.nvox = (uint64_t)p.nx * p.ny * p.nz;
+    d.q_per_view = p.n_histories / (uint64_t)p.n_views;
+    d.r_extra = p.n_histories % (uint64_t)p.n_views;
+    d.work_begin = p.history_offset;
+    d.work_count = p.history_count ? p.history_count : p.n_histories - p.history_offset;
+    d.tally_offset = tally_offset;
+    d.mu = p.mu140; d.act = p.activity; d.angles = p.angle_rad;
+    d.q32 = (uint32_t*)(ws + L.q[i]);
+    d.cdf = (uint64_t*)(ws + L.cdf[i]);
+    d.block_sums = (uint64_t*)(ws + L.bsum[i]);
+    d.guide = (uint32_t*)(ws + L.guide[i]);
+    d.views = (float2*)(ws + L.views[i]);
+    return d;
+}
+
+int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return MC_EDEVICE;
+}
+
+void resolve(const mc_options* opt, int& block, int& hpl, int& bpc) {
+    block = DEFAULT_BLOCK;
+    hpl = DEFAULT_HIST_PER_LANE;
+    bpc = 0;
+    if (opt) {
+        if (opt->block_size > 0) block = opt->block_size;
+        if (opt->hist_per_lane > 0) hpl = opt->hist_per_lane;
+        if (opt->blocks_per_cu > 0) bpc = opt->blocks_per_cu;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mc_workspace_bytes(const mc_problem* problems, int32_t n_problems, const mc_options*) {
+    if (!problems || n_problems < 1) return 0;
+    for (int i = 0; i < n_problems; ++i) if (!check_problem(problems[i])) return 0;
+    Layout L;
+    plan(problems, n_problems, L);
+    return L.total;
+}
+
+int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, const mc_options* opt,
+                            int64_t* tally, int64_t* tally_sq, int64_t* fates, int64_t* energy,
+                            int64_t* counters, mc_event* events, uint64_t event_capacity,
+                            uint64_t* n_events, int64_t* status, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+    if (!problems || n_problems < 1 || !tally || !fates || !status || !workspace) return MC_EINVAL;
+    if (events && !n_events) return MC_EINVAL;
+    for (int i = 0; i < n_problems; ++i) if (!check_problem(problems[i])) return MC_EINVAL;
+    int block, hpl, bpc;
+    resolve(opt, block, hpl, bpc);
+    if (block < 64 || block > 256 || block % 64 != 0) return MC_EINVAL;
+    if (hpl < 1 || hpl > (1 << 20)) return MC_EINVAL;
+    Layout L;
+    plan(problems, n_problems, L);
+    if (workspace_bytes < L.total) return MC_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    ProbDesc* d_desc = (ProbDesc*)(ws + L.desc);
+    uint64_t tally_elems = 0;
+    for (int i = 0; i < n_problems; ++i) {
+        const mc_problem& p = problems[i];
+        const ProbDesc h = host_desc(p, ws, L, i, tally_elems);
+        tally_elems += (uint64_t)p.n_views * 2 * p.nv * p.nu;
+        hipError_t e = launch_staging(d_desc + i, h, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    const uint32_t chunk = (uint32_t)(64 * hpl);
+    hipError_t e = launch_prepare_call(d_desc, n_problems, (uint64_t*)(ws + L.prefix),
+                                       (CallState*)(ws + L.state), status,
+                                       (unsigned long long*)n_events, tally, tally_elems, tally_sq,
+                                       fates, energy, counters, chunk, st);
+    if (e != hipSuccess) return hip_fail(e);
+    int dev = 0, n_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e);
+    if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return hip_fail(e);
+    if (bpc <= 0) bpc = transport_blocks_per_cu(block);
+    TransportArgs a;
+    a.descs = d_desc;
+    a.n_problems = n_problems;
+    a.work_prefix = (const uint64_t*)(ws + L.prefix);
+    a.total_work = 0;
+    a.chunk = chunk;
+    a.state = (CallState*)(ws + L.state);
+    a.tally = tally;
+    a.tally_sq = tally_sq;
+    a.fates = fates;
+    a.energy = energy;
+    a.counters = counters;
+    a.events = events;
+    a.event_capacity = events ? event_capacity : 0;
+    a.n_events = (unsigned long long*)n_events;
+    a.status = status;
+    hipEvent_t ev0 = opt ? (hipEvent_t)opt->kernel_events[0] : nullptr;
+    hipEvent_t ev1 = opt ? (hipEvent_t)opt->kernel_events[1] : nullptr;
+    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return hip_fail(e);
+    e = launch_transport(a, n_cu * bpc, block, st);
+    if (e != hipSuccess) return hip_fail(e);
+    if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return hip_fail(e);
+    return MC_OK;
+}
+
+int mc_replay_histories(const mc_problem* problem, const mc_options* opt, const int32_t* views,
+                        const uint64_t* hists, int64_t n, mc_record* records, int64_t* status,
+                        void* workspace, size_t workspace_bytes, void* stream) {
+    if (!problem || !status || !workspace || n < 0) return MC_EINVAL;
+    if (n > 0 && (!views || !hists || !records)) return MC_EINVAL;
+    if (!check_problem(*problem)) return MC_EINVAL;
+    int block, hpl, bpc;
+    resolve(opt, block, hpl, bpc);
+    if (block < 64 || block > 256 || block % 64 != 0) return MC_EINVAL;
+    Layout L;
+    plan(problem, 1, L);
+    if (workspace_bytes < L.total) return MC_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    ProbDesc* d_desc = (ProbDesc*)(ws + L.desc);
+    const ProbDesc h = host_desc(*problem, ws, L, 0, 0);
+    hipError_t e = launch_staging(d_desc, h, st);
+    if (e != hipSuccess) return hip_fail(e);
+    e = launch_replay(d_desc, views, hists, n, records, status, block, st);
+    if (e != hipSuccess) return hip_fail(e);
+    return MC_OK;
+}
+
+int mc_adjoint_mu(const mc_problem* problem, const mc_options*, const double* dL_dtally,
+                  const mc_event* events, const uint64_t* n_events, uint64_t event_capacity,
+                  int64_t* dL_dmu, int32_t frac_bits, int64_t* status, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+    if (!problem || !dL_dtally || !dL_dmu || !status || !workspace) return MC_EINVAL;
+    if (events && !n_events) return MC_EINVAL;
+    if (frac_bits < 0 || frac_bits > 62) return MC_EINVAL;
+    if (!check_problem(*problem)) return MC_EINVAL;
+    Layout L;
+    plan(problem, 1, L);
+    if (workspace_bytes < L.total) return MC_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    ProbDesc* d_desc = (ProbDesc*)(ws + L.desc);
+    const ProbDesc h = host_desc(*problem, ws, L, 0, 0);
+    hipError_t e = launch_staging(d_desc, h, st);
+    if (e != hipSuccess) return hip_fail(e);
+    int dev = 0, n_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e);
+    if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return hip_fail(e);
+    e = launch_adjoint(d_desc, events, n_events, events ? event_capacity : 0, dL_dtally, dL_dmu,
+                       h.nvox, frac_bits, status, n_cu, st);
+    if (e != hipSuccess) return hip_fail(e);
+    return MC_OK;
+}
+
+const char* mc_error_string(int code) {
+    switch (code) {
+        case MC_OK: return "ok";
+        case MC_EINVAL: return "invalid argument";
+        case MC_ENOMEM: return "workspace or capacity too small";
+        case MC_EDEVICE: return "HIP error";
+        case MC_EOVERFLOW: return "fixed-point overflow";
+        case MC_ECAPPED: return "history step cap reached";
+        default: return "unknown error";
+    }
+}
+
+int mc_last_hip_error(void) { return g_last_hip; }
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal definitions shared by the HIP translation units of libmcspect.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mcspect.h"
+
+namespace mcs {
+
+// Everything a kernel needs about one problem.  Host-filled fields come from
+// mc_problem; the staging kernels fill the rest on the device.
+struct ProbDesc {
+    // grid
+    int32_t nx, ny, nz, source_mode;
+    float hx, hy, hz, vox;          // half widths, voxel edge
+    float lx, ly, lz, inv_vox;      // full widths, 1/voxel
+    // camera
+    int32_t nu, nv, n_views, image_factor;
+    float pix, inv_pix, radius, cos_alpha;
+    float wu, wv, e_lo, e_hi;
+    float e_cut, f_pe;
+    uint32_t max_steps, pad0;
+    uint32_t seed, problem_id;
+    int32_t img_nx, img_ny;
+    double kn140;                   // Klein-Nishina bracket at 140 keV
+    uint64_t nvox;
+    uint64_t q_per_view, r_extra;   // N / V and N mod V
+    uint64_t work_begin;            // first work index of this call (within the problem)
+    uint64_t work_count;            // work indices of this call
+    uint64_t tally_offset;          // element offset of this problem's tally block
+    // inputs and staged tables (device pointers)
+    const float* mu;
+    const uint32_t* act;
+    const double* angles;
+    uint32_t* q32;                  // accept thresholds, linear layout
+    uint64_t* cdf;                  // inclusive prefix sum of activity
+    uint64_t* block_sums;           // scan scratch
+    uint32_t* guide;                // guide table, n_buckets + 1 entries
+    float2* views;                  // (cos, sin) per view
+    // filled on the device by staging
+    uint32_t mu_hat_bits;           // max mu, as float bits (mu >= 0)
+    uint32_t flags;                 // MC_STATUS_* bits found during staging
+    uint64_t total;                 // sum of activity
+    uint32_t shift;                 // bucket = t >> shift
+    uint32_t n_buckets;
+};
+
+constexpr int SCAN_ITEMS = 4096;    // activity values per scan block
+constexpr int SCAN_THREADS = 256;
+
+// Global counters of one call (in the workspace).
+struct CallState {
+    unsigned long long next_chunk;
+    unsigned long long pad[7];
+};
+
+// Host launchers (staging.hip)
+hipError_t launch_staging(ProbDesc* d_desc, const ProbDesc& h_desc, hipStream_t s);
+uint64_t guide_capacity(uint64_t nvox);   // power of two >= nvox
+
+// Host launchers (transport.hip)
+struct TransportArgs {
+    const ProbDesc* descs;
+    int32_t n_problems;
+    const uint64_t* work_prefix;    // [n_problems + 1], device
+    uint64_t total_work;
+    uint32_t chunk;                 // work indices per claim (per wave)
+    CallState* state;
+    int64_t* tally;
+    int64_t* tally_sq;
+    int64_t* fates;
+    int64_t* energy;
+    int64_t* counters;
+    mc_event* events;
+    uint64_t event_capacity;
+    unsigned long long* n_events;
+    int64_t* status;
+};
+hipError_t launch_transport(const TransportArgs& a, int grid, int block, hipStream_t s);
+hipError_t launch_replay(const ProbDesc* d_desc, const int32_t* views, const uint64_t* hists,
+                         int64_t n, mc_record* out, int64_t* status, int block, hipStream_t s);
+hipError_t launch_prepare_call(const ProbDesc* descs, int32_t n_problems, uint64_t* work_prefix,
+                               CallState* state, int64_t* status, unsigned long long* n_events,
+                               int64_t* tally, uint64_t tally_elems, int64_t* tally_sq,
+                               int64_t* fates, int64_t* energy, int64_t* counters,
+                               uint32_t chunk, hipStream_t s);
+
+// Host launcher (adjoint.hip)
+hipError_t launch_adjoint(const ProbDesc* d, const mc_event* events, const uint64_t* n_events,
+                          uint64_t capacity, const double* dL, int64_t* grad, uint64_t nvox,
+                          int frac_bits, int64_t* status, int n_cu, hipStream_t s);
+
+// Occupancy of the transport kernel (blocks per CU at this block size).
+int transport_blocks_per_cu(int block);
+
+}  // namespace mcs

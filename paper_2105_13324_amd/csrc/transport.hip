@@ -1,0 +1,319 @@
+// Photon transport kernels for gfx950.
+//
+// One photon history per lane, followed from emission to absorption, energy
+// cut or escape (history-by-history Monte Carlo, paper Sec. 2), then through
+// an ideal parallel-hole collimator into a photopeak-window projection tally
+// (Sec. 3).
+//
+// Execution model
+//  * Every iteration of the main loop draws exactly one Philox4x32-10 block
+//    per active lane.  The lane's state (emission part 1/2, tentative
+//    collision, Kahn attempt) picks the counter and what the four words mean,
+//    so the dominant cost -- the 10 Philox rounds -- runs with all lanes in
+//    lockstep, and only the short per-state tails diverge.
+//  * A lane whose history ends takes the next work index at once (lane
+//    refill), from a chunk its wavefront claimed with one global atomic.
+//    Chunks never straddle problems, and a wavefront finishes the histories of
+//    one problem before it starts another, so every problem constant is
+//    wave-uniform (scalar registers) even in the batched launch.
+//  * Fate counts, energies and work counters stay in registers and are
+//    reduced across the wavefront before one atomic per value; tallies are
+//    64-bit fixed-point integer atomics, so every sum is exact and
+//    order-independent: results are bit-identical from run to run.
+//  * Woodcock tracking: one 4-byte threshold gather per tentative collision;
+//    the accept test is an integer compare.
+#include "history.h"
+
+namespace mcs {
+namespace {
+
+__device__ __forceinline__ uint32_t wsum32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+    return v;
+}
+__device__ __forceinline__ long long wsum64(long long v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Wave-wide flush of one problem's accumulators (all 64 lanes must call).
+__device__ inline void flush(Acc& A, int p, const TransportArgs& T, int lane) {
+    uint32_t f[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) f[i] = wsum32(A.fate[i]);
+    const uint32_t nt = wsum32(A.n_tent), nr = wsum32(A.n_real), nk = wsum32(A.n_kahn),
+                   nh = wsum32(A.n_hist);
+    const long long ed = wsum64(A.e_dep), ee = wsum64(A.e_esc), ec = wsum64(A.e_cap);
+    if (lane == 0 && nh > 0) {
+        unsigned long long* fa = (unsigned long long*)(T.fates + (size_t)p * MC_N_FATES);
+#pragma unroll
+        for (int i = 0; i < 7; ++i) if (f[i]) atomicAdd(fa + i, (unsigned long long)f[i]);
+        if (T.energy) {
+            unsigned long long* ea = (unsigned long long*)(T.energy + (size_t)p * 4);
+            atomicAdd(ea + 0, (unsigned long long)ed);
+            atomicAdd(ea + 1, (unsigned long long)ee);
+            atomicAdd(ea + 2, (unsigned long long)ec);
+        }
+        if (T.counters) {
+            unsigned long long* ca = (unsigned long long*)(T.counters + (size_t)p * 4);
+            atomicAdd(ca + 0, (unsigned long long)nt);
+            atomicAdd(ca + 1, (unsigned long long)nr);
+            atomicAdd(ca + 2, (unsigned long long)nk);
+            atomicAdd(ca + 3, (unsigned long long)nh);
+        }
+        if (f[MC_CAPPED_FATE]) {
+            atomicOr((unsigned long long*)T.status, (unsigned long long)MC_STATUS_CAPPED);
+            atomicAdd((unsigned long long*)(T.status + 1), (unsigned long long)f[MC_CAPPED_FATE]);
+        }
+    }
+    acc_zero(A);
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Persistent transport: waves claim chunks of work until none are left.
+__global__ __launch_bounds__(256) void k_transport(TransportArgs T) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lane_lt = (1ull << lane) - 1ull;
+    const uint64_t full = __ballot(1);   // lanes of this wavefront
+    // chunk bookkeeping (wave-uniform)
+    uint64_t c_next = 0, c_end = 0;     // problem-local work indices
+    int p = -1;
+    bool exhausted = false, have_pending = false;
+    uint64_t pending = 0;
+    Cst C;
+    Lane L;
+    L.state = S_IDLE;
+    Acc A;
+    acc_zero(A);
+    // chunk prefix lives after the work prefix: [n_problems + 1] entries
+    const uint64_t* __restrict__ chunk_prefix = T.work_prefix + (T.n_problems + 1);
+    const uint64_t n_chunks = chunk_prefix[T.n_problems];
+
+    for (;;) {
+        uint64_t need = __ballot(L.state == S_IDLE);
+        while (need != 0 && !exhausted) {
+            if (c_next >= c_end) {
+                if (!have_pending) {
+                    unsigned long long base = 0;
+                    if (lane == 0) base = atomicAdd(&T.state->next_chunk, 1ull);
+                    pending = uniform64(base);
+                    have_pending = true;
+                    if (pending >= n_chunks) { exhausted = true; break; }
+                }
+                // problem of the pending chunk (uniform binary search)
+                int lo = 0, hi = T.n_problems - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (chunk_prefix[mid] <= pending) lo = mid; else hi = mid - 1;
+                }
+                const int np = __builtin_amdgcn_readfirstlane(lo);
+                if (np != p) {
+                    if (need != full) break;       // drain problem p first
+                    if (p >= 0) flush(A, p, T, lane);
+                    p = np;
+                    C = load_cst(T.descs + p);
+                }
+                const uint64_t local_chunk = pending - chunk_prefix[p];
+                const uint64_t cnt = T.work_prefix[p + 1] - T.work_prefix[p];
+                c_next = local_chunk * T.chunk;
+                c_end = min(c_next + T.chunk, cnt);
+                have_pending = false;
+                if (C.flags != 0) { c_next = c_end; continue; }   // staging found bad input
+            }
+            const uint64_t avail = c_end - c_next;
+            const uint32_t rank = __popcll(need & lane_lt);
+            if (L.state == S_IDLE && rank < avail) {
+                const uint64_t local = c_next + rank;
+                begin_history(C, L, C.work_begin + local, T.work_prefix[p] + local);
+            }
+            const uint64_t took = min((uint64_t)__popcll(need), avail);
+            c_next += took;
+            need = __ballot(L.state == S_IDLE);
+        }
+        if (exhausted && __ballot(L.state != S_IDLE) == 0) break;
+        if (L.state == S_IDLE) continue;
+
+        uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
+        counter_of(L, c2, c3);
+        philox10(c0, c1, c2, c3, C.seed, C.pid);
+        int iu = -1, iv = -1;
+        const int fate = advance(C, L, c0, c1, c2, c3, A, iu, iv);
+        if (fate != R_RUNNING) {
+            // constant indices keep the counters in registers
+            switch (fate) {
+                case MC_ABSORBED: A.fate[MC_ABSORBED]++; break;
+                case MC_CUT: A.fate[MC_CUT]++; break;
+                case MC_ESCAPED: A.fate[MC_ESCAPED]++; break;
+                case MC_ESCAPED_FOV: A.fate[MC_ESCAPED_FOV]++; break;
+                case MC_OUT_OF_WINDOW: A.fate[MC_OUT_OF_WINDOW]++; break;
+                case MC_TALLIED: A.fate[MC_TALLIED]++; break;
+                default: A.fate[MC_CAPPED_FATE]++; break;
+            }
+            A.n_hist++;
+            if (fate == MC_TALLIED) {
+                const int cls = L.n_scatter > 0 ? 1 : 0;
+                const uint32_t bin = (uint32_t)((((uint32_t)L.view * 2u + cls) * (uint32_t)C.nv + iv) *
+                                                (uint32_t)C.nu + iu);
+                const size_t gb = C.tally_offset + bin;
+                atomicAdd((unsigned long long*)(T.tally + gb), 1ull << 32);
+                if (T.tally_sq) atomicAdd((unsigned long long*)(T.tally_sq + gb), 1ull << 32);
+                if (T.n_events) {
+                    const unsigned long long idx = atomicAdd(T.n_events, 1ull);
+                    if (T.events && idx < T.event_capacity) {
+                        mc_event ev;
+                        ev.work = L.work;
+                        ev.bin = bin;
+                        ev.emit_voxel = L.emit_voxel;
+                        T.events[idx] = ev;
+                    }
+                }
+            }
+            L.state = S_IDLE;
+        }
+    }
+    if (p >= 0) flush(A, p, T, lane);
+}
+
+// Replay: one listed history per lane, run to its end, one record out.
+__global__ __launch_bounds__(256) void k_replay(const ProbDesc* __restrict__ d,
+                                                const int32_t* __restrict__ views,
+                                                const uint64_t* __restrict__ hists, int64_t n,
+                                                mc_record* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const Cst C = load_cst(d);
+    if (i >= n) return;
+    Lane L;
+    L.hist = hists[i];
+    L.view = views[i];
+    L.work = 0;
+    L.state = S_EMIT0;
+    L.n = 0; L.a = 0; L.n_scatter = 0; L.emit_voxel = 0;
+    L.e = 0.0f;
+    const bool view_ok = L.view >= 0 && L.view < d->n_views;
+    const float2 cs = view_ok ? C.views[L.view] : make_float2(1.0f, 0.0f);
+    L.vc = cs.x; L.vs = cs.y;
+    Acc A;
+    acc_zero(A);
+    mc_record r;
+    r.fate = -1; r.iu = -1; r.iv = -1;
+    if (C.flags == 0 && view_ok) {
+        for (;;) {
+            uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
+            counter_of(L, c2, c3);
+            philox10(c0, c1, c2, c3, C.seed, C.pid);
+            int iu = -1, iv = -1;
+            const int fate = advance(C, L, c0, c1, c2, c3, A, iu, iv);
+            if (fate != R_RUNNING) {
+                r.fate = fate;
+                r.iu = iu;
+                r.iv = iv;
+                break;
+            }
+        }
+    }
+    r.view = L.view;
+    r.n_scatter = L.n_scatter;
+    r.n_tent = (int32_t)A.n_tent;
+    r.emit_voxel = (int32_t)L.emit_voxel;
+    r.cls = L.n_scatter > 0 ? 1 : 0;
+    r.e_final = (double)L.e;
+    out[i] = r;
+}
+
+// Per-call preparation: zero outputs and counters, work and chunk prefixes.
+__global__ __launch_bounds__(256) void k_prepare(const ProbDesc* __restrict__ descs, int n_problems,
+                                                 uint64_t* work_prefix, uint32_t chunk,
+                                                 CallState* state, int64_t* status,
+                                                 unsigned long long* n_events,
+                                                 int64_t* tally, uint64_t tally_elems,
+                                                 int64_t* tally_sq, int64_t* fates, int64_t* energy,
+                                                 int64_t* counters) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = tid; i < tally_elems; i += stride) {
+        tally[i] = 0;
+        if (tally_sq) tally_sq[i] = 0;
+    }
+    for (uint64_t i = tid; i < (uint64_t)n_problems * MC_N_FATES; i += stride) fates[i] = 0;
+    for (uint64_t i = tid; i < (uint64_t)n_problems * 4; i += stride) {
+        if (energy) energy[i] = 0;
+        if (counters) counters[i] = 0;
+    }
+    if (tid == 0) {
+        uint64_t w = 0, c = 0;
+        uint64_t* chunk_prefix = work_prefix + (n_problems + 1);
+        for (int p = 0; p < n_problems; ++p) {
+            work_prefix[p] = w;
+            chunk_prefix[p] = c;
+            const uint64_t cnt = descs[p].work_count;
+            w += cnt;
+            c += (cnt + chunk - 1) / chunk;
+        }
+        work_prefix[n_problems] = w;
+        chunk_prefix[n_problems] = c;
+        state->next_chunk = 0;
+        status[0] = 0; status[1] = 0; status[2] = 0; status[3] = 0;
+        if (n_events) *n_events = 0;
+    }
+}
+
+// After transport: fold staging flags and list overflow into status.
+__global__ void k_finalize(const ProbDesc* __restrict__ descs, int n_problems, int64_t* status,
+                           const unsigned long long* n_events, uint64_t capacity) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint64_t f = 0;
+    for (int p = 0; p < n_problems; ++p) f |= descs[p].flags;
+    if (n_events && capacity != UINT64_MAX && *n_events > capacity) f |= MC_STATUS_LIST_OVERFLOW;
+    status[0] |= (int64_t)f;
+}
+
+__global__ void k_zero_status(int64_t* status) {
+    if (blockIdx.x == 0 && threadIdx.x < 4) status[threadIdx.x] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_prepare_call(const ProbDesc* descs, int32_t n_problems, uint64_t* work_prefix,
+                               CallState* state, int64_t* status, unsigned long long* n_events,
+                               int64_t* tally, uint64_t tally_elems, int64_t* tally_sq,
+                               int64_t* fates, int64_t* energy, int64_t* counters, uint32_t chunk,
+                               hipStream_t s) {
+    uint64_t g = (tally_elems + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    k_prepare<<<(int)g, 256, 0, s>>>(descs, n_problems, work_prefix, chunk, state, status, n_events,
+                                     tally, tally_elems, tally_sq, fates, energy, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_transport(const TransportArgs& a, int grid, int block, hipStream_t s) {
+    k_transport<<<grid, block, 0, s>>>(a);
+    // without a list the count is informational and cannot overflow
+    k_finalize<<<1, 64, 0, s>>>(a.descs, a.n_problems, a.status, a.n_events,
+                                a.events ? a.event_capacity : UINT64_MAX);
+    return hipGetLastError();
+}
+
+hipError_t launch_replay(const ProbDesc* d_desc, const int32_t* views, const uint64_t* hists,
+                         int64_t n, mc_record* out, int64_t* status, int block, hipStream_t s) {
+    k_zero_status<<<1, 64, 0, s>>>(status);
+    if (n > 0) {
+        const int64_t g = (n + block - 1) / block;
+        k_replay<<<(int)g, block, 0, s>>>(d_desc, views, hists, n, out);
+    }
+    k_finalize<<<1, 64, 0, s>>>(d_desc, 1, status, nullptr, 0);
+    return hipGetLastError();
+}
+
+int transport_blocks_per_cu(int block) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport, block, 0) != hipSuccess) return 1;
+    return n > 0 ? n : 1;
+}
+
+}  // namespace mcs

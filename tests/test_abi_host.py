@@ -1,0 +1,139 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every declared entry point, its structures match the header, and argument
+validation rejects bad inputs before touching the device."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcspect.h")
+
+
+def _mc():
+    import paper_2105_13324_amd as mc
+    return mc
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(mc\w+|mlem\w+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    mc = _mc()
+    lib = C.CDLL(mc.LIB_PATH)
+    decl = declared_functions()
+    assert decl, "no declarations found"
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(mc.EXPORTS) == decl
+    out = subprocess.run(["nm", "-D", "--defined-only", mc.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for name in decl:
+        assert re.search(r"\bT %s\b" % name, out), name
+
+
+def _layout_src(mc):
+    fields = " ".join("F(mc_problem, %s)" % n for n, _ in mc.McProblem._fields_)
+    return r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "mcspect.h"
+#define F(T, f) printf(#T " " #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("mc_problem size %zu\n", sizeof(mc_problem));
+  """ + fields + r"""
+  printf("mc_options size %zu\n", sizeof(mc_options));
+  printf("mc_event size %zu\n", sizeof(mc_event));
+  printf("mc_record size %zu\n", sizeof(mc_record));
+  F(mc_record, e_final)
+  return 0;
+}
+"""
+
+
+def test_struct_layout_matches_header():
+    mc = _mc()
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "l.c")
+        exe = os.path.join(d, "l")
+        open(src, "w").write(_layout_src(mc))
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = {}
+    for line in out.splitlines():
+        t, f, v = line.split()
+        got[(t, f)] = int(v)
+    assert got[("mc_problem", "size")] == C.sizeof(mc.McProblem)
+    for name, _ in mc.McProblem._fields_:
+        assert got[("mc_problem", name)] == getattr(mc.McProblem, name).offset, name
+    assert got[("mc_options", "size")] == C.sizeof(mc.McOptions)
+    assert got[("mc_event", "size")] == mc.EVENT_DTYPE.itemsize
+    assert got[("mc_record", "size")] == mc.RECORD_DTYPE.itemsize
+    assert got[("mc_record", "e_final")] == mc.RECORD_DTYPE.fields["e_final"][1]
+
+
+def _good():
+    mc = _mc()
+    p = mc.McProblem(nx=8, ny=8, nz=8, source_mode=0, voxel_cm=0.5, mu140=16, activity=16,
+                     n_views=4, nu=8, nv=8, angle_rad=16, pixel_cm=0.5, radius_cm=10.0,
+                     accept_half_angle_rad=0.05, e_lo_kev=126, e_hi_kev=154, e_cut_kev=10,
+                     pe_fraction=1e-3, n_histories=1000, history_offset=0, history_count=0,
+                     seed=0, problem_id=0, image_factor=0, max_steps=0)
+    return p
+
+
+def test_workspace_bytes_and_validation():
+    mc = _mc()
+    lib = mc._lib
+    p = _good()
+    n = lib.mc_workspace_bytes(C.byref(p), 1, None)
+    assert n > 8 ** 3 * 12
+    # grows with the grid
+    p2 = _good(); p2.nx = 16
+    assert lib.mc_workspace_bytes(C.byref(p2), 1, None) > n
+    bad = [
+        dict(nx=0), dict(voxel_cm=0.0), dict(voxel_cm=float("nan")), dict(mu140=None),
+        dict(activity=None), dict(angle_rad=None), dict(n_views=0), dict(nu=0), dict(pixel_cm=-1.0),
+        dict(radius_cm=2.0), dict(accept_half_angle_rad=0.0), dict(accept_half_angle_rad=2.0),
+        dict(e_lo_kev=160.0), dict(e_cut_kev=0.0), dict(pe_fraction=1.5), dict(n_histories=0),
+        dict(history_offset=2000), dict(history_offset=500, history_count=600),
+        dict(image_factor=3), dict(source_mode=7),
+    ]
+    for b in bad:
+        q = _good()
+        for k, v in b.items():
+            setattr(q, k, v)
+        assert lib.mc_workspace_bytes(C.byref(q), 1, None) == 0, b
+        rc = lib.mc_simulate_projections(C.byref(q), 1, None, 8, None, 8, None, None, None, 0,
+                                         None, 8, 8, 1 << 30, None)
+        assert rc == mc.MC_EINVAL, b
+
+
+def test_simulate_rejects_bad_buffers_before_launch():
+    mc = _mc()
+    lib = mc._lib
+    p = _good()
+    need = lib.mc_workspace_bytes(C.byref(p), 1, None)
+    sim = lib.mc_simulate_projections
+    # missing outputs
+    assert sim(C.byref(p), 1, None, None, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
+    assert sim(C.byref(p), 1, None, 8, None, None, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
+    assert sim(C.byref(p), 1, None, 8, None, 8, None, None, None, 0, None, None, 8, need, None) == mc.MC_EINVAL
+    # events without a counter
+    assert sim(C.byref(p), 1, None, 8, None, 8, None, None, 8, 10, None, 8, 8, need, None) == mc.MC_EINVAL
+    # workspace too small
+    assert sim(C.byref(p), 1, None, 8, None, 8, None, None, None, 0, None, 8, 8, need - 1, None) == mc.MC_ENOMEM
+    # bad options
+    o = mc.McOptions(hist_per_lane=0, block_size=96, blocks_per_cu=0, reserved=0)
+    assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
+    assert sim(None, 1, None, 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
+    assert mc._lib.mc_error_string(mc.MC_EINVAL) == b"invalid argument"
+    assert mc._lib.mc_replay_histories(C.byref(p), None, None, None, 5, None, 8, 8, need, None) == mc.MC_EINVAL

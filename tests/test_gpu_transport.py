@@ -1,0 +1,220 @@
+"""GPU parity of the forward transport against the FP64 oracle, through the C ABI.
+
+Parity bar (per history): identical fate, detector bin and scatter count for at
+least 99.9% of replayed histories (FP32 tracking against FP64 can flip a
+decision that sits within rounding of a boundary; the event-keyed random
+stream confines such a flip to its own history).  Aggregates: energies within
+1e-4 relative; fate counts and primary/scatter tally totals within 1e-4 of the
+number of histories (a count of a few hundred cannot be held to 1e-4 of itself
+when one flipped history out of 10^6 moves it by one).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import phantoms
+
+pytestmark = pytest.mark.gpu
+
+
+def _mc():
+    import paper_2105_13324_amd as mc
+    return mc
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def sample_ids(prob, n, seed=7):
+    """n seeded (view, history id) pairs spread over the problem's histories."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    N, V = prob.n_histories, prob.n_views
+    g = np.sort(rng.choice(N, size=min(n, N), replace=False))
+    q, r = divmod(N, V)
+    big = q + 1
+    view = np.where(g < r * big, g // big, r + (g - r * big) // max(q, 1))
+    hist = np.where(g < r * big, g % big, (g - r * big) % max(q, 1))
+    return view.astype(np.int32), hist.astype(np.uint64)
+
+
+def replay_parity(prob, n=100_000, seed=7):
+    mc = _mc()
+    views, hists = sample_ids(prob, n, seed)
+    dp = mc.to_device(prob)
+    g = mc.replay(dp, views, hists)
+    o = oracle.replay(prob, views, hists)
+    same = ((g["fate"] == o["fate"]) & (g["iu"] == o["iu"]) & (g["iv"] == o["iv"])
+            & (g["n_scatter"] == o["n_scatter"]))
+    frac = same.mean()
+    both = same & (g["n_tent"] == o["n_tent"])
+    rel_e = np.abs(g["e_final"][both] - o["e_final"][both]) / o["e_final"][both]
+    say(f"{prob.name}: replay identical {frac:.6f} ({(~same).sum()} differ of {len(same)}), "
+        f"n_tent identical {both.mean():.6f}, max rel dE {rel_e.max() if len(rel_e) else 0:.2e}, "
+        f"tallied {np.sum(o['fate'] == 5)}")
+    assert np.array_equal(g["emit_voxel"], o["emit_voxel"])      # integer inverse CDF: exact
+    assert frac >= 0.999
+    assert rel_e.max() < 1e-5
+    return g, o
+
+
+def aggregate_parity(prob, tol=1e-4, options=None):
+    mc = _mc()
+    dp = mc.to_device(prob)
+    sim = mc.simulate(dp, options=options)
+    st = sim.check_status()
+    o = oracle.simulate(prob)
+    fates = sim.fates.cpu().numpy()[0]
+    tally = mc.tally_float(sim.tally).reshape(prob.tally_shape)
+    tsq = mc.tally_float(sim.tally_sq).reshape(prob.tally_shape)
+    energy = sim.energy.cpu().numpy()[0].astype(np.float64) / mc.Q23
+    cnt = sim.counters.cpu().numpy()[0]
+    say(f"{prob.name}: gpu fates {fates.tolist()}\n  oracle fates {o['fates'].tolist()}")
+    say(f"  energy gpu {energy[:3]} oracle {o['energy'][:3]}")
+    assert cnt[3] == prob.n_histories == fates.sum()
+    assert tally.sum() == fates[5]
+    np.testing.assert_array_equal(tally, tsq)
+    N = prob.n_histories
+    for i in range(7):
+        assert abs(fates[i] - o["fates"][i]) <= tol * N, (i, fates[i], o["fates"][i])
+    for c in range(2):
+        a, b = tally[:, c].sum(), o["tally"][:, c].sum()
+        assert abs(a - b) <= tol * N, (c, a, b)
+    for i in range(3):
+        assert abs(energy[i] - o["energy"][i]) <= tol * max(o["energy"][i], 1.0), (i, energy[i], o["energy"][i])
+    assert abs(cnt[0] - o["n_tent"]) <= tol * o["n_tent"]
+    assert abs(cnt[1] - o["n_real"]) <= tol * o["n_real"]
+    assert abs(cnt[2] - o["n_kahn"]) <= tol * max(o["n_kahn"], 1)
+    # bin-by-bin: identical except for rare flipped histories
+    diff = np.abs(tally - o["tally"]).sum()
+    assert diff <= max(2, 1e-3 * tally.sum()), diff
+    return sim, o
+
+
+def test_point_cube_64_replay():
+    replay_parity(phantoms.point_cube_64(10 ** 6))
+
+
+def test_point_cube_64_aggregates():
+    aggregate_parity(phantoms.point_cube_64(10 ** 6))
+
+
+def test_point_cube_64_photoelectric_heavy():
+    p = phantoms.point_cube_64(300_000).with_(pe_fraction=0.3, name="pe_heavy")
+    replay_parity(p, 50_000)
+    aggregate_parity(p)
+
+
+def test_thorax_small_replay_and_aggregates():
+    p = phantoms.thorax_problem("thorax_64", 64, 0.6, 2, 60, 180.0, 64, 0.6, 2_000_000)
+    replay_parity(p)
+    aggregate_parity(p)
+
+
+def test_thorax_odd_non_cubic_grid():
+    mu, act = phantoms.thorax(48, 0.8, 9)
+    mu = np.ascontiguousarray(mu[3:44, 1:46, :])       # nz=41, ny=45, nx=48
+    act = np.ascontiguousarray(act[3:44, 1:46, :])
+    p = phantoms.thorax_problem("thorax_odd", 48, 0.8, 9, 7, 180.0, 40, 0.9, 700_001).with_(
+        nz=41, ny=45, nx=48, mu=mu, activity=act, e_cut_kev=10.0)
+    replay_parity(p, 50_000)
+    aggregate_parity(p)
+
+
+def test_vacuum_geometric_efficiency():
+    n = 16
+    mu = np.zeros((n, n, n), np.float32)
+    act = np.zeros((n, n, n), np.uint32)
+    act[n // 2, n // 2, n // 2] = 1
+    alpha = math.radians(20.0)
+    p = phantoms.point_source_cube("vac", n, 1.0, 400_000).with_(mu=mu, activity=act,
+                                                                 accept_half_angle_rad=alpha)
+    sim, o = aggregate_parity(p)
+    fates = sim.fates.cpu().numpy()[0]
+    pexp = 0.5 * (1 - math.cos(alpha))
+    z = (fates[5] - p.n_histories * pexp) / math.sqrt(p.n_histories * pexp * (1 - pexp))
+    assert abs(z) < 4
+
+
+def test_run_to_run_and_option_independence():
+    mc = _mc()
+    p = phantoms.thorax_problem("thorax_64", 64, 0.6, 2, 60, 180.0, 64, 0.6, 1_000_000)
+    dp = mc.to_device(p)
+    ref = mc.simulate(dp)
+    t0 = ref.tally.clone()
+    f0 = ref.fates.clone()
+    e0 = ref.energy.clone()
+    for opts in (None, {"hist_per_lane": 1}, {"hist_per_lane": 64, "block_size": 64},
+                 {"block_size": 128, "blocks_per_cu": 1}, {"hist_per_lane": 5, "blocks_per_cu": 3}):
+        s = mc.simulate(dp, options=opts)
+        assert bool((s.tally == t0).all()), opts
+        assert bool((s.fates == f0).all()), opts
+        assert bool((s.energy == e0).all()), opts
+
+
+def test_resume_ranges_sum_exactly():
+    mc = _mc()
+    p = phantoms.thorax_problem("thorax_64", 64, 0.6, 2, 13, 180.0, 64, 0.6, 500_003)
+    full = mc.simulate(mc.to_device(p))
+    a = mc.simulate(mc.to_device(p.with_(history_offset=0, history_count=123_457)))
+    b = mc.simulate(mc.to_device(p.with_(history_offset=123_457, history_count=0)))
+    assert bool((full.tally == a.tally + b.tally).all())
+    assert bool((full.fates == a.fates + b.fates).all())
+    assert bool((full.energy == a.energy + b.energy).all())
+
+
+@pytest.mark.parametrize("n", [1, 7, 59, 61])
+def test_tiny_history_counts(n):
+    # fewer histories than views: some views get none
+    p = phantoms.thorax_problem("thorax_32", 32, 1.2, 2, 60, 180.0, 32, 1.2, n)
+    mc = _mc()
+    sim = mc.simulate(mc.to_device(p))
+    o = oracle.simulate(p)
+    np.testing.assert_array_equal(sim.fates.cpu().numpy()[0], o["fates"])
+
+
+def test_event_list_matches_oracle_replay():
+    mc = _mc()
+    p = phantoms.thorax_problem("thorax_64", 64, 0.6, 2, 60, 180.0, 64, 0.6, 2_000_000)
+    sim = mc.simulate(mc.to_device(p), event_capacity=10_000)
+    ev = sim.events_numpy()
+    assert len(ev) == int(sim.n_events.item()) == int(sim.fates[0, 5].item())
+    q, r = divmod(p.n_histories, p.n_views)
+    g = ev["work"].astype(np.int64)
+    big = q + 1
+    view = np.where(g < r * big, g // big, r + (g - r * big) // q).astype(np.int32)
+    hist = np.where(g < r * big, g % big, (g - r * big) % q).astype(np.uint64)
+    o = oracle.replay(p, view, hist)
+    b = ((o["view"] * 2 + o["cls"]) * p.nv + o["iv"]) * p.nu + o["iu"]
+    ok = (o["fate"] == 5) & (b == ev["bin"]) & (o["emit_voxel"] == ev["emit_voxel"])
+    say(f"event list: {ok.mean():.6f} of {len(ok)} tallied histories confirmed by the oracle")
+    assert ok.mean() >= 0.999
+
+
+def test_bad_inputs_reported_in_status():
+    mc = _mc()
+    p = phantoms.point_cube_64(1000)
+    mu = p.mu.copy()
+    mu[3, 4, 5] = -0.1
+    with pytest.raises(mc.McError):
+        mc.simulate(mc.to_device(p.with_(mu=mu)))
+    with pytest.raises(mc.McError):
+        mc.simulate(mc.to_device(p.with_(activity=np.zeros_like(p.activity))))
+    mu = p.mu.copy()
+    mu[0, 0, 0] = np.nan
+    with pytest.raises(mc.McError):
+        mc.replay(mc.to_device(p.with_(mu=mu)), np.zeros(4, np.int32), np.arange(4, dtype=np.uint64))
+
+
+def test_step_cap_reported():
+    mc = _mc()
+    p = phantoms.point_cube_64(20_000).with_(max_steps=1)
+    sim = mc.simulate(mc.to_device(p))
+    st = sim.check_status()
+    o = oracle.simulate(p)
+    assert st[0] & mc.STATUS_CAPPED
+    assert st[1] == sim.fates[0, 6].item() == o["fates"][6] > 0

@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--histories", type=float, default=1e8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the transport path is built and timed on a single "
@@ -77,6 +79,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        # a plain copy of known size: 2^30 bytes read, 2^30 bytes written
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30}))
+        return
     import phantoms
     import paper_2105_13324_amd as mc
 

@@ -89,7 +89,8 @@ def _load():
         lib.orc_rotate.argtypes = [P(C.c_double), C.c_double, C.c_double]
         lib.orc_thresholds.argtypes = [P(_Problem), P(C.c_uint32), P(C.c_double)]
         lib.orc_simulate.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(_Result),
-                                     P(C.c_int64), P(C.c_int64), C.c_uint64, P(C.c_uint64)]
+                                     P(C.c_int64), P(C.c_int64), P(C.c_int64), C.c_uint64,
+                                     P(C.c_uint64)]
         lib.orc_replay.argtypes = [P(_Problem), P(C.c_int32), P(C.c_uint64), C.c_int64, C.c_void_p]
         lib.orc_adjoint.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(C.c_int64),
                                     C.c_int32, P(C.c_int32), C.c_double, P(C.c_double),
@@ -194,21 +195,23 @@ def thresholds(prob):
 
 def simulate(prob, n_threads: int = 0, want_triplets: bool = False, trip_cap: int = 1 << 22):
     """Forward simulation.  Returns dict with tally, tally_sq ([V,2,nv,nu], FP64),
-    fates, energy (deposited, escaped, capped), counters and, if asked, the
-    (image voxel, global bin) pairs of tallied histories."""
+    fates, energy (deposited, escaped, capped), counters and, if asked, per
+    tallied history its image voxel of emission (trip_i), bin (trip_j) and work
+    index relative to history_offset (trip_g)."""
     lib = _load()
     p, keep = _make_problem(prob, n_threads)
     tally = np.zeros(prob.tally_shape, dtype=np.float64)
     tsq = np.zeros(prob.tally_shape, dtype=np.float64)
     res = _Result()
-    ti = tj = None
+    ti = tj = tg = None
     ntrip = C.c_uint64(0)
     if want_triplets:
         ti = np.empty(trip_cap, dtype=np.int64)
         tj = np.empty(trip_cap, dtype=np.int64)
+        tg = np.empty(trip_cap, dtype=np.int64)
     rc = lib.orc_simulate(C.byref(p), _ptr(tally, C.c_double), _ptr(tsq, C.c_double),
                           C.byref(res), _ptr(ti, C.c_int64), _ptr(tj, C.c_int64),
-                          trip_cap if want_triplets else 0, C.byref(ntrip))
+                          _ptr(tg, C.c_int64), trip_cap if want_triplets else 0, C.byref(ntrip))
     if rc != 0:
         raise RuntimeError(f"orc_simulate failed ({rc})")
     out = _result_dict(res)
@@ -218,6 +221,7 @@ def simulate(prob, n_threads: int = 0, want_triplets: bool = False, trip_cap: in
         n = ntrip.value
         out["trip_i"] = ti[:n].copy()
         out["trip_j"] = tj[:n].copy()
+        out["trip_g"] = tg[:n].copy()
     return out
 
 

@@ -384,7 +384,7 @@ struct Acc {
     int64_t fates[8] = {0};
     double energy[4] = {0, 0, 0, 0};
     int64_t n_tent = 0, n_real = 0, n_kahn = 0, n_hist = 0;
-    std::vector<int64_t> trip_i, trip_j;
+    std::vector<int64_t> trip_i, trip_j, trip_g;
 };
 
 size_t bin_index(const orc_problem* p, int view, int cls, int iv, int iu) {
@@ -393,12 +393,14 @@ size_t bin_index(const orc_problem* p, int view, int cls, int iv, int iu) {
 
 int32_t image_voxel(const orc_problem* p, int32_t vox) {
     const int f = p->image_factor;
+    if (f <= 0) return vox;
     const int ix = vox % p->nx, iy = (vox / p->nx) % p->ny, iz = vox / (p->nx * p->ny);
     const int mx = p->nx / f, my = p->ny / f;
     return (ix / f) + mx * ((iy / f) + my * (iz / f));
 }
 
-void accumulate(const orc_problem* p, const History& h, Acc& a, bool want_tally, bool want_trip) {
+void accumulate(const orc_problem* p, const History& h, Acc& a, bool want_tally, bool want_trip,
+                uint64_t g = 0) {
     a.fates[h.fate]++;
     a.energy[0] += h.dep;
     if (h.fate == CAPPED) a.energy[2] += h.capped;
@@ -410,6 +412,7 @@ void accumulate(const orc_problem* p, const History& h, Acc& a, bool want_tally,
         if (want_trip) {
             a.trip_i.push_back(image_voxel(p, h.emit_voxel));
             a.trip_j.push_back((int64_t)b);
+            a.trip_g.push_back((int64_t)(g - p->history_offset));
         }
     }
 }
@@ -522,14 +525,17 @@ int orc_thresholds(const orc_problem* p, uint32_t* q_out, double* mu_hat) {
 }
 
 // Forward simulation.  tally / tally_sq: [V][2][nv][nu] (nullable).
-// trip_i / trip_j: (image voxel, global bin) per tallied history, capacity cap.
+// Per tallied history (capacity cap, nullable): trip_i image voxel of emission
+// (phantom voxel when image_factor is 0), trip_j bin, trip_g work index
+// relative to history_offset, in work-index order.
 int orc_simulate(const orc_problem* p, double* tally, double* tally_sq, orc_result* res,
-                 int64_t* trip_i, int64_t* trip_j, uint64_t trip_cap, uint64_t* n_trip) {
+                 int64_t* trip_i, int64_t* trip_j, int64_t* trip_g, uint64_t trip_cap,
+                 uint64_t* n_trip) {
     Setup s;
     if (!build_setup(p, s)) return -1;
     const size_t nbins = (size_t)p->n_views * 2 * p->nv * p->nu;
     const bool want_tally = tally != nullptr;
-    const bool want_trip = trip_i != nullptr && p->image_factor > 0;
+    const bool want_trip = trip_i != nullptr;
     const size_t nt = n_threads_for(p);
     std::vector<Acc> acc(nt);
     for (auto& a : acc) if (want_tally) { a.tally.assign(nbins, 0.0); a.tally_sq.assign(nbins, 0.0); }
@@ -539,7 +545,7 @@ int orc_simulate(const orc_problem* p, double* tally, double* tally_sq, orc_resu
             work_to_view_hist(s, g, view, hist);
             History h;
             run_history(s, view, hist, false, h);
-            accumulate(p, h, acc[t], want_tally, want_trip);
+            accumulate(p, h, acc[t], want_tally, want_trip, g);
         }
     });
     std::memset(res, 0, sizeof(*res));
@@ -558,7 +564,11 @@ int orc_simulate(const orc_problem* p, double* tally, double* tally_sq, orc_resu
             if (tally_sq) tally_sq[b] += a.tally_sq[b];
         }
         if (want_trip) for (size_t i = 0; i < a.trip_i.size(); ++i) {
-            if (nt_out < trip_cap) { trip_i[nt_out] = a.trip_i[i]; trip_j[nt_out] = a.trip_j[i]; }
+            if (nt_out < trip_cap) {
+                trip_i[nt_out] = a.trip_i[i];
+                trip_j[nt_out] = a.trip_j[i];
+                if (trip_g) trip_g[nt_out] = a.trip_g[i];
+            }
             ++nt_out;
         }
     }

@@ -66,7 +66,7 @@ __device__ void walk(const Cst& C, float ax, float ay, float az, float dx, float
 __device__ inline double g_of(const Cst& C, float e) {
     if (e == 140.0f) return 1.0;
     float a, b;
-    return energy_terms(C, e, a, b);
+    return (double)energy_terms(C, e, a, b);
 }
 
 // Replay one history; if it ends TALLIED in `bin`, walk its path with weight G.
@@ -74,7 +74,7 @@ __device__ inline double g_of(const Cst& C, float e) {
 __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now, double G,
                            long long* grad, double scale, int64_t* status, uint32_t& bin_out) {
     Lane L;
-    L.hist = hist; L.view = view; L.work = 0;
+    L.hist = hist; L.view = view;
     L.state = S_EMIT0; L.n = 0; L.a = 0; L.n_scatter = 0; L.emit_voxel = 0; L.e = 0.0f;
     const float2 cs = C.views[view];
     L.vc = cs.x; L.vs = cs.y;
@@ -116,17 +116,6 @@ __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now,
     }
 }
 
-__device__ inline void split_work(const Cst& C, uint64_t g, int& view, uint64_t& hist) {
-    const uint64_t big = C.q_per_view + 1;
-    if (g < C.r_extra * big) { view = (int)(g / big); hist = g - (uint64_t)view * big; }
-    else {
-        const uint64_t g2 = g - C.r_extra * big;
-        const uint64_t v = C.r_extra + g2 / C.q_per_view;
-        view = (int)v;
-        hist = g2 - (v - C.r_extra) * C.q_per_view;
-    }
-}
-
 // One listed tallied history per lane.
 __global__ __launch_bounds__(64) void k_adjoint_events(const ProbDesc* __restrict__ d,
                                                        const mc_event* __restrict__ events,
@@ -142,10 +131,10 @@ __global__ __launch_bounds__(64) void k_adjoint_events(const ProbDesc* __restric
     if (ev.work >= d->work_count) { atomicOr((unsigned long long*)status, (unsigned long long)MC_STATUS_BAD_EVENT); return; }
     const double G = dL[C.tally_offset + ev.bin];
     if (G == 0.0) return;
-    int view; uint64_t hist;
+    uint64_t view, hist;
     split_work(C, C.work_begin + ev.work, view, hist);
     uint32_t bin = 0;
-    const int fate = replay_path(C, hist, view, true, G, grad, scale, status, bin);
+    const int fate = replay_path(C, hist, (int)view, true, G, grad, scale, status, bin);
     if (fate != MC_TALLIED || bin != ev.bin)
         atomicOr((unsigned long long*)status, (unsigned long long)MC_STATUS_BAD_EVENT);
 }
@@ -159,14 +148,14 @@ __global__ __launch_bounds__(256) void k_adjoint_all(const ProbDesc* __restrict_
     const uint64_t cnt = d->work_count;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        int view; uint64_t hist;
+        uint64_t view, hist;
         split_work(C, C.work_begin + i, view, hist);
         uint32_t bin = 0;
-        const int fate = replay_path(C, hist, view, false, 0.0, grad, scale, status, bin);
+        const int fate = replay_path(C, hist, (int)view, false, 0.0, grad, scale, status, bin);
         if (fate != MC_TALLIED) continue;
         const double G = dL[C.tally_offset + bin];
         if (G == 0.0) continue;
-        replay_path(C, hist, view, true, G, grad, scale, status, bin);
+        replay_path(C, hist, (int)view, true, G, grad, scale, status, bin);
     }
 }
 

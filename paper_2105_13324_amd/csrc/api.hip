@@ -32,6 +32,7 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 // Host-visible checks of one problem.
 bool check_problem(const mc_problem& p) {
     if (p.nx < 1 || p.ny < 1 || p.nz < 1) return false;
+    if (p.nx > MAX_AXIS || p.ny > MAX_AXIS || p.nz > MAX_AXIS) return false;
     const uint64_t nvox = (uint64_t)p.nx * p.ny * p.nz;
     if (nvox >= (1ull << 31)) return false;
     if (p.source_mode != MC_SOURCE_VOXELS && p.source_mode != MC_SOURCE_POINT) return false;
@@ -44,7 +45,7 @@ bool check_problem(const mc_problem& p) {
     if (p.radius_cm <= 0.5 * std::sqrt(lx * lx + ly * ly)) return false;   // plane outside the grid
     if (!(p.accept_half_angle_rad > 0.0 && p.accept_half_angle_rad < 1.5707963267948966)) return false;
     if (!std::isfinite(p.e_lo_kev) || !std::isfinite(p.e_hi_kev) || p.e_lo_kev > p.e_hi_kev) return false;
-    if (!finite_pos(p.e_cut_kev) || p.e_cut_kev > 140.0) return false;
+    if (!std::isfinite(p.e_cut_kev) || p.e_cut_kev < 1.0 || p.e_cut_kev > 140.0) return false;
     if (!(p.pe_fraction >= 0.0 && p.pe_fraction <= 1.0)) return false;
     if (p.n_histories < 1) return false;
     if (p.n_histories / (uint64_t)p.n_views >= (1ull << 32) - 1) return false;
@@ -59,7 +60,7 @@ bool check_problem(const mc_problem& p) {
 
 struct Layout {
     size_t desc, prefix, state;
-    std::vector<size_t> q, cdf, bsum, guide, views;
+    std::vector<size_t> q, cdf, vid, bsum, bcnt, guide, views, kn;
     size_t total;
 };
 
@@ -68,15 +69,19 @@ bool plan(const mc_problem* probs, int n, Layout& L) {
     L.desc = off;   off += align256(sizeof(ProbDesc) * (size_t)n);
     L.prefix = off; off += align256(sizeof(uint64_t) * 2 * ((size_t)n + 1));
     L.state = off;  off += align256(sizeof(CallState));
-    L.q.resize(n); L.cdf.resize(n); L.bsum.resize(n); L.guide.resize(n); L.views.resize(n);
+    L.q.resize(n); L.cdf.resize(n); L.vid.resize(n); L.bsum.resize(n); L.bcnt.resize(n);
+    L.guide.resize(n); L.views.resize(n); L.kn.resize(n);
     for (int i = 0; i < n; ++i) {
         const mc_problem& p = probs[i];
         const uint64_t nvox = (uint64_t)p.nx * p.ny * p.nz;
         L.q[i] = off;     off += align256(4 * nvox);
         L.cdf[i] = off;   off += align256(8 * nvox);
+        L.vid[i] = off;   off += align256(4 * nvox);
         L.bsum[i] = off;  off += align256(8 * ((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS));
+        L.bcnt[i] = off;  off += align256(4 * ((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS));
         L.guide[i] = off; off += align256(4 * (guide_capacity(nvox) + 1));
         L.views[i] = off; off += align256(8 * (size_t)p.n_views);
+        L.kn[i] = off;    off += align256(4 * (size_t)KN_TABLE_N);
     }
     L.total = off;
     return true;
@@ -114,9 +119,12 @@ ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64
     d.mu = p.mu140; d.act = p.activity; d.angles = p.angle_rad;
     d.q32 = (uint32_t*)(ws + L.q[i]);
     d.cdf = (uint64_t*)(ws + L.cdf[i]);
+    d.vox_id = (uint32_t*)(ws + L.vid[i]);
     d.block_sums = (uint64_t*)(ws + L.bsum[i]);
+    d.block_cnt = (uint32_t*)(ws + L.bcnt[i]);
     d.guide = (uint32_t*)(ws + L.guide[i]);
     d.views = (float2*)(ws + L.views[i]);
+    d.kn_table = (float*)(ws + L.kn[i]);
     return d;
 }
 

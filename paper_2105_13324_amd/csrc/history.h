@@ -1,5 +1,11 @@
 // Device-side photon history: Philox stream, physics steps and the per-lane
 // state machine shared by the transport, replay and adjoint kernels.
+//
+// Every branch below runs for the lanes of a wavefront that are in that state
+// while the others wait, so each tail is kept short: no integer division, no
+// double precision, hardware transcendentals (v_log, v_sin/v_cos in
+// revolutions, v_rcp, v_sqrt), and the Klein-Nishina part of the attenuation
+// from a small table.
 #pragma once
 
 #include "mc_internal.h"
@@ -8,15 +14,16 @@ namespace mcs {
 namespace {
 
 constexpr uint32_t KAHN_MAX = 64;
+constexpr float MEC2_F = 510.99895f;
 constexpr float INV_MEC2 = (float)(1.0 / 510.99895);
-constexpr double MEC2_D = 510.99895;
 
 enum : int { S_IDLE = 0, S_EMIT0 = 1, S_EMIT1 = 2, S_STEP = 3, S_KAHN = 4 };
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
 // (words 0 and 2), xor-mixed with words 1 and 3 and the key; the key takes a
-// Weyl step after every round.
+// Weyl step after every round.  The key is wave-uniform, so its steps are
+// scalar adds.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
                                          uint32_t k0, uint32_t k1) {
@@ -40,19 +47,30 @@ __device__ __forceinline__ float unif(uint32_t r) {
     return fmaf((float)(r >> 9), 0x1p-23f, 0x1p-24f);
 }
 
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrtf_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
+// sin(2 pi u), cos(2 pi u): the hardware instructions take revolutions.
+__device__ __forceinline__ float sin_rev(float u) { return __builtin_amdgcn_sinf(u); }
+__device__ __forceinline__ float cos_rev(float u) { return __builtin_amdgcn_cosf(u); }
+
+// Table of the Klein-Nishina attenuation shape sigma_KN(E)/sigma_KN(140 keV)
+// at E = 140 - i/4 keV (filled in double precision during staging).
+constexpr float KN_TABLE_STEP_INV = 4.0f;
+
 // Problem constants a wavefront works with (wave-uniform).
 struct Cst {
     const float* mu;
     const uint32_t* q32;
     const uint64_t* cdf;
+    const uint32_t* vox_id;
     const uint32_t* guide;
     const float2* views;
+    const float* kn_table;
     int nx, ny, nz, source_mode;
     float hx, hy, hz, lx, ly, lz, inv_vox, vox;
-    int nu, nv;
+    int nu, nv, n_views;
     float inv_pix, radius, cos_alpha, wu, wv, e_lo, e_hi, e_cut;
     float f_pe, mu_hat, inv_mm140, p_pe140;
-    double kn140;
     uint32_t seed, pid, max_steps, shift;
     uint64_t total, q_per_view, r_extra, work_begin, tally_offset;
     uint32_t flags;
@@ -61,17 +79,17 @@ struct Cst {
 __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     Cst c;
     c.mu = d->mu;
-    c.q32 = d->q32; c.cdf = d->cdf; c.guide = d->guide; c.views = d->views;
+    c.q32 = d->q32; c.cdf = d->cdf; c.vox_id = d->vox_id; c.guide = d->guide; c.views = d->views;
+    c.kn_table = d->kn_table;
     c.nx = d->nx; c.ny = d->ny; c.nz = d->nz; c.source_mode = d->source_mode;
     c.hx = d->hx; c.hy = d->hy; c.hz = d->hz;
     c.lx = d->lx; c.ly = d->ly; c.lz = d->lz;
     c.inv_vox = d->inv_vox; c.vox = d->vox;
-    c.nu = d->nu; c.nv = d->nv;
+    c.nu = d->nu; c.nv = d->nv; c.n_views = d->n_views;
     c.inv_pix = d->inv_pix; c.radius = d->radius; c.cos_alpha = d->cos_alpha;
     c.wu = d->wu; c.wv = d->wv; c.e_lo = d->e_lo; c.e_hi = d->e_hi; c.e_cut = d->e_cut;
     c.f_pe = d->f_pe;
     c.mu_hat = __uint_as_float(d->mu_hat_bits);
-    c.kn140 = d->kn140;
     // g(140 keV) = 1 by construction: mu_max(140) = max mu, p_pe(140) = f.
     c.inv_mm140 = (float)(1.0 / (double)c.mu_hat);
     c.p_pe140 = c.f_pe;
@@ -82,42 +100,42 @@ __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     return c;
 }
 
-// Attenuation scale g(E) and photoelectric probability at energy e, in double
-// precision (once per scatter): g(E) = (1-f) KN(E)/KN(140) + f (140/E)^3.
-__device__ inline double energy_terms(const Cst& C, float e, float& inv_mm, float& p_pe) {
-    const double E = (double)e;
-    const double k = E / MEC2_D;
-    const double a = 1.0 + 2.0 * k;
-    const double la = log(a);
-    const double kn = (1.0 + k) / (k * k) * (2.0 * (1.0 + k) / a - la / k) + la / (2.0 * k)
-                      - (1.0 + 3.0 * k) / (a * a);
-    const double r = 140.0 / E;
-    const double pe = (double)C.f_pe * r * r * r;
-    const double g = (1.0 - (double)C.f_pe) * kn / C.kn140 + pe;
-    inv_mm = (float)(1.0 / ((double)C.mu_hat * g));
-    p_pe = (float)(pe / g);
+// Attenuation at energy e relative to 140 keV, g(E) = (1-f) KN(E)/KN(140) +
+// f (140/E)^3, its majorant reciprocal 1/(max mu g) and the photoelectric
+// share f (140/E)^3 / g.  The KN ratio is linearly interpolated (error below
+// 1e-6 relative over the table range), the photoelectric term is exact.
+__device__ inline float energy_terms(const Cst& C, float e, float& inv_mm, float& p_pe) {
+    const float t = (140.0f - e) * KN_TABLE_STEP_INV;
+    const int i = (int)t;
+    const float fr = t - (float)i;
+    const float k0 = C.kn_table[i], k1 = C.kn_table[i + 1];
+    const float kn = fmaf(fr, k1 - k0, k0);
+    const float x = 140.0f * rcpf(e);
+    const float pe = C.f_pe * x * x * x;
+    const float g = fmaf(1.0f - C.f_pe, kn, pe);
+    const float ig = rcpf(g);
+    inv_mm = rcpf(C.mu_hat * g);
+    p_pe = pe * ig;
     return g;
 }
 
 struct Lane {
-    uint64_t hist, work;
+    uint64_t hist;
     int view, state;
     uint32_t n, a, phi_word, emit_voxel;
     int n_scatter;
     float x, y, z, dx, dy, dz, e, inv_mm, p_pe, vc, vs;
 };
 
-// Per-lane accumulators of one problem (reduced across the wave on flush).
+// Per-lane work counters and energies of one problem (reduced across the
+// wave on flush).  Fate counts are kept wave-wide by the kernels.
 struct Acc {
-    uint32_t fate[7];
-    uint32_t n_tent, n_real, n_kahn, n_hist;
+    uint32_t n_tent, n_real, n_kahn;
     long long e_dep, e_esc, e_cap;
 };
 
 __device__ inline void acc_zero(Acc& A) {
-#pragma unroll
-    for (int i = 0; i < 7; ++i) A.fate[i] = 0;
-    A.n_tent = A.n_real = A.n_kahn = A.n_hist = 0;
+    A.n_tent = A.n_real = A.n_kahn = 0;
     A.e_dep = A.e_esc = A.e_cap = 0;
 }
 
@@ -132,7 +150,7 @@ enum : int { R_RUNNING = -1 };
 __device__ inline int escape(const Cst& C, const Lane& L, int& iu, int& iv) {
     const float dn = L.dx * L.vc + L.dy * L.vs;
     if (dn < C.cos_alpha) return MC_ESCAPED;
-    const float tp = (C.radius - (L.x * L.vc + L.y * L.vs)) / dn;
+    const float tp = (C.radius - (L.x * L.vc + L.y * L.vs)) * rcpf(dn);
     const float px = fmaf(tp, L.dx, L.x);
     const float py = fmaf(tp, L.dy, L.y);
     const float pz = fmaf(tp, L.dz, L.z);
@@ -145,21 +163,23 @@ __device__ inline int escape(const Cst& C, const Lane& L, int& iu, int& iv) {
     return MC_TALLIED;
 }
 
+// Turn the direction by polar cosine ct and azimuth 2 pi phi_u (standard
+// formula; near the poles the direction is taken as +-z).
 __device__ inline void rotate(Lane& L, float ct, float phi_u) {
-    float sp, cp;
-    sincospif(2.0f * phi_u, &sp, &cp);
-    const float st = sqrtf(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
+    const float sp = sin_rev(phi_u), cp = cos_rev(phi_u);
+    const float st = sqrtf_hw(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
     const float u = L.dx, v = L.dy, w = L.dz;
     if (fabsf(w) > 0.99999f) {
         L.dx = st * cp;
         L.dy = st * sp;
         L.dz = w > 0.0f ? ct : -ct;
     } else {
-        const float t = sqrtf((1.0f - w) * (1.0f + w));
-        const float it = 1.0f / t;
-        L.dx = st * (u * w * cp - v * sp) * it + u * ct;
-        L.dy = st * (v * w * cp + u * sp) * it + v * ct;
-        L.dz = -st * cp * t + w * ct;
+        const float t = sqrtf_hw((1.0f - w) * (1.0f + w));
+        const float it = rcpf(t);
+        const float a = st * it;
+        L.dx = fmaf(a, u * w * cp - v * sp, u * ct);
+        L.dy = fmaf(a, v * w * cp + u * sp, v * ct);
+        L.dz = fmaf(-st * cp, t, w * ct);
     }
 }
 
@@ -170,19 +190,38 @@ __device__ __forceinline__ void counter_of(const Lane& L, uint32_t& c2, uint32_t
     else if (L.state == S_KAHN) { c2 = L.n; c3 = 1 + L.a; }
 }
 
-// Start a history from its problem-local work index g.
-__device__ inline void begin_history(const Cst& C, Lane& L, uint64_t g, uint64_t work) {
+// Histories in view v: N_v = floor(N/V) + [v < N mod V].
+__device__ __forceinline__ uint64_t hists_in_view(const Cst& C, uint64_t v) {
+    return C.q_per_view + (v < C.r_extra ? 1u : 0u);
+}
+
+// Split a problem-local work index into (view, history id).  Uses 64-bit
+// division: call it wave-uniformly (once per claimed chunk), not per lane.
+__device__ inline void split_work(const Cst& C, uint64_t g, uint64_t& view, uint64_t& hist) {
     const uint64_t big = C.q_per_view + 1;
-    uint64_t view, hist;
     if (g < C.r_extra * big) { view = g / big; hist = g - view * big; }
     else {
         const uint64_t g2 = g - C.r_extra * big;
         view = C.r_extra + g2 / C.q_per_view;
         hist = g2 - (view - C.r_extra) * C.q_per_view;
     }
+}
+
+// Move (view, hist) forward by k histories (k small): no division.
+__device__ inline void advance_cursor(const Cst& C, uint64_t& view, uint64_t& hist, uint64_t k,
+                                      int n_views) {
+    hist += k;
+    uint64_t n = hists_in_view(C, view);
+    while (hist >= n && (int)view < n_views - 1) {
+        hist -= n;
+        ++view;
+        n = hists_in_view(C, view);
+    }
+}
+
+__device__ inline void begin_history(const Cst& C, Lane& L, uint64_t view, uint64_t hist) {
     L.hist = hist;
     L.view = (int)view;
-    L.work = work;
     L.state = S_EMIT0;
     L.n = 0; L.a = 0; L.n_scatter = 0;
     const float2 cs = C.views[view];
@@ -230,20 +269,24 @@ __device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, u
         return R_RUNNING;
     }
     if (L.state == S_KAHN) {
+        // Kahn's rejection sampler for x = E/E' on [1, 1+2k], k = E / m_e c^2
         A.n_kahn++;
         const float k = L.e * INV_MEC2;
+        const float ik = MEC2_F * rcpf(L.e);
         const float tk = 2.0f * k;
         const float r1 = unif(w0), r2 = unif(w1), r3 = unif(w2);
-        float xx;
+        const float den = fmaf(tk, r2, 1.0f);
+        float xx, ixx;
         bool acc;
-        if (r1 <= (1.0f + tk) / (9.0f + tk)) {
-            xx = fmaf(tk, r2, 1.0f);
-            const float ix = 1.0f / xx;
-            acc = r3 <= 4.0f * (ix - ix * ix);
+        if (r1 * (9.0f + tk) <= 1.0f + tk) {
+            xx = den;
+            ixx = rcpf(xx);
+            acc = r3 <= 4.0f * (ixx - ixx * ixx);
         } else {
-            xx = (1.0f + tk) / fmaf(tk, r2, 1.0f);
-            const float c = 1.0f - (xx - 1.0f) / k;
-            acc = r3 <= 0.5f * (c * c + 1.0f / xx);
+            xx = (1.0f + tk) * rcpf(den);
+            ixx = den * rcpf(1.0f + tk);
+            const float c = 1.0f - (xx - 1.0f) * ik;
+            acc = r3 <= 0.5f * fmaf(c, c, ixx);
         }
         if (!acc) {
             L.a += 1;
@@ -253,8 +296,8 @@ __device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, u
             }
             return R_RUNNING;
         }
-        const float ct = 1.0f - (xx - 1.0f) / k;
-        const float en = L.e / xx;
+        const float ct = 1.0f - (xx - 1.0f) * ik;
+        const float en = L.e * ixx;
         A.e_dep += to_q23(L.e - en);
         L.e = en;
         L.n_scatter += 1;
@@ -277,28 +320,25 @@ __device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, u
             const uint32_t mid = (lo + hi) >> 1;
             if (C.cdf[mid] > t) hi = mid; else lo = mid + 1;
         }
-        L.emit_voxel = lo;
+        const uint32_t packed = C.vox_id[lo];   // ix | iy << 10 | iz << 20
+        const uint32_t ix = packed & 1023u, iy = (packed >> 10) & 1023u, iz = packed >> 20;
+        L.emit_voxel = ix + (uint32_t)C.nx * (iy + (uint32_t)C.ny * iz);
         if (C.source_mode == MC_SOURCE_POINT) {
             L.x = 0.0f; L.y = 0.0f; L.z = 0.0f;
         } else {
-            const uint32_t ix = lo % (uint32_t)C.nx;
-            const uint32_t iy = (lo / (uint32_t)C.nx) % (uint32_t)C.ny;
             L.x = -C.hx + ((float)ix + unif(w2)) * C.vox;
             L.y = -C.hy + ((float)iy + unif(w3)) * C.vox;
+            L.z = (float)iz;   // completed with the next word block
         }
         L.state = S_EMIT1;
         return R_RUNNING;
     }
     // S_EMIT1: z position, direction, energy
-    if (C.source_mode != MC_SOURCE_POINT) {
-        const uint32_t iz = L.emit_voxel / ((uint32_t)C.nx * (uint32_t)C.ny);
-        L.z = -C.hz + ((float)iz + unif(w0)) * C.vox;
-    }
+    if (C.source_mode != MC_SOURCE_POINT) L.z = -C.hz + (L.z + unif(w0)) * C.vox;
     const float ct = fmaf(2.0f, unif(w1), -1.0f);
-    const float st = sqrtf((1.0f - ct) * (1.0f + ct));
-    float sp, cp;
-    sincospif(2.0f * unif(w2), &sp, &cp);
-    L.dx = st * cp; L.dy = st * sp; L.dz = ct;
+    const float st = sqrtf_hw((1.0f - ct) * (1.0f + ct));
+    const float u = unif(w2);
+    L.dx = st * cos_rev(u); L.dy = st * sin_rev(u); L.dz = ct;
     L.e = 140.0f;
     L.inv_mm = C.inv_mm140;
     L.p_pe = C.p_pe140;

@@ -34,19 +34,26 @@ struct ProbDesc {
     const uint32_t* act;
     const double* angles;
     uint32_t* q32;                  // accept thresholds, linear layout
-    uint64_t* cdf;                  // inclusive prefix sum of activity
-    uint64_t* block_sums;           // scan scratch
+    uint64_t* cdf;                  // inclusive prefix sum of activity over active voxels
+    uint32_t* vox_id;               // voxel index of each active voxel, in grid order
+    uint64_t* block_sums;           // scan scratch: activity per block
+    uint32_t* block_cnt;            // scan scratch: active voxels per block
     uint32_t* guide;                // guide table, n_buckets + 1 entries
     float2* views;                  // (cos, sin) per view
+    float* kn_table;                // sigma_KN(140 - i/4 keV) / sigma_KN(140), i < KN_TABLE_N
     // filled on the device by staging
     uint32_t mu_hat_bits;           // max mu, as float bits (mu >= 0)
     uint32_t flags;                 // MC_STATUS_* bits found during staging
     uint64_t total;                 // sum of activity
     uint32_t shift;                 // bucket = t >> shift
     uint32_t n_buckets;
+    uint32_t n_active;              // voxels with activity > 0
+    uint32_t pad1;
 };
 
 constexpr int SCAN_ITEMS = 4096;    // activity values per scan block
+constexpr int KN_TABLE_N = 568;     // entries of the Klein-Nishina shape table (>= 4*140 + 2)
+constexpr int MAX_AXIS = 1024;      // voxel indices are packed 10 bits per axis
 constexpr int SCAN_THREADS = 256;
 
 // Global counters of one call (in the workspace).
@@ -57,7 +64,7 @@ struct CallState {
 
 // Host launchers (staging.hip)
 hipError_t launch_staging(ProbDesc* d_desc, const ProbDesc& h_desc, hipStream_t s);
-uint64_t guide_capacity(uint64_t nvox);   // power of two >= nvox
+uint64_t guide_capacity(uint64_t nvox);   // guide entries needed (power of two >= 2 nvox)
 
 // Host launchers (transport.hip)
 struct TransportArgs {

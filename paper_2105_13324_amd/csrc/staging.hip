@@ -4,11 +4,14 @@
 //  * max mu, input validation and the activity total (one reduction pass);
 //  * accept thresholds Q_v = ceil(mu_v 2^24 / max mu) in double precision, so
 //    the real/virtual decision of Woodcock tracking is an exact integer compare;
-//  * the inclusive prefix sum of activity (uint64) and a guide table over its
-//    high bits, so that an emission voxel is found with one gather and a short
-//    binary search (Chen & Asau 1974 guide tables; same result as a plain
-//    inverse-CDF search);
-//  * (cos, sin) of each view angle.
+//  * the inclusive prefix sum of activity (uint64) over the active voxels only,
+//    their voxel indices, and a guide table over the high bits of the sum with
+//    about two buckets per active voxel, so an emission voxel is found with a
+//    guide gather, rarely a probe, and an index gather (Chen & Asau 1974 guide
+//    tables; the same voxel as a plain inverse-CDF search over all voxels);
+//  * (cos, sin) of each view angle;
+//  * the Klein-Nishina attenuation shape sigma_KN(E)/sigma_KN(140) at 1/4 keV
+//    steps, evaluated in double precision.
 //
 // Every pass streams the grid once with coalesced loads; the whole staging of
 // a 128^3 phantom moves ~40 MB and is far below the transport cost.
@@ -87,100 +90,141 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* pd) {
     }
 }
 
-// --- three-pass inclusive scan of the activity map (uint64) ---
+// --- three-pass scan of the activity map: uint64 inclusive sums and the
+// positions of active voxels, so the CDF is stored over active voxels only ---
 
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(ProbDesc* pd) {
     const uint64_t nvox = pd->nvox;
     const uint32_t* __restrict__ act = pd->act;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_ITEMS;
     uint64_t s = 0;
+    uint32_t c = 0;
     for (int j = threadIdx.x; j < SCAN_ITEMS; j += SCAN_THREADS) {
         const uint64_t i = base + j;
-        if (i < nvox) s += act[i];
+        if (i < nvox) {
+            const uint32_t a = act[i];
+            s += a;
+            c += a > 0;
+        }
     }
     s = wave_sum_u64(s);
+    c = (uint32_t)wave_sum_u64(c);
     __shared__ uint64_t part[SCAN_THREADS / 64];
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __shared__ uint32_t partc[SCAN_THREADS / 64];
+    if ((threadIdx.x & 63) == 0) { part[threadIdx.x >> 6] = s; partc[threadIdx.x >> 6] = c; }
     __syncthreads();
     if (threadIdx.x == 0) {
         uint64_t t = 0;
-        for (int w = 0; w < SCAN_THREADS / 64; ++w) t += part[w];
+        uint32_t tc = 0;
+        for (int w = 0; w < SCAN_THREADS / 64; ++w) { t += part[w]; tc += partc[w]; }
         pd->block_sums[blockIdx.x] = t;
+        pd->block_cnt[blockIdx.x] = tc;
     }
 }
 
-// Exclusive scan of the block sums, one block of 1024 threads, each thread a
-// contiguous run.
+// Exclusive scan of the block sums and counts, one block of 1024 threads,
+// each thread a contiguous run; also records the number of active voxels.
 __global__ __launch_bounds__(1024) void k_scan_top(ProbDesc* pd, int n_blocks) {
     __shared__ uint64_t tot[1024];
+    __shared__ uint32_t totc[1024];
     uint64_t* __restrict__ bs = pd->block_sums;
+    uint32_t* __restrict__ bc = pd->block_cnt;
     const int per = (n_blocks + 1023) / 1024;
     const int b0 = threadIdx.x * per;
     uint64_t s = 0;
-    for (int j = 0; j < per; ++j) if (b0 + j < n_blocks) s += bs[b0 + j];
+    uint32_t c = 0;
+    for (int j = 0; j < per; ++j) if (b0 + j < n_blocks) { s += bs[b0 + j]; c += bc[b0 + j]; }
     tot[threadIdx.x] = s;
+    totc[threadIdx.x] = c;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
         const uint64_t v = threadIdx.x >= (unsigned)off ? tot[threadIdx.x - off] : 0;
+        const uint32_t vc = threadIdx.x >= (unsigned)off ? totc[threadIdx.x - off] : 0;
         __syncthreads();
         tot[threadIdx.x] += v;
+        totc[threadIdx.x] += vc;
         __syncthreads();
     }
-    uint64_t run = tot[threadIdx.x] - s;  // exclusive prefix of this thread's run
+    if (threadIdx.x == 1023) pd->n_active = totc[1023];
+    uint64_t run = tot[threadIdx.x] - s;   // exclusive prefix of this thread's run
+    uint32_t runc = totc[threadIdx.x] - c;
     for (int j = 0; j < per; ++j) {
         if (b0 + j < n_blocks) {
             const uint64_t v = bs[b0 + j];
+            const uint32_t vc = bc[b0 + j];
             bs[b0 + j] = run;
+            bc[b0 + j] = runc;
             run += v;
+            runc += vc;
         }
     }
 }
 
-// Per block: 16 consecutive items per thread, thread-local inclusive scan,
-// block exclusive scan of thread totals, plus the block's offset.
+// Per block: 16 consecutive voxels per thread, thread-local scans, block
+// exclusive scans of the thread totals, plus the block offsets; each active
+// voxel writes its cumulative activity and its index at its compacted slot.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ProbDesc* pd) {
     constexpr int PER = SCAN_ITEMS / SCAN_THREADS;
     const uint64_t nvox = pd->nvox;
     const uint32_t* __restrict__ act = pd->act;
     uint64_t* __restrict__ cdf = pd->cdf;
+    uint32_t* __restrict__ vid = pd->vox_id;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_ITEMS + (uint64_t)threadIdx.x * PER;
-    uint64_t v[PER];
+    const uint32_t nx = (uint32_t)pd->nx, ny = (uint32_t)pd->ny;
+    uint32_t a[PER];
     uint64_t s = 0;
+    uint32_t c = 0;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const uint64_t i = base + j;
-        s += (i < nvox) ? act[i] : 0u;
-        v[j] = s;
+        a[j] = (i < nvox) ? act[i] : 0u;
+        s += a[j];
+        c += a[j] > 0;
     }
     __shared__ uint64_t tot[SCAN_THREADS];
+    __shared__ uint32_t totc[SCAN_THREADS];
     tot[threadIdx.x] = s;
+    totc[threadIdx.x] = c;
     __syncthreads();
     for (int off = 1; off < SCAN_THREADS; off <<= 1) {
         const uint64_t t = threadIdx.x >= (unsigned)off ? tot[threadIdx.x - off] : 0;
+        const uint32_t tc = threadIdx.x >= (unsigned)off ? totc[threadIdx.x - off] : 0;
         __syncthreads();
         tot[threadIdx.x] += t;
+        totc[threadIdx.x] += tc;
         __syncthreads();
     }
-    const uint64_t off = pd->block_sums[blockIdx.x] + tot[threadIdx.x] - s;
+    uint64_t run = pd->block_sums[blockIdx.x] + tot[threadIdx.x] - s;
+    uint32_t k = pd->block_cnt[blockIdx.x] + totc[threadIdx.x] - c;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        const uint64_t i = base + j;
-        if (i < nvox) cdf[i] = off + v[j];
+        if (a[j] > 0) {
+            run += a[j];
+            cdf[k] = run;
+            const uint32_t i = (uint32_t)(base + j);
+            const uint32_t ix = i % nx, iy = (i / nx) % ny, iz = i / (nx * ny);
+            vid[k] = ix | (iy << 10) | (iz << 20);   // packed 10 bits per axis
+            ++k;
+        }
     }
 }
 
-// Guide table: bucket b covers t in [b 2^s, (b+1) 2^s); guide[b] is the first
-// voxel whose cumulative activity exceeds b 2^s, guide[B] the last voxel.  The
+// Guide table over the compacted CDF: bucket b covers t in [b 2^s, (b+1) 2^s),
+// with about two buckets per active voxel; guide[b] is the first active slot
+// whose cumulative activity exceeds b 2^s and guide[B] the last slot, so the
 // answer for any t in bucket b lies in [guide[b], guide[b+1]].
 __global__ __launch_bounds__(RED_THREADS) void k_guide(ProbDesc* pd, uint64_t nb_cap) {
     const uint64_t total = pd->total;
-    const uint64_t nvox = pd->nvox;
-    if (total == 0) {
+    const uint64_t K = pd->n_active;
+    if (total == 0 || K == 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&pd->flags, (uint32_t)MC_STATUS_NO_ACTIVITY);
         return;
     }
+    uint64_t cap = 1;
+    while (cap < 2 * K) cap <<= 1;
+    if (cap > nb_cap) cap = nb_cap;
     uint32_t s = 0;
-    while (((total - 1) >> s) >= nb_cap) ++s;
+    while (((total - 1) >> s) >= cap) ++s;
     const uint64_t B = ((total - 1) >> s) + 1;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         pd->shift = s;
@@ -190,15 +234,31 @@ __global__ __launch_bounds__(RED_THREADS) void k_guide(ProbDesc* pd, uint64_t nb
     uint32_t* __restrict__ guide = pd->guide;
     for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= B;
          b += (uint64_t)gridDim.x * blockDim.x) {
-        if (b == B) { guide[b] = (uint32_t)(nvox - 1); continue; }
+        if (b == B) { guide[b] = (uint32_t)(K - 1); continue; }
         const uint64_t key = b << s;
-        uint64_t lo = 0, hi = nvox - 1;   // first i with cdf[i] > key; cdf[nvox-1] = total > key
+        uint64_t lo = 0, hi = K - 1;   // first slot with cdf > key; cdf[K-1] = total > key
         while (lo < hi) {
             const uint64_t mid = (lo + hi) >> 1;
             if (cdf[mid] > key) hi = mid; else lo = mid + 1;
         }
         guide[b] = (uint32_t)lo;
     }
+}
+
+// Klein-Nishina total cross-section per electron over 2 pi r_e^2 (closed form).
+__device__ double kn_bracket(double e) {
+    const double k = e / 510.99895;
+    const double a = 1.0 + 2.0 * k;
+    const double la = log(a);
+    return (1.0 + k) / (k * k) * (2.0 * (1.0 + k) / a - la / k) + la / (2.0 * k)
+           - (1.0 + 3.0 * k) / (a * a);
+}
+
+__global__ void k_kn_table(ProbDesc* pd) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= KN_TABLE_N) return;
+    const double e = fmax(140.0 - 0.25 * i, 0.5);
+    pd->kn_table[i] = (float)(kn_bracket(e) / kn_bracket(140.0));
 }
 
 int grid_for(uint64_t n, int threads, int cap) {
@@ -212,7 +272,7 @@ int grid_for(uint64_t n, int threads, int cap) {
 
 uint64_t guide_capacity(uint64_t nvox) {
     uint64_t c = 1;
-    while (c < nvox) c <<= 1;
+    while (c < 2 * nvox) c <<= 1;
     return c;
 }
 
@@ -227,6 +287,7 @@ hipError_t launch_staging(ProbDesc* d, const ProbDesc& h, hipStream_t st) {
     k_scan_final<<<nb, SCAN_THREADS, 0, st>>>(d);
     const uint64_t cap = guide_capacity(nvox);
     k_guide<<<grid_for(cap + 1, RED_THREADS, 8192), RED_THREADS, 0, st>>>(d, cap);
+    k_kn_table<<<(KN_TABLE_N + 255) / 256, 256, 0, st>>>(d);
     return hipGetLastError();
 }
 

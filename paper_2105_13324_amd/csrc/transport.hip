@@ -37,17 +37,17 @@ __device__ __forceinline__ long long wsum64(long long v) {
 }
 
 // Wave-wide flush of one problem's accumulators (all 64 lanes must call).
-__device__ inline void flush(Acc& A, int p, const TransportArgs& T, int lane) {
-    uint32_t f[7];
-#pragma unroll
-    for (int i = 0; i < 7; ++i) f[i] = wsum32(A.fate[i]);
-    const uint32_t nt = wsum32(A.n_tent), nr = wsum32(A.n_real), nk = wsum32(A.n_kahn),
-                   nh = wsum32(A.n_hist);
+// fc: wave-uniform fate counts.
+__device__ inline void flush(Acc& A, uint32_t* fc, int p, const TransportArgs& T, int lane) {
+    const uint32_t nt = wsum32(A.n_tent), nr = wsum32(A.n_real), nk = wsum32(A.n_kahn);
     const long long ed = wsum64(A.e_dep), ee = wsum64(A.e_esc), ec = wsum64(A.e_cap);
+    uint32_t nh = 0;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) nh += fc[i];
     if (lane == 0 && nh > 0) {
         unsigned long long* fa = (unsigned long long*)(T.fates + (size_t)p * MC_N_FATES);
 #pragma unroll
-        for (int i = 0; i < 7; ++i) if (f[i]) atomicAdd(fa + i, (unsigned long long)f[i]);
+        for (int i = 0; i < 7; ++i) if (fc[i]) atomicAdd(fa + i, (unsigned long long)fc[i]);
         if (T.energy) {
             unsigned long long* ea = (unsigned long long*)(T.energy + (size_t)p * 4);
             atomicAdd(ea + 0, (unsigned long long)ed);
@@ -61,12 +61,14 @@ __device__ inline void flush(Acc& A, int p, const TransportArgs& T, int lane) {
             atomicAdd(ca + 2, (unsigned long long)nk);
             atomicAdd(ca + 3, (unsigned long long)nh);
         }
-        if (f[MC_CAPPED_FATE]) {
+        if (fc[MC_CAPPED_FATE]) {
             atomicOr((unsigned long long*)T.status, (unsigned long long)MC_STATUS_CAPPED);
-            atomicAdd((unsigned long long*)(T.status + 1), (unsigned long long)f[MC_CAPPED_FATE]);
+            atomicAdd((unsigned long long*)(T.status + 1), (unsigned long long)fc[MC_CAPPED_FATE]);
         }
     }
     acc_zero(A);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) fc[i] = 0;
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -75,16 +77,23 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Problem-local work index of (view, hist): view-major order.
+__device__ __forceinline__ uint64_t work_of(const Cst& C, uint64_t view, uint64_t hist) {
+    return view * C.q_per_view + min(view, C.r_extra) + hist;
+}
+
 // Persistent transport: waves claim chunks of work until none are left.
 __global__ __launch_bounds__(256) void k_transport(TransportArgs T) {
     const int lane = threadIdx.x & 63;
     const uint64_t lane_lt = (1ull << lane) - 1ull;
     const uint64_t full = __ballot(1);   // lanes of this wavefront
-    // chunk bookkeeping (wave-uniform)
-    uint64_t c_next = 0, c_end = 0;     // problem-local work indices
+    // chunk bookkeeping (wave-uniform): problem-local work range [c_next, c_end)
+    // and the (view, history id) of c_next
+    uint64_t c_next = 0, c_end = 0, cur_view = 0, cur_hist = 0;
     int p = -1;
     bool exhausted = false, have_pending = false;
     uint64_t pending = 0;
+    uint32_t fc[7] = {0, 0, 0, 0, 0, 0, 0};   // wave-uniform fate counts
     Cst C;
     Lane L;
     L.state = S_IDLE;
@@ -114,7 +123,7 @@ __global__ __launch_bounds__(256) void k_transport(TransportArgs T) {
                 const int np = __builtin_amdgcn_readfirstlane(lo);
                 if (np != p) {
                     if (need != full) break;       // drain problem p first
-                    if (p >= 0) flush(A, p, T, lane);
+                    if (p >= 0) flush(A, fc, p, T, lane);
                     p = np;
                     C = load_cst(T.descs + p);
                 }
@@ -124,37 +133,34 @@ __global__ __launch_bounds__(256) void k_transport(TransportArgs T) {
                 c_end = min(c_next + T.chunk, cnt);
                 have_pending = false;
                 if (C.flags != 0) { c_next = c_end; continue; }   // staging found bad input
+                split_work(C, C.work_begin + c_next, cur_view, cur_hist);
             }
             const uint64_t avail = c_end - c_next;
             const uint32_t rank = __popcll(need & lane_lt);
             if (L.state == S_IDLE && rank < avail) {
-                const uint64_t local = c_next + rank;
-                begin_history(C, L, C.work_begin + local, T.work_prefix[p] + local);
+                uint64_t v = cur_view, h = cur_hist;
+                advance_cursor(C, v, h, rank, C.n_views);
+                begin_history(C, L, v, h);
             }
             const uint64_t took = min((uint64_t)__popcll(need), avail);
             c_next += took;
+            advance_cursor(C, cur_view, cur_hist, took, C.n_views);
             need = __ballot(L.state == S_IDLE);
         }
         if (exhausted && __ballot(L.state != S_IDLE) == 0) break;
-        if (L.state == S_IDLE) continue;
 
-        uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
-        counter_of(L, c2, c3);
-        philox10(c0, c1, c2, c3, C.seed, C.pid);
+        int fate = R_RUNNING;
         int iu = -1, iv = -1;
-        const int fate = advance(C, L, c0, c1, c2, c3, A, iu, iv);
-        if (fate != R_RUNNING) {
-            // constant indices keep the counters in registers
-            switch (fate) {
-                case MC_ABSORBED: A.fate[MC_ABSORBED]++; break;
-                case MC_CUT: A.fate[MC_CUT]++; break;
-                case MC_ESCAPED: A.fate[MC_ESCAPED]++; break;
-                case MC_ESCAPED_FOV: A.fate[MC_ESCAPED_FOV]++; break;
-                case MC_OUT_OF_WINDOW: A.fate[MC_OUT_OF_WINDOW]++; break;
-                case MC_TALLIED: A.fate[MC_TALLIED]++; break;
-                default: A.fate[MC_CAPPED_FATE]++; break;
-            }
-            A.n_hist++;
+        if (L.state != S_IDLE) {
+            uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
+            counter_of(L, c2, c3);
+            philox10(c0, c1, c2, c3, C.seed, C.pid);
+            fate = advance(C, L, c0, c1, c2, c3, A, iu, iv);
+        }
+        if (__ballot(fate != R_RUNNING) != 0) {
+            // fate counts through ballots: wave-uniform, no per-lane counters
+#pragma unroll
+            for (int f = 0; f < 7; ++f) fc[f] += (uint32_t)__popcll(__ballot(fate == f));
             if (fate == MC_TALLIED) {
                 const int cls = L.n_scatter > 0 ? 1 : 0;
                 const uint32_t bin = (uint32_t)((((uint32_t)L.view * 2u + cls) * (uint32_t)C.nv + iv) *
@@ -166,17 +172,17 @@ __global__ __launch_bounds__(256) void k_transport(TransportArgs T) {
                     const unsigned long long idx = atomicAdd(T.n_events, 1ull);
                     if (T.events && idx < T.event_capacity) {
                         mc_event ev;
-                        ev.work = L.work;
+                        ev.work = T.work_prefix[p] + (work_of(C, L.view, L.hist) - C.work_begin);
                         ev.bin = bin;
                         ev.emit_voxel = L.emit_voxel;
                         T.events[idx] = ev;
                     }
                 }
             }
-            L.state = S_IDLE;
+            if (fate != R_RUNNING) L.state = S_IDLE;
         }
     }
-    if (p >= 0) flush(A, p, T, lane);
+    if (p >= 0) flush(A, fc, p, T, lane);
 }
 
 // Replay: one listed history per lane, run to its end, one record out.
@@ -190,7 +196,6 @@ __global__ __launch_bounds__(256) void k_replay(const ProbDesc* __restrict__ d,
     Lane L;
     L.hist = hists[i];
     L.view = views[i];
-    L.work = 0;
     L.state = S_EMIT0;
     L.n = 0; L.a = 0; L.n_scatter = 0; L.emit_voxel = 0;
     L.e = 0.0f;

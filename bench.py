@@ -70,6 +70,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--histories", type=float, default=1e8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="time only the headline workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -146,9 +147,81 @@ def main():
         "status": int(st[0]),
         "wall_s": wall,
     }
+    if not args.no_extra:
+        rec["forms"] = extra_forms(mc, torch, args)
+        a = rec["forms"].get("adjoint")
+        if a:
+            rec["adjoint_histories_per_s"] = a["value"]
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(rec))
+
+
+def timed(torch, fn, steps):
+    """Mean ms of fn() over steps runs, bracketed by device syncs and events."""
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def extra_forms(mc, torch, args):
+    """Throughput of the other forms: the point-source cube, the batched graph
+    launch over 32 uneven thoraxes, and the adjoint (forward with event list +
+    replaying gradient) on the 128^3 x 1 mm cube."""
+    import phantoms
+    out = {}
+    steps = max(args.steps, 1)
+    # plain, point source in a 64^3 water cube, 1e6 histories
+    p1 = phantoms.point_cube_64(10 ** 6)
+    s1 = mc.Simulator(mc.to_device(p1), want_sq=True)
+    s1.run()
+    ms = timed(torch, s1.run, steps)
+    out["point_cube_64"] = {"value": p1.n_histories / (ms / 1e3), "unit": "histories/s",
+                            "ms_per_step": ms, "histories": p1.n_histories}
+    # batched: 32 thoraxes 96^3-160^3, 30-120 views, 1e7 histories each, one graph
+    probs = phantoms.batched_thoraxes(10 ** 7)
+    dps = [mc.to_device(p) for p in probs]
+    opts = mc.autotune(dps, reps=1)
+    s3 = mc.Simulator(dps, want_sq=False, options=opts)
+    runner = mc.GraphRunner(s3)
+    runner.replay()
+    ms = timed(torch, runner.replay, steps)
+    s3.check_status()
+    n3 = sum(p.n_histories for p in probs)
+    out["batched"] = {"value": n3 / (ms / 1e3), "unit": "histories/s", "ms_per_step": ms,
+                      "histories": n3, "problems": len(probs), "options": opts,
+                      "launch": "hipGraph replay: staging x32 + one persistent transport kernel"}
+    # adjoint: forward with event list, loss gradient, replaying adjoint
+    p4 = phantoms.point_cube_128_adjoint(10 ** 7)
+    d4 = mc.to_device(p4)
+    ref = mc.simulate(d4.with_(seed=1), want_sq=False)
+    lam_ref = ref.tally.view(p4.tally_shape).to(torch.float64).sum(dim=1) * 2.0 ** -32
+    gen = torch.Generator(device=lam_ref.device)
+    gen.manual_seed(4)
+    y = torch.poisson(lam_ref, generator=gen)
+    s4 = mc.Simulator(d4, event_capacity=1 << 16, want_sq=False)
+
+    def adjoint_step():
+        s4.run()
+        lam = s4.tally.view(p4.tally_shape).to(torch.float64).sum(dim=1) * 2.0 ** -32
+        eps = 1e-6 * float(p4.n_histories)
+        G = (1.0 - y / (lam + eps)).unsqueeze(1).expand(-1, 2, -1, -1).contiguous()
+        return mc.adjoint(d4, G, s4)
+    adjoint_step()
+    ms_fwd = timed(torch, s4.run, steps)
+    ms = timed(torch, adjoint_step, steps)
+    out["adjoint"] = {"value": p4.n_histories / (ms / 1e3), "unit": "histories/s",
+                      "ms_per_step": ms, "forward_ms": ms_fwd, "histories": p4.n_histories,
+                      "tallied": int(s4.n_events.item()),
+                      "step": "forward with event list + Poisson-loss gradient + replaying adjoint"}
+    return out
 
 
 if __name__ == "__main__":

@@ -109,7 +109,8 @@ typedef struct {
     int32_t hist_per_lane;      /* histories per lane per work claim, <=0: auto */
     int32_t block_size;         /* threads per block (64..256), <=0: auto       */
     int32_t blocks_per_cu;      /* resident blocks per CU to launch, <=0: auto  */
-    int32_t reserved;
+    int32_t brick_log2;         /* accept-threshold layout: 0 linear (default), */
+                                /* 2 or 3: 4^3 or 8^3 voxel bricks              */
     void* kernel_events[2];     /* optional hipEvent_t pair recorded on the     */
                                 /* stream right before / after the transport    */
                                 /* kernel (NULL: none)                          */

@@ -57,7 +57,7 @@ class McProblem(C.Structure):
 
 class McOptions(C.Structure):
     _fields_ = [("hist_per_lane", C.c_int32), ("block_size", C.c_int32),
-                ("blocks_per_cu", C.c_int32), ("reserved", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("brick_log2", C.c_int32),
                 ("kernel_events", C.c_void_p * 2)]
 
 
@@ -177,7 +177,8 @@ def _opts(options: Optional[dict]) -> Optional[McOptions]:
         return None
     o = McOptions(hist_per_lane=int(options.get("hist_per_lane", 0)),
                   block_size=int(options.get("block_size", 0)),
-                  blocks_per_cu=int(options.get("blocks_per_cu", 0)), reserved=0)
+                  blocks_per_cu=int(options.get("blocks_per_cu", 0)),
+                  brick_log2=int(options.get("brick_log2", 0)))
     ev = options.get("kernel_events")
     if ev is not None:
         o.kernel_events[0] = ev[0]
@@ -422,3 +423,96 @@ def _mc_project_fn():
 
     _FN = _Fn
     return _FN
+
+
+# ---------------------------------------------------------------------------
+# Graph capture and autotuning of the batched launch
+# ---------------------------------------------------------------------------
+
+class GraphRunner:
+    """One mc_simulate_projections call on a Simulator captured as a HIP graph
+    (staging + transport + finalize as graph nodes); replay() relaunches it.
+    The graph holds the Simulator's buffers and options as captured."""
+
+    def __init__(self, sim: Simulator, warmup: int = 1):
+        torch = _torch()
+        self.sim = sim
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(warmup):
+                sim.run()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, capture_error_mode="thread_local"):
+            sim.run()
+        torch.cuda.synchronize()
+
+    def replay(self):
+        self.graph.replay()
+
+
+def _size_class(problems: Sequence[DeviceProblem]) -> str:
+    vox = sum(p.nx * p.ny * p.nz for p in problems)
+    hist = sum((p.history_count or p.n_histories - p.history_offset) for p in problems)
+    views = sum(p.n_views for p in problems)
+    b = lambda x: int(np.floor(np.log2(max(x, 1))))
+    return f"n{len(problems)}_vox2^{b(vox)}_hist2^{b(hist)}_views2^{b(views)}"
+
+
+_TUNE_CACHE = {}
+
+
+def autotune(problems: Union[DeviceProblem, Sequence[DeviceProblem]], *,
+             bricks=(0, 2, 3), hist_per_lane=(4, 16, 64), block_sizes=(256,), reps: int = 2,
+             cache_path: Optional[str] = None, verbose: bool = False) -> dict:
+    """Pick launch options (threshold brick size, histories per lane claim,
+    block size) by timing the transport kernel on these problems.  Every
+    candidate gives bit-identical results (layout and scheduling only); the
+    choice is cached per (GPU arch, size class)."""
+    import json
+    torch = _torch()
+    if isinstance(problems, DeviceProblem):
+        problems = [problems]
+    arch = torch.cuda.get_device_properties(problems[0].mu.device).gcnArchName
+    key = f"{arch}|{_size_class(problems)}"
+    if cache_path and os.path.exists(cache_path) and not _TUNE_CACHE:
+        try:
+            _TUNE_CACHE.update(json.load(open(cache_path)))
+        except (OSError, ValueError):
+            pass
+    if key in _TUNE_CACHE:
+        return dict(_TUNE_CACHE[key])
+    timer = KernelTimer()
+    best, best_ms, log = None, float("inf"), []
+    sim = None
+    for b in bricks:
+        for h in hist_per_lane:
+            for bs in block_sizes:
+                opts = {"brick_log2": b, "hist_per_lane": h, "block_size": bs}
+                if sim is None:
+                    sim = Simulator(problems, want_sq=False, options=opts)
+                else:
+                    sim.options = _opts(opts)
+                sim.run()
+                ms = []
+                for _ in range(reps):
+                    sim.run(kernel_events=timer.handles)
+                    torch.cuda.synchronize()
+                    ms.append(timer.elapsed_ms())
+                t = min(ms)
+                log.append((opts, t))
+                if t < best_ms:
+                    best, best_ms = opts, t
+    if verbose:
+        for o, t in log:
+            print(f"autotune {o}: {t:.3f} ms")
+    _TUNE_CACHE[key] = dict(best)
+    if cache_path:
+        try:
+            with open(cache_path, "w") as f:
+                json.dump(_TUNE_CACHE, f, indent=1)
+        except OSError:
+            pass
+    return dict(best)

@@ -18,6 +18,15 @@ constexpr int DEFAULT_HIST_PER_LANE = 16;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr int MAX_BRICK_LOG2 = 3;
+
+// Threshold storage for the largest brick size (grid padded to whole bricks).
+uint64_t padded_voxels(const mc_problem& p) {
+    const uint64_t b = 1u << MAX_BRICK_LOG2;
+    const uint64_t px = (p.nx + b - 1) / b * b, py = (p.ny + b - 1) / b * b, pz = (p.nz + b - 1) / b * b;
+    return px * py * pz;
+}
+
 double kn_bracket(double e) {
     // Klein-Nishina total cross-section per electron over 2 pi r_e^2.
     const double k = e / 510.99895;
@@ -74,7 +83,7 @@ bool plan(const mc_problem* probs, int n, Layout& L) {
     for (int i = 0; i < n; ++i) {
         const mc_problem& p = probs[i];
         const uint64_t nvox = (uint64_t)p.nx * p.ny * p.nz;
-        L.q[i] = off;     off += align256(4 * nvox);
+        L.q[i] = off;     off += align256(4 * padded_voxels(p));
         L.cdf[i] = off;   off += align256(8 * nvox);
         L.vid[i] = off;   off += align256(4 * nvox);
         L.bsum[i] = off;  off += align256(8 * ((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS));
@@ -87,7 +96,8 @@ bool plan(const mc_problem* probs, int n, Layout& L) {
     return true;
 }
 
-ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64_t tally_offset) {
+ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64_t tally_offset,
+                   int brick_log2) {
     ProbDesc d;
     std::memset(&d, 0, sizeof(d));
     d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.source_mode = p.source_mode;
@@ -107,6 +117,9 @@ ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64
     d.e_lo = (float)p.e_lo_kev; d.e_hi = (float)p.e_hi_kev; d.e_cut = (float)p.e_cut_kev;
     d.f_pe = (float)p.pe_fraction;
     d.max_steps = p.max_steps ? p.max_steps : DEFAULT_MAX_STEPS;
+    d.brick_log2 = brick_log2;
+    const int b = 1 << brick_log2;
+    d.nbx = (p.nx + b - 1) / b; d.nby = (p.ny + b - 1) / b; d.nbz = (p.nz + b - 1) / b;
     d.seed = p.seed; d.problem_id = p.problem_id;
     if (p.image_factor > 0) { d.img_nx = p.nx / p.image_factor; d.img_ny = p.ny / p.image_factor; }
     d.kn140 = kn_bracket(140.0);
@@ -133,15 +146,24 @@ int hip_fail(hipError_t e) {
     return MC_EDEVICE;
 }
 
-void resolve(const mc_options* opt, int& block, int& hpl, int& bpc) {
+void resolve(const mc_options* opt, int& block, int& hpl, int& bpc, int& brick) {
     block = DEFAULT_BLOCK;
     hpl = DEFAULT_HIST_PER_LANE;
     bpc = 0;
+    brick = 0;
     if (opt) {
         if (opt->block_size > 0) block = opt->block_size;
         if (opt->hist_per_lane > 0) hpl = opt->hist_per_lane;
         if (opt->blocks_per_cu > 0) bpc = opt->blocks_per_cu;
+        if (opt->brick_log2 > 0) brick = opt->brick_log2;
     }
+}
+
+bool options_ok(int block, int hpl, int brick) {
+    if (block < 64 || block > 256 || block % 64 != 0) return false;
+    if (hpl < 1 || hpl > (1 << 20)) return false;
+    if (brick < 0 || brick > MAX_BRICK_LOG2 || brick == 1) return false;
+    return true;
 }
 
 }  // namespace
@@ -164,10 +186,9 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     if (!problems || n_problems < 1 || !tally || !fates || !status || !workspace) return MC_EINVAL;
     if (events && !n_events) return MC_EINVAL;
     for (int i = 0; i < n_problems; ++i) if (!check_problem(problems[i])) return MC_EINVAL;
-    int block, hpl, bpc;
-    resolve(opt, block, hpl, bpc);
-    if (block < 64 || block > 256 || block % 64 != 0) return MC_EINVAL;
-    if (hpl < 1 || hpl > (1 << 20)) return MC_EINVAL;
+    int block, hpl, bpc, brick;
+    resolve(opt, block, hpl, bpc, brick);
+    if (!options_ok(block, hpl, brick)) return MC_EINVAL;
     Layout L;
     plan(problems, n_problems, L);
     if (workspace_bytes < L.total) return MC_ENOMEM;
@@ -177,7 +198,7 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     uint64_t tally_elems = 0;
     for (int i = 0; i < n_problems; ++i) {
         const mc_problem& p = problems[i];
-        const ProbDesc h = host_desc(p, ws, L, i, tally_elems);
+        const ProbDesc h = host_desc(p, ws, L, i, tally_elems, brick);
         tally_elems += (uint64_t)p.n_views * 2 * p.nv * p.nu;
         hipError_t e = launch_staging(d_desc + i, h, st);
         if (e != hipSuccess) return hip_fail(e);
@@ -224,16 +245,16 @@ int mc_replay_histories(const mc_problem* problem, const mc_options* opt, const 
     if (!problem || !status || !workspace || n < 0) return MC_EINVAL;
     if (n > 0 && (!views || !hists || !records)) return MC_EINVAL;
     if (!check_problem(*problem)) return MC_EINVAL;
-    int block, hpl, bpc;
-    resolve(opt, block, hpl, bpc);
-    if (block < 64 || block > 256 || block % 64 != 0) return MC_EINVAL;
+    int block, hpl, bpc, brick;
+    resolve(opt, block, hpl, bpc, brick);
+    if (!options_ok(block, hpl, brick)) return MC_EINVAL;
     Layout L;
     plan(problem, 1, L);
     if (workspace_bytes < L.total) return MC_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)workspace;
     ProbDesc* d_desc = (ProbDesc*)(ws + L.desc);
-    const ProbDesc h = host_desc(*problem, ws, L, 0, 0);
+    const ProbDesc h = host_desc(*problem, ws, L, 0, 0, brick);
     hipError_t e = launch_staging(d_desc, h, st);
     if (e != hipSuccess) return hip_fail(e);
     e = launch_replay(d_desc, views, hists, n, records, status, block, st);
@@ -241,7 +262,7 @@ int mc_replay_histories(const mc_problem* problem, const mc_options* opt, const 
     return MC_OK;
 }
 
-int mc_adjoint_mu(const mc_problem* problem, const mc_options*, const double* dL_dtally,
+int mc_adjoint_mu(const mc_problem* problem, const mc_options* opt, const double* dL_dtally,
                   const mc_event* events, const uint64_t* n_events, uint64_t event_capacity,
                   int64_t* dL_dmu, int32_t frac_bits, int64_t* status, void* workspace,
                   size_t workspace_bytes, void* stream) {
@@ -249,13 +270,16 @@ int mc_adjoint_mu(const mc_problem* problem, const mc_options*, const double* dL
     if (events && !n_events) return MC_EINVAL;
     if (frac_bits < 0 || frac_bits > 62) return MC_EINVAL;
     if (!check_problem(*problem)) return MC_EINVAL;
+    int block, hpl, bpc, brick;
+    resolve(opt, block, hpl, bpc, brick);
+    if (!options_ok(block, hpl, brick)) return MC_EINVAL;
     Layout L;
     plan(problem, 1, L);
     if (workspace_bytes < L.total) return MC_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)workspace;
     ProbDesc* d_desc = (ProbDesc*)(ws + L.desc);
-    const ProbDesc h = host_desc(*problem, ws, L, 0, 0);
+    const ProbDesc h = host_desc(*problem, ws, L, 0, 0, brick);
     hipError_t e = launch_staging(d_desc, h, st);
     if (e != hipSuccess) return hip_fail(e);
     int dev = 0, n_cu = 0;

@@ -74,6 +74,8 @@ struct Cst {
     uint32_t seed, pid, max_steps, shift;
     uint64_t total, q_per_view, r_extra, work_begin, tally_offset;
     uint32_t flags;
+    int brick;
+    uint32_t bmask, nbx, nby;
 };
 
 __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
@@ -97,6 +99,9 @@ __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     c.total = d->total; c.q_per_view = d->q_per_view; c.r_extra = d->r_extra;
     c.work_begin = d->work_begin; c.tally_offset = d->tally_offset;
     c.flags = d->flags;
+    c.brick = d->brick_log2;
+    c.bmask = (1u << c.brick) - 1u;
+    c.nbx = (uint32_t)d->nbx; c.nby = (uint32_t)d->nby;
     return c;
 }
 
@@ -254,7 +259,8 @@ __device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, u
         const int ix = min((int)(tx * C.inv_vox), C.nx - 1);
         const int iy = min((int)(ty * C.inv_vox), C.ny - 1);
         const int iz = min((int)(tz * C.inv_vox), C.nz - 1);
-        const uint32_t q = C.q32[(uint32_t)ix + (uint32_t)C.nx * ((uint32_t)iy + (uint32_t)C.ny * (uint32_t)iz)];
+        const uint32_t q = C.q32[brick_index((uint32_t)ix, (uint32_t)iy, (uint32_t)iz, (uint32_t)C.nx,
+                                             (uint32_t)C.ny, C.brick, C.bmask, C.nbx, C.nby)];
         L.x = xn; L.y = yn; L.z = zn;
         if ((w1 >> 8) < q) {
             A.n_real++;

@@ -20,7 +20,9 @@ struct ProbDesc {
     float pix, inv_pix, radius, cos_alpha;
     float wu, wv, e_lo, e_hi;
     float e_cut, f_pe;
-    uint32_t max_steps, pad0;
+    uint32_t max_steps;
+    int32_t brick_log2;             // threshold layout: 0 linear, b > 0: 2^b-voxel cubic bricks
+    int32_t nbx, nby, nbz, pad0;    // bricks per axis
     uint32_t seed, problem_id;
     int32_t img_nx, img_ny;
     double kn140;                   // Klein-Nishina bracket at 140 keV
@@ -55,6 +57,17 @@ constexpr int SCAN_ITEMS = 4096;    // activity values per scan block
 constexpr int KN_TABLE_N = 568;     // entries of the Klein-Nishina shape table (>= 4*140 + 2)
 constexpr int MAX_AXIS = 1024;      // voxel indices are packed 10 bits per axis
 constexpr int SCAN_THREADS = 256;
+
+// Index of voxel (ix, iy, iz) in the threshold array: linear for b = 0, else
+// brick-major over nbx x nby x nbz bricks of 2^b voxels per side.
+__host__ __device__ inline uint32_t brick_index(uint32_t ix, uint32_t iy, uint32_t iz, uint32_t nx,
+                                                uint32_t ny, int b, uint32_t m, uint32_t nbx,
+                                                uint32_t nby) {
+    if (b == 0) return ix + nx * (iy + ny * iz);
+    const uint32_t brick = ((iz >> b) * nby + (iy >> b)) * nbx + (ix >> b);
+    const uint32_t local = (((iz & m) << b | (iy & m)) << b) | (ix & m);
+    return (brick << (3 * b)) | local;
+}
 
 // Global counters of one call (in the workspace).
 struct CallState {

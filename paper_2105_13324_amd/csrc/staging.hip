@@ -72,21 +72,27 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* pd) {
 }
 
 // Q_v in double precision: mu_v * 2^24 is exact, the division is correctly
-// rounded, ceil is exact.
+// rounded, ceil is exact.  Stored linear (b = 0) or in 2^b-voxel cubic bricks,
+// so a brick is a few whole cache lines (the layout never changes a result).
 __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* pd) {
     const uint64_t nvox = pd->nvox;
     const float mu_hat = __uint_as_float(pd->mu_hat_bits);
     const float* __restrict__ mu = pd->mu;
     uint32_t* __restrict__ q = pd->q32;
+    const uint32_t nx = (uint32_t)pd->nx, ny = (uint32_t)pd->ny;
+    const int b = pd->brick_log2;
+    const uint32_t m = (1u << b) - 1u;
+    const uint32_t nbx = (uint32_t)pd->nbx, nby = (uint32_t)pd->nby;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        const float m = mu[i];
+        const float mv = mu[i];
         uint32_t v = 0;
-        if (mu_hat > 0.0f && m > 0.0f) {
-            double t = ceil((double)m * 16777216.0 / (double)mu_hat);
+        if (mu_hat > 0.0f && mv > 0.0f) {
+            double t = ceil((double)mv * 16777216.0 / (double)mu_hat);
             v = t >= 16777216.0 ? 16777216u : (uint32_t)t;
         }
-        q[i] = v;
+        const uint32_t ix = (uint32_t)(i % nx), iy = (uint32_t)((i / nx) % ny), iz = (uint32_t)(i / ((uint64_t)nx * ny));
+        q[brick_index(ix, iy, iz, nx, ny, b, m, nbx, nby)] = v;
     }
 }
 

@@ -105,7 +105,7 @@ def test_workspace_bytes_and_validation():
         dict(radius_cm=2.0), dict(accept_half_angle_rad=0.0), dict(accept_half_angle_rad=2.0),
         dict(e_lo_kev=160.0), dict(e_cut_kev=0.0), dict(pe_fraction=1.5), dict(n_histories=0),
         dict(history_offset=2000), dict(history_offset=500, history_count=600),
-        dict(image_factor=3), dict(source_mode=7),
+        dict(image_factor=3), dict(source_mode=7), dict(nx=1025), dict(e_cut_kev=0.5),
     ]
     for b in bad:
         q = _good()
@@ -132,7 +132,9 @@ def test_simulate_rejects_bad_buffers_before_launch():
     # workspace too small
     assert sim(C.byref(p), 1, None, 8, None, 8, None, None, None, 0, None, 8, 8, need - 1, None) == mc.MC_ENOMEM
     # bad options
-    o = mc.McOptions(hist_per_lane=0, block_size=96, blocks_per_cu=0, reserved=0)
+    o = mc.McOptions(hist_per_lane=0, block_size=96, blocks_per_cu=0, brick_log2=0)
+    assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
+    o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=1)
     assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
     assert sim(None, 1, None, 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
     assert mc._lib.mc_error_string(mc.MC_EINVAL) == b"invalid argument"

@@ -71,6 +71,7 @@ def main():
     ap.add_argument("--histories", type=float, default=1e8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="time only the headline workload")
+    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 / 1e9-history form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -221,7 +222,38 @@ def extra_forms(mc, torch, args):
                       "ms_per_step": ms, "forward_ms": ms_fwd, "histories": p4.n_histories,
                       "tallied": int(s4.n_events.item()),
                       "step": "forward with event list + Poisson-loss gradient + replaying adjoint"}
+    del s4, d4, ref
+    if not args.no_large:
+        out["large_mlem"] = large_form(mc, torch, steps)
     return out
+
+
+def large_form(mc, torch, steps):
+    """256^3 x 1.5 mm thorax, 120 views over 360 deg, 128^2 x 3 mm, 1e9
+    histories with an event list, response matrix on the 64^3 image, 50 MLEM
+    iterations."""
+    import phantoms
+    p5 = phantoms.thorax_256(10 ** 9)
+    d5 = mc.to_device(p5)
+    s5 = mc.Simulator(d5, event_capacity=1 << 21, want_sq=False)
+    s5.run()
+    ms_fwd = timed(torch, s5.run, steps)
+    s5.check_status()
+    m = mc.system_matrix(d5, s5)
+    ms_sys = timed(torch, lambda: mc.system_matrix(d5, s5), steps)
+    ml = mc.Mlem(m)
+    img = torch.ones(m.n_img, dtype=torch.float32, device="cuda")
+
+    def recon():
+        img.fill_(1.0)
+        ml.run(img, 50)
+    recon()
+    ms_mlem = timed(torch, recon, steps)
+    return {"value": p5.n_histories / (ms_fwd / 1e3), "unit": "histories/s",
+            "forward_ms": ms_fwd, "system_matrix_ms": ms_sys, "mlem_50_ms": ms_mlem,
+            "mlem_iteration_ms": ms_mlem / 50, "histories": p5.n_histories,
+            "tallied": int(s5.n_events.item()), "nnz": m.nnz,
+            "bins": m.n_bins, "image_voxels": m.n_img}
 
 
 if __name__ == "__main__":

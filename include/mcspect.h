@@ -192,6 +192,45 @@ int mc_adjoint_mu(const mc_problem* problem, const mc_options* opt, const double
                   int64_t* dL_dmu, int32_t frac_bits, int64_t* status,
                   void* workspace, size_t workspace_bytes, void* stream);
 
+/* Workspace bytes of mc_system_matrix (0 on invalid arguments). */
+size_t mc_system_matrix_workspace_bytes(const mc_problem* problem, uint64_t event_capacity);
+
+/* Monte Carlo response matrix of Sec. 5.1 (Eq. IMC) from a forward call's
+ * event list: T_ij = c_ij / n_i(j), the estimated probability that a photon
+ * emitted in image voxel i is counted in projection bin j; c_ij counts the
+ * tallied histories emitted in i and counted in j, n_i(j) = N_view(j) A_i / A
+ * the expected emissions from i towards bin j's view (A_i: activity of image
+ * voxel i, A: total).  Image voxel = phantom voxel / image_factor per axis
+ * (image_factor >= 1).  Bins merge the primary and scatter classes:
+ * j = (view * nv + iv) * nu + iu, n_bins = V nv nu.  Both orientations are
+ * written as CSR with columns ascending:
+ *   T_rowptr   device int64 [n_bins + 1];  T_col int32, T_val float [capacity]
+ *   Tt_rowptr  device int64 [n_img + 1];   Tt_col int32, Tt_val float [capacity]
+ *   proj       device float [n_bins]: P_j = sum_i c_ij (nullable)
+ * nnz = T_rowptr[n_bins] = Tt_rowptr[n_img] <= min(*n_events, capacity).
+ * events / n_events / event_capacity: as returned by mc_simulate_projections
+ * for this problem.  Deterministic (integer counts, sorted rows). */
+int mc_system_matrix(const mc_problem* problem, const mc_event* events, const uint64_t* n_events,
+                     uint64_t event_capacity,
+                     int64_t* T_rowptr, int32_t* T_col, float* T_val,
+                     int64_t* Tt_rowptr, int32_t* Tt_col, float* Tt_val, float* proj,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace bytes of mlem_iterate. */
+size_t mlem_workspace_bytes(int64_t n_bins, int64_t n_vox);
+
+/* n_iter MLEM updates (Sec. 5.1, Eq. MLEM):
+ *   S_i <- S_i / sens_i * sum_j T_ij P_j / y_j,  y = T S,  sens_i = sum_j T_ij,
+ * with T given as CSR in both orientations (rows = bins: T_*, rows = voxels:
+ * Tt_*, the same matrix), float values, double accumulation.  image: device
+ * float [n_vox], in: S^0 (voxels with sens_i = 0 are set to 0), out: S^n_iter.
+ * proj: device float [n_bins].  A bin with y_j = 0 contributes nothing. */
+int mlem_iterate(int64_t n_bins, int64_t n_vox,
+                 const int64_t* T_rowptr, const int32_t* T_col, const float* T_val,
+                 const int64_t* Tt_rowptr, const int32_t* Tt_col, const float* Tt_val,
+                 const float* proj, float* image, int32_t n_iter,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
 /* Human-readable text for an MC_* code (static storage). */
 const char* mc_error_string(int code);
 

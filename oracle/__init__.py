@@ -280,10 +280,14 @@ def poisson_loss_grad(lam: np.ndarray, y: np.ndarray, eps: float):
 # ---------------------------------------------------------------------------
 
 def system_matrix(prob, trip_i: np.ndarray, trip_j: np.ndarray):
-    """T_hat_ij = c_ij / n_i with c_ij the tallied count of photons emitted in
-    image voxel i and counted in bin j, and n_i = N_view(j) * A_i / A the expected
-    number emitted in i towards that bin's view (A_i: activity summed over the
-    image voxel).  Returns (rows=bins CSR as scipy, image activity fraction)."""
+    """Response matrix of Sec. 5.1 (Eq. IMC) from the tallied histories.
+
+    T_ij = c_ij / n_i(j): c_ij tallied photons emitted in image voxel i and
+    counted in projection bin j (primary and scattered alike: j = (view, iv,
+    iu)), n_i(j) = N_view(j) * A_i / A the expected number emitted in i towards
+    bin j's view (A_i: activity summed over image voxel i, A: total).  Returns
+    (T as scipy CSR, rows = bins, FP64; P_j = sum_i c_ij; expected emissions
+    n_i per view-averaged history count)."""
     import scipy.sparse as sp
     f = prob.image_factor
     mx, my, mz = prob.nx // f, prob.ny // f, prob.nz // f
@@ -291,17 +295,19 @@ def system_matrix(prob, trip_i: np.ndarray, trip_j: np.ndarray):
     act = prob.activity.astype(np.float64)
     a_img = act.reshape(mz, f, my, f, mx, f).sum(axis=(1, 3, 5)).reshape(-1)
     total = act.sum()
-    nbins = prob.n_views * 2 * prob.nv * prob.nu
-    V = prob.n_views
-    per_bin_view = np.arange(nbins) // (2 * prob.nv * prob.nu)
+    V, per = prob.n_views, prob.nv * prob.nu
+    n_bins = V * per
+    view = trip_j // (2 * per)
+    row = view * per + trip_j % per
     n_view = np.array([prob.n_histories // V + (1 if k < prob.n_histories % V else 0)
                        for k in range(V)], dtype=np.float64)
-    c = sp.coo_matrix((np.ones(len(trip_i)), (trip_j, trip_i)), shape=(nbins, n_img)).tocsr()
+    c = sp.coo_matrix((np.ones(len(trip_i)), (row, trip_i)), shape=(n_bins, n_img)).tocsr()
     c.sum_duplicates()
+    P = np.asarray(c.sum(axis=1)).ravel()
     c = c.tocoo()
-    n_i = n_view[per_bin_view[c.row]] * a_img[c.col] / total
-    T = sp.csr_matrix((c.data / n_i, (c.row, c.col)), shape=(nbins, n_img))
-    return T, a_img / total
+    n_i = n_view[c.row // per] * a_img[c.col] / total
+    T = sp.csr_matrix((c.data / n_i, (c.row, c.col)), shape=(n_bins, n_img))
+    return T, P, a_img / total
 
 
 def mlem(T, P: np.ndarray, n_iter: int, S0: Optional[np.ndarray] = None) -> np.ndarray:

@@ -36,7 +36,8 @@ Q23 = float(2 ** 23)   # energy fixed point: Q40.23 keV
 
 # Exported symbols, as declared in include/mcspect.h.
 EXPORTS = ["mc_workspace_bytes", "mc_simulate_projections", "mc_replay_histories",
-           "mc_adjoint_mu", "mc_error_string", "mc_last_hip_error"]
+           "mc_adjoint_mu", "mc_system_matrix_workspace_bytes", "mc_system_matrix",
+           "mlem_workspace_bytes", "mlem_iterate", "mc_error_string", "mc_last_hip_error"]
 
 
 class McProblem(C.Structure):
@@ -79,6 +80,15 @@ _lib.mc_replay_histories.restype = C.c_int
 _lib.mc_adjoint_mu.argtypes = [C.POINTER(McProblem), C.POINTER(McOptions), _vp, _vp, _vp, _u64,
                                _vp, C.c_int32, _vp, _vp, _sz, _vp]
 _lib.mc_adjoint_mu.restype = C.c_int
+_lib.mc_system_matrix_workspace_bytes.argtypes = [C.POINTER(McProblem), _u64]
+_lib.mc_system_matrix_workspace_bytes.restype = _sz
+_lib.mc_system_matrix.argtypes = [C.POINTER(McProblem), _vp, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp,
+                                  _vp, _vp, _sz, _vp]
+_lib.mc_system_matrix.restype = C.c_int
+_lib.mlem_workspace_bytes.argtypes = [_i64, _i64]
+_lib.mlem_workspace_bytes.restype = _sz
+_lib.mlem_iterate.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, _sz, _vp]
+_lib.mlem_iterate.restype = C.c_int
 _lib.mc_error_string.argtypes = [C.c_int]
 _lib.mc_error_string.restype = C.c_char_p
 _lib.mc_last_hip_error.argtypes = []
@@ -516,3 +526,104 @@ def autotune(problems: Union[DeviceProblem, Sequence[DeviceProblem]], *,
         except OSError:
             pass
     return dict(best)
+
+
+# ---------------------------------------------------------------------------
+# Response matrix and MLEM (Sec. 5.1)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class SystemMatrix:
+    """Monte Carlo response matrix in CSR, both orientations (device tensors).
+    Rows of T are projection bins (view, iv, iu); rows of Tt are image voxels."""
+    n_bins: int
+    n_img: int
+    T_rowptr: "object"
+    T_col: "object"
+    T_val: "object"
+    Tt_rowptr: "object"
+    Tt_col: "object"
+    Tt_val: "object"
+    proj: "object"
+
+    @property
+    def nnz(self) -> int:
+        return int(self.T_rowptr[-1].item())
+
+    def to_scipy(self, transpose: bool = False):
+        import scipy.sparse as sp
+        n = self.nnz
+        if transpose:
+            return sp.csr_matrix((self.Tt_val[:n].cpu().numpy(), self.Tt_col[:n].cpu().numpy(),
+                                  self.Tt_rowptr.cpu().numpy()), shape=(self.n_img, self.n_bins))
+        return sp.csr_matrix((self.T_val[:n].cpu().numpy(), self.T_col[:n].cpu().numpy(),
+                              self.T_rowptr.cpu().numpy()), shape=(self.n_bins, self.n_img))
+
+
+def system_matrix(problem: DeviceProblem, sim: Simulator) -> SystemMatrix:
+    """Response matrix from the event list of a forward Simulator run."""
+    torch = _torch()
+    if sim.events is None:
+        raise McError("the forward run kept no event list")
+    if problem.image_factor < 1:
+        raise McError("problem.image_factor must be >= 1")
+    dev = problem.mu.device
+    f = problem.image_factor
+    n_bins = problem.n_views * problem.nv * problem.nu
+    n_img = (problem.nx // f) * (problem.ny // f) * (problem.nz // f)
+    cap = sim.event_capacity
+    arr = problem.c_struct()
+    nb = _lib.mc_system_matrix_workspace_bytes(C.byref(arr), cap)
+    if nb == 0:
+        raise McError("mc_system_matrix_workspace_bytes: invalid arguments")
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    m = SystemMatrix(n_bins, n_img,
+                     torch.empty(n_bins + 1, dtype=torch.int64, device=dev),
+                     torch.empty(cap, dtype=torch.int32, device=dev),
+                     torch.empty(cap, dtype=torch.float32, device=dev),
+                     torch.empty(n_img + 1, dtype=torch.int64, device=dev),
+                     torch.empty(cap, dtype=torch.int32, device=dev),
+                     torch.empty(cap, dtype=torch.float32, device=dev),
+                     torch.empty(n_bins, dtype=torch.float32, device=dev))
+    rc = _lib.mc_system_matrix(C.byref(arr), sim.events.data_ptr(), sim.n_events.data_ptr(), cap,
+                               m.T_rowptr.data_ptr(), m.T_col.data_ptr(), m.T_val.data_ptr(),
+                               m.Tt_rowptr.data_ptr(), m.Tt_col.data_ptr(), m.Tt_val.data_ptr(),
+                               m.proj.data_ptr(), ws.data_ptr(), nb, _stream_ptr())
+    _check(rc, "mc_system_matrix")
+    return m
+
+
+class Mlem:
+    """mlem_iterate on fixed CSR buffers (workspace allocated once)."""
+
+    def __init__(self, m: SystemMatrix):
+        torch = _torch()
+        self.m = m
+        nb = _lib.mlem_workspace_bytes(m.n_bins, m.n_img)
+        if nb == 0:
+            raise McError("mlem_workspace_bytes: invalid sizes")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=m.T_val.device)
+
+    def run(self, image, n_iter: int, proj=None):
+        """image: float32 device tensor [n_img], S^0 in, S^n_iter out (in place)."""
+        m = self.m
+        P = m.proj if proj is None else proj
+        rc = _lib.mlem_iterate(m.n_bins, m.n_img, m.T_rowptr.data_ptr(), m.T_col.data_ptr(),
+                               m.T_val.data_ptr(), m.Tt_rowptr.data_ptr(), m.Tt_col.data_ptr(),
+                               m.Tt_val.data_ptr(), P.data_ptr(), image.data_ptr(), int(n_iter),
+                               self.ws.data_ptr(), self.ws.numel(), _stream_ptr())
+        _check(rc, "mlem_iterate")
+        return image
+
+
+def csr_from_scipy(T, device="cuda") -> SystemMatrix:
+    """Device CSR pair from a host scipy matrix (rows = bins) and proj = 0."""
+    torch = _torch()
+    T = T.tocsr()
+    T.sort_indices()
+    Tt = T.T.tocsr()
+    Tt.sort_indices()
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a).astype(dt), device=device)
+    return SystemMatrix(T.shape[0], T.shape[1], t(T.indptr, np.int64), t(T.indices, np.int32),
+                        t(T.data, np.float32), t(Tt.indptr, np.int64), t(Tt.indices, np.int32),
+                        t(Tt.data, np.float32), torch.zeros(T.shape[0], dtype=torch.float32, device=device))

@@ -292,6 +292,57 @@ int mc_adjoint_mu(const mc_problem* problem, const mc_options* opt, const double
     return MC_OK;
 }
 
+size_t mc_system_matrix_workspace_bytes(const mc_problem* problem, uint64_t event_capacity) {
+    if (!problem || !check_problem(*problem) || problem->image_factor < 1) return 0;
+    const mc_problem& p = *problem;
+    const uint64_t n_bins = (uint64_t)p.n_views * p.nu * p.nv;
+    const uint64_t f = (uint64_t)p.image_factor;
+    const uint64_t n_img = (p.nx / f) * (p.ny / f) * (p.nz / f);
+    return sysmat_workspace_bytes(n_bins, n_img, event_capacity);
+}
+
+int mc_system_matrix(const mc_problem* problem, const mc_event* events, const uint64_t* n_events,
+                     uint64_t event_capacity, int64_t* T_rowptr, int32_t* T_col, float* T_val,
+                     int64_t* Tt_rowptr, int32_t* Tt_col, float* Tt_val, float* proj,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+    if (!problem || !events || !n_events || !T_rowptr || !T_col || !T_val || !Tt_rowptr ||
+        !Tt_col || !Tt_val || !workspace)
+        return MC_EINVAL;
+    if (!check_problem(*problem) || problem->image_factor < 1) return MC_EINVAL;
+    if (event_capacity < 1 || event_capacity >= (1ull << 31)) return MC_EINVAL;
+    const mc_problem& p = *problem;
+    if ((uint64_t)p.n_views * p.nu * p.nv >= (1ull << 31)) return MC_EINVAL;
+    if (workspace_bytes < mc_system_matrix_workspace_bytes(problem, event_capacity)) return MC_ENOMEM;
+    hipError_t e = launch_sysmat(events, (const unsigned long long*)n_events, event_capacity,
+                                 (uint32_t)p.nx, (uint32_t)p.ny, (uint32_t)p.nz,
+                                 (uint32_t)p.image_factor, (uint32_t)p.n_views, (uint32_t)p.nu,
+                                 (uint32_t)p.nv, p.n_histories, p.activity, T_rowptr, T_col, T_val,
+                                 Tt_rowptr, Tt_col, Tt_val, proj, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return MC_OK;
+}
+
+size_t mlem_workspace_bytes(int64_t n_bins, int64_t n_vox) {
+    if (n_bins < 1 || n_vox < 1) return 0;
+    return mlem_workspace((uint64_t)n_bins, (uint64_t)n_vox);
+}
+
+int mlem_iterate(int64_t n_bins, int64_t n_vox, const int64_t* T_rowptr, const int32_t* T_col,
+                 const float* T_val, const int64_t* Tt_rowptr, const int32_t* Tt_col,
+                 const float* Tt_val, const float* proj, float* image, int32_t n_iter,
+                 void* workspace, size_t workspace_bytes, void* stream) {
+    if (n_bins < 1 || n_vox < 1 || n_iter < 0) return MC_EINVAL;
+    if (n_bins >= (1ll << 31) || n_vox >= (1ll << 31)) return MC_EINVAL;
+    if (!T_rowptr || !T_col || !T_val || !Tt_rowptr || !Tt_col || !Tt_val || !proj || !image ||
+        !workspace)
+        return MC_EINVAL;
+    if (workspace_bytes < mlem_workspace((uint64_t)n_bins, (uint64_t)n_vox)) return MC_ENOMEM;
+    hipError_t e = launch_mlem(n_bins, n_vox, T_rowptr, T_col, T_val, Tt_rowptr, Tt_col, Tt_val,
+                               proj, image, n_iter, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return MC_OK;
+}
+
 const char* mc_error_string(int code) {
     switch (code) {
         case MC_OK: return "ok";

@@ -1,0 +1,411 @@
+// Monte Carlo response matrix and MLEM (paper Sec. 5.1, Eq. IMC and Eq. MLEM).
+//
+// Response matrix.  Each tallied history of the forward call is an event
+// (projection bin j, phantom voxel of emission).  With i the image voxel of
+// the emission (phantom voxel / image_factor per axis),
+//     T_ij = c_ij / n_i(j),   n_i(j) = N_view(j) * A_i / A,
+// c_ij the number of events (i, j), N_view(j) the histories of bin j's view,
+// A_i the activity in image voxel i and A the total: the estimated probability
+// that a photon emitted in image voxel i is counted in bin j.  Bins merge the
+// primary and scatter classes (the camera cannot tell them apart): j =
+// (view * nv + iv) * nu + iu.  The projection P_j = sum_i c_ij is the same
+// run's counts, so P = T n exactly.
+//
+// Both orientations are built as CSR (bins x voxels and voxels x bins) by a
+// deterministic counting sort: rows counted with integer atomics, scanned,
+// scattered, each row's columns sorted and merged.  Integer counts make the
+// result independent of the atomics' order.
+//
+// MLEM.  S_i <- S_i / sens_i * sum_j T_ij P_j / y_j, y = T S, sens_i =
+// sum_j T_ij; FP32 matrix values, FP64 accumulation; bins with y_j = 0 add
+// nothing; voxels with sens_i = 0 stay 0.  One thread per row: the matrix is
+// far sparser than one entry per row, so the row pointers and vectors are the
+// traffic (HBM-bound).
+#include "mc_internal.h"
+
+namespace mcs {
+namespace {
+
+constexpr int T256 = 256;
+constexpr int SCAN_PER = 16;                     // items per thread in the block scan
+constexpr int SCAN_BLOCK = T256 * SCAN_PER;      // items per scan block
+
+int grid_for(uint64_t n, int threads, int cap) {
+    uint64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > (uint64_t)cap) g = cap;
+    return (int)g;
+}
+
+__device__ inline uint64_t wave_sum64(uint64_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---- generic exclusive scan: uint32 counts -> uint64 offsets [n + 1] ----
+
+__global__ __launch_bounds__(T256) void k_sum_blocks(const uint32_t* __restrict__ in, uint64_t n,
+                                                     uint64_t* __restrict__ bsum) {
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK;
+    uint64_t s = 0;
+    for (int j = threadIdx.x; j < SCAN_BLOCK; j += T256) {
+        const uint64_t i = base + j;
+        if (i < n) s += in[i];
+    }
+    s = wave_sum64(s);
+    __shared__ uint64_t part[T256 / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < T256 / 64; ++w) t += part[w];
+        bsum[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint64_t* bsum, int nb) {
+    __shared__ uint64_t tot[1024];
+    const int per = (nb + 1023) / 1024;
+    const int b0 = threadIdx.x * per;
+    uint64_t s = 0;
+    for (int j = 0; j < per; ++j) if (b0 + j < nb) s += bsum[b0 + j];
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint64_t v = threadIdx.x >= (unsigned)off ? tot[threadIdx.x - off] : 0;
+        __syncthreads();
+        tot[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint64_t run = tot[threadIdx.x] - s;
+    for (int j = 0; j < per; ++j) {
+        if (b0 + j < nb) {
+            const uint64_t v = bsum[b0 + j];
+            bsum[b0 + j] = run;
+            run += v;
+        }
+    }
+}
+
+// out[i] = sum_{k<i} in[k] for i in [0, n]; out[n] = total.
+__global__ __launch_bounds__(T256) void k_scan_write(const uint32_t* __restrict__ in, uint64_t n,
+                                                     const uint64_t* __restrict__ bsum,
+                                                     uint64_t* __restrict__ out) {
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK + (uint64_t)threadIdx.x * SCAN_PER;
+    uint32_t v[SCAN_PER];
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+        const uint64_t i = base + j;
+        v[j] = i < n ? in[i] : 0u;
+        s += v[j];
+    }
+    __shared__ uint64_t tot[T256];
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < T256; off <<= 1) {
+        const uint64_t t = threadIdx.x >= (unsigned)off ? tot[threadIdx.x - off] : 0;
+        __syncthreads();
+        tot[threadIdx.x] += t;
+        __syncthreads();
+    }
+    uint64_t run = bsum[blockIdx.x] + tot[threadIdx.x] - s;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+        const uint64_t i = base + j;
+        if (i <= n) out[i] = run;   // i == n: the total
+        run += v[j];
+    }
+}
+
+hipError_t exclusive_scan(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* bsum,
+                          hipStream_t s) {
+    // one extra item so the block holding index n writes the total
+    const int nb = (int)((n + 1 + SCAN_BLOCK - 1) / SCAN_BLOCK);
+    k_sum_blocks<<<nb, T256, 0, s>>>(in, n, bsum);
+    k_scan_blocks<<<1, 1024, 0, s>>>(bsum, nb);
+    k_scan_write<<<nb, T256, 0, s>>>(in, n, bsum, out);
+    return hipGetLastError();
+}
+
+// ---- response matrix ----
+
+struct SysArgs {
+    const mc_event* events;
+    const unsigned long long* n_events;
+    uint64_t capacity;
+    uint32_t nv_nu;          // bins per view and class
+    uint32_t nx, ny, f, mx, my;
+    uint64_t q_per_view, r_extra;
+};
+
+__device__ inline uint64_t n_events_of(const SysArgs& a) {
+    const uint64_t n = *a.n_events;
+    return n < a.capacity ? n : a.capacity;
+}
+
+// projection bin (classes merged) and image voxel of event e
+__device__ inline void event_rc(const SysArgs& a, const mc_event& ev, uint32_t& bin, uint32_t& img) {
+    const uint32_t per_view = 2u * a.nv_nu;
+    const uint32_t view = ev.bin / per_view;
+    bin = view * a.nv_nu + (ev.bin % a.nv_nu);
+    const uint32_t v = ev.emit_voxel;
+    const uint32_t ix = v % a.nx, iy = (v / a.nx) % a.ny, iz = v / (a.nx * a.ny);
+    img = (ix / a.f) + a.mx * ((iy / a.f) + a.my * (iz / a.f));
+}
+
+__global__ __launch_bounds__(T256) void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ __launch_bounds__(T256) void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// activity per image voxel, and the total
+__global__ __launch_bounds__(T256) void k_image_activity(const uint32_t* __restrict__ act,
+                                                         uint32_t nx, uint32_t ny, uint32_t nz,
+                                                         uint32_t f, uint32_t mx, uint32_t my,
+                                                         unsigned long long* __restrict__ a_img,
+                                                         unsigned long long* __restrict__ total) {
+    const uint64_t n = (uint64_t)nx * ny * nz;
+    uint64_t sum = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t a = act[i];
+        if (!a) continue;
+        sum += a;
+        const uint32_t ix = (uint32_t)(i % nx), iy = (uint32_t)((i / nx) % ny), iz = (uint32_t)(i / ((uint64_t)nx * ny));
+        atomicAdd(a_img + (ix / f) + mx * ((iy / f) + my * (iz / f)), (unsigned long long)a);
+    }
+    sum = wave_sum64(sum);
+    if ((threadIdx.x & 63) == 0 && sum) atomicAdd(total, (unsigned long long)sum);
+}
+
+// count events per row (transpose = 0: rows are bins, 1: rows are image voxels)
+__global__ __launch_bounds__(T256) void k_count_rows(SysArgs a, int transpose, uint32_t* cnt) {
+    const uint64_t n = n_events_of(a);
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t bin, img;
+        event_rc(a, a.events[e], bin, img);
+        atomicAdd(cnt + (transpose ? img : bin), 1u);
+    }
+}
+
+__global__ __launch_bounds__(T256) void k_scatter(SysArgs a, int transpose, const uint64_t* start,
+                                                  uint32_t* fill, uint32_t* tmp_col) {
+    const uint64_t n = n_events_of(a);
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t bin, img;
+        event_rc(a, a.events[e], bin, img);
+        const uint32_t r = transpose ? img : bin, c = transpose ? bin : img;
+        const uint32_t k = atomicAdd(fill + r, 1u);
+        tmp_col[start[r] + k] = c;
+    }
+}
+
+// sort each row's columns (insertion sort: rows hold a handful of events)
+// and count the distinct ones
+__global__ __launch_bounds__(T256) void k_sort_rows(uint64_t n_rows, const uint64_t* start,
+                                                    uint32_t* tmp_col, uint32_t* row_nnz) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = start[r], e = start[r + 1];
+        for (uint64_t i = b + 1; i < e; ++i) {
+            const uint32_t v = tmp_col[i];
+            uint64_t j = i;
+            while (j > b && tmp_col[j - 1] > v) { tmp_col[j] = tmp_col[j - 1]; --j; }
+            tmp_col[j] = v;
+        }
+        uint32_t d = 0;
+        for (uint64_t i = b; i < e; ++i) d += (i == b || tmp_col[i] != tmp_col[i - 1]);
+        row_nnz[r] = d;
+    }
+}
+
+// distinct columns with their counts -> CSR column and value arrays
+__global__ __launch_bounds__(T256) void k_emit_rows(SysArgs a, int transpose, uint64_t n_rows,
+                                                    const uint64_t* start, const uint32_t* tmp_col,
+                                                    const uint64_t* rowptr_u, int64_t* rowptr,
+                                                    int32_t* col, float* val,
+                                                    const unsigned long long* a_img,
+                                                    const unsigned long long* total_p, float* proj) {
+    const double total = (double)*total_p;
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n_rows;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        rowptr[r] = (int64_t)rowptr_u[r];
+        if (r == n_rows) continue;
+        const uint64_t b = start[r], e = start[r + 1];
+        uint64_t o = rowptr_u[r];
+        if (!transpose && proj) proj[r] = (float)(e - b);
+        uint64_t i = b;
+        while (i < e) {
+            const uint32_t c = tmp_col[i];
+            uint64_t j = i;
+            while (j < e && tmp_col[j] == c) ++j;
+            const uint32_t bin = transpose ? c : (uint32_t)r;
+            const uint32_t img = transpose ? (uint32_t)r : c;
+            const uint64_t view = bin / a.nv_nu;
+            const double n_view = (double)(a.q_per_view + (view < a.r_extra ? 1u : 0u));
+            const double n_i = n_view * (double)a_img[img] / total;
+            col[o] = (int32_t)c;
+            val[o] = (float)((double)(j - i) / n_i);
+            ++o;
+            i = j;
+        }
+    }
+}
+
+// ---- MLEM ----
+
+__global__ __launch_bounds__(T256) void k_row_sums(int64_t n_rows, const int64_t* __restrict__ rp,
+                                                   const float* __restrict__ v, double* __restrict__ out) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t k = rp[r]; k < rp[r + 1]; ++k) s += (double)v[k];
+        out[r] = s;
+    }
+}
+
+__global__ __launch_bounds__(T256) void k_mlem_init(int64_t n_vox, const float* __restrict__ img,
+                                                    const double* __restrict__ sens,
+                                                    double* __restrict__ S) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * blockDim.x)
+        S[i] = sens[i] > 0.0 ? (double)img[i] : 0.0;
+}
+
+// y_j = sum_i T_ij S_i; ratio_j = P_j / y_j (0 when y_j = 0)
+__global__ __launch_bounds__(T256) void k_mlem_forward(int64_t n_bins, const int64_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col,
+                                                       const float* __restrict__ val,
+                                                       const double* __restrict__ S,
+                                                       const float* __restrict__ P,
+                                                       double* __restrict__ ratio) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_bins;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = rp[j], e = rp[j + 1];
+        double y = 0.0;
+        for (int64_t k = b; k < e; ++k) y += (double)val[k] * S[col[k]];
+        ratio[j] = y > 0.0 ? (double)P[j] / y : 0.0;
+    }
+}
+
+// S_i <- S_i * (sum_j T_ij ratio_j) / sens_i
+__global__ __launch_bounds__(T256) void k_mlem_update(int64_t n_vox, const int64_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col,
+                                                      const float* __restrict__ val,
+                                                      const double* __restrict__ ratio,
+                                                      const double* __restrict__ sens,
+                                                      double* __restrict__ S) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double si = sens[i];
+        if (!(si > 0.0)) { S[i] = 0.0; continue; }
+        double bsum = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) bsum += (double)val[k] * ratio[col[k]];
+        S[i] = S[i] * bsum / si;
+    }
+}
+
+__global__ __launch_bounds__(T256) void k_mlem_out(int64_t n_vox, const double* __restrict__ S,
+                                                   float* __restrict__ img) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * blockDim.x)
+        img[i] = (float)S[i];
+}
+
+}  // namespace
+
+// Workspace of the response-matrix build, in bytes (layout below).
+size_t sysmat_workspace_bytes(uint64_t n_bins, uint64_t n_img, uint64_t capacity) {
+    const uint64_t nr = n_bins > n_img ? n_bins : n_img;
+    auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+    const uint64_t nb = (nr + 1 + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    return al(4 * nr) /* cnt */ + al(4 * nr) /* fill */ + al(8 * (nr + 1)) /* start */
+         + al(8 * (nr + 1)) /* rowptr_u */ + al(4 * nr) /* row_nnz */ + al(8 * nb) /* bsum */
+         + al(4 * (capacity ? capacity : 1)) /* tmp_col */ + al(8 * (n_img + 1)) /* a_img, total */;
+}
+
+hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_events, uint64_t capacity,
+                         uint32_t nx, uint32_t ny, uint32_t nz, uint32_t f, uint32_t n_views,
+                         uint32_t nu, uint32_t nv, uint64_t n_hist, const uint32_t* activity,
+                         int64_t* T_rp, int32_t* T_col, float* T_val,
+                         int64_t* Tt_rp, int32_t* Tt_col, float* Tt_val, float* proj,
+                         void* workspace, hipStream_t s) {
+    const uint64_t n_bins = (uint64_t)n_views * nu * nv;
+    const uint32_t mx = nx / f, my = ny / f, mz = nz / f;
+    const uint64_t n_img = (uint64_t)mx * my * mz;
+    const uint64_t nr = n_bins > n_img ? n_bins : n_img;
+    auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+    char* w = (char*)workspace;
+    uint32_t* cnt = (uint32_t*)w;          w += al(4 * nr);
+    uint32_t* fill = (uint32_t*)w;         w += al(4 * nr);
+    uint64_t* start = (uint64_t*)w;        w += al(8 * (nr + 1));
+    uint64_t* rowptr_u = (uint64_t*)w;     w += al(8 * (nr + 1));
+    uint32_t* row_nnz = (uint32_t*)w;      w += al(4 * nr);
+    const uint64_t nb = (nr + 1 + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    uint64_t* bsum = (uint64_t*)w;         w += al(8 * nb);
+    uint32_t* tmp_col = (uint32_t*)w;      w += al(4 * (capacity ? capacity : 1));
+    unsigned long long* a_img = (unsigned long long*)w;   // n_img entries, then the total
+    unsigned long long* total = a_img + n_img;
+
+    SysArgs a;
+    a.events = events; a.n_events = n_events; a.capacity = capacity;
+    a.nv_nu = nu * nv;
+    a.nx = nx; a.ny = ny; a.f = f; a.mx = mx; a.my = my;
+    a.q_per_view = n_hist / n_views; a.r_extra = n_hist % n_views;
+
+    k_fill_u64<<<grid_for(n_img + 1, T256, 4096), T256, 0, s>>>((uint64_t*)a_img, n_img + 1, 0);
+    k_image_activity<<<grid_for((uint64_t)nx * ny * nz, T256, 8192), T256, 0, s>>>(
+        activity, nx, ny, nz, f, mx, my, a_img, total);
+    const int ge = grid_for(capacity ? capacity : 1, T256, 8192);
+    for (int transpose = 0; transpose < 2; ++transpose) {
+        const uint64_t n_rows = transpose ? n_img : n_bins;
+        k_fill_u32<<<grid_for(n_rows, T256, 4096), T256, 0, s>>>(cnt, n_rows, 0);
+        k_fill_u32<<<grid_for(n_rows, T256, 4096), T256, 0, s>>>(fill, n_rows, 0);
+        k_count_rows<<<ge, T256, 0, s>>>(a, transpose, cnt);
+        hipError_t e = exclusive_scan(cnt, n_rows, start, bsum, s);
+        if (e != hipSuccess) return e;
+        k_scatter<<<ge, T256, 0, s>>>(a, transpose, start, fill, tmp_col);
+        k_sort_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(n_rows, start, tmp_col, row_nnz);
+        e = exclusive_scan(row_nnz, n_rows, rowptr_u, bsum, s);
+        if (e != hipSuccess) return e;
+        k_emit_rows<<<grid_for(n_rows + 1, T256, 8192), T256, 0, s>>>(
+            a, transpose, n_rows, start, tmp_col, rowptr_u, transpose ? Tt_rp : T_rp,
+            transpose ? Tt_col : T_col, transpose ? Tt_val : T_val, a_img, total,
+            transpose ? nullptr : proj);
+    }
+    return hipGetLastError();
+}
+
+size_t mlem_workspace(uint64_t n_bins, uint64_t n_vox) {
+    auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+    return al(8 * n_vox) /* sens */ + al(8 * n_vox) /* S */ + al(8 * n_bins) /* ratio */;
+}
+
+hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, const int64_t* T_rp, const int32_t* T_col,
+                       const float* T_val, const int64_t* Tt_rp, const int32_t* Tt_col,
+                       const float* Tt_val, const float* proj, float* image, int32_t n_iter,
+                       void* workspace, hipStream_t s) {
+    auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+    char* w = (char*)workspace;
+    double* sens = (double*)w;  w += al(8 * n_vox);
+    double* S = (double*)w;     w += al(8 * n_vox);
+    double* ratio = (double*)w;
+    const int gv = grid_for((uint64_t)n_vox, T256, 8192), gb = grid_for((uint64_t)n_bins, T256, 16384);
+    k_row_sums<<<gv, T256, 0, s>>>(n_vox, Tt_rp, Tt_val, sens);
+    k_mlem_init<<<gv, T256, 0, s>>>(n_vox, image, sens, S);
+    for (int it = 0; it < n_iter; ++it) {
+        k_mlem_forward<<<gb, T256, 0, s>>>(n_bins, T_rp, T_col, T_val, S, proj, ratio);
+        k_mlem_update<<<gv, T256, 0, s>>>(n_vox, Tt_rp, Tt_col, Tt_val, ratio, sens, S);
+    }
+    k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, image);
+    return hipGetLastError();
+}
+
+}  // namespace mcs

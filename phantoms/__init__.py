@@ -239,3 +239,20 @@ def pick(rng_seed: int, candidates: np.ndarray, k: int) -> np.ndarray:
     """Seeded choice of k distinct entries from candidates (PCG64)."""
     rng = np.random.Generator(np.random.PCG64(rng_seed))
     return np.sort(rng.choice(candidates, size=k, replace=False))
+
+
+def random_system(n_bins: int, n_vox: int, density: float, seed: int):
+    """Seeded sparse non-negative matrix (bins x voxels, float32 values) and a
+    positive image, as scipy CSR and numpy arrays: a stand-in response matrix
+    for reconstruction tests."""
+    import scipy.sparse as sp
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nnz = max(1, int(n_bins * n_vox * density))
+    rows = rng.integers(0, n_bins, size=nnz)
+    cols = rng.integers(0, n_vox, size=nnz)
+    vals = rng.uniform(0.05, 1.0, size=nnz).astype(np.float32)
+    T = sp.coo_matrix((vals, (rows, cols)), shape=(n_bins, n_vox)).tocsr()
+    T.sum_duplicates()
+    T.data = T.data.astype(np.float32)
+    image = rng.uniform(0.5, 4.0, size=n_vox)
+    return T, image

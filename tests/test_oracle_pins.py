@@ -489,3 +489,25 @@ def test_mlem_small_toy_vs_constrained_maximiser():
     res = optimize.minimize(negll, x0=np.ones(2), bounds=[(1e-9, None)] * 2, method="L-BFGS-B",
                             options={"ftol": 1e-15, "gtol": 1e-12})
     np.testing.assert_allclose(S, res.x, rtol=1e-5)
+
+
+def test_system_matrix_normalisation_and_fixed_point():
+    """T n = P bin by bin with n_i the expected emissions per view (the
+    self-consistent reading), and hence n is an MLEM fixed point."""
+    V = 4
+    p = phantoms.thorax_problem("sm", 16, 2.4, 2, V, 180.0, 16, 2.4, 400_000, image_factor=2).with_(
+        accept_half_angle_rad=np.radians(15.0))
+    r = oracle.simulate(p, want_triplets=True)
+    T, P, frac = oracle.system_matrix(p, r["trip_i"], r["trip_j"])
+    assert P.sum() == r["fates"][5]
+    n = (p.n_histories / V) * frac            # N divisible by V: same count for every view
+    np.testing.assert_allclose(T @ n, P, rtol=1e-12, atol=1e-12)
+    S = oracle.mlem(T, P, 5, S0=n)
+    seen = np.asarray(T.sum(axis=0)).ravel() > 0
+    np.testing.assert_allclose(S[seen], n[seen], rtol=1e-10)
+    # a row is a bin: its entries are counts over expected emissions
+    i, j = r["trip_i"][0], r["trip_j"][0]
+    row = (j // (2 * p.nv * p.nu)) * p.nv * p.nu + j % (p.nv * p.nu)
+    c = np.sum((r["trip_i"] == i) & ((r["trip_j"] // (2 * p.nv * p.nu)) * p.nv * p.nu
+                                     + r["trip_j"] % (p.nv * p.nu) == row))
+    assert T[row, i] == pytest.approx(c / n[i], rel=1e-12)

@@ -133,7 +133,10 @@ struct Lane {
 };
 
 // Per-lane work counters and energies of one problem (reduced across the
-// wave on flush).  Fate counts are kept wave-wide by the kernels.
+// wave on flush).  Fate counts are kept wave-wide by the kernels.  Energy is
+// booked once per history: whatever leaves the grid (escape) or is left when
+// the step cap stops it is the history's outgoing energy, the rest of the
+// 140 keV was deposited (the Compton deposits telescope).
 struct Acc {
     uint32_t n_tent, n_real, n_kahn;
     long long e_dep, e_esc, e_cap;
@@ -144,8 +147,18 @@ __device__ inline void acc_zero(Acc& A) {
     A.e_dep = A.e_esc = A.e_cap = 0;
 }
 
+// keV -> Q40.23 fixed point, rounded to nearest even; |kev| < 256 fits int32.
 __device__ __forceinline__ long long to_q23(float kev) {
-    return __float2ll_rn(kev * 8388608.0f);
+    return (long long)__float2int_rn(kev * 8388608.0f);
+}
+
+// Book the energy of a finished history with fate f and final energy e.
+__device__ __forceinline__ void book_energy(Acc& A, int f, float e) {
+    const bool gone = (f == MC_ABSORBED) | (f == MC_CUT);
+    const float out = gone ? 0.0f : e;
+    A.e_dep += to_q23(140.0f - out);
+    if (f == MC_CAPPED_FATE) A.e_cap += to_q23(out);
+    else A.e_esc += to_q23(out);
 }
 
 // Outcome of one iteration.
@@ -241,7 +254,6 @@ __device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, u
         L.n += 1;
         if (L.n > C.max_steps) {
             L.n -= 1;
-            A.e_cap += to_q23(L.e);
             return MC_CAPPED_FATE;
         }
         A.n_tent++;
@@ -252,10 +264,7 @@ __device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, u
         const float tx = xn + C.hx, ty = yn + C.hy, tz = zn + C.hz;
         const bool inside = (tx >= 0.0f) & (tx < C.lx) & (ty >= 0.0f) & (ty < C.ly) &
                             (tz >= 0.0f) & (tz < C.lz);
-        if (!inside) {
-            A.e_esc += to_q23(L.e);
-            return escape(C, L, iu, iv);
-        }
+        if (!inside) return escape(C, L, iu, iv);
         const int ix = min((int)(tx * C.inv_vox), C.nx - 1);
         const int iy = min((int)(ty * C.inv_vox), C.ny - 1);
         const int iz = min((int)(tz * C.inv_vox), C.nz - 1);
@@ -264,10 +273,7 @@ __device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, u
         L.x = xn; L.y = yn; L.z = zn;
         if ((w1 >> 8) < q) {
             A.n_real++;
-            if (unif(w2) < L.p_pe) {
-                A.e_dep += to_q23(L.e);
-                return MC_ABSORBED;
-            }
+            if (unif(w2) < L.p_pe) return MC_ABSORBED;
             L.phi_word = w3;
             L.a = 0;
             L.state = S_KAHN;
@@ -296,22 +302,14 @@ __device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, u
         }
         if (!acc) {
             L.a += 1;
-            if (L.a >= KAHN_MAX) {
-                A.e_cap += to_q23(L.e);
-                return MC_CAPPED_FATE;
-            }
+            if (L.a >= KAHN_MAX) return MC_CAPPED_FATE;
             return R_RUNNING;
         }
         const float ct = 1.0f - (xx - 1.0f) * ik;
-        const float en = L.e * ixx;
-        A.e_dep += to_q23(L.e - en);
-        L.e = en;
+        L.e = L.e * ixx;
         L.n_scatter += 1;
         rotate(L, ct, unif(L.phi_word));
-        if (L.e < C.e_cut) {
-            A.e_dep += to_q23(L.e);
-            return MC_CUT;
-        }
+        if (L.e < C.e_cut) return MC_CUT;
         energy_terms(C, L.e, L.inv_mm, L.p_pe);
         L.state = S_STEP;
         return R_RUNNING;

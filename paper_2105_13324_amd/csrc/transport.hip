@@ -156,6 +156,7 @@ __global__ __launch_bounds__(256) void k_transport(TransportArgs T) {
             counter_of(L, c2, c3);
             philox10(c0, c1, c2, c3, C.seed, C.pid);
             fate = advance(C, L, c0, c1, c2, c3, A, iu, iv);
+            if (fate != R_RUNNING) book_energy(A, fate, L.e);
         }
         if (__ballot(fate != R_RUNNING) != 0) {
             // fate counts through ballots: wave-uniform, no per-lane counters

@@ -34,6 +34,31 @@ OPS_SCATTER = 95          # kinematics, rotation, attenuation terms (FP64 counte
 OPS_END = 35              # collimator, detector bin, window, bookkeeping
 
 
+# HBM traffic of one transport launch on the headline workload, from rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by what the same
+# counters read for a plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); keyed
+# by a hash of the kernel sources so a changed kernel reports null.
+COPY_SCALE = {"fetch": 2.0, "write": 1.0}
+TRAFFIC_KIB = {"11b16d1e03db43a5": {"fetch": 23846432.0625, "write": 5518.5625}}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    m = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2105_13324_amd", "csrc")
+    for f in ("history.h", "transport.hip", "mc_internal.h"):
+        with open(os.path.join(d, f), "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
+def traffic_bytes():
+    t = TRAFFIC_KIB.get(kernel_source_hash())
+    if t is None:
+        return None
+    return 1024.0 * (t["fetch"] * COPY_SCALE["fetch"] + t["write"] * COPY_SCALE["write"])
+
+
 def ops_per_history(n_tent, n_kahn, n_scatter, n_hist):
     per = (2 * (OPS_PHILOX) + OPS_EMISSION + OPS_END) * n_hist \
         + n_tent * (OPS_PHILOX + OPS_STEP) + n_kahn * (OPS_PHILOX + OPS_KAHN) \
@@ -131,7 +156,8 @@ def main():
     achieved = ops_h * n_hist / (k_ms / 1e3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "Tops/s (32-bit lane ops)", "frac": achieved / PEAK_LANE_OPS,
-                "traffic": None, "kernel": "k_transport", "kernel_ms": k_ms,
+                "traffic": traffic_bytes(), "traffic_unit": "bytes per launch",
+                "kernel": "k_transport", "kernel_ms": k_ms,
                 "ops_per_history": ops_h}
     rec = {
         "metric": "photon histories/s (128^3 thorax, 60 views) + adjoint μ-grad histories/s",

@@ -74,13 +74,11 @@ __device__ inline double g_of(const Cst& C, float e) {
 __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now, double G,
                            long long* grad, double scale, int64_t* status, uint32_t& bin_out) {
     Lane L;
-    L.hist = hist; L.view = view;
-    L.state = S_EMIT0; L.n = 0; L.a = 0; L.n_scatter = 0; L.emit_voxel = 0; L.e = 0.0f;
-    const float2 cs = C.views[view];
-    L.vc = cs.x; L.vs = cs.y;
+    const Emission em = emit_history(C, (uint32_t)hist, (uint32_t)view);
+    begin_history(C, L, (uint32_t)view, (uint32_t)hist, em);
     Acc A;
     acc_zero(A);
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;   // start of the current segment
+    float sx = L.x, sy = L.y, sz = L.z;   // start of the current segment
     for (;;) {
         uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
         counter_of(L, c2, c3);
@@ -89,7 +87,6 @@ __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now,
         const float e_flight = L.e;
         int iu = -1, iv = -1;
         const int fate = advance(C, L, c0, c1, c2, c3, A, iu, iv);
-        if (before == S_EMIT1) { sx = L.x; sy = L.y; sz = L.z; }
         if (fate == R_RUNNING) {
             if (walk_now && before == S_STEP && L.state == S_KAHN) {
                 // Compton vertex at L.x: close the segment, add the collision term

@@ -5,7 +5,8 @@
 // while the others wait, so each tail is kept short: no integer division, no
 // double precision, hardware transcendentals (v_log, v_sin/v_cos in
 // revolutions, v_rcp, v_sqrt), and the Klein-Nishina part of the attenuation
-// from a small table.
+// from a small table.  Emission is a separate, converged function: the
+// kernels emit histories in batches outside the per-lane state machine.
 #pragma once
 
 #include "mc_internal.h"
@@ -17,7 +18,7 @@ constexpr uint32_t KAHN_MAX = 64;
 constexpr float MEC2_F = 510.99895f;
 constexpr float INV_MEC2 = (float)(1.0 / 510.99895);
 
-enum : int { S_IDLE = 0, S_EMIT0 = 1, S_EMIT1 = 2, S_STEP = 3, S_KAHN = 4 };
+enum : int { S_IDLE = 0, S_STEP = 3, S_KAHN = 4 };
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
@@ -201,11 +202,12 @@ __device__ inline void rotate(Lane& L, float ct, float phi_u) {
     }
 }
 
+// Philox counter words 2 and 3 of a lane's next draw: tentative collision n+1
+// (sub-draw 0) or Kahn attempt a of collision n (sub-draw 1+a).
 __device__ __forceinline__ void counter_of(const Lane& L, uint32_t& c2, uint32_t& c3) {
-    c2 = 0; c3 = 0;
-    if (L.state == S_EMIT1) c3 = 1;
-    else if (L.state == S_STEP) c2 = L.n + 1;
-    else if (L.state == S_KAHN) { c2 = L.n; c3 = 1 + L.a; }
+    const bool kahn = L.state == S_KAHN;
+    c2 = kahn ? L.n : L.n + 1;
+    c3 = kahn ? 1 + L.a : 0;
 }
 
 // Histories in view v: N_v = floor(N/V) + [v < N mod V].
@@ -237,17 +239,68 @@ __device__ inline void advance_cursor(const Cst& C, uint64_t& view, uint64_t& hi
     }
 }
 
-__device__ inline void begin_history(const Cst& C, Lane& L, uint64_t view, uint64_t hist) {
+// Emission of history (view, hist): Philox event 0, sub-draws 0 and 1.
+// Sub-draw 0: words 0-1 pick the voxel by inverse CDF, words 2-3 the x and y
+// offsets in it; sub-draw 1: word 0 the z offset, word 1 cos(theta), word 2
+// the azimuth.  Runs with the wavefront converged (no per-lane branches
+// except the short guide-range search).
+struct Emission {
+    float x, y, z, dx, dy, dz;
+    uint32_t voxel;
+};
+
+__device__ inline Emission emit_history(const Cst& C, uint32_t hist, uint32_t view) {
+    uint32_t a0 = hist, a1 = view, a2 = 0, a3 = 0;
+    philox10(a0, a1, a2, a3, C.seed, C.pid);
+    uint32_t b0 = hist, b1 = view, b2 = 0, b3 = 1;
+    philox10(b0, b1, b2, b3, C.seed, C.pid);
+    // voxel: t = floor(R * total / 2^64) with R the 64-bit word pair
+    const uint64_t R = ((uint64_t)a0 << 32) | a1;
+    const uint64_t t = __umul64hi(R, C.total);
+    const uint64_t b = t >> C.shift;
+    uint32_t lo = C.guide[b], hi = C.guide[b + 1];
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (C.cdf[mid] > t) hi = mid; else lo = mid + 1;
+    }
+    const uint32_t packed = C.vox_id[lo];   // ix | iy << 10 | iz << 20
+    const uint32_t ix = packed & 1023u, iy = (packed >> 10) & 1023u, iz = packed >> 20;
+    Emission e;
+    e.voxel = ix + (uint32_t)C.nx * (iy + (uint32_t)C.ny * iz);
+    if (C.source_mode == MC_SOURCE_POINT) {
+        e.x = 0.0f; e.y = 0.0f; e.z = 0.0f;
+    } else {
+        e.x = -C.hx + ((float)ix + unif(a2)) * C.vox;
+        e.y = -C.hy + ((float)iy + unif(a3)) * C.vox;
+        e.z = -C.hz + ((float)iz + unif(b0)) * C.vox;
+    }
+    const float ct = fmaf(2.0f, unif(b1), -1.0f);
+    const float st = sqrtf_hw((1.0f - ct) * (1.0f + ct));
+    const float u = unif(b2);
+    e.dx = st * cos_rev(u); e.dy = st * sin_rev(u); e.dz = ct;
+    return e;
+}
+
+// Lane state at the start of transport (after emission).
+__device__ inline void begin_history(const Cst& C, Lane& L, uint32_t view, uint32_t hist,
+                                     const Emission& e) {
     L.hist = hist;
     L.view = (int)view;
-    L.state = S_EMIT0;
+    L.state = S_STEP;
     L.n = 0; L.a = 0; L.n_scatter = 0;
+    L.emit_voxel = e.voxel;
+    L.x = e.x; L.y = e.y; L.z = e.z;
+    L.dx = e.dx; L.dy = e.dy; L.dz = e.dz;
+    L.e = 140.0f;
+    L.inv_mm = C.inv_mm140;
+    L.p_pe = C.p_pe140;
     const float2 cs = C.views[view];
     L.vc = cs.x; L.vs = cs.y;
 }
 
-// One iteration of a lane's history given its Philox words.  Returns the fate
-// when the history ends (iu/iv set for escapes), else R_RUNNING.
+// One iteration of a lane's history (tentative collision or Kahn attempt)
+// given its Philox words.  Returns the fate when the history ends (iu/iv set
+// for escapes), else R_RUNNING.
 __device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, uint32_t w2,
                               uint32_t w3, Acc& A, int& iu, int& iv) {
     if (L.state == S_STEP) {
@@ -314,40 +367,6 @@ __device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, u
         L.state = S_STEP;
         return R_RUNNING;
     }
-    if (L.state == S_EMIT0) {
-        // voxel by inverse CDF: t = floor(R * total / 2^64) with R the 64-bit word pair
-        const uint64_t R = ((uint64_t)w0 << 32) | w1;
-        const uint64_t t = __umul64hi(R, C.total);
-        const uint64_t b = t >> C.shift;
-        uint32_t lo = C.guide[b], hi = C.guide[b + 1];
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (C.cdf[mid] > t) hi = mid; else lo = mid + 1;
-        }
-        const uint32_t packed = C.vox_id[lo];   // ix | iy << 10 | iz << 20
-        const uint32_t ix = packed & 1023u, iy = (packed >> 10) & 1023u, iz = packed >> 20;
-        L.emit_voxel = ix + (uint32_t)C.nx * (iy + (uint32_t)C.ny * iz);
-        if (C.source_mode == MC_SOURCE_POINT) {
-            L.x = 0.0f; L.y = 0.0f; L.z = 0.0f;
-        } else {
-            L.x = -C.hx + ((float)ix + unif(w2)) * C.vox;
-            L.y = -C.hy + ((float)iy + unif(w3)) * C.vox;
-            L.z = (float)iz;   // completed with the next word block
-        }
-        L.state = S_EMIT1;
-        return R_RUNNING;
-    }
-    // S_EMIT1: z position, direction, energy
-    if (C.source_mode != MC_SOURCE_POINT) L.z = -C.hz + (L.z + unif(w0)) * C.vox;
-    const float ct = fmaf(2.0f, unif(w1), -1.0f);
-    const float st = sqrtf_hw((1.0f - ct) * (1.0f + ct));
-    const float u = unif(w2);
-    L.dx = st * cos_rev(u); L.dy = st * sin_rev(u); L.dz = ct;
-    L.e = 140.0f;
-    L.inv_mm = C.inv_mm140;
-    L.p_pe = C.p_pe140;
-    L.n = 0;
-    L.state = S_STEP;
     return R_RUNNING;
 }
 

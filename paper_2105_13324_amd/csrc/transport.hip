@@ -82,14 +82,30 @@ __device__ __forceinline__ uint64_t work_of(const Cst& C, uint64_t view, uint64_
     return view * C.q_per_view + min(view, C.r_extra) + hist;
 }
 
+// Emission records a wavefront stages in LDS: two per lane.
+constexpr int EMIT_PER_LANE = 2;
+constexpr int EMIT_BATCH = 64 * EMIT_PER_LANE;
+constexpr int WAVES_PER_BLOCK_MAX = 4;    // 256 threads
+
+struct EmitRec {
+    float x, y, z, dx, dy, dz;
+    uint32_t voxel, view, hist;
+};
+
 // Persistent transport: waves claim chunks of work until none are left.
+// A wavefront emits the next EMIT_BATCH histories of its chunk in one
+// converged phase into LDS; idle lanes then start histories from there, so
+// the per-lane loop only alternates tentative collisions and Kahn attempts.
 __global__ __launch_bounds__(256) void k_transport(TransportArgs T) {
+    __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
     const int lane = threadIdx.x & 63;
+    EmitRec* __restrict__ my = stage[threadIdx.x >> 6];
     const uint64_t lane_lt = (1ull << lane) - 1ull;
     const uint64_t full = __ballot(1);   // lanes of this wavefront
     // chunk bookkeeping (wave-uniform): problem-local work range [c_next, c_end)
-    // and the (view, history id) of c_next
+    // and the (view, history id) of c_next; staged records [s_next, s_end)
     uint64_t c_next = 0, c_end = 0, cur_view = 0, cur_hist = 0;
+    uint32_t s_next = 0, s_end = 0;
     int p = -1;
     bool exhausted = false, have_pending = false;
     uint64_t pending = 0;
@@ -106,45 +122,71 @@ __global__ __launch_bounds__(256) void k_transport(TransportArgs T) {
     for (;;) {
         uint64_t need = __ballot(L.state == S_IDLE);
         while (need != 0 && !exhausted) {
-            if (c_next >= c_end) {
-                if (!have_pending) {
-                    unsigned long long base = 0;
-                    if (lane == 0) base = atomicAdd(&T.state->next_chunk, 1ull);
-                    pending = uniform64(base);
-                    have_pending = true;
-                    if (pending >= n_chunks) { exhausted = true; break; }
+            if (s_next >= s_end) {
+                // stage empty: emit the next batch of the chunk (claim one if needed)
+                if (c_next >= c_end) {
+                    if (!have_pending) {
+                        unsigned long long base = 0;
+                        if (lane == 0) base = atomicAdd(&T.state->next_chunk, 1ull);
+                        pending = uniform64(base);
+                        have_pending = true;
+                        if (pending >= n_chunks) { exhausted = true; break; }
+                    }
+                    // problem of the pending chunk (uniform binary search)
+                    int lo = 0, hi = T.n_problems - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (chunk_prefix[mid] <= pending) lo = mid; else hi = mid - 1;
+                    }
+                    const int np = __builtin_amdgcn_readfirstlane(lo);
+                    if (np != p) {
+                        if (need != full) break;       // drain problem p first
+                        if (p >= 0) flush(A, fc, p, T, lane);
+                        p = np;
+                        C = load_cst(T.descs + p);
+                    }
+                    const uint64_t local_chunk = pending - chunk_prefix[p];
+                    const uint64_t cnt = T.work_prefix[p + 1] - T.work_prefix[p];
+                    c_next = local_chunk * T.chunk;
+                    c_end = min(c_next + T.chunk, cnt);
+                    have_pending = false;
+                    if (C.flags != 0) { c_next = c_end; continue; }   // staging found bad input
+                    split_work(C, C.work_begin + c_next, cur_view, cur_hist);
                 }
-                // problem of the pending chunk (uniform binary search)
-                int lo = 0, hi = T.n_problems - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (chunk_prefix[mid] <= pending) lo = mid; else hi = mid - 1;
+                const uint32_t n_rec = (uint32_t)min((uint64_t)EMIT_BATCH, c_end - c_next);
+#pragma unroll 1
+                for (int k = 0; k < EMIT_PER_LANE; ++k) {
+                    const uint32_t slot = (uint32_t)(k * 64 + lane);
+                    if (slot < n_rec) {
+                        uint64_t v = cur_view, h = cur_hist;
+                        advance_cursor(C, v, h, slot, C.n_views);
+                        const Emission e = emit_history(C, (uint32_t)h, (uint32_t)v);
+                        EmitRec r;
+                        r.x = e.x; r.y = e.y; r.z = e.z; r.dx = e.dx; r.dy = e.dy; r.dz = e.dz;
+                        r.voxel = e.voxel; r.view = (uint32_t)v; r.hist = (uint32_t)h;
+                        my[slot] = r;
+                    }
                 }
-                const int np = __builtin_amdgcn_readfirstlane(lo);
-                if (np != p) {
-                    if (need != full) break;       // drain problem p first
-                    if (p >= 0) flush(A, fc, p, T, lane);
-                    p = np;
-                    C = load_cst(T.descs + p);
-                }
-                const uint64_t local_chunk = pending - chunk_prefix[p];
-                const uint64_t cnt = T.work_prefix[p + 1] - T.work_prefix[p];
-                c_next = local_chunk * T.chunk;
-                c_end = min(c_next + T.chunk, cnt);
-                have_pending = false;
-                if (C.flags != 0) { c_next = c_end; continue; }   // staging found bad input
-                split_work(C, C.work_begin + c_next, cur_view, cur_hist);
+                // the records are read by other lanes of this wavefront
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                s_next = 0;
+                s_end = n_rec;
+                c_next += n_rec;
+                advance_cursor(C, cur_view, cur_hist, n_rec, C.n_views);
             }
-            const uint64_t avail = c_end - c_next;
+            const uint32_t avail = s_end - s_next;
             const uint32_t rank = __popcll(need & lane_lt);
             if (L.state == S_IDLE && rank < avail) {
-                uint64_t v = cur_view, h = cur_hist;
-                advance_cursor(C, v, h, rank, C.n_views);
-                begin_history(C, L, v, h);
+                const EmitRec r = my[s_next + rank];
+                Emission e;
+                e.x = r.x; e.y = r.y; e.z = r.z; e.dx = r.dx; e.dy = r.dy; e.dz = r.dz;
+                e.voxel = r.voxel;
+                begin_history(C, L, r.view, r.hist, e);
             }
-            const uint64_t took = min((uint64_t)__popcll(need), avail);
-            c_next += took;
-            advance_cursor(C, cur_view, cur_hist, took, C.n_views);
+            const uint32_t took = min((uint32_t)__popcll(need), avail);
+            s_next += took;
             need = __ballot(L.state == S_IDLE);
         }
         if (exhausted && __ballot(L.state != S_IDLE) == 0) break;
@@ -197,17 +239,16 @@ __global__ __launch_bounds__(256) void k_replay(const ProbDesc* __restrict__ d,
     Lane L;
     L.hist = hists[i];
     L.view = views[i];
-    L.state = S_EMIT0;
-    L.n = 0; L.a = 0; L.n_scatter = 0; L.emit_voxel = 0;
+    L.n = 0; L.n_scatter = 0; L.emit_voxel = 0;
     L.e = 0.0f;
     const bool view_ok = L.view >= 0 && L.view < d->n_views;
-    const float2 cs = view_ok ? C.views[L.view] : make_float2(1.0f, 0.0f);
-    L.vc = cs.x; L.vs = cs.y;
     Acc A;
     acc_zero(A);
     mc_record r;
     r.fate = -1; r.iu = -1; r.iv = -1;
     if (C.flags == 0 && view_ok) {
+        const Emission e = emit_history(C, (uint32_t)L.hist, (uint32_t)L.view);
+        begin_history(C, L, (uint32_t)L.view, (uint32_t)L.hist, e);
         for (;;) {
             uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
             counter_of(L, c2, c3);

@@ -96,7 +96,7 @@ struct EmitRec {
 // A wavefront emits the next EMIT_BATCH histories of its chunk in one
 // converged phase into LDS; idle lanes then start histories from there, so
 // the per-lane loop only alternates tentative collisions and Kahn attempts.
-__global__ __launch_bounds__(256) void k_transport(TransportArgs T) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TransportArgs T) {
     __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
     const int lane = threadIdx.x & 63;
     EmitRec* __restrict__ my = stage[threadIdx.x >> 6];
@@ -120,8 +120,13 @@ __global__ __launch_bounds__(256) void k_transport(TransportArgs T) {
     const uint64_t n_chunks = chunk_prefix[T.n_problems];
 
     for (;;) {
-        uint64_t need = __ballot(L.state == S_IDLE);
-        while (need != 0 && !exhausted) {
+        // Refill: at most one chunk claim and one emission phase per iteration;
+        // idle lanes not served wait for the next one.  Lanes only pick a
+        // staged slot here and load it below, outside any loop.
+        const uint64_t need = __ballot(L.state == S_IDLE);
+        int slot = -1;
+        if (need != 0 && !exhausted) {
+            bool ready = true;
             if (s_next >= s_end) {
                 // stage empty: emit the next batch of the chunk (claim one if needed)
                 if (c_next >= c_end) {
@@ -130,64 +135,74 @@ __global__ __launch_bounds__(256) void k_transport(TransportArgs T) {
                         if (lane == 0) base = atomicAdd(&T.state->next_chunk, 1ull);
                         pending = uniform64(base);
                         have_pending = true;
-                        if (pending >= n_chunks) { exhausted = true; break; }
+                        if (pending >= n_chunks) exhausted = true;
                     }
-                    // problem of the pending chunk (uniform binary search)
-                    int lo = 0, hi = T.n_problems - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (chunk_prefix[mid] <= pending) lo = mid; else hi = mid - 1;
+                    if (!exhausted) {
+                        // problem of the pending chunk (uniform binary search)
+                        int lo = 0, hi = T.n_problems - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (chunk_prefix[mid] <= pending) lo = mid; else hi = mid - 1;
+                        }
+                        const int np = __builtin_amdgcn_readfirstlane(lo);
+                        if (np != p && need != full) {
+                            ready = false;                 // drain problem p first
+                        } else {
+                            if (np != p) {
+                                if (p >= 0) flush(A, fc, p, T, lane);
+                                p = np;
+                                C = load_cst(T.descs + p);
+                            }
+                            const uint64_t local_chunk = pending - chunk_prefix[p];
+                            const uint64_t cnt = T.work_prefix[p + 1] - T.work_prefix[p];
+                            c_next = local_chunk * T.chunk;
+                            c_end = min(c_next + T.chunk, cnt);
+                            have_pending = false;
+                            if (C.flags != 0) c_next = c_end;   // staging found bad input: skip
+                            else split_work(C, C.work_begin + c_next, cur_view, cur_hist);
+                        }
+                    } else {
+                        ready = false;
                     }
-                    const int np = __builtin_amdgcn_readfirstlane(lo);
-                    if (np != p) {
-                        if (need != full) break;       // drain problem p first
-                        if (p >= 0) flush(A, fc, p, T, lane);
-                        p = np;
-                        C = load_cst(T.descs + p);
-                    }
-                    const uint64_t local_chunk = pending - chunk_prefix[p];
-                    const uint64_t cnt = T.work_prefix[p + 1] - T.work_prefix[p];
-                    c_next = local_chunk * T.chunk;
-                    c_end = min(c_next + T.chunk, cnt);
-                    have_pending = false;
-                    if (C.flags != 0) { c_next = c_end; continue; }   // staging found bad input
-                    split_work(C, C.work_begin + c_next, cur_view, cur_hist);
                 }
-                const uint32_t n_rec = (uint32_t)min((uint64_t)EMIT_BATCH, c_end - c_next);
+                if (ready && c_next < c_end) {
+                    const uint32_t n_rec = (uint32_t)min((uint64_t)EMIT_BATCH, c_end - c_next);
 #pragma unroll 1
-                for (int k = 0; k < EMIT_PER_LANE; ++k) {
-                    const uint32_t slot = (uint32_t)(k * 64 + lane);
-                    if (slot < n_rec) {
-                        uint64_t v = cur_view, h = cur_hist;
-                        advance_cursor(C, v, h, slot, C.n_views);
-                        const Emission e = emit_history(C, (uint32_t)h, (uint32_t)v);
-                        EmitRec r;
-                        r.x = e.x; r.y = e.y; r.z = e.z; r.dx = e.dx; r.dy = e.dy; r.dz = e.dz;
-                        r.voxel = e.voxel; r.view = (uint32_t)v; r.hist = (uint32_t)h;
-                        my[slot] = r;
+                    for (int k = 0; k < EMIT_PER_LANE; ++k) {
+                        const uint32_t idx = (uint32_t)(k * 64 + lane);
+                        if (idx < n_rec) {
+                            uint64_t v = cur_view, h = cur_hist;
+                            advance_cursor(C, v, h, idx, C.n_views);
+                            const Emission e = emit_history(C, (uint32_t)h, (uint32_t)v);
+                            EmitRec r;
+                            r.x = e.x; r.y = e.y; r.z = e.z; r.dx = e.dx; r.dy = e.dy; r.dz = e.dz;
+                            r.voxel = e.voxel; r.view = (uint32_t)v; r.hist = (uint32_t)h;
+                            my[idx] = r;
+                        }
                     }
+                    // the records are read by other lanes of this wavefront
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    s_next = 0;
+                    s_end = n_rec;
+                    c_next += n_rec;
+                    advance_cursor(C, cur_view, cur_hist, n_rec, C.n_views);
                 }
-                // the records are read by other lanes of this wavefront
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                s_next = 0;
-                s_end = n_rec;
-                c_next += n_rec;
-                advance_cursor(C, cur_view, cur_hist, n_rec, C.n_views);
             }
-            const uint32_t avail = s_end - s_next;
-            const uint32_t rank = __popcll(need & lane_lt);
-            if (L.state == S_IDLE && rank < avail) {
-                const EmitRec r = my[s_next + rank];
-                Emission e;
-                e.x = r.x; e.y = r.y; e.z = r.z; e.dx = r.dx; e.dy = r.dy; e.dz = r.dz;
-                e.voxel = r.voxel;
-                begin_history(C, L, r.view, r.hist, e);
+            if (ready && s_next < s_end) {
+                const uint32_t avail = s_end - s_next;
+                const uint32_t rank = __popcll(need & lane_lt);
+                if (L.state == S_IDLE && rank < avail) slot = (int)(s_next + rank);
+                s_next += min((uint32_t)__popcll(need), avail);
             }
-            const uint32_t took = min((uint32_t)__popcll(need), avail);
-            s_next += took;
-            need = __ballot(L.state == S_IDLE);
+        }
+        if (slot >= 0) {
+            const EmitRec r = my[slot];
+            Emission e;
+            e.x = r.x; e.y = r.y; e.z = r.z; e.dx = r.dx; e.dy = r.dy; e.dz = r.dz;
+            e.voxel = r.voxel;
+            begin_history(C, L, r.view, r.hist, e);
         }
         if (exhausted && __ballot(L.state != S_IDLE) == 0) break;
 

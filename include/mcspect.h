@@ -209,9 +209,13 @@ size_t mc_system_matrix_workspace_bytes(const mc_problem* problem, uint64_t even
  *   proj       device float [n_bins]: P_j = sum_i c_ij (nullable)
  * nnz = T_rowptr[n_bins] = Tt_rowptr[n_img] <= min(*n_events, capacity).
  * events / n_events / event_capacity: as returned by mc_simulate_projections
- * for this problem.  Deterministic (integer counts, sorted rows). */
+ * for this problem.  class_mask selects the tallied histories used: bit 0
+ * primaries, bit 1 scattered photons (3: all; 1: the primary-only matrix a
+ * dual-matrix or additive-scatter reconstruction backprojects with; 2: with
+ * proj, the scatter projection).  Deterministic (integer counts, sorted
+ * rows). */
 int mc_system_matrix(const mc_problem* problem, const mc_event* events, const uint64_t* n_events,
-                     uint64_t event_capacity,
+                     uint64_t event_capacity, int32_t class_mask,
                      int64_t* T_rowptr, int32_t* T_col, float* T_val,
                      int64_t* Tt_rowptr, int32_t* Tt_col, float* Tt_val, float* proj,
                      void* workspace, size_t workspace_bytes, void* stream);
@@ -229,6 +233,29 @@ int mlem_iterate(int64_t n_bins, int64_t n_vox,
                  const int64_t* T_rowptr, const int32_t* T_col, const float* T_val,
                  const int64_t* Tt_rowptr, const int32_t* Tt_col, const float* Tt_val,
                  const float* proj, float* image, int32_t n_iter,
+                 void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace bytes of osem_iterate. */
+size_t osem_workspace_bytes(int64_t n_bins, int64_t n_vox, int32_t n_subsets);
+
+/* Ordered-subsets reconstruction in the forms the paper reviews (Sec. 5.3,
+ * Sec. 5.4): OSEM; the dual-matrix update of Eq. DMOS (reproject with c,
+ * backproject with b); OS-EM with an additive Monte Carlo scatter projection
+ * s (the Sohlberg OS-EM equation).  Subset k holds the views v with
+ * v mod n_subsets == k (view of bin j = j / bins_per_view); one iteration
+ * visits the subsets in order k = 0..n_subsets-1, each
+ *   y_j = sum_i c_ij S_i + s_j            (bins j of subset k)
+ *   S_i <- S_i / sens_k,i * sum_{j in k} b_ij P_j / y_j,  sens_k,i = sum_{j in k} b_ij
+ * (voxels with sens_k,i = 0 keep their value for that subset; voxels no bin
+ * sees start and stay at 0).  n_subsets = 1, b = c, s = NULL is MLEM.
+ *   C_*   CSR of c, rows = bins;  Bt_*  CSR of b transposed, rows = voxels
+ *   proj  device float [n_bins];  scatter  device float [n_bins] or NULL
+ *   image device float [n_vox]: S^0 in, result out.
+ * FP32 matrix values, FP64 accumulation. */
+int osem_iterate(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n_subsets,
+                 const int64_t* C_rowptr, const int32_t* C_col, const float* C_val,
+                 const int64_t* Bt_rowptr, const int32_t* Bt_col, const float* Bt_val,
+                 const float* proj, const float* scatter, float* image, int32_t n_iter,
                  void* workspace, size_t workspace_bytes, void* stream);
 
 /* Human-readable text for an MC_* code (static storage). */

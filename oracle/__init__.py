@@ -279,13 +279,15 @@ def poisson_loss_grad(lam: np.ndarray, y: np.ndarray, eps: float):
 # Response matrix and MLEM (Sec. 5.1)
 # ---------------------------------------------------------------------------
 
-def system_matrix(prob, trip_i: np.ndarray, trip_j: np.ndarray):
+def system_matrix(prob, trip_i: np.ndarray, trip_j: np.ndarray, classes: str = "all"):
     """Response matrix of Sec. 5.1 (Eq. IMC) from the tallied histories.
 
     T_ij = c_ij / n_i(j): c_ij tallied photons emitted in image voxel i and
     counted in projection bin j (primary and scattered alike: j = (view, iv,
     iu)), n_i(j) = N_view(j) * A_i / A the expected number emitted in i towards
-    bin j's view (A_i: activity summed over image voxel i, A: total).  Returns
+    bin j's view (A_i: activity summed over image voxel i, A: total).
+    classes = "primary" / "scatter" keeps only unscattered / scattered
+    photons (the dual-matrix backprojector, the scatter projection).  Returns
     (T as scipy CSR, rows = bins, FP64; P_j = sum_i c_ij; expected emissions
     n_i per view-averaged history count)."""
     import scipy.sparse as sp
@@ -297,6 +299,9 @@ def system_matrix(prob, trip_i: np.ndarray, trip_j: np.ndarray):
     total = act.sum()
     V, per = prob.n_views, prob.nv * prob.nu
     n_bins = V * per
+    cls = (trip_j // per) % 2
+    keep = {"all": np.ones(len(trip_j), bool), "primary": cls == 0, "scatter": cls == 1}[classes]
+    trip_i, trip_j = trip_i[keep], trip_j[keep]
     view = trip_j // (2 * per)
     row = view * per + trip_j % per
     n_view = np.array([prob.n_histories // V + (1 if k < prob.n_histories % V else 0)
@@ -328,6 +333,38 @@ def mlem(T, P: np.ndarray, n_iter: int, S0: Optional[np.ndarray] = None) -> np.n
         ratio[nz] = P[nz] / y[nz]
         back = T.T @ ratio
         S = np.where(seen, S * back / np.where(seen, sens, 1.0), 0.0)
+    return S
+
+
+def osem(c, P: np.ndarray, n_iter: int, n_subsets: int, bins_per_view: int, b=None,
+         scatter: Optional[np.ndarray] = None, S0: Optional[np.ndarray] = None) -> np.ndarray:
+    """Ordered subsets, written out from Sec. 5.3 (Eq. DMOS) and Sec. 5.4
+    (the Sohlberg OS-EM equation).  Subset k = views v with v mod n_subsets
+    == k.  For each subset in order:
+        y_j = sum_i c_ij S_i + s_j  (j in k)
+        S_i <- S_i / sum_{j in k} b_ij * sum_{j in k} b_ij P_j / y_j
+    b defaults to c (plain OSEM), s to 0; voxels with no weight in a subset
+    keep their value; voxels no bin sees are 0."""
+    c = c.tocsr().astype(np.float64)
+    b = c if b is None else b.tocsr().astype(np.float64)
+    P = np.asarray(P, dtype=np.float64)
+    s = np.zeros(c.shape[0]) if scatter is None else np.asarray(scatter, dtype=np.float64)
+    view = np.arange(c.shape[0]) // bins_per_view
+    subset = view % n_subsets
+    seen = np.asarray(b.sum(axis=0)).ravel() > 0
+    S = np.where(seen, 1.0, 0.0) if S0 is None else np.where(seen, np.asarray(S0, np.float64), 0.0)
+    for _ in range(n_iter):
+        for k in range(n_subsets):
+            rows = np.flatnonzero(subset == k)
+            ck, bk = c[rows], b[rows]
+            y = ck @ S + s[rows]
+            ratio = np.zeros_like(y)
+            nz = y > 0
+            ratio[nz] = P[rows][nz] / y[nz]
+            sens = np.asarray(bk.sum(axis=0)).ravel()
+            back = bk.T @ ratio
+            upd = sens > 0
+            S = np.where(upd, S * back / np.where(upd, sens, 1.0), S)
     return S
 
 

@@ -37,7 +37,8 @@ Q23 = float(2 ** 23)   # energy fixed point: Q40.23 keV
 # Exported symbols, as declared in include/mcspect.h.
 EXPORTS = ["mc_workspace_bytes", "mc_simulate_projections", "mc_replay_histories",
            "mc_adjoint_mu", "mc_system_matrix_workspace_bytes", "mc_system_matrix",
-           "mlem_workspace_bytes", "mlem_iterate", "mc_error_string", "mc_last_hip_error"]
+           "mlem_workspace_bytes", "mlem_iterate", "osem_workspace_bytes", "osem_iterate",
+           "mc_error_string", "mc_last_hip_error"]
 
 
 class McProblem(C.Structure):
@@ -82,8 +83,13 @@ _lib.mc_adjoint_mu.argtypes = [C.POINTER(McProblem), C.POINTER(McOptions), _vp, 
 _lib.mc_adjoint_mu.restype = C.c_int
 _lib.mc_system_matrix_workspace_bytes.argtypes = [C.POINTER(McProblem), _u64]
 _lib.mc_system_matrix_workspace_bytes.restype = _sz
-_lib.mc_system_matrix.argtypes = [C.POINTER(McProblem), _vp, _vp, _u64, _vp, _vp, _vp, _vp, _vp, _vp,
-                                  _vp, _vp, _sz, _vp]
+_lib.mc_system_matrix.argtypes = [C.POINTER(McProblem), _vp, _vp, _u64, C.c_int32, _vp, _vp, _vp,
+                                  _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.osem_workspace_bytes.argtypes = [_i64, _i64, C.c_int32]
+_lib.osem_workspace_bytes.restype = _sz
+_lib.osem_iterate.argtypes = [_i64, _i64, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                              _vp, _vp, C.c_int32, _vp, _sz, _vp]
+_lib.osem_iterate.restype = C.c_int
 _lib.mc_system_matrix.restype = C.c_int
 _lib.mlem_workspace_bytes.argtypes = [_i64, _i64]
 _lib.mlem_workspace_bytes.restype = _sz
@@ -560,8 +566,11 @@ class SystemMatrix:
                               self.T_rowptr.cpu().numpy()), shape=(self.n_bins, self.n_img))
 
 
-def system_matrix(problem: DeviceProblem, sim: Simulator) -> SystemMatrix:
-    """Response matrix from the event list of a forward Simulator run."""
+def system_matrix(problem: DeviceProblem, sim: Simulator, classes: str = "all") -> SystemMatrix:
+    """Response matrix from the event list of a forward Simulator run.
+    classes: "all", "primary" (backprojector of the dual-matrix and
+    additive-scatter forms) or "scatter" (its proj is the scatter projection)."""
+    mask = {"all": 3, "primary": 1, "scatter": 2}[classes]
     torch = _torch()
     if sim.events is None:
         raise McError("the forward run kept no event list")
@@ -586,7 +595,7 @@ def system_matrix(problem: DeviceProblem, sim: Simulator) -> SystemMatrix:
                      torch.empty(cap, dtype=torch.float32, device=dev),
                      torch.empty(n_bins, dtype=torch.float32, device=dev))
     rc = _lib.mc_system_matrix(C.byref(arr), sim.events.data_ptr(), sim.n_events.data_ptr(), cap,
-                               m.T_rowptr.data_ptr(), m.T_col.data_ptr(), m.T_val.data_ptr(),
+                               mask, m.T_rowptr.data_ptr(), m.T_col.data_ptr(), m.T_val.data_ptr(),
                                m.Tt_rowptr.data_ptr(), m.Tt_col.data_ptr(), m.Tt_val.data_ptr(),
                                m.proj.data_ptr(), ws.data_ptr(), nb, _stream_ptr())
     _check(rc, "mc_system_matrix")
@@ -627,3 +636,23 @@ def csr_from_scipy(T, device="cuda") -> SystemMatrix:
     return SystemMatrix(T.shape[0], T.shape[1], t(T.indptr, np.int64), t(T.indices, np.int32),
                         t(T.data, np.float32), t(Tt.indptr, np.int64), t(Tt.indices, np.int32),
                         t(Tt.data, np.float32), torch.zeros(T.shape[0], dtype=torch.float32, device=device))
+
+
+def osem(c: SystemMatrix, image, n_iter: int, n_subsets: int, bins_per_view: int,
+         b: Optional[SystemMatrix] = None, proj=None, scatter=None):
+    """Ordered-subsets reconstruction (OSEM; dual matrix with backprojector b;
+    additive scatter projection).  image: float32 device [n_img], in place."""
+    torch = _torch()
+    b = c if b is None else b
+    P = c.proj if proj is None else proj
+    nb = _lib.osem_workspace_bytes(c.n_bins, c.n_img, int(n_subsets))
+    if nb == 0:
+        raise McError("osem_workspace_bytes: invalid sizes")
+    ws = torch.empty(nb, dtype=torch.uint8, device=c.T_val.device)
+    rc = _lib.osem_iterate(c.n_bins, c.n_img, int(bins_per_view), int(n_subsets),
+                           c.T_rowptr.data_ptr(), c.T_col.data_ptr(), c.T_val.data_ptr(),
+                           b.Tt_rowptr.data_ptr(), b.Tt_col.data_ptr(), b.Tt_val.data_ptr(),
+                           P.data_ptr(), scatter.data_ptr() if scatter is not None else None,
+                           image.data_ptr(), int(n_iter), ws.data_ptr(), nb, _stream_ptr())
+    _check(rc, "osem_iterate")
+    return image

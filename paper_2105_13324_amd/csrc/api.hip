@@ -302,7 +302,8 @@ size_t mc_system_matrix_workspace_bytes(const mc_problem* problem, uint64_t even
 }
 
 int mc_system_matrix(const mc_problem* problem, const mc_event* events, const uint64_t* n_events,
-                     uint64_t event_capacity, int64_t* T_rowptr, int32_t* T_col, float* T_val,
+                     uint64_t event_capacity, int32_t class_mask, int64_t* T_rowptr, int32_t* T_col,
+                     float* T_val,
                      int64_t* Tt_rowptr, int32_t* Tt_col, float* Tt_val, float* proj,
                      void* workspace, size_t workspace_bytes, void* stream) {
     if (!problem || !events || !n_events || !T_rowptr || !T_col || !T_val || !Tt_rowptr ||
@@ -310,13 +311,15 @@ int mc_system_matrix(const mc_problem* problem, const mc_event* events, const ui
         return MC_EINVAL;
     if (!check_problem(*problem) || problem->image_factor < 1) return MC_EINVAL;
     if (event_capacity < 1 || event_capacity >= (1ull << 31)) return MC_EINVAL;
+    if (class_mask < 1 || class_mask > 3) return MC_EINVAL;
     const mc_problem& p = *problem;
     if ((uint64_t)p.n_views * p.nu * p.nv >= (1ull << 31)) return MC_EINVAL;
     if (workspace_bytes < mc_system_matrix_workspace_bytes(problem, event_capacity)) return MC_ENOMEM;
     hipError_t e = launch_sysmat(events, (const unsigned long long*)n_events, event_capacity,
                                  (uint32_t)p.nx, (uint32_t)p.ny, (uint32_t)p.nz,
                                  (uint32_t)p.image_factor, (uint32_t)p.n_views, (uint32_t)p.nu,
-                                 (uint32_t)p.nv, p.n_histories, p.activity, T_rowptr, T_col, T_val,
+                                 (uint32_t)p.nv, p.n_histories, p.activity, (uint32_t)class_mask,
+                                 T_rowptr, T_col, T_val,
                                  Tt_rowptr, Tt_col, Tt_val, proj, workspace, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
     return MC_OK;
@@ -339,6 +342,31 @@ int mlem_iterate(int64_t n_bins, int64_t n_vox, const int64_t* T_rowptr, const i
     if (workspace_bytes < mlem_workspace((uint64_t)n_bins, (uint64_t)n_vox)) return MC_ENOMEM;
     hipError_t e = launch_mlem(n_bins, n_vox, T_rowptr, T_col, T_val, Tt_rowptr, Tt_col, Tt_val,
                                proj, image, n_iter, workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return MC_OK;
+}
+
+size_t osem_workspace_bytes(int64_t n_bins, int64_t n_vox, int32_t n_subsets) {
+    if (n_bins < 1 || n_vox < 1 || n_subsets < 1) return 0;
+    return osem_workspace((uint64_t)n_bins, (uint64_t)n_vox, (uint32_t)n_subsets);
+}
+
+int osem_iterate(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n_subsets,
+                 const int64_t* C_rowptr, const int32_t* C_col, const float* C_val,
+                 const int64_t* Bt_rowptr, const int32_t* Bt_col, const float* Bt_val,
+                 const float* proj, const float* scatter, float* image, int32_t n_iter,
+                 void* workspace, size_t workspace_bytes, void* stream) {
+    if (n_bins < 1 || n_vox < 1 || n_iter < 0 || bins_per_view < 1 || n_subsets < 1) return MC_EINVAL;
+    if (n_bins >= (1ll << 31) || n_vox >= (1ll << 31) || n_bins % bins_per_view != 0) return MC_EINVAL;
+    if (n_subsets > n_bins / bins_per_view) return MC_EINVAL;
+    if (!C_rowptr || !C_col || !C_val || !Bt_rowptr || !Bt_col || !Bt_val || !proj || !image ||
+        !workspace)
+        return MC_EINVAL;
+    if (workspace_bytes < osem_workspace((uint64_t)n_bins, (uint64_t)n_vox, (uint32_t)n_subsets))
+        return MC_ENOMEM;
+    hipError_t e = launch_osem(n_bins, n_vox, bins_per_view, n_subsets, C_rowptr, C_col, C_val,
+                               Bt_rowptr, Bt_col, Bt_val, proj, scatter, image, n_iter, workspace,
+                               (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
     return MC_OK;
 }

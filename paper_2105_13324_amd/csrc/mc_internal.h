@@ -116,13 +116,20 @@ size_t sysmat_workspace_bytes(uint64_t n_bins, uint64_t n_img, uint64_t capacity
 hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_events, uint64_t capacity,
                          uint32_t nx, uint32_t ny, uint32_t nz, uint32_t f, uint32_t n_views,
                          uint32_t nu, uint32_t nv, uint64_t n_hist, const uint32_t* activity,
-                         int64_t* T_rp, int32_t* T_col, float* T_val,
+                         uint32_t class_mask, int64_t* T_rp, int32_t* T_col, float* T_val,
                          int64_t* Tt_rp, int32_t* Tt_col, float* Tt_val, float* proj,
                          void* workspace, hipStream_t s);
 size_t mlem_workspace(uint64_t n_bins, uint64_t n_vox);
 hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, const int64_t* T_rp, const int32_t* T_col,
                        const float* T_val, const int64_t* Tt_rp, const int32_t* Tt_col,
                        const float* Tt_val, const float* proj, float* image, int32_t n_iter,
+                       void* workspace, hipStream_t s);
+
+size_t osem_workspace(uint64_t n_bins, uint64_t n_vox, uint32_t n_sub);
+hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n_sub,
+                       const int64_t* C_rp, const int32_t* C_col, const float* C_val,
+                       const int64_t* Bt_rp, const int32_t* Bt_col, const float* Bt_val,
+                       const float* proj, const float* scatter, float* image, int32_t n_iter,
                        void* workspace, hipStream_t s);
 
 // Occupancy of the transport kernel (blocks per CU at this block size).

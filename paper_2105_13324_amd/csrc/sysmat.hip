@@ -134,6 +134,7 @@ struct SysArgs {
     const mc_event* events;
     const unsigned long long* n_events;
     uint64_t capacity;
+    uint32_t class_mask;     // bit 0: primary events, bit 1: scattered events
     uint32_t nv_nu;          // bins per view and class
     uint32_t nx, ny, f, mx, my;
     uint64_t q_per_view, r_extra;
@@ -144,14 +145,18 @@ __device__ inline uint64_t n_events_of(const SysArgs& a) {
     return n < a.capacity ? n : a.capacity;
 }
 
-// projection bin (classes merged) and image voxel of event e
-__device__ inline void event_rc(const SysArgs& a, const mc_event& ev, uint32_t& bin, uint32_t& img) {
+// projection bin (classes merged) and image voxel of event e; false if the
+// event's class is filtered out
+__device__ inline bool event_rc(const SysArgs& a, const mc_event& ev, uint32_t& bin, uint32_t& img) {
     const uint32_t per_view = 2u * a.nv_nu;
+    const uint32_t cls = (ev.bin / a.nv_nu) & 1u;
+    if (!((a.class_mask >> cls) & 1u)) return false;
     const uint32_t view = ev.bin / per_view;
     bin = view * a.nv_nu + (ev.bin % a.nv_nu);
     const uint32_t v = ev.emit_voxel;
     const uint32_t ix = v % a.nx, iy = (v / a.nx) % a.ny, iz = v / (a.nx * a.ny);
     img = (ix / a.f) + a.mx * ((iy / a.f) + a.my * (iz / a.f));
+    return true;
 }
 
 __global__ __launch_bounds__(T256) void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(T256) void k_count_rows(SysArgs a, int transpose, u
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t bin, img;
-        event_rc(a, a.events[e], bin, img);
+        if (!event_rc(a, a.events[e], bin, img)) continue;
         atomicAdd(cnt + (transpose ? img : bin), 1u);
     }
 }
@@ -200,7 +205,7 @@ __global__ __launch_bounds__(T256) void k_scatter(SysArgs a, int transpose, cons
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t bin, img;
-        event_rc(a, a.events[e], bin, img);
+        if (!event_rc(a, a.events[e], bin, img)) continue;
         const uint32_t r = transpose ? img : bin, c = transpose ? bin : img;
         const uint32_t k = atomicAdd(fill + r, 1u);
         tmp_col[start[r] + k] = c;
@@ -319,7 +324,114 @@ __global__ __launch_bounds__(T256) void k_mlem_out(int64_t n_vox, const double* 
         img[i] = (float)S[i];
 }
 
+// ---- ordered subsets (OSEM; dual matrix, Eq. DMOS; additive scatter, the
+// Sohlberg OS-EM equation).  Subset k holds the views v with v mod n_sub == k.
+
+// sens[k][i] = sum over the bins j of subset k of b_ij (row i of B^T)
+__global__ __launch_bounds__(T256) void k_subset_sens(int64_t n_vox, const int64_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col,
+                                                      const float* __restrict__ val,
+                                                      int32_t bins_per_view, int32_t n_sub,
+                                                      double* __restrict__ sens) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        for (int k = 0; k < n_sub; ++k) sens[(int64_t)k * n_vox + i] = 0.0;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const int k = (col[e] / bins_per_view) % n_sub;
+            sens[(int64_t)k * n_vox + i] += (double)val[e];
+        }
+    }
+}
+
+__global__ __launch_bounds__(T256) void k_os_init(int64_t n_vox, int32_t n_sub,
+                                                  const float* __restrict__ img,
+                                                  const double* __restrict__ sens,
+                                                  double* __restrict__ S) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double tot = 0.0;
+        for (int k = 0; k < n_sub; ++k) tot += sens[(int64_t)k * n_vox + i];
+        S[i] = tot > 0.0 ? (double)img[i] : 0.0;
+    }
+}
+
+// subset k: y_j = sum_i c_ij S_i + s_j, ratio_j = P_j / y_j on the subset's bins
+__global__ __launch_bounds__(T256) void k_os_forward(int64_t n_sub_bins, int32_t bins_per_view,
+                                                     int32_t n_sub, int32_t k,
+                                                     const int64_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ col,
+                                                     const float* __restrict__ val,
+                                                     const double* __restrict__ S,
+                                                     const float* __restrict__ P,
+                                                     const float* __restrict__ scat,
+                                                     double* __restrict__ ratio) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_sub_bins;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t view = k + (int64_t)n_sub * (t / bins_per_view);
+        const int64_t j = view * bins_per_view + t % bins_per_view;
+        double y = scat ? (double)scat[j] : 0.0;
+        for (int64_t e = rp[j]; e < rp[j + 1]; ++e) y += (double)val[e] * S[col[e]];
+        ratio[j] = y > 0.0 ? (double)P[j] / y : 0.0;
+    }
+}
+
+// subset k: S_i <- S_i * (sum_{j in k} b_ij ratio_j) / sens_k,i (unchanged where sens_k,i = 0)
+__global__ __launch_bounds__(T256) void k_os_update(int64_t n_vox, int32_t bins_per_view,
+                                                    int32_t n_sub, int32_t k,
+                                                    const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col,
+                                                    const float* __restrict__ val,
+                                                    const double* __restrict__ ratio,
+                                                    const double* __restrict__ sens,
+                                                    double* __restrict__ S) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double si = sens[(int64_t)k * n_vox + i];
+        if (!(si > 0.0)) continue;
+        double bsum = 0.0;
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const int32_t j = col[e];
+            if ((j / bins_per_view) % n_sub == k) bsum += (double)val[e] * ratio[j];
+        }
+        S[i] = S[i] * bsum / si;
+    }
+}
+
 }  // namespace
+
+size_t osem_workspace(uint64_t n_bins, uint64_t n_vox, uint32_t n_sub) {
+    auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+    return al(8 * n_vox * n_sub) /* sens per subset */ + al(8 * n_vox) /* S */ + al(8 * n_bins);
+}
+
+hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n_sub,
+                       const int64_t* C_rp, const int32_t* C_col, const float* C_val,
+                       const int64_t* Bt_rp, const int32_t* Bt_col, const float* Bt_val,
+                       const float* proj, const float* scatter, float* image, int32_t n_iter,
+                       void* workspace, hipStream_t s) {
+    auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+    char* w = (char*)workspace;
+    double* sens = (double*)w;  w += al(8 * (uint64_t)n_vox * n_sub);
+    double* S = (double*)w;     w += al(8 * (uint64_t)n_vox);
+    double* ratio = (double*)w;
+    const int64_t n_views = n_bins / bins_per_view;
+    const int gv = grid_for((uint64_t)n_vox, T256, 8192);
+    k_subset_sens<<<gv, T256, 0, s>>>(n_vox, Bt_rp, Bt_col, Bt_val, bins_per_view, n_sub, sens);
+    k_os_init<<<gv, T256, 0, s>>>(n_vox, n_sub, image, sens, S);
+    for (int it = 0; it < n_iter; ++it) {
+        for (int k = 0; k < n_sub; ++k) {
+            const int64_t views_k = (n_views - k + n_sub - 1) / n_sub;
+            const int64_t nb = views_k * bins_per_view;
+            if (nb <= 0) continue;
+            k_os_forward<<<grid_for((uint64_t)nb, T256, 16384), T256, 0, s>>>(
+                nb, bins_per_view, n_sub, k, C_rp, C_col, C_val, S, proj, scatter, ratio);
+            k_os_update<<<gv, T256, 0, s>>>(n_vox, bins_per_view, n_sub, k, Bt_rp, Bt_col, Bt_val,
+                                            ratio, sens, S);
+        }
+    }
+    k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, image);
+    return hipGetLastError();
+}
 
 // Workspace of the response-matrix build, in bytes (layout below).
 size_t sysmat_workspace_bytes(uint64_t n_bins, uint64_t n_img, uint64_t capacity) {
@@ -334,7 +446,7 @@ size_t sysmat_workspace_bytes(uint64_t n_bins, uint64_t n_img, uint64_t capacity
 hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_events, uint64_t capacity,
                          uint32_t nx, uint32_t ny, uint32_t nz, uint32_t f, uint32_t n_views,
                          uint32_t nu, uint32_t nv, uint64_t n_hist, const uint32_t* activity,
-                         int64_t* T_rp, int32_t* T_col, float* T_val,
+                         uint32_t class_mask, int64_t* T_rp, int32_t* T_col, float* T_val,
                          int64_t* Tt_rp, int32_t* Tt_col, float* Tt_val, float* proj,
                          void* workspace, hipStream_t s) {
     const uint64_t n_bins = (uint64_t)n_views * nu * nv;
@@ -356,6 +468,7 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
 
     SysArgs a;
     a.events = events; a.n_events = n_events; a.capacity = capacity;
+    a.class_mask = class_mask;
     a.nv_nu = nu * nv;
     a.nx = nx; a.ny = ny; a.f = f; a.mx = mx; a.my = my;
     a.q_per_view = n_hist / n_views; a.r_extra = n_hist % n_views;

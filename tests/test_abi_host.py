@@ -22,7 +22,7 @@ def _mc():
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"\b(mc\w+|mlem\w+)\s*\(", src)
+    names = re.findall(r"\b((?:mc|mlem|osem)_\w+)\s*\(", src)
     return sorted(set(names))
 
 

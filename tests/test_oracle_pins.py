@@ -511,3 +511,53 @@ def test_system_matrix_normalisation_and_fixed_point():
     c = np.sum((r["trip_i"] == i) & ((r["trip_j"] // (2 * p.nv * p.nu)) * p.nv * p.nu
                                      + r["trip_j"] % (p.nv * p.nu) == row))
     assert T[row, i] == pytest.approx(c / n[i], rel=1e-12)
+
+
+def _views_system(seed, n_views=12, bpv=40, n_vox=90, dens=0.05):
+    T, n = phantoms.random_system(n_views * bpv, n_vox, dens, seed)
+    sens = np.asarray(T.sum(axis=0)).ravel()
+    return T.astype(np.float64), np.where(sens > 0, n, 0.0), bpv
+
+
+def test_osem_one_subset_is_mlem():
+    T, n, bpv = _views_system(41)
+    rng = np.random.Generator(np.random.PCG64(42))
+    P = rng.poisson(T @ n * 5).astype(np.float64)
+    np.testing.assert_allclose(oracle.osem(T, P, 7, 1, bpv), oracle.mlem(T, P, 7), rtol=1e-12)
+
+
+def test_osem_fixed_point_and_subset_conservation():
+    T, n, bpv = _views_system(43)
+    P = T @ n
+    S = oracle.osem(T, P, 3, 4, bpv, S0=n)
+    np.testing.assert_allclose(S, n, rtol=1e-10)
+    # one subset update: sum_i sens_k,i S_i' = sum_{j in k, y_j > 0} P_j
+    rng = np.random.Generator(np.random.PCG64(44))
+    Pn = rng.poisson(P * 3).astype(np.float64) / 3
+    S1 = oracle.osem(T, Pn, 1, 1, bpv)               # any positive start
+    rows = np.flatnonzero((np.arange(T.shape[0]) // bpv) % 4 == 0)
+    sens0 = np.asarray(T[rows].sum(axis=0)).ravel()
+    y = T[rows] @ S1
+    S2 = oracle.osem(T, Pn, 1, 4, bpv, S0=S1)         # first update of the pass is subset 0
+    # isolate subset 0's update by running a one-pass, one-subset-only variant
+    mask = np.zeros(T.shape[0])
+    mask[rows] = 1
+    Tk = T.multiply(mask[:, None]).tocsr()
+    S_k = oracle.osem(Tk, Pn, 1, 4, bpv, S0=S1)
+    upd = sens0 > 0
+    assert np.dot(sens0[upd], S_k[upd]) == pytest.approx(Pn[rows][y > 0].sum(), rel=1e-12)
+    assert np.all(np.isfinite(S2))
+
+
+def test_osem_additive_scatter_and_dual_matrix_reduce():
+    T, n, bpv = _views_system(45)
+    Ts, _, _ = _views_system(46)
+    rng = np.random.Generator(np.random.PCG64(47))
+    P = rng.poisson((T + 0.3 * Ts) @ n * 4).astype(np.float64)
+    base = oracle.osem(T, P, 4, 3, bpv)
+    np.testing.assert_allclose(oracle.osem(T, P, 4, 3, bpv, scatter=np.zeros(T.shape[0])), base, rtol=1e-12)
+    np.testing.assert_allclose(oracle.osem(T, P, 4, 3, bpv, b=T), base, rtol=1e-12)
+    # consistent data with an additive scatter term: n is a fixed point
+    s = 0.3 * (Ts @ n)
+    Pc = T @ n + s
+    np.testing.assert_allclose(oracle.osem(T, Pc, 3, 3, bpv, scatter=s, S0=n), n, rtol=1e-10)

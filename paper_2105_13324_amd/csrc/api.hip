@@ -88,7 +88,7 @@ bool plan(const mc_problem* probs, int n, Layout& L) {
         L.vid[i] = off;   off += align256(4 * nvox);
         L.bsum[i] = off;  off += align256(8 * ((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS));
         L.bcnt[i] = off;  off += align256(4 * ((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS));
-        L.guide[i] = off; off += align256(4 * (guide_capacity(nvox) + 1));
+        L.guide[i] = off; off += align256(16 * guide_capacity(nvox));
         L.views[i] = off; off += align256(8 * (size_t)p.n_views);
         L.kn[i] = off;    off += align256(4 * (size_t)KN_TABLE_N);
     }
@@ -135,7 +135,7 @@ ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64
     d.vox_id = (uint32_t*)(ws + L.vid[i]);
     d.block_sums = (uint64_t*)(ws + L.bsum[i]);
     d.block_cnt = (uint32_t*)(ws + L.bcnt[i]);
-    d.guide = (uint32_t*)(ws + L.guide[i]);
+    d.guide = (uint4*)(ws + L.guide[i]);
     d.views = (float2*)(ws + L.views[i]);
     d.kn_table = (float*)(ws + L.kn[i]);
     return d;

@@ -64,7 +64,7 @@ struct Cst {
     const uint32_t* q32;
     const uint64_t* cdf;
     const uint32_t* vox_id;
-    const uint32_t* guide;
+    const uint4* guide;
     const float2* views;
     const float* kn_table;
     int nx, ny, nz, source_mode;
@@ -243,7 +243,7 @@ __device__ inline void advance_cursor(const Cst& C, uint64_t& view, uint64_t& hi
 // Sub-draw 0: words 0-1 pick the voxel by inverse CDF, words 2-3 the x and y
 // offsets in it; sub-draw 1: word 0 the z offset, word 1 cos(theta), word 2
 // the azimuth.  Runs with the wavefront converged (no per-lane branches
-// except the short guide-range search).
+// except the CDF search of a bucket that spans three or more voxels).
 struct Emission {
     float x, y, z, dx, dy, dz;
     uint32_t voxel;
@@ -258,12 +258,20 @@ __device__ inline Emission emit_history(const Cst& C, uint32_t hist, uint32_t vi
     const uint64_t R = ((uint64_t)a0 << 32) | a1;
     const uint64_t t = __umul64hi(R, C.total);
     const uint64_t b = t >> C.shift;
-    uint32_t lo = C.guide[b], hi = C.guide[b + 1];
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (C.cdf[mid] > t) hi = mid; else lo = mid + 1;
+    const uint4 g = C.guide[b];
+    uint32_t packed;                        // ix | iy << 10 | iz << 20
+    if (g.x & BUCKET_WIDE) {
+        // the bucket spans three or more voxels: search its CDF slots
+        uint32_t lo = g.y, hi = g.z;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (C.cdf[mid] > t) hi = mid; else lo = mid + 1;
+        }
+        packed = C.vox_id[lo];
+    } else {
+        const uint64_t split = ((uint64_t)g.w << 32) | g.z;
+        packed = (t - (b << C.shift)) < split ? g.x : g.y;
     }
-    const uint32_t packed = C.vox_id[lo];   // ix | iy << 10 | iz << 20
     const uint32_t ix = packed & 1023u, iy = (packed >> 10) & 1023u, iz = packed >> 20;
     Emission e;
     e.voxel = ix + (uint32_t)C.nx * (iy + (uint32_t)C.ny * iz);

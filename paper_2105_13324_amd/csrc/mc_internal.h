@@ -40,7 +40,7 @@ struct ProbDesc {
     uint32_t* vox_id;               // voxel index of each active voxel, in grid order
     uint64_t* block_sums;           // scan scratch: activity per block
     uint32_t* block_cnt;            // scan scratch: active voxels per block
-    uint32_t* guide;                // guide table, n_buckets + 1 entries
+    uint4* guide;                   // emission buckets (EmitBucket layout), n_buckets entries
     float2* views;                  // (cos, sin) per view
     float* kn_table;                // sigma_KN(140 - i/4 keV) / sigma_KN(140), i < KN_TABLE_N
     // filled on the device by staging
@@ -52,6 +52,14 @@ struct ProbDesc {
     uint32_t n_active;              // voxels with activity > 0
     uint32_t pad1;
 };
+
+// Emission bucket b covers t in [b << shift, (b + 1) << shift) of the integer
+// activity CDF.  Bucket layout, as a uint4 (x, y, z, w):
+//   narrow (x bit 31 clear): t falls in at most two active voxels; x and y are
+//     their packed coordinates, (w:z) the offset of t from the bucket start
+//     below which x is taken (all ones when both are the same voxel);
+//   wide (x = BUCKET_WIDE): the slots of the CDF search are [y, z].
+constexpr uint32_t BUCKET_WIDE = 0x80000000u;
 
 constexpr int SCAN_ITEMS = 4096;    // activity values per scan block
 constexpr int KN_TABLE_N = 568;     // entries of the Klein-Nishina shape table (>= 4*140 + 2)
@@ -77,7 +85,7 @@ struct CallState {
 
 // Host launchers (staging.hip)
 hipError_t launch_staging(ProbDesc* d_desc, const ProbDesc& h_desc, hipStream_t s);
-uint64_t guide_capacity(uint64_t nvox);   // guide entries needed (power of two >= 2 nvox)
+uint64_t guide_capacity(uint64_t nvox);   // emission buckets reserved (power of two >= 2 nvox)
 
 // Host launchers (transport.hip)
 struct TransportArgs {

@@ -219,6 +219,15 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ProbDesc* pd) {
 // with about two buckets per active voxel; guide[b] is the first active slot
 // whose cumulative activity exceeds b 2^s and guide[B] the last slot, so the
 // answer for any t in bucket b lies in [guide[b], guide[b+1]].
+__device__ inline uint64_t first_above(const uint64_t* __restrict__ cdf, uint64_t K, uint64_t key) {
+    uint64_t lo = 0, hi = K - 1;   // first slot with cdf > key; cdf[K-1] = total > key
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (cdf[mid] > key) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(RED_THREADS) void k_guide(ProbDesc* pd, uint64_t nb_cap) {
     const uint64_t total = pd->total;
     const uint64_t K = pd->n_active;
@@ -237,17 +246,25 @@ __global__ __launch_bounds__(RED_THREADS) void k_guide(ProbDesc* pd, uint64_t nb
         pd->n_buckets = (uint32_t)B;
     }
     const uint64_t* __restrict__ cdf = pd->cdf;
-    uint32_t* __restrict__ guide = pd->guide;
-    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= B;
+    const uint32_t* __restrict__ vid = pd->vox_id;
+    uint4* __restrict__ guide = pd->guide;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B;
          b += (uint64_t)gridDim.x * blockDim.x) {
-        if (b == B) { guide[b] = (uint32_t)(K - 1); continue; }
-        const uint64_t key = b << s;
-        uint64_t lo = 0, hi = K - 1;   // first slot with cdf > key; cdf[K-1] = total > key
-        while (lo < hi) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (cdf[mid] > key) hi = mid; else lo = mid + 1;
+        // t in [lo_t, hi_t] maps to slots [first_above(lo_t), first_above(hi_t)]
+        const uint64_t lo_t = b << s;
+        const uint64_t hi_t = min(lo_t + ((1ull << s) - 1ull), total - 1);
+        const uint64_t lo = first_above(cdf, K, lo_t);
+        const uint64_t hi = first_above(cdf, K, hi_t);
+        uint4 g;
+        if (hi == lo) {
+            g.x = vid[lo]; g.y = g.x; g.z = 0xFFFFFFFFu; g.w = 0xFFFFFFFFu;
+        } else if (hi == lo + 1) {
+            const uint64_t split = cdf[lo] - lo_t;   // t < cdf[lo] takes slot lo
+            g.x = vid[lo]; g.y = vid[hi]; g.z = (uint32_t)split; g.w = (uint32_t)(split >> 32);
+        } else {
+            g.x = BUCKET_WIDE; g.y = (uint32_t)lo; g.z = (uint32_t)hi; g.w = 0;
         }
-        guide[b] = (uint32_t)lo;
+        guide[b] = g;
     }
 }
 
@@ -292,7 +309,7 @@ hipError_t launch_staging(ProbDesc* d, const ProbDesc& h, hipStream_t st) {
     k_scan_top<<<1, 1024, 0, st>>>(d, nb);
     k_scan_final<<<nb, SCAN_THREADS, 0, st>>>(d);
     const uint64_t cap = guide_capacity(nvox);
-    k_guide<<<grid_for(cap + 1, RED_THREADS, 8192), RED_THREADS, 0, st>>>(d, cap);
+    k_guide<<<grid_for(cap, RED_THREADS, 8192), RED_THREADS, 0, st>>>(d, cap);
     k_kn_table<<<(KN_TABLE_N + 255) / 256, 256, 0, st>>>(d);
     return hipGetLastError();
 }

@@ -115,6 +115,46 @@ def test_thorax_small_replay_and_aggregates():
     aggregate_parity(p)
 
 
+def _bucket_kinds(act):
+    """Spans of the emission buckets the library cuts the activity CDF into
+    (cap = power of two >= 2 x active voxels, width 2^s): how many active
+    voxels each bucket's range of t meets, weighted by the t it covers."""
+    w = act.ravel().astype(np.uint64)
+    w = w[w > 0]
+    cdf = np.cumsum(w, dtype=np.uint64)
+    total, K = int(cdf[-1]), len(w)
+    cap = 1 << int(np.ceil(np.log2(2 * K)))
+    s = 0
+    while ((total - 1) >> s) >= cap:
+        s += 1
+    starts = np.arange(0, total, 1 << s, dtype=np.uint64)
+    ends = np.minimum(starts + np.uint64((1 << s) - 1), np.uint64(total - 1))
+    lo = np.searchsorted(cdf, starts, side="right")
+    hi = np.searchsorted(cdf, ends, side="right")
+    span = hi - lo + 1
+    mass = (ends - starts + np.uint64(1)).astype(np.float64) / total
+    return {k: float(mass[(span == k) if k < 3 else (span >= 3)].sum()) for k in (1, 2, 3)}
+
+
+def test_emission_buckets_skewed_activity():
+    """Activity over nine decades (one hot voxel, a warm block, a faint body)
+    gives emission buckets of every kind: inside one voxel, split between two,
+    and wide ones searched over the CDF.  The emitted voxel is integer
+    arithmetic on both sides and must be identical for every history."""
+    p = phantoms.thorax_problem("skewed_act", 40, 0.96, 3, 6, 180.0, 32, 1.2, 300_000)
+    act = p.activity.copy()
+    act[20, 20, 20] = 3_000_000_000
+    act[10:14, 24:30, 15:19] = np.where(act[10:14, 24:30, 15:19] > 0, 2_000_000, 0)
+    act[30, 5:9, :] = 7
+    p = p.with_(activity=act)
+    kinds = _bucket_kinds(act)
+    say(f"bucket mass by span: {kinds}")
+    assert kinds[1] > 0.5 and kinds[2] > 1e-4 and kinds[3] > 1e-3
+    g, o = replay_parity(p, n=60_000, seed=11)
+    v = g["emit_voxel"]
+    assert np.any(v == 20 + 40 * (20 + 40 * 20)) and len(np.unique(v)) >= 90   # hot, warm block, faint body
+
+
 def test_thorax_odd_non_cubic_grid():
     mu, act = phantoms.thorax(48, 0.8, 9)
     mu = np.ascontiguousarray(mu[3:44, 1:46, :])       # nz=41, ny=45, nx=48

@@ -111,6 +111,11 @@ typedef struct {
     int32_t blocks_per_cu;      /* resident blocks per CU to launch, <=0: auto  */
     int32_t brick_log2;         /* accept-threshold layout: 0 linear (default), */
                                 /* 2 or 3: 4^3 or 8^3 voxel bricks              */
+    int32_t threshold_bytes;    /* bytes per voxel of the threshold table: 0 or */
+                                /* 1: one-byte codes into a 256-entry palette   */
+                                /* when the map has at most 256 distinct        */
+                                /* thresholds (else 4); 4: always 32-bit        */
+    int32_t reserved;           /* set to 0                                     */
     void* kernel_events[2];     /* optional hipEvent_t pair recorded on the     */
                                 /* stream right before / after the transport    */
                                 /* kernel (NULL: none)                          */
@@ -152,7 +157,9 @@ size_t mc_workspace_bytes(const mc_problem* problems, int32_t n_problems,
  *              particular order; nullable
  *   n_events   device uint64 [1], number of tallied histories (may exceed the
  *              capacity: then status has MC_STATUS_LIST_OVERFLOW); nullable
- *   status     device int64 [4]: [0] MC_STATUS_* bits, [1] capped histories
+ *   status     device int64 [4]: [0] MC_STATUS_* bits, [1] capped histories,
+ *              [2] problems whose thresholds were read as one-byte palette
+ *              codes (see mc_options.threshold_bytes)
  *   workspace  device, at least mc_workspace_bytes(...)
  * Results are bit-identical from run to run and independent of the options. */
 int mc_simulate_projections(const mc_problem* problems, int32_t n_problems,

@@ -60,6 +60,7 @@ class McProblem(C.Structure):
 class McOptions(C.Structure):
     _fields_ = [("hist_per_lane", C.c_int32), ("block_size", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("brick_log2", C.c_int32),
+                ("threshold_bytes", C.c_int32), ("reserved", C.c_int32),
                 ("kernel_events", C.c_void_p * 2)]
 
 
@@ -194,7 +195,8 @@ def _opts(options: Optional[dict]) -> Optional[McOptions]:
     o = McOptions(hist_per_lane=int(options.get("hist_per_lane", 0)),
                   block_size=int(options.get("block_size", 0)),
                   blocks_per_cu=int(options.get("blocks_per_cu", 0)),
-                  brick_log2=int(options.get("brick_log2", 0)))
+                  brick_log2=int(options.get("brick_log2", 0)),
+                  threshold_bytes=int(options.get("threshold_bytes", 0)))
     ev = options.get("kernel_events")
     if ev is not None:
         o.kernel_events[0] = ev[0]

@@ -86,7 +86,7 @@ __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now,
         const int before = L.state;
         const float e_flight = L.e;
         int iu = -1, iv = -1;
-        const int fate = advance(C, L, c0, c1, c2, c3, A, iu, iv);
+        const int fate = advance(C, C.pal, L, c0, c1, c2, c3, A, iu, iv);
         if (fate == R_RUNNING) {
             if (walk_now && before == S_STEP && L.state == S_KAHN) {
                 // Compton vertex at L.x: close the segment, add the collision term
@@ -97,7 +97,7 @@ __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now,
                 const int iy = min((int)((L.y + C.hy) * C.inv_vox), C.ny - 1);
                 const int iz = min((int)((L.z + C.hz) * C.inv_vox), C.nz - 1);
                 const uint32_t v = (uint32_t)ix + (uint32_t)C.nx * ((uint32_t)iy + (uint32_t)C.ny * (uint32_t)iz);
-                add_fixed(grad, v, G / (double)C.mu[v], scale, status);
+                add_fixed(grad, v, G / (double)ldg(C.mu + v), scale, status);
                 sx = L.x; sy = L.y; sz = L.z;
             }
             continue;

@@ -69,7 +69,7 @@ bool check_problem(const mc_problem& p) {
 
 struct Layout {
     size_t desc, prefix, state;
-    std::vector<size_t> q, cdf, vid, bsum, bcnt, guide, views, kn;
+    std::vector<size_t> q, q8, pal, cdf, vid, bsum, bcnt, guide, views, kn;
     size_t total;
 };
 
@@ -78,12 +78,14 @@ bool plan(const mc_problem* probs, int n, Layout& L) {
     L.desc = off;   off += align256(sizeof(ProbDesc) * (size_t)n);
     L.prefix = off; off += align256(sizeof(uint64_t) * 2 * ((size_t)n + 1));
     L.state = off;  off += align256(sizeof(CallState));
-    L.q.resize(n); L.cdf.resize(n); L.vid.resize(n); L.bsum.resize(n); L.bcnt.resize(n);
+    L.q.resize(n); L.q8.resize(n); L.pal.resize(n); L.cdf.resize(n); L.vid.resize(n); L.bsum.resize(n); L.bcnt.resize(n);
     L.guide.resize(n); L.views.resize(n); L.kn.resize(n);
     for (int i = 0; i < n; ++i) {
         const mc_problem& p = probs[i];
         const uint64_t nvox = (uint64_t)p.nx * p.ny * p.nz;
         L.q[i] = off;     off += align256(4 * padded_voxels(p));
+        L.q8[i] = off;    off += align256(padded_voxels(p));
+        L.pal[i] = off;   off += align256(4 * (size_t)PALETTE_N);
         L.cdf[i] = off;   off += align256(8 * nvox);
         L.vid[i] = off;   off += align256(4 * nvox);
         L.bsum[i] = off;  off += align256(8 * ((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS));
@@ -97,7 +99,7 @@ bool plan(const mc_problem* probs, int n, Layout& L) {
 }
 
 ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64_t tally_offset,
-                   int brick_log2) {
+                   int brick_log2, int threshold_bytes) {
     ProbDesc d;
     std::memset(&d, 0, sizeof(d));
     d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.source_mode = p.source_mode;
@@ -131,6 +133,9 @@ ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64
     d.tally_offset = tally_offset;
     d.mu = p.mu140; d.act = p.activity; d.angles = p.angle_rad;
     d.q32 = (uint32_t*)(ws + L.q[i]);
+    d.q8 = (uint8_t*)(ws + L.q8[i]);
+    d.palette = (uint32_t*)(ws + L.pal[i]);
+    d.pal_state = threshold_bytes == 4 ? 1u : 0u;
     d.cdf = (uint64_t*)(ws + L.cdf[i]);
     d.vox_id = (uint32_t*)(ws + L.vid[i]);
     d.block_sums = (uint64_t*)(ws + L.bsum[i]);
@@ -146,23 +151,26 @@ int hip_fail(hipError_t e) {
     return MC_EDEVICE;
 }
 
-void resolve(const mc_options* opt, int& block, int& hpl, int& bpc, int& brick) {
+void resolve(const mc_options* opt, int& block, int& hpl, int& bpc, int& brick, int& qbytes) {
     block = DEFAULT_BLOCK;
     hpl = DEFAULT_HIST_PER_LANE;
     bpc = 0;
     brick = 0;
+    qbytes = 0;
     if (opt) {
         if (opt->block_size > 0) block = opt->block_size;
         if (opt->hist_per_lane > 0) hpl = opt->hist_per_lane;
         if (opt->blocks_per_cu > 0) bpc = opt->blocks_per_cu;
         if (opt->brick_log2 > 0) brick = opt->brick_log2;
+        qbytes = opt->threshold_bytes;
     }
 }
 
-bool options_ok(int block, int hpl, int brick) {
+bool options_ok(int block, int hpl, int brick, int qbytes) {
     if (block < 64 || block > 256 || block % 64 != 0) return false;
     if (hpl < 1 || hpl > (1 << 20)) return false;
     if (brick < 0 || brick > MAX_BRICK_LOG2 || brick == 1) return false;
+    if (qbytes != 0 && qbytes != 1 && qbytes != 4) return false;
     return true;
 }
 
@@ -186,9 +194,9 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     if (!problems || n_problems < 1 || !tally || !fates || !status || !workspace) return MC_EINVAL;
     if (events && !n_events) return MC_EINVAL;
     for (int i = 0; i < n_problems; ++i) if (!check_problem(problems[i])) return MC_EINVAL;
-    int block, hpl, bpc, brick;
-    resolve(opt, block, hpl, bpc, brick);
-    if (!options_ok(block, hpl, brick)) return MC_EINVAL;
+    int block, hpl, bpc, brick, qbytes;
+    resolve(opt, block, hpl, bpc, brick, qbytes);
+    if (!options_ok(block, hpl, brick, qbytes)) return MC_EINVAL;
     Layout L;
     plan(problems, n_problems, L);
     if (workspace_bytes < L.total) return MC_ENOMEM;
@@ -198,7 +206,7 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     uint64_t tally_elems = 0;
     for (int i = 0; i < n_problems; ++i) {
         const mc_problem& p = problems[i];
-        const ProbDesc h = host_desc(p, ws, L, i, tally_elems, brick);
+        const ProbDesc h = host_desc(p, ws, L, i, tally_elems, brick, qbytes);
         tally_elems += (uint64_t)p.n_views * 2 * p.nv * p.nu;
         hipError_t e = launch_staging(d_desc + i, h, st);
         if (e != hipSuccess) return hip_fail(e);
@@ -245,16 +253,16 @@ int mc_replay_histories(const mc_problem* problem, const mc_options* opt, const 
     if (!problem || !status || !workspace || n < 0) return MC_EINVAL;
     if (n > 0 && (!views || !hists || !records)) return MC_EINVAL;
     if (!check_problem(*problem)) return MC_EINVAL;
-    int block, hpl, bpc, brick;
-    resolve(opt, block, hpl, bpc, brick);
-    if (!options_ok(block, hpl, brick)) return MC_EINVAL;
+    int block, hpl, bpc, brick, qbytes;
+    resolve(opt, block, hpl, bpc, brick, qbytes);
+    if (!options_ok(block, hpl, brick, qbytes)) return MC_EINVAL;
     Layout L;
     plan(problem, 1, L);
     if (workspace_bytes < L.total) return MC_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)workspace;
     ProbDesc* d_desc = (ProbDesc*)(ws + L.desc);
-    const ProbDesc h = host_desc(*problem, ws, L, 0, 0, brick);
+    const ProbDesc h = host_desc(*problem, ws, L, 0, 0, brick, qbytes);
     hipError_t e = launch_staging(d_desc, h, st);
     if (e != hipSuccess) return hip_fail(e);
     e = launch_replay(d_desc, views, hists, n, records, status, block, st);
@@ -270,16 +278,16 @@ int mc_adjoint_mu(const mc_problem* problem, const mc_options* opt, const double
     if (events && !n_events) return MC_EINVAL;
     if (frac_bits < 0 || frac_bits > 62) return MC_EINVAL;
     if (!check_problem(*problem)) return MC_EINVAL;
-    int block, hpl, bpc, brick;
-    resolve(opt, block, hpl, bpc, brick);
-    if (!options_ok(block, hpl, brick)) return MC_EINVAL;
+    int block, hpl, bpc, brick, qbytes;
+    resolve(opt, block, hpl, bpc, brick, qbytes);
+    if (!options_ok(block, hpl, brick, qbytes)) return MC_EINVAL;
     Layout L;
     plan(problem, 1, L);
     if (workspace_bytes < L.total) return MC_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)workspace;
     ProbDesc* d_desc = (ProbDesc*)(ws + L.desc);
-    const ProbDesc h = host_desc(*problem, ws, L, 0, 0, brick);
+    const ProbDesc h = host_desc(*problem, ws, L, 0, 0, brick, qbytes);
     hipError_t e = launch_staging(d_desc, h, st);
     if (e != hipSuccess) return hip_fail(e);
     int dev = 0, n_cu = 0;

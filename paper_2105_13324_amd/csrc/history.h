@@ -48,6 +48,23 @@ __device__ __forceinline__ float unif(uint32_t r) {
     return fmaf((float)(r >> 9), 0x1p-23f, 0x1p-24f);
 }
 
+// Load through a global (address space 1) pointer: a global_load, where a
+// flat load of a pointer read from the descriptor would also wait on LDS.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+__device__ __forceinline__ uint4 ldg(const uint4* p) {
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const v4u v = *(const __attribute__((address_space(1))) v4u*)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ldg(const float2* p) {
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    const v2f v = *(const __attribute__((address_space(1))) v2f*)p;
+    return make_float2(v.x, v.y);
+}
+
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrtf_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
 // sin(2 pi u), cos(2 pi u): the hardware instructions take revolutions.
@@ -62,6 +79,8 @@ constexpr float KN_TABLE_STEP_INV = 4.0f;
 struct Cst {
     const float* mu;
     const uint32_t* q32;
+    const uint8_t* q8;
+    const uint32_t* pal;
     const uint64_t* cdf;
     const uint32_t* vox_id;
     const uint4* guide;
@@ -74,7 +93,7 @@ struct Cst {
     float f_pe, mu_hat, inv_mm140, p_pe140;
     uint32_t seed, pid, max_steps, shift;
     uint64_t total, q_per_view, r_extra, work_begin, tally_offset;
-    uint32_t flags;
+    uint32_t flags, use_pal;
     int brick;
     uint32_t bmask, nbx, nby;
 };
@@ -82,7 +101,7 @@ struct Cst {
 __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     Cst c;
     c.mu = d->mu;
-    c.q32 = d->q32; c.cdf = d->cdf; c.vox_id = d->vox_id; c.guide = d->guide; c.views = d->views;
+    c.q32 = d->q32; c.q8 = d->q8; c.pal = d->palette; c.cdf = d->cdf; c.vox_id = d->vox_id; c.guide = d->guide; c.views = d->views;
     c.kn_table = d->kn_table;
     c.nx = d->nx; c.ny = d->ny; c.nz = d->nz; c.source_mode = d->source_mode;
     c.hx = d->hx; c.hy = d->hy; c.hz = d->hz;
@@ -100,6 +119,7 @@ __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     c.total = d->total; c.q_per_view = d->q_per_view; c.r_extra = d->r_extra;
     c.work_begin = d->work_begin; c.tally_offset = d->tally_offset;
     c.flags = d->flags;
+    c.use_pal = d->pal_state == 0;
     c.brick = d->brick_log2;
     c.bmask = (1u << c.brick) - 1u;
     c.nbx = (uint32_t)d->nbx; c.nby = (uint32_t)d->nby;
@@ -114,7 +134,7 @@ __device__ inline float energy_terms(const Cst& C, float e, float& inv_mm, float
     const float t = (140.0f - e) * KN_TABLE_STEP_INV;
     const int i = (int)t;
     const float fr = t - (float)i;
-    const float k0 = C.kn_table[i], k1 = C.kn_table[i + 1];
+    const float k0 = ldg(C.kn_table + i), k1 = ldg(C.kn_table + i + 1);
     const float kn = fmaf(fr, k1 - k0, k0);
     const float x = 140.0f * rcpf(e);
     const float pe = C.f_pe * x * x * x;
@@ -258,16 +278,16 @@ __device__ inline Emission emit_history(const Cst& C, uint32_t hist, uint32_t vi
     const uint64_t R = ((uint64_t)a0 << 32) | a1;
     const uint64_t t = __umul64hi(R, C.total);
     const uint64_t b = t >> C.shift;
-    const uint4 g = C.guide[b];
+    const uint4 g = ldg(C.guide + b);
     uint32_t packed;                        // ix | iy << 10 | iz << 20
     if (g.x & BUCKET_WIDE) {
         // the bucket spans three or more voxels: search its CDF slots
         uint32_t lo = g.y, hi = g.z;
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (C.cdf[mid] > t) hi = mid; else lo = mid + 1;
+            if (ldg(C.cdf + mid) > t) hi = mid; else lo = mid + 1;
         }
-        packed = C.vox_id[lo];
+        packed = ldg(C.vox_id + lo);
     } else {
         const uint64_t split = ((uint64_t)g.w << 32) | g.z;
         packed = (t - (b << C.shift)) < split ? g.x : g.y;
@@ -302,15 +322,16 @@ __device__ inline void begin_history(const Cst& C, Lane& L, uint32_t view, uint3
     L.e = 140.0f;
     L.inv_mm = C.inv_mm140;
     L.p_pe = C.p_pe140;
-    const float2 cs = C.views[view];
+    const float2 cs = ldg(C.views + view);
     L.vc = cs.x; L.vs = cs.y;
 }
 
 // One iteration of a lane's history (tentative collision or Kahn attempt)
 // given its Philox words.  Returns the fate when the history ends (iu/iv set
-// for escapes), else R_RUNNING.
-__device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, uint32_t w2,
-                              uint32_t w3, Acc& A, int& iu, int& iv) {
+// for escapes), else R_RUNNING.  pal: the problem's threshold palette (global,
+// or a copy in LDS), read when C.use_pal.
+__device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32_t w0, uint32_t w1,
+                              uint32_t w2, uint32_t w3, Acc& A, int& iu, int& iv) {
     if (L.state == S_STEP) {
         L.n += 1;
         if (L.n > C.max_steps) {
@@ -329,8 +350,9 @@ __device__ inline int advance(const Cst& C, Lane& L, uint32_t w0, uint32_t w1, u
         const int ix = min((int)(tx * C.inv_vox), C.nx - 1);
         const int iy = min((int)(ty * C.inv_vox), C.ny - 1);
         const int iz = min((int)(tz * C.inv_vox), C.nz - 1);
-        const uint32_t q = C.q32[brick_index((uint32_t)ix, (uint32_t)iy, (uint32_t)iz, (uint32_t)C.nx,
-                                             (uint32_t)C.ny, C.brick, C.bmask, C.nbx, C.nby)];
+        const uint32_t k = brick_index((uint32_t)ix, (uint32_t)iy, (uint32_t)iz, (uint32_t)C.nx,
+                                       (uint32_t)C.ny, C.brick, C.bmask, C.nbx, C.nby);
+        const uint32_t q = C.use_pal ? pal[ldg(C.q8 + k)] : ldg(C.q32 + k);
         L.x = xn; L.y = yn; L.z = zn;
         if ((w1 >> 8) < q) {
             A.n_real++;

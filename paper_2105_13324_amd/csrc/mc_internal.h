@@ -35,7 +35,9 @@ struct ProbDesc {
     const float* mu;
     const uint32_t* act;
     const double* angles;
-    uint32_t* q32;                  // accept thresholds, linear layout
+    uint32_t* q32;                  // accept thresholds (linear or bricked layout)
+    uint8_t* q8;                    // palette codes, same layout (when pal_state == 0)
+    uint32_t* palette;              // PALETTE_N thresholds, open-addressing hash table
     uint64_t* cdf;                  // inclusive prefix sum of activity over active voxels
     uint32_t* vox_id;               // voxel index of each active voxel, in grid order
     uint64_t* block_sums;           // scan scratch: activity per block
@@ -50,7 +52,8 @@ struct ProbDesc {
     uint32_t shift;                 // bucket = t >> shift
     uint32_t n_buckets;
     uint32_t n_active;              // voxels with activity > 0
-    uint32_t pad1;
+    uint32_t pal_state;             // 0: palette in use; 1: 32-bit thresholds (host request
+                                    // or more than PALETTE_N distinct values, set by staging)
 };
 
 // Emission bucket b covers t in [b << shift, (b + 1) << shift) of the integer
@@ -60,6 +63,12 @@ struct ProbDesc {
 //     below which x is taken (all ones when both are the same voxel);
 //   wide (x = BUCKET_WIDE): the slots of the CDF search are [y, z].
 constexpr uint32_t BUCKET_WIDE = 0x80000000u;
+
+// Threshold palette: a 256-slot open-addressing table keyed by Q (Q <= 2^24,
+// so the all-ones word marks an empty slot); a voxel's code is its slot.
+constexpr int PALETTE_N = 256;
+constexpr uint32_t PALETTE_EMPTY = 0xFFFFFFFFu;
+__host__ __device__ inline uint32_t palette_hash(uint32_t q) { return (q * 2654435761u) >> 24; }
 
 constexpr int SCAN_ITEMS = 4096;    // activity values per scan block
 constexpr int KN_TABLE_N = 568;     // entries of the Klein-Nishina shape table (>= 4*140 + 2)

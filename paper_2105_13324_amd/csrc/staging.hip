@@ -4,11 +4,16 @@
 //  * max mu, input validation and the activity total (one reduction pass);
 //  * accept thresholds Q_v = ceil(mu_v 2^24 / max mu) in double precision, so
 //    the real/virtual decision of Woodcock tracking is an exact integer compare;
+//    when the map has at most 256 distinct thresholds (segmented phantoms have
+//    a handful) also one-byte codes into a palette of them, a table a quarter
+//    the size that stays in L2;
 //  * the inclusive prefix sum of activity (uint64) over the active voxels only,
-//    their voxel indices, and a guide table over the high bits of the sum with
-//    about two buckets per active voxel, so an emission voxel is found with a
-//    guide gather, rarely a probe, and an index gather (Chen & Asau 1974 guide
-//    tables; the same voxel as a plain inverse-CDF search over all voxels);
+//    their voxel indices, and a table of buckets over the high bits of the sum
+//    with about two buckets per active voxel (after the guide tables of Chen &
+//    Asau 1974); a bucket that meets at most two voxels holds their packed
+//    coordinates and split point, so an emission voxel is one 16-byte gather,
+//    rarely a short CDF search (the same voxel as a plain inverse-CDF search
+//    over all voxels);
 //  * (cos, sin) of each view angle;
 //  * the Klein-Nishina attenuation shape sigma_KN(E)/sigma_KN(140) at 1/4 keV
 //    steps, evaluated in double precision.
@@ -57,12 +62,23 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* pd) {
     mx = wave_max_u32(mx);
     flags = wave_or_u32(flags);
     sum = wave_sum_u64(sum);
-    if ((threadIdx.x & 63) == 0) {
+    // one atomic per block: same-address atomics serialise in L2
+    __shared__ uint32_t s_mx[RED_THREADS / 64], s_fl[RED_THREADS / 64];
+    __shared__ uint64_t s_sum[RED_THREADS / 64];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { s_mx[w] = mx; s_fl[w] = flags; s_sum[w] = sum; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < RED_THREADS / 64; ++k) {
+            mx = max(mx, s_mx[k]); flags |= s_fl[k]; sum += s_sum[k];
+        }
         atomicMax(&pd->mu_hat_bits, mx);
         if (flags) atomicOr(&pd->flags, flags);
         atomicAdd((unsigned long long*)&pd->total, (unsigned long long)sum);
     }
     if (blockIdx.x == 0) {
+        if (pd->pal_state == 0)
+            for (int k = threadIdx.x; k < PALETTE_N; k += blockDim.x) pd->palette[k] = PALETTE_EMPTY;
         for (int k = threadIdx.x; k < pd->n_views; k += blockDim.x) {
             const double a = pd->angles[k];
             if (!isfinite(a)) atomicOr(&pd->flags, (uint32_t)MC_STATUS_BAD_ANGLE);
@@ -71,9 +87,22 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* pd) {
     }
 }
 
+// Slot of q in the palette, inserting it if absent; PALETTE_N when full.
+__device__ inline uint32_t palette_insert(uint32_t* pal, uint32_t q) {
+    uint32_t h = palette_hash(q);
+    for (int probe = 0; probe < PALETTE_N; ++probe, h = (h + 1) & (PALETTE_N - 1)) {
+        uint32_t cur = __hip_atomic_load(pal + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == PALETTE_EMPTY) cur = atomicCAS(pal + h, PALETTE_EMPTY, q);
+        if (cur == PALETTE_EMPTY || cur == q) return h;
+    }
+    return PALETTE_N;
+}
+
 // Q_v in double precision: mu_v * 2^24 is exact, the division is correctly
 // rounded, ceil is exact.  Stored linear (b = 0) or in 2^b-voxel cubic bricks,
 // so a brick is a few whole cache lines (the layout never changes a result).
+// Each distinct Q also goes into the palette: a wavefront inserts each of its
+// distinct values once (leader lane), so the table sees few atomics.
 __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* pd) {
     const uint64_t nvox = pd->nvox;
     const float mu_hat = __uint_as_float(pd->mu_hat_bits);
@@ -83,6 +112,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* pd) {
     const int b = pd->brick_log2;
     const uint32_t m = (1u << b) - 1u;
     const uint32_t nbx = (uint32_t)pd->nbx, nby = (uint32_t)pd->nby;
+    const bool pal = pd->pal_state == 0;
+    bool full = false;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const float mv = mu[i];
@@ -93,6 +124,42 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* pd) {
         }
         const uint32_t ix = (uint32_t)(i % nx), iy = (uint32_t)((i / nx) % ny), iz = (uint32_t)(i / ((uint64_t)nx * ny));
         q[brick_index(ix, iy, iz, nx, ny, b, m, nbx, nby)] = v;
+        if (pal && !full) {
+            bool todo = true;
+            for (;;) {
+                const uint64_t left = __ballot(todo);
+                if (left == 0) break;
+                const int leader = __ffsll((unsigned long long)left) - 1;
+                const uint32_t lv = (uint32_t)__shfl((int)v, leader, 64);
+                if ((int)(threadIdx.x & 63) == leader && palette_insert(pd->palette, lv) == PALETTE_N)
+                    full = true;
+                if (v == lv) todo = false;
+            }
+        }
+    }
+    if (full) atomicOr(&pd->pal_state, 1u);
+}
+
+// One-byte palette codes in the threshold layout (skipped when the palette
+// overflowed or was not requested: the kernels then read the 32-bit table).
+__global__ __launch_bounds__(RED_THREADS) void k_codes(ProbDesc* pd) {
+    if (pd->pal_state != 0) return;
+    const uint64_t nvox = pd->nvox;
+    const uint32_t* __restrict__ q = pd->q32;
+    const uint32_t* __restrict__ pal = pd->palette;
+    uint8_t* __restrict__ code = pd->q8;
+    const uint32_t nx = (uint32_t)pd->nx, ny = (uint32_t)pd->ny;
+    const int b = pd->brick_log2;
+    const uint32_t m = (1u << b) - 1u;
+    const uint32_t nbx = (uint32_t)pd->nbx, nby = (uint32_t)pd->nby;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t ix = (uint32_t)(i % nx), iy = (uint32_t)((i / nx) % ny), iz = (uint32_t)(i / ((uint64_t)nx * ny));
+        const uint32_t k = brick_index(ix, iy, iz, nx, ny, b, m, nbx, nby);
+        const uint32_t v = q[k];
+        uint32_t h = palette_hash(v);
+        for (int probe = 0; probe < PALETTE_N && pal[h] != v; ++probe) h = (h + 1) & (PALETTE_N - 1);
+        code[k] = (uint8_t)h;
     }
 }
 
@@ -302,8 +369,9 @@ uint64_t guide_capacity(uint64_t nvox) {
 hipError_t launch_staging(ProbDesc* d, const ProbDesc& h, hipStream_t st) {
     const uint64_t nvox = h.nvox;
     k_write_desc<<<1, 64, 0, st>>>(h, d);
-    k_reduce<<<grid_for(nvox, RED_THREADS, 2048), RED_THREADS, 0, st>>>(d);
+    k_reduce<<<grid_for(nvox, RED_THREADS, 512), RED_THREADS, 0, st>>>(d);
     k_thresholds<<<grid_for(nvox, RED_THREADS, 8192), RED_THREADS, 0, st>>>(d);
+    k_codes<<<grid_for(nvox, RED_THREADS, 8192), RED_THREADS, 0, st>>>(d);
     const int nb = (int)((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS);
     k_scan_sums<<<nb, SCAN_THREADS, 0, st>>>(d);
     k_scan_top<<<1, 1024, 0, st>>>(d, nb);

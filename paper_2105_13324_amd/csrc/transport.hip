@@ -98,8 +98,10 @@ struct EmitRec {
 // the per-lane loop only alternates tentative collisions and Kahn attempts.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TransportArgs T) {
     __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
+    __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
     const int lane = threadIdx.x & 63;
     EmitRec* __restrict__ my = stage[threadIdx.x >> 6];
+    uint32_t* __restrict__ my_pal = pal_copy[threadIdx.x >> 6];
     const uint64_t lane_lt = (1ull << lane) - 1ull;
     const uint64_t full = __ballot(1);   // lanes of this wavefront
     // chunk bookkeeping (wave-uniform): problem-local work range [c_next, c_end)
@@ -152,6 +154,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                                 if (p >= 0) flush(A, fc, p, T, lane);
                                 p = np;
                                 C = load_cst(T.descs + p);
+                                if (C.use_pal) {
+                                    // the wave is drained: no lane reads the old palette
+#pragma unroll
+                                    for (int k = 0; k < PALETTE_N / 64; ++k)
+                                        my_pal[k * 64 + lane] = ldg(C.pal + k * 64 + lane);
+                                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                                    __builtin_amdgcn_wave_barrier();
+                                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                                }
                             }
                             const uint64_t local_chunk = pending - chunk_prefix[p];
                             const uint64_t cnt = T.work_prefix[p + 1] - T.work_prefix[p];
@@ -212,7 +223,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
             counter_of(L, c2, c3);
             philox10(c0, c1, c2, c3, C.seed, C.pid);
-            fate = advance(C, L, c0, c1, c2, c3, A, iu, iv);
+            fate = advance(C, my_pal, L, c0, c1, c2, c3, A, iu, iv);
             if (fate != R_RUNNING) book_energy(A, fate, L.e);
         }
         if (__ballot(fate != R_RUNNING) != 0) {
@@ -269,7 +280,7 @@ __global__ __launch_bounds__(256) void k_replay(const ProbDesc* __restrict__ d,
             counter_of(L, c2, c3);
             philox10(c0, c1, c2, c3, C.seed, C.pid);
             int iu = -1, iv = -1;
-            const int fate = advance(C, L, c0, c1, c2, c3, A, iu, iv);
+            const int fate = advance(C, C.pal, L, c0, c1, c2, c3, A, iu, iv);
             if (fate != R_RUNNING) {
                 r.fate = fate;
                 r.iu = iu;
@@ -329,9 +340,14 @@ __global__ void k_finalize(const ProbDesc* __restrict__ descs, int n_problems, i
                            const unsigned long long* n_events, uint64_t capacity) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     uint64_t f = 0;
-    for (int p = 0; p < n_problems; ++p) f |= descs[p].flags;
+    int64_t n_pal = 0;
+    for (int p = 0; p < n_problems; ++p) {
+        f |= descs[p].flags;
+        n_pal += descs[p].pal_state == 0;
+    }
     if (n_events && capacity != UINT64_MAX && *n_events > capacity) f |= MC_STATUS_LIST_OVERFLOW;
     status[0] |= (int64_t)f;
+    status[2] = n_pal;
 }
 
 __global__ void k_zero_status(int64_t* status) {

@@ -188,12 +188,48 @@ def test_run_to_run_and_option_independence():
     t0 = ref.tally.clone()
     f0 = ref.fates.clone()
     e0 = ref.energy.clone()
+    assert int(ref.check_status()[2]) == 1          # segmented map: one-byte palette codes
     for opts in (None, {"hist_per_lane": 1}, {"hist_per_lane": 64, "block_size": 64},
-                 {"block_size": 128, "blocks_per_cu": 1}, {"hist_per_lane": 5, "blocks_per_cu": 3}):
+                 {"block_size": 128, "blocks_per_cu": 1}, {"hist_per_lane": 5, "blocks_per_cu": 3},
+                 {"threshold_bytes": 4}, {"threshold_bytes": 4, "brick_log2": 3},
+                 {"threshold_bytes": 1, "brick_log2": 2}):
         s = mc.simulate(dp, options=opts)
+        want_pal = 0 if (opts or {}).get("threshold_bytes") == 4 else 1
+        assert int(s.check_status()[2]) == want_pal, opts
         assert bool((s.tally == t0).all()), opts
         assert bool((s.fates == f0).all()), opts
         assert bool((s.energy == e0).all()), opts
+
+
+@pytest.mark.parametrize("n_distinct", [256, 257])
+def test_threshold_palette_capacity(n_distinct):
+    """A water cube whose voxels take n_distinct attenuation values (+/-30 %):
+    256 distinct thresholds still fit the one-byte palette, 257 fall back to
+    the 32-bit table.  Either way the histories match the oracle and the
+    forced 32-bit run bit for bit."""
+    mc = _mc()
+    n = 32
+    p = phantoms.point_source_cube(f"pal{n_distinct}", n, 0.6, 400_000, seed=5).with_(
+        angles=phantoms.view_angles(8, 180.0), nu=32, nv=32, pixel_cm=1.2)
+    rng = np.random.Generator(np.random.PCG64(n_distinct))
+    levels = (phantoms.MU_WATER_140 * (0.7 + 0.6 * np.arange(n_distinct) / (n_distinct - 1))).astype(np.float32)
+    mu = levels[rng.integers(0, n_distinct, size=(n, n, n))]
+    mu.ravel()[:n_distinct] = levels                  # every level present
+    act = rng.integers(0, 3, size=(n, n, n)).astype(np.uint32)
+    p = p.with_(mu=mu, activity=act, source_mode=phantoms.SOURCE_VOXELS)
+    dp = mc.to_device(p)
+    a = mc.simulate(dp)
+    b = mc.simulate(dp, options={"threshold_bytes": 4})
+    assert int(a.check_status()[2]) == (1 if n_distinct <= 256 else 0)
+    assert int(b.check_status()[2]) == 0
+    for x, y in zip(outputs_of(a), outputs_of(b)):
+        np.testing.assert_array_equal(x, y)
+    replay_parity(p, n=20_000, seed=n_distinct)
+
+
+def outputs_of(sim):
+    return (sim.tally.cpu().numpy(), sim.fates.cpu().numpy(), sim.energy.cpu().numpy(),
+            sim.counters.cpu().numpy())
 
 
 def test_resume_ranges_sum_exactly():

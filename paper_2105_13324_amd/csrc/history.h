@@ -17,6 +17,7 @@ namespace {
 constexpr uint32_t KAHN_MAX = 64;
 constexpr float MEC2_F = 510.99895f;
 constexpr float INV_MEC2 = (float)(1.0 / 510.99895);
+constexpr float LN2_F = 0.693147180559945f;
 
 enum : int { S_IDLE = 0, S_STEP = 3, S_KAHN = 4 };
 
@@ -90,7 +91,7 @@ struct Cst {
     float hx, hy, hz, lx, ly, lz, inv_vox, vox;
     int nu, nv, n_views;
     float inv_pix, radius, cos_alpha, wu, wv, e_lo, e_hi, e_cut;
-    float f_pe, mu_hat, inv_mm140, p_pe140;
+    float f_pe, mu_hat, ln2_mm140, p_pe140;
     uint32_t seed, pid, max_steps, shift;
     uint64_t total, q_per_view, r_extra, work_begin, tally_offset;
     uint32_t flags, use_pal;
@@ -113,7 +114,7 @@ __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     c.f_pe = d->f_pe;
     c.mu_hat = __uint_as_float(d->mu_hat_bits);
     // g(140 keV) = 1 by construction: mu_max(140) = max mu, p_pe(140) = f.
-    c.inv_mm140 = (float)(1.0 / (double)c.mu_hat);
+    c.ln2_mm140 = (float)(0.69314718055994531 / (double)c.mu_hat);
     c.p_pe140 = c.f_pe;
     c.seed = d->seed; c.pid = d->problem_id; c.max_steps = d->max_steps; c.shift = d->shift;
     c.total = d->total; c.q_per_view = d->q_per_view; c.r_extra = d->r_extra;
@@ -127,10 +128,11 @@ __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
 }
 
 // Attenuation at energy e relative to 140 keV, g(E) = (1-f) KN(E)/KN(140) +
-// f (140/E)^3, its majorant reciprocal 1/(max mu g) and the photoelectric
-// share f (140/E)^3 / g.  The KN ratio is linearly interpolated (error below
-// 1e-6 relative over the table range), the photoelectric term is exact.
-__device__ inline float energy_terms(const Cst& C, float e, float& inv_mm, float& p_pe) {
+// f (140/E)^3, the flight scale ln2/(max mu g) (a flight is -log2(u) times
+// it, with the hardware log2) and the photoelectric share f (140/E)^3 / g.
+// The KN ratio is linearly interpolated (error below 1e-6 relative over the
+// table range), the photoelectric term is exact.
+__device__ inline float energy_terms(const Cst& C, float e, float& ln2_mm, float& p_pe) {
     const float t = (140.0f - e) * KN_TABLE_STEP_INV;
     const int i = (int)t;
     const float fr = t - (float)i;
@@ -140,7 +142,7 @@ __device__ inline float energy_terms(const Cst& C, float e, float& inv_mm, float
     const float pe = C.f_pe * x * x * x;
     const float g = fmaf(1.0f - C.f_pe, kn, pe);
     const float ig = rcpf(g);
-    inv_mm = rcpf(C.mu_hat * g);
+    ln2_mm = LN2_F * rcpf(C.mu_hat * g);
     p_pe = pe * ig;
     return g;
 }
@@ -150,7 +152,7 @@ struct Lane {
     int view, state;
     uint32_t n, a, phi_word, emit_voxel;
     int n_scatter;
-    float x, y, z, dx, dy, dz, e, inv_mm, p_pe, vc, vs;
+    float x, y, z, dx, dy, dz, e, ln2_mm, p_pe, vc, vs;
 };
 
 // Per-lane work counters and energies of one problem (reduced across the
@@ -320,7 +322,7 @@ __device__ inline void begin_history(const Cst& C, Lane& L, uint32_t view, uint3
     L.x = e.x; L.y = e.y; L.z = e.z;
     L.dx = e.dx; L.dy = e.dy; L.dz = e.dz;
     L.e = 140.0f;
-    L.inv_mm = C.inv_mm140;
+    L.ln2_mm = C.ln2_mm140;
     L.p_pe = C.p_pe140;
     const float2 cs = ldg(C.views + view);
     L.vc = cs.x; L.vs = cs.y;
@@ -339,7 +341,7 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
             return MC_CAPPED_FATE;
         }
         A.n_tent++;
-        const float s = -__logf(unif(w0)) * L.inv_mm;
+        const float s = -__builtin_amdgcn_logf(unif(w0)) * L.ln2_mm;
         const float xn = fmaf(s, L.dx, L.x);
         const float yn = fmaf(s, L.dy, L.y);
         const float zn = fmaf(s, L.dz, L.z);
@@ -393,7 +395,7 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
         L.n_scatter += 1;
         rotate(L, ct, unif(L.phi_word));
         if (L.e < C.e_cut) return MC_CUT;
-        energy_terms(C, L.e, L.inv_mm, L.p_pe);
+        energy_terms(C, L.e, L.ln2_mm, L.p_pe);
         L.state = S_STEP;
         return R_RUNNING;
     }

@@ -115,7 +115,9 @@ typedef struct {
                                 /* 1: one-byte codes into a 256-entry palette   */
                                 /* when the map has at most 256 distinct        */
                                 /* thresholds (else 4); 4: always 32-bit        */
-    int32_t reserved;           /* set to 0                                     */
+    int32_t forced_detection;   /* mc_simulate_projections only: 1 = the tally  */
+                                /* is the forced-detection estimate (Sec. 5.2)  */
+                                /* instead of analog arrivals; 0 = analog       */
     void* kernel_events[2];     /* optional hipEvent_t pair recorded on the     */
                                 /* stream right before / after the transport    */
                                 /* kernel (NULL: none)                          */
@@ -161,7 +163,21 @@ size_t mc_workspace_bytes(const mc_problem* problems, int32_t n_problems,
  *              [2] problems whose thresholds were read as one-byte palette
  *              codes (see mc_options.threshold_bytes)
  *   workspace  device, at least mc_workspace_bytes(...)
- * Results are bit-identical from run to run and independent of the options. */
+ * Results are bit-identical from run to run and independent of the options
+ * (apart from forced_detection, which changes what the tally estimates).
+ *
+ * Forced detection (opt->forced_detection = 1; Sec. 5.2): the analog
+ * histories run unchanged (fates, energies and counters are theirs), but the
+ * tally is scored by forced copies: at each history's emission point (class
+ * 0) and at each real collision (class 1) a copy leaves in a direction drawn
+ * uniformly in the collimator cone (Philox event of the point, sub-draw
+ * 0x80000000) with weight Omega_cone * pdf * exp(-g(E') * integral of mu140
+ * along the ray to the grid edge), pdf = 1/(4 pi) at emission and
+ * (1 - p_pe(E)) times the Klein-Nishina angular density at a collision; no
+ * score when E' is cut, outside the window or the ray misses the detector.
+ * The expected score of every bin equals its expected analog count.  The
+ * tally stays Q31.32; tally_sq holds the sum of squared scores in Q11.52.
+ * Events must be NULL (MC_EINVAL otherwise). */
 int mc_simulate_projections(const mc_problem* problems, int32_t n_problems,
                             const mc_options* opt,
                             int64_t* tally, int64_t* tally_sq, int64_t* fates,

@@ -91,6 +91,10 @@ def _load():
         lib.orc_simulate.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(_Result),
                                      P(C.c_int64), P(C.c_int64), P(C.c_int64), C.c_uint64,
                                      P(C.c_uint64)]
+        lib.orc_simulate_fd.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(_Result)]
+        lib.orc_kn_pdf.argtypes = [C.c_double, C.c_double]
+        lib.orc_kn_pdf.restype = C.c_double
+        lib.orc_ray_integral.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(C.c_double)]
         lib.orc_replay.argtypes = [P(_Problem), P(C.c_int32), P(C.c_uint64), C.c_int64, C.c_void_p]
         lib.orc_adjoint.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(C.c_int64),
                                     C.c_int32, P(C.c_int32), C.c_double, P(C.c_double),
@@ -223,6 +227,43 @@ def simulate(prob, n_threads: int = 0, want_triplets: bool = False, trip_cap: in
         out["trip_j"] = tj[:n].copy()
         out["trip_g"] = tg[:n].copy()
     return out
+
+
+def simulate_fd(prob, n_threads: int = 0):
+    """Forced-detection forward simulation (Sec. 5.2): the analog histories'
+    fates, energies and counters, and the forced-detection tally and the sum
+    of squared scores ([V,2,nv,nu], FP64)."""
+    lib = _load()
+    p, keep = _make_problem(prob, n_threads)
+    tally = np.zeros(prob.tally_shape, dtype=np.float64)
+    tsq = np.zeros(prob.tally_shape, dtype=np.float64)
+    res = _Result()
+    rc = lib.orc_simulate_fd(C.byref(p), _ptr(tally, C.c_double), _ptr(tsq, C.c_double),
+                             C.byref(res))
+    if rc != 0:
+        raise RuntimeError(f"orc_simulate_fd failed ({rc})")
+    out = _result_dict(res)
+    out["tally"] = tally
+    out["tally_sq"] = tsq
+    return out
+
+
+def kn_pdf(e_kev: float, cos_t: float) -> float:
+    """Klein-Nishina angular density per steradian at e_kev."""
+    return _load().orc_kn_pdf(float(e_kev), float(cos_t))
+
+
+def ray_integral(prob, x, d) -> float:
+    """Integral of the 140 keV attenuation map from point x along unit d to
+    the grid edge."""
+    lib = _load()
+    p, keep = _make_problem(prob)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = C.c_double(0.0)
+    if lib.orc_ray_integral(C.byref(p), _ptr(x, C.c_double), _ptr(d, C.c_double), C.byref(out)) != 0:
+        raise RuntimeError("orc_ray_integral failed")
+    return out.value
 
 
 def replay(prob, views: np.ndarray, hists: np.ndarray, n_threads: int = 0) -> np.ndarray:

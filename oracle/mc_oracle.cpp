@@ -16,7 +16,11 @@
 //    photon emitted in source voxel i is counted in projection bin j (Sec. 5.1,
 //    Eq. IMC);
 //  * the path-frozen likelihood-ratio gradient of the tallies with respect to
-//    the attenuation map, and its finite-difference check.
+//    the attenuation map, and its finite-difference check;
+//  * forced detection (Sec. 5.2): at emission and at every interaction a copy
+//    forced to the detector, weighted by the probabilities of not being
+//    absorbed there, of leaving in a direction the collimator passes and of
+//    crossing the rest of the object.
 //
 // The paper gives no cross-section model, tracking scheme, sampler or random
 // number generator.  The readings used here:
@@ -259,8 +263,87 @@ void rotate(double d[3], double cos_t, double phi) {
     }
 }
 
+void segment_voxels(const Setup& s, const double a[3], const double b[3],
+                    std::vector<std::pair<size_t, double>>& out);
+
+// ---------------------------------------------------------------------------
+// Forced detection (Sec. 5.2).  At the emission point and at every real
+// collision a copy of the photon is forced towards this view's detector and
+// scored with the weight the paper lists: the probability that it is not
+// absorbed at the point, that it leaves in a direction the collimator passes,
+// and that it crosses the rest of the object without interacting.  The
+// direction is drawn uniformly in the collimator cone (Philox event of the
+// point, sub-draw FD_SUB, words 0 and 1), so
+//   w = Omega_cone * pdf(direction) * exp(-g(E') * integral of mu140 on the ray)
+// with pdf = 1/(4 pi) at emission and (1 - p_pe(E)) * Klein-Nishina angular pdf
+// at a collision, and the expected score equals the expected analog count in
+// every bin.  A copy whose energy would be cut or falls outside the window, or
+// that misses the detector, scores nothing.
+// ---------------------------------------------------------------------------
+const uint32_t FD_SUB = 0x80000000u;
+
+// Klein-Nishina angular density per steradian at energy e (normalised over
+// the sphere): (r_e^2/2) eps^2 (eps + 1/eps - sin^2) / sigma_KN(e).
+double kn_pdf(double e, double cos_t) {
+    const double k = e / MEC2_KEV;
+    const double eps = 1.0 / (1.0 + k * (1.0 - cos_t));
+    return eps * eps * (eps + 1.0 / eps - (1.0 - cos_t * cos_t)) / (4.0 * PI * kn_total(e));
+}
+
+// Integral of mu140 along the ray x + t d, t >= 0, to where it leaves the grid.
+double ray_mu_integral(const Setup& s, const double x[3], const double d[3]) {
+    const double far = 4.0 * (s.L[0] + s.L[1] + s.L[2]);
+    const double b[3] = {x[0] + far * d[0], x[1] + far * d[1], x[2] + far * d[2]};
+    std::vector<std::pair<size_t, double>> pieces;
+    segment_voxels(s, x, b, pieces);
+    double sum = 0.0;
+    for (auto& pc : pieces) sum += (double)s.p->mu140[pc.first] * pc.second;
+    return sum;
+}
+
+struct FdSink {
+    std::vector<double>* tally;
+    std::vector<double>* tally_sq;
+};
+
+void fd_score(const Setup& s, int32_t view, uint64_t hist, uint32_t event, const double x[3],
+              const double* d_in, double e, int cls, FdSink& sink) {
+    const orc_problem* p = s.p;
+    const Words w = philox4x32_10((uint32_t)hist, (uint32_t)view, event, FD_SUB, p->seed,
+                                  p->problem_id);
+    const double cos_b = 1.0 - uniform(w.r[0]) * (1.0 - s.cos_alpha);
+    const double nx = s.nvec_x[view], ny = s.nvec_y[view];
+    double o[3] = {nx, ny, 0.0};
+    rotate(o, cos_b, 2.0 * PI * uniform(w.r[1]));
+    const double omega = 2.0 * PI * (1.0 - s.cos_alpha);
+    double weight, e2;
+    if (!d_in) {
+        weight = omega / (4.0 * PI);
+        e2 = e;
+    } else {
+        const double ct = d_in[0] * o[0] + d_in[1] * o[1] + d_in[2] * o[2];
+        e2 = e / (1.0 + (e / MEC2_KEV) * (1.0 - ct));
+        weight = (1.0 - s.xs.p_pe(e)) * omega * kn_pdf(e, ct);
+    }
+    if (e2 < p->e_cut_kev || !(e2 >= p->e_lo_kev && e2 <= p->e_hi_kev)) return;
+    const double dn = o[0] * nx + o[1] * ny;
+    const double tp = (p->radius_cm - (x[0] * nx + x[1] * ny)) / dn;
+    const double px = x[0] + tp * o[0], py = x[1] + tp * o[1], pz = x[2] + tp * o[2];
+    const double wu = p->nu * p->pixel_cm, wv = p->nv * p->pixel_cm;
+    const double au = (-ny * px + nx * py) + 0.5 * wu;
+    const double av = pz + 0.5 * wv;
+    if (!(au >= 0.0 && au < wu && av >= 0.0 && av < wv)) return;
+    const int iu = std::min((int)std::floor(au / p->pixel_cm), p->nu - 1);
+    const int iv = std::min((int)std::floor(av / p->pixel_cm), p->nv - 1);
+    const double score = weight * std::exp(-s.xs.g(e2) * ray_mu_integral(s, x, o));
+    const size_t b = (((size_t)view * 2 + cls) * p->nv + iv) * p->nu + iu;
+    (*sink.tally)[b] += score;
+    (*sink.tally_sq)[b] += score * score;
+}
+
 // Transport one history.  view/hist identify its random stream.
-void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, History& h) {
+void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, History& h,
+                 FdSink* fd = nullptr) {
     const orc_problem* p = s.p;
     const uint32_t k0 = p->seed, k1 = p->problem_id;
     const uint32_t c0 = (uint32_t)hist, c1 = (uint32_t)view;
@@ -293,6 +376,7 @@ void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, Hi
     double mu_max = s.mu_hat * s.xs.g(e);
     double p_pe = s.xs.p_pe(e);
     if (keep_path) h.verts.push_back(Vertex{{x[0], x[1], x[2]}, e});
+    if (fd) fd_score(s, view, hist, 0, x, nullptr, e, 0, *fd);
 
     // --- Woodcock loop: event n = 1, 2, ... ---
     uint32_t n = 0;
@@ -328,6 +412,7 @@ void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, Hi
         const size_t v = (size_t)idx[0] + (size_t)p->nx * ((size_t)idx[1] + (size_t)p->ny * idx[2]);
         if ((w.r[1] >> 8) >= s.Q[v]) continue;           // virtual collision
         h.n_real++;
+        if (fd) fd_score(s, view, hist, n, x, d, e, 1, *fd);
         if (uniform(w.r[2]) < p_pe) {                     // photoelectric absorption
             h.dep += e; h.fate = ABSORBED; break;
         }
@@ -574,6 +659,53 @@ int orc_simulate(const orc_problem* p, double* tally, double* tally_sq, orc_resu
     }
     if (n_trip) *n_trip = nt_out;
     return (want_trip && nt_out > trip_cap) ? -2 : 0;
+}
+
+// Forced-detection forward simulation: the same analog histories (fates,
+// energies and counters as orc_simulate), but the tally is the forced-
+// detection estimate, scored at emission (class 0) and at every real collision
+// (class 1); tally_sq sums the squared scores.  Analog arrivals are not tallied.
+int orc_simulate_fd(const orc_problem* p, double* tally, double* tally_sq, orc_result* res) {
+    Setup s;
+    if (!build_setup(p, s)) return -1;
+    const size_t nbins = (size_t)p->n_views * 2 * p->nv * p->nu;
+    const size_t nt = n_threads_for(p);
+    std::vector<Acc> acc(nt);
+    for (auto& a : acc) { a.tally.assign(nbins, 0.0); a.tally_sq.assign(nbins, 0.0); }
+    parallel_ranges(s.begin, s.end, nt, [&](size_t t, uint64_t b, uint64_t e) {
+        FdSink sink{&acc[t].tally, &acc[t].tally_sq};
+        for (uint64_t g = b; g < e; ++g) {
+            int32_t view; uint64_t hist;
+            work_to_view_hist(s, g, view, hist);
+            History h;
+            run_history(s, view, hist, false, h, &sink);
+            accumulate(p, h, acc[t], false, false, g);
+        }
+    });
+    std::memset(res, 0, sizeof(*res));
+    std::fill(tally, tally + nbins, 0.0);
+    if (tally_sq) std::fill(tally_sq, tally_sq + nbins, 0.0);
+    for (auto& a : acc) {
+        for (int i = 0; i < 8; ++i) res->fates[i] += a.fates[i];
+        for (int i = 0; i < 4; ++i) res->energy[i] += a.energy[i];
+        res->n_tent += a.n_tent; res->n_real += a.n_real; res->n_kahn += a.n_kahn;
+        res->n_hist += a.n_hist;
+        for (size_t b = 0; b < nbins; ++b) {
+            tally[b] += a.tally[b];
+            if (tally_sq) tally_sq[b] += a.tally_sq[b];
+        }
+    }
+    return 0;
+}
+
+double orc_kn_pdf(double e_kev, double cos_t) { return kn_pdf(e_kev, cos_t); }
+
+// Integral of mu140 from x along d to the grid edge (exact voxel pieces).
+int orc_ray_integral(const orc_problem* p, const double x[3], const double d[3], double* out) {
+    Setup s;
+    if (!build_setup(p, s)) return -1;
+    *out = ray_mu_integral(s, x, d);
+    return 0;
 }
 
 // Per-history records for the listed (view, history id) pairs.

@@ -33,6 +33,7 @@ STATUS_GRAD_OVERFLOW, STATUS_BAD_EVENT = 32, 64
 FATES = ["ABSORBED", "CUT", "ESCAPED", "ESCAPED_FOV", "OUT_OF_WINDOW", "TALLIED", "CAPPED", "SPARE"]
 Q32 = float(2 ** 32)   # tally fixed point: Q31.32
 Q23 = float(2 ** 23)   # energy fixed point: Q40.23 keV
+Q52 = float(2 ** 52)   # forced-detection sum of squared scores: Q11.52
 
 # Exported symbols, as declared in include/mcspect.h.
 EXPORTS = ["mc_workspace_bytes", "mc_simulate_projections", "mc_replay_histories",
@@ -60,7 +61,7 @@ class McProblem(C.Structure):
 class McOptions(C.Structure):
     _fields_ = [("hist_per_lane", C.c_int32), ("block_size", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("brick_log2", C.c_int32),
-                ("threshold_bytes", C.c_int32), ("reserved", C.c_int32),
+                ("threshold_bytes", C.c_int32), ("forced_detection", C.c_int32),
                 ("kernel_events", C.c_void_p * 2)]
 
 
@@ -196,7 +197,8 @@ def _opts(options: Optional[dict]) -> Optional[McOptions]:
                   block_size=int(options.get("block_size", 0)),
                   blocks_per_cu=int(options.get("blocks_per_cu", 0)),
                   brick_log2=int(options.get("brick_log2", 0)),
-                  threshold_bytes=int(options.get("threshold_bytes", 0)))
+                  threshold_bytes=int(options.get("threshold_bytes", 0)),
+                  forced_detection=int(options.get("forced_detection", 0)))
     ev = options.get("kernel_events")
     if ev is not None:
         o.kernel_events[0] = ev[0]
@@ -361,6 +363,11 @@ def replay(problem: DeviceProblem, views, hists, options=None) -> np.ndarray:
 def tally_float(t) -> np.ndarray:
     """Fixed-point tally -> float64 counts."""
     return t.cpu().numpy().astype(np.float64) / Q32
+
+
+def fd_tally_sq_float(t) -> np.ndarray:
+    """Forced-detection sum of squared scores (Q11.52) -> float64."""
+    return t.cpu().numpy().astype(np.float64) / Q52
 
 
 def adjoint(problem: DeviceProblem, dL_dtally, sim: Optional[Simulator] = None,

@@ -114,6 +114,7 @@ ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64
     d.inv_pix = (float)(1.0 / p.pixel_cm);
     d.radius = (float)p.radius_cm;
     d.cos_alpha = (float)std::cos(p.accept_half_angle_rad);
+    d.omc_alpha = (float)(2.0 * std::sin(0.5 * p.accept_half_angle_rad) * std::sin(0.5 * p.accept_half_angle_rad));
     d.wu = (float)(p.nu * p.pixel_cm);
     d.wv = (float)(p.nv * p.pixel_cm);
     d.e_lo = (float)p.e_lo_kev; d.e_hi = (float)p.e_hi_kev; d.e_cut = (float)p.e_cut_kev;
@@ -221,7 +222,10 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e);
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return hip_fail(e);
-    if (bpc <= 0) bpc = transport_blocks_per_cu(block);
+    if (opt && (opt->forced_detection < 0 || opt->forced_detection > 1)) return MC_EINVAL;
+    const bool fd = opt && opt->forced_detection == 1;
+    if (fd && events) return MC_EINVAL;
+    if (bpc <= 0) bpc = transport_blocks_per_cu(block, fd);
     TransportArgs a;
     a.descs = d_desc;
     a.n_problems = n_problems;
@@ -238,6 +242,7 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     a.event_capacity = events ? event_capacity : 0;
     a.n_events = (unsigned long long*)n_events;
     a.status = status;
+    a.forced_detection = fd ? 1 : 0;
     hipEvent_t ev0 = opt ? (hipEvent_t)opt->kernel_events[0] : nullptr;
     hipEvent_t ev1 = opt ? (hipEvent_t)opt->kernel_events[1] : nullptr;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return hip_fail(e);
@@ -277,6 +282,7 @@ int mc_adjoint_mu(const mc_problem* problem, const mc_options* opt, const double
     if (!problem || !dL_dtally || !dL_dmu || !status || !workspace) return MC_EINVAL;
     if (events && !n_events) return MC_EINVAL;
     if (frac_bits < 0 || frac_bits > 62) return MC_EINVAL;
+    if (opt && opt->forced_detection) return MC_EINVAL;   // adjoint of analog tallies only
     if (!check_problem(*problem)) return MC_EINVAL;
     int block, hpl, bpc, brick, qbytes;
     resolve(opt, block, hpl, bpc, brick, qbytes);

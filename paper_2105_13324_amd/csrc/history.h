@@ -132,12 +132,17 @@ __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
 // it, with the hardware log2) and the photoelectric share f (140/E)^3 / g.
 // The KN ratio is linearly interpolated (error below 1e-6 relative over the
 // table range), the photoelectric term is exact.
-__device__ inline float energy_terms(const Cst& C, float e, float& ln2_mm, float& p_pe) {
+// sigma_KN(e) / sigma_KN(140), linearly interpolated in the table.
+__device__ inline float kn_ratio(const Cst& C, float e) {
     const float t = (140.0f - e) * KN_TABLE_STEP_INV;
     const int i = (int)t;
     const float fr = t - (float)i;
     const float k0 = ldg(C.kn_table + i), k1 = ldg(C.kn_table + i + 1);
-    const float kn = fmaf(fr, k1 - k0, k0);
+    return fmaf(fr, k1 - k0, k0);
+}
+
+__device__ inline float energy_terms(const Cst& C, float e, float& ln2_mm, float& p_pe) {
+    const float kn = kn_ratio(C, e);
     const float x = 140.0f * rcpf(e);
     const float pe = C.f_pe * x * x * x;
     const float g = fmaf(1.0f - C.f_pe, kn, pe);
@@ -206,6 +211,26 @@ __device__ inline int escape(const Cst& C, const Lane& L, int& iu, int& iv) {
 
 // Turn the direction by polar cosine ct and azimuth 2 pi phi_u (standard
 // formula; near the poles the direction is taken as +-z).
+// Rotate unit direction (u, v, w) by polar cosine ct and azimuth phi_u (in
+// revolutions), with the near-pole branch for |w| > 0.99999.
+__device__ inline void rotate_dir(float& u, float& v, float& w, float ct, float phi_u) {
+    const float sp = sin_rev(phi_u), cp = cos_rev(phi_u);
+    const float st = sqrtf_hw(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
+    const float u0 = u, v0 = v, w0 = w;
+    if (fabsf(w0) > 0.99999f) {
+        u = st * cp;
+        v = st * sp;
+        w = w0 > 0.0f ? ct : -ct;
+    } else {
+        const float t = sqrtf_hw((1.0f - w0) * (1.0f + w0));
+        const float it = rcpf(t);
+        const float a = st * it;
+        u = fmaf(a, u0 * w0 * cp - v0 * sp, u0 * ct);
+        v = fmaf(a, v0 * w0 * cp + u0 * sp, v0 * ct);
+        w = fmaf(-st * cp, t, w0 * ct);
+    }
+}
+
 __device__ inline void rotate(Lane& L, float ct, float phi_u) {
     const float sp = sin_rev(phi_u), cp = cos_rev(phi_u);
     const float st = sqrtf_hw(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
@@ -400,6 +425,117 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
         return R_RUNNING;
     }
     return R_RUNNING;
+}
+
+// ---------------------------------------------------------------------------
+// Forced detection (Sec. 5.2).  At the emission point and at every real
+// collision a copy of the photon is forced to this view's detector, with the
+// weight the paper lists: the probabilities of not being absorbed there, of
+// leaving in a direction the collimator passes, and of crossing the rest of
+// the object.  The copy's direction is uniform in the collimator cone (Philox
+// event of the point, sub-draw FD_SUB, words 0 and 1):
+//   w = Omega_cone pdf(direction) exp(-g(E') integral of mu140 on the ray),
+// pdf = 1/(4 pi) at emission, (1 - p_pe(E)) times the Klein-Nishina angular
+// density at a collision; the expected score in each bin is the expected
+// analog count.  No score if E' is cut or outside the window, or the ray
+// misses the detector.
+// ---------------------------------------------------------------------------
+constexpr uint32_t FD_SUB = 0x80000000u;
+constexpr float FOUR_PI_F = 12.566370614359172f;
+constexpr float TWO_PI_F = 6.283185307179586f;
+
+struct FdPoint {
+    float x, y, z;       // scoring point
+    float dx, dy, dz;    // direction before the collision (unused at emission)
+    float e;             // energy before the collision
+    uint32_t view, hist, event;   // event 0: emission
+};
+
+// Integral of mu140 along p + t o (t >= 0, o a unit vector) to the grid edge:
+// voxel walk (Amanatides & Woo 1987) with the advancing axis chosen by
+// selects, so the lanes of a wavefront stay together.
+__device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox, float oy, float oz) {
+    const float px = x + C.hx, py = y + C.hy, pz = z + C.hz;
+    int ix = min(max((int)(px * C.inv_vox), 0), C.nx - 1);
+    int iy = min(max((int)(py * C.inv_vox), 0), C.ny - 1);
+    int iz = min(max((int)(pz * C.inv_vox), 0), C.nz - 1);
+    const float inf = __builtin_huge_valf();
+    const int sx = ox > 0.0f ? 1 : -1, sy = oy > 0.0f ? 1 : -1, sz = oz > 0.0f ? 1 : -1;
+    float tx = ox != 0.0f ? fmaxf(((float)(ix + (ox > 0.0f)) * C.vox - px) / ox, 0.0f) : inf;
+    float ty = oy != 0.0f ? fmaxf(((float)(iy + (oy > 0.0f)) * C.vox - py) / oy, 0.0f) : inf;
+    float tz = oz != 0.0f ? fmaxf(((float)(iz + (oz > 0.0f)) * C.vox - pz) / oz, 0.0f) : inf;
+    const float ddx = ox != 0.0f ? C.vox / fabsf(ox) : inf;
+    const float ddy = oy != 0.0f ? C.vox / fabsf(oy) : inf;
+    const float ddz = oz != 0.0f ? C.vox / fabsf(oz) : inf;
+    const float ex = ox > 0.0f ? (C.lx - px) / ox : (ox < 0.0f ? -px / ox : inf);
+    const float ey = oy > 0.0f ? (C.ly - py) / oy : (oy < 0.0f ? -py / oy : inf);
+    const float ez = oz > 0.0f ? (C.lz - pz) / oz : (oz < 0.0f ? -pz / oz : inf);
+    const float t_exit = fmaxf(fminf(ex, fminf(ey, ez)), 0.0f);
+    const int stx = sx, sty = sy * C.nx, stz = sz * C.nx * C.ny;
+    int v = ix + C.nx * (iy + C.ny * iz);
+    float t = 0.0f, sum = 0.0f;
+    const int max_iter = C.nx + C.ny + C.nz + 3;
+    for (int it = 0; it < max_iter; ++it) {
+        const float tn = fminf(tx, fminf(ty, tz));
+        const float te = fminf(tn, t_exit);
+        sum = fmaf(ldg(C.mu + v), te - t, sum);
+        if (tn >= t_exit) break;
+        t = tn;
+        const bool bx = (tx <= ty) & (tx <= tz);
+        const bool by = !bx & (ty <= tz);
+        const bool bz = !bx & !by;
+        ix += bx ? sx : 0; iy += by ? sy : 0; iz += bz ? sz : 0;
+        tx += bx ? ddx : 0.0f; ty += by ? ddy : 0.0f; tz += bz ? ddz : 0.0f;
+        v += bx ? stx : (by ? sty : stz);
+        if (((unsigned)ix >= (unsigned)C.nx) | ((unsigned)iy >= (unsigned)C.ny) |
+            ((unsigned)iz >= (unsigned)C.nz)) break;
+    }
+    return sum;
+}
+
+// Score one forced copy into the tallies (tally Q31.32, tally_sq Q11.52).
+// d: the problem's descriptor (cone and Klein-Nishina constants).
+__device__ inline void fd_score(const Cst& C, const ProbDesc* __restrict__ d, const FdPoint& q,
+                                int64_t* tally, int64_t* tally_sq) {
+    const float omc = d->omc_alpha, kn140 = (float)d->kn140;
+    uint32_t r0 = q.hist, r1 = q.view, r2 = q.event, r3 = FD_SUB;
+    philox10(r0, r1, r2, r3, C.seed, C.pid);
+    const float2 vw = ldg(C.views + q.view);
+    float ox = vw.x, oy = vw.y, oz = 0.0f;
+    rotate_dir(ox, oy, oz, fmaf(-unif(r0), omc, 1.0f), unif(r1));
+    float w, e2;
+    if (q.event == 0) {
+        w = 0.5f * omc;
+        e2 = q.e;
+    } else {
+        const float ct = q.dx * ox + q.dy * oy + q.dz * oz;
+        const float eps = rcpf(fmaf(q.e * INV_MEC2, 1.0f - ct, 1.0f));
+        e2 = q.e * eps;
+        float l2, ppe;
+        energy_terms(C, q.e, l2, ppe);
+        const float pdf = eps * eps * (eps + rcpf(eps) - (1.0f - ct * ct)) *
+                          rcpf(FOUR_PI_F * kn140 * kn_ratio(C, q.e));
+        w = (1.0f - ppe) * (TWO_PI_F * omc) * pdf;
+    }
+    if (!(e2 >= C.e_cut && e2 >= C.e_lo && e2 <= C.e_hi)) return;
+    const float dn = ox * vw.x + oy * vw.y;
+    const float tp = (C.radius - (q.x * vw.x + q.y * vw.y)) * rcpf(dn);
+    const float px = fmaf(tp, ox, q.x), py = fmaf(tp, oy, q.y), pz = fmaf(tp, oz, q.z);
+    const float au = (-vw.y * px + vw.x * py) + 0.5f * C.wu;
+    const float av = pz + 0.5f * C.wv;
+    if (!(au >= 0.0f && au < C.wu && av >= 0.0f && av < C.wv)) return;
+    const int iu = min((int)(au * C.inv_pix), C.nu - 1);
+    const int iv = min((int)(av * C.inv_pix), C.nv - 1);
+    float l2, ppe;
+    const float g = e2 == 140.0f ? 1.0f : energy_terms(C, e2, l2, ppe);
+    const float sc = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, ox, oy, oz));
+    const int cls = q.event == 0 ? 0 : 1;
+    const size_t b = C.tally_offset +
+                     ((((size_t)q.view * 2 + cls) * (size_t)C.nv + iv) * (size_t)C.nu + iu);
+    atomicAdd((unsigned long long*)(tally + b), (unsigned long long)__float2ll_rn(sc * 4294967296.0f));
+    if (tally_sq)
+        atomicAdd((unsigned long long*)(tally_sq + b),
+                  (unsigned long long)__float2ll_rn(sc * sc * 4503599627370496.0f));
 }
 
 }  // namespace

@@ -54,6 +54,8 @@ struct ProbDesc {
     uint32_t n_active;              // voxels with activity > 0
     uint32_t pal_state;             // 0: palette in use; 1: 32-bit thresholds (host request
                                     // or more than PALETTE_N distinct values, set by staging)
+    float omc_alpha;                // 1 - cos(alpha), from double precision (forced detection)
+    uint32_t pad2;
 };
 
 // Emission bucket b covers t in [b << shift, (b + 1) << shift) of the integer
@@ -103,6 +105,7 @@ struct TransportArgs {
     const uint64_t* work_prefix;    // [n_problems + 1], device
     uint64_t total_work;
     uint32_t chunk;                 // work indices per claim (per wave)
+    int32_t forced_detection;       // 1: forced-detection estimator in the tally
     CallState* state;
     int64_t* tally;
     int64_t* tally_sq;
@@ -150,6 +153,6 @@ hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int
                        void* workspace, hipStream_t s);
 
 // Occupancy of the transport kernel (blocks per CU at this block size).
-int transport_blocks_per_cu(int block);
+int transport_blocks_per_cu(int block, bool forced_detection);
 
 }  // namespace mcs

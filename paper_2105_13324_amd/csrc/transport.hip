@@ -7,21 +7,27 @@
 //
 // Execution model
 //  * Every iteration of the main loop draws exactly one Philox4x32-10 block
-//    per active lane.  The lane's state (emission part 1/2, tentative
-//    collision, Kahn attempt) picks the counter and what the four words mean,
-//    so the dominant cost -- the 10 Philox rounds -- runs with all lanes in
-//    lockstep, and only the short per-state tails diverge.
-//  * A lane whose history ends takes the next work index at once (lane
-//    refill), from a chunk its wavefront claimed with one global atomic.
-//    Chunks never straddle problems, and a wavefront finishes the histories of
-//    one problem before it starts another, so every problem constant is
-//    wave-uniform (scalar registers) even in the batched launch.
+//    per active lane.  The lane's state (tentative collision or Kahn attempt)
+//    picks the counter and what the four words mean, so the dominant cost --
+//    the 10 Philox rounds -- runs with all lanes in lockstep, and only the
+//    short per-state tails diverge.
+//  * Emission is converged: a wavefront emits the next 128 histories of its
+//    chunk into an LDS stage in one phase (two per lane), and a lane whose
+//    history ends starts the next staged one.  Chunks come from one global
+//    atomic and never straddle problems, and a wavefront finishes the
+//    histories of one problem before it starts another, so every problem
+//    constant is wave-uniform (scalar registers) even in the batched launch.
 //  * Fate counts, energies and work counters stay in registers and are
 //    reduced across the wavefront before one atomic per value; tallies are
 //    64-bit fixed-point integer atomics, so every sum is exact and
 //    order-independent: results are bit-identical from run to run.
-//  * Woodcock tracking: one 4-byte threshold gather per tentative collision;
-//    the accept test is an integer compare.
+//  * Woodcock tracking: one threshold gather per tentative collision (a
+//    one-byte palette code when the map allows, the palette in LDS); the
+//    accept test is an integer compare.
+//  * Forced detection (a second instantiation): the emission phase scores
+//    each emitted history's forced copy; real collisions queue their forced
+//    copies in a per-wave LDS ring that the wavefront scores 64 at a time, so
+//    the long ray walks run converged rather than inside one lane's history.
 #include "history.h"
 
 namespace mcs {
@@ -92,16 +98,32 @@ struct EmitRec {
     uint32_t voxel, view, hist;
 };
 
+constexpr uint32_t FD_RING = 128;         // forced-detection queue per wave
+
+// Score the n (<= 64) forced copies at the head of a wave's ring.
+__device__ inline void fd_drain(const Cst& C, int p, const FdPoint* ring, uint32_t& head, uint32_t n,
+                                int lane, const TransportArgs& T) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if ((uint32_t)lane < n) {
+        const FdPoint q = ring[(head + (uint32_t)lane) & (FD_RING - 1)];
+        fd_score(C, T.descs + p, q, T.tally, T.tally_sq);
+    }
+    head += n;
+}
+
 // Persistent transport: waves claim chunks of work until none are left.
 // A wavefront emits the next EMIT_BATCH histories of its chunk in one
 // converged phase into LDS; idle lanes then start histories from there, so
 // the per-lane loop only alternates tentative collisions and Kahn attempts.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TransportArgs T) {
-    __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
-    __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
+// FD: forced-detection estimator instead of analog arrivals in the tally.
+template <bool FD>
+__device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restrict__ my,
+                                               uint32_t* __restrict__ my_pal,
+                                               FdPoint* __restrict__ ring) {
     const int lane = threadIdx.x & 63;
-    EmitRec* __restrict__ my = stage[threadIdx.x >> 6];
-    uint32_t* __restrict__ my_pal = pal_copy[threadIdx.x >> 6];
+    uint32_t fd_head = 0, fd_tail = 0;    // wave-uniform ring cursors (FD)
     const uint64_t lane_lt = (1ull << lane) - 1ull;
     const uint64_t full = __ballot(1);   // lanes of this wavefront
     // chunk bookkeeping (wave-uniform): problem-local work range [c_next, c_end)
@@ -151,6 +173,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                             ready = false;                 // drain problem p first
                         } else {
                             if (np != p) {
+                                if constexpr (FD) {
+                                    if (p >= 0 && fd_tail != fd_head)
+                                        fd_drain(C, p, ring, fd_head, fd_tail - fd_head, lane, T);
+                                }
                                 if (p >= 0) flush(A, fc, p, T, lane);
                                 p = np;
                                 C = load_cst(T.descs + p);
@@ -189,6 +215,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                             r.x = e.x; r.y = e.y; r.z = e.z; r.dx = e.dx; r.dy = e.dy; r.dz = e.dz;
                             r.voxel = e.voxel; r.view = (uint32_t)v; r.hist = (uint32_t)h;
                             my[idx] = r;
+                            if constexpr (FD) {
+                                FdPoint q;
+                                q.x = e.x; q.y = e.y; q.z = e.z;
+                                q.dx = 0.0f; q.dy = 0.0f; q.dz = 0.0f;
+                                q.e = 140.0f;
+                                q.view = (uint32_t)v; q.hist = (uint32_t)h; q.event = 0;
+                                fd_score(C, T.descs + p, q, T.tally, T.tally_sq);
+                            }
                         }
                     }
                     // the records are read by other lanes of this wavefront
@@ -219,18 +253,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
         int fate = R_RUNNING;
         int iu = -1, iv = -1;
+        bool real = false;
         if (L.state != S_IDLE) {
             uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
             counter_of(L, c2, c3);
             philox10(c0, c1, c2, c3, C.seed, C.pid);
+            const uint32_t n_real0 = A.n_real;
             fate = advance(C, my_pal, L, c0, c1, c2, c3, A, iu, iv);
             if (fate != R_RUNNING) book_energy(A, fate, L.e);
+            if constexpr (FD) real = A.n_real != n_real0;
+        }
+        if constexpr (FD) {
+            // real collisions queue their forced copies (position, direction
+            // and energy before the collision are still the lane's)
+            const uint64_t m = __ballot(real);
+            if (m != 0) {
+                if (real) {
+                    FdPoint q;
+                    q.x = L.x; q.y = L.y; q.z = L.z; q.dx = L.dx; q.dy = L.dy; q.dz = L.dz;
+                    q.e = L.e; q.view = (uint32_t)L.view; q.hist = (uint32_t)L.hist; q.event = L.n;
+                    ring[(fd_tail + (uint32_t)__popcll(m & lane_lt)) & (FD_RING - 1)] = q;
+                }
+                fd_tail += (uint32_t)__popcll(m);
+                if (fd_tail - fd_head >= 64) fd_drain(C, p, ring, fd_head, 64, lane, T);
+            }
         }
         if (__ballot(fate != R_RUNNING) != 0) {
             // fate counts through ballots: wave-uniform, no per-lane counters
 #pragma unroll
             for (int f = 0; f < 7; ++f) fc[f] += (uint32_t)__popcll(__ballot(fate == f));
-            if (fate == MC_TALLIED) {
+            if (!FD && fate == MC_TALLIED) {
                 const int cls = L.n_scatter > 0 ? 1 : 0;
                 const uint32_t bin = (uint32_t)((((uint32_t)L.view * 2u + cls) * (uint32_t)C.nv + iv) *
                                                 (uint32_t)C.nu + iu);
@@ -251,7 +303,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             if (fate != R_RUNNING) L.state = S_IDLE;
         }
     }
+    if constexpr (FD) {
+        if (p >= 0 && fd_tail != fd_head) fd_drain(C, p, ring, fd_head, fd_tail - fd_head, lane, T);
+    }
     if (p >= 0) flush(A, fc, p, T, lane);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TransportArgs T) {
+    __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
+    __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
+    transport_body<false>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr);
+}
+
+__global__ __launch_bounds__(256) void k_transport_fd(TransportArgs T) {
+    __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
+    __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
+    __shared__ FdPoint ring[WAVES_PER_BLOCK_MAX][FD_RING];
+    transport_body<true>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6],
+                         ring[threadIdx.x >> 6]);
 }
 
 // Replay: one listed history per lane, run to its end, one record out.
@@ -370,7 +439,8 @@ hipError_t launch_prepare_call(const ProbDesc* descs, int32_t n_problems, uint64
 }
 
 hipError_t launch_transport(const TransportArgs& a, int grid, int block, hipStream_t s) {
-    k_transport<<<grid, block, 0, s>>>(a);
+    if (a.forced_detection) k_transport_fd<<<grid, block, 0, s>>>(a);
+    else k_transport<<<grid, block, 0, s>>>(a);
     // without a list the count is informational and cannot overflow
     k_finalize<<<1, 64, 0, s>>>(a.descs, a.n_problems, a.status, a.n_events,
                                 a.events ? a.event_capacity : UINT64_MAX);
@@ -388,9 +458,12 @@ hipError_t launch_replay(const ProbDesc* d_desc, const int32_t* views, const uin
     return hipGetLastError();
 }
 
-int transport_blocks_per_cu(int block) {
+int transport_blocks_per_cu(int block, bool forced_detection) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport, block, 0) != hipSuccess) return 1;
+    const hipError_t e = forced_detection
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport_fd, block, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport, block, 0);
+    if (e != hipSuccess) return 1;
     return n > 0 ? n : 1;
 }
 

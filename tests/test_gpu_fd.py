@@ -1,0 +1,134 @@
+"""Forced detection (Sec. 5.2) on the GPU against the oracle, through the C ABI.
+
+Bars: the analog part of a forced-detection run (fates, energies, counters)
+equals the plain run bit for bit; the forced-detection tally (FP32 scores in
+Q31.32) agrees with the oracle's FP64 scores in class totals to 2e-5 and bin
+by bin to 3e-4 of the total in L1: a score whose detector hit lies within
+FP32 rounding (~3e-6 cm on ~30 cm coordinates) of a pixel edge lands in the
+neighbouring pixel, about 2e-5 of scores per axis at 6 mm pixels, and the
+rare history whose analog decision flips moves its scoring points; on the
+point source the primary estimate matches the narrow-beam closed form; runs
+are bit-identical from run to run and across launch options.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+import phantoms
+
+pytestmark = pytest.mark.gpu
+
+FD = {"forced_detection": 1}
+
+
+def _mc():
+    import paper_2105_13324_amd as mc
+    return mc
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def outputs(sim):
+    return (sim.tally.cpu().numpy().copy(), sim.fates.cpu().numpy().copy(),
+            sim.energy.cpu().numpy().copy(), sim.counters.cpu().numpy().copy())
+
+
+def fd_parity(prob, rel_bin=3e-4, rel_class=2e-5):
+    mc = _mc()
+    dp = mc.to_device(prob)
+    g = mc.simulate(dp, options=FD)
+    a = mc.simulate(dp, want_sq=False)
+    o = oracle.simulate_fd(prob)
+    gt = mc.tally_float(g.tally).reshape(prob.tally_shape)
+    gsq = mc.fd_tally_sq_float(g.tally_sq).reshape(prob.tally_shape)
+    ot = o["tally"]
+    # the analog histories are untouched
+    np.testing.assert_array_equal(g.fates.cpu().numpy(), a.fates.cpu().numpy())
+    np.testing.assert_array_equal(g.energy.cpu().numpy(), a.energy.cpu().numpy())
+    np.testing.assert_array_equal(g.counters.cpu().numpy(), a.counters.cpu().numpy())
+    tot = ot.sum()
+    l1 = np.abs(gt - ot).sum() / tot
+    cls_rel = [abs(gt[:, c].sum() - ot[:, c].sum()) / ot[:, c].sum() for c in range(2)]
+    sq_rel = abs(gsq.sum() - o["tally_sq"].sum()) / o["tally_sq"].sum()
+    say(f"{prob.name}: FD total {gt.sum():.6e} oracle {tot:.6e}; bin L1 {l1:.2e}; "
+        f"class rel {cls_rel[0]:.2e} {cls_rel[1]:.2e}; sum sq rel {sq_rel:.2e}; "
+        f"nonzero bins {np.count_nonzero(gt)} / {np.count_nonzero(ot)}")
+    assert l1 <= rel_bin
+    assert max(cls_rel) <= rel_class
+    assert sq_rel <= 1e-3
+    return g, gt, o
+
+
+def test_fd_point_cube_closed_form_and_oracle():
+    p = phantoms.point_cube_64(200_000)
+    g, gt, o = fd_parity(p)
+    pexp = 0.5 * integrate.quad(lambda c: math.exp(-float(np.float32(0.151)) * 6.4 / c),
+                                math.cos(p.accept_half_angle_rad), 1.0)[0]
+    got = gt[0, 0].sum() / p.n_histories
+    say(f"point cube FD primary per history {got:.8e}, closed form {pexp:.8e}")
+    assert got == pytest.approx(pexp, rel=2e-5)
+
+
+def test_fd_thorax_small_matches_oracle():
+    p = phantoms.thorax_problem("fd_thorax32", 32, 1.2, 2, 12, 180.0, 32, 1.2, 300_000)
+    fd_parity(p)
+
+
+def test_fd_thorax_photoelectric_wide_cone():
+    """Photoelectric share 0.3 at 140 keV (the not-absorbed factor matters),
+    15 degree cone, window down to 100 keV (scatter class well populated)."""
+    p = phantoms.thorax_problem("fd_pe", 32, 1.2, 3, 6, 180.0, 32, 1.2, 200_000).with_(
+        pe_fraction=0.3, accept_half_angle_rad=math.radians(15.0), e_lo_kev=100.0, e_cut_kev=100.0)
+    fd_parity(p)
+
+
+def test_fd_thorax_128_full_geometry_sampled():
+    """The headline geometry (128^3 thorax, 60 views, 64^2 x 6 mm) on a slice of
+    its 1e8 histories: work indices [4e7, 4e7 + 2e5)."""
+    p = phantoms.thorax_128(10 ** 8).with_(history_offset=40_000_000, history_count=200_000)
+    fd_parity(p)
+
+
+def test_fd_run_to_run_and_options():
+    mc = _mc()
+    p = phantoms.thorax_problem("fd_opts", 40, 0.96, 4, 8, 180.0, 32, 1.2, 150_000)
+    dp = mc.to_device(p)
+    ref = outputs(mc.simulate(dp, options=FD))
+    for opts in ({}, {"hist_per_lane": 1}, {"block_size": 128, "blocks_per_cu": 1},
+                 {"hist_per_lane": 7, "brick_log2": 2}, {"threshold_bytes": 4}):
+        got = outputs(mc.simulate(dp, options={**FD, **opts}))
+        for x, y in zip(got, ref):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_fd_batched_equals_individual():
+    mc = _mc()
+    rng = np.random.Generator(np.random.PCG64(23))
+    probs = []
+    for i in range(4):
+        n = int(rng.integers(24, 41))
+        probs.append(phantoms.thorax_problem(f"fdb{i}", n, 38.4 / n, 1100 + i, int(rng.integers(3, 12)),
+                                             180.0, 32, 1.2, 60_000 + 11 * i, problem_id=i))
+    dps = [mc.to_device(p) for p in probs]
+    batch = outputs(mc.simulate(dps, options=FD))
+    off = 0
+    for i, dp in enumerate(dps):
+        one = outputs(mc.simulate(dp, options=FD))
+        np.testing.assert_array_equal(batch[0][off:off + one[0].size], one[0])
+        np.testing.assert_array_equal(batch[1][i], one[1][0])
+        off += one[0].size
+
+
+def test_fd_rejects_event_list():
+    mc = _mc()
+    p = phantoms.point_cube_64(1000)
+    dp = mc.to_device(p)
+    with pytest.raises(mc.McError):
+        mc.simulate(dp, options=FD, event_capacity=16)

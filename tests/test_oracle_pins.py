@@ -561,3 +561,107 @@ def test_osem_additive_scatter_and_dual_matrix_reduce():
     s = 0.3 * (Ts @ n)
     Pc = T @ n + s
     np.testing.assert_allclose(oracle.osem(T, Pc, 3, 3, bpv, scatter=s, S0=n), n, rtol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Forced detection (Sec. 5.2)
+# ---------------------------------------------------------------------------
+
+def test_fd_angular_density_normalised_and_matches_kahn_sampler():
+    """The angular density forced detection weights with integrates to one over
+    the sphere and is the distribution Kahn's sampler draws from (chi-square of
+    the sampler's cos(theta) against bin integrals of the density)."""
+    for e in (20.0, 126.0, 140.0):
+        norm = 2 * math.pi * integrate.quad(lambda c: oracle.kn_pdf(e, c), -1, 1,
+                                            epsabs=0, epsrel=1e-12)[0]
+        assert norm == pytest.approx(1.0, rel=1e-10)
+    e, n = 140.0, 200_000
+    k = e / MEC2
+    x, _ = oracle.kahn_samples(e, n, seed=11)
+    cos = 1.0 - (x - 1.0) / k
+    edges = np.linspace(-1, 1, 51)
+    expected = np.array([2 * math.pi * integrate.quad(lambda c: oracle.kn_pdf(e, c), a, b)[0]
+                         for a, b in zip(edges[:-1], edges[1:])])
+    counts, _ = np.histogram(cos, bins=edges)
+    chi2 = np.sum((counts - n * expected) ** 2 / (n * expected))
+    assert stats.chi2.sf(chi2, len(counts) - 1) > 1e-4
+
+
+def test_fd_ray_integral_closed_forms():
+    """Exact line integrals: mu times the distance to the exit face in the water
+    cube, and the two lengths in a two-material slab."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    p = phantoms.point_cube_64(10)
+    H = 6.4
+    mu_w = float(np.float32(0.151))
+    for _ in range(20):
+        x = rng.uniform(-H * 0.99, H * 0.99, 3)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        t_exit = min((math.copysign(H, d[a]) - x[a]) / d[a] for a in range(3))
+        assert oracle.ray_integral(p, x, d) == pytest.approx(mu_w * t_exit, rel=1e-12)
+    mu, act = phantoms.slab_phantom(64, 0.2, 0.3, 0.05, 40)     # interface at x = 1.6 cm
+    ps = p.with_(mu=mu, activity=act)
+    ma, mb = float(np.float32(0.3)), float(np.float32(0.05))
+    for _ in range(20):
+        x = np.array([rng.uniform(-6.3, 1.5), rng.uniform(-1, 1), rng.uniform(-1, 1)])
+        d = np.array([1.0, rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3)])
+        d /= np.linalg.norm(d)
+        t_exit = min((math.copysign(H, d[a]) - x[a]) / d[a] for a in range(3))
+        t_if = (1.6 - x[0]) / d[0]
+        want = ma * t_if + mb * (t_exit - t_if) if t_if < t_exit else ma * t_exit
+        assert oracle.ray_integral(ps, x, d) == pytest.approx(want, rel=1e-12)
+
+
+def test_fd_point_source_primaries_closed_form():
+    """Point source in the water cube: each history's emission score is
+    (1 - cos a)/2 exp(-mu h / cos b) with b uniform in the cone, whose mean is
+    the narrow-beam closed form 1/2 int exp(-mu h / c) dc; the analog part of
+    the run (fates, energies) is unchanged."""
+    N = 200_000
+    p = phantoms.point_cube_64(N)
+    r = oracle.simulate_fd(p)
+    a = oracle.simulate(p)
+    alpha = p.accept_half_angle_rad
+    pexp = _cone_primary_prob(alpha, 0.151 * 6.4)
+    got = r["tally"][0, 0].sum() / N
+    lo = 0.5 * (1 - math.cos(alpha)) * math.exp(-0.151 * 6.4 / math.cos(alpha))
+    hi = 0.5 * (1 - math.cos(alpha)) * math.exp(-0.151 * 6.4)
+    sd = (hi - lo) / math.sqrt(12 * N)          # spread of one history's score is below (hi-lo)/sqrt(12)
+    assert abs(got - pexp) < 5 * sd + 1e-9 * pexp
+    np.testing.assert_array_equal(r["fates"], a["fates"])
+    np.testing.assert_allclose(r["energy"], a["energy"], rtol=1e-12)
+    # primaries land within D tan(alpha) of the detector centre
+    iv, iu = np.nonzero(r["tally"][0, 0])
+    uc = (iu + 0.5) * p.pixel_cm - 0.5 * p.nu * p.pixel_cm
+    vc = (iv + 0.5) * p.pixel_cm - 0.5 * p.nv * p.pixel_cm
+    assert np.max(np.hypot(uc, vc)) <= p.radius_cm * math.tan(alpha) + p.pixel_cm
+
+
+def _batch_totals(prob, n_batch, fd):
+    """Per-class window totals of n_batch independent runs (Philox seeds
+    100 + b), each covering every view."""
+    out = []
+    for b in range(n_batch):
+        r = (oracle.simulate_fd if fd else oracle.simulate)(prob.with_(seed=100 + b))
+        out.append([r["tally"][:, 0].sum(), r["tally"][:, 1].sum()])
+    return np.array(out)
+
+
+def test_fd_unbiased_against_analog():
+    """Forced detection and analog transport estimate the same expected counts:
+    a 32^3 thorax, 4 views, 15 degree cone, photoelectric share 0.3 at 140 keV
+    (so the not-absorbed factor matters).  Per class, the two totals agree
+    within 4 combined standard errors (batch means)."""
+    base = phantoms.thorax_problem("fd_thorax", 32, 1.2, 2, 4, 180.0, 32, 1.2, 1)
+    base = base.with_(accept_half_angle_rad=math.radians(15.0), pe_fraction=0.3,
+                      e_lo_kev=100.0, e_cut_kev=100.0)
+    na, nf = 500_000, 25_000           # histories per batch
+    A = _batch_totals(base.with_(n_histories=na), 8, fd=False) / na
+    F = _batch_totals(base.with_(n_histories=nf), 8, fd=True) / nf
+    ma, mf = A.mean(0), F.mean(0)
+    se = np.sqrt(A.var(0, ddof=1) / 8 + F.var(0, ddof=1) / 8)
+    assert np.all(mf > 0) and np.all(ma > 0)
+    assert np.all(np.abs(ma - mf) < 4 * se), (ma, mf, se)
+    # forced detection's estimate is far tighter per history
+    assert np.all(F.std(0) * math.sqrt(nf) < A.std(0) * math.sqrt(na))

@@ -200,8 +200,9 @@ def timed(torch, fn, steps):
 
 def extra_forms(mc, torch, args):
     """Throughput of the other forms: the point-source cube, the batched graph
-    launch over 32 uneven thoraxes, and the adjoint (forward with event list +
-    replaying gradient) on the 128^3 x 1 mm cube."""
+    launch over 32 uneven thoraxes, the adjoint (forward with event list +
+    replaying gradient) on the 128^3 x 1 mm cube, forced detection on the
+    128^3 thorax, and the large workload with reconstruction."""
     import phantoms
     out = {}
     steps = max(args.steps, 1)
@@ -249,9 +250,48 @@ def extra_forms(mc, torch, args):
                       "tallied": int(s4.n_events.item()),
                       "step": "forward with event list + Poisson-loss gradient + replaying adjoint"}
     del s4, d4, ref
+    out["forced_detection"] = fd_form(mc, torch, steps)
     if not args.no_large:
         out["large_mlem"] = large_form(mc, torch, steps)
     return out
+
+
+def fd_form(mc, torch, steps):
+    """Forced detection (Sec. 5.2) on the 128^3 thorax, 60 views, 1e7
+    histories: throughput, and the figure of merit 1 / (variance per history x
+    time per history) of the total window count against analog transport.
+    Analog variance per history is binomial, p (1 - p); the forced-detection
+    variance comes from 16 independent seeds of 1e6 histories."""
+    import phantoms
+    n = 10 ** 7
+    p = phantoms.thorax_128(n)
+    dp = mc.to_device(p)
+    fd = {"forced_detection": 1}
+    sf = mc.Simulator(dp, want_sq=True, options=fd)
+    sf.run()
+    ms_fd = timed(torch, sf.run, steps)
+    sf.check_status()
+    sa = mc.Simulator(dp, want_sq=False)
+    sa.run()
+    ms_an = timed(torch, sa.run, steps)
+    p_an = float(mc.tally_float(sa.tally).sum()) / n
+    nz_fd = int((sf.tally != 0).sum().item())
+    nz_an = int((sa.tally != 0).sum().item())
+    m = 10 ** 6
+    totals = []
+    for k in range(16):
+        sk = mc.simulate(mc.to_device(p.with_(n_histories=m, seed=2000 + k)), want_sq=False, options=fd)
+        totals.append(float(mc.tally_float(sk.tally).sum()) / m)
+    var_fd = float(np.var(totals, ddof=1)) * m
+    var_an = p_an * (1.0 - p_an)
+    t_fd, t_an = ms_fd / n, ms_an / n
+    return {"value": n / (ms_fd / 1e3), "unit": "histories/s", "ms_per_step": ms_fd,
+            "histories": n, "analog_ms_per_step": ms_an,
+            "window_count_per_history": {"forced_detection": float(np.mean(totals)), "analog": p_an},
+            "variance_per_history": {"forced_detection": var_fd, "analog": var_an},
+            "fom_gain": (var_an * t_an) / (var_fd * t_fd),
+            "nonzero_bins": {"forced_detection": nz_fd, "analog": nz_an},
+            "seeds": 16}
 
 
 def large_form(mc, torch, steps):

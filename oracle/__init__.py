@@ -92,6 +92,7 @@ def _load():
                                      P(C.c_int64), P(C.c_int64), P(C.c_int64), C.c_uint64,
                                      P(C.c_uint64)]
         lib.orc_simulate_fd.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(_Result)]
+        lib.orc_set_box_skip.argtypes = [C.c_int]
         lib.orc_kn_pdf.argtypes = [C.c_double, C.c_double]
         lib.orc_kn_pdf.restype = C.c_double
         lib.orc_ray_integral.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(C.c_double)]
@@ -246,6 +247,12 @@ def simulate_fd(prob, n_threads: int = 0):
     out["tally"] = tally
     out["tally_sq"] = tsq
     return out
+
+
+def set_box_skip(on: bool) -> None:
+    """Switch the escape shortcut for photons leaving the attenuation box
+    (on by default; tests compare against it switched off)."""
+    _load().orc_set_box_skip(1 if on else 0)
 
 
 def kn_pdf(e_kev: float, cos_t: float) -> float:

@@ -165,7 +165,15 @@ struct Setup {
     std::vector<double> nvec_x, nvec_y;  // view normals
     uint64_t q_per_view, r_extra;
     uint64_t begin, end;           // global work range
+    int box_first[3], box_last[3]; // attenuation box: voxel index range of mu > 0
+    bool box_empty;
 };
+
+// When set (the default), a photon at a tentative collision point in a voxel
+// outside the attenuation box, moving away from the box on that axis, escapes
+// at once (it could only have virtual collisions); tests switch it off to
+// check that nothing but the number of tentative collisions changes.
+bool g_box_skip = true;
 
 bool build_setup(const orc_problem* p, Setup& s) {
     s.p = p;
@@ -186,6 +194,14 @@ bool build_setup(const orc_problem* p, Setup& s) {
             s.Q[i] = (uint32_t)q;
         }
     }
+    int lo[3] = {p->nx, p->ny, p->nz}, hi[3] = {-1, -1, -1};
+    for (size_t i = 0; i < nvox; ++i) {
+        if (!(p->mu140[i] > 0.0f)) continue;
+        const int c[3] = {(int)(i % p->nx), (int)((i / p->nx) % p->ny), (int)(i / ((size_t)p->nx * p->ny))};
+        for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], c[a]); hi[a] = std::max(hi[a], c[a]); }
+    }
+    s.box_empty = hi[0] < 0;
+    for (int a = 0; a < 3; ++a) { s.box_first[a] = lo[a]; s.box_last[a] = hi[a]; }
     s.cdf.assign(nvox, 0);
     uint64_t acc = 0;
     for (size_t i = 0; i < nvox; ++i) { acc += p->activity[i]; s.cdf[i] = acc; }
@@ -244,6 +260,18 @@ bool voxel_of(const Setup& s, const double x[3], int idx[3]) {
         idx[a] = std::min(i, n[a] - 1);
     }
     return true;
+}
+
+// True if voxel idx lies outside the attenuation box on some axis and d does
+// not point back towards the box on that axis: the ray can never enter the
+// box again, so every later collision would be virtual.
+bool leaves_box(const Setup& s, const int idx[3], const double d[3]) {
+    if (s.box_empty) return false;   // no attenuation anywhere: no shortcut
+    for (int a = 0; a < 3; ++a) {
+        if (idx[a] < s.box_first[a] && d[a] <= 0.0) return true;
+        if (idx[a] > s.box_last[a] && d[a] >= 0.0) return true;
+    }
+    return false;
 }
 
 // Rotate direction d by polar angle (cos_t) and azimuth phi.
@@ -388,7 +416,12 @@ void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, Hi
         const double step = -std::log(uniform(w.r[0])) / mu_max;
         const double xn[3] = {x[0] + step * d[0], x[1] + step * d[1], x[2] + step * d[2]};
         int idx[3];
-        if (!voxel_of(s, xn, idx)) {
+        const bool in_grid = voxel_of(s, xn, idx);
+        // in the air outside the attenuation box and moving away from it, every
+        // remaining collision would be virtual: escape now along the same ray
+        const bool box_exit = in_grid && g_box_skip && leaves_box(s, idx, d);
+        if (box_exit) { x[0] = xn[0]; x[1] = xn[1]; x[2] = xn[2]; }
+        if (!in_grid || box_exit) {
             // Escape: the photon leaves the grid along d from x (last inside point).
             h.esc = e;
             const double nx = s.nvec_x[view], ny = s.nvec_y[view];
@@ -699,6 +732,9 @@ int orc_simulate_fd(const orc_problem* p, double* tally, double* tally_sq, orc_r
 }
 
 double orc_kn_pdf(double e_kev, double cos_t) { return kn_pdf(e_kev, cos_t); }
+
+// Switch the escape-from-the-attenuation-box shortcut (default on).
+void orc_set_box_skip(int on) { g_box_skip = on != 0; }
 
 // Integral of mu140 from x along d to the grid edge (exact voxel pieces).
 int orc_ray_integral(const orc_problem* p, const double x[3], const double d[3], double* out) {

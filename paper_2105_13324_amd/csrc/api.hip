@@ -137,6 +137,7 @@ ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64
     d.q8 = (uint8_t*)(ws + L.q8[i]);
     d.palette = (uint32_t*)(ws + L.pal[i]);
     d.pal_state = threshold_bytes == 4 ? 1u : 0u;
+    for (int a = 0; a < 3; ++a) { d.bb_lo[a] = INT32_MAX; d.bb_hi[a] = -1; }
     d.cdf = (uint64_t*)(ws + L.cdf[i]);
     d.vox_id = (uint32_t*)(ws + L.vid[i]);
     d.block_sums = (uint64_t*)(ws + L.bsum[i]);

@@ -89,6 +89,8 @@ struct Cst {
     const float* kn_table;
     int nx, ny, nz, source_mode;
     float hx, hy, hz, lx, ly, lz, inv_vox, vox;
+    uint32_t bbx, bby, bbz;   // attenuation box per axis: first | last voxel << 16
+    uint32_t box_margin;      // the box leaves air on some side of the grid
     int nu, nv, n_views;
     float inv_pix, radius, cos_alpha, wu, wv, e_lo, e_hi, e_cut;
     float f_pe, mu_hat, ln2_mm140, p_pe140;
@@ -108,6 +110,16 @@ __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     c.hx = d->hx; c.hy = d->hy; c.hz = d->hz;
     c.lx = d->lx; c.ly = d->ly; c.lz = d->lz;
     c.inv_vox = d->inv_vox; c.vox = d->vox;
+    if (d->bb_hi[0] >= 0) {
+        c.bbx = (uint32_t)d->bb_lo[0] | (uint32_t)d->bb_hi[0] << 16;
+        c.bby = (uint32_t)d->bb_lo[1] | (uint32_t)d->bb_hi[1] << 16;
+        c.bbz = (uint32_t)d->bb_lo[2] | (uint32_t)d->bb_hi[2] << 16;
+    } else {   // no attenuation anywhere: first 0, last 0xFFFF, so no shortcut
+        c.bbx = c.bby = c.bbz = 0xFFFF0000u;
+    }
+    c.box_margin = (c.bbx != ((uint32_t)(c.nx - 1) << 16)) | (c.bby != ((uint32_t)(c.ny - 1) << 16)) |
+                   (c.bbz != ((uint32_t)(c.nz - 1) << 16));
+    if (d->bb_hi[0] < 0) c.box_margin = 0;
     c.nu = d->nu; c.nv = d->nv; c.n_views = d->n_views;
     c.inv_pix = d->inv_pix; c.radius = d->radius; c.cos_alpha = d->cos_alpha;
     c.wu = d->wu; c.wv = d->wv; c.e_lo = d->e_lo; c.e_hi = d->e_hi; c.e_cut = d->e_cut;
@@ -153,44 +165,52 @@ __device__ inline float energy_terms(const Cst& C, float e, float& ln2_mm, float
 }
 
 struct Lane {
-    uint64_t hist;
+    uint32_t hist;      // history id within its view (< 2^32 by the problem checks)
     int view, state;
     uint32_t n, a, phi_word, emit_voxel;
     int n_scatter;
     float x, y, z, dx, dy, dz, e, ln2_mm, p_pe, vc, vs;
 };
 
-// Per-lane work counters and energies of one problem (reduced across the
-// wave on flush).  Fate counts are kept wave-wide by the kernels.  Energy is
-// booked once per history: whatever leaves the grid (escape) or is left when
-// the step cap stops it is the history's outgoing energy, the rest of the
-// 140 keV was deposited (the Compton deposits telescope).
+// Per-lane work counters of a history (replay and adjoint; the transport
+// kernel counts by wavefront ballots instead).
 struct Acc {
     uint32_t n_tent, n_real, n_kahn;
-    long long e_dep, e_esc, e_cap;
 };
 
 __device__ inline void acc_zero(Acc& A) {
     A.n_tent = A.n_real = A.n_kahn = 0;
-    A.e_dep = A.e_esc = A.e_cap = 0;
 }
 
 // keV -> Q40.23 fixed point, rounded to nearest even; |kev| < 256 fits int32.
+// A history's energy is booked once: what leaves the grid (escape) or is left
+// at the step cap is its outgoing energy; the rest of the 140 keV was
+// deposited (the Compton deposits telescope).
 __device__ __forceinline__ long long to_q23(float kev) {
     return (long long)__float2int_rn(kev * 8388608.0f);
 }
 
-// Book the energy of a finished history with fate f and final energy e.
-__device__ __forceinline__ void book_energy(Acc& A, int f, float e) {
-    const bool gone = (f == MC_ABSORBED) | (f == MC_CUT);
-    const float out = gone ? 0.0f : e;
-    A.e_dep += to_q23(140.0f - out);
-    if (f == MC_CAPPED_FATE) A.e_cap += to_q23(out);
-    else A.e_esc += to_q23(out);
-}
-
 // Outcome of one iteration.
 enum : int { R_RUNNING = -1 };
+
+// Voxel (ix, iy, iz) inside the attenuation box.
+__device__ inline bool in_box(const Cst& C, int ix, int iy, int iz) {
+    return ((uint32_t)(ix - (int)(C.bbx & 0xFFFFu)) <= (uint32_t)((int)(C.bbx >> 16) - (int)(C.bbx & 0xFFFFu))) &
+           ((uint32_t)(iy - (int)(C.bby & 0xFFFFu)) <= (uint32_t)((int)(C.bby >> 16) - (int)(C.bby & 0xFFFFu))) &
+           ((uint32_t)(iz - (int)(C.bbz & 0xFFFFu)) <= (uint32_t)((int)(C.bbz >> 16) - (int)(C.bbz & 0xFFFFu)));
+}
+
+// Voxel (ix, iy, iz) outside the attenuation box on some axis with the
+// direction not pointing back towards the box on that axis: the ray never
+// enters the box again, so every later collision would be virtual.
+__device__ inline bool leaves_box(const Cst& C, int ix, int iy, int iz, float dx, float dy, float dz) {
+    const int x0 = (int)(C.bbx & 0xFFFFu), x1 = (int)(C.bbx >> 16);
+    const int y0 = (int)(C.bby & 0xFFFFu), y1 = (int)(C.bby >> 16);
+    const int z0 = (int)(C.bbz & 0xFFFFu), z1 = (int)(C.bbz >> 16);
+    return ((ix < x0) & (dx <= 0.0f)) | ((ix > x1) & (dx >= 0.0f)) |
+           ((iy < y0) & (dy <= 0.0f)) | ((iy > y1) & (dy >= 0.0f)) |
+           ((iz < z0) & (dz <= 0.0f)) | ((iz > z1) & (dz >= 0.0f));
+}
 
 // Per-lane escape: collimator, detector bin, window.  Returns the fate; sets iu, iv.
 __device__ inline int escape(const Cst& C, const Lane& L, int& iu, int& iv) {
@@ -377,6 +397,12 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
         const int ix = min((int)(tx * C.inv_vox), C.nx - 1);
         const int iy = min((int)(ty * C.inv_vox), C.ny - 1);
         const int iz = min((int)(tz * C.inv_vox), C.nz - 1);
+        if (C.box_margin && leaves_box(C, ix, iy, iz, L.dx, L.dy, L.dz)) {
+            // in the air outside the attenuation box, moving away from it:
+            // every later collision would be virtual, so escape now along this ray
+            L.x = xn; L.y = yn; L.z = zn;
+            return escape(C, L, iu, iv);
+        }
         const uint32_t k = brick_index((uint32_t)ix, (uint32_t)iy, (uint32_t)iz, (uint32_t)C.nx,
                                        (uint32_t)C.ny, C.brick, C.bmask, C.nbx, C.nby);
         const uint32_t q = C.use_pal ? pal[ldg(C.q8 + k)] : ldg(C.q32 + k);
@@ -453,7 +479,11 @@ struct FdPoint {
 
 // Integral of mu140 along p + t o (t >= 0, o a unit vector) to the grid edge:
 // voxel walk (Amanatides & Woo 1987) with the advancing axis chosen by
-// selects, so the lanes of a wavefront stay together.
+// selects, so the lanes of a wavefront stay together.  The walk runs
+// RAY_BATCH crossings of pure arithmetic, then issues their RAY_BATCH mu
+// gathers together, so the gathers' latencies overlap.
+constexpr int RAY_BATCH = 8;
+
 __device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox, float oy, float oz) {
     const float px = x + C.hx, py = y + C.hy, pz = z + C.hz;
     int ix = min(max((int)(px * C.inv_vox), 0), C.nx - 1);
@@ -470,25 +500,49 @@ __device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox
     const float ex = ox > 0.0f ? (C.lx - px) / ox : (ox < 0.0f ? -px / ox : inf);
     const float ey = oy > 0.0f ? (C.ly - py) / oy : (oy < 0.0f ? -py / oy : inf);
     const float ez = oz > 0.0f ? (C.lz - pz) / oz : (oz < 0.0f ? -pz / oz : inf);
-    const float t_exit = fmaxf(fminf(ex, fminf(ey, ez)), 0.0f);
+    float t_exit = fmaxf(fminf(ex, fminf(ey, ez)), 0.0f);
+    if (in_box(C, ix, iy, iz)) {
+        // mu is zero outside the attenuation box: stop where the ray leaves it
+        const float bx = ox > 0.0f ? ((float)((C.bbx >> 16) + 1u) * C.vox - px) / ox
+                                   : (ox < 0.0f ? ((float)(C.bbx & 0xFFFFu) * C.vox - px) / ox : inf);
+        const float by = oy > 0.0f ? ((float)((C.bby >> 16) + 1u) * C.vox - py) / oy
+                                   : (oy < 0.0f ? ((float)(C.bby & 0xFFFFu) * C.vox - py) / oy : inf);
+        const float bz = oz > 0.0f ? ((float)((C.bbz >> 16) + 1u) * C.vox - pz) / oz
+                                   : (oz < 0.0f ? ((float)(C.bbz & 0xFFFFu) * C.vox - pz) / oz : inf);
+        t_exit = fminf(t_exit, fmaxf(fminf(bx, fminf(by, bz)), 0.0f));
+    }
     const int stx = sx, sty = sy * C.nx, stz = sz * C.nx * C.ny;
     int v = ix + C.nx * (iy + C.ny * iz);
     float t = 0.0f, sum = 0.0f;
-    const int max_iter = C.nx + C.ny + C.nz + 3;
-    for (int it = 0; it < max_iter; ++it) {
-        const float tn = fminf(tx, fminf(ty, tz));
-        const float te = fminf(tn, t_exit);
-        sum = fmaf(ldg(C.mu + v), te - t, sum);
-        if (tn >= t_exit) break;
-        t = tn;
-        const bool bx = (tx <= ty) & (tx <= tz);
-        const bool by = !bx & (ty <= tz);
-        const bool bz = !bx & !by;
-        ix += bx ? sx : 0; iy += by ? sy : 0; iz += bz ? sz : 0;
-        tx += bx ? ddx : 0.0f; ty += by ? ddy : 0.0f; tz += bz ? ddz : 0.0f;
-        v += bx ? stx : (by ? sty : stz);
-        if (((unsigned)ix >= (unsigned)C.nx) | ((unsigned)iy >= (unsigned)C.ny) |
-            ((unsigned)iz >= (unsigned)C.nz)) break;
+    bool done = false;
+    const int max_batches = (C.nx + C.ny + C.nz + 3) / RAY_BATCH + 1;
+    for (int it = 0; it < max_batches; ++it) {
+        int vb[RAY_BATCH];
+        float lb[RAY_BATCH];
+#pragma unroll
+        for (int k = 0; k < RAY_BATCH; ++k) {
+            // piece k: voxel v from t to min(next plane, exit); a finished
+            // lane repeats its last (valid) voxel with length 0
+            const float tn = fminf(tx, fminf(ty, tz));
+            vb[k] = v;
+            lb[k] = done ? 0.0f : fminf(tn, t_exit) - t;
+            const bool bx = (tx <= ty) & (tx <= tz);
+            const bool by = !bx & (ty <= tz);
+            const bool bz = !bx & !by;
+            const int nix = ix + (bx ? sx : 0), niy = iy + (by ? sy : 0), niz = iz + (bz ? sz : 0);
+            const bool out = ((unsigned)nix >= (unsigned)C.nx) | ((unsigned)niy >= (unsigned)C.ny) |
+                             ((unsigned)niz >= (unsigned)C.nz);
+            done = done | (tn >= t_exit) | out;
+            if (!done) {
+                t = tn;
+                ix = nix; iy = niy; iz = niz;
+                tx += bx ? ddx : 0.0f; ty += by ? ddy : 0.0f; tz += bz ? ddz : 0.0f;
+                v += bx ? stx : (by ? sty : stz);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RAY_BATCH; ++k) sum = fmaf(ldg(C.mu + vb[k]), lb[k], sum);
+        if (done) break;
     }
     return sum;
 }

@@ -56,6 +56,7 @@ struct ProbDesc {
                                     // or more than PALETTE_N distinct values, set by staging)
     float omc_alpha;                // 1 - cos(alpha), from double precision (forced detection)
     uint32_t pad2;
+    int32_t bb_lo[3], bb_hi[3];     // attenuation box: voxel index range of mu > 0 (staging)
 };
 
 // Emission bucket b covers t in [b << shift, (b + 1) << shift) of the integer

@@ -1,7 +1,8 @@
 // Input staging: from the caller's attenuation and activity maps to the tables
 // the transport kernels read.
 //
-//  * max mu, input validation and the activity total (one reduction pass);
+//  * max mu, input validation, the activity total and the attenuation box
+//    (the voxel index range of mu > 0) in one reduction pass;
 //  * accept thresholds Q_v = ceil(mu_v 2^24 / max mu) in double precision, so
 //    the real/virtual decision of Woodcock tracking is an exact integer compare;
 //    when the map has at most 256 distinct thresholds (segmented phantoms have
@@ -50,31 +51,56 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* pd) {
     const uint64_t nvox = pd->nvox;
     const float* __restrict__ mu = pd->mu;
     const uint32_t* __restrict__ act = pd->act;
+    const uint32_t nx = (uint32_t)pd->nx, ny = (uint32_t)pd->ny;
     uint32_t mx = 0, flags = 0;
     uint64_t sum = 0;
+    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {-1, -1, -1};
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const float m = mu[i];
         if (!(m >= 0.0f) || !isfinite(m)) flags |= MC_STATUS_BAD_MU;
-        else if (m > 0.0f) mx = max(mx, __float_as_uint(m));
+        else if (m > 0.0f) {
+            mx = max(mx, __float_as_uint(m));
+            const uint32_t i32 = (uint32_t)i, row = i32 / nx;   // nvox < 2^31: 32-bit division
+            const int c[3] = {(int)(i32 - row * nx), (int)(row % ny), (int)(row / ny)};
+            for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], c[a]); hi[a] = max(hi[a], c[a]); }
+        }
         sum += act[i];
     }
     mx = wave_max_u32(mx);
     flags = wave_or_u32(flags);
     sum = wave_sum_u64(sum);
+    for (int a = 0; a < 3; ++a) {
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[a] = min(lo[a], __shfl_xor(lo[a], o, 64));
+            hi[a] = max(hi[a], __shfl_xor(hi[a], o, 64));
+        }
+    }
+
     // one atomic per block: same-address atomics serialise in L2
     __shared__ uint32_t s_mx[RED_THREADS / 64], s_fl[RED_THREADS / 64];
     __shared__ uint64_t s_sum[RED_THREADS / 64];
+    __shared__ int s_lo[RED_THREADS / 64][3], s_hi[RED_THREADS / 64][3];
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { s_mx[w] = mx; s_fl[w] = flags; s_sum[w] = sum; }
+    if ((threadIdx.x & 63) == 0) {
+        s_mx[w] = mx; s_fl[w] = flags; s_sum[w] = sum;
+        for (int a = 0; a < 3; ++a) { s_lo[w][a] = lo[a]; s_hi[w][a] = hi[a]; }
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int k = 1; k < RED_THREADS / 64; ++k) {
             mx = max(mx, s_mx[k]); flags |= s_fl[k]; sum += s_sum[k];
+            for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], s_lo[k][a]); hi[a] = max(hi[a], s_hi[k][a]); }
         }
         atomicMax(&pd->mu_hat_bits, mx);
         if (flags) atomicOr(&pd->flags, flags);
         atomicAdd((unsigned long long*)&pd->total, (unsigned long long)sum);
+        if (hi[0] >= 0) {
+            for (int a = 0; a < 3; ++a) {
+                atomicMin(&pd->bb_lo[a], lo[a]);
+                atomicMax(&pd->bb_hi[a], hi[a]);
+            }
+        }
     }
     if (blockIdx.x == 0) {
         if (pd->pal_state == 0)
@@ -122,7 +148,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* pd) {
             double t = ceil((double)mv * 16777216.0 / (double)mu_hat);
             v = t >= 16777216.0 ? 16777216u : (uint32_t)t;
         }
-        const uint32_t ix = (uint32_t)(i % nx), iy = (uint32_t)((i / nx) % ny), iz = (uint32_t)(i / ((uint64_t)nx * ny));
+        const uint32_t i32 = (uint32_t)i, row = i32 / nx;   // nvox < 2^31: 32-bit division
+        const uint32_t ix = i32 - row * nx, iy = row % ny, iz = row / ny;
         q[brick_index(ix, iy, iz, nx, ny, b, m, nbx, nby)] = v;
         if (pal && !full) {
             bool todo = true;
@@ -154,7 +181,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_codes(ProbDesc* pd) {
     const uint32_t nbx = (uint32_t)pd->nbx, nby = (uint32_t)pd->nby;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t ix = (uint32_t)(i % nx), iy = (uint32_t)((i / nx) % ny), iz = (uint32_t)(i / ((uint64_t)nx * ny));
+        const uint32_t i32 = (uint32_t)i, row = i32 / nx;   // nvox < 2^31: 32-bit division
+        const uint32_t ix = i32 - row * nx, iy = row % ny, iz = row / ny;
         const uint32_t k = brick_index(ix, iy, iz, nx, ny, b, m, nbx, nby);
         const uint32_t v = q[k];
         uint32_t h = palette_hash(v);

@@ -43,10 +43,12 @@ __device__ __forceinline__ long long wsum64(long long v) {
 }
 
 // Wave-wide flush of one problem's accumulators (all 64 lanes must call).
-// fc: wave-uniform fate counts.
-__device__ inline void flush(Acc& A, uint32_t* fc, int p, const TransportArgs& T, int lane) {
-    const uint32_t nt = wsum32(A.n_tent), nr = wsum32(A.n_real), nk = wsum32(A.n_kahn);
-    const long long ed = wsum64(A.e_dep), ee = wsum64(A.e_esc), ec = wsum64(A.e_cap);
+// fc: wave-uniform fate counts; wc: wave-uniform tentative collisions, real
+// collisions, Kahn attempts; e_esc: the lane's escaped energy (Q40.23).  The
+// deposited energy is filled in after the kernel (k_finalize).
+__device__ inline void flush(long long& e_esc, uint32_t* fc, uint32_t* wc, int p,
+                             const TransportArgs& T, int lane) {
+    const long long ee = wsum64(e_esc);
     uint32_t nh = 0;
 #pragma unroll
     for (int i = 0; i < 7; ++i) nh += fc[i];
@@ -54,17 +56,12 @@ __device__ inline void flush(Acc& A, uint32_t* fc, int p, const TransportArgs& T
         unsigned long long* fa = (unsigned long long*)(T.fates + (size_t)p * MC_N_FATES);
 #pragma unroll
         for (int i = 0; i < 7; ++i) if (fc[i]) atomicAdd(fa + i, (unsigned long long)fc[i]);
-        if (T.energy) {
-            unsigned long long* ea = (unsigned long long*)(T.energy + (size_t)p * 4);
-            atomicAdd(ea + 0, (unsigned long long)ed);
-            atomicAdd(ea + 1, (unsigned long long)ee);
-            atomicAdd(ea + 2, (unsigned long long)ec);
-        }
+        if (T.energy) atomicAdd((unsigned long long*)(T.energy + (size_t)p * 4 + 1), (unsigned long long)ee);
         if (T.counters) {
             unsigned long long* ca = (unsigned long long*)(T.counters + (size_t)p * 4);
-            atomicAdd(ca + 0, (unsigned long long)nt);
-            atomicAdd(ca + 1, (unsigned long long)nr);
-            atomicAdd(ca + 2, (unsigned long long)nk);
+            atomicAdd(ca + 0, (unsigned long long)wc[0]);
+            atomicAdd(ca + 1, (unsigned long long)wc[1]);
+            atomicAdd(ca + 2, (unsigned long long)wc[2]);
             atomicAdd(ca + 3, (unsigned long long)nh);
         }
         if (fc[MC_CAPPED_FATE]) {
@@ -72,9 +69,10 @@ __device__ inline void flush(Acc& A, uint32_t* fc, int p, const TransportArgs& T
             atomicAdd((unsigned long long*)(T.status + 1), (unsigned long long)fc[MC_CAPPED_FATE]);
         }
     }
-    acc_zero(A);
+    e_esc = 0;
 #pragma unroll
     for (int i = 0; i < 7; ++i) fc[i] = 0;
+    wc[0] = wc[1] = wc[2] = 0;
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -134,10 +132,12 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
     bool exhausted = false, have_pending = false;
     uint64_t pending = 0;
     uint32_t fc[7] = {0, 0, 0, 0, 0, 0, 0};   // wave-uniform fate counts
+    uint32_t wc[3] = {0, 0, 0};               // wave-uniform work counters
+    long long e_esc = 0;                      // escaped energy, Q40.23 (per lane)
     Cst C;
     Lane L;
     L.state = S_IDLE;
-    Acc A;
+    Acc A;            // advance()'s per-lane counters: unused here (counted by ballots)
     acc_zero(A);
     // chunk prefix lives after the work prefix: [n_problems + 1] entries
     const uint64_t* __restrict__ chunk_prefix = T.work_prefix + (T.n_problems + 1);
@@ -177,7 +177,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                                     if (p >= 0 && fd_tail != fd_head)
                                         fd_drain(C, p, ring, fd_head, fd_tail - fd_head, lane, T);
                                 }
-                                if (p >= 0) flush(A, fc, p, T, lane);
+                                if (p >= 0) flush(e_esc, fc, wc, p, T, lane);
                                 p = np;
                                 C = load_cst(T.descs + p);
                                 if (C.use_pal) {
@@ -253,16 +253,31 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
 
         int fate = R_RUNNING;
         int iu = -1, iv = -1;
-        bool real = false;
-        if (L.state != S_IDLE) {
-            uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
+        const int before = L.state;
+        if (before != S_IDLE) {
+            uint32_t c0 = L.hist, c1 = (uint32_t)L.view, c2, c3;
             counter_of(L, c2, c3);
             philox10(c0, c1, c2, c3, C.seed, C.pid);
-            const uint32_t n_real0 = A.n_real;
             fate = advance(C, my_pal, L, c0, c1, c2, c3, A, iu, iv);
-            if (fate != R_RUNNING) book_energy(A, fate, L.e);
-            if constexpr (FD) real = A.n_real != n_real0;
+            if (fate != R_RUNNING) {
+                // outgoing energy: escaped, or left at the step cap (rare: booked at once)
+                const float out = (fate == MC_ABSORBED) | (fate == MC_CUT) ? 0.0f : L.e;
+                if (fate == MC_CAPPED_FATE) {
+                    if (T.energy)
+                        atomicAdd((unsigned long long*)(T.energy + (size_t)p * 4 + 2),
+                                  (unsigned long long)to_q23(out));
+                } else {
+                    e_esc += to_q23(out);
+                }
+            }
         }
+        // work counters by ballot: a tentative collision unless the step cap
+        // stopped it; a real one if it absorbed or started a Compton scatter
+        const bool real = (before == S_STEP) &
+                          ((fate == MC_ABSORBED) | ((fate == R_RUNNING) & (L.state == S_KAHN)));
+        wc[0] += (uint32_t)__popcll(__ballot((before == S_STEP) & (fate != MC_CAPPED_FATE)));
+        wc[1] += (uint32_t)__popcll(__ballot(real));
+        wc[2] += (uint32_t)__popcll(__ballot(before == S_KAHN));
         if constexpr (FD) {
             // real collisions queue their forced copies (position, direction
             // and energy before the collision are still the lane's)
@@ -271,7 +286,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                 if (real) {
                     FdPoint q;
                     q.x = L.x; q.y = L.y; q.z = L.z; q.dx = L.dx; q.dy = L.dy; q.dz = L.dz;
-                    q.e = L.e; q.view = (uint32_t)L.view; q.hist = (uint32_t)L.hist; q.event = L.n;
+                    q.e = L.e; q.view = (uint32_t)L.view; q.hist = L.hist; q.event = L.n;
                     ring[(fd_tail + (uint32_t)__popcll(m & lane_lt)) & (FD_RING - 1)] = q;
                 }
                 fd_tail += (uint32_t)__popcll(m);
@@ -306,7 +321,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
     if constexpr (FD) {
         if (p >= 0 && fd_tail != fd_head) fd_drain(C, p, ring, fd_head, fd_tail - fd_head, lane, T);
     }
-    if (p >= 0) flush(A, fc, p, T, lane);
+    if (p >= 0) flush(e_esc, fc, wc, p, T, lane);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TransportArgs T) {
@@ -332,11 +347,11 @@ __global__ __launch_bounds__(256) void k_replay(const ProbDesc* __restrict__ d,
     const Cst C = load_cst(d);
     if (i >= n) return;
     Lane L;
-    L.hist = hists[i];
+    L.hist = (uint32_t)hists[i];
     L.view = views[i];
     L.n = 0; L.n_scatter = 0; L.emit_voxel = 0;
     L.e = 0.0f;
-    const bool view_ok = L.view >= 0 && L.view < d->n_views;
+    const bool view_ok = L.view >= 0 && L.view < d->n_views && hists[i] <= 0xFFFFFFFFull;
     Acc A;
     acc_zero(A);
     mc_record r;
@@ -406,13 +421,22 @@ __global__ __launch_bounds__(256) void k_prepare(const ProbDesc* __restrict__ de
 
 // After transport: fold staging flags and list overflow into status.
 __global__ void k_finalize(const ProbDesc* __restrict__ descs, int n_problems, int64_t* status,
-                           const unsigned long long* n_events, uint64_t capacity) {
+                           const unsigned long long* n_events, uint64_t capacity,
+                           const int64_t* fates, int64_t* energy) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     uint64_t f = 0;
     int64_t n_pal = 0;
     for (int p = 0; p < n_problems; ++p) {
         f |= descs[p].flags;
         n_pal += descs[p].pal_state == 0;
+        if (energy) {
+            // every history started with 140 keV: what did not leave (escaped
+            // or capped) was deposited
+            int64_t nh = 0;
+            for (int k = 0; k < MC_N_FATES; ++k) nh += fates[(size_t)p * MC_N_FATES + k];
+            int64_t* e = energy + (size_t)p * 4;
+            e[0] = nh * (int64_t)(140ll << 23) - e[1] - e[2];
+        }
     }
     if (n_events && capacity != UINT64_MAX && *n_events > capacity) f |= MC_STATUS_LIST_OVERFLOW;
     status[0] |= (int64_t)f;
@@ -443,7 +467,7 @@ hipError_t launch_transport(const TransportArgs& a, int grid, int block, hipStre
     else k_transport<<<grid, block, 0, s>>>(a);
     // without a list the count is informational and cannot overflow
     k_finalize<<<1, 64, 0, s>>>(a.descs, a.n_problems, a.status, a.n_events,
-                                a.events ? a.event_capacity : UINT64_MAX);
+                                a.events ? a.event_capacity : UINT64_MAX, a.fates, a.energy);
     return hipGetLastError();
 }
 
@@ -454,7 +478,7 @@ hipError_t launch_replay(const ProbDesc* d_desc, const int32_t* views, const uin
         const int64_t g = (n + block - 1) / block;
         k_replay<<<(int)g, block, 0, s>>>(d_desc, views, hists, n, out);
     }
-    k_finalize<<<1, 64, 0, s>>>(d_desc, 1, status, nullptr, 0);
+    k_finalize<<<1, 64, 0, s>>>(d_desc, 1, status, nullptr, 0, nullptr, nullptr);
     return hipGetLastError();
 }
 

@@ -665,3 +665,28 @@ def test_fd_unbiased_against_analog():
     assert np.all(np.abs(ma - mf) < 4 * se), (ma, mf, se)
     # forced detection's estimate is far tighter per history
     assert np.all(F.std(0) * math.sqrt(nf) < A.std(0) * math.sqrt(na))
+
+
+def test_box_escape_shortcut_changes_only_step_counts():
+    """Photons in a voxel outside the attenuation box and moving away from it
+    escape at once: with the shortcut switched off every replayed history ends
+    with the same fate, bin, scatter count and energy, and only the number of
+    tentative collisions drops (here by a quarter) when it is on."""
+    p = phantoms.thorax_problem("box", 48, 0.8, 2, 12, 180.0, 32, 1.2, 200_000)
+    rng = np.random.Generator(np.random.PCG64(13))
+    views = rng.integers(0, p.n_views, 20_000).astype(np.int32)
+    hists = rng.integers(0, p.n_histories // p.n_views, 20_000).astype(np.uint64)
+    try:
+        oracle.set_box_skip(False)
+        a = oracle.replay(p, views, hists)
+        ra = oracle.simulate(p)
+    finally:
+        oracle.set_box_skip(True)
+    b = oracle.replay(p, views, hists)
+    rb = oracle.simulate(p)
+    for f in ("fate", "iu", "iv", "n_scatter", "emit_voxel", "cls", "e_final"):
+        np.testing.assert_array_equal(a[f], b[f])
+    assert np.all(b["n_tent"] <= a["n_tent"])
+    np.testing.assert_array_equal(ra["tally"], rb["tally"])
+    np.testing.assert_array_equal(ra["fates"], rb["fates"])
+    assert rb["n_tent"] < 0.85 * ra["n_tent"]

@@ -21,6 +21,8 @@
 //
 // Every pass streams the grid once with coalesced loads; the whole staging of
 // a 128^3 phantom moves ~40 MB and is far below the transport cost.
+#include <algorithm>
+
 #include "mc_internal.h"
 
 namespace mcs {
@@ -55,18 +57,24 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* pd) {
     uint32_t mx = 0, flags = 0;
     uint64_t sum = 0;
     int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {-1, -1, -1};
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const float m = mu[i];
-        if (!(m >= 0.0f) || !isfinite(m)) flags |= MC_STATUS_BAD_MU;
-        else if (m > 0.0f) {
-            mx = max(mx, __float_as_uint(m));
-            const uint32_t i32 = (uint32_t)i, row = i32 / nx;   // nvox < 2^31: 32-bit division
-            const int c[3] = {(int)(i32 - row * nx), (int)(row % ny), (int)(row / ny)};
-            for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], c[a]); hi[a] = max(hi[a], c[a]); }
+    // one grid row (iy, iz) per block step, threads along x: no index division
+    const uint32_t nrows = ny * (uint32_t)pd->nz;
+    for (uint32_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+        const int iy = (int)(r % ny), iz = (int)(r / ny);
+        for (uint32_t ix = threadIdx.x; ix < nx; ix += blockDim.x) {
+            const uint64_t i = (uint64_t)r * nx + ix;
+            const float m = mu[i];
+            if (!(m >= 0.0f) || !isfinite(m)) flags |= MC_STATUS_BAD_MU;
+            else if (m > 0.0f) {
+                mx = max(mx, __float_as_uint(m));
+                lo[0] = min(lo[0], (int)ix); hi[0] = max(hi[0], (int)ix);
+                lo[1] = min(lo[1], iy); hi[1] = max(hi[1], iy);
+                lo[2] = min(lo[2], iz); hi[2] = max(hi[2], iz);
+            }
+            sum += act[i];
         }
-        sum += act[i];
     }
+    (void)nvox;
     mx = wave_max_u32(mx);
     flags = wave_or_u32(flags);
     sum = wave_sum_u64(sum);
@@ -88,7 +96,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* pd) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < RED_THREADS / 64; ++k) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
             mx = max(mx, s_mx[k]); flags |= s_fl[k]; sum += s_sum[k];
             for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], s_lo[k][a]); hi[a] = max(hi[a], s_hi[k][a]); }
         }
@@ -140,16 +148,17 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* pd) {
     const uint32_t nbx = (uint32_t)pd->nbx, nby = (uint32_t)pd->nby;
     const bool pal = pd->pal_state == 0;
     bool full = false;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const float mv = mu[i];
+    const uint32_t nrows = ny * (uint32_t)pd->nz;
+    (void)nvox;
+    for (uint32_t r = blockIdx.x; r < nrows; r += gridDim.x)
+    for (uint32_t ix = threadIdx.x; ix < nx; ix += blockDim.x) {
+        const uint32_t iy = r % ny, iz = r / ny;
+        const float mv = mu[(uint64_t)r * nx + ix];
         uint32_t v = 0;
         if (mu_hat > 0.0f && mv > 0.0f) {
             double t = ceil((double)mv * 16777216.0 / (double)mu_hat);
             v = t >= 16777216.0 ? 16777216u : (uint32_t)t;
         }
-        const uint32_t i32 = (uint32_t)i, row = i32 / nx;   // nvox < 2^31: 32-bit division
-        const uint32_t ix = i32 - row * nx, iy = row % ny, iz = row / ny;
         q[brick_index(ix, iy, iz, nx, ny, b, m, nbx, nby)] = v;
         if (pal && !full) {
             bool todo = true;
@@ -179,10 +188,11 @@ __global__ __launch_bounds__(RED_THREADS) void k_codes(ProbDesc* pd) {
     const int b = pd->brick_log2;
     const uint32_t m = (1u << b) - 1u;
     const uint32_t nbx = (uint32_t)pd->nbx, nby = (uint32_t)pd->nby;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvox;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t i32 = (uint32_t)i, row = i32 / nx;   // nvox < 2^31: 32-bit division
-        const uint32_t ix = i32 - row * nx, iy = row % ny, iz = row / ny;
+    const uint32_t nrows = ny * (uint32_t)pd->nz;
+    (void)nvox;
+    for (uint32_t r = blockIdx.x; r < nrows; r += gridDim.x)
+    for (uint32_t ix = threadIdx.x; ix < nx; ix += blockDim.x) {
+        const uint32_t iy = r % ny, iz = r / ny;
         const uint32_t k = brick_index(ix, iy, iz, nx, ny, b, m, nbx, nby);
         const uint32_t v = q[k];
         uint32_t h = palette_hash(v);
@@ -397,9 +407,12 @@ uint64_t guide_capacity(uint64_t nvox) {
 hipError_t launch_staging(ProbDesc* d, const ProbDesc& h, hipStream_t st) {
     const uint64_t nvox = h.nvox;
     k_write_desc<<<1, 64, 0, st>>>(h, d);
-    k_reduce<<<grid_for(nvox, RED_THREADS, 512), RED_THREADS, 0, st>>>(d);
-    k_thresholds<<<grid_for(nvox, RED_THREADS, 8192), RED_THREADS, 0, st>>>(d);
-    k_codes<<<grid_for(nvox, RED_THREADS, 8192), RED_THREADS, 0, st>>>(d);
+    // row-per-block passes: a block walks grid rows (iy, iz), threads along x
+    const int row_threads = (int)std::min<uint64_t>(RED_THREADS, ((uint64_t)h.nx + 63) / 64 * 64);
+    const uint64_t nrows = (uint64_t)h.ny * h.nz;
+    k_reduce<<<(int)std::min<uint64_t>(nrows, 512), row_threads, 0, st>>>(d);
+    k_thresholds<<<(int)std::min<uint64_t>(nrows, 8192), row_threads, 0, st>>>(d);
+    k_codes<<<(int)std::min<uint64_t>(nrows, 8192), row_threads, 0, st>>>(d);
     const int nb = (int)((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS);
     k_scan_sums<<<nb, SCAN_THREADS, 0, st>>>(d);
     k_scan_top<<<1, 1024, 0, st>>>(d, nb);

@@ -39,7 +39,7 @@ OPS_END = 35              # collimator, detector bin, window, bookkeeping
 # counters read for a plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); keyed
 # by a hash of the kernel sources so a changed kernel reports null.
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
-TRAFFIC_KIB = {"2e23e39c0d702a47": {"fetch": 5927373.125, "write": 5518.28125}}
+TRAFFIC_KIB = {"b645066227e343da": {"fetch": 4688408.5625, "write": 5326.25}}
 
 
 def kernel_source_hash() -> str:

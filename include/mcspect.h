@@ -123,11 +123,14 @@ typedef struct {
                                 /* kernel (NULL: none)                          */
 } mc_options;
 
-/* A tallied history, as written to the optional event list. */
+/* One tally contribution, as written to the optional event list: a tallied
+ * history (analog), or one forced-detection score. */
 typedef struct {
     uint64_t work;        /* call-global work index (problems concatenated)     */
     uint32_t bin;         /* bin within its problem: ((view*2+cls)*nv+iv)*nu+iu */
     uint32_t emit_voxel;  /* phantom voxel of emission                          */
+    int64_t weight;       /* contribution to the bin, Q31.32: 1 << 32 for an    */
+                          /* analog arrival, the score for a forced copy        */
 } mc_event;
 
 /* Per-history record written by mc_replay_histories. */
@@ -177,7 +180,10 @@ size_t mc_workspace_bytes(const mc_problem* problems, int32_t n_problems,
  * score when E' is cut, outside the window or the ray misses the detector.
  * The expected score of every bin equals its expected analog count.  The
  * tally stays Q31.32; tally_sq holds the sum of squared scores in Q11.52.
- * Events must be NULL (MC_EINVAL otherwise). */
+ * The event list, if given, holds one event per nonzero score (its weight is
+ * the score; n_events counts them), so mc_system_matrix builds the forced-
+ * detection response matrix from it; without a list n_events stays 0.
+ * mc_adjoint_mu takes analog event lists only. */
 int mc_simulate_projections(const mc_problem* problems, int32_t n_problems,
                             const mc_options* opt,
                             int64_t* tally, int64_t* tally_sq, int64_t* fates,
@@ -220,8 +226,10 @@ size_t mc_system_matrix_workspace_bytes(const mc_problem* problem, uint64_t even
 
 /* Monte Carlo response matrix of Sec. 5.1 (Eq. IMC) from a forward call's
  * event list: T_ij = c_ij / n_i(j), the estimated probability that a photon
- * emitted in image voxel i is counted in projection bin j; c_ij counts the
- * tallied histories emitted in i and counted in j, n_i(j) = N_view(j) A_i / A
+ * emitted in image voxel i is counted in projection bin j; c_ij sums the
+ * weights of the events emitted in i and counted in j (the number of tallied
+ * histories for an analog list, forced-detection scores for a forced-
+ * detection list), n_i(j) = N_view(j) A_i / A
  * the expected emissions from i towards bin j's view (A_i: activity of image
  * voxel i, A: total).  Image voxel = phantom voxel / image_factor per axis
  * (image_factor >= 1).  Bins merge the primary and scatter classes:
@@ -230,6 +238,8 @@ size_t mc_system_matrix_workspace_bytes(const mc_problem* problem, uint64_t even
  *   T_rowptr   device int64 [n_bins + 1];  T_col int32, T_val float [capacity]
  *   Tt_rowptr  device int64 [n_img + 1];   Tt_col int32, Tt_val float [capacity]
  *   proj       device float [n_bins]: P_j = sum_i c_ij (nullable)
+ * c_ij is summed in Q31.32 integers, so the result does not depend on the
+ * order of the list.
  * nnz = T_rowptr[n_bins] = Tt_rowptr[n_img] <= min(*n_events, capacity).
  * events / n_events / event_capacity: as returned by mc_simulate_projections
  * for this problem.  class_mask selects the tallied histories used: bit 0

@@ -91,7 +91,9 @@ def _load():
         lib.orc_simulate.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(_Result),
                                      P(C.c_int64), P(C.c_int64), P(C.c_int64), C.c_uint64,
                                      P(C.c_uint64)]
-        lib.orc_simulate_fd.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(_Result)]
+        lib.orc_simulate_fd.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(_Result),
+                                        P(C.c_int64), P(C.c_int64), P(C.c_double), P(C.c_int64),
+                                        C.c_uint64, P(C.c_uint64)]
         lib.orc_set_box_skip.argtypes = [C.c_int]
         lib.orc_kn_pdf.argtypes = [C.c_double, C.c_double]
         lib.orc_kn_pdf.restype = C.c_double
@@ -230,22 +232,37 @@ def simulate(prob, n_threads: int = 0, want_triplets: bool = False, trip_cap: in
     return out
 
 
-def simulate_fd(prob, n_threads: int = 0):
+def simulate_fd(prob, n_threads: int = 0, want_triplets: bool = False, trip_cap: int = 1 << 24):
     """Forced-detection forward simulation (Sec. 5.2): the analog histories'
     fates, energies and counters, and the forced-detection tally and the sum
-    of squared scores ([V,2,nv,nu], FP64)."""
+    of squared scores ([V,2,nv,nu], FP64); with want_triplets, per nonzero
+    score its image voxel of emission (trip_i), bin (trip_j), score (trip_w)
+    and work index relative to history_offset (trip_g)."""
     lib = _load()
     p, keep = _make_problem(prob, n_threads)
     tally = np.zeros(prob.tally_shape, dtype=np.float64)
     tsq = np.zeros(prob.tally_shape, dtype=np.float64)
     res = _Result()
+    ti = tj = tg = tw = None
+    ntrip = C.c_uint64(0)
+    if want_triplets:
+        ti = np.empty(trip_cap, dtype=np.int64)
+        tj = np.empty(trip_cap, dtype=np.int64)
+        tg = np.empty(trip_cap, dtype=np.int64)
+        tw = np.empty(trip_cap, dtype=np.float64)
     rc = lib.orc_simulate_fd(C.byref(p), _ptr(tally, C.c_double), _ptr(tsq, C.c_double),
-                             C.byref(res))
+                             C.byref(res), _ptr(ti, C.c_int64), _ptr(tj, C.c_int64),
+                             _ptr(tw, C.c_double), _ptr(tg, C.c_int64),
+                             trip_cap if want_triplets else 0, C.byref(ntrip))
     if rc != 0:
         raise RuntimeError(f"orc_simulate_fd failed ({rc})")
     out = _result_dict(res)
     out["tally"] = tally
     out["tally_sq"] = tsq
+    if want_triplets:
+        n = ntrip.value
+        for k, a in (("trip_i", ti), ("trip_j", tj), ("trip_w", tw), ("trip_g", tg)):
+            out[k] = a[:n].copy()
     return out
 
 
@@ -327,12 +344,14 @@ def poisson_loss_grad(lam: np.ndarray, y: np.ndarray, eps: float):
 # Response matrix and MLEM (Sec. 5.1)
 # ---------------------------------------------------------------------------
 
-def system_matrix(prob, trip_i: np.ndarray, trip_j: np.ndarray, classes: str = "all"):
+def system_matrix(prob, trip_i: np.ndarray, trip_j: np.ndarray, classes: str = "all",
+                  trip_w: Optional[np.ndarray] = None):
     """Response matrix of Sec. 5.1 (Eq. IMC) from the tallied histories.
 
     T_ij = c_ij / n_i(j): c_ij tallied photons emitted in image voxel i and
     counted in projection bin j (primary and scattered alike: j = (view, iv,
-    iu)), n_i(j) = N_view(j) * A_i / A the expected number emitted in i towards
+    iu)) -- or, with trip_w, the summed forced-detection scores of those
+    contributions -- n_i(j) = N_view(j) * A_i / A the expected number emitted in i towards
     bin j's view (A_i: activity summed over image voxel i, A: total).
     classes = "primary" / "scatter" keeps only unscattered / scattered
     photons (the dual-matrix backprojector, the scatter projection).  Returns
@@ -349,12 +368,13 @@ def system_matrix(prob, trip_i: np.ndarray, trip_j: np.ndarray, classes: str = "
     n_bins = V * per
     cls = (trip_j // per) % 2
     keep = {"all": np.ones(len(trip_j), bool), "primary": cls == 0, "scatter": cls == 1}[classes]
-    trip_i, trip_j = trip_i[keep], trip_j[keep]
+    w = np.ones(len(trip_i)) if trip_w is None else np.asarray(trip_w, dtype=np.float64)
+    trip_i, trip_j, w = trip_i[keep], trip_j[keep], w[keep]
     view = trip_j // (2 * per)
     row = view * per + trip_j % per
     n_view = np.array([prob.n_histories // V + (1 if k < prob.n_histories % V else 0)
                        for k in range(V)], dtype=np.float64)
-    c = sp.coo_matrix((np.ones(len(trip_i)), (row, trip_i)), shape=(n_bins, n_img)).tocsr()
+    c = sp.coo_matrix((w, (row, trip_i)), shape=(n_bins, n_img)).tocsr()
     c.sum_duplicates()
     P = np.asarray(c.sum(axis=1)).ravel()
     c = c.tocoo()

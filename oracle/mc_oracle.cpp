@@ -329,9 +329,16 @@ double ray_mu_integral(const Setup& s, const double x[3], const double d[3]) {
     return sum;
 }
 
+int32_t image_voxel(const orc_problem* p, int32_t vox);
+
 struct FdSink {
     std::vector<double>* tally;
     std::vector<double>* tally_sq;
+    bool want_trip = false;
+    int32_t emit_img = 0;          // image voxel of the current history's emission
+    int64_t work = 0;              // its work index relative to history_offset
+    std::vector<int64_t> ti, tj, tg;
+    std::vector<double> tw;
 };
 
 void fd_score(const Setup& s, int32_t view, uint64_t hist, uint32_t event, const double x[3],
@@ -367,6 +374,12 @@ void fd_score(const Setup& s, int32_t view, uint64_t hist, uint32_t event, const
     const size_t b = (((size_t)view * 2 + cls) * p->nv + iv) * p->nu + iu;
     (*sink.tally)[b] += score;
     (*sink.tally_sq)[b] += score * score;
+    if (sink.want_trip) {
+        sink.ti.push_back(sink.emit_img);
+        sink.tj.push_back((int64_t)b);
+        sink.tw.push_back(score);
+        sink.tg.push_back(sink.work);
+    }
 }
 
 // Transport one history.  view/hist identify its random stream.
@@ -404,7 +417,10 @@ void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, Hi
     double mu_max = s.mu_hat * s.xs.g(e);
     double p_pe = s.xs.p_pe(e);
     if (keep_path) h.verts.push_back(Vertex{{x[0], x[1], x[2]}, e});
-    if (fd) fd_score(s, view, hist, 0, x, nullptr, e, 0, *fd);
+    if (fd) {
+        fd->emit_img = image_voxel(p, (int32_t)vox);
+        fd_score(s, view, hist, 0, x, nullptr, e, 0, *fd);
+    }
 
     // --- Woodcock loop: event n = 1, 2, ... ---
     uint32_t n = 0;
@@ -698,23 +714,45 @@ int orc_simulate(const orc_problem* p, double* tally, double* tally_sq, orc_resu
 // energies and counters as orc_simulate), but the tally is the forced-
 // detection estimate, scored at emission (class 0) and at every real collision
 // (class 1); tally_sq sums the squared scores.  Analog arrivals are not tallied.
-int orc_simulate_fd(const orc_problem* p, double* tally, double* tally_sq, orc_result* res) {
+int orc_simulate_fd(const orc_problem* p, double* tally, double* tally_sq, orc_result* res,
+                    int64_t* trip_i, int64_t* trip_j, double* trip_w, int64_t* trip_g,
+                    uint64_t trip_cap, uint64_t* n_trip) {
     Setup s;
     if (!build_setup(p, s)) return -1;
     const size_t nbins = (size_t)p->n_views * 2 * p->nv * p->nu;
     const size_t nt = n_threads_for(p);
+    const bool want_trip = trip_i != nullptr;
     std::vector<Acc> acc(nt);
-    for (auto& a : acc) { a.tally.assign(nbins, 0.0); a.tally_sq.assign(nbins, 0.0); }
+    std::vector<FdSink> sinks(nt);
+    for (size_t t = 0; t < nt; ++t) {
+        acc[t].tally.assign(nbins, 0.0);
+        acc[t].tally_sq.assign(nbins, 0.0);
+        sinks[t].tally = &acc[t].tally;
+        sinks[t].tally_sq = &acc[t].tally_sq;
+        sinks[t].want_trip = want_trip;
+    }
     parallel_ranges(s.begin, s.end, nt, [&](size_t t, uint64_t b, uint64_t e) {
-        FdSink sink{&acc[t].tally, &acc[t].tally_sq};
+        FdSink& sink = sinks[t];
         for (uint64_t g = b; g < e; ++g) {
             int32_t view; uint64_t hist;
             work_to_view_hist(s, g, view, hist);
             History h;
+            sink.work = (int64_t)(g - p->history_offset);
             run_history(s, view, hist, false, h, &sink);
             accumulate(p, h, acc[t], false, false, g);
         }
     });
+    uint64_t n_out = 0;
+    for (auto& k : sinks) {
+        for (size_t i = 0; i < k.ti.size(); ++i) {
+            if (want_trip && n_out < trip_cap) {
+                trip_i[n_out] = k.ti[i]; trip_j[n_out] = k.tj[i];
+                trip_w[n_out] = k.tw[i]; trip_g[n_out] = k.tg[i];
+            }
+            ++n_out;
+        }
+    }
+    if (n_trip) *n_trip = n_out;
     std::memset(res, 0, sizeof(*res));
     std::fill(tally, tally + nbins, 0.0);
     if (tally_sq) std::fill(tally_sq, tally_sq + nbins, 0.0);
@@ -728,7 +766,7 @@ int orc_simulate_fd(const orc_problem* p, double* tally, double* tally_sq, orc_r
             if (tally_sq) tally_sq[b] += a.tally_sq[b];
         }
     }
-    return 0;
+    return (want_trip && n_out > trip_cap) ? -2 : 0;
 }
 
 double orc_kn_pdf(double e_kev, double cos_t) { return kn_pdf(e_kev, cos_t); }

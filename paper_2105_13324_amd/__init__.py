@@ -65,7 +65,8 @@ class McOptions(C.Structure):
                 ("kernel_events", C.c_void_p * 2)]
 
 
-EVENT_DTYPE = np.dtype([("work", np.uint64), ("bin", np.uint32), ("emit_voxel", np.uint32)])
+EVENT_DTYPE = np.dtype([("work", np.uint64), ("bin", np.uint32), ("emit_voxel", np.uint32),
+                        ("weight", np.int64)])
 RECORD_DTYPE = np.dtype([("fate", np.int32), ("view", np.int32), ("iu", np.int32), ("iv", np.int32),
                          ("n_scatter", np.int32), ("n_tent", np.int32), ("emit_voxel", np.int32),
                          ("cls", np.int32), ("e_final", np.float64)])
@@ -274,7 +275,7 @@ class Simulator:
         self.counters = torch.zeros((n, 4), dtype=torch.int64, device=dev)
         self.status = torch.zeros(4, dtype=torch.int64, device=dev)
         self.event_capacity = int(event_capacity)
-        self.events = (torch.zeros((max(self.event_capacity, 1), 2), dtype=torch.int64, device=dev)
+        self.events = (torch.zeros((max(self.event_capacity, 1), 3), dtype=torch.int64, device=dev)
                        if self.event_capacity else None)
         self.n_events = torch.zeros(1, dtype=torch.int64, device=dev)
         nb = _lib.mc_workspace_bytes(self._arr, n, C.byref(self.options) if self.options else None)

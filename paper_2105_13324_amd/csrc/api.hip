@@ -194,6 +194,7 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
                             uint64_t* n_events, int64_t* status, void* workspace,
                             size_t workspace_bytes, void* stream) {
     if (!problems || n_problems < 1 || !tally || !fates || !status || !workspace) return MC_EINVAL;
+    if (opt && (opt->forced_detection < 0 || opt->forced_detection > 1)) return MC_EINVAL;
     if (events && !n_events) return MC_EINVAL;
     for (int i = 0; i < n_problems; ++i) if (!check_problem(problems[i])) return MC_EINVAL;
     int block, hpl, bpc, brick, qbytes;
@@ -223,9 +224,7 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e);
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return hip_fail(e);
-    if (opt && (opt->forced_detection < 0 || opt->forced_detection > 1)) return MC_EINVAL;
     const bool fd = opt && opt->forced_detection == 1;
-    if (fd && events) return MC_EINVAL;
     if (bpc <= 0) bpc = transport_blocks_per_cu(block, fd);
     TransportArgs a;
     a.descs = d_desc;

@@ -475,6 +475,7 @@ struct FdPoint {
     float dx, dy, dz;    // direction before the collision (unused at emission)
     float e;             // energy before the collision
     uint32_t view, hist, event;   // event 0: emission
+    uint32_t voxel;      // phantom voxel of the history's emission
 };
 
 // Integral of mu140 along p + t o (t >= 0, o a unit vector) to the grid edge:
@@ -547,10 +548,11 @@ __device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox
     return sum;
 }
 
-// Score one forced copy into the tallies (tally Q31.32, tally_sq Q11.52).
-// d: the problem's descriptor (cone and Klein-Nishina constants).
-__device__ inline void fd_score(const Cst& C, const ProbDesc* __restrict__ d, const FdPoint& q,
-                                int64_t* tally, int64_t* tally_sq) {
+// Score of one forced copy: false if it scores nothing, else its bin within
+// the problem (tally layout) and its weight.  d: the problem's descriptor
+// (cone and Klein-Nishina constants).
+__device__ inline bool fd_eval(const Cst& C, const ProbDesc* __restrict__ d, const FdPoint& q,
+                               uint32_t& bin, float& score) {
     const float omc = d->omc_alpha, kn140 = (float)d->kn140;
     uint32_t r0 = q.hist, r1 = q.view, r2 = q.event, r3 = FD_SUB;
     philox10(r0, r1, r2, r3, C.seed, C.pid);
@@ -571,25 +573,21 @@ __device__ inline void fd_score(const Cst& C, const ProbDesc* __restrict__ d, co
                           rcpf(FOUR_PI_F * kn140 * kn_ratio(C, q.e));
         w = (1.0f - ppe) * (TWO_PI_F * omc) * pdf;
     }
-    if (!(e2 >= C.e_cut && e2 >= C.e_lo && e2 <= C.e_hi)) return;
+    if (!(e2 >= C.e_cut && e2 >= C.e_lo && e2 <= C.e_hi)) return false;
     const float dn = ox * vw.x + oy * vw.y;
     const float tp = (C.radius - (q.x * vw.x + q.y * vw.y)) * rcpf(dn);
     const float px = fmaf(tp, ox, q.x), py = fmaf(tp, oy, q.y), pz = fmaf(tp, oz, q.z);
     const float au = (-vw.y * px + vw.x * py) + 0.5f * C.wu;
     const float av = pz + 0.5f * C.wv;
-    if (!(au >= 0.0f && au < C.wu && av >= 0.0f && av < C.wv)) return;
+    if (!(au >= 0.0f && au < C.wu && av >= 0.0f && av < C.wv)) return false;
     const int iu = min((int)(au * C.inv_pix), C.nu - 1);
     const int iv = min((int)(av * C.inv_pix), C.nv - 1);
     float l2, ppe;
     const float g = e2 == 140.0f ? 1.0f : energy_terms(C, e2, l2, ppe);
-    const float sc = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, ox, oy, oz));
-    const int cls = q.event == 0 ? 0 : 1;
-    const size_t b = C.tally_offset +
-                     ((((size_t)q.view * 2 + cls) * (size_t)C.nv + iv) * (size_t)C.nu + iu);
-    atomicAdd((unsigned long long*)(tally + b), (unsigned long long)__float2ll_rn(sc * 4294967296.0f));
-    if (tally_sq)
-        atomicAdd((unsigned long long*)(tally_sq + b),
-                  (unsigned long long)__float2ll_rn(sc * sc * 4503599627370496.0f));
+    score = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, ox, oy, oz));
+    const uint32_t cls = q.event == 0 ? 0u : 1u;
+    bin = ((q.view * 2u + cls) * (uint32_t)C.nv + (uint32_t)iv) * (uint32_t)C.nu + (uint32_t)iu;
+    return true;
 }
 
 }  // namespace

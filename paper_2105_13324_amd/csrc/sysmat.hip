@@ -1,10 +1,11 @@
 // Monte Carlo response matrix and MLEM (paper Sec. 5.1, Eq. IMC and Eq. MLEM).
 //
-// Response matrix.  Each tallied history of the forward call is an event
-// (projection bin j, phantom voxel of emission).  With i the image voxel of
+// Response matrix.  Each tally contribution of the forward call is an event
+// (projection bin j, phantom voxel of emission, weight: 1 for an analog
+// arrival, the score of a forced-detection copy).  With i the image voxel of
 // the emission (phantom voxel / image_factor per axis),
 //     T_ij = c_ij / n_i(j),   n_i(j) = N_view(j) * A_i / A,
-// c_ij the number of events (i, j), N_view(j) the histories of bin j's view,
+// c_ij the summed weight of the events (i, j), N_view(j) the histories of bin j's view,
 // A_i the activity in image voxel i and A the total: the estimated probability
 // that a photon emitted in image voxel i is counted in bin j.  Bins merge the
 // primary and scatter classes (the camera cannot tell them apart): j =
@@ -13,8 +14,8 @@
 //
 // Both orientations are built as CSR (bins x voxels and voxels x bins) by a
 // deterministic counting sort: rows counted with integer atomics, scanned,
-// scattered, each row's columns sorted and merged.  Integer counts make the
-// result independent of the atomics' order.
+// scattered, each row's columns sorted and merged.  Weights are summed as
+// Q31.32 integers, so the result does not depend on the atomics' order.
 //
 // MLEM.  S_i <- S_i / sens_i * sum_j T_ij P_j / y_j, y = T S, sens_i =
 // sum_j T_ij; FP32 matrix values, FP64 accumulation; bins with y_j = 0 add
@@ -200,30 +201,61 @@ __global__ __launch_bounds__(T256) void k_count_rows(SysArgs a, int transpose, u
 }
 
 __global__ __launch_bounds__(T256) void k_scatter(SysArgs a, int transpose, const uint64_t* start,
-                                                  uint32_t* fill, uint32_t* tmp_col) {
+                                                  uint32_t* fill, uint32_t* tmp_col, int64_t* tmp_w) {
     const uint64_t n = n_events_of(a);
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t bin, img;
-        if (!event_rc(a, a.events[e], bin, img)) continue;
+        const mc_event ev = a.events[e];
+        if (!event_rc(a, ev, bin, img)) continue;
         const uint32_t r = transpose ? img : bin, c = transpose ? bin : img;
         const uint32_t k = atomicAdd(fill + r, 1u);
         tmp_col[start[r] + k] = c;
+        tmp_w[start[r] + k] = ev.weight;
     }
 }
 
-// sort each row's columns (insertion sort: rows hold a handful of events)
-// and count the distinct ones
+// Sift-down of heap node i over [0, n) of the row (col keys, weights carried).
+__device__ inline void sift(uint32_t* col, int64_t* w, uint64_t i, uint64_t n) {
+    for (;;) {
+        uint64_t m = i;
+        const uint64_t l = 2 * i + 1, r = l + 1;
+        if (l < n && col[l] > col[m]) m = l;
+        if (r < n && col[r] > col[m]) m = r;
+        if (m == i) return;
+        const uint32_t tc = col[i]; col[i] = col[m]; col[m] = tc;
+        const int64_t tw = w[i]; w[i] = w[m]; w[m] = tw;
+        i = m;
+    }
+}
+
+// sort each row's (column, weight) pairs by column -- insertion sort for the
+// short rows of analog lists, heapsort for the long rows of forced-detection
+// lists -- and count the distinct columns
 __global__ __launch_bounds__(T256) void k_sort_rows(uint64_t n_rows, const uint64_t* start,
-                                                    uint32_t* tmp_col, uint32_t* row_nnz) {
+                                                    uint32_t* tmp_col, int64_t* tmp_w,
+                                                    uint32_t* row_nnz) {
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
          r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t b = start[r], e = start[r + 1];
-        for (uint64_t i = b + 1; i < e; ++i) {
-            const uint32_t v = tmp_col[i];
-            uint64_t j = i;
-            while (j > b && tmp_col[j - 1] > v) { tmp_col[j] = tmp_col[j - 1]; --j; }
-            tmp_col[j] = v;
+        const uint64_t b = start[r], e = start[r + 1], n = e - b;
+        uint32_t* col = tmp_col + b;
+        int64_t* w = tmp_w + b;
+        if (n <= 32) {
+            for (uint64_t i = 1; i < n; ++i) {
+                const uint32_t v = col[i];
+                const int64_t wv = w[i];
+                uint64_t j = i;
+                while (j > 0 && col[j - 1] > v) { col[j] = col[j - 1]; w[j] = w[j - 1]; --j; }
+                col[j] = v;
+                w[j] = wv;
+            }
+        } else {
+            for (uint64_t i = n / 2; i-- > 0;) sift(col, w, i, n);
+            for (uint64_t k = n - 1; k > 0; --k) {
+                const uint32_t tc = col[0]; col[0] = col[k]; col[k] = tc;
+                const int64_t tw = w[0]; w[0] = w[k]; w[k] = tw;
+                sift(col, w, 0, k);
+            }
         }
         uint32_t d = 0;
         for (uint64_t i = b; i < e; ++i) d += (i == b || tmp_col[i] != tmp_col[i - 1]);
@@ -234,6 +266,7 @@ __global__ __launch_bounds__(T256) void k_sort_rows(uint64_t n_rows, const uint6
 // distinct columns with their counts -> CSR column and value arrays
 __global__ __launch_bounds__(T256) void k_emit_rows(SysArgs a, int transpose, uint64_t n_rows,
                                                     const uint64_t* start, const uint32_t* tmp_col,
+                                                    const int64_t* tmp_w,
                                                     const uint64_t* rowptr_u, int64_t* rowptr,
                                                     int32_t* col, float* val,
                                                     const unsigned long long* a_img,
@@ -245,19 +278,24 @@ __global__ __launch_bounds__(T256) void k_emit_rows(SysArgs a, int transpose, ui
         if (r == n_rows) continue;
         const uint64_t b = start[r], e = start[r + 1];
         uint64_t o = rowptr_u[r];
-        if (!transpose && proj) proj[r] = (float)(e - b);
+        if (!transpose && proj) {
+            long long tot = 0;
+            for (uint64_t i = b; i < e; ++i) tot += tmp_w[i];
+            proj[r] = (float)((double)tot * 0x1p-32);
+        }
         uint64_t i = b;
         while (i < e) {
             const uint32_t c = tmp_col[i];
             uint64_t j = i;
-            while (j < e && tmp_col[j] == c) ++j;
+            long long cw = 0;
+            while (j < e && tmp_col[j] == c) { cw += tmp_w[j]; ++j; }
             const uint32_t bin = transpose ? c : (uint32_t)r;
             const uint32_t img = transpose ? (uint32_t)r : c;
             const uint64_t view = bin / a.nv_nu;
             const double n_view = (double)(a.q_per_view + (view < a.r_extra ? 1u : 0u));
             const double n_i = n_view * (double)a_img[img] / total;
             col[o] = (int32_t)c;
-            val[o] = (float)((double)(j - i) / n_i);
+            val[o] = (float)((double)cw * 0x1p-32 / n_i);
             ++o;
             i = j;
         }
@@ -440,7 +478,8 @@ size_t sysmat_workspace_bytes(uint64_t n_bins, uint64_t n_img, uint64_t capacity
     const uint64_t nb = (nr + 1 + SCAN_BLOCK - 1) / SCAN_BLOCK;
     return al(4 * nr) /* cnt */ + al(4 * nr) /* fill */ + al(8 * (nr + 1)) /* start */
          + al(8 * (nr + 1)) /* rowptr_u */ + al(4 * nr) /* row_nnz */ + al(8 * nb) /* bsum */
-         + al(4 * (capacity ? capacity : 1)) /* tmp_col */ + al(8 * (n_img + 1)) /* a_img, total */;
+         + al(4 * (capacity ? capacity : 1)) /* tmp_col */ + al(8 * (capacity ? capacity : 1)) /* tmp_w */
+         + al(8 * (n_img + 1)) /* a_img, total */;
 }
 
 hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_events, uint64_t capacity,
@@ -463,6 +502,7 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
     const uint64_t nb = (nr + 1 + SCAN_BLOCK - 1) / SCAN_BLOCK;
     uint64_t* bsum = (uint64_t*)w;         w += al(8 * nb);
     uint32_t* tmp_col = (uint32_t*)w;      w += al(4 * (capacity ? capacity : 1));
+    int64_t* tmp_w = (int64_t*)w;          w += al(8 * (capacity ? capacity : 1));
     unsigned long long* a_img = (unsigned long long*)w;   // n_img entries, then the total
     unsigned long long* total = a_img + n_img;
 
@@ -484,12 +524,12 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
         k_count_rows<<<ge, T256, 0, s>>>(a, transpose, cnt);
         hipError_t e = exclusive_scan(cnt, n_rows, start, bsum, s);
         if (e != hipSuccess) return e;
-        k_scatter<<<ge, T256, 0, s>>>(a, transpose, start, fill, tmp_col);
-        k_sort_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(n_rows, start, tmp_col, row_nnz);
+        k_scatter<<<ge, T256, 0, s>>>(a, transpose, start, fill, tmp_col, tmp_w);
+        k_sort_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
         e = exclusive_scan(row_nnz, n_rows, rowptr_u, bsum, s);
         if (e != hipSuccess) return e;
         k_emit_rows<<<grid_for(n_rows + 1, T256, 8192), T256, 0, s>>>(
-            a, transpose, n_rows, start, tmp_col, rowptr_u, transpose ? Tt_rp : T_rp,
+            a, transpose, n_rows, start, tmp_col, tmp_w, rowptr_u, transpose ? Tt_rp : T_rp,
             transpose ? Tt_col : T_col, transpose ? Tt_val : T_val, a_img, total,
             transpose ? nullptr : proj);
     }

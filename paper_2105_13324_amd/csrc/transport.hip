@@ -98,6 +98,44 @@ struct EmitRec {
 
 constexpr uint32_t FD_RING = 128;         // forced-detection queue per wave
 
+// Score the forced copy of each active lane: tally (Q31.32), sum of squares
+// (Q11.52) and, if listed, one event each (appended with one atomic per
+// wavefront by its first active lane).
+__device__ inline void fd_commit(const Cst& C, int p, const FdPoint& q, int lane,
+                                 const TransportArgs& T) {
+    uint32_t bin = 0;
+    float sc = 0.0f;
+    const bool ok = fd_eval(C, T.descs + p, q, bin, sc);
+    const long long w = (long long)__float2ll_rn(sc * 4294967296.0f);
+    if (ok) {
+        const size_t b = C.tally_offset + bin;
+        atomicAdd((unsigned long long*)(T.tally + b), (unsigned long long)w);
+        if (T.tally_sq)
+            atomicAdd((unsigned long long*)(T.tally_sq + b),
+                      (unsigned long long)__float2ll_rn(sc * sc * 4503599627370496.0f));
+    }
+    if (T.events) {            // forced copies are counted only when listed
+        const uint64_t m = __ballot(ok);
+        if (m != 0) {
+            unsigned long long base = 0;
+            if (lane == __ffsll((unsigned long long)__ballot(1)) - 1)
+                base = atomicAdd(T.n_events, (unsigned long long)__popcll(m));
+            base = uniform64(base);
+            if (ok) {
+                const uint64_t idx = base + (uint64_t)__popcll(m & ((1ull << lane) - 1ull));
+                if (idx < T.event_capacity) {
+                    mc_event ev;
+                    ev.work = T.work_prefix[p] + (work_of(C, q.view, q.hist) - C.work_begin);
+                    ev.bin = bin;
+                    ev.emit_voxel = q.voxel;
+                    ev.weight = w;
+                    T.events[idx] = ev;
+                }
+            }
+        }
+    }
+}
+
 // Score the n (<= 64) forced copies at the head of a wave's ring.
 __device__ inline void fd_drain(const Cst& C, int p, const FdPoint* ring, uint32_t& head, uint32_t n,
                                 int lane, const TransportArgs& T) {
@@ -106,7 +144,7 @@ __device__ inline void fd_drain(const Cst& C, int p, const FdPoint* ring, uint32
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if ((uint32_t)lane < n) {
         const FdPoint q = ring[(head + (uint32_t)lane) & (FD_RING - 1)];
-        fd_score(C, T.descs + p, q, T.tally, T.tally_sq);
+        fd_commit(C, p, q, lane, T);
     }
     head += n;
 }
@@ -169,14 +207,11 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                             if (chunk_prefix[mid] <= pending) lo = mid; else hi = mid - 1;
                         }
                         const int np = __builtin_amdgcn_readfirstlane(lo);
-                        if (np != p && need != full) {
+                        // drain problem p first: no lane busy, no forced copy queued
+                        if (np != p && (need != full || (FD && fd_tail != fd_head))) {
                             ready = false;                 // drain problem p first
                         } else {
                             if (np != p) {
-                                if constexpr (FD) {
-                                    if (p >= 0 && fd_tail != fd_head)
-                                        fd_drain(C, p, ring, fd_head, fd_tail - fd_head, lane, T);
-                                }
                                 if (p >= 0) flush(e_esc, fc, wc, p, T, lane);
                                 p = np;
                                 C = load_cst(T.descs + p);
@@ -221,7 +256,8 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                                 q.dx = 0.0f; q.dy = 0.0f; q.dz = 0.0f;
                                 q.e = 140.0f;
                                 q.view = (uint32_t)v; q.hist = (uint32_t)h; q.event = 0;
-                                fd_score(C, T.descs + p, q, T.tally, T.tally_sq);
+                                q.voxel = e.voxel;
+                                fd_commit(C, p, q, lane, T);
                             }
                         }
                     }
@@ -249,7 +285,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             e.voxel = r.voxel;
             begin_history(C, L, r.view, r.hist, e);
         }
-        if (exhausted && __ballot(L.state != S_IDLE) == 0) break;
+        if (exhausted && __ballot(L.state != S_IDLE) == 0 && (!FD || fd_tail == fd_head)) break;
 
         int fate = R_RUNNING;
         int iu = -1, iv = -1;
@@ -287,11 +323,17 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                     FdPoint q;
                     q.x = L.x; q.y = L.y; q.z = L.z; q.dx = L.dx; q.dy = L.dy; q.dz = L.dz;
                     q.e = L.e; q.view = (uint32_t)L.view; q.hist = L.hist; q.event = L.n;
+                    q.voxel = L.emit_voxel;
                     ring[(fd_tail + (uint32_t)__popcll(m & lane_lt)) & (FD_RING - 1)] = q;
                 }
                 fd_tail += (uint32_t)__popcll(m);
-                if (fd_tail - fd_head >= 64) fd_drain(C, p, ring, fd_head, 64, lane, T);
             }
+            // the one place forced copies of collisions are scored (one code
+            // path, so a score never depends on where it was drained): 64 at
+            // a time, or what is left once no lane is busy
+            const uint32_t cnt = fd_tail - fd_head;
+            if (cnt >= 64 || (cnt != 0 && __ballot(L.state != S_IDLE) == 0))
+                fd_drain(C, p, ring, fd_head, cnt < 64 ? cnt : 64u, lane, T);
         }
         if (__ballot(fate != R_RUNNING) != 0) {
             // fate counts through ballots: wave-uniform, no per-lane counters
@@ -311,15 +353,13 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                         ev.work = T.work_prefix[p] + (work_of(C, L.view, L.hist) - C.work_begin);
                         ev.bin = bin;
                         ev.emit_voxel = L.emit_voxel;
+                        ev.weight = 1ll << 32;
                         T.events[idx] = ev;
                     }
                 }
             }
             if (fate != R_RUNNING) L.state = S_IDLE;
         }
-    }
-    if constexpr (FD) {
-        if (p >= 0 && fd_tail != fd_head) fd_drain(C, p, ring, fd_head, fd_tail - fd_head, lane, T);
     }
     if (p >= 0) flush(e_esc, fc, wc, p, T, lane);
 }

@@ -138,6 +138,12 @@ def test_simulate_rejects_bad_buffers_before_launch():
     assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
     o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=0, threshold_bytes=2)
     assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
+    o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=0, forced_detection=2)
+    assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
+    # the adjoint is of analog tallies only
+    o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=0, forced_detection=1)
+    assert mc._lib.mc_adjoint_mu(C.byref(p), C.byref(o), 8, None, None, 0, 8, 40, 8, 8, need,
+                                 None) == mc.MC_EINVAL
     assert sim(None, 1, None, 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
     assert mc._lib.mc_error_string(mc.MC_EINVAL) == b"invalid argument"
     assert mc._lib.mc_replay_histories(C.byref(p), None, None, None, 5, None, 8, 8, need, None) == mc.MC_EINVAL

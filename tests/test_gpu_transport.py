@@ -266,6 +266,7 @@ def test_event_list_matches_oracle_replay():
     hist = np.where(g < r * big, g % big, (g - r * big) % q).astype(np.uint64)
     o = oracle.replay(p, view, hist)
     b = ((o["view"] * 2 + o["cls"]) * p.nv + o["iv"]) * p.nu + o["iu"]
+    assert np.all(ev["weight"] == 1 << 32)              # an analog arrival counts one
     ok = (o["fate"] == 5) & (b == ev["bin"]) & (o["emit_voxel"] == ev["emit_voxel"])
     say(f"event list: {ok.mean():.6f} of {len(ok)} tallied histories confirmed by the oracle")
     assert ok.mean() >= 0.999

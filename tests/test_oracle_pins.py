@@ -690,3 +690,28 @@ def test_box_escape_shortcut_changes_only_step_counts():
     np.testing.assert_array_equal(ra["tally"], rb["tally"])
     np.testing.assert_array_equal(ra["fates"], rb["fates"])
     assert rb["n_tent"] < 0.85 * ra["n_tent"]
+
+
+def test_fd_response_matrix_consistency():
+    """The forced-detection response matrix (weights = scores) reproduces its
+    run's forced-detection projection (P = T n with n the expected emissions
+    per image voxel), its projection equals the run's tally with the classes
+    merged, and its sensitivity per image voxel agrees with the analog
+    matrix's within the analog counting error."""
+    p = phantoms.thorax_problem("fd_sys", 32, 1.2, 2, 6, 180.0, 32, 1.2, 40_000,
+                                image_factor=4).with_(accept_half_angle_rad=math.radians(8.0))
+    r = oracle.simulate_fd(p, want_triplets=True)
+    T, P, frac = oracle.system_matrix(p, r["trip_i"], r["trip_j"], trip_w=r["trip_w"])
+    np.testing.assert_allclose(P, r["tally"].sum(axis=1).reshape(-1), rtol=1e-12, atol=1e-18)
+    per = p.nv * p.nu
+    q, rem = divmod(p.n_histories, p.n_views)
+    n_view = np.array([q + (k < rem) for k in range(p.n_views)], dtype=np.float64)
+    TP = (T @ frac) * np.repeat(n_view, per)           # sum_i T_ij N_view(j) A_i / A
+    np.testing.assert_allclose(TP, P, rtol=1e-9, atol=1e-15)
+    assert T.nnz > 20 * len(np.unique(r["trip_i"]))      # dense compared with analog lists
+    a = oracle.simulate(p.with_(n_histories=4_000_000), want_triplets=True)
+    Ta, Pa, _ = oracle.system_matrix(p.with_(n_histories=4_000_000), a["trip_i"], a["trip_j"])
+    sf = np.asarray(T.sum(axis=0)).ravel()
+    sa = np.asarray(Ta.sum(axis=0)).ravel()
+    # compare the total sensitivity (analog: ~1e4 counts, 1 % error)
+    assert abs(sf.sum() - sa.sum()) < 4 * sa.sum() / math.sqrt(Pa.sum())

@@ -294,6 +294,32 @@ def fd_form(mc, torch, steps):
             "seeds": 16}
 
 
+def large_fd(mc, torch, steps, p5):
+    """Forced-detection response matrix on the large workload: 1e8 histories
+    with an event list (one event per score), the weighted response matrix
+    and 50 MLEM iterations on it."""
+    p = p5.with_(n_histories=10 ** 8)
+    dp = mc.to_device(p)
+    cap = 3 * p.n_histories
+    sim = mc.Simulator(dp, event_capacity=cap, want_sq=False, options={"forced_detection": 1})
+    sim.run()
+    ms_fwd = timed(torch, sim.run, 1)
+    n_ev = int(sim.n_events.item())
+    m = mc.system_matrix(dp, sim)
+    ms_sys = timed(torch, lambda: mc.system_matrix(dp, sim), 1)
+    img = torch.ones(m.n_img, dtype=torch.float32, device="cuda")
+    ml = mc.Mlem(m)
+
+    def recon():
+        img.fill_(1.0)
+        ml.run(img, 50)
+    recon()
+    ms_mlem = timed(torch, recon, steps)
+    return {"histories": p.n_histories, "forward_ms": ms_fwd, "events": n_ev,
+            "events_listed": min(n_ev, cap), "system_matrix_ms": ms_sys, "nnz": m.nnz,
+            "mlem_50_ms": ms_mlem, "histories_per_s": p.n_histories / (ms_fwd / 1e3)}
+
+
 def large_form(mc, torch, steps):
     """256^3 x 1.5 mm thorax, 120 views over 360 deg, 128^2 x 3 mm, 1e9
     histories with an event list, response matrix on the 64^3 image, 50 MLEM
@@ -323,12 +349,14 @@ def large_form(mc, torch, steps):
         mc.osem(m, img_os, 10, 8, p5.nu * p5.nv)
     os_recon()
     ms_os = timed(torch, os_recon, steps)
+    n_tallied, nnz, n_bins, n_img = int(s5.n_events.item()), m.nnz, m.n_bins, m.n_img
+    fd = large_fd(mc, torch, steps, p5)
     return {"value": p5.n_histories / (ms_fwd / 1e3), "unit": "histories/s",
             "forward_ms": ms_fwd, "system_matrix_ms": ms_sys, "mlem_50_ms": ms_mlem,
             "mlem_iteration_ms": ms_mlem / 50, "osem_8_subsets_10_iterations_ms": ms_os,
             "osem_iteration_ms": ms_os / 10, "histories": p5.n_histories,
-            "tallied": int(s5.n_events.item()), "nnz": m.nnz,
-            "bins": m.n_bins, "image_voxels": m.n_img}
+            "tallied": n_tallied, "nnz": nnz,
+            "bins": n_bins, "image_voxels": n_img, "forced_detection": fd}
 
 
 if __name__ == "__main__":

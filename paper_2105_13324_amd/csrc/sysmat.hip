@@ -303,15 +303,47 @@ __global__ __launch_bounds__(T256) void k_emit_rows(SysArgs a, int transpose, ui
 }
 
 // ---- MLEM ----
+//
+// Row kernels: a matrix whose rows hold on average at least WAVE_ROW_MIN
+// entries (forced-detection matrices) is read one wavefront per row --
+// coalesced loads, FP64 wavefront reduction -- and a sparse one (analog
+// matrices: far fewer entries than rows) one thread per row.  The choice
+// depends only on the matrix, so results are deterministic.
+
+constexpr int64_t WAVE_ROW_MIN = 8;
+
+__device__ inline double wave_sum_f64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// For each row r: done(r, sum over the row's entries of term(k)).
+template <class Term, class Done>
+__device__ inline void for_rows(int64_t n_rows, const int64_t* __restrict__ rp, Term term, Done done) {
+    const bool wave_mode = rp[n_rows] >= WAVE_ROW_MIN * n_rows;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    if (wave_mode) {
+        const int lane = threadIdx.x & 63;
+        for (int64_t r = tid >> 6; r < n_rows; r += nt >> 6) {
+            double acc = 0.0;
+            for (int64_t k = rp[r] + lane; k < rp[r + 1]; k += 64) acc += term(k);
+            acc = wave_sum_f64(acc);
+            if (lane == 0) done(r, acc);
+        }
+    } else {
+        for (int64_t r = tid; r < n_rows; r += nt) {
+            double acc = 0.0;
+            for (int64_t k = rp[r]; k < rp[r + 1]; ++k) acc += term(k);
+            done(r, acc);
+        }
+    }
+}
 
 __global__ __launch_bounds__(T256) void k_row_sums(int64_t n_rows, const int64_t* __restrict__ rp,
                                                    const float* __restrict__ v, double* __restrict__ out) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int64_t k = rp[r]; k < rp[r + 1]; ++k) s += (double)v[k];
-        out[r] = s;
-    }
+    for_rows(n_rows, rp, [&](int64_t k) { return (double)v[k]; },
+             [&](int64_t r, double acc) { out[r] = acc; });
 }
 
 __global__ __launch_bounds__(T256) void k_mlem_init(int64_t n_vox, const float* __restrict__ img,
@@ -329,13 +361,8 @@ __global__ __launch_bounds__(T256) void k_mlem_forward(int64_t n_bins, const int
                                                        const double* __restrict__ S,
                                                        const float* __restrict__ P,
                                                        double* __restrict__ ratio) {
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_bins;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = rp[j], e = rp[j + 1];
-        double y = 0.0;
-        for (int64_t k = b; k < e; ++k) y += (double)val[k] * S[col[k]];
-        ratio[j] = y > 0.0 ? (double)P[j] / y : 0.0;
-    }
+    for_rows(n_bins, rp, [&](int64_t k) { return (double)val[k] * S[col[k]]; },
+             [&](int64_t j, double y) { ratio[j] = y > 0.0 ? (double)P[j] / y : 0.0; });
 }
 
 // S_i <- S_i * (sum_j T_ij ratio_j) / sens_i
@@ -345,14 +372,11 @@ __global__ __launch_bounds__(T256) void k_mlem_update(int64_t n_vox, const int64
                                                       const double* __restrict__ ratio,
                                                       const double* __restrict__ sens,
                                                       double* __restrict__ S) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const double si = sens[i];
-        if (!(si > 0.0)) { S[i] = 0.0; continue; }
-        double bsum = 0.0;
-        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) bsum += (double)val[k] * ratio[col[k]];
-        S[i] = S[i] * bsum / si;
-    }
+    for_rows(n_vox, rp, [&](int64_t k) { return (double)val[k] * ratio[col[k]]; },
+             [&](int64_t i, double bsum) {
+                 const double si = sens[i];
+                 S[i] = si > 0.0 ? S[i] * bsum / si : 0.0;
+             });
 }
 
 __global__ __launch_bounds__(T256) void k_mlem_out(int64_t n_vox, const double* __restrict__ S,
@@ -371,14 +395,10 @@ __global__ __launch_bounds__(T256) void k_subset_sens(int64_t n_vox, const int64
                                                       const float* __restrict__ val,
                                                       int32_t bins_per_view, int32_t n_sub,
                                                       double* __restrict__ sens) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        for (int k = 0; k < n_sub; ++k) sens[(int64_t)k * n_vox + i] = 0.0;
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-            const int k = (col[e] / bins_per_view) % n_sub;
-            sens[(int64_t)k * n_vox + i] += (double)val[e];
-        }
-    }
+    for (int k = 0; k < n_sub; ++k)
+        for_rows(n_vox, rp,
+                 [&](int64_t e) { return (col[e] / bins_per_view) % n_sub == k ? (double)val[e] : 0.0; },
+                 [&](int64_t i, double acc) { sens[(int64_t)k * n_vox + i] = acc; });
 }
 
 __global__ __launch_bounds__(T256) void k_os_init(int64_t n_vox, int32_t n_sub,
@@ -393,7 +413,8 @@ __global__ __launch_bounds__(T256) void k_os_init(int64_t n_vox, int32_t n_sub,
     }
 }
 
-// subset k: y_j = sum_i c_ij S_i + s_j, ratio_j = P_j / y_j on the subset's bins
+// subset k: y_j = sum_i c_ij S_i + s_j, ratio_j = P_j / y_j on the subset's
+// bins (row t of the subset is bin j of view k + n_sub * (t / bins_per_view))
 __global__ __launch_bounds__(T256) void k_os_forward(int64_t n_sub_bins, int32_t bins_per_view,
                                                      int32_t n_sub, int32_t k,
                                                      const int64_t* __restrict__ rp,
@@ -402,14 +423,25 @@ __global__ __launch_bounds__(T256) void k_os_forward(int64_t n_sub_bins, int32_t
                                                      const double* __restrict__ S,
                                                      const float* __restrict__ P,
                                                      const float* __restrict__ scat,
-                                                     double* __restrict__ ratio) {
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_sub_bins;
-         t += (int64_t)gridDim.x * blockDim.x) {
+                                                     double* __restrict__ ratio, int64_t n_bins) {
+    // the mode follows the whole matrix's density (the subset rows are a
+    // view-interleaved part of it)
+    const bool wave_mode = rp[n_bins] >= WAVE_ROW_MIN * n_bins;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t step = wave_mode ? 64 : 1;
+    const int64_t first = wave_mode ? lane : 0;
+    for (int64_t t = wave_mode ? tid >> 6 : tid; t < n_sub_bins; t += wave_mode ? nt >> 6 : nt) {
         const int64_t view = k + (int64_t)n_sub * (t / bins_per_view);
         const int64_t j = view * bins_per_view + t % bins_per_view;
-        double y = scat ? (double)scat[j] : 0.0;
-        for (int64_t e = rp[j]; e < rp[j + 1]; ++e) y += (double)val[e] * S[col[e]];
-        ratio[j] = y > 0.0 ? (double)P[j] / y : 0.0;
+        double y = 0.0;
+        for (int64_t e = rp[j] + first; e < rp[j + 1]; e += step) y += (double)val[e] * S[col[e]];
+        if (wave_mode) y = wave_sum_f64(y);
+        if (!wave_mode || lane == 0) {
+            y += scat ? (double)scat[j] : 0.0;
+            ratio[j] = y > 0.0 ? (double)P[j] / y : 0.0;
+        }
     }
 }
 
@@ -422,20 +454,19 @@ __global__ __launch_bounds__(T256) void k_os_update(int64_t n_vox, int32_t bins_
                                                     const double* __restrict__ ratio,
                                                     const double* __restrict__ sens,
                                                     double* __restrict__ S) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const double si = sens[(int64_t)k * n_vox + i];
-        if (!(si > 0.0)) continue;
-        double bsum = 0.0;
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-            const int32_t j = col[e];
-            if ((j / bins_per_view) % n_sub == k) bsum += (double)val[e] * ratio[j];
-        }
-        S[i] = S[i] * bsum / si;
-    }
+    for_rows(n_vox, rp,
+             [&](int64_t e) {
+                 const int32_t j = col[e];
+                 return (j / bins_per_view) % n_sub == k ? (double)val[e] * ratio[j] : 0.0;
+             },
+             [&](int64_t i, double bsum) {
+                 const double si = sens[(int64_t)k * n_vox + i];
+                 if (si > 0.0) S[i] = S[i] * bsum / si;
+             });
 }
 
 }  // namespace
+
 
 size_t osem_workspace(uint64_t n_bins, uint64_t n_vox, uint32_t n_sub) {
     auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
@@ -462,7 +493,7 @@ hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int
             const int64_t nb = views_k * bins_per_view;
             if (nb <= 0) continue;
             k_os_forward<<<grid_for((uint64_t)nb, T256, 16384), T256, 0, s>>>(
-                nb, bins_per_view, n_sub, k, C_rp, C_col, C_val, S, proj, scatter, ratio);
+                nb, bins_per_view, n_sub, k, C_rp, C_col, C_val, S, proj, scatter, ratio, n_bins);
             k_os_update<<<gv, T256, 0, s>>>(n_vox, bins_per_view, n_sub, k, Bt_rp, Bt_col, Bt_val,
                                             ratio, sens, S);
         }

@@ -50,6 +50,34 @@ def test_mlem_kernel_matches_oracle():
     assert np.all(g[~m_] <= 1e-5 * o.max())
 
 
+@pytest.mark.parametrize("density", [0.004, 0.1])
+def test_mlem_sparse_and_dense_rows(density):
+    """Sparse rows (one thread per row) and dense rows (one wavefront per row,
+    as forced-detection matrices have) give the oracle's MLEM and OSEM images."""
+    mc = _mc()
+    import torch
+    T, truth = phantoms.random_system(2400, 400, density, seed=34)
+    rng = np.random.Generator(np.random.PCG64(35))
+    P = rng.poisson(T.astype(np.float64) @ truth * 5).astype(np.float32)
+    m = mc.csr_from_scipy(T)
+    m.proj = torch.as_tensor(P, device="cuda")
+    img = torch.ones(T.shape[1], dtype=torch.float32, device="cuda")
+    mc.Mlem(m).run(img, 20)
+    T64 = T.astype(np.float64)
+    o = oracle.mlem(T64, P.astype(np.float64), 20)
+    g = img.cpu().numpy().astype(np.float64)
+    msk = o > 1e-6 * o.max()
+    rel = np.max(np.abs(g[msk] - o[msk]) / o[msk])
+    img2 = torch.ones(T.shape[1], dtype=torch.float32, device="cuda")
+    mc.osem(m, img2, 4, 6, 100)
+    o2 = oracle.osem(T64, P.astype(np.float64), 4, 6, 100)
+    g2 = img2.cpu().numpy().astype(np.float64)
+    msk2 = o2 > 1e-6 * o2.max()
+    rel2 = np.max(np.abs(g2[msk2] - o2[msk2]) / o2[msk2])
+    say(f"density {density}: {T.nnz / T.shape[0]:.1f} per bin row; MLEM max rel {rel:.2e}, OSEM {rel2:.2e}")
+    assert rel <= 1e-6 and rel2 <= 1e-6
+
+
 def test_mlem_fixed_point_on_gpu():
     mc = _mc()
     import torch

@@ -22,6 +22,8 @@
 // nothing; voxels with sens_i = 0 stay 0.  One thread per row: the matrix is
 // far sparser than one entry per row, so the row pointers and vectors are the
 // traffic (HBM-bound).
+#include <algorithm>
+
 #include "mc_internal.h"
 
 namespace mcs {
@@ -229,9 +231,13 @@ __device__ inline void sift(uint32_t* col, int64_t* w, uint64_t i, uint64_t n) {
     }
 }
 
-// sort each row's (column, weight) pairs by column -- insertion sort for the
-// short rows of analog lists, heapsort for the long rows of forced-detection
-// lists -- and count the distinct columns
+constexpr uint64_t ROW_SHORT = 32;      // rows up to this length: one thread, insertion sort
+constexpr uint64_t ROW_LDS = 4096;      // rows up to this length: one wavefront, LDS bitonic sort
+
+// sort each row's (column, weight) pairs by column and count the distinct
+// columns: short rows (analog lists) by insertion sort here, rows longer than
+// ROW_LDS by heapsort here; the rows between (forced-detection lists) are
+// left to k_sort_rows_wave
 __global__ __launch_bounds__(T256) void k_sort_rows(uint64_t n_rows, const uint64_t* start,
                                                     uint32_t* tmp_col, int64_t* tmp_w,
                                                     uint32_t* row_nnz) {
@@ -240,7 +246,8 @@ __global__ __launch_bounds__(T256) void k_sort_rows(uint64_t n_rows, const uint6
         const uint64_t b = start[r], e = start[r + 1], n = e - b;
         uint32_t* col = tmp_col + b;
         int64_t* w = tmp_w + b;
-        if (n <= 32) {
+        if (n > ROW_SHORT && n <= ROW_LDS) continue;
+        if (n <= ROW_SHORT) {
             for (uint64_t i = 1; i < n; ++i) {
                 const uint32_t v = col[i];
                 const int64_t wv = w[i];
@@ -260,6 +267,53 @@ __global__ __launch_bounds__(T256) void k_sort_rows(uint64_t n_rows, const uint6
         uint32_t d = 0;
         for (uint64_t i = b; i < e; ++i) d += (i == b || tmp_col[i] != tmp_col[i - 1]);
         row_nnz[r] = d;
+    }
+}
+
+// one wavefront per row of ROW_SHORT < length <= ROW_LDS: bitonic sort of the
+// (column, weight) pairs in LDS, padded to a power of two, then the count of
+// distinct columns
+__global__ __launch_bounds__(64) void k_sort_rows_wave(uint64_t n_rows, const uint64_t* start,
+                                                       uint32_t* tmp_col, int64_t* tmp_w,
+                                                       uint32_t* row_nnz) {
+    __shared__ uint32_t key[ROW_LDS];
+    __shared__ int64_t wt[ROW_LDS];
+    const uint32_t lane = threadIdx.x;
+    for (uint64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
+        const uint64_t b = start[r], n = start[r + 1] - b;
+        if (n <= ROW_SHORT || n > ROW_LDS) continue;
+        uint32_t m = 1;
+        while (m < n) m <<= 1;
+        for (uint32_t i = lane; i < m; i += 64) {
+            key[i] = i < n ? tmp_col[b + i] : 0xFFFFFFFFu;
+            wt[i] = i < n ? tmp_w[b + i] : 0;
+        }
+        __syncthreads();
+        for (uint32_t k = 2; k <= m; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t i = lane; i < m; i += 64) {
+                    const uint32_t x = i ^ j;
+                    if (x > i) {
+                        const bool up = (i & k) == 0;
+                        const uint32_t ki = key[i], kx = key[x];
+                        if ((ki > kx) == up) {
+                            key[i] = kx; key[x] = ki;
+                            const int64_t t = wt[i]; wt[i] = wt[x]; wt[x] = t;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        uint32_t d = 0;
+        for (uint32_t i = lane; i < n; i += 64) {
+            tmp_col[b + i] = key[i];
+            tmp_w[b + i] = wt[i];
+            d += (i == 0 || key[i] != key[i - 1]);
+        }
+        for (int o = 32; o > 0; o >>= 1) d += (uint32_t)__shfl_xor((int)d, o, 64);
+        if (lane == 0) row_nnz[r] = d;
+        __syncthreads();
     }
 }
 
@@ -557,6 +611,8 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
         if (e != hipSuccess) return e;
         k_scatter<<<ge, T256, 0, s>>>(a, transpose, start, fill, tmp_col, tmp_w);
         k_sort_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
+        k_sort_rows_wave<<<(int)std::min<uint64_t>(n_rows ? n_rows : 1, 16384), 64, 0, s>>>(
+            n_rows, start, tmp_col, tmp_w, row_nnz);
         e = exclusive_scan(row_nnz, n_rows, rowptr_u, bsum, s);
         if (e != hipSuccess) return e;
         k_emit_rows<<<grid_for(n_rows + 1, T256, 8192), T256, 0, s>>>(

@@ -95,6 +95,10 @@ def _load():
                                         P(C.c_int64), P(C.c_int64), P(C.c_double), P(C.c_int64),
                                         C.c_uint64, P(C.c_uint64)]
         lib.orc_set_box_skip.argtypes = [C.c_int]
+        lib.orc_simulate_cfd.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(_Result)]
+        lib.orc_cfd_kernel.argtypes = [C.c_double, C.c_double, C.c_double, P(C.c_double), P(C.c_int32)]
+        lib.orc_cfd_layers.argtypes = [P(_Problem)]
+        lib.orc_cfd_layers.restype = C.c_int32
         lib.orc_kn_pdf.argtypes = [C.c_double, C.c_double]
         lib.orc_kn_pdf.restype = C.c_double
         lib.orc_ray_integral.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(C.c_double)]
@@ -263,6 +267,37 @@ def simulate_fd(prob, n_threads: int = 0, want_triplets: bool = False, trip_cap:
         n = ntrip.value
         for k, a in (("trip_i", ti), ("trip_j", tj), ("trip_w", tw), ("trip_g", tg)):
             out[k] = a[:n].copy()
+    return out
+
+
+def simulate_cfd(prob, n_threads: int = 0, want_layers: bool = False):
+    """Convolution-based forced detection (Sec. 5.2): the analog histories'
+    fates, energies and counters; tally [V,2,nv,nu] from the depth layers
+    convolved with the collimator response; with want_layers the deposits
+    [V, L, 2, nv, nu]."""
+    lib = _load()
+    p, keep = _make_problem(prob, n_threads)
+    L = lib.orc_cfd_layers(C.byref(p))
+    tally = np.zeros(prob.tally_shape, dtype=np.float64)
+    lay = np.zeros((prob.n_views, L, 2, prob.nv, prob.nu), dtype=np.float64) if want_layers else None
+    res = _Result()
+    if lib.orc_simulate_cfd(C.byref(p), _ptr(tally, C.c_double), _ptr(lay, C.c_double), C.byref(res)) != 0:
+        raise RuntimeError("orc_simulate_cfd failed")
+    out = _result_dict(res)
+    out["tally"] = tally
+    if want_layers:
+        out["layers"] = lay
+    return out
+
+
+def cfd_kernel(depth_cm: float, alpha: float, pixel_cm: float) -> np.ndarray:
+    """Collimator response at a depth, on the pixel grid ((2h+1) x (2h+1))."""
+    lib = _load()
+    h = C.c_int32(0)
+    lib.orc_cfd_kernel(float(depth_cm), float(alpha), float(pixel_cm), None, C.byref(h))
+    n = 2 * h.value + 1
+    out = np.zeros((n, n), dtype=np.float64)
+    lib.orc_cfd_kernel(float(depth_cm), float(alpha), float(pixel_cm), _ptr(out, C.c_double), C.byref(h))
     return out
 
 

@@ -334,6 +334,8 @@ int32_t image_voxel(const orc_problem* p, int32_t vox);
 struct FdSink {
     std::vector<double>* tally;
     std::vector<double>* tally_sq;
+    bool cfd = false;              // convolution-based: deposit into depth layers
+    std::vector<std::pair<size_t, double>> layer_dep;   // (layer bin, weight)
     bool want_trip = false;
     int32_t emit_img = 0;          // image voxel of the current history's emission
     int64_t work = 0;              // its work index relative to history_offset
@@ -341,9 +343,87 @@ struct FdSink {
     std::vector<double> tw;
 };
 
+// ---------------------------------------------------------------------------
+// Convolution-based forced detection (CFD, Sec. 5.2).  The forced copy goes
+// along the perpendicular n_k to the detector: its weight is the forced-
+// detection weight with the direction at the cone axis, Omega_cone * pdf(n_k)
+// * exp(-g(E') * integral of mu140 along n_k), and instead of being followed
+// it is stored in a sub-projection layer: layer l = floor(d / pixel) of the
+// depth d = D - n_k . x, pixel of the perpendicular hit (u_k . x, z).  After
+// all histories each layer is convolved with the collimator response at its
+// depth (cfd_kernel) and the layers are summed into the projection.
+// ---------------------------------------------------------------------------
+int cfd_layers(const orc_problem* p) {
+    return (int)std::ceil(2.0 * p->radius_cm / p->pixel_cm);
+}
+
+// Collimator response at depth d (cm) on the pixel grid: a cone of half-angle
+// alpha with directions uniform in solid angle spreads a point's photons over
+// a disk of radius d tan(alpha) with plane density d / (2 pi (1 - cos a)
+// (d^2 + r^2)^(3/2)).  Integrated over each pixel with CFD_SUB x CFD_SUB
+// midpoint samples, normalised to sum 1; offsets -h..h.  Returns h.
+const int CFD_SUB = 8;
+int cfd_half_width(double d, double tan_a, double pix) {
+    return (int)std::ceil(d * tan_a / pix + 0.5);
+}
+void cfd_kernel(double d, double alpha, double pix, int h, std::vector<double>& k) {
+    const int n = 2 * h + 1;
+    k.assign((size_t)n * n, 0.0);
+    const double rho = d * std::tan(alpha), omc = 1.0 - std::cos(alpha);
+    double tot = 0.0;
+    for (int b = -h; b <= h; ++b)
+        for (int a = -h; a <= h; ++a) {
+            double acc = 0.0;
+            for (int t = 0; t < CFD_SUB; ++t)
+                for (int u = 0; u < CFD_SUB; ++u) {
+                    const double x = (a + (u + 0.5) / CFD_SUB - 0.5) * pix;
+                    const double y = (b + (t + 0.5) / CFD_SUB - 0.5) * pix;
+                    const double r2 = x * x + y * y;
+                    if (r2 > rho * rho) continue;
+                    acc += d / (2.0 * PI * omc * std::pow(d * d + r2, 1.5));
+                }
+            acc *= (pix / CFD_SUB) * (pix / CFD_SUB);
+            k[(size_t)(b + h) * n + (a + h)] = acc;
+            tot += acc;
+        }
+    if (tot > 0.0) for (auto& v : k) v /= tot;
+    else k[(size_t)h * n + h] = 1.0;
+}
+
+void cfd_score(const Setup& s, int32_t view, const double x[3], const double* d_in, double e,
+               int cls, FdSink& sink) {
+    const orc_problem* p = s.p;
+    const double nx = s.nvec_x[view], ny = s.nvec_y[view];
+    const double o[3] = {nx, ny, 0.0};
+    const double omega = 2.0 * PI * (1.0 - s.cos_alpha);
+    double weight, e2;
+    if (!d_in) {
+        weight = omega / (4.0 * PI);
+        e2 = e;
+    } else {
+        const double ct = d_in[0] * nx + d_in[1] * ny;
+        e2 = e / (1.0 + (e / MEC2_KEV) * (1.0 - ct));
+        weight = (1.0 - s.xs.p_pe(e)) * omega * kn_pdf(e, ct);
+    }
+    if (e2 < p->e_cut_kev || !(e2 >= p->e_lo_kev && e2 <= p->e_hi_kev)) return;
+    const double wu = p->nu * p->pixel_cm, wv = p->nv * p->pixel_cm;
+    const double au = (-ny * x[0] + nx * x[1]) + 0.5 * wu;
+    const double av = x[2] + 0.5 * wv;
+    if (!(au >= 0.0 && au < wu && av >= 0.0 && av < wv)) return;
+    const int iu = std::min((int)std::floor(au / p->pixel_cm), p->nu - 1);
+    const int iv = std::min((int)std::floor(av / p->pixel_cm), p->nv - 1);
+    const int L = cfd_layers(p);
+    const double depth = p->radius_cm - (x[0] * nx + x[1] * ny);
+    const int l = std::min(std::max((int)std::floor(depth / p->pixel_cm), 0), L - 1);
+    const double score = weight * std::exp(-s.xs.g(e2) * ray_mu_integral(s, x, o));
+    const size_t b = ((((size_t)view * L + l) * 2 + cls) * p->nv + iv) * p->nu + iu;
+    sink.layer_dep.emplace_back(b, score);
+}
+
 void fd_score(const Setup& s, int32_t view, uint64_t hist, uint32_t event, const double x[3],
               const double* d_in, double e, int cls, FdSink& sink) {
     const orc_problem* p = s.p;
+    if (sink.cfd) { cfd_score(s, view, x, d_in, e, cls, sink); return; }
     const Words w = philox4x32_10((uint32_t)hist, (uint32_t)view, event, FD_SUB, p->seed,
                                   p->problem_id);
     const double cos_b = 1.0 - uniform(w.r[0]) * (1.0 - s.cos_alpha);
@@ -768,6 +848,85 @@ int orc_simulate_fd(const orc_problem* p, double* tally, double* tally_sq, orc_r
     }
     return (want_trip && n_out > trip_cap) ? -2 : 0;
 }
+
+// Convolution-based forced detection (see cfd_score): the same analog
+// histories; tally [V][2][nv][nu] = sum over depth layers of the layer
+// deposits convolved with the collimator response at the layer's centre
+// depth; layers (nullable) [V][L][2][nv][nu] returns the deposits.
+int orc_simulate_cfd(const orc_problem* p, double* tally, double* layers, orc_result* res) {
+    Setup s;
+    if (!build_setup(p, s)) return -1;
+    const size_t nbins = (size_t)p->n_views * 2 * p->nv * p->nu;
+    const int L = cfd_layers(p);
+    const size_t nlay = nbins * (size_t)L;
+    const size_t nt = n_threads_for(p);
+    std::vector<Acc> acc(nt);
+    std::vector<FdSink> sinks(nt);
+    std::vector<std::vector<double>> dummy(nt);
+    for (size_t t = 0; t < nt; ++t) {
+        sinks[t].tally = &dummy[t];
+        sinks[t].tally_sq = &dummy[t];
+        sinks[t].cfd = true;
+    }
+    parallel_ranges(s.begin, s.end, nt, [&](size_t t, uint64_t b, uint64_t e) {
+        for (uint64_t g = b; g < e; ++g) {
+            int32_t view; uint64_t hist;
+            work_to_view_hist(s, g, view, hist);
+            History h;
+            run_history(s, view, hist, false, h, &sinks[t]);
+            accumulate(p, h, acc[t], false, false, g);
+        }
+    });
+    std::vector<double> lay(nlay, 0.0);
+    for (auto& k : sinks) for (auto& d : k.layer_dep) lay[d.first] += d.second;
+    if (layers) std::copy(lay.begin(), lay.end(), layers);
+    std::fill(tally, tally + nbins, 0.0);
+    std::vector<double> ker;
+    const double tan_a = std::tan(p->accept_half_angle_rad);
+    for (int l = 0; l < L; ++l) {
+        const double d = (l + 0.5) * p->pixel_cm;
+        const int h = cfd_half_width(d, tan_a, p->pixel_cm);
+        cfd_kernel(d, p->accept_half_angle_rad, p->pixel_cm, h, ker);
+        const int n = 2 * h + 1;
+        for (int v = 0; v < p->n_views; ++v)
+            for (int c = 0; c < 2; ++c)
+                for (int iv = 0; iv < p->nv; ++iv)
+                    for (int iu = 0; iu < p->nu; ++iu) {
+                        const double w = lay[((((size_t)v * L + l) * 2 + c) * p->nv + iv) * p->nu + iu];
+                        if (w == 0.0) continue;
+                        for (int b = -h; b <= h; ++b) {
+                            const int ov = iv + b;
+                            if (ov < 0 || ov >= p->nv) continue;
+                            for (int a = -h; a <= h; ++a) {
+                                const int ou = iu + a;
+                                if (ou < 0 || ou >= p->nu) continue;
+                                tally[(((size_t)v * 2 + c) * p->nv + ov) * p->nu + ou] +=
+                                    w * ker[(size_t)(b + h) * n + (a + h)];
+                            }
+                        }
+                    }
+    }
+    std::memset(res, 0, sizeof(*res));
+    for (auto& a : acc) {
+        for (int i = 0; i < 8; ++i) res->fates[i] += a.fates[i];
+        for (int i = 0; i < 4; ++i) res->energy[i] += a.energy[i];
+        res->n_tent += a.n_tent; res->n_real += a.n_real; res->n_kahn += a.n_kahn;
+        res->n_hist += a.n_hist;
+    }
+    return 0;
+}
+
+// Collimator response at depth d (see cfd_kernel): writes (2h+1)^2 values.
+int orc_cfd_kernel(double depth_cm, double alpha, double pixel_cm, double* out, int32_t* half) {
+    const int h = cfd_half_width(depth_cm, std::tan(alpha), pixel_cm);
+    std::vector<double> k;
+    cfd_kernel(depth_cm, alpha, pixel_cm, h, k);
+    if (out) std::copy(k.begin(), k.end(), out);
+    *half = h;
+    return 0;
+}
+
+int32_t orc_cfd_layers(const orc_problem* p) { return cfd_layers(p); }
 
 double orc_kn_pdf(double e_kev, double cos_t) { return kn_pdf(e_kev, cos_t); }
 

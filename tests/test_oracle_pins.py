@@ -715,3 +715,70 @@ def test_fd_response_matrix_consistency():
     sa = np.asarray(Ta.sum(axis=0)).ravel()
     # compare the total sensitivity (analog: ~1e4 counts, 1 % error)
     assert abs(sf.sum() - sa.sum()) < 4 * sa.sum() / math.sqrt(Pa.sum())
+
+
+# ---------------------------------------------------------------------------
+# Convolution-based forced detection (Sec. 5.2)
+# ---------------------------------------------------------------------------
+
+def test_cfd_collimator_response():
+    """The depth-dependent response of the ideal cone collimator: normalised,
+    symmetric, confined to the disk of radius d tan(alpha), and its encircled
+    fraction follows the closed form (1 - cos atan(r/d)) / (1 - cos alpha)
+    (uniform directions in the cone) to within the pixel discretisation."""
+    a = math.radians(2.0)
+    for d, pix in ((5.0, 0.6), (28.0, 0.6), (40.0, 0.3)):
+        k = oracle.cfd_kernel(d, a, pix)
+        assert k.sum() == pytest.approx(1.0, abs=1e-12)
+        np.testing.assert_allclose(k, k[::-1, :], atol=1e-15)
+        np.testing.assert_allclose(k, k.T, atol=1e-15)
+        h = (k.shape[0] - 1) // 2
+        yy, xx = np.mgrid[-h:h + 1, -h:h + 1] * pix
+        r_near = np.hypot(np.maximum(np.abs(xx) - pix / 2, 0), np.maximum(np.abs(yy) - pix / 2, 0))
+        assert np.all(k[r_near > d * math.tan(a) + 1e-12] == 0.0)
+    d = 20.0
+    rho = d * math.tan(a)
+    for n_pix, tol in ((40, 0.05), (80, 0.025)):
+        pix = rho / n_pix
+        k = oracle.cfd_kernel(d, a, pix)
+        h = (k.shape[0] - 1) // 2
+        yy, xx = np.mgrid[-h:h + 1, -h:h + 1] * pix
+        r = np.hypot(xx, yy)
+        for f in (0.3, 0.6, 0.9):
+            want = (1 - math.cos(math.atan(f * rho / d))) / (1 - math.cos(a))
+            assert abs(k[r <= f * rho].sum() - want) <= tol * want
+
+
+def test_cfd_point_source_closed_form():
+    """Point source in the water cube: every history deposits the same
+    primary weight (1 - cos a)/2 exp(-mu h) in one layer and pixel, so the
+    primary projection is exactly N times that weight spread by the response
+    at that layer's depth."""
+    N = 20_000
+    p = phantoms.point_cube_64(N)
+    r = oracle.simulate_cfd(p, want_layers=True)
+    w = 0.5 * (1 - math.cos(p.accept_half_angle_rad)) * math.exp(-float(np.float32(0.151)) * 6.4)
+    lay = r["layers"][0, :, 0]
+    nz = np.argwhere(lay != 0)
+    assert len(nz) == 1
+    l, iv, iu = nz[0]
+    assert lay[l, iv, iu] == pytest.approx(N * w, rel=1e-12)
+    assert l == int(math.floor(p.radius_cm / p.pixel_cm))
+    k = oracle.cfd_kernel((l + 0.5) * p.pixel_cm, p.accept_half_angle_rad, p.pixel_cm)
+    h = (k.shape[0] - 1) // 2
+    proj = r["tally"][0, 0]
+    np.testing.assert_allclose(proj[iv - h:iv + h + 1, iu - h:iu + h + 1], N * w * k, rtol=1e-12)
+    assert proj.sum() == pytest.approx(N * w, rel=1e-12)
+
+
+def test_cfd_agrees_with_forced_detection():
+    """On the same histories CFD differs from forced detection only by taking
+    the attenuation and angular density at the cone axis and the spread from
+    the response: per class the totals agree to O(alpha^2) (here 3e-3), and
+    the analog part of the run is unchanged."""
+    p = phantoms.thorax_problem("cfd_thorax", 32, 1.2, 2, 12, 180.0, 32, 1.2, 100_000)
+    c = oracle.simulate_cfd(p)
+    f = oracle.simulate_fd(p)
+    for k in range(2):
+        assert c["tally"][:, k].sum() == pytest.approx(f["tally"][:, k].sum(), rel=3e-3)
+    np.testing.assert_array_equal(c["fates"], f["fates"])

@@ -117,7 +117,9 @@ typedef struct {
                                 /* thresholds (else 4); 4: always 32-bit        */
     int32_t forced_detection;   /* mc_simulate_projections only: 1 = the tally  */
                                 /* is the forced-detection estimate (Sec. 5.2)  */
-                                /* instead of analog arrivals; 0 = analog       */
+                                /* instead of analog arrivals; 2 = convolution- */
+                                /* based forced detection; 0 = analog; also     */
+                                /* passed to mc_workspace_bytes (2 needs more)  */
     void* kernel_events[2];     /* optional hipEvent_t pair recorded on the     */
                                 /* stream right before / after the transport    */
                                 /* kernel (NULL: none)                          */
@@ -183,6 +185,21 @@ size_t mc_workspace_bytes(const mc_problem* problems, int32_t n_problems,
  * The event list, if given, holds one event per nonzero score (its weight is
  * the score; n_events counts them), so mc_system_matrix builds the forced-
  * detection response matrix from it; without a list n_events stays 0.
+ *
+ * Convolution-based forced detection (opt->forced_detection = 2; Sec. 5.2):
+ * the same histories and forced copies, but each copy goes along the detector
+ * normal n_k with the weight above taken at that direction, and is stored in
+ * the depth layer l = floor((D - n_k . x) / pixel) (clamped to the
+ * ceil(2 D / pixel) layers) at the pixel of its perpendicular hit.  After
+ * transport every layer is convolved with the response of the ideal cone
+ * collimator at its centre depth d = (l + 1/2) pixel: the plane density of
+ * directions uniform in the cone, d / (2 pi (1 - cos a) (d^2 + r^2)^(3/2))
+ * for r <= d tan a, integrated over each pixel with 8 x 8 midpoint samples
+ * and normalised, on offsets -h..h with h = ceil(d tan a / pixel + 1/2); the
+ * convolved layers (FP64, rounded once to Q31.32) are the tally.  tally_sq
+ * stays 0, events must be NULL (MC_EINVAL otherwise) and n_events stays 0.
+ * Problems whose deepest response has h > 24 are rejected (MC_EINVAL); the
+ * workspace holds the layers, 8 * V * L * 2 * nv * nu bytes per problem.
  * mc_adjoint_mu takes analog event lists only. */
 int mc_simulate_projections(const mc_problem* problems, int32_t n_problems,
                             const mc_options* opt,

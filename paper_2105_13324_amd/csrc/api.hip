@@ -67,19 +67,29 @@ bool check_problem(const mc_problem& p) {
     return true;
 }
 
+// Convolution-based forced detection geometry: layers of one pixel's depth
+// over [0, 2 D]; the largest response half-width is the deepest layer's.
+int cfd_layers(const mc_problem& p) { return (int)std::ceil(2.0 * p.radius_cm / p.pixel_cm); }
+int cfd_hmax(const mc_problem& p) {
+    const int nl = cfd_layers(p);
+    return cfd_half_width((nl - 0.5) * p.pixel_cm, std::tan(p.accept_half_angle_rad), p.pixel_cm);
+}
+bool cfd_ok(const mc_problem& p) { return cfd_layers(p) >= 1 && cfd_hmax(p) <= CFD_MAX_H; }
+
 struct Layout {
     size_t desc, prefix, state;
-    std::vector<size_t> q, q8, pal, cdf, vid, bsum, bcnt, guide, views, kn;
+    std::vector<size_t> q, q8, pal, cdf, vid, bsum, bcnt, guide, views, kn, lay, kern, hw;
     size_t total;
 };
 
-bool plan(const mc_problem* probs, int n, Layout& L) {
+bool plan(const mc_problem* probs, int n, Layout& L, bool cfd = false) {
     size_t off = 0;
     L.desc = off;   off += align256(sizeof(ProbDesc) * (size_t)n);
     L.prefix = off; off += align256(sizeof(uint64_t) * 2 * ((size_t)n + 1));
     L.state = off;  off += align256(sizeof(CallState));
     L.q.resize(n); L.q8.resize(n); L.pal.resize(n); L.cdf.resize(n); L.vid.resize(n); L.bsum.resize(n); L.bcnt.resize(n);
     L.guide.resize(n); L.views.resize(n); L.kn.resize(n);
+    L.lay.assign(n, 0); L.kern.assign(n, 0); L.hw.assign(n, 0);
     for (int i = 0; i < n; ++i) {
         const mc_problem& p = probs[i];
         const uint64_t nvox = (uint64_t)p.nx * p.ny * p.nz;
@@ -93,13 +103,19 @@ bool plan(const mc_problem* probs, int n, Layout& L) {
         L.guide[i] = off; off += align256(16 * guide_capacity(nvox));
         L.views[i] = off; off += align256(8 * (size_t)p.n_views);
         L.kn[i] = off;    off += align256(4 * (size_t)KN_TABLE_N);
+        if (cfd) {
+            const size_t nl = (size_t)cfd_layers(p), m = 2 * (size_t)cfd_hmax(p) + 1;
+            L.lay[i] = off;  off += align256(8 * nl * 2 * p.n_views * (size_t)p.nv * p.nu);
+            L.kern[i] = off; off += align256(8 * nl * m * m);
+            L.hw[i] = off;   off += align256(4 * nl);
+        }
     }
     L.total = off;
     return true;
 }
 
 ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64_t tally_offset,
-                   int brick_log2, int threshold_bytes) {
+                   int brick_log2, int threshold_bytes, bool cfd = false) {
     ProbDesc d;
     std::memset(&d, 0, sizeof(d));
     d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.source_mode = p.source_mode;
@@ -145,6 +161,16 @@ ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64
     d.guide = (uint4*)(ws + L.guide[i]);
     d.views = (float2*)(ws + L.views[i]);
     d.kn_table = (float*)(ws + L.kn[i]);
+    if (cfd) {
+        d.layers = (int64_t*)(ws + L.lay[i]);
+        d.cfd_kern = (double*)(ws + L.kern[i]);
+        d.cfd_h = (uint32_t*)(ws + L.hw[i]);
+        d.cfd_L = cfd_layers(p);
+        d.cfd_hmax = cfd_hmax(p);
+        d.alpha = p.accept_half_angle_rad;
+        d.cfd_pix = p.pixel_cm;
+        d.cfd_tan = std::tan(p.accept_half_angle_rad);
+    }
     return d;
 }
 
@@ -180,11 +206,13 @@ bool options_ok(int block, int hpl, int brick, int qbytes) {
 
 extern "C" {
 
-size_t mc_workspace_bytes(const mc_problem* problems, int32_t n_problems, const mc_options*) {
+size_t mc_workspace_bytes(const mc_problem* problems, int32_t n_problems, const mc_options* opt) {
     if (!problems || n_problems < 1) return 0;
-    for (int i = 0; i < n_problems; ++i) if (!check_problem(problems[i])) return 0;
+    const bool cfd = opt && opt->forced_detection == 2;
+    for (int i = 0; i < n_problems; ++i)
+        if (!check_problem(problems[i]) || (cfd && !cfd_ok(problems[i]))) return 0;
     Layout L;
-    plan(problems, n_problems, L);
+    plan(problems, n_problems, L, cfd);
     return L.total;
 }
 
@@ -194,25 +222,34 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
                             uint64_t* n_events, int64_t* status, void* workspace,
                             size_t workspace_bytes, void* stream) {
     if (!problems || n_problems < 1 || !tally || !fates || !status || !workspace) return MC_EINVAL;
-    if (opt && (opt->forced_detection < 0 || opt->forced_detection > 1)) return MC_EINVAL;
+    if (opt && (opt->forced_detection < 0 || opt->forced_detection > 2)) return MC_EINVAL;
+    const bool cfd = opt && opt->forced_detection == 2;
     if (events && !n_events) return MC_EINVAL;
-    for (int i = 0; i < n_problems; ++i) if (!check_problem(problems[i])) return MC_EINVAL;
+    if (cfd && events) return MC_EINVAL;   // convolved tallies have no per-copy bins
+    for (int i = 0; i < n_problems; ++i)
+        if (!check_problem(problems[i]) || (cfd && !cfd_ok(problems[i]))) return MC_EINVAL;
     int block, hpl, bpc, brick, qbytes;
     resolve(opt, block, hpl, bpc, brick, qbytes);
     if (!options_ok(block, hpl, brick, qbytes)) return MC_EINVAL;
     Layout L;
-    plan(problems, n_problems, L);
+    plan(problems, n_problems, L, cfd);
     if (workspace_bytes < L.total) return MC_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)workspace;
     ProbDesc* d_desc = (ProbDesc*)(ws + L.desc);
     uint64_t tally_elems = 0;
+    std::vector<ProbDesc> hd;
+    if (cfd) hd.reserve(n_problems);
     for (int i = 0; i < n_problems; ++i) {
         const mc_problem& p = problems[i];
-        const ProbDesc h = host_desc(p, ws, L, i, tally_elems, brick, qbytes);
+        const ProbDesc h = host_desc(p, ws, L, i, tally_elems, brick, qbytes, cfd);
         tally_elems += (uint64_t)p.n_views * 2 * p.nv * p.nu;
         hipError_t e = launch_staging(d_desc + i, h, st);
         if (e != hipSuccess) return hip_fail(e);
+        if (cfd) {
+            if ((e = launch_cfd_setup(d_desc + i, h, st)) != hipSuccess) return hip_fail(e);
+            hd.push_back(h);
+        }
     }
     const uint32_t chunk = (uint32_t)(64 * hpl);
     hipError_t e = launch_prepare_call(d_desc, n_problems, (uint64_t*)(ws + L.prefix),
@@ -224,7 +261,7 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e);
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return hip_fail(e);
-    const bool fd = opt && opt->forced_detection == 1;
+    const int fd = opt ? opt->forced_detection : 0;
     if (bpc <= 0) bpc = transport_blocks_per_cu(block, fd);
     TransportArgs a;
     a.descs = d_desc;
@@ -242,13 +279,15 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     a.event_capacity = events ? event_capacity : 0;
     a.n_events = (unsigned long long*)n_events;
     a.status = status;
-    a.forced_detection = fd ? 1 : 0;
+    a.forced_detection = fd;
     hipEvent_t ev0 = opt ? (hipEvent_t)opt->kernel_events[0] : nullptr;
     hipEvent_t ev1 = opt ? (hipEvent_t)opt->kernel_events[1] : nullptr;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return hip_fail(e);
     e = launch_transport(a, n_cu * bpc, block, st);
     if (e != hipSuccess) return hip_fail(e);
     if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return hip_fail(e);
+    for (int i = 0; i < (int)hd.size(); ++i)
+        if ((e = launch_cfd_convolve(d_desc + i, hd[i], tally, st)) != hipSuccess) return hip_fail(e);
     return MC_OK;
 }
 

@@ -590,5 +590,49 @@ __device__ inline bool fd_eval(const Cst& C, const ProbDesc* __restrict__ d, con
     return true;
 }
 
+// Convolution-based forced detection (Sec. 5.2): the forced copy goes along
+// the detector normal n_k instead of a direction drawn in the cone, with the
+// weight above taken at that direction, and is stored in the sub-projection
+// layer of its depth D - n_k . x (one pixel per layer, clamped to the layer
+// range) at the pixel of its perpendicular hit.  Returns false if it scores
+// nothing, else its index in the problem's layers [V][L][2][nv][nu] and its
+// weight.  The layers are convolved with the collimator response of their
+// depth after transport.
+__device__ inline bool cfd_eval(const Cst& C, const ProbDesc* __restrict__ d, const FdPoint& q,
+                                uint64_t& lbin, float& score) {
+    const float omc = d->omc_alpha, kn140 = (float)d->kn140;
+    const float2 vw = ldg(C.views + q.view);
+    float w, e2;
+    if (q.event == 0) {
+        w = 0.5f * omc;
+        e2 = q.e;
+    } else {
+        const float ct = q.dx * vw.x + q.dy * vw.y;
+        const float eps = rcpf(fmaf(q.e * INV_MEC2, 1.0f - ct, 1.0f));
+        e2 = q.e * eps;
+        float l2, ppe;
+        energy_terms(C, q.e, l2, ppe);
+        const float pdf = eps * eps * (eps + rcpf(eps) - (1.0f - ct * ct)) *
+                          rcpf(FOUR_PI_F * kn140 * kn_ratio(C, q.e));
+        w = (1.0f - ppe) * (TWO_PI_F * omc) * pdf;
+    }
+    if (!(e2 >= C.e_cut && e2 >= C.e_lo && e2 <= C.e_hi)) return false;
+    const float au = (-vw.y * q.x + vw.x * q.y) + 0.5f * C.wu;
+    const float av = q.z + 0.5f * C.wv;
+    if (!(au >= 0.0f && au < C.wu && av >= 0.0f && av < C.wv)) return false;
+    const int iu = min((int)(au * C.inv_pix), C.nu - 1);
+    const int iv = min((int)(av * C.inv_pix), C.nv - 1);
+    const int nl = d->cfd_L;
+    const float depth = C.radius - (q.x * vw.x + q.y * vw.y);
+    const int l = min(max((int)floorf(depth * C.inv_pix), 0), nl - 1);
+    float l2, ppe;
+    const float g = e2 == 140.0f ? 1.0f : energy_terms(C, e2, l2, ppe);
+    score = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, vw.x, vw.y, 0.0f));
+    const uint32_t cls = q.event == 0 ? 0u : 1u;
+    lbin = ((((uint64_t)q.view * (uint64_t)nl + (uint64_t)l) * 2u + cls) * (uint64_t)C.nv + (uint64_t)iv) *
+               (uint64_t)C.nu + (uint64_t)iu;
+    return true;
+}
+
 }  // namespace
 }  // namespace mcs

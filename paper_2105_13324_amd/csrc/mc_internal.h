@@ -57,7 +57,24 @@ struct ProbDesc {
     float omc_alpha;                // 1 - cos(alpha), from double precision (forced detection)
     uint32_t pad2;
     int32_t bb_lo[3], bb_hi[3];     // attenuation box: voxel index range of mu > 0 (staging)
+    // convolution-based forced detection (layers null otherwise)
+    int64_t* layers;                // [V][cfd_L][2][nv][nu] deposits, Q31.32
+    double* cfd_kern;               // [cfd_L][2 cfd_hmax + 1]^2 collimator responses
+    uint32_t* cfd_h;                // [cfd_L] response half-width per layer
+    int32_t cfd_L, cfd_hmax;        // depth layers (one pixel thick); largest half-width
+    double alpha, cfd_pix, cfd_tan; // collimator half-angle (rad), pixel (cm), tan(alpha)
 };
+
+// Convolution-based forced detection geometry (host and device agree):
+// L = ceil(2 D / pixel) layers of one pixel's depth; layer l's response is
+// evaluated at depth (l + 1/2) pixel with half-width h_l = ceil(d tan a /
+// pixel + 1/2) pixels and CFD_SUB x CFD_SUB samples per pixel.
+constexpr int CFD_SUB = 8;
+constexpr int CFD_MAX_H = 24;     // largest response half-width (pixels) accepted
+constexpr int CFD_TILE = 16;      // output tile edge of the convolution
+__host__ __device__ inline int cfd_half_width(double depth, double tan_a, double pix) {
+    return (int)ceil(depth * tan_a / pix + 0.5);
+}
 
 // Emission bucket b covers t in [b << shift, (b + 1) << shift) of the integer
 // activity CDF.  Bucket layout, as a uint4 (x, y, z, w):
@@ -95,6 +112,13 @@ struct CallState {
     unsigned long long pad[7];
 };
 
+// Host launchers (cfd.hip): zero the layers and build the responses (per call,
+// before transport); convolve the layers into the tally (after transport).
+// The host sizes the response table with cfd_hmax; each layer's half-width is
+// capped at it, so the table is never overrun.
+hipError_t launch_cfd_setup(ProbDesc* d, const ProbDesc& h, hipStream_t s);
+hipError_t launch_cfd_convolve(const ProbDesc* d, const ProbDesc& h, int64_t* tally, hipStream_t s);
+
 // Host launchers (staging.hip)
 hipError_t launch_staging(ProbDesc* d_desc, const ProbDesc& h_desc, hipStream_t s);
 uint64_t guide_capacity(uint64_t nvox);   // emission buckets reserved (power of two >= 2 nvox)
@@ -106,7 +130,7 @@ struct TransportArgs {
     const uint64_t* work_prefix;    // [n_problems + 1], device
     uint64_t total_work;
     uint32_t chunk;                 // work indices per claim (per wave)
-    int32_t forced_detection;       // 1: forced-detection estimator in the tally
+    int32_t forced_detection;       // 1: forced detection in the tally; 2: into CFD layers
     CallState* state;
     int64_t* tally;
     int64_t* tally_sq;
@@ -154,6 +178,6 @@ hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int
                        void* workspace, hipStream_t s);
 
 // Occupancy of the transport kernel (blocks per CU at this block size).
-int transport_blocks_per_cu(int block, bool forced_detection);
+int transport_blocks_per_cu(int block, int forced_detection);
 
 }  // namespace mcs

@@ -101,8 +101,19 @@ constexpr uint32_t FD_RING = 128;         // forced-detection queue per wave
 // Score the forced copy of each active lane: tally (Q31.32), sum of squares
 // (Q11.52) and, if listed, one event each (appended with one atomic per
 // wavefront by its first active lane).
+template <int MODE>
 __device__ inline void fd_commit(const Cst& C, int p, const FdPoint& q, int lane,
                                  const TransportArgs& T) {
+    if constexpr (MODE == 2) {
+        // convolution-based: deposit into the depth layer (no events, no
+        // sum of squares)
+        uint64_t lb = 0;
+        float sc = 0.0f;
+        if (cfd_eval(C, T.descs + p, q, lb, sc))
+            atomicAdd((unsigned long long*)(T.descs[p].layers + lb),
+                      (unsigned long long)(long long)__float2ll_rn(sc * 4294967296.0f));
+        return;
+    }
     uint32_t bin = 0;
     float sc = 0.0f;
     const bool ok = fd_eval(C, T.descs + p, q, bin, sc);
@@ -137,6 +148,7 @@ __device__ inline void fd_commit(const Cst& C, int p, const FdPoint& q, int lane
 }
 
 // Score the n (<= 64) forced copies at the head of a wave's ring.
+template <int MODE>
 __device__ inline void fd_drain(const Cst& C, int p, const FdPoint* ring, uint32_t& head, uint32_t n,
                                 int lane, const TransportArgs& T) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -144,7 +156,7 @@ __device__ inline void fd_drain(const Cst& C, int p, const FdPoint* ring, uint32
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if ((uint32_t)lane < n) {
         const FdPoint q = ring[(head + (uint32_t)lane) & (FD_RING - 1)];
-        fd_commit(C, p, q, lane, T);
+        fd_commit<MODE>(C, p, q, lane, T);
     }
     head += n;
 }
@@ -153,11 +165,13 @@ __device__ inline void fd_drain(const Cst& C, int p, const FdPoint* ring, uint32
 // A wavefront emits the next EMIT_BATCH histories of its chunk in one
 // converged phase into LDS; idle lanes then start histories from there, so
 // the per-lane loop only alternates tentative collisions and Kahn attempts.
-// FD: forced-detection estimator instead of analog arrivals in the tally.
-template <bool FD>
+// MODE 0: analog arrivals into the tally; 1: forced detection (tally);
+// 2: convolution-based forced detection (depth layers).
+template <int MODE>
 __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restrict__ my,
                                                uint32_t* __restrict__ my_pal,
                                                FdPoint* __restrict__ ring) {
+    constexpr bool FD = MODE != 0;
     const int lane = threadIdx.x & 63;
     uint32_t fd_head = 0, fd_tail = 0;    // wave-uniform ring cursors (FD)
     const uint64_t lane_lt = (1ull << lane) - 1ull;
@@ -257,7 +271,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                                 q.e = 140.0f;
                                 q.view = (uint32_t)v; q.hist = (uint32_t)h; q.event = 0;
                                 q.voxel = e.voxel;
-                                fd_commit(C, p, q, lane, T);
+                                fd_commit<MODE>(C, p, q, lane, T);
                             }
                         }
                     }
@@ -297,7 +311,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             fate = advance(C, my_pal, L, c0, c1, c2, c3, A, iu, iv);
             if (fate != R_RUNNING) {
                 // outgoing energy: escaped, or left at the step cap (rare: booked at once)
-                const float out = (fate == MC_ABSORBED) | (fate == MC_CUT) ? 0.0f : L.e;
+                const float out = ((fate == MC_ABSORBED) | (fate == MC_CUT)) ? 0.0f : L.e;
                 if (fate == MC_CAPPED_FATE) {
                     if (T.energy)
                         atomicAdd((unsigned long long*)(T.energy + (size_t)p * 4 + 2),
@@ -333,7 +347,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             // a time, or what is left once no lane is busy
             const uint32_t cnt = fd_tail - fd_head;
             if (cnt >= 64 || (cnt != 0 && __ballot(L.state != S_IDLE) == 0))
-                fd_drain(C, p, ring, fd_head, cnt < 64 ? cnt : 64u, lane, T);
+                fd_drain<MODE>(C, p, ring, fd_head, cnt < 64 ? cnt : 64u, lane, T);
         }
         if (__ballot(fate != R_RUNNING) != 0) {
             // fate counts through ballots: wave-uniform, no per-lane counters
@@ -367,15 +381,23 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TransportArgs T) {
     __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
     __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
-    transport_body<false>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr);
+    transport_body<0>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr);
 }
 
 __global__ __launch_bounds__(256) void k_transport_fd(TransportArgs T) {
     __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
     __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
     __shared__ FdPoint ring[WAVES_PER_BLOCK_MAX][FD_RING];
-    transport_body<true>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6],
-                         ring[threadIdx.x >> 6]);
+    transport_body<1>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6],
+                      ring[threadIdx.x >> 6]);
+}
+
+__global__ __launch_bounds__(256) void k_transport_cfd(TransportArgs T) {
+    __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
+    __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
+    __shared__ FdPoint ring[WAVES_PER_BLOCK_MAX][FD_RING];
+    transport_body<2>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6],
+                      ring[threadIdx.x >> 6]);
 }
 
 // Replay: one listed history per lane, run to its end, one record out.
@@ -503,7 +525,8 @@ hipError_t launch_prepare_call(const ProbDesc* descs, int32_t n_problems, uint64
 }
 
 hipError_t launch_transport(const TransportArgs& a, int grid, int block, hipStream_t s) {
-    if (a.forced_detection) k_transport_fd<<<grid, block, 0, s>>>(a);
+    if (a.forced_detection == 2) k_transport_cfd<<<grid, block, 0, s>>>(a);
+    else if (a.forced_detection) k_transport_fd<<<grid, block, 0, s>>>(a);
     else k_transport<<<grid, block, 0, s>>>(a);
     // without a list the count is informational and cannot overflow
     k_finalize<<<1, 64, 0, s>>>(a.descs, a.n_problems, a.status, a.n_events,
@@ -522,9 +545,11 @@ hipError_t launch_replay(const ProbDesc* d_desc, const int32_t* views, const uin
     return hipGetLastError();
 }
 
-int transport_blocks_per_cu(int block, bool forced_detection) {
+int transport_blocks_per_cu(int block, int forced_detection) {
     int n = 0;
-    const hipError_t e = forced_detection
+    const hipError_t e = forced_detection == 2
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport_cfd, block, 0)
+        : forced_detection
         ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport_fd, block, 0)
         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport, block, 0);
     if (e != hipSuccess) return 1;

@@ -2,6 +2,7 @@
 every declared entry point, its structures match the header, and argument
 validation rejects bad inputs before touching the device."""
 import ctypes as C
+import math
 import os
 import re
 import subprocess
@@ -138,8 +139,23 @@ def test_simulate_rejects_bad_buffers_before_launch():
     assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
     o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=0, threshold_bytes=2)
     assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
-    o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=0, forced_detection=2)
+    o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=0, forced_detection=3)
     assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
+    # convolution-based forced detection: the depth layers need more workspace,
+    # an event list is refused, and so is a response wider than 24 pixels
+    o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=0, forced_detection=2)
+    need_cfd = lib.mc_workspace_bytes(C.byref(p), 1, C.byref(o))
+    L = math.ceil(2 * p.radius_cm / p.pixel_cm)
+    assert need_cfd >= need + 8 * L * 2 * p.n_views * p.nv * p.nu
+    assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_ENOMEM
+    assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, 8, 10, 8, 8, 8, need_cfd,
+               None) == mc.MC_EINVAL
+    wide = _good()
+    wide.accept_half_angle_rad = 1.4
+    assert lib.mc_workspace_bytes(C.byref(wide), 1, None) > 0
+    assert lib.mc_workspace_bytes(C.byref(wide), 1, C.byref(o)) == 0
+    assert sim(C.byref(wide), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need_cfd,
+               None) == mc.MC_EINVAL
     # the adjoint is of analog tallies only
     o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=0, forced_detection=1)
     assert mc._lib.mc_adjoint_mu(C.byref(p), C.byref(o), 8, None, None, 0, 8, 40, 8, 8, need,

@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="time only the headline workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 256^3 / 1e9-history form")
+    ap.add_argument("--only-form", choices=["forced_detection"], default=None,
+                    help="time only this side form (forced detection and its convolution-based "
+                         "form) and print its record; for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -117,6 +120,9 @@ def main():
         return
     import phantoms
     import paper_2105_13324_amd as mc
+    if args.only_form == "forced_detection":
+        print(json.dumps({"form": "forced_detection", **fd_form(mc, torch, args.steps)}))
+        return
 
     n_hist = int(args.histories)
     prob = phantoms.thorax_128(n_hist)
@@ -257,41 +263,63 @@ def extra_forms(mc, torch, args):
 
 
 def fd_form(mc, torch, steps):
-    """Forced detection (Sec. 5.2) on the 128^3 thorax, 60 views, 1e7
-    histories: throughput, and the figure of merit 1 / (variance per history x
-    time per history) of the total window count against analog transport.
-    Analog variance per history is binomial, p (1 - p); the forced-detection
-    variance comes from 16 independent seeds of 1e6 histories."""
+    """Forced detection and convolution-based forced detection (Sec. 5.2) on
+    the 128^3 thorax, 60 views, 1e7 histories: throughput, and figures of
+    merit 1 / (variance per history x time per history) against analog
+    transport, for the total window count and for the projection bin by bin
+    (variances summed over bins).  Analog variances are binomial, p (1 - p)
+    per bin; the forced estimates' variances come from 16 independent seeds
+    of 1e6 histories."""
     import phantoms
     n = 10 ** 7
     p = phantoms.thorax_128(n)
     dp = mc.to_device(p)
-    fd = {"forced_detection": 1}
-    sf = mc.Simulator(dp, want_sq=True, options=fd)
-    sf.run()
-    ms_fd = timed(torch, sf.run, steps)
-    sf.check_status()
     sa = mc.Simulator(dp, want_sq=False)
     sa.run()
     ms_an = timed(torch, sa.run, steps)
-    p_an = float(mc.tally_float(sa.tally).sum()) / n
-    nz_fd = int((sf.tally != 0).sum().item())
+    pb = mc.tally_float(sa.tally) / n
+    p_an = float(pb.sum())
+    var_an = p_an * (1.0 - p_an)
+    bins_an = float((pb * (1.0 - pb)).sum())
     nz_an = int((sa.tally != 0).sum().item())
     m = 10 ** 6
-    totals = []
-    for k in range(16):
-        sk = mc.simulate(mc.to_device(p.with_(n_histories=m, seed=2000 + k)), want_sq=False, options=fd)
-        totals.append(float(mc.tally_float(sk.tally).sum()) / m)
-    var_fd = float(np.var(totals, ddof=1)) * m
-    var_an = p_an * (1.0 - p_an)
-    t_fd, t_an = ms_fd / n, ms_an / n
-    return {"value": n / (ms_fd / 1e3), "unit": "histories/s", "ms_per_step": ms_fd,
-            "histories": n, "analog_ms_per_step": ms_an,
-            "window_count_per_history": {"forced_detection": float(np.mean(totals)), "analog": p_an},
-            "variance_per_history": {"forced_detection": var_fd, "analog": var_an},
-            "fom_gain": (var_an * t_an) / (var_fd * t_fd),
-            "nonzero_bins": {"forced_detection": nz_fd, "analog": nz_an},
-            "seeds": 16}
+    out = {}
+    for name, mode in (("forced_detection", 1), ("convolution_fd", 2)):
+        opt = {"forced_detection": mode}
+        sf = mc.Simulator(dp, want_sq=mode == 1, options=opt)
+        sf.run()
+        ms = timed(torch, sf.run, steps)
+        sf.check_status()
+        timers = [mc.KernelTimer() for _ in range(steps)]
+        for t in timers:
+            sf.run(kernel_events=t.handles)
+        torch.cuda.synchronize()
+        k_ms = float(np.mean([t.elapsed_ms() for t in timers]))
+        nz = int((sf.tally != 0).sum().item())
+        del sf
+        tallies = []
+        for k in range(16):
+            sk = mc.simulate(mc.to_device(p.with_(n_histories=m, seed=2000 + k)), want_sq=False,
+                             options=opt)
+            tallies.append(mc.tally_float(sk.tally) / m)
+        tallies = np.stack(tallies)
+        totals = tallies.sum(axis=1)
+        var = float(np.var(totals, ddof=1)) * m
+        bins = float(np.var(tallies, axis=0, ddof=1).sum()) * m
+        t_f, t_an = ms / n, ms_an / n
+        out[name] = {"value": n / (ms / 1e3), "unit": "histories/s", "ms_per_step": ms,
+                     "transport_ms": k_ms, "histories": n,
+                     "window_count_per_history": float(np.mean(totals)),
+                     "variance_per_history": var, "bin_variance_per_history": bins,
+                     "fom_gain": (var_an * t_an) / (var * t_f),
+                     "bin_fom_gain": (bins_an * t_an) / (bins * t_f),
+                     "nonzero_bins": nz}
+    fd = out.pop("forced_detection")
+    fd.update({"analog_ms_per_step": ms_an, "analog_window_count_per_history": p_an,
+               "analog_variance_per_history": var_an, "analog_bin_variance_per_history": bins_an,
+               "analog_nonzero_bins": nz_an, "seeds": 16,
+               "convolution_fd": out["convolution_fd"]})
+    return fd
 
 
 def large_fd(mc, torch, steps, p5):

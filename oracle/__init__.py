@@ -51,6 +51,7 @@ class _Problem(C.Structure):
         ("n_histories", C.c_uint64), ("history_offset", C.c_uint64), ("history_count", C.c_uint64),
         ("seed", C.c_uint32), ("problem_id", C.c_uint32), ("max_steps", C.c_uint32),
         ("n_threads", C.c_uint32),
+        ("activity_prev", C.POINTER(C.c_uint32)),
     ]
 
 
@@ -121,6 +122,8 @@ def _make_problem(prob, n_threads: int = 0):
     mu = np.ascontiguousarray(prob.mu, dtype=np.float32)
     act = np.ascontiguousarray(prob.activity, dtype=np.uint32)
     ang = np.ascontiguousarray(prob.angles, dtype=np.float64)
+    prev = (np.ascontiguousarray(prob.activity_prev, dtype=np.uint32)
+            if getattr(prob, "activity_prev", None) is not None else None)
     p = _Problem(nx=prob.nx, ny=prob.ny, nz=prob.nz, source_mode=prob.source_mode,
                  voxel_cm=prob.voxel_cm, mu140=_ptr(mu, C.c_float), activity=_ptr(act, C.c_uint32),
                  n_views=prob.n_views, nu=prob.nu, nv=prob.nv, image_factor=prob.image_factor,
@@ -130,8 +133,8 @@ def _make_problem(prob, n_threads: int = 0):
                  pe_fraction=prob.pe_fraction, n_histories=prob.n_histories,
                  history_offset=prob.history_offset, history_count=prob.history_count,
                  seed=prob.seed, problem_id=prob.problem_id, max_steps=prob.max_steps,
-                 n_threads=n_threads)
-    return p, (mu, act, ang)
+                 n_threads=n_threads, activity_prev=_ptr(prev, C.c_uint32))
+    return p, (mu, act, ang, prev)
 
 
 def _result_dict(r: _Result):

@@ -130,6 +130,7 @@ typedef struct {
     double e_lo_kev, e_hi_kev, e_cut_kev, pe_fraction;
     uint64_t n_histories, history_offset, history_count;
     uint32_t seed, problem_id, max_steps, n_threads;
+    const uint32_t* activity_prev;   // nullable: the source is activity - activity_prev
 } orc_problem;
 
 typedef struct {
@@ -175,6 +176,15 @@ struct Setup {
 // check that nothing but the number of tentative collisions changes.
 bool g_box_skip = true;
 
+// Reuse of photon tracks (Sec. 5.3): the projection of the new estimate is
+// the old projection plus the projection of the difference d = lambda(k) -
+// lambda(k-1) (activity - activity_prev), a source of signed activity.  Its
+// histories are drawn from |d| and every tally contribution carries the sign
+// of d at the emitting voxel.
+double source_sign(const orc_problem* p, int32_t vox) {
+    return (p->activity_prev && p->activity[vox] < p->activity_prev[vox]) ? -1.0 : 1.0;
+}
+
 bool build_setup(const orc_problem* p, Setup& s) {
     s.p = p;
     const size_t nvox = (size_t)p->nx * p->ny * p->nz;
@@ -202,9 +212,15 @@ bool build_setup(const orc_problem* p, Setup& s) {
     }
     s.box_empty = hi[0] < 0;
     for (int a = 0; a < 3; ++a) { s.box_first[a] = lo[a]; s.box_last[a] = hi[a]; }
+    // a difference source (reuse of photon tracks) emits in proportion to
+    // the magnitude of the difference
     s.cdf.assign(nvox, 0);
     uint64_t acc = 0;
-    for (size_t i = 0; i < nvox; ++i) { acc += p->activity[i]; s.cdf[i] = acc; }
+    for (size_t i = 0; i < nvox; ++i) {
+        const int64_t a = (int64_t)p->activity[i] - (p->activity_prev ? (int64_t)p->activity_prev[i] : 0);
+        acc += (uint64_t)(a < 0 ? -a : a);
+        s.cdf[i] = acc;
+    }
     s.total = acc;
     if (s.total == 0) return false;
     s.xs.f_pe = p->pe_fraction;
@@ -244,6 +260,7 @@ struct History {
     int32_t fate = -1, view = 0, iu = -1, iv = -1, n_scatter = 0, n_tent = 0, n_real = 0,
             n_kahn = 0, emit_voxel = -1, cls = 0;
     double e = E0_KEV, dep = 0.0, esc = 0.0, capped = 0.0;
+    double sign = 1.0;           // of the emitting voxel's activity (signed source)
     // path (only filled when requested)
     std::vector<Vertex> verts;   // emission point, then each Compton vertex
     double dfinal[3] = {0, 0, 0};
@@ -338,6 +355,7 @@ struct FdSink {
     std::vector<std::pair<size_t, double>> layer_dep;   // (layer bin, weight)
     bool want_trip = false;
     int32_t emit_img = 0;          // image voxel of the current history's emission
+    double sign = 1.0;             // sign of its source (signed source)
     int64_t work = 0;              // its work index relative to history_offset
     std::vector<int64_t> ti, tj, tg;
     std::vector<double> tw;
@@ -415,7 +433,7 @@ void cfd_score(const Setup& s, int32_t view, const double x[3], const double* d_
     const int L = cfd_layers(p);
     const double depth = p->radius_cm - (x[0] * nx + x[1] * ny);
     const int l = std::min(std::max((int)std::floor(depth / p->pixel_cm), 0), L - 1);
-    const double score = weight * std::exp(-s.xs.g(e2) * ray_mu_integral(s, x, o));
+    const double score = sink.sign * weight * std::exp(-s.xs.g(e2) * ray_mu_integral(s, x, o));
     const size_t b = ((((size_t)view * L + l) * 2 + cls) * p->nv + iv) * p->nu + iu;
     sink.layer_dep.emplace_back(b, score);
 }
@@ -450,7 +468,7 @@ void fd_score(const Setup& s, int32_t view, uint64_t hist, uint32_t event, const
     if (!(au >= 0.0 && au < wu && av >= 0.0 && av < wv)) return;
     const int iu = std::min((int)std::floor(au / p->pixel_cm), p->nu - 1);
     const int iv = std::min((int)std::floor(av / p->pixel_cm), p->nv - 1);
-    const double score = weight * std::exp(-s.xs.g(e2) * ray_mu_integral(s, x, o));
+    const double score = sink.sign * weight * std::exp(-s.xs.g(e2) * ray_mu_integral(s, x, o));
     const size_t b = (((size_t)view * 2 + cls) * p->nv + iv) * p->nu + iu;
     (*sink.tally)[b] += score;
     (*sink.tally_sq)[b] += score * score;
@@ -478,6 +496,7 @@ void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, Hi
     // voxel i with cdf[i-1] <= t < cdf[i]
     const size_t vox = (size_t)(std::upper_bound(s.cdf.begin(), s.cdf.end(), t) - s.cdf.begin());
     h.emit_voxel = (int32_t)vox;
+    h.sign = source_sign(p, (int32_t)vox);
     double x[3];
     if (p->source_mode == 1) {
         x[0] = x[1] = x[2] = 0.0;
@@ -499,6 +518,7 @@ void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, Hi
     if (keep_path) h.verts.push_back(Vertex{{x[0], x[1], x[2]}, e});
     if (fd) {
         fd->emit_img = image_voxel(p, (int32_t)vox);
+        fd->sign = h.sign;
         fd_score(s, view, hist, 0, x, nullptr, e, 0, *fd);
     }
 
@@ -622,7 +642,7 @@ void accumulate(const orc_problem* p, const History& h, Acc& a, bool want_tally,
     a.n_tent += h.n_tent; a.n_real += h.n_real; a.n_kahn += h.n_kahn; a.n_hist++;
     if (h.fate == TALLIED) {
         const size_t b = bin_index(p, h.view, h.cls, h.iv, h.iu);
-        if (want_tally) { a.tally[b] += 1.0; a.tally_sq[b] += 1.0; }
+        if (want_tally) { a.tally[b] += h.sign; a.tally_sq[b] += 1.0; }
         if (want_trip) {
             a.trip_i.push_back(image_voxel(p, h.emit_voxel));
             a.trip_j.push_back((int64_t)b);
@@ -979,6 +999,7 @@ int orc_adjoint(const orc_problem* p, const double* G, double* grad, int64_t* n_
                 const double* lam, const double* y, double eps, double* fd_out,
                 orc_result* res) {
     Setup s;
+    if (p->activity_prev) return -1;   // the adjoint is of plain (unsigned) sources
     if (!build_setup(p, s)) return -1;
     const size_t nvox = (size_t)p->nx * p->ny * p->nz;
     const size_t nloss = (size_t)p->n_views * p->nv * p->nu;

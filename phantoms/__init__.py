@@ -62,6 +62,9 @@ class Problem:
     max_steps: int = 1000
     history_offset: int = 0
     history_count: int = 0    # 0 = all remaining histories
+    # optional previous activity [nz, ny, nx] uint32: the source is then the
+    # difference activity - activity_prev (signed)
+    activity_prev: Optional[np.ndarray] = None
 
     @property
     def n_views(self) -> int:
@@ -227,6 +230,17 @@ def thorax_256(n_hist: int = 10**9) -> Problem:
     """256^3 thorax at 1.5 mm, 120 views over 360 degrees, 128x128 pixels at 3 mm."""
     return thorax_problem("thorax_256", 256, 0.15, 5, 120, 360.0, 128, 0.3, n_hist,
                           image_factor=4)
+
+
+def estimate_pair(act: np.ndarray, rel: float, seed: int, scale: int = 1000, bias: float = 0.0):
+    """Two successive image estimates for reuse of photon tracks: the previous
+    one is act * scale, the new one that times (1 + bias + rel * U(-1, 1))
+    voxel by voxel (numpy PCG64(seed)), rounded.  Returns (new, previous),
+    uint32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    prev = act.astype(np.float64) * scale
+    new = np.rint(prev * (1.0 + bias + rel * rng.uniform(-1.0, 1.0, size=act.shape)))
+    return new.astype(np.uint32), prev.astype(np.uint32)
 
 
 def poisson_target(lam: np.ndarray, seed: int = 4) -> np.ndarray:

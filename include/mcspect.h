@@ -103,6 +103,16 @@ typedef struct {
     uint32_t seed, problem_id;  /* Philox key                                   */
     int32_t image_factor;       /* >0: image voxel = phantom voxel / factor     */
     uint32_t max_steps;         /* cap on tentative collisions (0 = 1000)       */
+    const uint32_t* activity_prev; /* device [nz*ny*nx] or NULL: reuse of photon */
+                                /* tracks (Sec. 5.3): the source is then the    */
+                                /* signed difference d = activity -             */
+                                /* activity_prev; histories are drawn from |d|  */
+                                /* and every tally contribution (and event      */
+                                /* weight) carries the sign of d at the         */
+                                /* emitting voxel, so tally x sum|d| / (N / V)  */
+                                /* is the projection of d, to be added to that  */
+                                /* of activity_prev.  Forward projection only:  */
+                                /* mc_adjoint_mu and mc_system_matrix reject it */
 } mc_problem;
 
 typedef struct {

@@ -55,6 +55,7 @@ class McProblem(C.Structure):
         ("n_histories", C.c_uint64), ("history_offset", C.c_uint64), ("history_count", C.c_uint64),
         ("seed", C.c_uint32), ("problem_id", C.c_uint32),
         ("image_factor", C.c_int32), ("max_steps", C.c_uint32),
+        ("activity_prev", C.c_void_p),
     ]
 
 
@@ -70,7 +71,7 @@ EVENT_DTYPE = np.dtype([("work", np.uint64), ("bin", np.uint32), ("emit_voxel", 
 RECORD_DTYPE = np.dtype([("fate", np.int32), ("view", np.int32), ("iu", np.int32), ("iv", np.int32),
                          ("n_scatter", np.int32), ("n_tent", np.int32), ("emit_voxel", np.int32),
                          ("cls", np.int32), ("e_final", np.float64)])
-assert C.sizeof(McProblem) == 160
+assert C.sizeof(McProblem) == 168
 
 _vp, _i32, _i64, _u64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
 _lib.mc_workspace_bytes.argtypes = [C.POINTER(McProblem), _i32, C.POINTER(McOptions)]
@@ -148,6 +149,7 @@ class DeviceProblem:
     max_steps: int = 1000
     history_offset: int = 0
     history_count: int = 0
+    activity_prev: Optional[object] = None   # device uint32 map: difference source
 
     @property
     def n_views(self) -> int:
@@ -172,7 +174,8 @@ class DeviceProblem:
             e_hi_kev=self.e_hi_kev, e_cut_kev=self.e_cut_kev, pe_fraction=self.pe_fraction,
             n_histories=self.n_histories, history_offset=self.history_offset,
             history_count=self.history_count, seed=self.seed, problem_id=self.problem_id,
-            image_factor=self.image_factor, max_steps=self.max_steps)
+            image_factor=self.image_factor, max_steps=self.max_steps,
+            activity_prev=self.activity_prev.data_ptr() if self.activity_prev is not None else None)
 
 
 _SCALARS = ["nx", "ny", "nz", "voxel_cm", "nu", "nv", "pixel_cm", "radius_cm",
@@ -188,7 +191,10 @@ def to_device(prob, device="cuda") -> DeviceProblem:
     act = torch.from_numpy(np.ascontiguousarray(prob.activity, dtype=np.uint32).view(np.int32)).to(device)
     ang = torch.from_numpy(np.ascontiguousarray(prob.angles, dtype=np.float64)).to(device)
     kw = {k: getattr(prob, k) for k in _SCALARS}
-    return DeviceProblem(mu=mu, activity=act, angles=ang, **kw)
+    prev = getattr(prob, "activity_prev", None)
+    if prev is not None:
+        prev = torch.from_numpy(np.ascontiguousarray(prev, dtype=np.uint32).view(np.int32)).to(device)
+    return DeviceProblem(mu=mu, activity=act, angles=ang, activity_prev=prev, **kw)
 
 
 def _opts(options: Optional[dict]) -> Optional[McOptions]:
@@ -364,6 +370,59 @@ def replay(problem: DeviceProblem, views, hists, options=None) -> np.ndarray:
 def tally_float(t) -> np.ndarray:
     """Fixed-point tally -> float64 counts."""
     return t.cpu().numpy().astype(np.float64) / Q32
+
+
+class RptProjector:
+    """Reuse of photon tracks (Sec. 5.3) for the reprojections of an iterative
+    reconstruction: the first call simulates the whole estimate; each later
+    call simulates only the difference to the previous estimate (a signed
+    source, activity_prev) and adds its projection to the previous one.
+
+    problem: the geometry and camera (its activity is replaced per call).
+    histories_per_unit: histories per unit of source activity (|d| for a
+    difference), rounded to a whole number per view, at least one per view.
+    Projections are float64 tensors [V, 2, nv, nu] in activity units: the
+    expected projection of a source of total activity A from N histories over
+    V views is tally x A V / N."""
+
+    def __init__(self, problem: DeviceProblem, histories_per_unit: float, options=None):
+        self.problem = problem
+        self.hpu = float(histories_per_unit)
+        self.options = options
+        self.prev = None
+        self.projection = None
+        self.histories = []        # histories simulated per call
+        self.seed = int(problem.seed)
+
+    def _run(self, activity, prev):
+        torch = _torch()
+        a = activity.to(torch.int64) & 0xFFFFFFFF        # the maps hold uint32 bits
+        if prev is not None:
+            total = int((a - (prev.to(torch.int64) & 0xFFFFFFFF)).abs().sum().item())
+        else:
+            total = int(a.sum().item())
+        V = self.problem.n_views
+        per_view = max(1, int(round(self.hpu * total / V)))
+        n = per_view * V
+        self.seed += 1
+        dp = self.problem.with_(activity=activity, activity_prev=prev, n_histories=n,
+                                history_offset=0, history_count=0, seed=self.seed)
+        self.histories.append(n)
+        if total == 0:
+            return torch.zeros(dp.tally_shape, dtype=torch.float64, device=activity.device)
+        sim = simulate(dp, want_sq=False, options=self.options)
+        return sim.tally.view(dp.tally_shape).to(torch.float64) * (2.0 ** -32 * total * V / n)
+
+    def project(self, activity):
+        """Projection of the estimate `activity` (device uint32 map stored as
+        int32, as to_device makes it)."""
+        activity = activity.contiguous()
+        if self.prev is None:
+            self.projection = self._run(activity, None)
+        else:
+            self.projection = self.projection + self._run(activity, self.prev)
+        self.prev = activity.clone()
+        return self.projection
 
 
 def fd_tally_sq_float(t) -> np.ndarray:

@@ -149,6 +149,7 @@ ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64
     d.work_count = p.history_count ? p.history_count : p.n_histories - p.history_offset;
     d.tally_offset = tally_offset;
     d.mu = p.mu140; d.act = p.activity; d.angles = p.angle_rad;
+    d.act_prev = p.activity_prev;
     d.q32 = (uint32_t*)(ws + L.q[i]);
     d.q8 = (uint8_t*)(ws + L.q8[i]);
     d.palette = (uint32_t*)(ws + L.pal[i]);
@@ -322,6 +323,7 @@ int mc_adjoint_mu(const mc_problem* problem, const mc_options* opt, const double
     if (events && !n_events) return MC_EINVAL;
     if (frac_bits < 0 || frac_bits > 62) return MC_EINVAL;
     if (opt && opt->forced_detection) return MC_EINVAL;   // adjoint of analog tallies only
+    if (problem->activity_prev) return MC_EINVAL;         // and of plain sources
     if (!check_problem(*problem)) return MC_EINVAL;
     int block, hpl, bpc, brick, qbytes;
     resolve(opt, block, hpl, bpc, brick, qbytes);
@@ -363,6 +365,7 @@ int mc_system_matrix(const mc_problem* problem, const mc_event* events, const ui
         !Tt_col || !Tt_val || !workspace)
         return MC_EINVAL;
     if (!check_problem(*problem) || problem->image_factor < 1) return MC_EINVAL;
+    if (problem->activity_prev) return MC_EINVAL;   // normalised by a plain source's activity
     if (event_capacity < 1 || event_capacity >= (1ull << 31)) return MC_EINVAL;
     if (class_mask < 1 || class_mask > 3) return MC_EINVAL;
     const mc_problem& p = *problem;

@@ -63,7 +63,25 @@ struct ProbDesc {
     uint32_t* cfd_h;                // [cfd_L] response half-width per layer
     int32_t cfd_L, cfd_hmax;        // depth layers (one pixel thick); largest half-width
     double alpha, cfd_pix, cfd_tan; // collimator half-angle (rad), pixel (cm), tan(alpha)
+    const uint32_t* act_prev;       // nullable: the source is act - act_prev (signed)
 };
+
+// Emission weight of voxel i: the activity, or for a difference source the
+// magnitude of act - act_prev.
+__device__ inline uint32_t source_weight(const uint32_t* __restrict__ act,
+                                         const uint32_t* __restrict__ prev, uint64_t i) {
+    const uint32_t a = act[i];
+    if (!prev) return a;
+    const uint32_t b = prev[i];
+    return a >= b ? a - b : b - a;
+}
+
+// Fixed-point weight of one contribution from a history emitted in voxel v:
+// negative where a difference source is negative.
+__device__ inline long long signed_weight(const ProbDesc* __restrict__ d, uint32_t v, long long w) {
+    const uint32_t* prev = d->act_prev;
+    return (prev && d->act[v] < prev[v]) ? -w : w;
+}
 
 // Convolution-based forced detection geometry (host and device agree):
 // L = ceil(2 D / pixel) layers of one pixel's depth; layer l's response is

@@ -53,6 +53,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* pd) {
     const uint64_t nvox = pd->nvox;
     const float* __restrict__ mu = pd->mu;
     const uint32_t* __restrict__ act = pd->act;
+    const uint32_t* __restrict__ prev = pd->act_prev;
     const uint32_t nx = (uint32_t)pd->nx, ny = (uint32_t)pd->ny;
     uint32_t mx = 0, flags = 0;
     uint64_t sum = 0;
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* pd) {
                 lo[1] = min(lo[1], iy); hi[1] = max(hi[1], iy);
                 lo[2] = min(lo[2], iz); hi[2] = max(hi[2], iz);
             }
-            sum += act[i];
+            sum += source_weight(act, prev, i);
         }
     }
     (void)nvox;
@@ -207,13 +208,14 @@ __global__ __launch_bounds__(RED_THREADS) void k_codes(ProbDesc* pd) {
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(ProbDesc* pd) {
     const uint64_t nvox = pd->nvox;
     const uint32_t* __restrict__ act = pd->act;
+    const uint32_t* __restrict__ prev = pd->act_prev;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_ITEMS;
     uint64_t s = 0;
     uint32_t c = 0;
     for (int j = threadIdx.x; j < SCAN_ITEMS; j += SCAN_THREADS) {
         const uint64_t i = base + j;
         if (i < nvox) {
-            const uint32_t a = act[i];
+            const uint32_t a = source_weight(act, prev, i);
             s += a;
             c += a > 0;
         }
@@ -278,6 +280,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ProbDesc* pd) {
     constexpr int PER = SCAN_ITEMS / SCAN_THREADS;
     const uint64_t nvox = pd->nvox;
     const uint32_t* __restrict__ act = pd->act;
+    const uint32_t* __restrict__ prev = pd->act_prev;
     uint64_t* __restrict__ cdf = pd->cdf;
     uint32_t* __restrict__ vid = pd->vox_id;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_ITEMS + (uint64_t)threadIdx.x * PER;
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ProbDesc* pd) {
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const uint64_t i = base + j;
-        a[j] = (i < nvox) ? act[i] : 0u;
+        a[j] = (i < nvox) ? source_weight(act, prev, i) : 0u;
         s += a[j];
         c += a[j] > 0;
     }

@@ -111,13 +111,14 @@ __device__ inline void fd_commit(const Cst& C, int p, const FdPoint& q, int lane
         float sc = 0.0f;
         if (cfd_eval(C, T.descs + p, q, lb, sc))
             atomicAdd((unsigned long long*)(T.descs[p].layers + lb),
-                      (unsigned long long)(long long)__float2ll_rn(sc * 4294967296.0f));
+                      (unsigned long long)signed_weight(T.descs + p, q.voxel,
+                                                        __float2ll_rn(sc * 4294967296.0f)));
         return;
     }
     uint32_t bin = 0;
     float sc = 0.0f;
     const bool ok = fd_eval(C, T.descs + p, q, bin, sc);
-    const long long w = (long long)__float2ll_rn(sc * 4294967296.0f);
+    const long long w = signed_weight(T.descs + p, q.voxel, __float2ll_rn(sc * 4294967296.0f));
     if (ok) {
         const size_t b = C.tally_offset + bin;
         atomicAdd((unsigned long long*)(T.tally + b), (unsigned long long)w);
@@ -358,7 +359,8 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                 const uint32_t bin = (uint32_t)((((uint32_t)L.view * 2u + cls) * (uint32_t)C.nv + iv) *
                                                 (uint32_t)C.nu + iu);
                 const size_t gb = C.tally_offset + bin;
-                atomicAdd((unsigned long long*)(T.tally + gb), 1ull << 32);
+                const long long w = signed_weight(T.descs + p, L.emit_voxel, 1ll << 32);
+                atomicAdd((unsigned long long*)(T.tally + gb), (unsigned long long)w);
                 if (T.tally_sq) atomicAdd((unsigned long long*)(T.tally_sq + gb), 1ull << 32);
                 if (T.n_events) {
                     const unsigned long long idx = atomicAdd(T.n_events, 1ull);
@@ -367,7 +369,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                         ev.work = T.work_prefix[p] + (work_of(C, L.view, L.hist) - C.work_begin);
                         ev.bin = bin;
                         ev.emit_voxel = L.emit_voxel;
-                        ev.weight = 1ll << 32;
+                        ev.weight = w;
                         T.events[idx] = ev;
                     }
                 }

@@ -160,6 +160,15 @@ def test_simulate_rejects_bad_buffers_before_launch():
     o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=0, forced_detection=1)
     assert mc._lib.mc_adjoint_mu(C.byref(p), C.byref(o), 8, None, None, 0, 8, 40, 8, 8, need,
                                  None) == mc.MC_EINVAL
+    # difference sources (reuse of photon tracks) are forward-only
+    q = _good()
+    q.activity_prev = 16
+    assert lib.mc_workspace_bytes(C.byref(q), 1, None) == need
+    assert mc._lib.mc_adjoint_mu(C.byref(q), None, 8, None, None, 0, 8, 40, 8, 8, need,
+                                 None) == mc.MC_EINVAL
+    q.image_factor = 2
+    assert mc._lib.mc_system_matrix(C.byref(q), 8, 8, 16, 3, 8, 8, 8, 8, 8, 8, None, 8,
+                                    1 << 30, None) == mc.MC_EINVAL
     assert sim(None, 1, None, 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
     assert mc._lib.mc_error_string(mc.MC_EINVAL) == b"invalid argument"
     assert mc._lib.mc_replay_histories(C.byref(p), None, None, None, 5, None, 8, 8, need, None) == mc.MC_EINVAL

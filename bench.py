@@ -257,6 +257,7 @@ def extra_forms(mc, torch, args):
                       "step": "forward with event list + Poisson-loss gradient + replaying adjoint"}
     del s4, d4, ref
     out["forced_detection"] = fd_form(mc, torch, steps)
+    out["reuse_of_photon_tracks"] = rpt_form(mc, torch, steps)
     if not args.no_large:
         out["large_mlem"] = large_form(mc, torch, steps)
     return out
@@ -320,6 +321,38 @@ def fd_form(mc, torch, steps):
                "analog_nonzero_bins": nz_an, "seeds": 16,
                "convolution_fd": out["convolution_fd"]})
     return fd
+
+
+def rpt_form(mc, torch, steps):
+    """Reuse of photon tracks (Sec. 5.3) on the 128^3 thorax, 60 views: the
+    reprojection of a new estimate (each voxel of the previous one changed by
+    U(-5 %, +5 %)) at 1e8 histories per previous-estimate activity, as a full
+    simulation and as the previous projection plus the simulated difference
+    (histories in proportion to sum |d|, the same histories per unit of
+    activity)."""
+    import phantoms
+    p = phantoms.thorax_128(10 ** 8)
+    new, prev = phantoms.estimate_pair(p.activity, 0.05, 41)
+    V = p.n_views
+    hpu = 1e8 / float(prev.sum(dtype=np.int64))
+    a_new = float(new.sum(dtype=np.int64))
+    a_diff = float(np.abs(new.astype(np.int64) - prev.astype(np.int64)).sum())
+    n_full = int(round(hpu * a_new / V)) * V
+    n_diff = max(1, int(round(hpu * a_diff / V))) * V
+    full = mc.Simulator(mc.to_device(p.with_(activity=new, n_histories=n_full)), want_sq=False)
+    diff = mc.Simulator(mc.to_device(p.with_(activity=new, activity_prev=prev, n_histories=n_diff)),
+                        want_sq=False)
+    full.run()
+    diff.run()
+    ms_full = timed(torch, full.run, steps)
+    ms_diff = timed(torch, diff.run, steps)
+    full.check_status()
+    diff.check_status()
+    neg = int((diff.tally < 0).sum().item())
+    return {"full_ms": ms_full, "difference_ms": ms_diff, "histories_full": n_full,
+            "histories_difference": n_diff, "difference_fraction": a_diff / a_new,
+            "speedup": ms_full / ms_diff, "negative_bins": neg,
+            "step": "staging + transport of the new estimate vs of the difference source"}
 
 
 def large_fd(mc, torch, steps, p5):

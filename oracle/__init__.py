@@ -15,6 +15,7 @@ and it shares no code with the GPU library.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from typing import Optional
@@ -478,3 +479,64 @@ def poisson_loglik(T, P: np.ndarray, S: np.ndarray) -> float:
     y = T @ S
     m = y > 0
     return float(np.sum(P[m] * np.log(y[m]) - y[m]))
+
+
+# ---------------------------------------------------------------------------
+# Coarse-grid scatter modelling (Sec. 5.4): the scatter projection is
+# simulated with larger source voxels and larger detector pixels, then
+# expanded and interpolated back to the normal pixel size.
+# ---------------------------------------------------------------------------
+
+def block_activity(act: np.ndarray, f: int) -> np.ndarray:
+    """Source with f^3-voxel source voxels: every voxel takes the summed
+    activity of its f x f x f block (so an emission is uniform over the
+    block).  act [nz, ny, nx] with every axis a multiple of f; returns uint64."""
+    nz, ny, nx = act.shape
+    if nz % f or ny % f or nx % f:
+        raise ValueError("grid not divisible by the coarsening factor")
+    out = np.zeros(act.shape, dtype=np.uint64)
+    a = act.astype(np.uint64)
+    for bz in range(nz // f):
+        for by in range(ny // f):
+            zs, ys = slice(bz * f, (bz + 1) * f), slice(by * f, (by + 1) * f)
+            for bx in range(nx // f):
+                xs = slice(bx * f, (bx + 1) * f)
+                out[zs, ys, xs] = a[zs, ys, xs].sum()
+    return out
+
+
+def expand_projection(coarse: np.ndarray, f: int) -> np.ndarray:
+    """Coarse projection [..., nv_c, nu_c] -> [..., nv_c f, nu_c f]: each
+    normal pixel takes the bilinear interpolation, at its centre, of the
+    coarse values read as samples at the coarse pixel centres (held constant
+    beyond the outermost centres), divided by f^2 (counts per normal pixel)."""
+    c = np.asarray(coarse, dtype=np.float64)
+    nvc, nuc = c.shape[-2:]
+    out = np.zeros(c.shape[:-2] + (nvc * f, nuc * f))
+
+    def weights(i, n_c):
+        x = min(max((i + 0.5) / f - 0.5, 0.0), n_c - 1.0)
+        i0 = int(math.floor(x))
+        i1 = min(i0 + 1, n_c - 1)
+        return i0, i1, x - i0
+
+    for j in range(nvc * f):
+        j0, j1, ty = weights(j, nvc)
+        for i in range(nuc * f):
+            i0, i1, tx = weights(i, nuc)
+            out[..., j, i] = ((1 - ty) * ((1 - tx) * c[..., j0, i0] + tx * c[..., j0, i1])
+                              + ty * ((1 - tx) * c[..., j1, i0] + tx * c[..., j1, i1])) / (f * f)
+    return out
+
+
+def coarse_problem(prob, f: int):
+    """The problem CGSM simulates: block-summed source (block_activity, which
+    must fit uint32), detector pixels f times larger (nu, nv multiples of f);
+    attenuation, geometry and history budget unchanged."""
+    act = block_activity(prob.activity, f)
+    if act.max() > np.iinfo(np.uint32).max:
+        raise ValueError("block activity exceeds 32 bits")
+    if prob.nu % f or prob.nv % f:
+        raise ValueError("detector not divisible by the coarsening factor")
+    return prob.with_(activity=act.astype(np.uint32), nu=prob.nu // f, nv=prob.nv // f,
+                      pixel_cm=prob.pixel_cm * f)

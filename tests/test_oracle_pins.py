@@ -853,3 +853,69 @@ def test_rpt_projection_identity():
     # the difference's projection is the ~10 % change, well resolved
     assert pd.sum() == pytest.approx(pn.sum() - pp.sum(), rel=0.2)
     assert pd.sum() > 10 * math.sqrt(vd.sum())
+
+
+# --- coarse-grid scatter modelling (Sec. 5.4) --------------------------------
+
+def test_cgsm_block_activity():
+    """Block-summed source: equal to the reshape-and-sum of each block,
+    repeated over the block; total f^3 times the original; f = 1 changes
+    nothing; indivisible grids are refused."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    act = rng.integers(0, 1000, size=(6, 4, 8)).astype(np.uint32)
+    for f in (1, 2):
+        b = oracle.block_activity(act, f)
+        s = act.astype(np.uint64).reshape(6 // f, f, 4 // f, f, 8 // f, f).sum(axis=(1, 3, 5))
+        np.testing.assert_array_equal(b[::f, ::f, ::f], s)
+        np.testing.assert_array_equal(b, np.kron(s, np.ones((f, f, f), dtype=np.uint64)))
+        assert int(b.sum()) == f ** 3 * int(act.sum(dtype=np.uint64))
+    np.testing.assert_array_equal(oracle.block_activity(act, 1), act)
+    with pytest.raises(ValueError):
+        oracle.block_activity(act, 3)
+
+
+def test_cgsm_expand_projection():
+    """The expansion is scipy's linear interpolation on the coarse pixel
+    centres (coordinates clamped to the outermost centres) divided by f^2;
+    a constant stays constant (/f^2); a ramp along u is reproduced exactly
+    between the outermost centres; f = 1 is the identity."""
+    from scipy.interpolate import RegularGridInterpolator
+    rng = np.random.Generator(np.random.PCG64(5))
+    c = rng.uniform(0.0, 10.0, size=(3, 2, 5, 7))
+    for f in (1, 2, 3):
+        e = oracle.expand_projection(c, f)
+        assert e.shape == (3, 2, 5 * f, 7 * f)
+        yc, xc = np.arange(5.0), np.arange(7.0)
+        yf = np.clip((np.arange(5 * f) + 0.5) / f - 0.5, 0, 4)
+        xf = np.clip((np.arange(7 * f) + 0.5) / f - 0.5, 0, 6)
+        Y, X = np.meshgrid(yf, xf, indexing="ij")
+        for v in range(3):
+            for k in range(2):
+                ref = RegularGridInterpolator((yc, xc), c[v, k])(np.stack([Y, X], -1)) / f ** 2
+                np.testing.assert_allclose(e[v, k], ref, rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(oracle.expand_projection(c, 1), c)
+    const = np.full((1, 1, 4, 4), 8.0)
+    np.testing.assert_allclose(oracle.expand_projection(const, 2), 2.0, rtol=0, atol=1e-15)
+    ramp = np.tile(np.arange(6.0), (1, 1, 3, 1))
+    e = oracle.expand_projection(ramp, 2)
+    u = (np.arange(12) + 0.5) / 2 - 0.5
+    inner = (u >= 0) & (u <= 5)
+    np.testing.assert_allclose(e[0, 0, :, inner].T, np.tile(u[inner] / 4, (6, 1)), rtol=1e-14)
+
+
+def test_cgsm_scatter_estimate():
+    """Coarse-grid scatter: with f = 1 the coarse problem is the problem
+    (identical tallies); with f = 2 the expanded forced-detection scatter
+    projection from 1e6 histories lies closer (relative L2) to an 8e6-history
+    fine reference than the fine estimate from the same 1e6 histories, with
+    its total within 2 % (the smoothing the method relies on)."""
+    p = phantoms.thorax_problem("cgsm", 32, 1.2, 2, 12, 180.0, 32, 1.2, 1_000_000, seed=9)
+    a = oracle.simulate_fd(p.with_(n_histories=60_000))
+    b = oracle.simulate_fd(oracle.coarse_problem(p.with_(n_histories=60_000), 1))
+    np.testing.assert_array_equal(a["tally"], b["tally"])
+    ref = oracle.simulate_fd(p.with_(n_histories=8_000_000, seed=5))["tally"][:, 1] / 8e6
+    fine = oracle.simulate_fd(p)["tally"][:, 1] / 1e6
+    cg = oracle.expand_projection(oracle.simulate_fd(oracle.coarse_problem(p, 2))["tally"], 2)[:, 1] / 1e6
+    rl2 = lambda x: np.linalg.norm(x - ref) / np.linalg.norm(ref)
+    assert rl2(cg) < 0.7 * rl2(fine), (rl2(cg), rl2(fine))
+    assert cg.sum() == pytest.approx(ref.sum(), rel=0.02)

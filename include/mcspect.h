@@ -71,7 +71,8 @@ enum {
     MC_STATUS_CAPPED = 16,       /* a history hit max_steps (fate CAPPED)     */
     MC_STATUS_GRAD_OVERFLOW = 32,/* a gradient term exceeded the fixed-point  */
                                  /* range at this frac_bits (term dropped)    */
-    MC_STATUS_BAD_EVENT = 64     /* an event did not replay to its bin        */
+    MC_STATUS_BAD_EVENT = 64,    /* an event did not replay to its bin        */
+    MC_STATUS_ACTIVITY_OVERFLOW = 128 /* a block activity sum exceeds 32 bits */
 };
 
 /* Fate counters, in this order: */
@@ -317,6 +318,32 @@ int osem_iterate(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n
                  const int64_t* Bt_rowptr, const int32_t* Bt_col, const float* Bt_val,
                  const float* proj, const float* scatter, float* image, int32_t n_iter,
                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* Coarse-grid scatter modelling (Sec. 5.4), step 1: the source with larger
+ * source voxels.  Every voxel of out takes the summed activity of the
+ * f x f x f block holding it, so that the simulator's emission (voxel by
+ * activity, uniform inside the voxel) is uniform over the block.
+ *   act, out  device uint32 [nz][ny][nx] (distinct buffers)
+ *   status    device int64 [1]: MC_STATUS_ACTIVITY_OVERFLOW is or-ed in if a
+ *             block sum exceeds 2^32 - 1 (that block is written saturated)
+ * nx, ny, nz must be multiples of f >= 1 (MC_EINVAL otherwise).  The coarse
+ * problem is the same problem with activity = out, nu / f by nv / f
+ * detector bins of f times the pixel size. */
+int mc_block_activity(const uint32_t* act, int32_t nx, int32_t ny, int32_t nz, int32_t factor,
+                      uint32_t* out, int64_t* status, void* stream);
+
+/* Coarse-grid scatter modelling (Sec. 5.4), step 2: a projection simulated
+ * on the coarse detector, expanded and interpolated to the normal pixels:
+ * out pixel (j, i) of every plane = the bilinear interpolation at
+ * ((i + 1/2) / f - 1/2, (j + 1/2) / f - 1/2) in coarse pixel units (each
+ * coordinate clamped to [0, n_c - 1]) of the coarse values read as samples
+ * at the coarse pixel centres, divided by f^2 (counts per normal pixel).
+ *   coarse  device int64 [n_planes][nv_c][nu_c], Q31.32 (a tally: planes =
+ *           views x classes)
+ *   out     device double [n_planes][nv_c f][nu_c f], counts
+ * MC_EINVAL for sizes < 1. */
+int mc_expand_projection(const int64_t* coarse, int64_t n_planes, int32_t nu_c, int32_t nv_c,
+                         int32_t factor, double* out, void* stream);
 
 /* Human-readable text for an MC_* code (static storage). */
 const char* mc_error_string(int code);

@@ -29,7 +29,7 @@ _lib = C.CDLL(LIB_PATH)
 
 MC_OK, MC_EINVAL, MC_ENOMEM, MC_EDEVICE, MC_EOVERFLOW, MC_ECAPPED = 0, -1, -2, -3, -4, -5
 STATUS_BAD_MU, STATUS_NO_ACTIVITY, STATUS_BAD_ANGLE, STATUS_LIST_OVERFLOW, STATUS_CAPPED = 1, 2, 4, 8, 16
-STATUS_GRAD_OVERFLOW, STATUS_BAD_EVENT = 32, 64
+STATUS_GRAD_OVERFLOW, STATUS_BAD_EVENT, STATUS_ACTIVITY_OVERFLOW = 32, 64, 128
 FATES = ["ABSORBED", "CUT", "ESCAPED", "ESCAPED_FOV", "OUT_OF_WINDOW", "TALLIED", "CAPPED", "SPARE"]
 Q32 = float(2 ** 32)   # tally fixed point: Q31.32
 Q23 = float(2 ** 23)   # energy fixed point: Q40.23 keV
@@ -39,6 +39,7 @@ Q52 = float(2 ** 52)   # forced-detection sum of squared scores: Q11.52
 EXPORTS = ["mc_workspace_bytes", "mc_simulate_projections", "mc_replay_histories",
            "mc_adjoint_mu", "mc_system_matrix_workspace_bytes", "mc_system_matrix",
            "mlem_workspace_bytes", "mlem_iterate", "osem_workspace_bytes", "osem_iterate",
+           "mc_block_activity", "mc_expand_projection",
            "mc_error_string", "mc_last_hip_error"]
 
 
@@ -99,6 +100,10 @@ _lib.mlem_workspace_bytes.argtypes = [_i64, _i64]
 _lib.mlem_workspace_bytes.restype = _sz
 _lib.mlem_iterate.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, _sz, _vp]
 _lib.mlem_iterate.restype = C.c_int
+_lib.mc_block_activity.argtypes = [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]
+_lib.mc_block_activity.restype = C.c_int
+_lib.mc_expand_projection.argtypes = [_vp, _i64, _i32, _i32, _i32, _vp, _vp]
+_lib.mc_expand_projection.restype = C.c_int
 _lib.mc_error_string.argtypes = [C.c_int]
 _lib.mc_error_string.restype = C.c_char_p
 _lib.mc_last_hip_error.argtypes = []
@@ -423,6 +428,40 @@ class RptProjector:
             self.projection = self.projection + self._run(activity, self.prev)
         self.prev = activity.clone()
         return self.projection
+
+
+def coarse_problem(problem: DeviceProblem, factor: int) -> DeviceProblem:
+    """Coarse-grid scatter modelling (Sec. 5.4): the same problem with the
+    block-summed source (mc_block_activity) and a detector of factor times
+    larger pixels (nu, nv multiples of factor).  Raises if a block sum
+    overflows 32 bits."""
+    torch = _torch()
+    f = int(factor)
+    if problem.activity_prev is not None:
+        raise McError("coarse_problem takes a plain source")
+    if problem.nu % f or problem.nv % f:
+        raise McError("detector size not a multiple of the coarsening factor")
+    out = torch.empty_like(problem.activity)
+    status = torch.zeros(1, dtype=torch.int64, device=out.device)
+    _check(_lib.mc_block_activity(problem.activity.data_ptr(), problem.nx, problem.ny, problem.nz, f,
+                                  out.data_ptr(), status.data_ptr(), _stream_ptr()), "mc_block_activity")
+    if int(status.item()) & STATUS_ACTIVITY_OVERFLOW:
+        raise McError("block activity exceeds 32 bits")
+    return problem.with_(activity=out, nu=problem.nu // f, nv=problem.nv // f,
+                         pixel_cm=problem.pixel_cm * f)
+
+
+def expand_projection(tally, shape, factor: int):
+    """A coarse Q31.32 tally [V, 2, nv_c, nu_c] expanded to counts per normal
+    pixel, float64 [V, 2, nv_c f, nu_c f] (mc_expand_projection)."""
+    torch = _torch()
+    V, K, nv_c, nu_c = shape
+    f = int(factor)
+    src = tally.contiguous()
+    out = torch.empty((V, K, nv_c * f, nu_c * f), dtype=torch.float64, device=tally.device)
+    _check(_lib.mc_expand_projection(src.data_ptr(), V * K, nu_c, nv_c, f,
+                                     out.data_ptr(), _stream_ptr()), "mc_expand_projection")
+    return out
 
 
 def fd_tally_sq_float(t) -> np.ndarray:

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmcspect.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "staging.hip", "transport.hip", "adjoint.hip", "sysmat.hip", "cfd.hip"]
+SOURCES = ["api.hip", "staging.hip", "transport.hip", "adjoint.hip", "sysmat.hip", "cfd.hip", "cgsm.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

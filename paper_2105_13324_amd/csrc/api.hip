@@ -427,6 +427,25 @@ int osem_iterate(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n
     return MC_OK;
 }
 
+int mc_block_activity(const uint32_t* act, int32_t nx, int32_t ny, int32_t nz, int32_t factor,
+                      uint32_t* out, int64_t* status, void* stream) {
+    if (!act || !out || !status || act == out) return MC_EINVAL;
+    if (nx < 1 || ny < 1 || nz < 1 || factor < 1) return MC_EINVAL;
+    if (nx % factor || ny % factor || nz % factor) return MC_EINVAL;
+    if ((uint64_t)nx * ny * nz >= (1ull << 40)) return MC_EINVAL;
+    const hipError_t e = launch_block_activity(act, nx, ny, nz, factor, out, status, (hipStream_t)stream);
+    return e == hipSuccess ? MC_OK : hip_fail(e);
+}
+
+int mc_expand_projection(const int64_t* coarse, int64_t n_planes, int32_t nu_c, int32_t nv_c,
+                         int32_t factor, double* out, void* stream) {
+    if (!coarse || !out || n_planes < 1 || nu_c < 1 || nv_c < 1 || factor < 1) return MC_EINVAL;
+    if ((uint64_t)nu_c * factor >= (1ull << 20) || (uint64_t)nv_c * factor >= (1ull << 20)) return MC_EINVAL;
+    if ((uint64_t)n_planes * nu_c * factor * nv_c * factor >= (1ull << 40)) return MC_EINVAL;
+    const hipError_t e = launch_expand(coarse, (uint64_t)n_planes, nu_c, nv_c, factor, out, (hipStream_t)stream);
+    return e == hipSuccess ? MC_OK : hip_fail(e);
+}
+
 const char* mc_error_string(int code) {
     switch (code) {
         case MC_OK: return "ok";

@@ -130,6 +130,13 @@ struct CallState {
     unsigned long long pad[7];
 };
 
+// Host launchers (cgsm.hip): block-summed source; coarse projection expanded
+// to the normal pixels.
+hipError_t launch_block_activity(const uint32_t* act, int nx, int ny, int nz, int f, uint32_t* out,
+                                 int64_t* status, hipStream_t s);
+hipError_t launch_expand(const int64_t* coarse, uint64_t n_planes, int nu_c, int nv_c, int f, double* out,
+                         hipStream_t s);
+
 // Host launchers (cfd.hip): zero the layers and build the responses (per call,
 // before transport); convolve the layers into the tally (after transport).
 // The host sizes the response table with cfd_hmax; each layer's half-width is

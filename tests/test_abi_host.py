@@ -169,6 +169,15 @@ def test_simulate_rejects_bad_buffers_before_launch():
     q.image_factor = 2
     assert mc._lib.mc_system_matrix(C.byref(q), 8, 8, 16, 3, 8, 8, 8, 8, 8, 8, None, 8,
                                     1 << 30, None) == mc.MC_EINVAL
+    # coarse-grid scatter helpers: sizes are checked before any launch
+    ba, ex = mc._lib.mc_block_activity, mc._lib.mc_expand_projection
+    assert ba(8, 8, 8, 8, 3, 16, 8, None) == mc.MC_EINVAL       # 8 not a multiple of 3
+    assert ba(8, 8, 8, 8, 2, 8, 8, None) == mc.MC_EINVAL        # in place
+    assert ba(8, 8, 8, 8, 0, 16, 8, None) == mc.MC_EINVAL
+    assert ba(None, 8, 8, 8, 2, 16, 8, None) == mc.MC_EINVAL
+    assert ex(8, 0, 4, 4, 2, 16, None) == mc.MC_EINVAL
+    assert ex(8, 2, 4, 4, 0, 16, None) == mc.MC_EINVAL
+    assert ex(None, 2, 4, 4, 2, 16, None) == mc.MC_EINVAL
     assert sim(None, 1, None, 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
     assert mc._lib.mc_error_string(mc.MC_EINVAL) == b"invalid argument"
     assert mc._lib.mc_replay_histories(C.byref(p), None, None, None, 5, None, 8, 8, need, None) == mc.MC_EINVAL

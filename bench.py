@@ -258,6 +258,7 @@ def extra_forms(mc, torch, args):
     del s4, d4, ref
     out["forced_detection"] = fd_form(mc, torch, steps)
     out["reuse_of_photon_tracks"] = rpt_form(mc, torch, steps)
+    out["coarse_grid_scatter"] = cgsm_form(mc, torch, steps)
     if not args.no_large:
         out["large_mlem"] = large_form(mc, torch, steps)
     return out
@@ -353,6 +354,45 @@ def rpt_form(mc, torch, steps):
             "histories_difference": n_diff, "difference_fraction": a_diff / a_new,
             "speedup": ms_full / ms_diff, "negative_bins": neg,
             "step": "staging + transport of the new estimate vs of the difference source"}
+
+
+def cgsm_form(mc, torch, steps):
+    """Coarse-grid scatter modelling (Sec. 5.4) on the 128^3 thorax, 60
+    views: the forced-detection scatter projection from 1e7 histories on the
+    normal problem and on the coarse one (source blocks of 2^3 voxels, 2 x 2
+    pixels, expanded back), timed, and each compared (relative L2) with a
+    1e8-history normal-grid reference; the history gain is the squared ratio
+    of the two errors."""
+    import phantoms
+    n = 10 ** 7
+    p = phantoms.thorax_128(n)
+    dp = mc.to_device(p)
+    fd = {"forced_detection": 1}
+    ref = mc.simulate(dp.with_(n_histories=10 ** 8, seed=77), want_sq=False, options=fd)
+    r = ref.tally.view(p.tally_shape)[:, 1].to(torch.float64) * (2.0 ** -32 / 10 ** 8)
+    del ref
+    fine = mc.Simulator(dp, want_sq=False, options=fd)
+    cp = mc.coarse_problem(dp, 2)
+    coarse = mc.Simulator(cp, want_sq=False, options=fd)
+
+    def cgsm_step():
+        coarse.run()
+        return mc.expand_projection(coarse.tally, cp.tally_shape, 2)
+    fine.run()
+    e = cgsm_step()
+    ms_fine = timed(torch, fine.run, steps)
+    ms_cgsm = timed(torch, cgsm_step, steps)
+    ms_coarsen = timed(torch, lambda: mc.coarse_problem(dp, 2), steps)
+    f = fine.tally.view(p.tally_shape)[:, 1].to(torch.float64) * (2.0 ** -32 / n)
+    c = e[:, 1] / n
+    err_f = float(torch.linalg.norm(f - r) / torch.linalg.norm(r))
+    err_c = float(torch.linalg.norm(c - r) / torch.linalg.norm(r))
+    return {"fine_ms": ms_fine, "cgsm_ms": ms_cgsm, "coarsen_ms": ms_coarsen, "histories": n,
+            "scatter_rel_l2": {"fine": err_f, "cgsm": err_c},
+            "scatter_total_rel": float(c.sum() / r.sum() - 1.0),
+            "history_gain": (err_f / err_c) ** 2,
+            "step": "forced-detection transport of the coarse problem + expansion (coarsening "
+                    "timed apart: once per source estimate)"}
 
 
 def large_fd(mc, torch, steps, p5):

@@ -464,6 +464,47 @@ def expand_projection(tally, shape, factor: int):
     return out
 
 
+class ScatterModel:
+    """Monte Carlo scatter projection for OS-EM with an additive scatter term
+    (Sec. 5.4), with the two accelerations the paper reviews: coarse-grid
+    scatter modelling (the scatter is simulated on coarse_problem(problem,
+    factor) and expanded) and intermittent scatter modelling (only the first
+    n_updates calls simulate; later calls return the last estimate).
+
+    estimate(activity): the class-1 (scattered) projection [V, nv, nu],
+    float64, in activity units (tally x A V / N for a source of total
+    activity A from N histories over V views).  activity: device uint32 map
+    (stored as int32, as to_device makes it) on the problem's grid."""
+
+    def __init__(self, problem: DeviceProblem, histories: int, factor: int = 2, n_updates: int = 2,
+                 forced_detection: int = 1):
+        self.problem = problem
+        V = problem.n_views
+        self.histories = max(1, int(histories) // V) * V
+        self.factor = int(factor)
+        self.n_updates = int(n_updates)
+        self.options = {"forced_detection": int(forced_detection)} if forced_detection else None
+        self.calls = 0
+        self.simulations = 0
+        self.last = None
+
+    def estimate(self, activity):
+        torch = _torch()
+        self.calls += 1
+        if self.last is not None and self.simulations >= self.n_updates:
+            return self.last
+        dp = self.problem.with_(activity=activity.contiguous(), n_histories=self.histories,
+                                history_offset=0, history_count=0,
+                                seed=int(self.problem.seed) + self.simulations)
+        cp = coarse_problem(dp, self.factor)
+        sim = simulate(cp, want_sq=False, options=self.options)
+        total = float((activity.to(torch.int64) & 0xFFFFFFFF).sum().item())
+        e = expand_projection(sim.tally, cp.tally_shape, self.factor)[:, 1]
+        self.last = e * (total * self.problem.n_views / self.histories)
+        self.simulations += 1
+        return self.last
+
+
 def fd_tally_sq_float(t) -> np.ndarray:
     """Forced-detection sum of squared scores (Q11.52) -> float64."""
     return t.cpu().numpy().astype(np.float64) / Q52

@@ -53,6 +53,7 @@ class _Problem(C.Structure):
         ("seed", C.c_uint32), ("problem_id", C.c_uint32), ("max_steps", C.c_uint32),
         ("n_threads", C.c_uint32),
         ("activity_prev", C.POINTER(C.c_uint32)),
+        ("e0_kev", C.c_double),
     ]
 
 
@@ -72,8 +73,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build()
+        build(force=False)          # (re)builds a missing or stale library
         lib = C.CDLL(_LIB_PATH)
         P = C.POINTER
         lib.orc_philox.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
@@ -134,7 +134,8 @@ def _make_problem(prob, n_threads: int = 0):
                  pe_fraction=prob.pe_fraction, n_histories=prob.n_histories,
                  history_offset=prob.history_offset, history_count=prob.history_count,
                  seed=prob.seed, problem_id=prob.problem_id, max_steps=prob.max_steps,
-                 n_threads=n_threads, activity_prev=_ptr(prev, C.c_uint32))
+                 n_threads=n_threads, activity_prev=_ptr(prev, C.c_uint32),
+                 e0_kev=float(getattr(prob, "e0_kev", 140.0)))
     return p, (mu, act, ang, prev)
 
 

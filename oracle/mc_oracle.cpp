@@ -86,7 +86,7 @@ double uniform(uint32_t r) { return ((double)(r >> 9) + 0.5) * (1.0 / 8388608.0)
 // ---------------------------------------------------------------------------
 // Physics (double precision).
 // ---------------------------------------------------------------------------
-const double E0_KEV = 140.0;
+const double E0_KEV = 140.0;        // energy the attenuation map is given at (and Tc-99m line)
 const double MEC2_KEV = 510.99895;  // electron rest energy (CODATA 2018)
 const double PI = 3.14159265358979323846;
 
@@ -131,6 +131,7 @@ typedef struct {
     uint64_t n_histories, history_offset, history_count;
     uint32_t seed, problem_id, max_steps, n_threads;
     const uint32_t* activity_prev;   // nullable: the source is activity - activity_prev
+    double e0_kev;                   // emission line energy (0: 140 keV)
 } orc_problem;
 
 typedef struct {
@@ -185,8 +186,15 @@ double source_sign(const orc_problem* p, int32_t vox) {
     return (p->activity_prev && p->activity[vox] < p->activity_prev[vox]) ? -1.0 : 1.0;
 }
 
+// Emission line (Sec. 3: Tc-99m emits at 140 keV, Tl-201 at 71 and 167 keV;
+// a multi-line source is one problem per line).  The attenuation map stays
+// given at 140 keV and g(E) scales it to any energy.
+double emission_energy(const orc_problem* p) { return p->e0_kev > 0.0 ? p->e0_kev : E0_KEV; }
+
 bool build_setup(const orc_problem* p, Setup& s) {
     s.p = p;
+    const double e0 = emission_energy(p);
+    if (!(e0 >= p->e_cut_kev && e0 <= 500.0)) return false;
     const size_t nvox = (size_t)p->nx * p->ny * p->nz;
     s.L[0] = p->nx * p->voxel_cm; s.L[1] = p->ny * p->voxel_cm; s.L[2] = p->nz * p->voxel_cm;
     for (int a = 0; a < 3; ++a) s.H[a] = 0.5 * s.L[a];
@@ -512,7 +520,7 @@ void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, Hi
     const double phi = 2.0 * PI * uniform(w1.r[2]);
     const double sin_t = std::sqrt(std::max(0.0, 1.0 - cos_t * cos_t));
     double d[3] = {sin_t * std::cos(phi), sin_t * std::sin(phi), cos_t};
-    double e = E0_KEV;
+    double e = emission_energy(p);
     double mu_max = s.mu_hat * s.xs.g(e);
     double p_pe = s.xs.p_pe(e);
     if (keep_path) h.verts.push_back(Vertex{{x[0], x[1], x[2]}, e});

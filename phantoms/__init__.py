@@ -65,6 +65,7 @@ class Problem:
     # optional previous activity [nz, ny, nx] uint32: the source is then the
     # difference activity - activity_prev (signed)
     activity_prev: Optional[np.ndarray] = None
+    e0_kev: float = 140.0     # emission line energy
 
     @property
     def n_views(self) -> int:

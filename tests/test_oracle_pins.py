@@ -919,3 +919,54 @@ def test_cgsm_scatter_estimate():
     rl2 = lambda x: np.linalg.norm(x - ref) / np.linalg.norm(ref)
     assert rl2(cg) < 0.7 * rl2(fine), (rl2(cg), rl2(fine))
     assert cg.sum() == pytest.approx(ref.sum(), rel=0.02)
+
+
+# --- emission lines (Sec. 3: Tl-201 at 71 and 167 keV) ----------------------
+
+def _g_numeric(e, f_pe):
+    """Attenuation at e relative to 140 keV from the numerically integrated
+    Klein-Nishina cross-section and the E^-3 photoelectric term."""
+    kn = lambda x: integrate.quad(kn_pdf_cos, -1.0, 1.0, args=(x / MEC2,), epsrel=1e-12)[0]
+    return (1.0 - f_pe) * kn(e) / kn(140.0) + f_pe * (140.0 / e) ** 3
+
+
+@pytest.mark.parametrize("e0", [71.0, 167.0])
+def test_emission_line_narrow_beam(e0):
+    """A point source emitting at e0 in the water cube: primaries counted in a
+    window about e0 follow 1/2 int exp(-mu140 g(e0) h / c) dc with g from
+    the integrated cross-section (20 degree cone)."""
+    N = 400_000
+    p = phantoms.point_cube_64(N).with_(e0_kev=e0, e_lo_kev=e0 - 10.0, e_hi_kev=e0 + 10.0,
+                                        e_cut_kev=min(e0 - 10.0, 100.0),
+                                        accept_half_angle_rad=math.radians(20.0), pe_fraction=0.02)
+    r = oracle.simulate(p)
+    g = _g_numeric(e0, 0.02)
+    pexp = _cone_primary_prob(p.accept_half_angle_rad, float(np.float32(0.151)) * g * 6.4)
+    assert abs(binom_z(r["tally"][0, 0].sum(), N, pexp)) < 4
+    assert g == pytest.approx(oracle.g_of_e(e0, 0.02), rel=1e-9)
+
+
+@pytest.mark.parametrize("e0", [71.0, 167.0])
+def test_emission_line_branch_and_conservation(e0):
+    """With the cut at the line energy every Compton scatter ends its history,
+    so the first real collision's branch is observed: P(absorbed) =
+    f (140/e0)^3 / g(e0); energies add up to e0 per history."""
+    N = 300_000
+    f = 0.05
+    p = phantoms.point_source_cube("pe_line", 32, 0.5, N, e_cut=e0).with_(pe_fraction=f, e0_kev=e0,
+                                                                          e_lo_kev=e0 - 5, e_hi_kev=e0 + 5)
+    r = oracle.simulate(p)
+    a, c = r["fates"][0], r["fates"][1]
+    assert abs(binom_z(a, a + c, f * (140.0 / e0) ** 3 / _g_numeric(e0, f))) < 4
+    q = phantoms.thorax_problem("t_line", 24, 1.6, 2, 6, 180.0, 24, 1.6, 100_000).with_(
+        e0_kev=e0, e_cut_kev=20.0, e_lo_kev=0.9 * e0, e_hi_kev=1.1 * e0)
+    s = oracle.simulate(q)
+    assert s["energy"][:3].sum() == pytest.approx(e0 * q.n_histories, rel=1e-12)
+    assert s["fates"].sum() == q.n_histories
+
+
+def test_emission_line_limits():
+    p = phantoms.point_cube_64(100)
+    for bad in (dict(e0_kev=600.0), dict(e0_kev=80.0, e_cut_kev=90.0)):
+        with pytest.raises(RuntimeError):
+            oracle.simulate(p.with_(**bad))

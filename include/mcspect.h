@@ -114,6 +114,17 @@ typedef struct {
                                 /* is the projection of d, to be added to that  */
                                 /* of activity_prev.  Forward projection only:  */
                                 /* mc_adjoint_mu and mc_system_matrix reject it */
+    double e0_kev;              /* emission line energy (Sec. 3: Tc-99m 140,    */
+                                /* Tl-201 71 and 167 keV); 0 = 140.  At most    */
+                                /* 500 keV, exactly representable in FP32, and  */
+                                /* >= e_cut_kev.  mu140 stays the map at 140    */
+                                /* keV (scaled by g(E)).  A multi-line source   */
+                                /* is one problem per line (histories split by  */
+                                /* the line intensities); problems with the     */
+                                /* same seed and problem_id run the same        */
+                                /* histories, so a line tallied in several      */
+                                /* windows is several problems differing only   */
+                                /* in e_lo_kev / e_hi_kev                       */
 } mc_problem;
 
 typedef struct {

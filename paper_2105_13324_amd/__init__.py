@@ -57,6 +57,7 @@ class McProblem(C.Structure):
         ("seed", C.c_uint32), ("problem_id", C.c_uint32),
         ("image_factor", C.c_int32), ("max_steps", C.c_uint32),
         ("activity_prev", C.c_void_p),
+        ("e0_kev", C.c_double),
     ]
 
 
@@ -72,7 +73,7 @@ EVENT_DTYPE = np.dtype([("work", np.uint64), ("bin", np.uint32), ("emit_voxel", 
 RECORD_DTYPE = np.dtype([("fate", np.int32), ("view", np.int32), ("iu", np.int32), ("iv", np.int32),
                          ("n_scatter", np.int32), ("n_tent", np.int32), ("emit_voxel", np.int32),
                          ("cls", np.int32), ("e_final", np.float64)])
-assert C.sizeof(McProblem) == 168
+assert C.sizeof(McProblem) == 176
 
 _vp, _i32, _i64, _u64, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_size_t
 _lib.mc_workspace_bytes.argtypes = [C.POINTER(McProblem), _i32, C.POINTER(McOptions)]
@@ -155,6 +156,7 @@ class DeviceProblem:
     history_offset: int = 0
     history_count: int = 0
     activity_prev: Optional[object] = None   # device uint32 map: difference source
+    e0_kev: float = 140.0                    # emission line energy
 
     @property
     def n_views(self) -> int:
@@ -180,13 +182,14 @@ class DeviceProblem:
             n_histories=self.n_histories, history_offset=self.history_offset,
             history_count=self.history_count, seed=self.seed, problem_id=self.problem_id,
             image_factor=self.image_factor, max_steps=self.max_steps,
-            activity_prev=self.activity_prev.data_ptr() if self.activity_prev is not None else None)
+            activity_prev=self.activity_prev.data_ptr() if self.activity_prev is not None else None,
+            e0_kev=self.e0_kev)
 
 
 _SCALARS = ["nx", "ny", "nz", "voxel_cm", "nu", "nv", "pixel_cm", "radius_cm",
             "accept_half_angle_rad", "e_lo_kev", "e_hi_kev", "e_cut_kev", "n_histories", "seed",
             "problem_id", "source_mode", "image_factor", "pe_fraction", "max_steps",
-            "history_offset", "history_count"]
+            "history_offset", "history_count", "e0_kev"]
 
 
 def to_device(prob, device="cuda") -> DeviceProblem:

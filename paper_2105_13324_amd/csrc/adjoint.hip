@@ -64,7 +64,7 @@ __device__ void walk(const Cst& C, float ax, float ay, float az, float dx, float
 }
 
 __device__ inline double g_of(const Cst& C, float e) {
-    if (e == 140.0f) return 1.0;
+    if (e == C.e0) return (double)C.g0;
     float a, b;
     return (double)energy_terms(C, e, a, b);
 }

@@ -54,7 +54,9 @@ bool check_problem(const mc_problem& p) {
     if (p.radius_cm <= 0.5 * std::sqrt(lx * lx + ly * ly)) return false;   // plane outside the grid
     if (!(p.accept_half_angle_rad > 0.0 && p.accept_half_angle_rad < 1.5707963267948966)) return false;
     if (!std::isfinite(p.e_lo_kev) || !std::isfinite(p.e_hi_kev) || p.e_lo_kev > p.e_hi_kev) return false;
-    if (!std::isfinite(p.e_cut_kev) || p.e_cut_kev < 1.0 || p.e_cut_kev > 140.0) return false;
+    const double e0 = p.e0_kev > 0.0 ? p.e0_kev : 140.0;
+    if (!(e0 <= MAX_LINE_KEV) || (double)(float)e0 != e0) return false;
+    if (!std::isfinite(p.e_cut_kev) || p.e_cut_kev < 1.0 || p.e_cut_kev > e0) return false;
     if (!(p.pe_fraction >= 0.0 && p.pe_fraction <= 1.0)) return false;
     if (p.n_histories < 1) return false;
     if (p.n_histories / (uint64_t)p.n_views >= (1ull << 32) - 1) return false;
@@ -150,6 +152,7 @@ ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64
     d.tally_offset = tally_offset;
     d.mu = p.mu140; d.act = p.activity; d.angles = p.angle_rad;
     d.act_prev = p.activity_prev;
+    d.e0 = (float)(p.e0_kev > 0.0 ? p.e0_kev : 140.0);
     d.q32 = (uint32_t*)(ws + L.q[i]);
     d.q8 = (uint8_t*)(ws + L.q8[i]);
     d.palette = (uint32_t*)(ws + L.pal[i]);

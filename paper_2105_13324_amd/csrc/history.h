@@ -93,13 +93,38 @@ struct Cst {
     uint32_t box_margin;      // the box leaves air on some side of the grid
     int nu, nv, n_views;
     float inv_pix, radius, cos_alpha, wu, wv, e_lo, e_hi, e_cut;
-    float f_pe, mu_hat, ln2_mm140, p_pe140;
+    float f_pe, mu_hat, ln2_mm0, p_pe0, e0, g0;   // attenuation terms at the line e0
     uint32_t seed, pid, max_steps, shift;
     uint64_t total, q_per_view, r_extra, work_begin, tally_offset;
     uint32_t flags, use_pal;
     int brick;
     uint32_t bmask, nbx, nby;
 };
+
+// Attenuation at energy e relative to 140 keV, g(E) = (1-f) KN(E)/KN(140) +
+// f (140/E)^3, the flight scale ln2/(max mu g) (a flight is -log2(u) times
+// it, with the hardware log2) and the photoelectric share f (140/E)^3 / g.
+// The KN ratio is linearly interpolated (error below 1e-6 relative over the
+// table range), the photoelectric term is exact.
+// sigma_KN(e) / sigma_KN(140), linearly interpolated in the table.
+__device__ inline float kn_ratio(const Cst& C, float e) {
+    const float t = (C.e0 - e) * KN_TABLE_STEP_INV;
+    const int i = (int)t;
+    const float fr = t - (float)i;
+    const float k0 = ldg(C.kn_table + i), k1 = ldg(C.kn_table + i + 1);
+    return fmaf(fr, k1 - k0, k0);
+}
+
+__device__ inline float energy_terms(const Cst& C, float e, float& ln2_mm, float& p_pe) {
+    const float kn = kn_ratio(C, e);
+    const float x = 140.0f * rcpf(e);
+    const float pe = C.f_pe * x * x * x;
+    const float g = fmaf(1.0f - C.f_pe, kn, pe);
+    const float ig = rcpf(g);
+    ln2_mm = LN2_F * rcpf(C.mu_hat * g);
+    p_pe = pe * ig;
+    return g;
+}
 
 __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     Cst c;
@@ -125,9 +150,15 @@ __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     c.wu = d->wu; c.wv = d->wv; c.e_lo = d->e_lo; c.e_hi = d->e_hi; c.e_cut = d->e_cut;
     c.f_pe = d->f_pe;
     c.mu_hat = __uint_as_float(d->mu_hat_bits);
-    // g(140 keV) = 1 by construction: mu_max(140) = max mu, p_pe(140) = f.
-    c.ln2_mm140 = (float)(0.69314718055994531 / (double)c.mu_hat);
-    c.p_pe140 = c.f_pe;
+    c.e0 = d->e0;
+    if (c.e0 == 140.0f) {
+        // g(140 keV) = 1 by construction: mu_max(140) = max mu, p_pe(140) = f.
+        c.g0 = 1.0f;
+        c.ln2_mm0 = (float)(0.69314718055994531 / (double)c.mu_hat);
+        c.p_pe0 = c.f_pe;
+    } else {
+        c.g0 = energy_terms(c, c.e0, c.ln2_mm0, c.p_pe0);
+    }
     c.seed = d->seed; c.pid = d->problem_id; c.max_steps = d->max_steps; c.shift = d->shift;
     c.total = d->total; c.q_per_view = d->q_per_view; c.r_extra = d->r_extra;
     c.work_begin = d->work_begin; c.tally_offset = d->tally_offset;
@@ -137,31 +168,6 @@ __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     c.bmask = (1u << c.brick) - 1u;
     c.nbx = (uint32_t)d->nbx; c.nby = (uint32_t)d->nby;
     return c;
-}
-
-// Attenuation at energy e relative to 140 keV, g(E) = (1-f) KN(E)/KN(140) +
-// f (140/E)^3, the flight scale ln2/(max mu g) (a flight is -log2(u) times
-// it, with the hardware log2) and the photoelectric share f (140/E)^3 / g.
-// The KN ratio is linearly interpolated (error below 1e-6 relative over the
-// table range), the photoelectric term is exact.
-// sigma_KN(e) / sigma_KN(140), linearly interpolated in the table.
-__device__ inline float kn_ratio(const Cst& C, float e) {
-    const float t = (140.0f - e) * KN_TABLE_STEP_INV;
-    const int i = (int)t;
-    const float fr = t - (float)i;
-    const float k0 = ldg(C.kn_table + i), k1 = ldg(C.kn_table + i + 1);
-    return fmaf(fr, k1 - k0, k0);
-}
-
-__device__ inline float energy_terms(const Cst& C, float e, float& ln2_mm, float& p_pe) {
-    const float kn = kn_ratio(C, e);
-    const float x = 140.0f * rcpf(e);
-    const float pe = C.f_pe * x * x * x;
-    const float g = fmaf(1.0f - C.f_pe, kn, pe);
-    const float ig = rcpf(g);
-    ln2_mm = LN2_F * rcpf(C.mu_hat * g);
-    p_pe = pe * ig;
-    return g;
 }
 
 struct Lane {
@@ -366,9 +372,9 @@ __device__ inline void begin_history(const Cst& C, Lane& L, uint32_t view, uint3
     L.emit_voxel = e.voxel;
     L.x = e.x; L.y = e.y; L.z = e.z;
     L.dx = e.dx; L.dy = e.dy; L.dz = e.dz;
-    L.e = 140.0f;
-    L.ln2_mm = C.ln2_mm140;
-    L.p_pe = C.p_pe140;
+    L.e = C.e0;
+    L.ln2_mm = C.ln2_mm0;
+    L.p_pe = C.p_pe0;
     const float2 cs = ldg(C.views + view);
     L.vc = cs.x; L.vs = cs.y;
 }
@@ -583,7 +589,7 @@ __device__ inline bool fd_eval(const Cst& C, const ProbDesc* __restrict__ d, con
     const int iu = min((int)(au * C.inv_pix), C.nu - 1);
     const int iv = min((int)(av * C.inv_pix), C.nv - 1);
     float l2, ppe;
-    const float g = e2 == 140.0f ? 1.0f : energy_terms(C, e2, l2, ppe);
+    const float g = e2 == C.e0 ? C.g0 : energy_terms(C, e2, l2, ppe);
     score = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, ox, oy, oz));
     const uint32_t cls = q.event == 0 ? 0u : 1u;
     bin = ((q.view * 2u + cls) * (uint32_t)C.nv + (uint32_t)iv) * (uint32_t)C.nu + (uint32_t)iu;
@@ -626,7 +632,7 @@ __device__ inline bool cfd_eval(const Cst& C, const ProbDesc* __restrict__ d, co
     const float depth = C.radius - (q.x * vw.x + q.y * vw.y);
     const int l = min(max((int)floorf(depth * C.inv_pix), 0), nl - 1);
     float l2, ppe;
-    const float g = e2 == 140.0f ? 1.0f : energy_terms(C, e2, l2, ppe);
+    const float g = e2 == C.e0 ? C.g0 : energy_terms(C, e2, l2, ppe);
     score = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, vw.x, vw.y, 0.0f));
     const uint32_t cls = q.event == 0 ? 0u : 1u;
     lbin = ((((uint64_t)q.view * (uint64_t)nl + (uint64_t)l) * 2u + cls) * (uint64_t)C.nv + (uint64_t)iv) *

@@ -44,7 +44,7 @@ struct ProbDesc {
     uint32_t* block_cnt;            // scan scratch: active voxels per block
     uint4* guide;                   // emission buckets (EmitBucket layout), n_buckets entries
     float2* views;                  // (cos, sin) per view
-    float* kn_table;                // sigma_KN(140 - i/4 keV) / sigma_KN(140), i < KN_TABLE_N
+    float* kn_table;                // sigma_KN(e0 - i/4 keV) / sigma_KN(140), i < KN_TABLE_N
     // filled on the device by staging
     uint32_t mu_hat_bits;           // max mu, as float bits (mu >= 0)
     uint32_t flags;                 // MC_STATUS_* bits found during staging
@@ -64,6 +64,8 @@ struct ProbDesc {
     int32_t cfd_L, cfd_hmax;        // depth layers (one pixel thick); largest half-width
     double alpha, cfd_pix, cfd_tan; // collimator half-angle (rad), pixel (cm), tan(alpha)
     const uint32_t* act_prev;       // nullable: the source is act - act_prev (signed)
+    float e0;                       // emission line energy (keV)
+    uint32_t pad4;
 };
 
 // Emission weight of voxel i: the activity, or for a difference source the
@@ -109,7 +111,8 @@ constexpr uint32_t PALETTE_EMPTY = 0xFFFFFFFFu;
 __host__ __device__ inline uint32_t palette_hash(uint32_t q) { return (q * 2654435761u) >> 24; }
 
 constexpr int SCAN_ITEMS = 4096;    // activity values per scan block
-constexpr int KN_TABLE_N = 568;     // entries of the Klein-Nishina shape table (>= 4*140 + 2)
+constexpr int KN_TABLE_N = 2048;    // entries of the Klein-Nishina shape table (>= 4*500 + 2)
+constexpr double MAX_LINE_KEV = 500.0;   // highest emission line accepted
 constexpr int MAX_AXIS = 1024;      // voxel indices are packed 10 bits per axis
 constexpr int SCAN_THREADS = 256;
 

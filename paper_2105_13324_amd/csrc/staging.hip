@@ -388,7 +388,7 @@ __device__ double kn_bracket(double e) {
 __global__ void k_kn_table(ProbDesc* pd) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= KN_TABLE_N) return;
-    const double e = fmax(140.0 - 0.25 * i, 0.5);
+    const double e = fmax((double)pd->e0 - 0.25 * i, 0.5);
     pd->kn_table[i] = (float)(kn_bracket(e) / kn_bracket(140.0));
 }
 

@@ -269,7 +269,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                                 FdPoint q;
                                 q.x = e.x; q.y = e.y; q.z = e.z;
                                 q.dx = 0.0f; q.dy = 0.0f; q.dz = 0.0f;
-                                q.e = 140.0f;
+                                q.e = C.e0;
                                 q.view = (uint32_t)v; q.hist = (uint32_t)h; q.event = 0;
                                 q.voxel = e.voxel;
                                 fd_commit<MODE>(C, p, q, lane, T);
@@ -494,12 +494,12 @@ __global__ void k_finalize(const ProbDesc* __restrict__ descs, int n_problems, i
         f |= descs[p].flags;
         n_pal += descs[p].pal_state == 0;
         if (energy) {
-            // every history started with 140 keV: what did not leave (escaped
-            // or capped) was deposited
+            // every history started at the line energy: what did not leave
+            // (escaped or capped) was deposited
             int64_t nh = 0;
             for (int k = 0; k < MC_N_FATES; ++k) nh += fates[(size_t)p * MC_N_FATES + k];
             int64_t* e = energy + (size_t)p * 4;
-            e[0] = nh * (int64_t)(140ll << 23) - e[1] - e[2];
+            e[0] = nh * (int64_t)llrint((double)descs[p].e0 * 8388608.0) - e[1] - e[2];
         }
     }
     if (n_events && capacity != UINT64_MAX && *n_events > capacity) f |= MC_STATUS_LIST_OVERFLOW;

@@ -233,6 +233,29 @@ def thorax_256(n_hist: int = 10**9) -> Problem:
                           image_factor=4)
 
 
+# Tl-201 (Sec. 3): photons at 71 and 167 keV.  Their relative yields
+# (0.9 : 0.1) and the 20 % photopeak windows about each line are input choices.
+TL201_LINES = ((71.0, 0.9), (167.0, 0.1))
+TL201_WINDOWS = ((64.0, 78.0), (150.0, 184.0))
+
+
+def line_window_problems(base: Problem, n_hist: int, lines=TL201_LINES,
+                         windows=TL201_WINDOWS) -> List[Problem]:
+    """A multi-line source acquired in several windows: one problem per (line,
+    window), line-major.  Line k gets round(n_hist p_k / V) V histories and
+    problem_id k, so all windows of a line see the same photons; the cut is
+    the lowest window edge."""
+    V = base.n_views
+    e_cut = min(lo for lo, _ in windows)
+    out = []
+    for k, (e0, frac) in enumerate(lines):
+        n_k = max(1, int(round(n_hist * frac / V))) * V
+        for w, (lo, hi) in enumerate(windows):
+            out.append(base.with_(name=f"{base.name}_l{k}_w{w}", e0_kev=e0, e_lo_kev=lo, e_hi_kev=hi,
+                                  e_cut_kev=e_cut, n_histories=n_k, problem_id=k))
+    return out
+
+
 def estimate_pair(act: np.ndarray, rel: float, seed: int, scale: int = 1000, bias: float = 0.0):
     """Two successive image estimates for reuse of photon tracks: the previous
     one is act * scale, the new one that times (1 + bias + rel * U(-1, 1))

@@ -1,0 +1,83 @@
+"""Emission lines other than 140 keV (Sec. 3: Tl-201 at 71 and 167 keV) and
+multi-window acquisition on the GPU against the oracle, through the C ABI.
+
+Bars: as for the 140 keV source (replayed histories identical to 99.9 %,
+aggregates to 1e-4 of the histories, bin by bin up to rare flips; forced
+detection to 3e-4 bin L1 and 2e-5 per class); in a line-by-window batch the
+problems of one line run the same histories (every fate but the window
+split identical) and each matches its own oracle run.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import phantoms
+
+pytestmark = pytest.mark.gpu
+
+from test_gpu_transport import aggregate_parity, replay_parity  # noqa: E402
+from test_gpu_fd import fd_parity  # noqa: E402
+
+
+def _mc():
+    import paper_2105_13324_amd as mc
+    return mc
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("e0", [71.0, 167.0])
+def test_line_energy_matches_oracle(e0):
+    p = phantoms.thorax_problem(f"line_{int(e0)}", 64, 0.6, 2, 60, 180.0, 64, 0.6, 2_000_000).with_(
+        e0_kev=e0, e_lo_kev=0.9 * e0, e_hi_kev=1.1 * e0, e_cut_kev=0.5 * e0, pe_fraction=0.01)
+    say(f"line parity e0 {e0}")
+    replay_parity(p)
+    aggregate_parity(p)
+
+
+def test_line_energy_point_cube_wide_cone():
+    p = phantoms.point_cube_64(1_000_000).with_(e0_kev=71.0, e_lo_kev=64.0, e_hi_kev=78.0,
+                                                e_cut_kev=30.0, pe_fraction=0.02,
+                                                accept_half_angle_rad=math.radians(10.0))
+    replay_parity(p)
+    aggregate_parity(p)
+
+
+@pytest.mark.parametrize("e0", [71.0, 167.0])
+def test_line_energy_forced_detection(e0):
+    p = phantoms.thorax_problem(f"line_fd_{int(e0)}", 32, 1.2, 3, 12, 180.0, 32, 1.2, 300_000).with_(
+        e0_kev=e0, e_lo_kev=0.9 * e0, e_hi_kev=1.1 * e0, e_cut_kev=0.5 * e0, pe_fraction=0.01)
+    fd_parity(p)
+
+
+def test_tl201_line_window_batch():
+    mc = _mc()
+    base = phantoms.thorax_problem("tl201", 48, 0.8, 4, 24, 180.0, 48, 0.8, 1).with_(
+        pe_fraction=0.01, accept_half_angle_rad=math.radians(5.0))
+    probs = phantoms.line_window_problems(base, 4_800_000)
+    assert [p.problem_id for p in probs] == [0, 0, 1, 1]
+    sim = mc.simulate([mc.to_device(p) for p in probs])
+    fates = sim.fates.cpu().numpy()
+    cnt = sim.counters.cpu().numpy()
+    tallies = [t.cpu().numpy().astype(np.float64) / mc.Q32 for t in sim.tallies()]
+    for k in (0, 2):           # the two windows of one line: the same photons
+        a, b = fates[k], fates[k + 1]
+        np.testing.assert_array_equal(a[[0, 1, 2, 3, 6]], b[[0, 1, 2, 3, 6]])
+        assert a[4] + a[5] == b[4] + b[5]
+        np.testing.assert_array_equal(cnt[k], cnt[k + 1])
+    for i, p in enumerate(probs):
+        o = oracle.simulate(p)
+        diff = np.abs(tallies[i] - o["tally"]).sum()
+        say(f"{p.name}: e0 {p.e0_kev} window {p.e_lo_kev}-{p.e_hi_kev}: tallied {fates[i][5]} "
+            f"(oracle {o['fates'][5]:.0f}), bin diff {diff:.0f}")
+        assert diff <= max(2, 1e-3 * fates[i][5])
+        assert abs(fates[i][5] - o["fates"][5]) <= 1e-4 * p.n_histories
+    # 167 keV photons scattered down into the 71 keV window: scattered class only
+    low_from_high = tallies[2]
+    assert low_from_high[:, 1].sum() > 0 and low_from_high[:, 0].sum() == 0

@@ -259,6 +259,7 @@ def extra_forms(mc, torch, args):
     out["forced_detection"] = fd_form(mc, torch, steps)
     out["reuse_of_photon_tracks"] = rpt_form(mc, torch, steps)
     out["coarse_grid_scatter"] = cgsm_form(mc, torch, steps)
+    out["tl201_dual_window"] = tl201_form(mc, torch, steps)
     if not args.no_large:
         out["large_mlem"] = large_form(mc, torch, steps)
     return out
@@ -393,6 +394,30 @@ def cgsm_form(mc, torch, steps):
             "history_gain": (err_f / err_c) ** 2,
             "step": "forced-detection transport of the coarse problem + expansion (coarsening "
                     "timed apart: once per source estimate)"}
+
+
+def tl201_form(mc, torch, steps):
+    """Tl-201 (Sec. 3) on the 128^3 thorax, 60 views: 1e8 photons split 0.9 :
+    0.1 between the 71 and 167 keV lines, each acquired in both 20 %
+    photopeak windows (four problems, one persistent launch; the windows of a
+    line run the same photons).  value: emitted photons per second."""
+    import phantoms
+    base = phantoms.thorax_128(1)
+    probs = phantoms.line_window_problems(base, 10 ** 8)
+    dps = [mc.to_device(p) for p in probs]
+    sim = mc.Simulator(dps, want_sq=False)
+    sim.run()
+    ms = timed(torch, sim.run, steps)
+    sim.check_status()
+    n_phot = sum(p.n_histories for p in probs[::2])
+    fates = sim.fates.cpu().numpy()
+    tal = [float(t.sum().item()) * 2.0 ** -32 for t in sim.tallies()]
+    return {"value": n_phot / (ms / 1e3), "unit": "emitted photons/s", "ms_per_step": ms,
+            "photons": n_phot, "histories_simulated": sum(p.n_histories for p in probs),
+            "window_counts_per_photon": {
+                "64-78 keV": (tal[0] + tal[2]) / n_phot, "150-184 keV": (tal[1] + tal[3]) / n_phot},
+            "low_window_share_from_167_keV": tal[2] / max(tal[0] + tal[2], 1e-30),
+            "photoelectric_absorbed_share_71keV": float(fates[0][0]) / probs[0].n_histories}
 
 
 def large_fd(mc, torch, steps, p5):

@@ -107,6 +107,7 @@ def test_workspace_bytes_and_validation():
         dict(e_lo_kev=160.0), dict(e_cut_kev=0.0), dict(pe_fraction=1.5), dict(n_histories=0),
         dict(history_offset=2000), dict(history_offset=500, history_count=600),
         dict(image_factor=3), dict(source_mode=7), dict(nx=1025), dict(e_cut_kev=0.5),
+        dict(e0_kev=600.0), dict(e0_kev=71.1), dict(e0_kev=5.0), dict(e0_kev=80.0, e_cut_kev=90.0),
     ]
     for b in bad:
         q = _good()

@@ -97,7 +97,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="time only the headline workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 256^3 / 1e9-history form")
-    ap.add_argument("--only-form", choices=["forced_detection"], default=None,
+    ap.add_argument("--only-form", choices=["forced_detection", "batched"], default=None,
                     help="time only this side form (forced detection and its convolution-based "
                          "form) and print its record; for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -120,8 +120,9 @@ def main():
         return
     import phantoms
     import paper_2105_13324_amd as mc
-    if args.only_form == "forced_detection":
-        print(json.dumps({"form": "forced_detection", **fd_form(mc, torch, args.steps)}))
+    if args.only_form:
+        fn = {"forced_detection": fd_form, "batched": batched_form}[args.only_form]
+        print(json.dumps({"form": args.only_form, **fn(mc, torch, args.steps)}))
         return
 
     n_hist = int(args.histories)
@@ -219,19 +220,7 @@ def extra_forms(mc, torch, args):
     ms = timed(torch, s1.run, steps)
     out["point_cube_64"] = {"value": p1.n_histories / (ms / 1e3), "unit": "histories/s",
                             "ms_per_step": ms, "histories": p1.n_histories}
-    # batched: 32 thoraxes 96^3-160^3, 30-120 views, 1e7 histories each, one graph
-    probs = phantoms.batched_thoraxes(10 ** 7)
-    dps = [mc.to_device(p) for p in probs]
-    opts = mc.autotune(dps, reps=1)
-    s3 = mc.Simulator(dps, want_sq=False, options=opts)
-    runner = mc.GraphRunner(s3)
-    runner.replay()
-    ms = timed(torch, runner.replay, steps)
-    s3.check_status()
-    n3 = sum(p.n_histories for p in probs)
-    out["batched"] = {"value": n3 / (ms / 1e3), "unit": "histories/s", "ms_per_step": ms,
-                      "histories": n3, "problems": len(probs), "options": opts,
-                      "launch": "hipGraph replay: staging x32 + one persistent transport kernel"}
+    out["batched"] = batched_form(mc, torch, steps)
     # adjoint: forward with event list, loss gradient, replaying adjoint
     p4 = phantoms.point_cube_128_adjoint(10 ** 7)
     d4 = mc.to_device(p4)
@@ -263,6 +252,30 @@ def extra_forms(mc, torch, args):
     if not args.no_large:
         out["large_mlem"] = large_form(mc, torch, steps)
     return out
+
+
+def batched_form(mc, torch, steps):
+    """32 thoraxes 96^3-160^3, 30-120 views, 1e7 histories each: staging of
+    every problem and one persistent transport kernel, replayed as one HIP
+    graph, with the autotuned options."""
+    import phantoms
+    probs = phantoms.batched_thoraxes(10 ** 7)
+    dps = [mc.to_device(p) for p in probs]
+    opts = mc.autotune(dps, reps=1)
+    s3 = mc.Simulator(dps, want_sq=False, options=opts)
+    runner = mc.GraphRunner(s3)
+    runner.replay()
+    ms = timed(torch, runner.replay, steps)
+    s3.check_status()
+    timers = [mc.KernelTimer() for _ in range(steps)]
+    for t in timers:
+        s3.run(kernel_events=t.handles)
+    torch.cuda.synchronize()
+    k_ms = float(np.mean([t.elapsed_ms() for t in timers]))
+    n3 = sum(p.n_histories for p in probs)
+    return {"value": n3 / (ms / 1e3), "unit": "histories/s", "ms_per_step": ms,
+            "transport_ms": k_ms, "histories": n3, "problems": len(probs), "options": opts,
+            "launch": "hipGraph replay: staging x32 + one persistent transport kernel"}
 
 
 def fd_form(mc, torch, steps):

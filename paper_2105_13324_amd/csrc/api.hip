@@ -243,17 +243,17 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     ProbDesc* d_desc = (ProbDesc*)(ws + L.desc);
     uint64_t tally_elems = 0;
     std::vector<ProbDesc> hd;
-    if (cfd) hd.reserve(n_problems);
+    hd.reserve(n_problems);
     for (int i = 0; i < n_problems; ++i) {
         const mc_problem& p = problems[i];
-        const ProbDesc h = host_desc(p, ws, L, i, tally_elems, brick, qbytes, cfd);
+        hd.push_back(host_desc(p, ws, L, i, tally_elems, brick, qbytes, cfd));
         tally_elems += (uint64_t)p.n_views * 2 * p.nv * p.nu;
-        hipError_t e = launch_staging(d_desc + i, h, st);
+    }
+    {
+        hipError_t e = launch_staging_batch(d_desc, hd.data(), n_problems, st);
         if (e != hipSuccess) return hip_fail(e);
-        if (cfd) {
-            if ((e = launch_cfd_setup(d_desc + i, h, st)) != hipSuccess) return hip_fail(e);
-            hd.push_back(h);
-        }
+        for (int i = 0; cfd && i < n_problems; ++i)
+            if ((e = launch_cfd_setup(d_desc + i, hd[i], st)) != hipSuccess) return hip_fail(e);
     }
     const uint32_t chunk = (uint32_t)(64 * hpl);
     hipError_t e = launch_prepare_call(d_desc, n_problems, (uint64_t*)(ws + L.prefix),
@@ -290,7 +290,7 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     e = launch_transport(a, n_cu * bpc, block, st);
     if (e != hipSuccess) return hip_fail(e);
     if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return hip_fail(e);
-    for (int i = 0; i < (int)hd.size(); ++i)
+    for (int i = 0; cfd && i < (int)hd.size(); ++i)
         if ((e = launch_cfd_convolve(d_desc + i, hd[i], tally, st)) != hipSuccess) return hip_fail(e);
     return MC_OK;
 }

@@ -149,7 +149,13 @@ hipError_t launch_cfd_convolve(const ProbDesc* d, const ProbDesc& h, int64_t* ta
 
 // Host launchers (staging.hip)
 hipError_t launch_staging(ProbDesc* d_desc, const ProbDesc& h_desc, hipStream_t s);
-uint64_t guide_capacity(uint64_t nvox);   // emission buckets reserved (power of two >= 2 nvox)
+// emission buckets reserved: the power of two >= 2 nvox
+__host__ __device__ inline uint64_t guide_capacity(uint64_t nvox) {
+    uint64_t c = 1;
+    while (c < 2 * nvox) c <<= 1;
+    return c;
+}
+hipError_t launch_staging_batch(ProbDesc* d_descs, const ProbDesc* h_descs, int n, hipStream_t s);
 
 // Host launchers (transport.hip)
 struct TransportArgs {

@@ -49,7 +49,8 @@ __global__ void k_write_desc(ProbDesc d, ProbDesc* out) {
 
 // Max mu (as bits: order-preserving for non-negative floats), bad-value flags,
 // activity total, view table.
-__global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* pd) {
+__global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* descs) {
+    ProbDesc* pd = descs + blockIdx.y;
     const uint64_t nvox = pd->nvox;
     const float* __restrict__ mu = pd->mu;
     const uint32_t* __restrict__ act = pd->act;
@@ -138,7 +139,8 @@ __device__ inline uint32_t palette_insert(uint32_t* pal, uint32_t q) {
 // so a brick is a few whole cache lines (the layout never changes a result).
 // Each distinct Q also goes into the palette: a wavefront inserts each of its
 // distinct values once (leader lane), so the table sees few atomics.
-__global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* pd) {
+__global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* descs) {
+    ProbDesc* pd = descs + blockIdx.y;
     const uint64_t nvox = pd->nvox;
     const float mu_hat = __uint_as_float(pd->mu_hat_bits);
     const float* __restrict__ mu = pd->mu;
@@ -179,7 +181,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* pd) {
 
 // One-byte palette codes in the threshold layout (skipped when the palette
 // overflowed or was not requested: the kernels then read the 32-bit table).
-__global__ __launch_bounds__(RED_THREADS) void k_codes(ProbDesc* pd) {
+__global__ __launch_bounds__(RED_THREADS) void k_codes(ProbDesc* descs) {
+    ProbDesc* pd = descs + blockIdx.y;
     if (pd->pal_state != 0) return;
     const uint64_t nvox = pd->nvox;
     const uint32_t* __restrict__ q = pd->q32;
@@ -205,8 +208,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_codes(ProbDesc* pd) {
 // --- three-pass scan of the activity map: uint64 inclusive sums and the
 // positions of active voxels, so the CDF is stored over active voxels only ---
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(ProbDesc* pd) {
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(ProbDesc* descs) {
+    ProbDesc* pd = descs + blockIdx.y;
     const uint64_t nvox = pd->nvox;
+    if ((uint64_t)blockIdx.x * SCAN_ITEMS >= nvox) return;   // past this problem's blocks
     const uint32_t* __restrict__ act = pd->act;
     const uint32_t* __restrict__ prev = pd->act_prev;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_ITEMS;
@@ -237,7 +242,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(ProbDesc* pd) {
 
 // Exclusive scan of the block sums and counts, one block of 1024 threads,
 // each thread a contiguous run; also records the number of active voxels.
-__global__ __launch_bounds__(1024) void k_scan_top(ProbDesc* pd, int n_blocks) {
+__global__ __launch_bounds__(1024) void k_scan_top(ProbDesc* descs) {
+    ProbDesc* pd = descs + blockIdx.y;
+    const int n_blocks = (int)((pd->nvox + SCAN_ITEMS - 1) / SCAN_ITEMS);
     __shared__ uint64_t tot[1024];
     __shared__ uint32_t totc[1024];
     uint64_t* __restrict__ bs = pd->block_sums;
@@ -276,9 +283,11 @@ __global__ __launch_bounds__(1024) void k_scan_top(ProbDesc* pd, int n_blocks) {
 // Per block: 16 consecutive voxels per thread, thread-local scans, block
 // exclusive scans of the thread totals, plus the block offsets; each active
 // voxel writes its cumulative activity and its index at its compacted slot.
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ProbDesc* pd) {
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ProbDesc* descs) {
+    ProbDesc* pd = descs + blockIdx.y;
     constexpr int PER = SCAN_ITEMS / SCAN_THREADS;
     const uint64_t nvox = pd->nvox;
+    if ((uint64_t)blockIdx.x * SCAN_ITEMS >= nvox) return;   // past this problem's blocks
     const uint32_t* __restrict__ act = pd->act;
     const uint32_t* __restrict__ prev = pd->act_prev;
     uint64_t* __restrict__ cdf = pd->cdf;
@@ -336,7 +345,9 @@ __device__ inline uint64_t first_above(const uint64_t* __restrict__ cdf, uint64_
     return lo;
 }
 
-__global__ __launch_bounds__(RED_THREADS) void k_guide(ProbDesc* pd, uint64_t nb_cap) {
+__global__ __launch_bounds__(RED_THREADS) void k_guide(ProbDesc* descs) {
+    ProbDesc* pd = descs + blockIdx.y;
+    const uint64_t nb_cap = guide_capacity(pd->nvox);
     const uint64_t total = pd->total;
     const uint64_t K = pd->n_active;
     if (total == 0 || K == 0) {
@@ -385,7 +396,8 @@ __device__ double kn_bracket(double e) {
            - (1.0 + 3.0 * k) / (a * a);
 }
 
-__global__ void k_kn_table(ProbDesc* pd) {
+__global__ void k_kn_table(ProbDesc* descs) {
+    ProbDesc* pd = descs + blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= KN_TABLE_N) return;
     const double e = fmax((double)pd->e0 - 0.25 * i, 0.5);
@@ -401,29 +413,37 @@ int grid_for(uint64_t n, int threads, int cap) {
 
 }  // namespace
 
-uint64_t guide_capacity(uint64_t nvox) {
-    uint64_t c = 1;
-    while (c < 2 * nvox) c <<= 1;
-    return c;
+
+// The problems' descriptors are written one by one (by value, so the launch
+// can be captured in a graph); every other pass is one launch for all
+// problems, blockIdx.y picking the problem and each block walking that
+// problem's share, so small problems overlap instead of queueing.
+hipError_t launch_staging_batch(ProbDesc* d, const ProbDesc* h, int n, hipStream_t st) {
+    uint64_t max_rows = 1, max_nb = 1, max_cap = 1;
+    int max_nx = 1;
+    for (int i = 0; i < n; ++i) {
+        k_write_desc<<<1, 64, 0, st>>>(h[i], d + i);
+        max_rows = std::max<uint64_t>(max_rows, (uint64_t)h[i].ny * h[i].nz);
+        max_nx = std::max(max_nx, h[i].nx);
+        max_nb = std::max<uint64_t>(max_nb, (h[i].nvox + SCAN_ITEMS - 1) / SCAN_ITEMS);
+        max_cap = std::max<uint64_t>(max_cap, guide_capacity(h[i].nvox));
+    }
+    // row-per-block passes: a block walks grid rows (iy, iz), threads along x
+    const int row_threads = (int)std::min<uint64_t>(RED_THREADS, ((uint64_t)max_nx + 63) / 64 * 64);
+    const unsigned ny = (unsigned)n;
+    k_reduce<<<dim3((unsigned)std::min<uint64_t>(max_rows, 512), ny), row_threads, 0, st>>>(d);
+    k_thresholds<<<dim3((unsigned)std::min<uint64_t>(max_rows, 8192), ny), row_threads, 0, st>>>(d);
+    k_codes<<<dim3((unsigned)std::min<uint64_t>(max_rows, 8192), ny), row_threads, 0, st>>>(d);
+    k_scan_sums<<<dim3((unsigned)max_nb, ny), SCAN_THREADS, 0, st>>>(d);
+    k_scan_top<<<dim3(1, ny), 1024, 0, st>>>(d);
+    k_scan_final<<<dim3((unsigned)max_nb, ny), SCAN_THREADS, 0, st>>>(d);
+    k_guide<<<dim3((unsigned)grid_for(max_cap, RED_THREADS, 8192), ny), RED_THREADS, 0, st>>>(d);
+    k_kn_table<<<dim3((KN_TABLE_N + 255) / 256, ny), 256, 0, st>>>(d);
+    return hipGetLastError();
 }
 
 hipError_t launch_staging(ProbDesc* d, const ProbDesc& h, hipStream_t st) {
-    const uint64_t nvox = h.nvox;
-    k_write_desc<<<1, 64, 0, st>>>(h, d);
-    // row-per-block passes: a block walks grid rows (iy, iz), threads along x
-    const int row_threads = (int)std::min<uint64_t>(RED_THREADS, ((uint64_t)h.nx + 63) / 64 * 64);
-    const uint64_t nrows = (uint64_t)h.ny * h.nz;
-    k_reduce<<<(int)std::min<uint64_t>(nrows, 512), row_threads, 0, st>>>(d);
-    k_thresholds<<<(int)std::min<uint64_t>(nrows, 8192), row_threads, 0, st>>>(d);
-    k_codes<<<(int)std::min<uint64_t>(nrows, 8192), row_threads, 0, st>>>(d);
-    const int nb = (int)((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS);
-    k_scan_sums<<<nb, SCAN_THREADS, 0, st>>>(d);
-    k_scan_top<<<1, 1024, 0, st>>>(d, nb);
-    k_scan_final<<<nb, SCAN_THREADS, 0, st>>>(d);
-    const uint64_t cap = guide_capacity(nvox);
-    k_guide<<<grid_for(cap, RED_THREADS, 8192), RED_THREADS, 0, st>>>(d, cap);
-    k_kn_table<<<(KN_TABLE_N + 255) / 256, 256, 0, st>>>(d);
-    return hipGetLastError();
+    return launch_staging_batch(d, &h, 1, st);
 }
 
 }  // namespace mcs

@@ -123,6 +123,18 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* descs) {
     }
 }
 
+// True if the block has already put q in the palette; otherwise records it
+// (a full block set records nothing and answers false).
+__device__ inline bool block_seen(uint32_t* set, uint32_t q) {
+    uint32_t h = palette_hash(q);
+    for (int probe = 0; probe < PALETTE_N; ++probe, h = (h + 1) & (PALETTE_N - 1)) {
+        const uint32_t cur = atomicCAS(set + h, PALETTE_EMPTY, q);
+        if (cur == PALETTE_EMPTY) return false;
+        if (cur == q) return true;
+    }
+    return false;
+}
+
 // Slot of q in the palette, inserting it if absent; PALETTE_N when full.
 __device__ inline uint32_t palette_insert(uint32_t* pal, uint32_t q) {
     uint32_t h = palette_hash(q);
@@ -153,6 +165,11 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* descs) {
     bool full = false;
     const uint32_t nrows = ny * (uint32_t)pd->nz;
     (void)nvox;
+    // the block's own set of the values it has put in the palette: a value
+    // reaches the global table once per block, not once per wavefront
+    __shared__ uint32_t seen[PALETTE_N];
+    for (int k = threadIdx.x; k < PALETTE_N; k += blockDim.x) seen[k] = PALETTE_EMPTY;
+    __syncthreads();
     for (uint32_t r = blockIdx.x; r < nrows; r += gridDim.x)
     for (uint32_t ix = threadIdx.x; ix < nx; ix += blockDim.x) {
         const uint32_t iy = r % ny, iz = r / ny;
@@ -170,7 +187,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* descs) {
                 if (left == 0) break;
                 const int leader = __ffsll((unsigned long long)left) - 1;
                 const uint32_t lv = (uint32_t)__shfl((int)v, leader, 64);
-                if ((int)(threadIdx.x & 63) == leader && palette_insert(pd->palette, lv) == PALETTE_N)
+                if ((int)(threadIdx.x & 63) == leader && !block_seen(seen, lv) &&
+                    palette_insert(pd->palette, lv) == PALETTE_N)
                     full = true;
                 if (v == lv) todo = false;
             }
@@ -367,13 +385,28 @@ __global__ __launch_bounds__(RED_THREADS) void k_guide(ProbDesc* descs) {
     const uint64_t* __restrict__ cdf = pd->cdf;
     const uint32_t* __restrict__ vid = pd->vox_id;
     uint4* __restrict__ guide = pd->guide;
-    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B;
-         b += (uint64_t)gridDim.x * blockDim.x) {
-        // t in [lo_t, hi_t] maps to slots [first_above(lo_t), first_above(hi_t)]
+    // bucket b spans slots [lo(b), hi(b)], lo(b) = first_above(b 2^s) and
+    // hi(b) = first_above((b + 1) 2^s - 1), which is lo(b + 1), or one less
+    // when a slot's cumulative sum is exactly (b + 1) 2^s (the sums strictly
+    // increase).  A wavefront finds lo for 64 consecutive buckets, one search
+    // per lane, and completes 63 of them with its neighbour's lo.
+    const int lane = threadIdx.x & 63;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t grp = wave; grp * 63 < B; grp += n_waves) {
+        const uint64_t b = grp * 63 + (uint64_t)lane;
+        const uint64_t lo = b < B ? first_above(cdf, K, b << s) : K;
+        const uint32_t nl = (uint32_t)__shfl_down((int)(uint32_t)lo, 1, 64);
+        const uint32_t nh = (uint32_t)__shfl_down((int)(uint32_t)(lo >> 32), 1, 64);
+        if (lane == 63 || b >= B) continue;
+        uint64_t hi;
+        if (b + 1 < B) {
+            hi = (uint64_t)nl | ((uint64_t)nh << 32);
+            if (hi > 0 && cdf[hi - 1] == ((b + 1) << s)) --hi;
+        } else {
+            hi = K - 1;                       // the last bucket ends at total - 1
+        }
         const uint64_t lo_t = b << s;
-        const uint64_t hi_t = min(lo_t + ((1ull << s) - 1ull), total - 1);
-        const uint64_t lo = first_above(cdf, K, lo_t);
-        const uint64_t hi = first_above(cdf, K, hi_t);
         uint4 g;
         if (hi == lo) {
             g.x = vid[lo]; g.y = g.x; g.z = 0xFFFFFFFFu; g.w = 0xFFFFFFFFu;

@@ -39,7 +39,7 @@ OPS_END = 35              # collimator, detector bin, window, bookkeeping
 # counters read for a plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); keyed
 # by a hash of the kernel sources so a changed kernel reports null.
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
-TRAFFIC_KIB = {"b645066227e343da": {"fetch": 4688408.5625, "write": 5326.25}}
+TRAFFIC_KIB = {"601dcc218ff9024e": {"fetch": 4687977.8125, "write": 5326.28125}}
 
 
 def kernel_source_hash() -> str:
@@ -98,8 +98,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="time only the headline workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 256^3 / 1e9-history form")
     ap.add_argument("--only-form", choices=["forced_detection", "batched"], default=None,
-                    help="time only this side form (forced detection and its convolution-based "
-                         "form) and print its record; for profiling")
+                    help="time only this side form (forced_detection: forced detection and "
+                         "its convolution-based form; batched: the 32-thorax graph) and print "
+                         "its record; for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()

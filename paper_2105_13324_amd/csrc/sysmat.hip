@@ -279,41 +279,50 @@ __global__ __launch_bounds__(64) void k_sort_rows_wave(uint64_t n_rows, const ui
     __shared__ uint32_t key[ROW_LDS];
     __shared__ int64_t wt[ROW_LDS];
     const uint32_t lane = threadIdx.x;
-    for (uint64_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
-        const uint64_t b = start[r], n = start[r + 1] - b;
-        if (n <= ROW_SHORT || n > ROW_LDS) continue;
-        uint32_t m = 1;
-        while (m < n) m <<= 1;
-        for (uint32_t i = lane; i < m; i += 64) {
-            key[i] = i < n ? tmp_col[b + i] : 0xFFFFFFFFu;
-            wt[i] = i < n ? tmp_w[b + i] : 0;
+    // 64 rows are screened at once (a lane each); the wavefront then sorts
+    // the ones of this length class in turn
+    for (uint64_t r0 = (uint64_t)blockIdx.x * 64; r0 < n_rows; r0 += (uint64_t)gridDim.x * 64) {
+        bool need = false;
+        if (r0 + lane < n_rows) {
+            const uint64_t len = start[r0 + lane + 1] - start[r0 + lane];
+            need = len > ROW_SHORT && len <= ROW_LDS;
         }
-        __syncthreads();
-        for (uint32_t k = 2; k <= m; k <<= 1) {
-            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = lane; i < m; i += 64) {
-                    const uint32_t x = i ^ j;
-                    if (x > i) {
-                        const bool up = (i & k) == 0;
-                        const uint32_t ki = key[i], kx = key[x];
-                        if ((ki > kx) == up) {
-                            key[i] = kx; key[x] = ki;
-                            const int64_t t = wt[i]; wt[i] = wt[x]; wt[x] = t;
+        for (uint64_t todo = __ballot(need); todo != 0; todo &= todo - 1) {
+            const uint64_t r = r0 + (uint64_t)(__ffsll((unsigned long long)todo) - 1);
+            const uint64_t b = start[r], n = start[r + 1] - b;
+            uint32_t m = 1;
+            while (m < n) m <<= 1;
+            for (uint32_t i = lane; i < m; i += 64) {
+                key[i] = i < n ? tmp_col[b + i] : 0xFFFFFFFFu;
+                wt[i] = i < n ? tmp_w[b + i] : 0;
+            }
+            __syncthreads();
+            for (uint32_t k = 2; k <= m; k <<= 1) {
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    for (uint32_t i = lane; i < m; i += 64) {
+                        const uint32_t x = i ^ j;
+                        if (x > i) {
+                            const bool up = (i & k) == 0;
+                            const uint32_t ki = key[i], kx = key[x];
+                            if ((ki > kx) == up) {
+                                key[i] = kx; key[x] = ki;
+                                const int64_t t = wt[i]; wt[i] = wt[x]; wt[x] = t;
+                            }
                         }
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
+            uint32_t d = 0;
+            for (uint32_t i = lane; i < n; i += 64) {
+                tmp_col[b + i] = key[i];
+                tmp_w[b + i] = wt[i];
+                d += (i == 0 || key[i] != key[i - 1]);
+            }
+            for (int o = 32; o > 0; o >>= 1) d += (uint32_t)__shfl_xor((int)d, o, 64);
+            if (lane == 0) row_nnz[r] = d;
+            __syncthreads();
         }
-        uint32_t d = 0;
-        for (uint32_t i = lane; i < n; i += 64) {
-            tmp_col[b + i] = key[i];
-            tmp_w[b + i] = wt[i];
-            d += (i == 0 || key[i] != key[i - 1]);
-        }
-        for (int o = 32; o > 0; o >>= 1) d += (uint32_t)__shfl_xor((int)d, o, 64);
-        if (lane == 0) row_nnz[r] = d;
-        __syncthreads();
     }
 }
 
@@ -611,7 +620,7 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
         if (e != hipSuccess) return e;
         k_scatter<<<ge, T256, 0, s>>>(a, transpose, start, fill, tmp_col, tmp_w);
         k_sort_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
-        k_sort_rows_wave<<<(int)std::min<uint64_t>(n_rows ? n_rows : 1, 16384), 64, 0, s>>>(
+        k_sort_rows_wave<<<(int)std::min<uint64_t>(n_rows ? (n_rows + 63) / 64 : 1, 16384), 64, 0, s>>>(
             n_rows, start, tmp_col, tmp_w, row_nnz);
         e = exclusive_scan(row_nnz, n_rows, rowptr_u, bsum, s);
         if (e != hipSuccess) return e;

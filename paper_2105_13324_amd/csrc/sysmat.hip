@@ -233,20 +233,24 @@ __device__ inline void sift(uint32_t* col, int64_t* w, uint64_t i, uint64_t n) {
 
 constexpr uint64_t ROW_SHORT = 32;      // rows up to this length: one thread, insertion sort
 constexpr uint64_t ROW_LDS = 4096;      // rows up to this length: one wavefront, LDS bitonic sort
+constexpr uint64_t ROW_BIG = 8192;      // rows up to this length: one 256-thread block, LDS bitonic sort
 
 // sort each row's (column, weight) pairs by column and count the distinct
-// columns: short rows (analog lists) by insertion sort here, rows longer than
-// ROW_LDS by heapsort here; the rows between (forced-detection lists) are
-// left to k_sort_rows_wave
+// columns: short rows (analog lists) by insertion sort here; longer rows are
+// left to k_sort_rows_wave and k_sort_rows_block.  With heap = 1 the kernel
+// instead heapsorts the rows k_sort_rows_block could not take (marked
+// ROW_OVERFLOW in row_nnz).
+constexpr uint32_t ROW_OVERFLOW = 0xFFFFFFFFu;
+
 __global__ __launch_bounds__(T256) void k_sort_rows(uint64_t n_rows, const uint64_t* start,
                                                     uint32_t* tmp_col, int64_t* tmp_w,
-                                                    uint32_t* row_nnz) {
+                                                    uint32_t* row_nnz, int heap) {
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
          r += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t b = start[r], e = start[r + 1], n = e - b;
         uint32_t* col = tmp_col + b;
         int64_t* w = tmp_w + b;
-        if (n > ROW_SHORT && n <= ROW_LDS) continue;
+        if (heap ? row_nnz[r] != ROW_OVERFLOW : n > ROW_SHORT) continue;
         if (n <= ROW_SHORT) {
             for (uint64_t i = 1; i < n; ++i) {
                 const uint32_t v = col[i];
@@ -270,25 +274,32 @@ __global__ __launch_bounds__(T256) void k_sort_rows(uint64_t n_rows, const uint6
     }
 }
 
-// one wavefront per row of ROW_SHORT < length <= ROW_LDS: bitonic sort of the
-// (column, weight) pairs in LDS, padded to a power of two, then the count of
-// distinct columns
+// one wavefront per row of ROW_SHORT < length <= 1024 (two classes):
+// bitonic sort of the (column, weight) pairs in LDS, padded to a power of
+// two, then the count of distinct columns
+// Instantiated per length class (LO, HI] so that the LDS a wavefront holds
+// (12 B per entry) fits the class and short-row classes keep many
+// wavefronts resident per CU.
+template <uint32_t LO, uint32_t HI>
 __global__ __launch_bounds__(64) void k_sort_rows_wave(uint64_t n_rows, const uint64_t* start,
                                                        uint32_t* tmp_col, int64_t* tmp_w,
                                                        uint32_t* row_nnz) {
-    __shared__ uint32_t key[ROW_LDS];
-    __shared__ int64_t wt[ROW_LDS];
+    __shared__ uint32_t key[HI];
+    __shared__ int64_t wt[HI];
     const uint32_t lane = threadIdx.x;
-    // 64 rows are screened at once (a lane each); the wavefront then sorts
-    // the ones of this length class in turn
-    for (uint64_t r0 = (uint64_t)blockIdx.x * 64; r0 < n_rows; r0 += (uint64_t)gridDim.x * 64) {
+    // 64 rows are screened at once (a lane each; rows gridDim.x apart, so
+    // runs of long rows spread over the grid); the wavefront then sorts the
+    // ones of this length class in turn
+    const uint64_t stride = gridDim.x;
+    for (uint64_t r0 = blockIdx.x; r0 < n_rows; r0 += stride * 64) {
         bool need = false;
-        if (r0 + lane < n_rows) {
-            const uint64_t len = start[r0 + lane + 1] - start[r0 + lane];
-            need = len > ROW_SHORT && len <= ROW_LDS;
+        const uint64_t rl = r0 + lane * stride;
+        if (rl < n_rows) {
+            const uint64_t len = start[rl + 1] - start[rl];
+            need = len > LO && len <= HI;
         }
         for (uint64_t todo = __ballot(need); todo != 0; todo &= todo - 1) {
-            const uint64_t r = r0 + (uint64_t)(__ffsll((unsigned long long)todo) - 1);
+            const uint64_t r = r0 + (uint64_t)(__ffsll((unsigned long long)todo) - 1) * stride;
             const uint64_t b = start[r], n = start[r + 1] - b;
             uint32_t m = 1;
             while (m < n) m <<= 1;
@@ -321,6 +332,124 @@ __global__ __launch_bounds__(64) void k_sort_rows_wave(uint64_t n_rows, const ui
             }
             for (int o = 32; o > 0; o >>= 1) d += (uint32_t)__shfl_xor((int)d, o, 64);
             if (lane == 0) row_nnz[r] = d;
+            __syncthreads();
+        }
+    }
+}
+
+// one 256-thread block per row longer than 1024 entries (the dense voxel
+// rows of forced-detection matrices), in 48 KB of LDS up to ROW_LDS entries
+// and 96 KB up to ROW_BIG: the same bitonic sort.  Longer rows: their
+// entries are first summed per
+// column in an LDS hash table of ROW_BIG slots (64-bit integer adds: exact,
+// so the order does not matter), the table is sorted, and the row is
+// rewritten as its distinct columns with their sums followed by copies of
+// the last column with weight 0 (which the merge adds as 0); a row with more
+// than ROW_BIG distinct columns is marked ROW_OVERFLOW for the heapsort.  A
+// block screens 256 rows per step (rows gridDim.x apart), lists the long
+// ones and sorts them in turn.
+// Instantiated per class: rows of (LO, CAP] entries are sorted in CAP
+// slots; with AGG also every longer row goes through the column sums.
+__device__ inline uint32_t col_hash(uint32_t c) { return (c * 2654435761u) >> 19; }   // 13 bits
+
+template <uint32_t LO, uint32_t CAP, bool AGG>
+__global__ __launch_bounds__(T256) void k_sort_rows_block(uint64_t n_rows, const uint64_t* start,
+                                                          uint32_t* tmp_col, int64_t* tmp_w,
+                                                          uint32_t* row_nnz) {
+    static_assert(!AGG || CAP == 8192, "col_hash gives 13 bits");
+    __shared__ uint32_t key[CAP];
+    __shared__ int64_t wt[CAP];
+    __shared__ uint32_t list[T256];
+    __shared__ uint32_t n_list, n_distinct, overflow;
+    const uint32_t t = threadIdx.x;
+    const uint64_t stride = gridDim.x;
+    for (uint64_t r0 = blockIdx.x; r0 < n_rows; r0 += stride * T256) {
+        if (t == 0) n_list = 0;
+        __syncthreads();
+        const uint64_t rl = r0 + t * stride;
+        if (rl < n_rows) {
+            const uint64_t len = start[rl + 1] - start[rl];
+            if (len > LO && (AGG || len <= CAP)) list[atomicAdd(&n_list, 1u)] = t;
+        }
+        __syncthreads();
+        const uint32_t nl = n_list;
+        for (uint32_t q = 0; q < nl; ++q) {
+            const uint64_t r = r0 + (uint64_t)list[q] * stride;
+            const uint64_t b = start[r], n = start[r + 1] - b;
+            const bool agg = AGG && n > CAP;
+            uint32_t m = CAP;
+            if (!agg) {
+                m = 1;
+                while (m < n) m <<= 1;
+                for (uint32_t i = t; i < m; i += T256) {
+                    key[i] = i < n ? tmp_col[b + i] : 0xFFFFFFFFu;
+                    wt[i] = i < n ? tmp_w[b + i] : 0;
+                }
+            } else {
+                for (uint32_t i = t; i < CAP; i += T256) { key[i] = 0xFFFFFFFFu; wt[i] = 0; }
+            }
+            if (t == 0) { n_distinct = 0; overflow = 0; }
+            __syncthreads();
+            if (agg) {
+                for (uint64_t i = t; i < n; i += T256) {
+                    const uint32_t c = tmp_col[b + i];
+                    const int64_t w = tmp_w[b + i];
+                    uint32_t h = col_hash(c);
+                    uint32_t probe = 0;
+                    for (; probe < CAP; ++probe, h = (h + 1) & (CAP - 1)) {
+                        const uint32_t cur = atomicCAS(&key[h], 0xFFFFFFFFu, c);
+                        if (cur == 0xFFFFFFFFu || cur == c) {
+                            atomicAdd((unsigned long long*)&wt[h], (unsigned long long)w);
+                            break;
+                        }
+                    }
+                    if (probe == CAP) overflow = 1;
+                }
+                __syncthreads();
+                if (overflow) {                   // left to the heapsort
+                    if (t == 0) row_nnz[r] = ROW_OVERFLOW;
+                    __syncthreads();
+                    continue;
+                }
+            }
+            for (uint32_t k = 2; k <= m; k <<= 1) {
+                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                    for (uint32_t i = t; i < m; i += T256) {
+                        const uint32_t x = i ^ j;
+                        if (x > i) {
+                            const bool up = (i & k) == 0;
+                            const uint32_t ki = key[i], kx = key[x];
+                            if ((ki > kx) == up) {
+                                key[i] = kx; key[x] = ki;
+                                const int64_t tw = wt[i]; wt[i] = wt[x]; wt[x] = tw;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            if (!agg) {
+                uint32_t d = 0;
+                for (uint32_t i = t; i < n; i += T256) {
+                    tmp_col[b + i] = key[i];
+                    tmp_w[b + i] = wt[i];
+                    d += (i == 0 || key[i] != key[i - 1]);
+                }
+                atomicAdd(&n_distinct, d);
+            } else {
+                // distinct columns: the slots before the first empty one
+                uint32_t d = 0;
+                for (uint32_t i = t; i < CAP; i += T256) d += key[i] != 0xFFFFFFFFu;
+                atomicAdd(&n_distinct, d);
+                __syncthreads();
+                const uint32_t nd = n_distinct;
+                for (uint64_t i = t; i < n; i += T256) {
+                    tmp_col[b + i] = i < nd ? key[i] : key[nd - 1];
+                    tmp_w[b + i] = i < nd ? wt[i] : 0;
+                }
+            }
+            __syncthreads();
+            if (t == 0) row_nnz[r] = n_distinct;
             __syncthreads();
         }
     }
@@ -619,9 +748,15 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
         hipError_t e = exclusive_scan(cnt, n_rows, start, bsum, s);
         if (e != hipSuccess) return e;
         k_scatter<<<ge, T256, 0, s>>>(a, transpose, start, fill, tmp_col, tmp_w);
-        k_sort_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
-        k_sort_rows_wave<<<(int)std::min<uint64_t>(n_rows ? (n_rows + 63) / 64 : 1, 16384), 64, 0, s>>>(
-            n_rows, start, tmp_col, tmp_w, row_nnz);
+        k_sort_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz, 0);
+        const int gw = (int)std::min<uint64_t>(n_rows ? (n_rows + 63) / 64 : 1, 16384);
+        k_sort_rows_wave<ROW_SHORT, 256><<<gw, 64, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
+        k_sort_rows_wave<256, 1024><<<gw, 64, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
+        // rows of 1025..4096 entries: one 256-thread block each (below)
+        const int gb = (int)std::min<uint64_t>(n_rows ? (n_rows + T256 - 1) / T256 : 1, 4096);
+        k_sort_rows_block<1024, ROW_LDS, false><<<gb, T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
+        k_sort_rows_block<ROW_LDS, ROW_BIG, true><<<gb, T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
+        k_sort_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz, 1);
         e = exclusive_scan(row_nnz, n_rows, rowptr_u, bsum, s);
         if (e != hipSuccess) return e;
         k_emit_rows<<<grid_for(n_rows + 1, T256, 8192), T256, 0, s>>>(

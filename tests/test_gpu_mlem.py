@@ -239,3 +239,67 @@ def test_dual_matrix_and_scatter_forms_thorax():
         rl2 = np.linalg.norm(g - o) / np.linalg.norm(o)
         say(f"{name}: rel L2 {rl2:.2e}, flipped {n_flip}/{n_tal}")
         assert rl2 <= 1e-4 + 3 * np.sqrt(n_flip / max(n_tal, 1))
+
+
+def test_system_matrix_row_length_classes():
+    """A hand-made weighted event list whose voxel rows span every sorting
+    path of the response-matrix build (short rows, one wavefront up to 4096
+    entries, one block up to 8192, LDS column sums beyond, heapsort for a
+    row of more than 8192 distinct columns) and whose bin rows repeat
+    columns: the CSR matches the oracle's matrix from the same contributions
+    (sums of Q31.32 weights, exact before the FP32 store)."""
+    import types
+    import torch
+    mc = _mc()
+    p = phantoms.thorax_problem("rowlen", 32, 1.2, 2, 4, 180.0, 64, 0.6, 4_000_000, image_factor=4)
+    p = p.with_(activity=np.ones_like(p.activity))
+    rng = np.random.Generator(np.random.PCG64(77))
+    per = p.nv * p.nu
+    n_bins_cls = p.n_views * 2 * per
+    f, nx = p.image_factor, p.nx
+    # phantom voxels inside image voxels 0, 1, 2 and a few others
+    def phantom_voxel(img):
+        mx, my = nx // f, p.ny // f
+        ix, iy, iz = img % mx, (img // mx) % my, img // (mx * my)
+        return ((iz * f) * p.ny + iy * f) * nx + ix * f
+    lengths = {0: 3000, 1: 6000, 2: 20000, 3: 20, 5: 1, 100: 700, 200: 12000}
+    emit, bins = [], []
+    for img, n in lengths.items():
+        emit.append(np.full(n, phantom_voxel(img), dtype=np.uint32))
+        if img == 2:      # many repeats: 20000 entries over 3000 bins
+            b = rng.choice(n_bins_cls, size=3000, replace=False)[rng.integers(0, 3000, size=n)]
+        elif img == 200:  # 12000 distinct bin rows: more than the LDS table holds
+            rowsel = rng.choice(n_bins_cls // 2, size=n, replace=False)
+            b = (rowsel // per) * 2 * per + rng.integers(0, 2, size=n) * per + rowsel % per
+        else:
+            b = rng.integers(0, n_bins_cls, size=n)
+        bins.append(np.asarray(b).astype(np.uint32))
+    emit = np.concatenate(emit)
+    bins = np.concatenate(bins)
+    w = rng.integers(1, 1 << 34, size=len(bins)).astype(np.int64)
+    perm = rng.permutation(len(bins))
+    emit, bins, w = emit[perm], bins[perm], w[perm]
+    ev = np.zeros(len(bins), dtype=mc.EVENT_DTYPE)
+    ev["work"] = np.arange(len(bins))
+    ev["bin"], ev["emit_voxel"], ev["weight"] = bins, emit, w
+    cap = len(ev)
+    raw = torch.from_numpy(ev.view(np.int64).reshape(cap, 3).copy()).cuda()
+    sim = types.SimpleNamespace(events=raw, event_capacity=cap,
+                                n_events=torch.tensor([cap], dtype=torch.int64, device="cuda"))
+    m = mc.system_matrix(mc.to_device(p), sim)
+    Tg = m.to_scipy().astype(np.float64)
+    mx = nx // f
+    img_of = lambda v: ((v % nx) // f) + mx * (((v // nx) % p.ny) // f + (p.ny // f) * ((v // (nx * p.ny)) // f))
+    To, Po, _ = oracle.system_matrix(p, img_of(emit.astype(np.int64)), bins.astype(np.int64),
+                                     trip_w=w.astype(np.float64) / 2.0 ** 32)
+    assert Tg.nnz == To.nnz
+    Tt = m.to_scipy(transpose=True).astype(np.float64)
+    assert abs(Tt - To.T.tocsr()).max() <= 1e-6 * abs(To).max()
+    d = abs(Tg - To)
+    assert d.max() <= 1e-6 * abs(To).max()
+    np.testing.assert_allclose(m.proj.cpu().numpy(), Po, rtol=1e-6)
+    rows = np.diff(m.Tt_rowptr.cpu().numpy())
+    say(f"voxel row nnz: {[int(rows[k]) for k in lengths]}")
+    for img, n in lengths.items():
+        assert rows[img] == len(np.unique(bins[emit == phantom_voxel(img)] // (2 * per) * per
+                                          + bins[emit == phantom_voxel(img)] % per))

@@ -469,6 +469,7 @@ __global__ __launch_bounds__(T256) void k_emit_rows(SysArgs a, int transpose, ui
         rowptr[r] = (int64_t)rowptr_u[r];
         if (r == n_rows) continue;
         const uint64_t b = start[r], e = start[r + 1];
+        if (e - b > ROW_SHORT) continue;          // k_emit_rows_wave
         uint64_t o = rowptr_u[r];
         if (!transpose && proj) {
             long long tot = 0;
@@ -490,6 +491,64 @@ __global__ __launch_bounds__(T256) void k_emit_rows(SysArgs a, int transpose, ui
             val[o] = (float)((double)cw * 0x1p-32 / n_i);
             ++o;
             i = j;
+        }
+    }
+}
+
+
+// The same for rows longer than ROW_SHORT, one wavefront per row: the lanes
+// take 64 consecutive entries at a time, each entry that starts a run of
+// equal columns gets its output slot from a ballot and sums its run (runs
+// are short), so the reads are coalesced.  Rows are screened 64 at a time,
+// gridDim.x apart.
+__global__ __launch_bounds__(64) void k_emit_rows_wave(SysArgs a, int transpose, uint64_t n_rows,
+                                                       const uint64_t* start, const uint32_t* tmp_col,
+                                                       const int64_t* tmp_w, const uint64_t* rowptr_u,
+                                                       int32_t* col, float* val,
+                                                       const unsigned long long* a_img,
+                                                       const unsigned long long* total_p, float* proj) {
+    const double total = (double)*total_p;
+    const uint32_t lane = threadIdx.x;
+    const uint64_t lane_lt = (1ull << lane) - 1ull;
+    const uint64_t stride = gridDim.x;
+    for (uint64_t r0 = blockIdx.x; r0 < n_rows; r0 += stride * 64) {
+        bool need = false;
+        const uint64_t rl = r0 + lane * stride;
+        if (rl < n_rows) need = start[rl + 1] - start[rl] > ROW_SHORT;
+        for (uint64_t todo = __ballot(need); todo != 0; todo &= todo - 1) {
+            const uint64_t r = r0 + (uint64_t)(__ffsll((unsigned long long)todo) - 1) * stride;
+            const uint64_t b = start[r], e = start[r + 1];
+            uint64_t o = rowptr_u[r];
+            long long tot = 0;
+            for (uint64_t c0 = b; c0 < e; c0 += 64) {
+                const uint64_t i = c0 + lane;
+                const bool valid = i < e;
+                uint32_t c = 0;
+                bool first = false;
+                if (valid) {
+                    c = tmp_col[i];
+                    tot += tmp_w[i];
+                    first = i == b || tmp_col[i - 1] != c;
+                }
+                const uint64_t m = __ballot(first);
+                if (first) {
+                    long long cw = 0;
+                    for (uint64_t j = i; j < e && tmp_col[j] == c; ++j) cw += tmp_w[j];
+                    const uint32_t bin = transpose ? c : (uint32_t)r;
+                    const uint32_t img = transpose ? (uint32_t)r : c;
+                    const uint64_t view = bin / a.nv_nu;
+                    const double n_view = (double)(a.q_per_view + (view < a.r_extra ? 1u : 0u));
+                    const double n_i = n_view * (double)a_img[img] / total;
+                    const uint64_t slot = o + (uint64_t)__popcll(m & lane_lt);
+                    col[slot] = (int32_t)c;
+                    val[slot] = (float)((double)cw * 0x1p-32 / n_i);
+                }
+                o += (uint64_t)__popcll(m);
+            }
+            if (!transpose && proj) {
+                for (int k = 32; k > 0; k >>= 1) tot += __shfl_xor(tot, k, 64);
+                if (lane == 0) proj[r] = (float)((double)tot * 0x1p-32);
+            }
         }
     }
 }
@@ -763,6 +822,9 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
             a, transpose, n_rows, start, tmp_col, tmp_w, rowptr_u, transpose ? Tt_rp : T_rp,
             transpose ? Tt_col : T_col, transpose ? Tt_val : T_val, a_img, total,
             transpose ? nullptr : proj);
+        k_emit_rows_wave<<<gw, 64, 0, s>>>(a, transpose, n_rows, start, tmp_col, tmp_w, rowptr_u,
+                                           transpose ? Tt_col : T_col, transpose ? Tt_val : T_val,
+                                           a_img, total, transpose ? nullptr : proj);
     }
     return hipGetLastError();
 }

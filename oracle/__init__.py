@@ -54,6 +54,7 @@ class _Problem(C.Structure):
         ("n_threads", C.c_uint32),
         ("activity_prev", C.POINTER(C.c_uint32)),
         ("e0_kev", C.c_double),
+        ("vr_flags", C.c_int32), ("pad", C.c_int32), ("vr_cone_rad", C.c_double),
     ]
 
 
@@ -135,7 +136,9 @@ def _make_problem(prob, n_threads: int = 0):
                  history_offset=prob.history_offset, history_count=prob.history_count,
                  seed=prob.seed, problem_id=prob.problem_id, max_steps=prob.max_steps,
                  n_threads=n_threads, activity_prev=_ptr(prev, C.c_uint32),
-                 e0_kev=float(getattr(prob, "e0_kev", 140.0)))
+                 e0_kev=float(getattr(prob, "e0_kev", 140.0)),
+                 vr_flags=int(getattr(prob, "vr_flags", 0)),
+                 vr_cone_rad=float(getattr(prob, "vr_cone_rad", 0.0)))
     return p, (mu, act, ang, prev)
 
 

@@ -132,6 +132,9 @@ typedef struct {
     uint32_t seed, problem_id, max_steps, n_threads;
     const uint32_t* activity_prev;   // nullable: the source is activity - activity_prev
     double e0_kev;                   // emission line energy (0: 140 keV)
+    int32_t vr_flags;                // VR_FORCED_DIRECTION | VR_FORCED_INTERACTION
+    int32_t pad;
+    double vr_cone_rad;              // forced direction: cone half-angle about the view normal
 } orc_problem;
 
 typedef struct {
@@ -191,10 +194,21 @@ double source_sign(const orc_problem* p, int32_t vox) {
 // given at 140 keV and g(E) scales it to any energy.
 double emission_energy(const orc_problem* p) { return p->e0_kev > 0.0 ? p->e0_kev : E0_KEV; }
 
+// Variance reduction by weighting (Sec. 5.2).  Forced direction: every
+// photon leaves in the cone of half-angle beta about the view normal, with
+// weight Omega / (4 pi) = (1 - cos beta) / 2 (unbiased for the photons that
+// start inside the cone; the scatter of those emitted outside it is left
+// out).  Forced interaction: a real collision is always a Compton scatter and
+// the weight takes the factor sigma_C / sigma_tot = 1 - p_pe(E).  A tallied
+// photon adds its weight (tally) and its squared weight (tally_sq).
+const int32_t VR_FORCED_DIRECTION = 1, VR_FORCED_INTERACTION = 2;
+
 bool build_setup(const orc_problem* p, Setup& s) {
     s.p = p;
     const double e0 = emission_energy(p);
     if (!(e0 >= p->e_cut_kev && e0 <= 500.0)) return false;
+    if (p->vr_flags < 0 || p->vr_flags > 3) return false;
+    if ((p->vr_flags & VR_FORCED_DIRECTION) && !(p->vr_cone_rad > 0.0 && p->vr_cone_rad <= PI)) return false;
     const size_t nvox = (size_t)p->nx * p->ny * p->nz;
     s.L[0] = p->nx * p->voxel_cm; s.L[1] = p->ny * p->voxel_cm; s.L[2] = p->nz * p->voxel_cm;
     for (int a = 0; a < 3; ++a) s.H[a] = 0.5 * s.L[a];
@@ -269,6 +283,7 @@ struct History {
             n_kahn = 0, emit_voxel = -1, cls = 0;
     double e = E0_KEV, dep = 0.0, esc = 0.0, capped = 0.0;
     double sign = 1.0;           // of the emitting voxel's activity (signed source)
+    double w = 1.0;              // statistical weight (forced direction / interaction)
     // path (only filled when requested)
     std::vector<Vertex> verts;   // emission point, then each Compton vertex
     double dfinal[3] = {0, 0, 0};
@@ -516,10 +531,20 @@ void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, Hi
         x[1] = -s.H[1] + (iy + uniform(w0.r[3])) * p->voxel_cm;
         x[2] = -s.H[2] + (iz + uniform(w1.r[0])) * p->voxel_cm;
     }
-    const double cos_t = 2.0 * uniform(w1.r[1]) - 1.0;
-    const double phi = 2.0 * PI * uniform(w1.r[2]);
-    const double sin_t = std::sqrt(std::max(0.0, 1.0 - cos_t * cos_t));
-    double d[3] = {sin_t * std::cos(phi), sin_t * std::sin(phi), cos_t};
+    double d[3];
+    if (p->vr_flags & VR_FORCED_DIRECTION) {
+        // forced direction: uniform in the cone of half-angle beta about the
+        // view normal (the same two words), weight Omega / (4 pi)
+        const double cb = std::cos(p->vr_cone_rad);
+        d[0] = s.nvec_x[view]; d[1] = s.nvec_y[view]; d[2] = 0.0;
+        rotate(d, 1.0 - uniform(w1.r[1]) * (1.0 - cb), 2.0 * PI * uniform(w1.r[2]));
+        h.w = 0.5 * (1.0 - cb);
+    } else {
+        const double cos_t = 2.0 * uniform(w1.r[1]) - 1.0;
+        const double phi = 2.0 * PI * uniform(w1.r[2]);
+        const double sin_t = std::sqrt(std::max(0.0, 1.0 - cos_t * cos_t));
+        d[0] = sin_t * std::cos(phi); d[1] = sin_t * std::sin(phi); d[2] = cos_t;
+    }
     double e = emission_energy(p);
     double mu_max = s.mu_hat * s.xs.g(e);
     double p_pe = s.xs.p_pe(e);
@@ -570,7 +595,9 @@ void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, Hi
         if ((w.r[1] >> 8) >= s.Q[v]) continue;           // virtual collision
         h.n_real++;
         if (fd) fd_score(s, view, hist, n, x, d, e, 1, *fd);
-        if (uniform(w.r[2]) < p_pe) {                     // photoelectric absorption
+        if (p->vr_flags & VR_FORCED_INTERACTION) {
+            h.w *= 1.0 - p_pe;                            // forced interaction: always Compton
+        } else if (uniform(w.r[2]) < p_pe) {              // photoelectric absorption
             h.dep += e; h.fate = ABSORBED; break;
         }
         // Compton: Kahn's sampler for x = E/E' on [1, 1+2k].
@@ -650,7 +677,7 @@ void accumulate(const orc_problem* p, const History& h, Acc& a, bool want_tally,
     a.n_tent += h.n_tent; a.n_real += h.n_real; a.n_kahn += h.n_kahn; a.n_hist++;
     if (h.fate == TALLIED) {
         const size_t b = bin_index(p, h.view, h.cls, h.iv, h.iu);
-        if (want_tally) { a.tally[b] += h.sign; a.tally_sq[b] += 1.0; }
+        if (want_tally) { a.tally[b] += h.sign * h.w; a.tally_sq[b] += h.w * h.w; }
         if (want_trip) {
             a.trip_i.push_back(image_voxel(p, h.emit_voxel));
             a.trip_j.push_back((int64_t)b);
@@ -826,6 +853,7 @@ int orc_simulate_fd(const orc_problem* p, double* tally, double* tally_sq, orc_r
                     int64_t* trip_i, int64_t* trip_j, double* trip_w, int64_t* trip_g,
                     uint64_t trip_cap, uint64_t* n_trip) {
     Setup s;
+    if (p->vr_flags) return -1;          // forced detection runs the analog histories
     if (!build_setup(p, s)) return -1;
     const size_t nbins = (size_t)p->n_views * 2 * p->nv * p->nu;
     const size_t nt = n_threads_for(p);
@@ -883,6 +911,7 @@ int orc_simulate_fd(const orc_problem* p, double* tally, double* tally_sq, orc_r
 // depth; layers (nullable) [V][L][2][nv][nu] returns the deposits.
 int orc_simulate_cfd(const orc_problem* p, double* tally, double* layers, orc_result* res) {
     Setup s;
+    if (p->vr_flags) return -1;
     if (!build_setup(p, s)) return -1;
     const size_t nbins = (size_t)p->n_views * 2 * p->nv * p->nu;
     const int L = cfd_layers(p);
@@ -1007,7 +1036,7 @@ int orc_adjoint(const orc_problem* p, const double* G, double* grad, int64_t* n_
                 const double* lam, const double* y, double eps, double* fd_out,
                 orc_result* res) {
     Setup s;
-    if (p->activity_prev) return -1;   // the adjoint is of plain (unsigned) sources
+    if (p->activity_prev || p->vr_flags) return -1;   // the adjoint is of plain analog sources
     if (!build_setup(p, s)) return -1;
     const size_t nvox = (size_t)p->nx * p->ny * p->nz;
     const size_t nloss = (size_t)p->n_views * p->nv * p->nu;

@@ -66,6 +66,10 @@ class Problem:
     # difference activity - activity_prev (signed)
     activity_prev: Optional[np.ndarray] = None
     e0_kev: float = 140.0     # emission line energy
+    # variance reduction by weighting, for the oracle (the GPU library takes
+    # these as call options): 1 forced direction, 2 forced interaction
+    vr_flags: int = 0
+    vr_cone_rad: float = 0.0
 
     @property
     def n_views(self) -> int:

@@ -970,3 +970,64 @@ def test_emission_line_limits():
     for bad in (dict(e0_kev=600.0), dict(e0_kev=80.0, e_cut_kev=90.0)):
         with pytest.raises(RuntimeError):
             oracle.simulate(p.with_(**bad))
+
+
+# --- forced direction and forced interaction (Sec. 5.2) ---------------------
+
+def test_forced_direction_vacuum_exact():
+    """Forced direction into the acceptance cone in vacuum: every photon is
+    detected as a primary with weight (1 - cos a)/2, so the tally total is
+    N (1 - cos a) / 2 exactly (the analog geometric efficiency, without
+    noise), and the sum of squared weights N ((1 - cos a)/2)^2."""
+    N = 50_000
+    a = math.radians(3.0)
+    p = phantoms.point_cube_64(N).with_(mu=np.zeros((64, 64, 64), np.float32), accept_half_angle_rad=a,
+                                        vr_flags=1, vr_cone_rad=a)
+    r = oracle.simulate(p)
+    w = 0.5 * (1.0 - math.cos(a))
+    assert r["tally"][0, 0].sum() == pytest.approx(N * w, rel=1e-12)
+    assert r["tally_sq"].sum() == pytest.approx(N * w * w, rel=1e-12)
+    assert r["fates"][5] == N
+
+
+def test_forced_direction_narrow_beam():
+    """In the water cube the weighted primaries estimate 1/2 int exp(-mu h/c)
+    dc over the cone, the analog closed form, to well within its small
+    variance; a wider forcing cone (2 alpha) gives the same expectation."""
+    N = 100_000
+    a = math.radians(2.0)
+    pexp = _cone_primary_prob(a, float(np.float32(0.151)) * 6.4)
+    for beta in (a, 2 * a):
+        p = phantoms.point_cube_64(N).with_(vr_flags=1, vr_cone_rad=beta)
+        r = oracle.simulate(p)
+        est = r["tally"][0, 0].sum() / N
+        w = 0.5 * (1.0 - math.cos(beta))
+        sd = math.sqrt(pexp * w / N)          # binomial in units of the weight
+        assert abs(est - pexp) < 5 * sd + 1e-12, (beta, est, pexp)
+
+
+def test_forced_interaction_unbiased():
+    """Forced interaction replaces photoelectric absorption by the weight
+    factor 1 - p_pe(E): no history is absorbed, and with a large
+    photoelectric share (0.3) the weighted tally per class agrees with
+    analog transport of independent histories within 5 standard errors."""
+    base = phantoms.thorax_problem("fi", 24, 1.6, 2, 8, 180.0, 24, 1.6, 400_000).with_(
+        pe_fraction=0.3, accept_half_angle_rad=math.radians(10.0), e_lo_kev=100.0, e_cut_kev=100.0)
+    fi = oracle.simulate(base.with_(vr_flags=2, seed=31))
+    an = oracle.simulate(base.with_(seed=32))
+    assert fi["fates"][0] == 0
+    for c in range(2):
+        a, b = fi["tally"][:, c].sum(), an["tally"][:, c].sum()
+        se = math.sqrt(fi["tally_sq"][:, c].sum() + an["tally_sq"][:, c].sum())
+        assert abs(a - b) < 5 * se, (c, a, b, se)
+    # the weights are products of (1 - p_pe) factors: below 1, above 0.7^k
+    assert np.all(fi["tally_sq"] <= fi["tally"] + 1e-12)
+
+
+def test_variance_reduction_refused_where_undefined():
+    p = phantoms.point_cube_64(100)
+    for bad in (dict(vr_flags=4), dict(vr_flags=1, vr_cone_rad=0.0)):
+        with pytest.raises(RuntimeError):
+            oracle.simulate(p.with_(**bad))
+    with pytest.raises(RuntimeError):
+        oracle.simulate_fd(p.with_(vr_flags=2))

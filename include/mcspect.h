@@ -145,6 +145,19 @@ typedef struct {
     void* kernel_events[2];     /* optional hipEvent_t pair recorded on the     */
                                 /* stream right before / after the transport    */
                                 /* kernel (NULL: none)                          */
+    int32_t variance_reduction; /* weighted analog transport (Sec. 5.2), bits:  */
+                                /* 1 forced direction: every photon leaves in   */
+                                /* the cone of the half-angle below about the   */
+                                /* view normal (the same two emission words),   */
+                                /* weight (1 - cos) / 2; 2 forced interaction:  */
+                                /* a real collision is always Compton and the   */
+                                /* weight takes 1 - p_pe(E).  Arrivals add     */
+                                /* their weight (Q31.32) to the tally and its   */
+                                /* square (Q11.52) to tally_sq, and events      */
+                                /* carry it.  Not with forced_detection; the    */
+                                /* adjoint rejects it; replay honours it.       */
+    int32_t pad_vr;
+    double forced_direction_half_angle_rad;  /* (0, pi] when bit 1 is set      */
 } mc_options;
 
 /* One tally contribution, as written to the optional event list: a tallied

@@ -65,7 +65,9 @@ class McOptions(C.Structure):
     _fields_ = [("hist_per_lane", C.c_int32), ("block_size", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("brick_log2", C.c_int32),
                 ("threshold_bytes", C.c_int32), ("forced_detection", C.c_int32),
-                ("kernel_events", C.c_void_p * 2)]
+                ("kernel_events", C.c_void_p * 2),
+                ("variance_reduction", C.c_int32), ("pad_vr", C.c_int32),
+                ("forced_direction_half_angle_rad", C.c_double)]
 
 
 EVENT_DTYPE = np.dtype([("work", np.uint64), ("bin", np.uint32), ("emit_voxel", np.uint32),
@@ -213,7 +215,9 @@ def _opts(options: Optional[dict]) -> Optional[McOptions]:
                   blocks_per_cu=int(options.get("blocks_per_cu", 0)),
                   brick_log2=int(options.get("brick_log2", 0)),
                   threshold_bytes=int(options.get("threshold_bytes", 0)),
-                  forced_detection=int(options.get("forced_detection", 0)))
+                  forced_detection=int(options.get("forced_detection", 0)),
+                  variance_reduction=int(options.get("variance_reduction", 0)),
+                  forced_direction_half_angle_rad=float(options.get("forced_direction_half_angle", 0.0)))
     ev = options.get("kernel_events")
     if ev is not None:
         o.kernel_events[0] = ev[0]

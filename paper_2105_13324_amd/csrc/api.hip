@@ -198,6 +198,24 @@ void resolve(const mc_options* opt, int& block, int& hpl, int& bpc, int& brick, 
     }
 }
 
+// Variance-reduction options (weighted analog): flags in [0, 3], a forced-
+// direction cone in (0, pi], and not together with forced detection.
+bool vr_ok(const mc_options* opt) {
+    if (!opt) return true;
+    const int v = opt->variance_reduction;
+    if (v < 0 || v > 3) return false;
+    if ((v & VR_FORCED_DIRECTION) &&
+        !(opt->forced_direction_half_angle_rad > 0.0 && opt->forced_direction_half_angle_rad <= 3.14159265358979323846))
+        return false;
+    if (v && opt->forced_detection) return false;
+    return true;
+}
+float vr_omc(const mc_options* opt) {
+    if (!opt || !(opt->variance_reduction & VR_FORCED_DIRECTION)) return 0.0f;
+    const double h = 0.5 * opt->forced_direction_half_angle_rad;
+    return (float)(2.0 * std::sin(h) * std::sin(h));
+}
+
 bool options_ok(int block, int hpl, int brick, int qbytes) {
     if (block < 64 || block > 256 || block % 64 != 0) return false;
     if (hpl < 1 || hpl > (1 << 20)) return false;
@@ -227,6 +245,7 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
                             size_t workspace_bytes, void* stream) {
     if (!problems || n_problems < 1 || !tally || !fates || !status || !workspace) return MC_EINVAL;
     if (opt && (opt->forced_detection < 0 || opt->forced_detection > 2)) return MC_EINVAL;
+    if (!vr_ok(opt)) return MC_EINVAL;
     const bool cfd = opt && opt->forced_detection == 2;
     if (events && !n_events) return MC_EINVAL;
     if (cfd && events) return MC_EINVAL;   // convolved tallies have no per-copy bins
@@ -266,7 +285,8 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return hip_fail(e);
     const int fd = opt ? opt->forced_detection : 0;
-    if (bpc <= 0) bpc = transport_blocks_per_cu(block, fd);
+    const int vr = opt ? opt->variance_reduction : 0;
+    if (bpc <= 0) bpc = transport_blocks_per_cu(block, fd, vr);
     TransportArgs a;
     a.descs = d_desc;
     a.n_problems = n_problems;
@@ -284,6 +304,8 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     a.n_events = (unsigned long long*)n_events;
     a.status = status;
     a.forced_detection = fd;
+    a.vr_flags = vr;
+    a.vr_omc = vr_omc(opt);
     hipEvent_t ev0 = opt ? (hipEvent_t)opt->kernel_events[0] : nullptr;
     hipEvent_t ev1 = opt ? (hipEvent_t)opt->kernel_events[1] : nullptr;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return hip_fail(e);
@@ -303,7 +325,7 @@ int mc_replay_histories(const mc_problem* problem, const mc_options* opt, const 
     if (!check_problem(*problem)) return MC_EINVAL;
     int block, hpl, bpc, brick, qbytes;
     resolve(opt, block, hpl, bpc, brick, qbytes);
-    if (!options_ok(block, hpl, brick, qbytes)) return MC_EINVAL;
+    if (!options_ok(block, hpl, brick, qbytes) || !vr_ok(opt)) return MC_EINVAL;
     Layout L;
     plan(problem, 1, L);
     if (workspace_bytes < L.total) return MC_ENOMEM;
@@ -313,7 +335,8 @@ int mc_replay_histories(const mc_problem* problem, const mc_options* opt, const 
     const ProbDesc h = host_desc(*problem, ws, L, 0, 0, brick, qbytes);
     hipError_t e = launch_staging(d_desc, h, st);
     if (e != hipSuccess) return hip_fail(e);
-    e = launch_replay(d_desc, views, hists, n, records, status, block, st);
+    e = launch_replay(d_desc, views, hists, n, records, status, block, opt ? opt->variance_reduction : 0,
+                      vr_omc(opt), st);
     if (e != hipSuccess) return hip_fail(e);
     return MC_OK;
 }
@@ -325,7 +348,8 @@ int mc_adjoint_mu(const mc_problem* problem, const mc_options* opt, const double
     if (!problem || !dL_dtally || !dL_dmu || !status || !workspace) return MC_EINVAL;
     if (events && !n_events) return MC_EINVAL;
     if (frac_bits < 0 || frac_bits > 62) return MC_EINVAL;
-    if (opt && opt->forced_detection) return MC_EINVAL;   // adjoint of analog tallies only
+    if (opt && (opt->forced_detection || opt->variance_reduction))
+        return MC_EINVAL;                                  // adjoint of analog tallies only
     if (problem->activity_prev) return MC_EINVAL;         // and of plain sources
     if (!check_problem(*problem)) return MC_EINVAL;
     int block, hpl, bpc, brick, qbytes;

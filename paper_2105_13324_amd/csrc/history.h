@@ -176,6 +176,7 @@ struct Lane {
     uint32_t n, a, phi_word, emit_voxel;
     int n_scatter;
     float x, y, z, dx, dy, dz, e, ln2_mm, p_pe, vc, vs;
+    float w;            // statistical weight (forced direction / interaction)
 };
 
 // Per-lane work counters of a history (replay and adjoint; the transport
@@ -322,7 +323,11 @@ struct Emission {
     uint32_t voxel;
 };
 
-__device__ inline Emission emit_history(const Cst& C, uint32_t hist, uint32_t view) {
+// vr_dir: forced direction (Sec. 5.2): the direction is drawn uniformly in
+// the cone about the view normal with 1 - cos(half-angle) = omc, from the
+// same two words that otherwise give a direction on the sphere.
+__device__ inline Emission emit_history(const Cst& C, uint32_t hist, uint32_t view, bool vr_dir = false,
+                                        float omc = 0.0f) {
     uint32_t a0 = hist, a1 = view, a2 = 0, a3 = 0;
     philox10(a0, a1, a2, a3, C.seed, C.pid);
     uint32_t b0 = hist, b1 = view, b2 = 0, b3 = 1;
@@ -355,6 +360,12 @@ __device__ inline Emission emit_history(const Cst& C, uint32_t hist, uint32_t vi
         e.y = -C.hy + ((float)iy + unif(a3)) * C.vox;
         e.z = -C.hz + ((float)iz + unif(b0)) * C.vox;
     }
+    if (vr_dir) {
+        const float2 vw = ldg(C.views + view);
+        e.dx = vw.x; e.dy = vw.y; e.dz = 0.0f;
+        rotate_dir(e.dx, e.dy, e.dz, fmaf(-unif(b1), omc, 1.0f), unif(b2));
+        return e;
+    }
     const float ct = fmaf(2.0f, unif(b1), -1.0f);
     const float st = sqrtf_hw((1.0f - ct) * (1.0f + ct));
     const float u = unif(b2);
@@ -377,14 +388,17 @@ __device__ inline void begin_history(const Cst& C, Lane& L, uint32_t view, uint3
     L.p_pe = C.p_pe0;
     const float2 cs = ldg(C.views + view);
     L.vc = cs.x; L.vs = cs.y;
+    L.w = 1.0f;
 }
 
 // One iteration of a lane's history (tentative collision or Kahn attempt)
 // given its Philox words.  Returns the fate when the history ends (iu/iv set
 // for escapes), else R_RUNNING.  pal: the problem's threshold palette (global,
 // or a copy in LDS), read when C.use_pal.
+// fi: forced interaction (Sec. 5.2): a real collision is always a Compton
+// scatter and the weight takes the factor 1 - p_pe(E).
 __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32_t w0, uint32_t w1,
-                              uint32_t w2, uint32_t w3, Acc& A, int& iu, int& iv) {
+                              uint32_t w2, uint32_t w3, Acc& A, int& iu, int& iv, bool fi = false) {
     if (L.state == S_STEP) {
         L.n += 1;
         if (L.n > C.max_steps) {
@@ -415,7 +429,8 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
         L.x = xn; L.y = yn; L.z = zn;
         if ((w1 >> 8) < q) {
             A.n_real++;
-            if (unif(w2) < L.p_pe) return MC_ABSORBED;
+            if (fi) L.w *= 1.0f - L.p_pe;
+            else if (unif(w2) < L.p_pe) return MC_ABSORBED;
             L.phi_word = w3;
             L.a = 0;
             L.state = S_KAHN;

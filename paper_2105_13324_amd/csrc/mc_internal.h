@@ -175,10 +175,14 @@ struct TransportArgs {
     uint64_t event_capacity;
     unsigned long long* n_events;
     int64_t* status;
+    int32_t vr_flags;               // VR_FORCED_DIRECTION | VR_FORCED_INTERACTION (weighted analog)
+    float vr_omc;                   // forced direction: 1 - cos(cone half-angle)
 };
+constexpr int32_t VR_FORCED_DIRECTION = 1, VR_FORCED_INTERACTION = 2;
 hipError_t launch_transport(const TransportArgs& a, int grid, int block, hipStream_t s);
 hipError_t launch_replay(const ProbDesc* d_desc, const int32_t* views, const uint64_t* hists,
-                         int64_t n, mc_record* out, int64_t* status, int block, hipStream_t s);
+                         int64_t n, mc_record* out, int64_t* status, int block, int32_t vr_flags,
+                         float vr_omc, hipStream_t s);
 hipError_t launch_prepare_call(const ProbDesc* descs, int32_t n_problems, uint64_t* work_prefix,
                                CallState* state, int64_t* status, unsigned long long* n_events,
                                int64_t* tally, uint64_t tally_elems, int64_t* tally_sq,
@@ -212,6 +216,6 @@ hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int
                        void* workspace, hipStream_t s);
 
 // Occupancy of the transport kernel (blocks per CU at this block size).
-int transport_blocks_per_cu(int block, int forced_detection);
+int transport_blocks_per_cu(int block, int forced_detection, int vr_flags);
 
 }  // namespace mcs

@@ -167,12 +167,16 @@ __device__ inline void fd_drain(const Cst& C, int p, const FdPoint* ring, uint32
 // converged phase into LDS; idle lanes then start histories from there, so
 // the per-lane loop only alternates tentative collisions and Kahn attempts.
 // MODE 0: analog arrivals into the tally; 1: forced detection (tally);
-// 2: convolution-based forced detection (depth layers).
+// 2: convolution-based forced detection (depth layers); 3: weighted analog
+// (forced direction and / or forced interaction; arrivals add their weight).
 template <int MODE>
 __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restrict__ my,
                                                uint32_t* __restrict__ my_pal,
                                                FdPoint* __restrict__ ring) {
-    constexpr bool FD = MODE != 0;
+    constexpr bool FD = MODE == 1 || MODE == 2;
+    constexpr bool VR = MODE == 3;
+    const bool vr_dir = VR && (T.vr_flags & VR_FORCED_DIRECTION);
+    const bool vr_fi = VR && (T.vr_flags & VR_FORCED_INTERACTION);
     const int lane = threadIdx.x & 63;
     uint32_t fd_head = 0, fd_tail = 0;    // wave-uniform ring cursors (FD)
     const uint64_t lane_lt = (1ull << lane) - 1ull;
@@ -260,7 +264,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                         if (idx < n_rec) {
                             uint64_t v = cur_view, h = cur_hist;
                             advance_cursor(C, v, h, idx, C.n_views);
-                            const Emission e = emit_history(C, (uint32_t)h, (uint32_t)v);
+                            const Emission e = emit_history(C, (uint32_t)h, (uint32_t)v, vr_dir, T.vr_omc);
                             EmitRec r;
                             r.x = e.x; r.y = e.y; r.z = e.z; r.dx = e.dx; r.dy = e.dy; r.dz = e.dz;
                             r.voxel = e.voxel; r.view = (uint32_t)v; r.hist = (uint32_t)h;
@@ -299,6 +303,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             e.x = r.x; e.y = r.y; e.z = r.z; e.dx = r.dx; e.dy = r.dy; e.dz = r.dz;
             e.voxel = r.voxel;
             begin_history(C, L, r.view, r.hist, e);
+            if (vr_dir) L.w = 0.5f * T.vr_omc;     // Omega / (4 pi)
         }
         if (exhausted && __ballot(L.state != S_IDLE) == 0 && (!FD || fd_tail == fd_head)) break;
 
@@ -309,7 +314,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             uint32_t c0 = L.hist, c1 = (uint32_t)L.view, c2, c3;
             counter_of(L, c2, c3);
             philox10(c0, c1, c2, c3, C.seed, C.pid);
-            fate = advance(C, my_pal, L, c0, c1, c2, c3, A, iu, iv);
+            fate = advance(C, my_pal, L, c0, c1, c2, c3, A, iu, iv, vr_fi);
             if (fate != R_RUNNING) {
                 // outgoing energy: escaped, or left at the step cap (rare: booked at once)
                 const float out = ((fate == MC_ABSORBED) | (fate == MC_CUT)) ? 0.0f : L.e;
@@ -359,9 +364,13 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                 const uint32_t bin = (uint32_t)((((uint32_t)L.view * 2u + cls) * (uint32_t)C.nv + iv) *
                                                 (uint32_t)C.nu + iu);
                 const size_t gb = C.tally_offset + bin;
-                const long long w = signed_weight(T.descs + p, L.emit_voxel, 1ll << 32);
+                const long long w = signed_weight(T.descs + p, L.emit_voxel,
+                                                  VR ? __float2ll_rn(L.w * 4294967296.0f) : 1ll << 32);
                 atomicAdd((unsigned long long*)(T.tally + gb), (unsigned long long)w);
-                if (T.tally_sq) atomicAdd((unsigned long long*)(T.tally_sq + gb), 1ull << 32);
+                if (T.tally_sq)   // Q31.32 for unit weights; Q11.52 for weighted arrivals
+                    atomicAdd((unsigned long long*)(T.tally_sq + gb),
+                              VR ? (unsigned long long)__float2ll_rn(L.w * L.w * 4503599627370496.0f)
+                                 : 1ull << 32);
                 if (T.n_events) {
                     const unsigned long long idx = atomicAdd(T.n_events, 1ull);
                     if (T.events && idx < T.event_capacity) {
@@ -394,6 +403,12 @@ __global__ __launch_bounds__(256) void k_transport_fd(TransportArgs T) {
                       ring[threadIdx.x >> 6]);
 }
 
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport_vr(TransportArgs T) {
+    __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
+    __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
+    transport_body<3>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr);
+}
+
 __global__ __launch_bounds__(256) void k_transport_cfd(TransportArgs T) {
     __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
     __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
@@ -406,7 +421,8 @@ __global__ __launch_bounds__(256) void k_transport_cfd(TransportArgs T) {
 __global__ __launch_bounds__(256) void k_replay(const ProbDesc* __restrict__ d,
                                                 const int32_t* __restrict__ views,
                                                 const uint64_t* __restrict__ hists, int64_t n,
-                                                mc_record* __restrict__ out) {
+                                                mc_record* __restrict__ out, int32_t vr_flags,
+                                                float vr_omc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const Cst C = load_cst(d);
     if (i >= n) return;
@@ -421,14 +437,16 @@ __global__ __launch_bounds__(256) void k_replay(const ProbDesc* __restrict__ d,
     mc_record r;
     r.fate = -1; r.iu = -1; r.iv = -1;
     if (C.flags == 0 && view_ok) {
-        const Emission e = emit_history(C, (uint32_t)L.hist, (uint32_t)L.view);
+        const Emission e = emit_history(C, (uint32_t)L.hist, (uint32_t)L.view,
+                                        (vr_flags & VR_FORCED_DIRECTION) != 0, vr_omc);
         begin_history(C, L, (uint32_t)L.view, (uint32_t)L.hist, e);
         for (;;) {
             uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
             counter_of(L, c2, c3);
             philox10(c0, c1, c2, c3, C.seed, C.pid);
             int iu = -1, iv = -1;
-            const int fate = advance(C, C.pal, L, c0, c1, c2, c3, A, iu, iv);
+            const int fate = advance(C, C.pal, L, c0, c1, c2, c3, A, iu, iv,
+                                     (vr_flags & VR_FORCED_INTERACTION) != 0);
             if (fate != R_RUNNING) {
                 r.fate = fate;
                 r.iu = iu;
@@ -527,7 +545,8 @@ hipError_t launch_prepare_call(const ProbDesc* descs, int32_t n_problems, uint64
 }
 
 hipError_t launch_transport(const TransportArgs& a, int grid, int block, hipStream_t s) {
-    if (a.forced_detection == 2) k_transport_cfd<<<grid, block, 0, s>>>(a);
+    if (a.vr_flags) k_transport_vr<<<grid, block, 0, s>>>(a);
+    else if (a.forced_detection == 2) k_transport_cfd<<<grid, block, 0, s>>>(a);
     else if (a.forced_detection) k_transport_fd<<<grid, block, 0, s>>>(a);
     else k_transport<<<grid, block, 0, s>>>(a);
     // without a list the count is informational and cannot overflow
@@ -537,19 +556,22 @@ hipError_t launch_transport(const TransportArgs& a, int grid, int block, hipStre
 }
 
 hipError_t launch_replay(const ProbDesc* d_desc, const int32_t* views, const uint64_t* hists,
-                         int64_t n, mc_record* out, int64_t* status, int block, hipStream_t s) {
+                         int64_t n, mc_record* out, int64_t* status, int block, int32_t vr_flags,
+                         float vr_omc, hipStream_t s) {
     k_zero_status<<<1, 64, 0, s>>>(status);
     if (n > 0) {
         const int64_t g = (n + block - 1) / block;
-        k_replay<<<(int)g, block, 0, s>>>(d_desc, views, hists, n, out);
+        k_replay<<<(int)g, block, 0, s>>>(d_desc, views, hists, n, out, vr_flags, vr_omc);
     }
     k_finalize<<<1, 64, 0, s>>>(d_desc, 1, status, nullptr, 0, nullptr, nullptr);
     return hipGetLastError();
 }
 
-int transport_blocks_per_cu(int block, int forced_detection) {
+int transport_blocks_per_cu(int block, int forced_detection, int vr_flags) {
     int n = 0;
-    const hipError_t e = forced_detection == 2
+    const hipError_t e = vr_flags
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport_vr, block, 0)
+        : forced_detection == 2
         ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport_cfd, block, 0)
         : forced_detection
         ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport_fd, block, 0)

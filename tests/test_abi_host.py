@@ -170,6 +170,20 @@ def test_simulate_rejects_bad_buffers_before_launch():
     q.image_factor = 2
     assert mc._lib.mc_system_matrix(C.byref(q), 8, 8, 16, 3, 8, 8, 8, 8, 8, 8, None, 8,
                                     1 << 30, None) == mc.MC_EINVAL
+    # weighted analog transport: flags 0..3, a forced-direction cone, not
+    # with forced detection, not for the adjoint
+    for kw in (dict(variance_reduction=4), dict(variance_reduction=-1),
+               dict(variance_reduction=1, forced_direction_half_angle_rad=0.0),
+               dict(variance_reduction=1, forced_direction_half_angle_rad=4.0),
+               dict(variance_reduction=2, forced_detection=1)):
+        o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=0, **kw)
+        assert sim(C.byref(p), 1, C.byref(o), 8, None, 8, None, None, None, 0, None, 8, 8, need,
+                   None) == mc.MC_EINVAL, kw
+        assert mc._lib.mc_replay_histories(C.byref(p), C.byref(o), 8, 8, 5, 8, 8, 8, need,
+                                           None) == mc.MC_EINVAL, kw
+    o = mc.McOptions(hist_per_lane=0, block_size=0, blocks_per_cu=0, brick_log2=0, variance_reduction=2)
+    assert mc._lib.mc_adjoint_mu(C.byref(p), C.byref(o), 8, None, None, 0, 8, 40, 8, 8, need,
+                                 None) == mc.MC_EINVAL
     # coarse-grid scatter helpers: sizes are checked before any launch
     ba, ex = mc._lib.mc_block_activity, mc._lib.mc_expand_projection
     assert ba(8, 8, 8, 8, 3, 16, 8, None) == mc.MC_EINVAL       # 8 not a multiple of 3

@@ -280,8 +280,9 @@ def batched_form(mc, torch, steps):
 
 
 def fd_form(mc, torch, steps):
-    """Forced detection and convolution-based forced detection (Sec. 5.2) on
-    the 128^3 thorax, 60 views, 1e7 histories: throughput, and figures of
+    """Forced detection, convolution-based forced detection, forced direction
+    (into the acceptance cone) and forced interaction (Sec. 5.2) on the 128^3
+    thorax, 60 views, 1e7 histories: throughput, and figures of
     merit 1 / (variance per history x time per history) against analog
     transport, for the total window count and for the projection bin by bin
     (variances summed over bins).  Analog variances are binomial, p (1 - p)
@@ -301,9 +302,14 @@ def fd_form(mc, torch, steps):
     nz_an = int((sa.tally != 0).sum().item())
     m = 10 ** 6
     out = {}
-    for name, mode in (("forced_detection", 1), ("convolution_fd", 2)):
-        opt = {"forced_detection": mode}
-        sf = mc.Simulator(dp, want_sq=mode == 1, options=opt)
+    alpha = p.accept_half_angle_rad
+    for name, opt in (("forced_detection", {"forced_detection": 1}),
+                      ("convolution_fd", {"forced_detection": 2}),
+                      ("forced_direction", {"variance_reduction": 1, "forced_direction_half_angle": alpha}),
+                      ("forced_interaction", {"variance_reduction": 2}),
+                      ("forced_direction_and_interaction",
+                       {"variance_reduction": 3, "forced_direction_half_angle": alpha})):
+        sf = mc.Simulator(dp, want_sq=False, options=opt)
         sf.run()
         ms = timed(torch, sf.run, steps)
         sf.check_status()
@@ -334,8 +340,8 @@ def fd_form(mc, torch, steps):
     fd = out.pop("forced_detection")
     fd.update({"analog_ms_per_step": ms_an, "analog_window_count_per_history": p_an,
                "analog_variance_per_history": var_an, "analog_bin_variance_per_history": bins_an,
-               "analog_nonzero_bins": nz_an, "seeds": 16,
-               "convolution_fd": out["convolution_fd"]})
+               "analog_nonzero_bins": nz_an, "seeds": 16})
+    fd.update(out)      # the other estimators, same fields
     return fd
 
 

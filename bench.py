@@ -39,7 +39,7 @@ OPS_END = 35              # collimator, detector bin, window, bookkeeping
 # counters read for a plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); keyed
 # by a hash of the kernel sources so a changed kernel reports null.
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
-TRAFFIC_KIB = {"601dcc218ff9024e": {"fetch": 4687977.8125, "write": 5326.28125}}
+TRAFFIC_KIB = {"9d2b7c2f78f4efd5": {"fetch": 4687792.5625, "write": 5326.4375}}
 
 
 def kernel_source_hash() -> str:

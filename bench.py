@@ -241,10 +241,22 @@ def extra_forms(mc, torch, args):
     adjoint_step()
     ms_fwd = timed(torch, s4.run, steps)
     ms = timed(torch, adjoint_step, steps)
+    timers = [mc.KernelTimer() for _ in range(steps)]
+    for t in timers:
+        s4.run(kernel_events=t.handles)
+    torch.cuda.synchronize()
+    k_fwd = float(np.mean([t.elapsed_ms() for t in timers]))
+    lam = s4.tally.view(p4.tally_shape).to(torch.float64).sum(dim=1) * 2.0 ** -32
+    G = (1.0 - y / (lam + 1e-6 * float(p4.n_histories))).unsqueeze(1).expand(-1, 2, -1, -1).contiguous()
+    ms_adj = timed(torch, lambda: mc.adjoint(d4, G, s4), steps)
     out["adjoint"] = {"value": p4.n_histories / (ms / 1e3), "unit": "histories/s",
-                      "ms_per_step": ms, "forward_ms": ms_fwd, "histories": p4.n_histories,
-                      "tallied": int(s4.n_events.item()),
-                      "step": "forward with event list + Poisson-loss gradient + replaying adjoint"}
+                      "ms_per_step": ms, "forward_ms": ms_fwd, "adjoint_call_ms": ms_adj,
+                      "histories": p4.n_histories, "tallied": int(s4.n_events.item()),
+                      "step": "forward with event list + Poisson-loss gradient + replaying adjoint",
+                      "roofline": transport_roofline(s4, k_fwd),
+                      "roofline_note": "dominant kernel: the forward transport; the adjoint call "
+                                       "replays only the tallied histories (a few wavefronts) and "
+                                       "is bound by launch and host synchronisation"}
     del s4, d4, ref
     out["forced_detection"] = fd_form(mc, torch, steps)
     out["reuse_of_photon_tracks"] = rpt_form(mc, torch, steps)
@@ -276,7 +288,21 @@ def batched_form(mc, torch, steps):
     n3 = sum(p.n_histories for p in probs)
     return {"value": n3 / (ms / 1e3), "unit": "histories/s", "ms_per_step": ms,
             "transport_ms": k_ms, "histories": n3, "problems": len(probs), "options": opts,
-            "launch": "hipGraph replay: staging x32 + one persistent transport kernel"}
+            "launch": "hipGraph replay: staging x32 + one persistent transport kernel",
+            "roofline": transport_roofline(s3, k_ms)}
+
+
+def transport_roofline(sim, k_ms):
+    """ALU roofline of one transport launch from the work counters of all its
+    problems (the operation model of the headline line)."""
+    cnt = sim.counters.cpu().numpy().astype(np.float64).sum(axis=0)
+    absorbed = float(sim.fates.cpu().numpy()[:, 0].sum())
+    ops_h = ops_per_history(cnt[0], cnt[2], cnt[1] - absorbed, cnt[3])
+    achieved = ops_h * cnt[3] / (k_ms / 1e3)
+    return {"bound": "alu", "kernel": "k_transport", "kernel_ms": k_ms,
+            "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "Tops/s (32-bit lane ops)", "frac": achieved / PEAK_LANE_OPS,
+            "ops_per_history": ops_h}
 
 
 def fd_form(mc, torch, steps):

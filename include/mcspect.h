@@ -158,6 +158,13 @@ typedef struct {
                                 /* adjoint rejects it; replay honours it.       */
     int32_t pad_vr;
     double forced_direction_half_angle_rad;  /* (0, pi] when bit 1 is set      */
+    int32_t reuse_staging;      /* mc_adjoint_mu only: 1 = the workspace holds  */
+                                /* the staged tables of this same problem, with */
+                                /* unchanged inputs, from the last              */
+                                /* mc_simulate_projections that used it (one    */
+                                /* problem, earlier on the same stream): the    */
+                                /* staging passes are skipped                   */
+    int32_t pad_rs;
 } mc_options;
 
 /* One tally contribution, as written to the optional event list: a tallied

@@ -67,7 +67,8 @@ class McOptions(C.Structure):
                 ("threshold_bytes", C.c_int32), ("forced_detection", C.c_int32),
                 ("kernel_events", C.c_void_p * 2),
                 ("variance_reduction", C.c_int32), ("pad_vr", C.c_int32),
-                ("forced_direction_half_angle_rad", C.c_double)]
+                ("forced_direction_half_angle_rad", C.c_double),
+                ("reuse_staging", C.c_int32), ("pad_rs", C.c_int32)]
 
 
 EVENT_DTYPE = np.dtype([("work", np.uint64), ("bin", np.uint32), ("emit_voxel", np.uint32),
@@ -535,9 +536,20 @@ def adjoint(problem: DeviceProblem, dL_dtally, sim: Optional[Simulator] = None,
     nb = _lib.mc_workspace_bytes(C.byref(arr), 1, None)
     if nb == 0:
         raise McError("mc_workspace_bytes: invalid problem description")
-    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    if sim is not None and sim.options is not None and (sim.options.forced_detection or
+                                                         sim.options.variance_reduction):
+        raise McError("the adjoint takes the event list of an analog forward run")
+    # the forward Simulator of this one problem already staged its tables
+    opt = None
+    if sim is not None and len(sim.problems) == 1 and sim.problems[0] is problem:
+        ws, nb = sim.workspace, sim.workspace.numel()
+        opt = McOptions(reuse_staging=1)
+        if sim.options is not None:
+            opt.brick_log2, opt.threshold_bytes = sim.options.brick_log2, sim.options.threshold_bytes
+    else:
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     use_events = sim is not None and sim.events is not None
-    rc = _lib.mc_adjoint_mu(C.byref(arr), None, G.data_ptr(),
+    rc = _lib.mc_adjoint_mu(C.byref(arr), C.byref(opt) if opt is not None else None, G.data_ptr(),
                             sim.events.data_ptr() if use_events else None,
                             sim.n_events.data_ptr() if use_events else None,
                             sim.event_capacity if use_events else 0,

@@ -362,8 +362,11 @@ int mc_adjoint_mu(const mc_problem* problem, const mc_options* opt, const double
     char* ws = (char*)workspace;
     ProbDesc* d_desc = (ProbDesc*)(ws + L.desc);
     const ProbDesc h = host_desc(*problem, ws, L, 0, 0, brick, qbytes);
-    hipError_t e = launch_staging(d_desc, h, st);
-    if (e != hipSuccess) return hip_fail(e);
+    hipError_t e = hipSuccess;
+    if (!(opt && opt->reuse_staging)) {
+        e = launch_staging(d_desc, h, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
     int dev = 0, n_cu = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e);
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)

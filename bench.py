@@ -218,9 +218,13 @@ def extra_forms(mc, torch, args):
     p1 = phantoms.point_cube_64(10 ** 6)
     s1 = mc.Simulator(mc.to_device(p1), want_sq=True)
     s1.run()
-    ms = timed(torch, s1.run, steps)
+    ms_eager = timed(torch, s1.run, steps)
+    g1 = mc.GraphRunner(s1)
+    g1.replay()
+    ms = timed(torch, g1.replay, steps)
     out["point_cube_64"] = {"value": p1.n_histories / (ms / 1e3), "unit": "histories/s",
-                            "ms_per_step": ms, "histories": p1.n_histories}
+                            "ms_per_step": ms, "eager_ms_per_step": ms_eager,
+                            "histories": p1.n_histories, "launch": "hipGraph replay of one call"}
     out["batched"] = batched_form(mc, torch, steps)
     # adjoint: forward with event list, loss gradient, replaying adjoint
     p4 = phantoms.point_cube_128_adjoint(10 ** 7)

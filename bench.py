@@ -25,7 +25,8 @@ PEAK_HBM_GBS = 8000.0
 N_CU, CLOCK_HZ = 256, 2.4e9
 PEAK_LANE_OPS = N_CU * 64 * CLOCK_HZ  # one 32-bit VALU operation per lane per clock
 
-# Algorithmic 32-bit operation model per unit of work:
+# Algorithmic 32-bit operation model per unit of work (lane operations counted
+# from the source of each step):
 OPS_PHILOX = 100          # 10 rounds x (2 lo + 2 hi products, 4 xor, 2 key adds)
 OPS_EMISSION = 50         # voxel pick (64-bit product, guide, search), position, direction
 OPS_STEP = 35             # flight length, move, inside test, voxel index, accept test

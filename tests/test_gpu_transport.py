@@ -295,3 +295,22 @@ def test_step_cap_reported():
     o = oracle.simulate(p)
     assert st[0] & mc.STATUS_CAPPED
     assert st[1] == sim.fates[0, 6].item() == o["fates"][6] > 0
+
+
+def test_max_axis_grid():
+    """The largest grid axis (1024 voxels: packed coordinates use all 10
+    bits), with activity in the last voxel along every axis and in the
+    first: emission voxels identical to the oracle's, aggregates to 1e-4."""
+    nx, ny, nz, vox = 1024, 8, 8, 0.05
+    mu = np.full((nz, ny, nx), 0.151, np.float32)
+    act = np.zeros((nz, ny, nx), np.uint32)
+    act[nz - 1, ny - 1, nx - 1] = 5
+    act[0, 0, 0] = 3
+    act[nz // 2, ny // 2, 700:710] = 1
+    base = phantoms.point_cube_64(400_000)
+    p = base.with_(name="max_axis", nx=nx, ny=ny, nz=nz, voxel_cm=vox, mu=mu, activity=act,
+                   source_mode=phantoms.SOURCE_VOXELS, accept_half_angle_rad=math.radians(10.0),
+                   radius_cm=phantoms.detector_radius(nx, ny, vox), nu=64, nv=16, pixel_cm=0.8)
+    g, o = replay_parity(p, n=100_000)
+    assert (g["emit_voxel"] == nx * ny * nz - 1).any() and (g["emit_voxel"] == 0).any()
+    aggregate_parity(p)

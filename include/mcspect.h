@@ -320,7 +320,12 @@ size_t mlem_workspace_bytes(int64_t n_bins, int64_t n_vox);
  * with T given as CSR in both orientations (rows = bins: T_*, rows = voxels:
  * Tt_*, the same matrix), float values, double accumulation.  image: device
  * float [n_vox], in: S^0 (voxels with sens_i = 0 are set to 0), out: S^n_iter.
- * proj: device float [n_bins].  A bin with y_j = 0 contributes nothing. */
+ * proj: device float [n_bins].  A bin with y_j = 0 contributes nothing.
+ * Deterministic: the summation order depends only on the matrix.  Columns of
+ * each Tt row in ascending order (as mc_system_matrix writes them) let large
+ * detectors (n_bins >= 2^19) backproject one bin slice per XCD from L2; any
+ * column order gives the same result.  Asynchronous on stream: no host
+ * synchronisation, no allocation. */
 int mlem_iterate(int64_t n_bins, int64_t n_vox,
                  const int64_t* T_rowptr, const int32_t* T_col, const float* T_val,
                  const int64_t* Tt_rowptr, const int32_t* Tt_col, const float* Tt_val,

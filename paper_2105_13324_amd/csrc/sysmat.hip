@@ -19,9 +19,9 @@
 //
 // MLEM.  S_i <- S_i / sens_i * sum_j T_ij P_j / y_j, y = T S, sens_i =
 // sum_j T_ij; FP32 matrix values, FP64 accumulation; bins with y_j = 0 add
-// nothing; voxels with sens_i = 0 stay 0.  One thread per row: the matrix is
-// far sparser than one entry per row, so the row pointers and vectors are the
-// traffic (HBM-bound).
+// nothing; voxels with sens_i = 0 stay 0.  Rows are swept by groups of 1 to
+// 64 lanes sized to the mean row length; on large detectors the
+// backprojection works on one bin slice per XCD so its gathers hit L2.
 #include <algorithm>
 
 #include "mc_internal.h"
@@ -605,29 +605,245 @@ __global__ __launch_bounds__(T256) void k_mlem_init(int64_t n_vox, const float* 
         S[i] = sens[i] > 0.0 ? (double)img[i] : 0.0;
 }
 
-// y_j = sum_i T_ij S_i; ratio_j = P_j / y_j (0 when y_j = 0)
+// Lanes that share one row in the MLEM sweeps: the smallest group of 1, 4, 16
+// or 64 lanes for which four entries per lane cover the mean row (nnz /
+// n_rows entries), so that short rows do not leave most of a wavefront idle.
+__device__ inline int lanes_per_row(int64_t nnz, int64_t n_rows) {
+    if (nnz <= 4 * n_rows) return 1;
+    if (nnz <= 16 * n_rows) return 4;
+    if (nnz <= 64 * n_rows) return 16;
+    return 64;
+}
+
+// The rows a group of GS lanes visits: row g, g + n_groups, ... (g: the
+// group's index among n_groups); every lane of a group sees the same rows.
+template <int GS>
+struct RowGroups {
+    int64_t first, step;
+    int sub;
+    __device__ RowGroups(int64_t block, int64_t n_blocks) {
+        const int64_t t = block * blockDim.x + threadIdx.x;
+        first = t / GS;
+        step = n_blocks * blockDim.x / GS;
+        sub = (int)(threadIdx.x & (GS - 1));
+    }
+};
+
+// Sum over k in [k0, k1) of term(k, valid) by a group of GS lanes (sub: the
+// lane's index in the group).  Indices past the end are clamped to k1 - 1 so
+// every load is in bounds and issued unconditionally; term() zeroes them.
+// Each lane adds its four terms in order, then a butterfly over the group:
+// the summation order depends only on the row and GS.
+template <int GS, class Term>
+__device__ inline double group_row_sum(int64_t k0, int64_t k1, int sub, Term term) {
+    double acc = 0.0;
+    for (int64_t k = k0 + sub; k < k1; k += 4 * GS) {
+        double t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t kk = k + (int64_t)u * GS;
+            t[u] = term(kk < k1 ? kk : k1 - 1, kk < k1);
+        }
+        acc += t[0];
+        acc += t[1];
+        acc += t[2];
+        acc += t[3];
+    }
+#pragma unroll
+    for (int o = GS / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, GS);
+    return acc;
+}
+
+// A group's rows of n, four per pass: bounds(q, lo, hi) loads the entry
+// ranges of four rows before any of them is summed (row by row, with
+// group_row_sum), so a sparse matrix (most rows empty or one entry long)
+// keeps four row-pointer loads in flight per lane.  done(q, lo, len, sum)
+// runs for every row q < n; the test is group-uniform.  (Summing the four
+// rows interleaved was slower on forced-detection matrices: a pass then
+// lasts as long as the longest of the four rows.)
+template <int GS, class Bounds, class Term, class Done>
+__device__ inline void sweep_rows(const RowGroups<GS>& G, int64_t n, Bounds bounds, Term term,
+                                  Done done) {
+    for (int64_t r = G.first; r < n; r += 4 * G.step) {
+        int64_t lo[4], hi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t q = r + u * G.step;
+            bounds(q < n ? q : n - 1, lo[u], hi[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (r + u * G.step < n)
+                done(r + u * G.step, lo[u], hi[u] - lo[u], group_row_sum<GS>(lo[u], hi[u], G.sub, term));
+    }
+}
+
+// y_j = sum_i T_ij S_i; ratio_j = P_j / y_j (0 when y_j = 0).  An empty bin
+// row is skipped: no entry of T^T refers to it, so its ratio is never read.
+template <int GS>
+__device__ inline void mlem_forward_rows(int64_t n_bins, const int64_t* __restrict__ rp,
+                                         const int32_t* __restrict__ col,
+                                         const float* __restrict__ val,
+                                         const double* __restrict__ S,
+                                         const float* __restrict__ P, double* __restrict__ ratio) {
+    const RowGroups<GS> G(blockIdx.x, gridDim.x);
+    sweep_rows(G, n_bins, [&](int64_t j, int64_t& lo, int64_t& hi) { lo = rp[j]; hi = rp[j + 1]; },
+               [&](int64_t k, bool ok) {
+                   const double x = (double)val[k] * S[col[k]];
+                   return ok ? x : 0.0;
+               },
+               [&](int64_t j, int64_t, int64_t len, double y) {
+                   if (len > 0 && G.sub == 0) ratio[j] = y > 0.0 ? (double)P[j] / y : 0.0;
+               });
+}
+
 __global__ __launch_bounds__(T256) void k_mlem_forward(int64_t n_bins, const int64_t* __restrict__ rp,
                                                        const int32_t* __restrict__ col,
                                                        const float* __restrict__ val,
                                                        const double* __restrict__ S,
                                                        const float* __restrict__ P,
                                                        double* __restrict__ ratio) {
-    for_rows(n_bins, rp, [&](int64_t k) { return (double)val[k] * S[col[k]]; },
-             [&](int64_t j, double y) { ratio[j] = y > 0.0 ? (double)P[j] / y : 0.0; });
+    switch (lanes_per_row(rp[n_bins], n_bins)) {
+        case 1: mlem_forward_rows<1>(n_bins, rp, col, val, S, P, ratio); break;
+        case 4: mlem_forward_rows<4>(n_bins, rp, col, val, S, P, ratio); break;
+        case 16: mlem_forward_rows<16>(n_bins, rp, col, val, S, P, ratio); break;
+        default: mlem_forward_rows<64>(n_bins, rp, col, val, S, P, ratio); break;
+    }
 }
 
-// S_i <- S_i * (sum_j T_ij ratio_j) / sens_i
-__global__ __launch_bounds__(T256) void k_mlem_update(int64_t n_vox, const int64_t* __restrict__ rp,
+// Backprojection by bin slices.  When the ratio vector is larger than one
+// XCD's L2 (4 MB) and T^T has at least 16 entries per voxel row, the bin
+// range is cut into MLEM_SEGS equal slices and workgroup b works on slice
+// b mod MLEM_SEGS only: workgroups are handed to the 8 XCDs in turn, so each
+// XCD gathers from one slice of ratio (under 4 MB at 2^22 bins) that stays in
+// its L2, instead of every gather missing to HBM.  Each voxel row is cut at
+// the slice boundaries (binary search over its ascending columns, once per
+// call); the MLEM_SEGS partial sums are added in slice order.  Any cut is
+// correct (the pieces always partition the row), so rows whose columns are
+// not ascending lose only the locality.
+constexpr int MLEM_SEGS = 8;
+constexpr int64_t MLEM_SEG_MIN_BINS = (int64_t)1 << 19;
+
+__host__ __device__ inline bool mlem_sliced(int64_t n_bins, int64_t nnz, int64_t n_vox) {
+    return n_bins >= MLEM_SEG_MIN_BINS && nnz >= 16 * n_vox;
+}
+
+// sb[i][s] (s = 0..MLEM_SEGS): first entry of voxel row i in slice s, with
+// sb[i][0] = rp[i] and sb[i][MLEM_SEGS] = rp[i + 1]; non-decreasing in s.
+__global__ __launch_bounds__(T256) void k_mlem_slices(int64_t n_vox, int64_t n_bins,
+                                                      const int64_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col,
+                                                      int64_t* __restrict__ sb) {
+    if (!mlem_sliced(n_bins, rp[n_vox], n_vox)) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t lo = rp[i];
+        const int64_t hi = rp[i + 1];
+        int64_t* out = sb + i * (MLEM_SEGS + 1);
+        out[0] = lo;
+        for (int s = 1; s < MLEM_SEGS; ++s) {
+            const int64_t bound = n_bins * s / MLEM_SEGS;
+            int64_t a = lo, b = hi;
+            while (a < b) {
+                const int64_t mid = (a + b) >> 1;
+                if ((int64_t)col[mid] < bound) a = mid + 1; else b = mid;
+            }
+            out[s] = a;
+            lo = a;
+        }
+        out[MLEM_SEGS] = hi;
+    }
+}
+
+// S_i <- S_i * (sum_j T_ij ratio_j) / sens_i over whole voxel rows.  An
+// empty row has sens_i = 0, so its S_i is already 0 and is skipped.
+template <int GS>
+__device__ inline void mlem_update_rows(int64_t n_vox, const int64_t* __restrict__ rp,
+                                        const int32_t* __restrict__ col,
+                                        const float* __restrict__ val,
+                                        const double* __restrict__ ratio,
+                                        const double* __restrict__ sens, double* __restrict__ S) {
+    const RowGroups<GS> G(blockIdx.x, gridDim.x);
+    sweep_rows(G, n_vox, [&](int64_t i, int64_t& lo, int64_t& hi) { lo = rp[i]; hi = rp[i + 1]; },
+               [&](int64_t k, bool ok) {
+                   const double x = (double)val[k] * ratio[col[k]];
+                   return ok ? x : 0.0;
+               },
+               [&](int64_t i, int64_t, int64_t len, double b) {
+                   if (len > 0 && G.sub == 0) {
+                       const double si = sens[i];
+                       S[i] = si > 0.0 ? S[i] * b / si : 0.0;
+                   }
+               });
+}
+
+// part[s][i] = sum over the entries of voxel row i in slice s of T_ij ratio_j,
+// slice s = blockIdx.x mod MLEM_SEGS (gridDim.x is a multiple of MLEM_SEGS).
+template <int GS>
+__device__ inline void mlem_back_slices(int64_t n_vox, const int64_t* __restrict__ sb,
+                                        const int32_t* __restrict__ col,
+                                        const float* __restrict__ val,
+                                        const double* __restrict__ ratio,
+                                        double* __restrict__ part) {
+    const int seg = (int)(blockIdx.x % MLEM_SEGS);
+    const RowGroups<GS> G(blockIdx.x / MLEM_SEGS, gridDim.x / MLEM_SEGS);
+    sweep_rows(G, n_vox,
+               [&](int64_t i, int64_t& lo, int64_t& hi) {
+                   const int64_t* b = sb + i * (MLEM_SEGS + 1) + seg;
+                   lo = b[0];
+                   hi = b[1];
+               },
+               [&](int64_t k, bool ok) {
+                   const double x = (double)val[k] * ratio[col[k]];
+                   return ok ? x : 0.0;
+               },
+               [&](int64_t i, int64_t, int64_t, double acc) {
+                   if (G.sub == 0) part[(int64_t)seg * n_vox + i] = acc;
+               });
+}
+
+__global__ __launch_bounds__(T256) void k_mlem_update(int64_t n_vox, int64_t n_bins,
+                                                      const int64_t* __restrict__ rp,
                                                       const int32_t* __restrict__ col,
                                                       const float* __restrict__ val,
                                                       const double* __restrict__ ratio,
                                                       const double* __restrict__ sens,
-                                                      double* __restrict__ S) {
-    for_rows(n_vox, rp, [&](int64_t k) { return (double)val[k] * ratio[col[k]]; },
-             [&](int64_t i, double bsum) {
-                 const double si = sens[i];
-                 S[i] = si > 0.0 ? S[i] * bsum / si : 0.0;
-             });
+                                                      double* __restrict__ S,
+                                                      const int64_t* __restrict__ sb,
+                                                      double* __restrict__ part) {
+    const int64_t nnz = rp[n_vox];
+    if (mlem_sliced(n_bins, nnz, n_vox)) {
+        switch (lanes_per_row(nnz, n_vox * MLEM_SEGS)) {
+            case 1: mlem_back_slices<1>(n_vox, sb, col, val, ratio, part); break;
+            case 4: mlem_back_slices<4>(n_vox, sb, col, val, ratio, part); break;
+            case 16: mlem_back_slices<16>(n_vox, sb, col, val, ratio, part); break;
+            default: mlem_back_slices<64>(n_vox, sb, col, val, ratio, part); break;
+        }
+        return;
+    }
+    switch (lanes_per_row(nnz, n_vox)) {
+        case 1: mlem_update_rows<1>(n_vox, rp, col, val, ratio, sens, S); break;
+        case 4: mlem_update_rows<4>(n_vox, rp, col, val, ratio, sens, S); break;
+        case 16: mlem_update_rows<16>(n_vox, rp, col, val, ratio, sens, S); break;
+        default: mlem_update_rows<64>(n_vox, rp, col, val, ratio, sens, S); break;
+    }
+}
+
+// Sliced backprojection, second half: S_i <- S_i * (sum_s part[s][i]) / sens_i.
+__global__ __launch_bounds__(T256) void k_mlem_combine(int64_t n_vox, int64_t n_bins,
+                                                       const int64_t* __restrict__ rp,
+                                                       const double* __restrict__ part,
+                                                       const double* __restrict__ sens,
+                                                       double* __restrict__ S) {
+    if (!mlem_sliced(n_bins, rp[n_vox], n_vox)) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double b = 0.0;
+#pragma unroll
+        for (int s = 0; s < MLEM_SEGS; ++s) b += part[(int64_t)s * n_vox + i];
+        const double si = sens[i];
+        S[i] = si > 0.0 ? S[i] * b / si : 0.0;
+    }
 }
 
 __global__ __launch_bounds__(T256) void k_mlem_out(int64_t n_vox, const double* __restrict__ S,
@@ -831,7 +1047,10 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
 
 size_t mlem_workspace(uint64_t n_bins, uint64_t n_vox) {
     auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
-    return al(8 * n_vox) /* sens */ + al(8 * n_vox) /* S */ + al(8 * n_bins) /* ratio */;
+    size_t b = al(8 * n_vox) /* sens */ + al(8 * n_vox) /* S */ + al(8 * n_bins) /* ratio */;
+    if ((int64_t)n_bins >= MLEM_SEG_MIN_BINS)
+        b += al(8 * (MLEM_SEGS + 1) * n_vox) /* slice cuts */ + al(8 * MLEM_SEGS * n_vox) /* partials */;
+    return b;
 }
 
 hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, const int64_t* T_rp, const int32_t* T_col,
@@ -842,13 +1061,35 @@ hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, const int64_t* T_rp, const
     char* w = (char*)workspace;
     double* sens = (double*)w;  w += al(8 * n_vox);
     double* S = (double*)w;     w += al(8 * n_vox);
-    double* ratio = (double*)w;
-    const int gv = grid_for((uint64_t)n_vox, T256, 8192), gb = grid_for((uint64_t)n_bins, T256, 16384);
+    double* ratio = (double*)w; w += al(8 * n_bins);
+    // slicing is decided on the device from nnz; n_bins alone rules it out
+    const bool may_slice = n_bins >= MLEM_SEG_MIN_BINS;
+    int64_t* sb = nullptr;
+    double* part = nullptr;
+    if (may_slice) {
+        sb = (int64_t*)w;       w += al(8 * (MLEM_SEGS + 1) * (uint64_t)n_vox);
+        part = (double*)w;
+    }
+    const int gv = grid_for((uint64_t)n_vox, T256, 8192);
+    // The sweeps are grid-strided: one resident round of workgroups at most
+    // (more only costs dispatch time and a ragged last round).
+    int dev = 0, n_cu = 0, bpc_f = 0, bpc_u = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_f, k_mlem_forward, T256, 0)) != hipSuccess)
+        return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_u, k_mlem_update, T256, 0)) != hipSuccess)
+        return e;
+    const int gb = grid_for((uint64_t)n_bins, T256, std::max(1, n_cu * bpc_f));
+    const int gu = MLEM_SEGS * grid_for((uint64_t)n_vox, T256, std::max(1, n_cu * bpc_u / MLEM_SEGS));
     k_row_sums<<<gv, T256, 0, s>>>(n_vox, Tt_rp, Tt_val, sens);
     k_mlem_init<<<gv, T256, 0, s>>>(n_vox, image, sens, S);
+    if (may_slice) k_mlem_slices<<<gv, T256, 0, s>>>(n_vox, n_bins, Tt_rp, Tt_col, sb);
     for (int it = 0; it < n_iter; ++it) {
         k_mlem_forward<<<gb, T256, 0, s>>>(n_bins, T_rp, T_col, T_val, S, proj, ratio);
-        k_mlem_update<<<gv, T256, 0, s>>>(n_vox, Tt_rp, Tt_col, Tt_val, ratio, sens, S);
+        k_mlem_update<<<gu, T256, 0, s>>>(n_vox, n_bins, Tt_rp, Tt_col, Tt_val, ratio, sens, S, sb, part);
+        if (may_slice) k_mlem_combine<<<gv, T256, 0, s>>>(n_vox, n_bins, Tt_rp, part, sens, S);
     }
     k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, image);
     return hipGetLastError();

@@ -78,6 +78,67 @@ def test_mlem_sparse_and_dense_rows(density):
     assert rel <= 1e-6 and rel2 <= 1e-6
 
 
+def _mlem_vs_oracle(T, P, n_iter, m=None):
+    mc = _mc()
+    import torch
+    m = mc.csr_from_scipy(T) if m is None else m
+    m.proj = torch.as_tensor(P, device="cuda")
+    ml = mc.Mlem(m)
+    img = torch.ones(T.shape[1], dtype=torch.float32, device="cuda")
+    ml.run(img, n_iter)
+    img2 = torch.ones(T.shape[1], dtype=torch.float32, device="cuda")
+    ml.run(img2, n_iter)
+    assert torch.equal(img, img2), "MLEM must be deterministic"
+    o = oracle.mlem(T.astype(np.float64), P.astype(np.float64), n_iter)
+    g = img.cpu().numpy().astype(np.float64)
+    msk = o > 1e-6 * o.max()
+    rel = np.max(np.abs(g[msk] - o[msk]) / o[msk])
+    assert np.all(g[~msk] <= 1e-5 * o.max())
+    return rel
+
+
+@pytest.mark.parametrize("n_bins,n_vox,density", [
+    (1000, 4000, 0.03),        # 120 entries per bin row (64 lanes), 30 per voxel row (16)
+    (600_000, 3000, 2e-5),     # large detector, 12 entries per voxel row: whole rows
+    (600_000, 3000, 1e-4),     # bin slices, 7.5 entries per slice (4 lanes)
+    (600_000, 3000, 1e-3),     # bin slices, 75 entries per slice (64 lanes)
+])
+def test_mlem_row_groups_and_bin_slices(n_bins, n_vox, density):
+    """Every lane-group size of the sweeps and the per-XCD bin slices of the
+    backprojection (2^19 bins or more, 16 entries per voxel row or more) give
+    the oracle's image, bit-identically on a second run."""
+    T, truth = phantoms.random_system(n_bins, n_vox, density, seed=36)
+    rng = np.random.Generator(np.random.PCG64(37))
+    P = rng.poisson(T.astype(np.float64) @ truth * 20).astype(np.float32)
+    rel = _mlem_vs_oracle(T, P, 20)
+    say(f"{n_bins} x {n_vox}, {T.nnz} entries: MLEM max rel {rel:.2e}")
+    assert rel <= 1e-6
+
+
+def test_mlem_bin_slices_unsorted_rows():
+    """Voxel rows whose columns are not ascending: the slice cuts then do not
+    follow the slices, but the pieces still cover each row, so the result is
+    the oracle's."""
+    mc = _mc()
+    import torch
+    T, truth = phantoms.random_system(600_000, 2000, 2e-4, seed=38)
+    rng = np.random.Generator(np.random.PCG64(39))
+    P = rng.poisson(T.astype(np.float64) @ truth * 20).astype(np.float32)
+    m = mc.csr_from_scipy(T)
+    Tt = T.T.tocsr()
+    Tt.sort_indices()
+    col, val = Tt.indices.copy(), Tt.data.copy()
+    for i in range(Tt.shape[0]):      # reverse every voxel row
+        a, b = Tt.indptr[i], Tt.indptr[i + 1]
+        col[a:b] = col[a:b][::-1]
+        val[a:b] = val[a:b][::-1]
+    m.Tt_col = torch.as_tensor(col.astype(np.int32), device="cuda")
+    m.Tt_val = torch.as_tensor(val.astype(np.float32), device="cuda")
+    rel = _mlem_vs_oracle(T, P, 15, m=m)
+    say(f"unsorted voxel rows: MLEM max rel {rel:.2e}")
+    assert rel <= 1e-6
+
+
 def test_mlem_fixed_point_on_gpu():
     mc = _mc()
     import torch

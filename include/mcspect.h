@@ -280,7 +280,8 @@ int mc_adjoint_mu(const mc_problem* problem, const mc_options* opt, const double
                   int64_t* dL_dmu, int32_t frac_bits, int64_t* status,
                   void* workspace, size_t workspace_bytes, void* stream);
 
-/* Workspace bytes of mc_system_matrix (0 on invalid arguments). */
+/* Workspace bytes of mc_system_matrix (0 on invalid arguments): about 36 B
+ * per event of capacity (radix-sort buffers) plus 8 B per bin and voxel. */
 size_t mc_system_matrix_workspace_bytes(const mc_problem* problem, uint64_t event_capacity);
 
 /* Monte Carlo response matrix of Sec. 5.1 (Eq. IMC) from a forward call's

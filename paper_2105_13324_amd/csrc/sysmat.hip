@@ -12,10 +12,10 @@
 // (view * nv + iv) * nu + iu.  The projection P_j = sum_i c_ij is the same
 // run's counts, so P = T n exactly.
 //
-// Both orientations are built as CSR (bins x voxels and voxels x bins) by a
-// deterministic counting sort: rows counted with integer atomics, scanned,
-// scattered, each row's columns sorted and merged.  Weights are summed as
-// Q31.32 integers, so the result does not depend on the atomics' order.
+// Both orientations are built as CSR (bins x voxels and voxels x bins): the
+// events are radix-sorted by (row, column), runs of equal keys merged, and
+// the weights summed as Q31.32 integers, so the result does not depend on the
+// order of the event list.
 //
 // MLEM.  S_i <- S_i / sens_i * sum_j T_ij P_j / y_j, y = T S, sens_i =
 // sum_j T_ij; FP32 matrix values, FP64 accumulation; bins with y_j = 0 add
@@ -47,8 +47,18 @@ __device__ inline uint64_t wave_sum64(uint64_t v) {
 
 // ---- generic exclusive scan: uint32 counts -> uint64 offsets [n + 1] ----
 
-__global__ __launch_bounds__(T256) void k_sum_blocks(const uint32_t* __restrict__ in, uint64_t n,
+// n_dev (nullable): a device-side count below n; items from it on are taken
+// as 0 without being read, and outputs past it are not written.
+__device__ inline uint64_t scan_limit(uint64_t n, const uint64_t* n_dev) {
+    if (!n_dev) return n;
+    const uint64_t m = *n_dev;
+    return m < n ? m : n;
+}
+
+__global__ __launch_bounds__(T256) void k_sum_blocks(const uint32_t* __restrict__ in, uint64_t n_host,
+                                                     const uint64_t* __restrict__ n_dev,
                                                      uint64_t* __restrict__ bsum) {
+    const uint64_t n = scan_limit(n_host, n_dev);
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK;
     uint64_t s = 0;
     for (int j = threadIdx.x; j < SCAN_BLOCK; j += T256) {
@@ -91,9 +101,12 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint64_t* bsum, int nb) {
 }
 
 // out[i] = sum_{k<i} in[k] for i in [0, n]; out[n] = total.
-__global__ __launch_bounds__(T256) void k_scan_write(const uint32_t* __restrict__ in, uint64_t n,
+__global__ __launch_bounds__(T256) void k_scan_write(const uint32_t* __restrict__ in, uint64_t n_host,
+                                                     const uint64_t* __restrict__ n_dev,
                                                      const uint64_t* __restrict__ bsum,
                                                      uint64_t* __restrict__ out) {
+    const uint64_t n = scan_limit(n_host, n_dev);
+    if ((uint64_t)blockIdx.x * SCAN_BLOCK > n) return;   // past the limit: no output here
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK + (uint64_t)threadIdx.x * SCAN_PER;
     uint32_t v[SCAN_PER];
     uint64_t s = 0;
@@ -121,13 +134,14 @@ __global__ __launch_bounds__(T256) void k_scan_write(const uint32_t* __restrict_
     }
 }
 
+// out[i] = sum_{k<i} in[k] for i in [0, min(n, *n_dev)] (n_dev nullable).
 hipError_t exclusive_scan(const uint32_t* in, uint64_t n, uint64_t* out, uint64_t* bsum,
-                          hipStream_t s) {
+                          hipStream_t s, const uint64_t* n_dev = nullptr) {
     // one extra item so the block holding index n writes the total
     const int nb = (int)((n + 1 + SCAN_BLOCK - 1) / SCAN_BLOCK);
-    k_sum_blocks<<<nb, T256, 0, s>>>(in, n, bsum);
+    k_sum_blocks<<<nb, T256, 0, s>>>(in, n, n_dev, bsum);
     k_scan_blocks<<<1, 1024, 0, s>>>(bsum, nb);
-    k_scan_write<<<nb, T256, 0, s>>>(in, n, bsum, out);
+    k_scan_write<<<nb, T256, 0, s>>>(in, n, n_dev, bsum, out);
     return hipGetLastError();
 }
 
@@ -162,10 +176,6 @@ __device__ inline bool event_rc(const SysArgs& a, const mc_event& ev, uint32_t& 
     return true;
 }
 
-__global__ __launch_bounds__(T256) void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
-}
 __global__ __launch_bounds__(T256) void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
@@ -191,365 +201,275 @@ __global__ __launch_bounds__(T256) void k_image_activity(const uint32_t* __restr
     if ((threadIdx.x & 63) == 0 && sum) atomicAdd(total, (unsigned long long)sum);
 }
 
-// count events per row (transpose = 0: rows are bins, 1: rows are image voxels)
-__global__ __launch_bounds__(T256) void k_count_rows(SysArgs a, int transpose, uint32_t* cnt) {
-    const uint64_t n = n_events_of(a);
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t bin, img;
-        if (!event_rc(a, a.events[e], bin, img)) continue;
-        atomicAdd(cnt + (transpose ? img : bin), 1u);
-    }
+// ---- response matrix rows by LSD radix sort ----
+//
+// Each orientation sorts the events by the key (row << col_bits) | col with
+// a least-significant-digit radix sort (8-bit digits, stable), so a row's
+// events end up together, ordered by column, with duplicates adjacent.  A
+// pass is three launches: per-tile digit histograms (LDS counters), one
+// exclusive scan of the histograms in digit-major order (the global output
+// offset of every (digit, tile)), and a stable scatter: within a tile, items
+// are ranked round by round (256 consecutive items), inside a wavefront by
+// matching digits with eight ballots and across the four wavefronts through
+// LDS counts.  No global atomics: the per-event atomics of a counting sort
+// contend on the rows that collect many events.  The event count is read on
+// the device, so nothing waits on the host; tiles past it do no work.
+// Events of a filtered class take row n_rows and sort last.
+
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;              // digits per pass (= T256)
+constexpr int RADIX_ITEMS = 16;                     // items per thread and tile
+constexpr uint64_t RADIX_TILE = (uint64_t)T256 * RADIX_ITEMS;
+static_assert(RADIX == T256, "one digit counter per thread");
+
+int bit_width(uint64_t v) {
+    int b = 0;
+    while (v) { ++b; v >>= 1; }
+    return b;
 }
 
-__global__ __launch_bounds__(T256) void k_scatter(SysArgs a, int transpose, const uint64_t* start,
-                                                  uint32_t* fill, uint32_t* tmp_col, int64_t* tmp_w) {
+// Tile of workgroup b.  Workgroups are dealt to the 8 XCDs in turn; the
+// tiles that hold items (the first `used`) are remapped so that each XCD
+// takes a contiguous run of them, so neighbouring tiles share one L2 (their
+// histogram and offset lines, and the adjacent digit runs they write).
+// Empty tiles keep their own index.
+__device__ inline uint32_t tile_of(uint32_t b, uint64_t n) {
+    const uint32_t used = (uint32_t)((n + RADIX_TILE - 1) / RADIX_TILE);
+    if (b >= used) return b;
+    const uint32_t per = used / 8, rem = used % 8, x = b % 8, q = b / 8;
+    return x * per + (x < rem ? x : rem) + q;
+}
+
+__global__ __launch_bounds__(T256) void k_make_keys(SysArgs a, int transpose, uint64_t n_rows,
+                                                    int col_bits, uint64_t* __restrict__ keys,
+                                                    int64_t* __restrict__ vals) {
     const uint64_t n = n_events_of(a);
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t bin, img;
         const mc_event ev = a.events[e];
-        if (!event_rc(a, ev, bin, img)) continue;
-        const uint32_t r = transpose ? img : bin, c = transpose ? bin : img;
-        const uint32_t k = atomicAdd(fill + r, 1u);
-        tmp_col[start[r] + k] = c;
-        tmp_w[start[r] + k] = ev.weight;
-    }
-}
-
-// Sift-down of heap node i over [0, n) of the row (col keys, weights carried).
-__device__ inline void sift(uint32_t* col, int64_t* w, uint64_t i, uint64_t n) {
-    for (;;) {
-        uint64_t m = i;
-        const uint64_t l = 2 * i + 1, r = l + 1;
-        if (l < n && col[l] > col[m]) m = l;
-        if (r < n && col[r] > col[m]) m = r;
-        if (m == i) return;
-        const uint32_t tc = col[i]; col[i] = col[m]; col[m] = tc;
-        const int64_t tw = w[i]; w[i] = w[m]; w[m] = tw;
-        i = m;
-    }
-}
-
-constexpr uint64_t ROW_SHORT = 32;      // rows up to this length: one thread, insertion sort
-constexpr uint64_t ROW_LDS = 4096;      // rows up to this length: one wavefront, LDS bitonic sort
-constexpr uint64_t ROW_BIG = 8192;      // rows up to this length: one 256-thread block, LDS bitonic sort
-
-// sort each row's (column, weight) pairs by column and count the distinct
-// columns: short rows (analog lists) by insertion sort here; longer rows are
-// left to k_sort_rows_wave and k_sort_rows_block.  With heap = 1 the kernel
-// instead heapsorts the rows k_sort_rows_block could not take (marked
-// ROW_OVERFLOW in row_nnz).
-constexpr uint32_t ROW_OVERFLOW = 0xFFFFFFFFu;
-
-__global__ __launch_bounds__(T256) void k_sort_rows(uint64_t n_rows, const uint64_t* start,
-                                                    uint32_t* tmp_col, int64_t* tmp_w,
-                                                    uint32_t* row_nnz, int heap) {
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
-         r += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t b = start[r], e = start[r + 1], n = e - b;
-        uint32_t* col = tmp_col + b;
-        int64_t* w = tmp_w + b;
-        if (heap ? row_nnz[r] != ROW_OVERFLOW : n > ROW_SHORT) continue;
-        if (n <= ROW_SHORT) {
-            for (uint64_t i = 1; i < n; ++i) {
-                const uint32_t v = col[i];
-                const int64_t wv = w[i];
-                uint64_t j = i;
-                while (j > 0 && col[j - 1] > v) { col[j] = col[j - 1]; w[j] = w[j - 1]; --j; }
-                col[j] = v;
-                w[j] = wv;
-            }
+        if (event_rc(a, ev, bin, img)) {
+            const uint64_t r = transpose ? img : bin, c = transpose ? bin : img;
+            keys[e] = (r << col_bits) | c;
+            vals[e] = ev.weight;
         } else {
-            for (uint64_t i = n / 2; i-- > 0;) sift(col, w, i, n);
-            for (uint64_t k = n - 1; k > 0; --k) {
-                const uint32_t tc = col[0]; col[0] = col[k]; col[k] = tc;
-                const int64_t tw = w[0]; w[0] = w[k]; w[k] = tw;
-                sift(col, w, 0, k);
-            }
-        }
-        uint32_t d = 0;
-        for (uint64_t i = b; i < e; ++i) d += (i == b || tmp_col[i] != tmp_col[i - 1]);
-        row_nnz[r] = d;
-    }
-}
-
-// one wavefront per row of ROW_SHORT < length <= 1024 (two classes):
-// bitonic sort of the (column, weight) pairs in LDS, padded to a power of
-// two, then the count of distinct columns
-// Instantiated per length class (LO, HI] so that the LDS a wavefront holds
-// (12 B per entry) fits the class and short-row classes keep many
-// wavefronts resident per CU.
-template <uint32_t LO, uint32_t HI>
-__global__ __launch_bounds__(64) void k_sort_rows_wave(uint64_t n_rows, const uint64_t* start,
-                                                       uint32_t* tmp_col, int64_t* tmp_w,
-                                                       uint32_t* row_nnz) {
-    __shared__ uint32_t key[HI];
-    __shared__ int64_t wt[HI];
-    const uint32_t lane = threadIdx.x;
-    // 64 rows are screened at once (a lane each; rows gridDim.x apart, so
-    // runs of long rows spread over the grid); the wavefront then sorts the
-    // ones of this length class in turn
-    const uint64_t stride = gridDim.x;
-    for (uint64_t r0 = blockIdx.x; r0 < n_rows; r0 += stride * 64) {
-        bool need = false;
-        const uint64_t rl = r0 + lane * stride;
-        if (rl < n_rows) {
-            const uint64_t len = start[rl + 1] - start[rl];
-            need = len > LO && len <= HI;
-        }
-        for (uint64_t todo = __ballot(need); todo != 0; todo &= todo - 1) {
-            const uint64_t r = r0 + (uint64_t)(__ffsll((unsigned long long)todo) - 1) * stride;
-            const uint64_t b = start[r], n = start[r + 1] - b;
-            uint32_t m = 1;
-            while (m < n) m <<= 1;
-            for (uint32_t i = lane; i < m; i += 64) {
-                key[i] = i < n ? tmp_col[b + i] : 0xFFFFFFFFu;
-                wt[i] = i < n ? tmp_w[b + i] : 0;
-            }
-            __syncthreads();
-            for (uint32_t k = 2; k <= m; k <<= 1) {
-                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                    for (uint32_t i = lane; i < m; i += 64) {
-                        const uint32_t x = i ^ j;
-                        if (x > i) {
-                            const bool up = (i & k) == 0;
-                            const uint32_t ki = key[i], kx = key[x];
-                            if ((ki > kx) == up) {
-                                key[i] = kx; key[x] = ki;
-                                const int64_t t = wt[i]; wt[i] = wt[x]; wt[x] = t;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            uint32_t d = 0;
-            for (uint32_t i = lane; i < n; i += 64) {
-                tmp_col[b + i] = key[i];
-                tmp_w[b + i] = wt[i];
-                d += (i == 0 || key[i] != key[i - 1]);
-            }
-            for (int o = 32; o > 0; o >>= 1) d += (uint32_t)__shfl_xor((int)d, o, 64);
-            if (lane == 0) row_nnz[r] = d;
-            __syncthreads();
+            keys[e] = n_rows << col_bits;
+            vals[e] = 0;
         }
     }
 }
 
-// one 256-thread block per row longer than 1024 entries (the dense voxel
-// rows of forced-detection matrices), in 48 KB of LDS up to ROW_LDS entries
-// and 96 KB up to ROW_BIG: the same bitonic sort.  Longer rows: their
-// entries are first summed per
-// column in an LDS hash table of ROW_BIG slots (64-bit integer adds: exact,
-// so the order does not matter), the table is sorted, and the row is
-// rewritten as its distinct columns with their sums followed by copies of
-// the last column with weight 0 (which the merge adds as 0); a row with more
-// than ROW_BIG distinct columns is marked ROW_OVERFLOW for the heapsort.  A
-// block screens 256 rows per step (rows gridDim.x apart), lists the long
-// ones and sorts them in turn.
-// Instantiated per class: rows of (LO, CAP] entries are sorted in CAP
-// slots; with AGG also every longer row goes through the column sums.
-__device__ inline uint32_t col_hash(uint32_t c) { return (c * 2654435761u) >> 19; }   // 13 bits
+// hist[d * n_tiles + t]: items of tile t (one workgroup per tile) with digit d
+__global__ __launch_bounds__(T256) void k_radix_hist(const uint64_t* __restrict__ keys, SysArgs a,
+                                                     int shift, uint32_t n_tiles,
+                                                     uint32_t* __restrict__ hist) {
+    __shared__ uint32_t cnt[RADIX];
+    const uint64_t n = n_events_of(a);
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t tile = tile_of(blockIdx.x, n);
+    const uint64_t base = (uint64_t)tile * RADIX_TILE;
+    for (int j = 0; j < RADIX_ITEMS; ++j) {
+        const uint64_t i = base + (uint64_t)j * T256 + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (RADIX - 1)], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * n_tiles + tile] = cnt[threadIdx.x];
+}
 
-template <uint32_t LO, uint32_t CAP, bool AGG>
-__global__ __launch_bounds__(T256) void k_sort_rows_block(uint64_t n_rows, const uint64_t* start,
-                                                          uint32_t* tmp_col, int64_t* tmp_w,
-                                                          uint32_t* row_nnz) {
-    static_assert(!AGG || CAP == 8192, "col_hash gives 13 bits");
-    __shared__ uint32_t key[CAP];
-    __shared__ int64_t wt[CAP];
-    __shared__ uint32_t list[T256];
-    __shared__ uint32_t n_list, n_distinct, overflow;
-    const uint32_t t = threadIdx.x;
-    const uint64_t stride = gridDim.x;
-    for (uint64_t r0 = blockIdx.x; r0 < n_rows; r0 += stride * T256) {
-        if (t == 0) n_list = 0;
-        __syncthreads();
-        const uint64_t rl = r0 + t * stride;
-        if (rl < n_rows) {
-            const uint64_t len = start[rl + 1] - start[rl];
-            if (len > LO && (AGG || len <= CAP)) list[atomicAdd(&n_list, 1u)] = t;
+// Stable scatter of tile t's items to offs[d * n_tiles + t] + their rank
+// among the tile's items of digit d.  Each wavefront takes a quarter of the
+// tile (1024 consecutive items, 16 per lane, loaded at once) and ranks it on
+// its own, 64 items per round: lanes with equal digits found with eight
+// ballots, and a running count per digit kept in the wavefront's row of LDS.
+// After one barrier, the earlier wavefronts' counts place each item in a
+// digit-ordered copy of the tile in LDS (keys, then values through the same
+// 32 KB), which is written out so that each digit's run from this tile (16
+// items on average) goes to consecutive addresses.
+constexpr uint32_t RADIX_WAVE_ITEMS = (uint32_t)(RADIX_TILE / (T256 / 64));
+
+__global__ __launch_bounds__(T256) void k_radix_scatter(const uint64_t* __restrict__ kin,
+                                                        const int64_t* __restrict__ vin,
+                                                        uint64_t* __restrict__ kout,
+                                                        int64_t* __restrict__ vout, SysArgs a,
+                                                        int shift, uint32_t n_tiles,
+                                                        const uint32_t* __restrict__ hist,
+                                                        const uint64_t* __restrict__ offs) {
+    __shared__ uint64_t stage[RADIX_TILE];         // the tile's keys, then values, in digit order
+    __shared__ uint16_t sdig[RADIX_TILE];          // the digit of each staged slot
+    __shared__ uint64_t gbase[RADIX];              // global slot of each digit's first item
+    __shared__ uint32_t lstart[RADIX];             // tile slot of each digit's first item
+    __shared__ uint32_t wcnt[T256 / 64][RADIX];    // items of each digit per wavefront
+    __shared__ uint32_t wsum[T256 / 64];
+    const uint64_t n = n_events_of(a);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t lane_lt = (1ull << lane) - 1ull;
+    const uint32_t tile = tile_of(blockIdx.x, n);
+    const uint64_t base = (uint64_t)tile * RADIX_TILE;
+    if (base >= n) return;       // an empty tile (the whole workgroup leaves)
+    const uint64_t wbase = base + (uint64_t)wave * RADIX_WAVE_ITEMS;
+
+    uint64_t k[RADIX_ITEMS];
+    int64_t v[RADIX_ITEMS];
+#pragma unroll
+    for (int j = 0; j < RADIX_ITEMS; ++j) {
+        const uint64_t i = wbase + (uint64_t)j * 64 + lane;
+        k[j] = i < n ? kin[i] : 0;
+        v[j] = i < n ? vin[i] : 0;
+    }
+    // tile slots: exclusive scan of this tile's digit counts
+    const uint32_t c = hist[(uint64_t)threadIdx.x * n_tiles + tile];
+    gbase[threadIdx.x] = offs[(uint64_t)threadIdx.x * n_tiles + tile];
+#pragma unroll
+    for (int w = 0; w < T256 / 64; ++w) wcnt[w][threadIdx.x] = 0;
+    uint32_t x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+    lstart[threadIdx.x] = pre + x - c;
+
+    // rank within this wavefront: items of the same digit in earlier rounds
+    // (the running count) plus lower lanes of this round
+    uint32_t rk[RADIX_ITEMS];
+#pragma unroll
+    for (int j = 0; j < RADIX_ITEMS; ++j) {
+        const bool ok = wbase + (uint64_t)j * 64 + lane < n;
+        const uint32_t d = ok ? (uint32_t)(k[j] >> shift) & (RADIX - 1) : 0;
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < RADIX_BITS; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
         }
-        __syncthreads();
-        const uint32_t nl = n_list;
-        for (uint32_t q = 0; q < nl; ++q) {
-            const uint64_t r = r0 + (uint64_t)list[q] * stride;
-            const uint64_t b = start[r], n = start[r + 1] - b;
-            const bool agg = AGG && n > CAP;
-            uint32_t m = CAP;
-            if (!agg) {
-                m = 1;
-                while (m < n) m <<= 1;
-                for (uint32_t i = t; i < m; i += T256) {
-                    key[i] = i < n ? tmp_col[b + i] : 0xFFFFFFFFu;
-                    wt[i] = i < n ? tmp_w[b + i] : 0;
-                }
-            } else {
-                for (uint32_t i = t; i < CAP; i += T256) { key[i] = 0xFFFFFFFFu; wt[i] = 0; }
-            }
-            if (t == 0) { n_distinct = 0; overflow = 0; }
-            __syncthreads();
-            if (agg) {
-                for (uint64_t i = t; i < n; i += T256) {
-                    const uint32_t c = tmp_col[b + i];
-                    const int64_t w = tmp_w[b + i];
-                    uint32_t h = col_hash(c);
-                    uint32_t probe = 0;
-                    for (; probe < CAP; ++probe, h = (h + 1) & (CAP - 1)) {
-                        const uint32_t cur = atomicCAS(&key[h], 0xFFFFFFFFu, c);
-                        if (cur == 0xFFFFFFFFu || cur == c) {
-                            atomicAdd((unsigned long long*)&wt[h], (unsigned long long)w);
-                            break;
-                        }
-                    }
-                    if (probe == CAP) overflow = 1;
-                }
-                __syncthreads();
-                if (overflow) {                   // left to the heapsort
-                    if (t == 0) row_nnz[r] = ROW_OVERFLOW;
-                    __syncthreads();
-                    continue;
-                }
-            }
-            for (uint32_t k = 2; k <= m; k <<= 1) {
-                for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                    for (uint32_t i = t; i < m; i += T256) {
-                        const uint32_t x = i ^ j;
-                        if (x > i) {
-                            const bool up = (i & k) == 0;
-                            const uint32_t ki = key[i], kx = key[x];
-                            if ((ki > kx) == up) {
-                                key[i] = kx; key[x] = ki;
-                                const int64_t tw = wt[i]; wt[i] = wt[x]; wt[x] = tw;
-                            }
-                        }
-                    }
-                    __syncthreads();
-                }
-            }
-            if (!agg) {
-                uint32_t d = 0;
-                for (uint32_t i = t; i < n; i += T256) {
-                    tmp_col[b + i] = key[i];
-                    tmp_w[b + i] = wt[i];
-                    d += (i == 0 || key[i] != key[i - 1]);
-                }
-                atomicAdd(&n_distinct, d);
-            } else {
-                // distinct columns: the slots before the first empty one
-                uint32_t d = 0;
-                for (uint32_t i = t; i < CAP; i += T256) d += key[i] != 0xFFFFFFFFu;
-                atomicAdd(&n_distinct, d);
-                __syncthreads();
-                const uint32_t nd = n_distinct;
-                for (uint64_t i = t; i < n; i += T256) {
-                    tmp_col[b + i] = i < nd ? key[i] : key[nd - 1];
-                    tmp_w[b + i] = i < nd ? wt[i] : 0;
-                }
-            }
-            __syncthreads();
-            if (t == 0) row_nnz[r] = n_distinct;
-            __syncthreads();
+        const uint32_t rank = (uint32_t)__popcll(peers & lane_lt);
+        const uint32_t before = ok ? wcnt[wave][d] : 0;
+        rk[j] = before + rank;
+        if (ok && rank == 0) wcnt[wave][d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // tile slots of this lane's items (kept for the second staging)
+    uint32_t slot[RADIX_ITEMS];
+#pragma unroll
+    for (int j = 0; j < RADIX_ITEMS; ++j) {
+        slot[j] = RADIX_TILE;
+        if (wbase + (uint64_t)j * 64 + lane >= n) continue;
+        const uint32_t d = (uint32_t)(k[j] >> shift) & (RADIX - 1);
+        uint32_t sl = lstart[d] + rk[j];
+        for (int w = 0; w < wave; ++w) sl += wcnt[w][d];
+        slot[j] = sl;
+        if (sl < RADIX_TILE) {
+            stage[sl] = k[j];
+            sdig[sl] = (uint16_t)d;
         }
+    }
+    __syncthreads();
+    const uint64_t in_tile = n - base < RADIX_TILE ? n - base : RADIX_TILE;
+    for (uint32_t t = threadIdx.x; t < in_tile; t += T256) {
+        const uint32_t d = sdig[t];
+        const uint64_t pos = gbase[d] + (t - lstart[d]);
+        if (pos < a.capacity) kout[pos] = stage[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RADIX_ITEMS; ++j)
+        if (slot[j] < RADIX_TILE) stage[slot[j]] = (uint64_t)v[j];
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < in_tile; t += T256) {
+        const uint32_t d = sdig[t];
+        const uint64_t pos = gbase[d] + (t - lstart[d]);
+        if (pos < a.capacity) vout[pos] = (int64_t)stage[t];
     }
 }
 
-// distinct columns with their counts -> CSR column and value arrays
-__global__ __launch_bounds__(T256) void k_emit_rows(SysArgs a, int transpose, uint64_t n_rows,
-                                                    const uint64_t* start, const uint32_t* tmp_col,
-                                                    const int64_t* tmp_w,
-                                                    const uint64_t* rowptr_u, int64_t* rowptr,
-                                                    int32_t* col, float* val,
-                                                    const unsigned long long* a_img,
-                                                    const unsigned long long* total_p, float* proj) {
-    const double total = (double)*total_p;
+// start[r] (r = 0..n_rows): first sorted position whose row is >= r (a
+// binary search, so start is non-decreasing and within [0, n] whatever the
+// keys hold); the filtered events (row n_rows) follow start[n_rows].
+__global__ __launch_bounds__(T256) void k_row_starts(const uint64_t* __restrict__ keys, SysArgs a,
+                                                     int col_bits, uint64_t n_rows,
+                                                     uint64_t* __restrict__ start) {
+    const uint64_t n = n_events_of(a);
     for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n_rows;
          r += (uint64_t)gridDim.x * blockDim.x) {
-        rowptr[r] = (int64_t)rowptr_u[r];
-        if (r == n_rows) continue;
-        const uint64_t b = start[r], e = start[r + 1];
-        if (e - b > ROW_SHORT) continue;          // k_emit_rows_wave
-        uint64_t o = rowptr_u[r];
-        if (!transpose && proj) {
-            long long tot = 0;
-            for (uint64_t i = b; i < e; ++i) tot += tmp_w[i];
-            proj[r] = (float)((double)tot * 0x1p-32);
+        const uint64_t key = r << col_bits;
+        uint64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < key) lo = mid + 1; else hi = mid;
         }
-        uint64_t i = b;
-        while (i < e) {
-            const uint32_t c = tmp_col[i];
-            uint64_t j = i;
-            long long cw = 0;
-            while (j < e && tmp_col[j] == c) { cw += tmp_w[j]; ++j; }
-            const uint32_t bin = transpose ? c : (uint32_t)r;
-            const uint32_t img = transpose ? (uint32_t)r : c;
-            const uint64_t view = bin / a.nv_nu;
-            const double n_view = (double)(a.q_per_view + (view < a.r_extra ? 1u : 0u));
-            const double n_i = n_view * (double)a_img[img] / total;
-            col[o] = (int32_t)c;
-            val[o] = (float)((double)cw * 0x1p-32 / n_i);
-            ++o;
-            i = j;
-        }
+        start[r] = lo;
     }
 }
 
+// flag[i] = 1 where a run of equal keys starts, for the valid (unfiltered)
+// items i < start[n_rows] (the scan below reads no further)
+__global__ __launch_bounds__(T256) void k_run_heads(const uint64_t* __restrict__ keys,
+                                                    const uint64_t* __restrict__ start,
+                                                    uint64_t n_rows, uint64_t capacity,
+                                                    uint32_t* __restrict__ flag) {
+    const uint64_t n_valid = start[n_rows] < capacity ? start[n_rows] : capacity;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_valid;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        flag[i] = i == 0 || keys[i] != keys[i - 1];
+}
 
-// The same for rows longer than ROW_SHORT, one wavefront per row: the lanes
-// take 64 consecutive entries at a time, each entry that starts a run of
-// equal columns gets its output slot from a ballot and sums its run (runs
-// are short), so the reads are coalesced.  Rows are screened 64 at a time,
-// gridDim.x apart.
-__global__ __launch_bounds__(64) void k_emit_rows_wave(SysArgs a, int transpose, uint64_t n_rows,
-                                                       const uint64_t* start, const uint32_t* tmp_col,
-                                                       const int64_t* tmp_w, const uint64_t* rowptr_u,
-                                                       int32_t* col, float* val,
-                                                       const unsigned long long* a_img,
-                                                       const unsigned long long* total_p, float* proj) {
+// rowptr[r] = distinct entries before row r (head_pos: exclusive scan of the run heads)
+__global__ __launch_bounds__(T256) void k_rows_from_runs(const uint64_t* __restrict__ start,
+                                                         const uint64_t* __restrict__ head_pos,
+                                                         uint64_t n_rows, int64_t* __restrict__ rowptr) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n_rows;
+         r += (uint64_t)gridDim.x * blockDim.x)
+        rowptr[r] = (int64_t)head_pos[start[r]];
+}
+
+// Each run of equal keys (one distinct (row, column)) becomes CSR entry
+// head_pos[i] of its first item i: the column and T = c / n_i(j), with c the
+// run's summed weight.
+__global__ __launch_bounds__(T256) void k_emit_runs(SysArgs a, int transpose,
+                                                    const uint64_t* __restrict__ keys,
+                                                    const int64_t* __restrict__ w,
+                                                    const uint64_t* __restrict__ start,
+                                                    const uint64_t* __restrict__ head_pos,
+                                                    uint64_t n_rows, int col_bits,
+                                                    int32_t* __restrict__ col, float* __restrict__ val,
+                                                    const unsigned long long* __restrict__ a_img,
+                                                    const unsigned long long* __restrict__ total_p) {
+    const uint64_t n_valid = start[n_rows];
     const double total = (double)*total_p;
-    const uint32_t lane = threadIdx.x;
-    const uint64_t lane_lt = (1ull << lane) - 1ull;
-    const uint64_t stride = gridDim.x;
-    for (uint64_t r0 = blockIdx.x; r0 < n_rows; r0 += stride * 64) {
-        bool need = false;
-        const uint64_t rl = r0 + lane * stride;
-        if (rl < n_rows) need = start[rl + 1] - start[rl] > ROW_SHORT;
-        for (uint64_t todo = __ballot(need); todo != 0; todo &= todo - 1) {
-            const uint64_t r = r0 + (uint64_t)(__ffsll((unsigned long long)todo) - 1) * stride;
-            const uint64_t b = start[r], e = start[r + 1];
-            uint64_t o = rowptr_u[r];
-            long long tot = 0;
-            for (uint64_t c0 = b; c0 < e; c0 += 64) {
-                const uint64_t i = c0 + lane;
-                const bool valid = i < e;
-                uint32_t c = 0;
-                bool first = false;
-                if (valid) {
-                    c = tmp_col[i];
-                    tot += tmp_w[i];
-                    first = i == b || tmp_col[i - 1] != c;
-                }
-                const uint64_t m = __ballot(first);
-                if (first) {
-                    long long cw = 0;
-                    for (uint64_t j = i; j < e && tmp_col[j] == c; ++j) cw += tmp_w[j];
-                    const uint32_t bin = transpose ? c : (uint32_t)r;
-                    const uint32_t img = transpose ? (uint32_t)r : c;
-                    const uint64_t view = bin / a.nv_nu;
-                    const double n_view = (double)(a.q_per_view + (view < a.r_extra ? 1u : 0u));
-                    const double n_i = n_view * (double)a_img[img] / total;
-                    const uint64_t slot = o + (uint64_t)__popcll(m & lane_lt);
-                    col[slot] = (int32_t)c;
-                    val[slot] = (float)((double)cw * 0x1p-32 / n_i);
-                }
-                o += (uint64_t)__popcll(m);
-            }
-            if (!transpose && proj) {
-                for (int k = 32; k > 0; k >>= 1) tot += __shfl_xor(tot, k, 64);
-                if (lane == 0) proj[r] = (float)((double)tot * 0x1p-32);
-            }
-        }
+    const uint64_t mask = (1ull << col_bits) - 1ull;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_valid;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[i];
+        if (i > 0 && keys[i - 1] == k) continue;
+        long long cw = 0;
+        for (uint64_t j = i; j < n_valid && keys[j] == k; ++j) cw += w[j];
+        const uint32_t r = (uint32_t)(k >> col_bits), c = (uint32_t)(k & mask);
+        const uint32_t bin = transpose ? c : r;
+        const uint32_t img = transpose ? r : c;
+        const uint64_t view = bin / a.nv_nu;
+        const double n_view = (double)(a.q_per_view + (view < a.r_extra ? 1u : 0u));
+        const double n_i = n_view * (double)a_img[img] / total;
+        const uint64_t o = head_pos[i];
+        col[o] = (int32_t)c;
+        val[o] = (float)((double)cw * 0x1p-32 / n_i);
+    }
+}
+
+// P_j = the summed weight of bin row j's events (all its items)
+__global__ __launch_bounds__(T256) void k_proj_rows(const int64_t* __restrict__ w,
+                                                    const uint64_t* __restrict__ start,
+                                                    uint64_t n_rows, float* __restrict__ proj) {
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        long long tot = 0;
+        for (uint64_t i = start[r]; i < start[r + 1]; ++i) tot += w[i];
+        proj[r] = (float)((double)tot * 0x1p-32);
     }
 }
 
@@ -970,14 +890,48 @@ hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int
 }
 
 // Workspace of the response-matrix build, in bytes (layout below).
-size_t sysmat_workspace_bytes(uint64_t n_bins, uint64_t n_img, uint64_t capacity) {
-    const uint64_t nr = n_bins > n_img ? n_bins : n_img;
+// Workspace of the response-matrix build (layout in sysmat_layout).
+struct SysLayout {
+    uint64_t* start;       // [nr + 1] row starts in the sorted items
+    uint64_t* bsum;        // scan block sums
+    uint32_t* hist;        // [RADIX * n_tiles] digit histograms
+    uint64_t* offs;        // [RADIX * n_tiles + 1] their exclusive scan
+    uint64_t* keys[2];     // [cap + 1] sort keys (double buffer; the spare one
+                           //  then holds the run-head positions)
+    int64_t* vals[2];      // [cap] weights, Q31.32
+    uint32_t* flag;        // [cap] run heads
+    unsigned long long* a_img;   // [n_img + 1] activity per image voxel, then the total
+    size_t bytes;
+};
+
+SysLayout sysmat_layout(char* w, uint64_t n_bins, uint64_t n_img, uint64_t capacity) {
     auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
-    const uint64_t nb = (nr + 1 + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    return al(4 * nr) /* cnt */ + al(4 * nr) /* fill */ + al(8 * (nr + 1)) /* start */
-         + al(8 * (nr + 1)) /* rowptr_u */ + al(4 * nr) /* row_nnz */ + al(8 * nb) /* bsum */
-         + al(4 * (capacity ? capacity : 1)) /* tmp_col */ + al(8 * (capacity ? capacity : 1)) /* tmp_w */
-         + al(8 * (n_img + 1)) /* a_img, total */;
+    const uint64_t nr = n_bins > n_img ? n_bins : n_img;
+    const uint64_t cap = capacity ? capacity : 1;
+    const uint64_t n_tiles = (cap + RADIX_TILE - 1) / RADIX_TILE;
+    uint64_t scan_n = nr;
+    if (cap > scan_n) scan_n = cap;
+    if (RADIX * n_tiles > scan_n) scan_n = RADIX * n_tiles;
+    const uint64_t nb = (scan_n + 1 + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    SysLayout L;
+    char* p = w;
+    auto take = [&](uint64_t bytes) { char* q = p; p += al(bytes); return q; };
+    L.start = (uint64_t*)take(8 * (nr + 1));
+    L.bsum = (uint64_t*)take(8 * nb);
+    L.hist = (uint32_t*)take(4 * RADIX * n_tiles);
+    L.offs = (uint64_t*)take(8 * (RADIX * n_tiles + 1));
+    L.keys[0] = (uint64_t*)take(8 * (cap + 1));
+    L.keys[1] = (uint64_t*)take(8 * (cap + 1));
+    L.vals[0] = (int64_t*)take(8 * cap);
+    L.vals[1] = (int64_t*)take(8 * cap);
+    L.flag = (uint32_t*)take(4 * cap);
+    L.a_img = (unsigned long long*)take(8 * (n_img + 1));
+    L.bytes = (size_t)(p - w);
+    return L;
+}
+
+size_t sysmat_workspace_bytes(uint64_t n_bins, uint64_t n_img, uint64_t capacity) {
+    return sysmat_layout(nullptr, n_bins, n_img, capacity).bytes;
 }
 
 hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_events, uint64_t capacity,
@@ -989,19 +943,10 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
     const uint64_t n_bins = (uint64_t)n_views * nu * nv;
     const uint32_t mx = nx / f, my = ny / f, mz = nz / f;
     const uint64_t n_img = (uint64_t)mx * my * mz;
-    const uint64_t nr = n_bins > n_img ? n_bins : n_img;
-    auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
-    char* w = (char*)workspace;
-    uint32_t* cnt = (uint32_t*)w;          w += al(4 * nr);
-    uint32_t* fill = (uint32_t*)w;         w += al(4 * nr);
-    uint64_t* start = (uint64_t*)w;        w += al(8 * (nr + 1));
-    uint64_t* rowptr_u = (uint64_t*)w;     w += al(8 * (nr + 1));
-    uint32_t* row_nnz = (uint32_t*)w;      w += al(4 * nr);
-    const uint64_t nb = (nr + 1 + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    uint64_t* bsum = (uint64_t*)w;         w += al(8 * nb);
-    uint32_t* tmp_col = (uint32_t*)w;      w += al(4 * (capacity ? capacity : 1));
-    int64_t* tmp_w = (int64_t*)w;          w += al(8 * (capacity ? capacity : 1));
-    unsigned long long* a_img = (unsigned long long*)w;   // n_img entries, then the total
+    const SysLayout L = sysmat_layout((char*)workspace, n_bins, n_img, capacity);
+    const uint64_t cap = capacity ? capacity : 1;
+    const uint32_t n_tiles = (uint32_t)((cap + RADIX_TILE - 1) / RADIX_TILE);
+    unsigned long long* a_img = L.a_img;
     unsigned long long* total = a_img + n_img;
 
     SysArgs a;
@@ -1014,33 +959,37 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
     k_fill_u64<<<grid_for(n_img + 1, T256, 4096), T256, 0, s>>>((uint64_t*)a_img, n_img + 1, 0);
     k_image_activity<<<grid_for((uint64_t)nx * ny * nz, T256, 8192), T256, 0, s>>>(
         activity, nx, ny, nz, f, mx, my, a_img, total);
-    const int ge = grid_for(capacity ? capacity : 1, T256, 8192);
+    const int ge = grid_for(cap, T256, 8192);
     for (int transpose = 0; transpose < 2; ++transpose) {
         const uint64_t n_rows = transpose ? n_img : n_bins;
-        k_fill_u32<<<grid_for(n_rows, T256, 4096), T256, 0, s>>>(cnt, n_rows, 0);
-        k_fill_u32<<<grid_for(n_rows, T256, 4096), T256, 0, s>>>(fill, n_rows, 0);
-        k_count_rows<<<ge, T256, 0, s>>>(a, transpose, cnt);
-        hipError_t e = exclusive_scan(cnt, n_rows, start, bsum, s);
+        const uint64_t n_cols = transpose ? n_bins : n_img;
+        // rows 0..n_rows (n_rows: filtered events), columns 0..n_cols - 1
+        const int col_bits = std::max(1, bit_width(n_cols - 1));
+        const int key_bits = col_bits + bit_width(n_rows);
+        k_make_keys<<<ge, T256, 0, s>>>(a, transpose, n_rows, col_bits, L.keys[0], L.vals[0]);
+        int cur = 0;
+        for (int shift = 0; shift < key_bits; shift += RADIX_BITS) {
+            k_radix_hist<<<n_tiles, T256, 0, s>>>(L.keys[cur], a, shift, n_tiles, L.hist);
+            hipError_t e = exclusive_scan(L.hist, (uint64_t)RADIX * n_tiles, L.offs, L.bsum, s);
+            if (e != hipSuccess) return e;
+            k_radix_scatter<<<n_tiles, T256, 0, s>>>(L.keys[cur], L.vals[cur], L.keys[cur ^ 1],
+                                                     L.vals[cur ^ 1], a, shift, n_tiles, L.hist, L.offs);
+            cur ^= 1;
+        }
+        const uint64_t* keys = L.keys[cur];
+        const int64_t* w = L.vals[cur];
+        uint64_t* head_pos = L.keys[cur ^ 1];
+        k_row_starts<<<grid_for(n_rows + 1, T256, 8192), T256, 0, s>>>(keys, a, col_bits, n_rows, L.start);
+        k_run_heads<<<ge, T256, 0, s>>>(keys, L.start, n_rows, cap, L.flag);
+        hipError_t e = exclusive_scan(L.flag, cap, head_pos, L.bsum, s, L.start + n_rows);
         if (e != hipSuccess) return e;
-        k_scatter<<<ge, T256, 0, s>>>(a, transpose, start, fill, tmp_col, tmp_w);
-        k_sort_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz, 0);
-        const int gw = (int)std::min<uint64_t>(n_rows ? (n_rows + 63) / 64 : 1, 16384);
-        k_sort_rows_wave<ROW_SHORT, 256><<<gw, 64, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
-        k_sort_rows_wave<256, 1024><<<gw, 64, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
-        // rows of 1025..4096 entries: one 256-thread block each (below)
-        const int gb = (int)std::min<uint64_t>(n_rows ? (n_rows + T256 - 1) / T256 : 1, 4096);
-        k_sort_rows_block<1024, ROW_LDS, false><<<gb, T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
-        k_sort_rows_block<ROW_LDS, ROW_BIG, true><<<gb, T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz);
-        k_sort_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(n_rows, start, tmp_col, tmp_w, row_nnz, 1);
-        e = exclusive_scan(row_nnz, n_rows, rowptr_u, bsum, s);
-        if (e != hipSuccess) return e;
-        k_emit_rows<<<grid_for(n_rows + 1, T256, 8192), T256, 0, s>>>(
-            a, transpose, n_rows, start, tmp_col, tmp_w, rowptr_u, transpose ? Tt_rp : T_rp,
-            transpose ? Tt_col : T_col, transpose ? Tt_val : T_val, a_img, total,
-            transpose ? nullptr : proj);
-        k_emit_rows_wave<<<gw, 64, 0, s>>>(a, transpose, n_rows, start, tmp_col, tmp_w, rowptr_u,
-                                           transpose ? Tt_col : T_col, transpose ? Tt_val : T_val,
-                                           a_img, total, transpose ? nullptr : proj);
+        k_rows_from_runs<<<grid_for(n_rows + 1, T256, 8192), T256, 0, s>>>(
+            L.start, head_pos, n_rows, transpose ? Tt_rp : T_rp);
+        k_emit_runs<<<ge, T256, 0, s>>>(a, transpose, keys, w, L.start, head_pos, n_rows, col_bits,
+                                        transpose ? Tt_col : T_col, transpose ? Tt_val : T_val,
+                                        a_img, total);
+        if (!transpose && proj)
+            k_proj_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(w, L.start, n_rows, proj);
     }
     return hipGetLastError();
 }

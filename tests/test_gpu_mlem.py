@@ -303,12 +303,12 @@ def test_dual_matrix_and_scatter_forms_thorax():
 
 
 def test_system_matrix_row_length_classes():
-    """A hand-made weighted event list whose voxel rows span every sorting
-    path of the response-matrix build (short rows, one wavefront up to 4096
-    entries, one block up to 8192, LDS column sums beyond, heapsort for a
-    row of more than 8192 distinct columns) and whose bin rows repeat
-    columns: the CSR matches the oracle's matrix from the same contributions
-    (sums of Q31.32 weights, exact before the FP32 store)."""
+    """A hand-made weighted event list whose voxel rows range from 1 to
+    20000 events (one with 12000 distinct columns, one with 20000 events over
+    3000 columns) and whose bin rows repeat columns: long rows cross many
+    radix tiles and runs of equal keys span tile boundaries.  The CSR matches
+    the oracle's matrix from the same contributions (sums of Q31.32 weights,
+    exact before the FP32 store)."""
     import types
     import torch
     mc = _mc()

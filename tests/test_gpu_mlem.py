@@ -364,3 +364,51 @@ def test_system_matrix_row_length_classes():
     for img, n in lengths.items():
         assert rows[img] == len(np.unique(bins[emit == phantom_voxel(img)] // (2 * per) * per
                                           + bins[emit == phantom_voxel(img)] % per))
+
+
+@pytest.mark.parametrize("case", ["empty", "over_capacity", "garbage_tail", "primary", "scatter"])
+def test_system_matrix_list_edges(case):
+    """Event-list edge cases of the response-matrix build against the oracle:
+    an empty list (every row pointer 0, P = 0); a device-side count above the
+    capacity (only the first `capacity` events count); slots past the count
+    holding garbage (never read); the primary-only and scatter-only classes."""
+    import types
+    import torch
+    mc = _mc()
+    p = phantoms.thorax_problem("edges", 32, 1.2, 4, 4, 360.0, 16, 0.6, 1_000_000, image_factor=2)
+    p = p.with_(activity=np.ones_like(p.activity))
+    per = p.nv * p.nu
+    n_bins_cls = p.n_views * 2 * per
+    rng = np.random.Generator(np.random.PCG64(91))
+    n_ev = 0 if case == "empty" else 50_000
+    emit = rng.integers(0, p.nx * p.ny * p.nz, size=n_ev).astype(np.uint32)
+    bins = rng.integers(0, n_bins_cls, size=n_ev).astype(np.uint32)
+    w = rng.integers(1, 1 << 34, size=n_ev).astype(np.int64)
+    cap = {"empty": 1000, "over_capacity": 30_000, "garbage_tail": 80_000}.get(case, n_ev)
+    ev = np.zeros(cap, dtype=mc.EVENT_DTYPE)
+    used = min(n_ev, cap)
+    ev["bin"][:used], ev["emit_voxel"][:used], ev["weight"][:used] = bins[:used], emit[:used], w[:used]
+    if case == "garbage_tail":       # out-of-range bins and voxels past the count
+        ev["bin"][n_ev:] = 0xFFFFFFF0
+        ev["emit_voxel"][n_ev:] = 0xFFFFFFF0
+        ev["weight"][n_ev:] = -1
+    raw = torch.from_numpy(ev.view(np.int64).reshape(cap, 3).copy()).cuda()
+    sim = types.SimpleNamespace(events=raw, event_capacity=cap,
+                                n_events=torch.tensor([n_ev], dtype=torch.int64, device="cuda"))
+    classes = case if case in ("primary", "scatter") else "all"
+    m = mc.system_matrix(mc.to_device(p), sim, classes=classes)
+    mx = p.nx // p.image_factor
+    f = p.image_factor
+    img_of = lambda v: ((v % p.nx) // f) + mx * (((v // p.nx) % p.ny) // f + (p.ny // f) * ((v // (p.nx * p.ny)) // f))
+    To, Po, _ = oracle.system_matrix(p, img_of(emit[:used].astype(np.int64)), bins[:used].astype(np.int64),
+                                     classes=classes, trip_w=w[:used].astype(np.float64) / 2.0 ** 32)
+    Tg = m.to_scipy().astype(np.float64)
+    Tt = m.to_scipy(transpose=True).astype(np.float64)
+    say(f"{case}: {used} events, nnz {Tg.nnz} (oracle {To.nnz})")
+    assert Tg.nnz == To.nnz and Tt.nnz == To.nnz
+    if To.nnz:
+        assert abs(Tg - To).max() <= 1e-6 * abs(To).max()
+        assert abs(Tt - To.T.tocsr()).max() <= 1e-6 * abs(To).max()
+    else:
+        assert not m.T_rowptr.any().item() and not m.Tt_rowptr.any().item()
+    np.testing.assert_allclose(m.proj.cpu().numpy(), Po, rtol=1e-6, atol=0)

@@ -98,10 +98,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="time only the headline workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 256^3 / 1e9-history form")
-    ap.add_argument("--only-form", choices=["forced_detection", "batched"], default=None,
+    ap.add_argument("--only-form", choices=["forced_detection", "batched", "large_mlem"], default=None,
                     help="time only this side form (forced_detection: forced detection and "
-                         "its convolution-based form; batched: the 32-thorax graph) and print "
-                         "its record; for profiling")
+                         "its convolution-based form; batched: the 32-thorax graph; large_mlem: "
+                         "the 256^3 thorax with response matrices and MLEM) and print its "
+                         "record; for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -123,7 +124,7 @@ def main():
     import phantoms
     import paper_2105_13324_amd as mc
     if args.only_form:
-        fn = {"forced_detection": fd_form, "batched": batched_form}[args.only_form]
+        fn = {"forced_detection": fd_form, "batched": batched_form, "large_mlem": large_form}[args.only_form]
         print(json.dumps({"form": args.only_form, **fn(mc, torch, args.steps)}))
         return
 

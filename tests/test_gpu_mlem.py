@@ -366,12 +366,15 @@ def test_system_matrix_row_length_classes():
                                           + bins[emit == phantom_voxel(img)] % per))
 
 
-@pytest.mark.parametrize("case", ["empty", "over_capacity", "garbage_tail", "primary", "scatter"])
+@pytest.mark.parametrize("case", ["empty", "over_capacity", "garbage_tail", "primary", "scatter",
+                                  "one_key", "reverse_sorted"])
 def test_system_matrix_list_edges(case):
     """Event-list edge cases of the response-matrix build against the oracle:
     an empty list (every row pointer 0, P = 0); a device-side count above the
     capacity (only the first `capacity` events count); slots past the count
-    holding garbage (never read); the primary-only and scatter-only classes."""
+    holding garbage (never read); the primary-only and scatter-only classes;
+    every event on one (voxel, bin) key (one run across all radix tiles); a
+    list in descending key order."""
     import types
     import torch
     mc = _mc()
@@ -384,6 +387,11 @@ def test_system_matrix_list_edges(case):
     emit = rng.integers(0, p.nx * p.ny * p.nz, size=n_ev).astype(np.uint32)
     bins = rng.integers(0, n_bins_cls, size=n_ev).astype(np.uint32)
     w = rng.integers(1, 1 << 34, size=n_ev).astype(np.int64)
+    if case == "one_key":
+        emit[:], bins[:] = emit[0], bins[0]
+    if case == "reverse_sorted":
+        order = np.lexsort((emit, bins))[::-1]
+        emit, bins, w = emit[order], bins[order], w[order]
     cap = {"empty": 1000, "over_capacity": 30_000, "garbage_tail": 80_000}.get(case, n_ev)
     ev = np.zeros(cap, dtype=mc.EVENT_DTYPE)
     used = min(n_ev, cap)

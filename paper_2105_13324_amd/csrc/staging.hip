@@ -29,6 +29,7 @@ namespace mcs {
 namespace {
 
 constexpr int RED_THREADS = 256;
+constexpr int ROWS = 4;        // grid rows a row pass loads at once
 
 __device__ inline uint64_t wave_sum_u64(uint64_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -59,21 +60,33 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* descs) {
     uint32_t mx = 0, flags = 0;
     uint64_t sum = 0;
     int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {-1, -1, -1};
-    // one grid row (iy, iz) per block step, threads along x: no index division
+    // grid rows (iy, iz) per block step, threads along x: no index division;
+    // ROWS rows per step, their loads issued before any is used
     const uint32_t nrows = ny * (uint32_t)pd->nz;
-    for (uint32_t r = blockIdx.x; r < nrows; r += gridDim.x) {
-        const int iy = (int)(r % ny), iz = (int)(r / ny);
-        for (uint32_t ix = threadIdx.x; ix < nx; ix += blockDim.x) {
+    for (uint32_t r0 = blockIdx.x; r0 < nrows; r0 += ROWS * gridDim.x)
+    for (uint32_t ix = threadIdx.x; ix < nx; ix += blockDim.x) {
+        float m[ROWS];
+        uint32_t w[ROWS];
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) {
+            const uint32_t r = r0 + (uint32_t)u * gridDim.x;
             const uint64_t i = (uint64_t)r * nx + ix;
-            const float m = mu[i];
-            if (!(m >= 0.0f) || !isfinite(m)) flags |= MC_STATUS_BAD_MU;
-            else if (m > 0.0f) {
-                mx = max(mx, __float_as_uint(m));
+            m[u] = r < nrows ? mu[i] : 0.0f;
+            w[u] = r < nrows ? source_weight(act, prev, i) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) {
+            const uint32_t r = r0 + (uint32_t)u * gridDim.x;
+            if (r >= nrows) break;
+            const int iy = (int)(r % ny), iz = (int)(r / ny);
+            if (!(m[u] >= 0.0f) || !isfinite(m[u])) flags |= MC_STATUS_BAD_MU;
+            else if (m[u] > 0.0f) {
+                mx = max(mx, __float_as_uint(m[u]));
                 lo[0] = min(lo[0], (int)ix); hi[0] = max(hi[0], (int)ix);
                 lo[1] = min(lo[1], iy); hi[1] = max(hi[1], iy);
                 lo[2] = min(lo[2], iz); hi[2] = max(hi[2], iz);
             }
-            sum += source_weight(act, prev, i);
+            sum += w[u];
         }
     }
     (void)nvox;
@@ -164,24 +177,21 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* descs) {
     const bool pal = pd->pal_state == 0;
     bool full = false;
     const uint32_t nrows = ny * (uint32_t)pd->nz;
-    (void)nvox;
     // the block's own set of the values it has put in the palette: a value
     // reaches the global table once per block, not once per wavefront
     __shared__ uint32_t seen[PALETTE_N];
     for (int k = threadIdx.x; k < PALETTE_N; k += blockDim.x) seen[k] = PALETTE_EMPTY;
     __syncthreads();
-    for (uint32_t r = blockIdx.x; r < nrows; r += gridDim.x)
-    for (uint32_t ix = threadIdx.x; ix < nx; ix += blockDim.x) {
-        const uint32_t iy = r % ny, iz = r / ny;
-        const float mv = mu[(uint64_t)r * nx + ix];
+    // Q of one value, and its palette entry: a wavefront inserts each of its
+    // distinct values once (leader lane); lanes with ok = false only vote
+    auto threshold = [&](float mv, bool ok) -> uint32_t {
         uint32_t v = 0;
-        if (mu_hat > 0.0f && mv > 0.0f) {
-            double t = ceil((double)mv * 16777216.0 / (double)mu_hat);
+        if (ok && mu_hat > 0.0f && mv > 0.0f) {
+            const double t = ceil((double)mv * 16777216.0 / (double)mu_hat);
             v = t >= 16777216.0 ? 16777216u : (uint32_t)t;
         }
-        q[brick_index(ix, iy, iz, nx, ny, b, m, nbx, nby)] = v;
         if (pal && !full) {
-            bool todo = true;
+            bool todo = ok;
             for (;;) {
                 const uint64_t left = __ballot(todo);
                 if (left == 0) break;
@@ -191,6 +201,44 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* descs) {
                     palette_insert(pd->palette, lv) == PALETTE_N)
                     full = true;
                 if (v == lv) todo = false;
+            }
+        }
+        return v;
+    };
+    if (b == 0) {
+        // linear layout: the table index is the voxel index, so whole
+        // wavefronts stream the grid, ROWS values per thread in flight
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nvox; i0 += ROWS * stride) {
+            float mv[ROWS];
+#pragma unroll
+            for (int u = 0; u < ROWS; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * stride;
+                mv[u] = i < nvox ? mu[i] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < ROWS; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * stride;
+                const uint32_t v = threshold(mv[u], i < nvox);
+                if (i < nvox) q[i] = v;
+            }
+        }
+    } else {
+        for (uint32_t r0 = blockIdx.x; r0 < nrows; r0 += ROWS * gridDim.x)
+        for (uint32_t ix = threadIdx.x; ix < nx; ix += blockDim.x) {
+            // ROWS rows per step, their loads issued before any is used
+            float mrow[ROWS];
+#pragma unroll
+            for (int u = 0; u < ROWS; ++u) {
+                const uint32_t r = r0 + (uint32_t)u * gridDim.x;
+                mrow[u] = r < nrows ? mu[(uint64_t)r * nx + ix] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < ROWS; ++u) {
+                const uint32_t r = r0 + (uint32_t)u * gridDim.x;
+                if (r >= nrows) break;
+                const uint32_t v = threshold(mrow[u], true);
+                q[brick_index(ix, r % ny, r / ny, nx, ny, b, m, nbx, nby)] = v;
             }
         }
     }
@@ -211,15 +259,44 @@ __global__ __launch_bounds__(RED_THREADS) void k_codes(ProbDesc* descs) {
     const uint32_t m = (1u << b) - 1u;
     const uint32_t nbx = (uint32_t)pd->nbx, nby = (uint32_t)pd->nby;
     const uint32_t nrows = ny * (uint32_t)pd->nz;
-    (void)nvox;
-    for (uint32_t r = blockIdx.x; r < nrows; r += gridDim.x)
-    for (uint32_t ix = threadIdx.x; ix < nx; ix += blockDim.x) {
-        const uint32_t iy = r % ny, iz = r / ny;
-        const uint32_t k = brick_index(ix, iy, iz, nx, ny, b, m, nbx, nby);
-        const uint32_t v = q[k];
+    auto code_of = [&](uint32_t v) {
         uint32_t h = palette_hash(v);
         for (int probe = 0; probe < PALETTE_N && pal[h] != v; ++probe) h = (h + 1) & (PALETTE_N - 1);
-        code[k] = (uint8_t)h;
+        return (uint8_t)h;
+    };
+    if (b == 0) {
+        // linear layout: whole wavefronts stream the table, ROWS values per thread
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nvox; i0 += ROWS * stride) {
+            uint32_t v[ROWS];
+#pragma unroll
+            for (int u = 0; u < ROWS; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * stride;
+                v[u] = i < nvox ? q[i] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < ROWS; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * stride;
+                if (i < nvox) code[i] = code_of(v[u]);
+            }
+        }
+        return;
+    }
+    for (uint32_t r0 = blockIdx.x; r0 < nrows; r0 += ROWS * gridDim.x)
+    for (uint32_t ix = threadIdx.x; ix < nx; ix += blockDim.x) {
+        // ROWS rows per step, their loads issued before any is used
+        uint32_t k[ROWS], v[ROWS];
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) {
+            const uint32_t r = r0 + (uint32_t)u * gridDim.x;
+            k[u] = brick_index(ix, r % ny, r / ny, nx, ny, b, m, nbx, nby);
+            v[u] = r < nrows ? q[k[u]] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) {
+            if (r0 + (uint32_t)u * gridDim.x >= nrows) break;
+            code[k[u]] = code_of(v[u]);
+        }
     }
 }
 
@@ -465,8 +542,11 @@ hipError_t launch_staging_batch(ProbDesc* d, const ProbDesc* h, int n, hipStream
     const int row_threads = (int)std::min<uint64_t>(RED_THREADS, ((uint64_t)max_nx + 63) / 64 * 64);
     const unsigned ny = (unsigned)n;
     k_reduce<<<dim3((unsigned)std::min<uint64_t>(max_rows, 512), ny), row_threads, 0, st>>>(d);
-    k_thresholds<<<dim3((unsigned)std::min<uint64_t>(max_rows, 8192), ny), row_threads, 0, st>>>(d);
-    k_codes<<<dim3((unsigned)std::min<uint64_t>(max_rows, 8192), ny), row_threads, 0, st>>>(d);
+    const unsigned row_blocks = (unsigned)std::min<uint64_t>((max_rows + ROWS - 1) / ROWS, 8192);
+    // each workgroup puts each threshold value it meets into the palette once
+    // (a round trip to memory): fewer, larger workgroups for this pass
+    k_thresholds<<<dim3(std::min(row_blocks, 1024u), ny), row_threads, 0, st>>>(d);
+    k_codes<<<dim3(row_blocks, ny), row_threads, 0, st>>>(d);
     k_scan_sums<<<dim3((unsigned)max_nb, ny), SCAN_THREADS, 0, st>>>(d);
     k_scan_top<<<dim3(1, ny), 1024, 0, st>>>(d);
     k_scan_final<<<dim3((unsigned)max_nb, ny), SCAN_THREADS, 0, st>>>(d);

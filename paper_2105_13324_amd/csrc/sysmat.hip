@@ -801,7 +801,38 @@ __global__ __launch_bounds__(T256) void k_os_init(int64_t n_vox, int32_t n_sub,
 }
 
 // subset k: y_j = sum_i c_ij S_i + s_j, ratio_j = P_j / y_j on the subset's
-// bins (row t of the subset is bin j of view k + n_sub * (t / bins_per_view))
+// bins (row t of the subset is bin j of view k + n_sub * (t / bins_per_view));
+// rows swept as in MLEM, the group size following the whole matrix's density
+template <int GS>
+__device__ inline void os_forward_rows(int64_t n_sub_bins, int32_t bins_per_view, int32_t n_sub,
+                                       int32_t k, const int64_t* __restrict__ rp,
+                                       const int32_t* __restrict__ col,
+                                       const float* __restrict__ val,
+                                       const double* __restrict__ S, const float* __restrict__ P,
+                                       const float* __restrict__ scat, double* __restrict__ ratio) {
+    const RowGroups<GS> G(blockIdx.x, gridDim.x);
+    auto bin_of = [&](int64_t t) {
+        const int64_t view = k + (int64_t)n_sub * (t / bins_per_view);
+        return view * bins_per_view + t % bins_per_view;
+    };
+    sweep_rows(G, n_sub_bins,
+               [&](int64_t t, int64_t& lo, int64_t& hi) {
+                   const int64_t j = bin_of(t);
+                   lo = rp[j];
+                   hi = rp[j + 1];
+               },
+               [&](int64_t e, bool ok) {
+                   const double x = (double)val[e] * S[col[e]];
+                   return ok ? x : 0.0;
+               },
+               [&](int64_t t, int64_t, int64_t, double y) {
+                   if (G.sub != 0) return;
+                   const int64_t j = bin_of(t);
+                   y += scat ? (double)scat[j] : 0.0;
+                   ratio[j] = y > 0.0 ? (double)P[j] / y : 0.0;
+               });
+}
+
 __global__ __launch_bounds__(T256) void k_os_forward(int64_t n_sub_bins, int32_t bins_per_view,
                                                      int32_t n_sub, int32_t k,
                                                      const int64_t* __restrict__ rp,
@@ -811,28 +842,39 @@ __global__ __launch_bounds__(T256) void k_os_forward(int64_t n_sub_bins, int32_t
                                                      const float* __restrict__ P,
                                                      const float* __restrict__ scat,
                                                      double* __restrict__ ratio, int64_t n_bins) {
-    // the mode follows the whole matrix's density (the subset rows are a
-    // view-interleaved part of it)
-    const bool wave_mode = rp[n_bins] >= WAVE_ROW_MIN * n_bins;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
-    const int lane = threadIdx.x & 63;
-    const int64_t step = wave_mode ? 64 : 1;
-    const int64_t first = wave_mode ? lane : 0;
-    for (int64_t t = wave_mode ? tid >> 6 : tid; t < n_sub_bins; t += wave_mode ? nt >> 6 : nt) {
-        const int64_t view = k + (int64_t)n_sub * (t / bins_per_view);
-        const int64_t j = view * bins_per_view + t % bins_per_view;
-        double y = 0.0;
-        for (int64_t e = rp[j] + first; e < rp[j + 1]; e += step) y += (double)val[e] * S[col[e]];
-        if (wave_mode) y = wave_sum_f64(y);
-        if (!wave_mode || lane == 0) {
-            y += scat ? (double)scat[j] : 0.0;
-            ratio[j] = y > 0.0 ? (double)P[j] / y : 0.0;
-        }
+    switch (lanes_per_row(rp[n_bins], n_bins)) {
+        case 1: os_forward_rows<1>(n_sub_bins, bins_per_view, n_sub, k, rp, col, val, S, P, scat, ratio); break;
+        case 4: os_forward_rows<4>(n_sub_bins, bins_per_view, n_sub, k, rp, col, val, S, P, scat, ratio); break;
+        case 16: os_forward_rows<16>(n_sub_bins, bins_per_view, n_sub, k, rp, col, val, S, P, scat, ratio); break;
+        default: os_forward_rows<64>(n_sub_bins, bins_per_view, n_sub, k, rp, col, val, S, P, scat, ratio); break;
     }
 }
 
 // subset k: S_i <- S_i * (sum_{j in k} b_ij ratio_j) / sens_k,i (unchanged where sens_k,i = 0)
+template <int GS>
+__device__ inline void os_update_rows(int64_t n_vox, int32_t bins_per_view, int32_t n_sub, int32_t k,
+                                      const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                      const float* __restrict__ val,
+                                      const double* __restrict__ ratio,
+                                      const double* __restrict__ sens, double* __restrict__ S) {
+    const RowGroups<GS> G(blockIdx.x, gridDim.x);
+    sweep_rows(G, n_vox, [&](int64_t i, int64_t& lo, int64_t& hi) { lo = rp[i]; hi = rp[i + 1]; },
+               [&](int64_t e, bool ok) {
+                   // every entry gathers its ratio (loads issued together);
+                   // entries outside subset k then count 0.  Masking the
+                   // gather instead serialises the loads and was slower.
+                   const int32_t j = col[e];
+                   const bool in_k = (j / bins_per_view) % n_sub == k;
+                   const double x = (double)val[e] * ratio[j];
+                   return ok && in_k ? x : 0.0;
+               },
+               [&](int64_t i, int64_t, int64_t, double bsum) {
+                   if (G.sub != 0) return;
+                   const double si = sens[(int64_t)k * n_vox + i];
+                   if (si > 0.0) S[i] = S[i] * bsum / si;
+               });
+}
+
 __global__ __launch_bounds__(T256) void k_os_update(int64_t n_vox, int32_t bins_per_view,
                                                     int32_t n_sub, int32_t k,
                                                     const int64_t* __restrict__ rp,
@@ -841,15 +883,12 @@ __global__ __launch_bounds__(T256) void k_os_update(int64_t n_vox, int32_t bins_
                                                     const double* __restrict__ ratio,
                                                     const double* __restrict__ sens,
                                                     double* __restrict__ S) {
-    for_rows(n_vox, rp,
-             [&](int64_t e) {
-                 const int32_t j = col[e];
-                 return (j / bins_per_view) % n_sub == k ? (double)val[e] * ratio[j] : 0.0;
-             },
-             [&](int64_t i, double bsum) {
-                 const double si = sens[(int64_t)k * n_vox + i];
-                 if (si > 0.0) S[i] = S[i] * bsum / si;
-             });
+    switch (lanes_per_row(rp[n_vox], n_vox)) {
+        case 1: os_update_rows<1>(n_vox, bins_per_view, n_sub, k, rp, col, val, ratio, sens, S); break;
+        case 4: os_update_rows<4>(n_vox, bins_per_view, n_sub, k, rp, col, val, ratio, sens, S); break;
+        case 16: os_update_rows<16>(n_vox, bins_per_view, n_sub, k, rp, col, val, ratio, sens, S); break;
+        default: os_update_rows<64>(n_vox, bins_per_view, n_sub, k, rp, col, val, ratio, sens, S); break;
+    }
 }
 
 }  // namespace

@@ -12,9 +12,14 @@
 // with G = dL/dtally.  The kernels here replay each tallied history from its
 // Philox counter -- no path is stored -- and walk every segment voxel by voxel
 // (Amanatides & Woo 1987 grid traversal), adding -G g(E) len to each crossed
-// voxel and +G/mu0 at each Compton vertex.  Sums are 64-bit fixed point with
-// frac_bits fractional bits: integer atomics, so the result is bit-exact from
-// run to run.
+// voxel and +G/mu0 at each Compton vertex.  A tallied history is replayed by
+// a whole wavefront (every lane the same path), and each segment is cut into
+// 64 equal pieces, one per lane, so a long walk is not one lane's serial
+// chain.  Sums are 64-bit fixed point with frac_bits fractional bits:
+// integer atomics, so the result is bit-exact from run to run and does not
+// depend on the order of the additions.
+#include <algorithm>
+
 #include "history.h"
 
 namespace mcs {
@@ -30,17 +35,20 @@ __device__ inline void add_fixed(long long* grad, uint32_t v, double val, double
     atomicAdd((unsigned long long*)(grad + v), (unsigned long long)__double2ll_rn(s));
 }
 
-// Walk the ray a + t d, t in [0, t_end) (t_end = +inf: to the grid exit), adding
-// w * (length in voxel) to every voxel it crosses.  a must be inside the grid.
-__device__ void walk(const Cst& C, float ax, float ay, float az, float dx, float dy, float dz,
-                     float t_end, double w, long long* grad, double scale, int64_t* status) {
-    const float px = ax + C.hx, py = ay + C.hy, pz = az + C.hz;
+// Walk the ray a + t d over t in [t0, t1), adding w * (length in voxel) to
+// every voxel the piece crosses; the piece starts in the voxel holding
+// a + t0 d (clamped to the grid) and stops at t1 or at the grid edge.
+__device__ void walk_piece(const Cst& C, float ax, float ay, float az, float dx, float dy, float dz,
+                           float t0, float t1, double w, long long* grad, double scale,
+                           int64_t* status) {
+    if (!(t1 > t0)) return;
+    const float px = fmaf(t0, dx, ax) + C.hx, py = fmaf(t0, dy, ay) + C.hy, pz = fmaf(t0, dz, az) + C.hz;
     int ix = min(max((int)(px * C.inv_vox), 0), C.nx - 1);
     int iy = min(max((int)(py * C.inv_vox), 0), C.ny - 1);
     int iz = min(max((int)(pz * C.inv_vox), 0), C.nz - 1);
     const int sx = dx > 0.0f ? 1 : -1, sy = dy > 0.0f ? 1 : -1, sz = dz > 0.0f ? 1 : -1;
     const float inf = __builtin_huge_valf();
-    // parametric distance to the next plane on each axis, and between planes
+    // parametric distance (from t0) to the next plane on each axis, and between planes
     float tx = dx != 0.0f ? (((float)(ix + (dx > 0.0f)) * C.vox) - px) / dx : inf;
     float ty = dy != 0.0f ? (((float)(iy + (dy > 0.0f)) * C.vox) - py) / dy : inf;
     float tz = dz != 0.0f ? (((float)(iz + (dz > 0.0f)) * C.vox) - pz) / dz : inf;
@@ -48,6 +56,7 @@ __device__ void walk(const Cst& C, float ax, float ay, float az, float dx, float
     const float ddy = dy != 0.0f ? C.vox / fabsf(dy) : inf;
     const float ddz = dz != 0.0f ? C.vox / fabsf(dz) : inf;
     tx = fmaxf(tx, 0.0f); ty = fmaxf(ty, 0.0f); tz = fmaxf(tz, 0.0f);
+    const float t_end = t1 - t0;
     float t = 0.0f;
     const int max_iter = C.nx + C.ny + C.nz + 3;
     for (int it = 0; it < max_iter; ++it) {
@@ -63,6 +72,24 @@ __device__ void walk(const Cst& C, float ax, float ay, float az, float dx, float
     }
 }
 
+// Walk the ray a + t d, t in [0, t_end) (t_end = +inf: to the grid exit), by
+// the whole wavefront: the range is cut into 64 equal pieces, lane k walks
+// piece k.  Every lane must call it with the same arguments.
+__device__ void walk_wave(const Cst& C, float ax, float ay, float az, float dx, float dy, float dz,
+                          float t_end, double w, long long* grad, double scale, int64_t* status) {
+    const float inf = __builtin_huge_valf();
+    const float px = ax + C.hx, py = ay + C.hy, pz = az + C.hz;
+    const float ex = dx > 0.0f ? (C.lx - px) / dx : (dx < 0.0f ? -px / dx : inf);
+    const float ey = dy > 0.0f ? (C.ly - py) / dy : (dy < 0.0f ? -py / dy : inf);
+    const float ez = dz > 0.0f ? (C.lz - pz) / dz : (dz < 0.0f ? -pz / dz : inf);
+    const float len = fminf(t_end, fmaxf(fminf(ex, fminf(ey, ez)), 0.0f));
+    const int lane = threadIdx.x & 63;
+    const float piece = len * (1.0f / 64.0f);
+    const float t0 = (float)lane * piece;
+    const float t1 = lane == 63 ? len : (float)(lane + 1) * piece;
+    walk_piece(C, ax, ay, az, dx, dy, dz, t0, t1, w, grad, scale, status);
+}
+
 __device__ inline double g_of(const Cst& C, float e) {
     if (e == C.e0) return (double)C.g0;
     float a, b;
@@ -70,7 +97,9 @@ __device__ inline double g_of(const Cst& C, float e) {
 }
 
 // Replay one history; if it ends TALLIED in `bin`, walk its path with weight G.
-// walk_now = false: only report the fate/bin (first pass of replay-all mode).
+// walk_now = false: only report the fate/bin (first pass of replay-all mode);
+// walk_now = true: every lane of the wavefront replays the same history (the
+// walks are shared by the lanes).
 __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now, double G,
                            long long* grad, double scale, int64_t* status, uint32_t& bin_out) {
     Lane L;
@@ -92,12 +121,14 @@ __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now,
                 // Compton vertex at L.x: close the segment, add the collision term
                 const float ex = L.x - sx, ey = L.y - sy, ez = L.z - sz;
                 const float len = ex * L.dx + ey * L.dy + ez * L.dz;
-                walk(C, sx, sy, sz, L.dx, L.dy, L.dz, len, -G * g_of(C, e_flight), grad, scale, status);
-                const int ix = min((int)((L.x + C.hx) * C.inv_vox), C.nx - 1);
-                const int iy = min((int)((L.y + C.hy) * C.inv_vox), C.ny - 1);
-                const int iz = min((int)((L.z + C.hz) * C.inv_vox), C.nz - 1);
-                const uint32_t v = (uint32_t)ix + (uint32_t)C.nx * ((uint32_t)iy + (uint32_t)C.ny * (uint32_t)iz);
-                add_fixed(grad, v, G / (double)ldg(C.mu + v), scale, status);
+                walk_wave(C, sx, sy, sz, L.dx, L.dy, L.dz, len, -G * g_of(C, e_flight), grad, scale, status);
+                if ((threadIdx.x & 63) == 0) {
+                    const int ix = min((int)((L.x + C.hx) * C.inv_vox), C.nx - 1);
+                    const int iy = min((int)((L.y + C.hy) * C.inv_vox), C.ny - 1);
+                    const int iz = min((int)((L.z + C.hz) * C.inv_vox), C.nz - 1);
+                    const uint32_t v = (uint32_t)ix + (uint32_t)C.nx * ((uint32_t)iy + (uint32_t)C.ny * (uint32_t)iz);
+                    add_fixed(grad, v, G / (double)ldg(C.mu + v), scale, status);
+                }
                 sx = L.x; sy = L.y; sz = L.z;
             }
             continue;
@@ -106,53 +137,75 @@ __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now,
             const int cls = L.n_scatter > 0 ? 1 : 0;
             bin_out = (uint32_t)((((uint32_t)L.view * 2u + cls) * (uint32_t)C.nv + iv) * (uint32_t)C.nu + iu);
             if (walk_now)
-                walk(C, sx, sy, sz, L.dx, L.dy, L.dz, __builtin_huge_valf(), -G * g_of(C, L.e),
-                     grad, scale, status);
+                walk_wave(C, sx, sy, sz, L.dx, L.dy, L.dz, __builtin_huge_valf(), -G * g_of(C, L.e),
+                          grad, scale, status);
         }
         return fate;
     }
 }
 
-// One listed tallied history per lane.
-__global__ __launch_bounds__(64) void k_adjoint_events(const ProbDesc* __restrict__ d,
-                                                       const mc_event* __restrict__ events,
-                                                       const unsigned long long* __restrict__ n_events,
-                                                       uint64_t capacity, const double* __restrict__ dL,
-                                                       long long* grad, double scale, int64_t* status) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One listed tallied history per wavefront (grid-strided over the list).
+__global__ __launch_bounds__(256) void k_adjoint_events(const ProbDesc* __restrict__ d,
+                                                        const mc_event* __restrict__ events,
+                                                        const unsigned long long* __restrict__ n_events,
+                                                        uint64_t capacity, const double* __restrict__ dL,
+                                                        long long* grad, double scale, int64_t* status) {
     const uint64_t n = min((uint64_t)*n_events, capacity);
-    if (i >= n) return;
     const Cst C = load_cst(d);
     if (C.flags) return;
-    const mc_event ev = events[i];
-    if (ev.work >= d->work_count) { atomicOr((unsigned long long*)status, (unsigned long long)MC_STATUS_BAD_EVENT); return; }
-    const double G = dL[C.tally_offset + ev.bin];
-    if (G == 0.0) return;
-    uint64_t view, hist;
-    split_work(C, C.work_begin + ev.work, view, hist);
-    uint32_t bin = 0;
-    const int fate = replay_path(C, hist, (int)view, true, G, grad, scale, status, bin);
-    if (fate != MC_TALLIED || bin != ev.bin)
-        atomicOr((unsigned long long*)status, (unsigned long long)MC_STATUS_BAD_EVENT);
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const bool lead = (threadIdx.x & 63) == 0;
+    for (uint64_t i = wave; i < n; i += n_waves) {
+        const mc_event ev = events[i];
+        if (ev.work >= d->work_count) {
+            if (lead) atomicOr((unsigned long long*)status, (unsigned long long)MC_STATUS_BAD_EVENT);
+            continue;
+        }
+        const double G = dL[C.tally_offset + ev.bin];
+        if (G == 0.0) continue;
+        uint64_t view, hist;
+        split_work(C, C.work_begin + ev.work, view, hist);
+        uint32_t bin = 0;
+        const int fate = replay_path(C, hist, (int)view, true, G, grad, scale, status, bin);
+        if (lead && (fate != MC_TALLIED || bin != ev.bin))
+            atomicOr((unsigned long long*)status, (unsigned long long)MC_STATUS_BAD_EVENT);
+    }
 }
 
-// Every history of the call's range: replay, and walk the tallied ones.
+// Every history of the call's range: each lane replays its own to find the
+// tallied ones, then the wavefront walks each of those together.
 __global__ __launch_bounds__(256) void k_adjoint_all(const ProbDesc* __restrict__ d,
                                                      const double* __restrict__ dL, long long* grad,
                                                      double scale, int64_t* status) {
     const Cst C = load_cst(d);
     if (C.flags) return;
     const uint64_t cnt = d->work_count;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t view, hist;
-        split_work(C, C.work_begin + i, view, hist);
-        uint32_t bin = 0;
-        const int fate = replay_path(C, hist, (int)view, false, 0.0, grad, scale, status, bin);
-        if (fate != MC_TALLIED) continue;
-        const double G = dL[C.tally_offset + bin];
-        if (G == 0.0) continue;
-        replay_path(C, hist, (int)view, true, G, grad, scale, status, bin);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // wave-uniform loop bound: every lane stays for the shared walks
+    const uint64_t first = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+    for (uint64_t i0 = first; i0 < cnt; i0 += stride) {
+        const uint64_t i = i0 + (threadIdx.x & 63);
+        uint64_t view = 0, hist = 0;
+        double G = 0.0;
+        bool walk_it = false;
+        if (i < cnt) {
+            split_work(C, C.work_begin + i, view, hist);
+            uint32_t bin = 0;
+            const int fate = replay_path(C, hist, (int)view, false, 0.0, grad, scale, status, bin);
+            if (fate == MC_TALLIED) {
+                G = dL[C.tally_offset + bin];
+                walk_it = G != 0.0;
+            }
+        }
+        for (uint64_t m = __ballot(walk_it); m != 0; m &= m - 1) {
+            const int src = __ffsll((unsigned long long)m) - 1;
+            const uint64_t h = (uint64_t)__shfl((long long)hist, src, 64);
+            const int v = __shfl((int)view, src, 64);
+            const double g = __shfl(G, src, 64);
+            uint32_t bin = 0;
+            replay_path(C, h, v, true, g, grad, scale, status, bin);
+        }
     }
 }
 
@@ -178,9 +231,11 @@ hipError_t launch_adjoint(const ProbDesc* d, const mc_event* events, const uint6
     const double scale = ldexp(1.0, frac_bits);
     if (events) {
         if (capacity > 0) {
-            const uint64_t g = (capacity + 63) / 64;
-            k_adjoint_events<<<(int)g, 64, 0, s>>>(d, events, (const unsigned long long*)n_events,
-                                                   capacity, dL, (long long*)grad, scale, status);
+            // one wavefront per listed history, at most n_cu * 32 wavefronts (grid-strided)
+            const uint64_t waves = std::min<uint64_t>(capacity, (uint64_t)n_cu * 32);
+            k_adjoint_events<<<(int)((waves + 3) / 4), 256, 0, s>>>(
+                d, events, (const unsigned long long*)n_events, capacity, dL, (long long*)grad, scale,
+                status);
         }
     } else {
         k_adjoint_all<<<n_cu * 8, 256, 0, s>>>(d, dL, (long long*)grad, scale, status);

@@ -98,7 +98,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="time only the headline workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 256^3 / 1e9-history form")
-    ap.add_argument("--only-form", choices=["forced_detection", "batched", "large_mlem"], default=None,
+    ap.add_argument("--only-form", choices=["forced_detection", "batched", "large_mlem", "adjoint"],
+                    default=None,
                     help="time only this side form (forced_detection: forced detection and "
                          "its convolution-based form; batched: the 32-thorax graph; large_mlem: "
                          "the 256^3 thorax with response matrices and MLEM) and print its "
@@ -124,7 +125,8 @@ def main():
     import phantoms
     import paper_2105_13324_amd as mc
     if args.only_form:
-        fn = {"forced_detection": fd_form, "batched": batched_form, "large_mlem": large_form}[args.only_form]
+        fn = {"forced_detection": fd_form, "batched": batched_form, "large_mlem": large_form,
+              "adjoint": adjoint_form}[args.only_form]
         print(json.dumps({"form": args.only_form, **fn(mc, torch, args.steps)}))
         return
 
@@ -228,7 +230,20 @@ def extra_forms(mc, torch, args):
                             "ms_per_step": ms, "eager_ms_per_step": ms_eager,
                             "histories": p1.n_histories, "launch": "hipGraph replay of one call"}
     out["batched"] = batched_form(mc, torch, steps)
-    # adjoint: forward with event list, loss gradient, replaying adjoint
+    out["adjoint"] = adjoint_form(mc, torch, steps)
+    out["forced_detection"] = fd_form(mc, torch, steps)
+    out["reuse_of_photon_tracks"] = rpt_form(mc, torch, steps)
+    out["coarse_grid_scatter"] = cgsm_form(mc, torch, steps)
+    out["tl201_dual_window"] = tl201_form(mc, torch, steps)
+    if not args.no_large:
+        out["large_mlem"] = large_form(mc, torch, steps)
+    return out
+
+
+def adjoint_form(mc, torch, steps):
+    """Adjoint step on the 128^3 x 1 mm cube, 1e7 histories: forward with an
+    event list, Poisson-loss gradient, replaying adjoint."""
+    import phantoms
     p4 = phantoms.point_cube_128_adjoint(10 ** 7)
     d4 = mc.to_device(p4)
     ref = mc.simulate(d4.with_(seed=1), want_sq=False)
@@ -255,22 +270,14 @@ def extra_forms(mc, torch, args):
     lam = s4.tally.view(p4.tally_shape).to(torch.float64).sum(dim=1) * 2.0 ** -32
     G = (1.0 - y / (lam + 1e-6 * float(p4.n_histories))).unsqueeze(1).expand(-1, 2, -1, -1).contiguous()
     ms_adj = timed(torch, lambda: mc.adjoint(d4, G, s4), steps)
-    out["adjoint"] = {"value": p4.n_histories / (ms / 1e3), "unit": "histories/s",
-                      "ms_per_step": ms, "forward_ms": ms_fwd, "adjoint_call_ms": ms_adj,
-                      "histories": p4.n_histories, "tallied": int(s4.n_events.item()),
-                      "step": "forward with event list + Poisson-loss gradient + replaying adjoint",
-                      "roofline": transport_roofline(s4, k_fwd),
-                      "roofline_note": "dominant kernel: the forward transport; the adjoint call "
-                                       "replays only the tallied histories (a few wavefronts) and "
-                                       "is bound by launch and host synchronisation"}
-    del s4, d4, ref
-    out["forced_detection"] = fd_form(mc, torch, steps)
-    out["reuse_of_photon_tracks"] = rpt_form(mc, torch, steps)
-    out["coarse_grid_scatter"] = cgsm_form(mc, torch, steps)
-    out["tl201_dual_window"] = tl201_form(mc, torch, steps)
-    if not args.no_large:
-        out["large_mlem"] = large_form(mc, torch, steps)
-    return out
+    return {"value": p4.n_histories / (ms / 1e3), "unit": "histories/s",
+            "ms_per_step": ms, "forward_ms": ms_fwd, "adjoint_call_ms": ms_adj,
+            "histories": p4.n_histories, "tallied": int(s4.n_events.item()),
+            "step": "forward with event list + Poisson-loss gradient + replaying adjoint",
+            "roofline": transport_roofline(s4, k_fwd),
+            "roofline_note": "dominant kernel: the forward transport; the adjoint call replays "
+                             "only the tallied histories, one wavefront each with the segment "
+                             "walks split over its lanes, and reads its status back once"}
 
 
 def batched_form(mc, torch, steps):

@@ -9,6 +9,10 @@
 
 using namespace mcs;
 
+namespace mcs {
+size_t staging_block_scratch_u64(uint64_t nvox);   // staging.hip
+}
+
 namespace {
 
 thread_local int g_last_hip = 0;
@@ -101,7 +105,7 @@ bool plan(const mc_problem* probs, int n, Layout& L, bool cfd = false) {
         L.pal[i] = off;   off += align256(4 * (size_t)PALETTE_N);
         L.cdf[i] = off;   off += align256(8 * nvox);
         L.vid[i] = off;   off += align256(4 * nvox);
-        L.bsum[i] = off;  off += align256(8 * ((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS));
+        L.bsum[i] = off;  off += align256(8 * staging_block_scratch_u64(nvox));
         L.bcnt[i] = off;  off += align256(4 * ((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS));
         L.guide[i] = off; off += align256(16 * guide_capacity(nvox));
         L.views[i] = off; off += align256(8 * (size_t)p.n_views);

@@ -30,6 +30,8 @@ namespace {
 
 constexpr int RED_THREADS = 256;
 constexpr int ROWS = 4;        // grid rows a row pass loads at once
+constexpr int REDUCE_BLOCKS = 512;      // most workgroups of k_reduce per problem
+constexpr int REDUCE_PART_U64 = 4;      // partial results per workgroup
 
 __device__ inline uint64_t wave_sum_u64(uint64_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -100,7 +102,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* descs) {
         }
     }
 
-    // one atomic per block: same-address atomics serialise in L2
+    // per-block partials (the scan's block-sum scratch, idle until the scan):
+    // k_reduce_final combines them.  One atomic per block on the same few
+    // descriptor fields serialised in memory.
     __shared__ uint32_t s_mx[RED_THREADS / 64], s_fl[RED_THREADS / 64];
     __shared__ uint64_t s_sum[RED_THREADS / 64];
     __shared__ int s_lo[RED_THREADS / 64][3], s_hi[RED_THREADS / 64][3];
@@ -111,19 +115,20 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* descs) {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+        for (int k = 1; k < (int)((blockDim.x + 63) >> 6); ++k) {
             mx = max(mx, s_mx[k]); flags |= s_fl[k]; sum += s_sum[k];
             for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], s_lo[k][a]); hi[a] = max(hi[a], s_hi[k][a]); }
         }
-        atomicMax(&pd->mu_hat_bits, mx);
-        if (flags) atomicOr(&pd->flags, flags);
-        atomicAdd((unsigned long long*)&pd->total, (unsigned long long)sum);
-        if (hi[0] >= 0) {
-            for (int a = 0; a < 3; ++a) {
-                atomicMin(&pd->bb_lo[a], lo[a]);
-                atomicMax(&pd->bb_hi[a], hi[a]);
-            }
+        uint64_t lo_p = 0, hi_p = 0;     // 16 bits per axis: lo (0xFFFF: none), hi + 1 (0: none)
+        for (int a = 0; a < 3; ++a) {
+            lo_p |= (uint64_t)(hi[a] >= 0 ? (uint32_t)lo[a] : 0xFFFFu) << (16 * a);
+            hi_p |= (uint64_t)(hi[a] >= 0 ? (uint32_t)hi[a] + 1u : 0u) << (16 * a);
         }
+        uint64_t* part = pd->block_sums + (uint64_t)blockIdx.x * REDUCE_PART_U64;
+        part[0] = (uint64_t)mx | ((uint64_t)flags << 32);
+        part[1] = sum;
+        part[2] = lo_p;
+        part[3] = hi_p;
     }
     if (blockIdx.x == 0) {
         if (pd->pal_state == 0)
@@ -132,6 +137,59 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(ProbDesc* descs) {
             const double a = pd->angles[k];
             if (!isfinite(a)) atomicOr(&pd->flags, (uint32_t)MC_STATUS_BAD_ANGLE);
             pd->views[k] = make_float2((float)cos(a), (float)sin(a));
+        }
+    }
+}
+
+// Combine k_reduce's n_parts partials: max mu, flags, activity total and the
+// attenuation box, written to the descriptor (one workgroup per problem).
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_final(ProbDesc* descs, int n_parts) {
+    ProbDesc* pd = descs + blockIdx.y;
+    uint32_t mx = 0, flags = 0;
+    uint64_t sum = 0;
+    uint32_t lo[3] = {0xFFFFu, 0xFFFFu, 0xFFFFu}, hi[3] = {0, 0, 0};
+    for (int b = threadIdx.x; b < n_parts; b += blockDim.x) {
+        const uint64_t* part = pd->block_sums + (uint64_t)b * REDUCE_PART_U64;
+        const uint64_t p0 = part[0], p2 = part[2], p3 = part[3];
+        mx = max(mx, (uint32_t)p0);
+        flags |= (uint32_t)(p0 >> 32);
+        sum += part[1];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = min(lo[a], (uint32_t)(p2 >> (16 * a)) & 0xFFFFu);
+            hi[a] = max(hi[a], (uint32_t)(p3 >> (16 * a)) & 0xFFFFu);
+        }
+    }
+    mx = wave_max_u32(mx);
+    flags = wave_or_u32(flags);
+    sum = wave_sum_u64(sum);
+    for (int a = 0; a < 3; ++a) {
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[a] = min(lo[a], (uint32_t)__shfl_xor((int)lo[a], o, 64));
+            hi[a] = max(hi[a], (uint32_t)__shfl_xor((int)hi[a], o, 64));
+        }
+    }
+    __shared__ uint32_t s_mx[RED_THREADS / 64], s_fl[RED_THREADS / 64];
+    __shared__ uint64_t s_sum[RED_THREADS / 64];
+    __shared__ uint32_t s_lo[RED_THREADS / 64][3], s_hi[RED_THREADS / 64][3];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_mx[w] = mx; s_fl[w] = flags; s_sum[w] = sum;
+        for (int a = 0; a < 3; ++a) { s_lo[w][a] = lo[a]; s_hi[w][a] = hi[a]; }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)((blockDim.x + 63) >> 6); ++k) {
+            mx = max(mx, s_mx[k]); flags |= s_fl[k]; sum += s_sum[k];
+            for (int a = 0; a < 3; ++a) { lo[a] = min(lo[a], s_lo[k][a]); hi[a] = max(hi[a], s_hi[k][a]); }
+        }
+        pd->mu_hat_bits = mx;
+        if (flags) pd->flags |= flags;
+        pd->total = sum;
+        if (hi[0] > 0) {
+            for (int a = 0; a < 3; ++a) {
+                pd->bb_lo[a] = (int)lo[a];
+                pd->bb_hi[a] = (int)hi[a] - 1;
+            }
         }
     }
 }
@@ -541,7 +599,9 @@ hipError_t launch_staging_batch(ProbDesc* d, const ProbDesc* h, int n, hipStream
     // row-per-block passes: a block walks grid rows (iy, iz), threads along x
     const int row_threads = (int)std::min<uint64_t>(RED_THREADS, ((uint64_t)max_nx + 63) / 64 * 64);
     const unsigned ny = (unsigned)n;
-    k_reduce<<<dim3((unsigned)std::min<uint64_t>(max_rows, 512), ny), row_threads, 0, st>>>(d);
+    const unsigned red_blocks = (unsigned)std::min<uint64_t>(max_rows, REDUCE_BLOCKS);
+    k_reduce<<<dim3(red_blocks, ny), row_threads, 0, st>>>(d);
+    k_reduce_final<<<dim3(1, ny), RED_THREADS, 0, st>>>(d, (int)red_blocks);
     const unsigned row_blocks = (unsigned)std::min<uint64_t>((max_rows + ROWS - 1) / ROWS, 8192);
     // each workgroup puts each threshold value it meets into the palette once
     // (a round trip to memory): fewer, larger workgroups for this pass
@@ -553,6 +613,14 @@ hipError_t launch_staging_batch(ProbDesc* d, const ProbDesc* h, int n, hipStream
     k_guide<<<dim3((unsigned)grid_for(max_cap, RED_THREADS, 8192), ny), RED_THREADS, 0, st>>>(d);
     k_kn_table<<<dim3((KN_TABLE_N + 255) / 256, ny), 256, 0, st>>>(d);
     return hipGetLastError();
+}
+
+// Entries (uint64) of a problem's block-sum scratch: the scan's block sums,
+// and before them k_reduce's partials.
+size_t staging_block_scratch_u64(uint64_t nvox) {
+    const uint64_t nb = (nvox + SCAN_ITEMS - 1) / SCAN_ITEMS;
+    const uint64_t red = (uint64_t)REDUCE_BLOCKS * REDUCE_PART_U64;
+    return (size_t)(nb > red ? nb : red);
 }
 
 hipError_t launch_staging(ProbDesc* d, const ProbDesc& h, hipStream_t st) {

@@ -241,7 +241,11 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* descs) {
     for (int k = threadIdx.x; k < PALETTE_N; k += blockDim.x) seen[k] = PALETTE_EMPTY;
     __syncthreads();
     // Q of one value, and its palette entry: a wavefront inserts each of its
-    // distinct values once (leader lane); lanes with ok = false only vote
+    // distinct values once (leader lane); lanes with ok = false only vote.
+    // The last four values the wavefront inserted are kept (wave-uniform):
+    // a row whose values are all among them skips the insert loop.
+    uint32_t recent[4] = {PALETTE_EMPTY, PALETTE_EMPTY, PALETTE_EMPTY, PALETTE_EMPTY};
+    uint32_t n_recent = 0;
     auto threshold = [&](float mv, bool ok) -> uint32_t {
         uint32_t v = 0;
         if (ok && mu_hat > 0.0f && mv > 0.0f) {
@@ -249,7 +253,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* descs) {
             v = t >= 16777216.0 ? 16777216u : (uint32_t)t;
         }
         if (pal && !full) {
-            bool todo = ok;
+            const bool known = (v == recent[0]) | (v == recent[1]) | (v == recent[2]) | (v == recent[3]);
+            bool todo = ok && !known;
             for (;;) {
                 const uint64_t left = __ballot(todo);
                 if (left == 0) break;
@@ -259,6 +264,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_thresholds(ProbDesc* descs) {
                     palette_insert(pd->palette, lv) == PALETTE_N)
                     full = true;
                 if (v == lv) todo = false;
+                recent[n_recent & 3u] = lv;   // lv is wave-uniform: so is the cache
+                ++n_recent;
             }
         }
         return v;

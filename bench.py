@@ -102,8 +102,8 @@ def main():
                     default=None,
                     help="time only this side form (forced_detection: forced detection and "
                          "its convolution-based form; batched: the 32-thorax graph; large_mlem: "
-                         "the 256^3 thorax with response matrices and MLEM) and print its "
-                         "record; for profiling")
+                         "the 256^3 thorax with response matrices and MLEM; adjoint: the "
+                         "adjoint step on the 128^3 cube) and print its record; for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()

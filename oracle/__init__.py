@@ -54,7 +54,7 @@ class _Problem(C.Structure):
         ("n_threads", C.c_uint32),
         ("activity_prev", C.POINTER(C.c_uint32)),
         ("e0_kev", C.c_double),
-        ("vr_flags", C.c_int32), ("pad", C.c_int32), ("vr_cone_rad", C.c_double),
+        ("vr_flags", C.c_int32), ("escape_shortcut", C.c_int32), ("vr_cone_rad", C.c_double),
     ]
 
 
@@ -97,7 +97,6 @@ def _load():
         lib.orc_simulate_fd.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(_Result),
                                         P(C.c_int64), P(C.c_int64), P(C.c_double), P(C.c_int64),
                                         C.c_uint64, P(C.c_uint64)]
-        lib.orc_set_box_skip.argtypes = [C.c_int]
         lib.orc_simulate_cfd.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(_Result)]
         lib.orc_cfd_kernel.argtypes = [C.c_double, C.c_double, C.c_double, P(C.c_double), P(C.c_int32)]
         lib.orc_cfd_layers.argtypes = [P(_Problem)]
@@ -106,6 +105,8 @@ def _load():
         lib.orc_kn_pdf.restype = C.c_double
         lib.orc_ray_integral.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(C.c_double)]
         lib.orc_replay.argtypes = [P(_Problem), P(C.c_int32), P(C.c_uint64), C.c_int64, C.c_void_p]
+        lib.orc_adjoint_list.argtypes = [P(_Problem), P(C.c_double), P(C.c_int32), P(C.c_uint64),
+                                         C.c_int64, P(C.c_double), P(C.c_int64)]
         lib.orc_adjoint.argtypes = [P(_Problem), P(C.c_double), P(C.c_double), P(C.c_int64),
                                     C.c_int32, P(C.c_int32), C.c_double, P(C.c_double),
                                     P(C.c_double), C.c_double, P(C.c_double), P(_Result)]
@@ -119,8 +120,14 @@ def _ptr(a: Optional[np.ndarray], ct):
     return a.ctypes.data_as(C.POINTER(ct))
 
 
-def _make_problem(prob, n_threads: int = 0):
-    """Marshal a phantoms.Problem into the C structure (keeps arrays alive)."""
+def _make_problem(prob, n_threads: int = 0, escape_shortcut: bool = False):
+    """Marshal a phantoms.Problem into the C structure (keeps arrays alive).
+
+    escape_shortcut: end a history at once when its tentative collision point
+    lies outside the attenuation box and it moves away from it (exact in real
+    arithmetic, fewer virtual steps).  Off by default: the oracle walks every
+    history to the grid edge; only the step-count comparison with a kernel
+    that takes the shortcut, and timing, switch it on."""
     mu = np.ascontiguousarray(prob.mu, dtype=np.float32)
     act = np.ascontiguousarray(prob.activity, dtype=np.uint32)
     ang = np.ascontiguousarray(prob.angles, dtype=np.float64)
@@ -138,7 +145,8 @@ def _make_problem(prob, n_threads: int = 0):
                  n_threads=n_threads, activity_prev=_ptr(prev, C.c_uint32),
                  e0_kev=float(getattr(prob, "e0_kev", 140.0)),
                  vr_flags=int(getattr(prob, "vr_flags", 0)),
-                 vr_cone_rad=float(getattr(prob, "vr_cone_rad", 0.0)))
+                 vr_cone_rad=float(getattr(prob, "vr_cone_rad", 0.0)),
+                 escape_shortcut=1 if escape_shortcut else 0)
     return p, (mu, act, ang, prev)
 
 
@@ -212,13 +220,14 @@ def thresholds(prob):
 # Transport
 # ---------------------------------------------------------------------------
 
-def simulate(prob, n_threads: int = 0, want_triplets: bool = False, trip_cap: int = 1 << 22):
+def simulate(prob, n_threads: int = 0, want_triplets: bool = False, trip_cap: int = 1 << 22,
+             escape_shortcut: bool = False):
     """Forward simulation.  Returns dict with tally, tally_sq ([V,2,nv,nu], FP64),
     fates, energy (deposited, escaped, capped), counters and, if asked, per
     tallied history its image voxel of emission (trip_i), bin (trip_j) and work
     index relative to history_offset (trip_g)."""
     lib = _load()
-    p, keep = _make_problem(prob, n_threads)
+    p, keep = _make_problem(prob, n_threads, escape_shortcut)
     tally = np.zeros(prob.tally_shape, dtype=np.float64)
     tsq = np.zeros(prob.tally_shape, dtype=np.float64)
     res = _Result()
@@ -309,12 +318,6 @@ def cfd_kernel(depth_cm: float, alpha: float, pixel_cm: float) -> np.ndarray:
     return out
 
 
-def set_box_skip(on: bool) -> None:
-    """Switch the escape shortcut for photons leaving the attenuation box
-    (on by default; tests compare against it switched off)."""
-    _load().orc_set_box_skip(1 if on else 0)
-
-
 def kn_pdf(e_kev: float, cos_t: float) -> float:
     """Klein-Nishina angular density per steradian at e_kev."""
     return _load().orc_kn_pdf(float(e_kev), float(cos_t))
@@ -333,9 +336,10 @@ def ray_integral(prob, x, d) -> float:
     return out.value
 
 
-def replay(prob, views: np.ndarray, hists: np.ndarray, n_threads: int = 0) -> np.ndarray:
+def replay(prob, views: np.ndarray, hists: np.ndarray, n_threads: int = 0,
+           escape_shortcut: bool = False) -> np.ndarray:
     lib = _load()
-    p, keep = _make_problem(prob, n_threads)
+    p, keep = _make_problem(prob, n_threads, escape_shortcut)
     views = np.ascontiguousarray(views, dtype=np.int32)
     hists = np.ascontiguousarray(hists, dtype=np.uint64)
     out = np.zeros(len(views), dtype=RECORD_DTYPE)
@@ -371,6 +375,26 @@ def adjoint(prob, G: np.ndarray, pert_voxels=None, delta: float = 1e-3, lam=None
     out["n_contrib"] = ncon.reshape(prob.mu.shape)
     out["fd"] = fd[:npert]
     return out
+
+
+def adjoint_list(prob, G: np.ndarray, views: np.ndarray, hists: np.ndarray, n_threads: int = 0):
+    """The path-frozen gradient of sum_b G_b tally_b restricted to the listed
+    (view, history id) pairs: each is replayed and, if tallied, adds
+    G_b (c_{h,v}/mu0_v - lt_{h,v}).  Returns (grad [nz,ny,nx], bin of each
+    listed history in the tally layout or -1 when it is not tallied)."""
+    lib = _load()
+    p, keep = _make_problem(prob, n_threads)
+    G = np.ascontiguousarray(G, dtype=np.float64).reshape(-1)
+    views = np.ascontiguousarray(views, dtype=np.int32)
+    hists = np.ascontiguousarray(hists, dtype=np.uint64)
+    grad = np.zeros(prob.n_vox, dtype=np.float64)
+    bins = np.empty(len(views), dtype=np.int64)
+    rc = lib.orc_adjoint_list(C.byref(p), _ptr(G, C.c_double), _ptr(views, C.c_int32),
+                              _ptr(hists, C.c_uint64), len(views), _ptr(grad, C.c_double),
+                              _ptr(bins, C.c_int64))
+    if rc != 0:
+        raise RuntimeError("orc_adjoint_list failed")
+    return grad.reshape(prob.mu.shape), bins
 
 
 # ---------------------------------------------------------------------------

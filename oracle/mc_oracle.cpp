@@ -133,7 +133,8 @@ typedef struct {
     const uint32_t* activity_prev;   // nullable: the source is activity - activity_prev
     double e0_kev;                   // emission line energy (0: 140 keV)
     int32_t vr_flags;                // VR_FORCED_DIRECTION | VR_FORCED_INTERACTION
-    int32_t pad;
+    int32_t escape_shortcut;         // 0 (default): plain Woodcock walk to the grid edge;
+                                     // 1: escape at once outside the attenuation box
     double vr_cone_rad;              // forced direction: cone half-angle about the view normal
 } orc_problem;
 
@@ -174,11 +175,6 @@ struct Setup {
     bool box_empty;
 };
 
-// When set (the default), a photon at a tentative collision point in a voxel
-// outside the attenuation box, moving away from the box on that axis, escapes
-// at once (it could only have virtual collisions); tests switch it off to
-// check that nothing but the number of tentative collisions changes.
-bool g_box_skip = true;
 
 // Reuse of photon tracks (Sec. 5.3): the projection of the new estimate is
 // the old projection plus the projection of the difference d = lambda(k) -
@@ -503,6 +499,33 @@ void fd_score(const Setup& s, int32_t view, uint64_t hist, uint32_t event, const
     }
 }
 
+// Kahn's rejection sampler (Kahn 1954) for x = E/E' of a Compton scatter at
+// energy e, x on [1, 1+2k] with k = e / m_e c^2: attempt a takes its three
+// uniforms from Philox counter (c0, c1, event, 1 + a).  With probability
+// (1+2k)/(9+2k) the candidate is x = 1 + 2k rho2, kept if rho3 <= 4 (1/x -
+// 1/x^2); otherwise x = (1+2k)/(1 + 2k rho2), kept if rho3 <= (c^2 + 1/x)/2
+// with c = 1 - (x-1)/k.  Returns x, or NaN when KAHN_MAX_ATTEMPTS attempts
+// all fail; *attempts receives the number of attempts made.  The transport
+// and the sampler check below both call this one function.
+double kahn_sample(double e, uint32_t c0, uint32_t c1, uint32_t event, uint32_t k0, uint32_t k1,
+                   int32_t* attempts) {
+    const double k = e / MEC2_KEV;
+    for (uint32_t a = 0; a < KAHN_MAX_ATTEMPTS; ++a) {
+        *attempts = (int32_t)a + 1;
+        const Words wk = philox4x32_10(c0, c1, event, 1 + a, k0, k1);
+        const double r1 = uniform(wk.r[0]), r2 = uniform(wk.r[1]), r3 = uniform(wk.r[2]);
+        if (r1 <= (1.0 + 2.0 * k) / (9.0 + 2.0 * k)) {
+            const double xx = 1.0 + 2.0 * k * r2;
+            if (r3 <= 4.0 * (1.0 / xx - 1.0 / (xx * xx))) return xx;
+        } else {
+            const double xx = (1.0 + 2.0 * k) / (1.0 + 2.0 * k * r2);
+            const double c = 1.0 - (xx - 1.0) / k;
+            if (r3 <= 0.5 * (c * c + 1.0 / xx)) return xx;
+        }
+    }
+    return NAN;
+}
+
 // Transport one history.  view/hist identify its random stream.
 void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, History& h,
                  FdSink* fd = nullptr) {
@@ -566,9 +589,11 @@ void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, Hi
         const double xn[3] = {x[0] + step * d[0], x[1] + step * d[1], x[2] + step * d[2]};
         int idx[3];
         const bool in_grid = voxel_of(s, xn, idx);
-        // in the air outside the attenuation box and moving away from it, every
-        // remaining collision would be virtual: escape now along the same ray
-        const bool box_exit = in_grid && g_box_skip && leaves_box(s, idx, d);
+        // Optional shortcut (off unless the problem asks for it): in the air
+        // outside the attenuation box and moving away from it, every remaining
+        // collision would be virtual, so the photon escapes along the same ray.
+        // Exact in real arithmetic; it only drops the remaining virtual steps.
+        const bool box_exit = in_grid && p->escape_shortcut && leaves_box(s, idx, d);
         if (box_exit) { x[0] = xn[0]; x[1] = xn[1]; x[2] = xn[2]; }
         if (!in_grid || box_exit) {
             // Escape: the photon leaves the grid along d from x (last inside point).
@@ -602,22 +627,10 @@ void run_history(const Setup& s, int32_t view, uint64_t hist, bool keep_path, Hi
         }
         // Compton: Kahn's sampler for x = E/E' on [1, 1+2k].
         const double k = e / MEC2_KEV;
-        double xr = 1.0;
-        bool accepted = false;
-        for (uint32_t a = 0; a < KAHN_MAX_ATTEMPTS; ++a) {
-            h.n_kahn++;
-            const Words wk = philox4x32_10(c0, c1, n, 1 + a, k0, k1);
-            const double r1 = uniform(wk.r[0]), r2 = uniform(wk.r[1]), r3 = uniform(wk.r[2]);
-            if (r1 <= (1.0 + 2.0 * k) / (9.0 + 2.0 * k)) {
-                const double xx = 1.0 + 2.0 * k * r2;
-                if (r3 <= 4.0 * (1.0 / xx - 1.0 / (xx * xx))) { xr = xx; accepted = true; break; }
-            } else {
-                const double xx = (1.0 + 2.0 * k) / (1.0 + 2.0 * k * r2);
-                const double c = 1.0 - (xx - 1.0) / k;
-                if (r3 <= 0.5 * (c * c + 1.0 / xx)) { xr = xx; accepted = true; break; }
-            }
-        }
-        if (!accepted) { h.fate = CAPPED; h.capped = e; break; }
+        int32_t attempts = 0;
+        const double xr = kahn_sample(e, c0, c1, n, k0, k1, &attempts);
+        h.n_kahn += attempts;
+        if (std::isnan(xr)) { h.fate = CAPPED; h.capped = e; break; }
         const double cos_s = 1.0 - (xr - 1.0) / k;
         const double e_new = e / xr;
         h.dep += e - e_new;
@@ -739,6 +752,35 @@ void segment_voxels(const Setup& s, const double a[3], const double b[3],
     }
 }
 
+// The two parts of a tallied path's likelihood-ratio derivative: the
+// energy-weighted length g(E_seg) len(seg n v) of every segment piece (from
+// the emission point to each Compton vertex in turn, then from the last
+// vertex to beyond the grid along the final direction), and the voxel of
+// every Compton vertex.
+void path_terms(const Setup& s, const History& h, std::vector<std::pair<size_t, double>>& pieces,
+                std::vector<std::pair<size_t, double>>& lv, std::vector<size_t>& cv) {
+    const orc_problem* p = s.p;
+    for (size_t k = 0; k < h.verts.size(); ++k) {
+        const double* a = h.verts[k].x;
+        double bpt[3];
+        if (k + 1 < h.verts.size()) {
+            for (int c = 0; c < 3; ++c) bpt[c] = h.verts[k + 1].x[c];
+        } else {
+            const double far = 4.0 * (s.L[0] + s.L[1] + s.L[2]);
+            for (int c = 0; c < 3; ++c) bpt[c] = a[c] + far * h.dfinal[c];
+        }
+        pieces.clear();
+        segment_voxels(s, a, bpt, pieces);
+        const double ge = s.xs.g(h.verts[k].e_after);
+        for (auto& pc : pieces) lv.emplace_back(pc.first, ge * pc.second);
+        if (k + 1 < h.verts.size()) {
+            int idx[3];
+            voxel_of(s, h.verts[k + 1].x, idx);
+            cv.push_back((size_t)idx[0] + (size_t)p->nx * ((size_t)idx[1] + (size_t)p->ny * idx[2]));
+        }
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -756,27 +798,16 @@ double orc_kn_total(double e_kev) { return kn_total(e_kev); }
 double orc_g(double e_kev, double f_pe) { XS xs{f_pe, kn_total(E0_KEV)}; return xs.g(e_kev); }
 double orc_p_pe(double e_kev, double f_pe) { XS xs{f_pe, kn_total(E0_KEV)}; return xs.p_pe(e_kev); }
 
-// Kahn samples of x = E/E' at energy e_kev, history h using words
-// (h, 0, 1, 1+a) under key (seed, 0).  Returns the attempt count in *attempts.
+// Kahn samples of x = E/E' at energy e_kev through the transport's own
+// sampler (kahn_sample): sample h uses the Philox counters of collision 1 of
+// history (h mod 2^32) in "view" h >> 32 under key (seed, 0).  Returns the
+// total attempt count in *attempts.
 void orc_kahn_samples(double e_kev, uint32_t seed, uint64_t n, double* x_out, int64_t* attempts) {
-    const double k = e_kev / MEC2_KEV;
     int64_t att = 0;
     for (uint64_t h = 0; h < n; ++h) {
-        double xr = NAN;
-        for (uint32_t a = 0; a < KAHN_MAX_ATTEMPTS; ++a) {
-            ++att;
-            const Words wk = philox4x32_10((uint32_t)h, (uint32_t)(h >> 32), 1, 1 + a, seed, 0);
-            const double r1 = uniform(wk.r[0]), r2 = uniform(wk.r[1]), r3 = uniform(wk.r[2]);
-            if (r1 <= (1.0 + 2.0 * k) / (9.0 + 2.0 * k)) {
-                const double xx = 1.0 + 2.0 * k * r2;
-                if (r3 <= 4.0 * (1.0 / xx - 1.0 / (xx * xx))) { xr = xx; break; }
-            } else {
-                const double xx = (1.0 + 2.0 * k) / (1.0 + 2.0 * k * r2);
-                const double c = 1.0 - (xx - 1.0) / k;
-                if (r3 <= 0.5 * (c * c + 1.0 / xx)) { xr = xx; break; }
-            }
-        }
-        x_out[h] = xr;
+        int32_t a = 0;
+        x_out[h] = kahn_sample(e_kev, (uint32_t)h, (uint32_t)(h >> 32), 1, seed, 0, &a);
+        att += a;
     }
     *attempts = att;
 }
@@ -987,9 +1018,6 @@ int32_t orc_cfd_layers(const orc_problem* p) { return cfd_layers(p); }
 
 double orc_kn_pdf(double e_kev, double cos_t) { return kn_pdf(e_kev, cos_t); }
 
-// Switch the escape-from-the-attenuation-box shortcut (default on).
-void orc_set_box_skip(int on) { g_box_skip = on != 0; }
-
 // Integral of mu140 from x along d to the grid edge (exact voxel pieces).
 int orc_ray_integral(const orc_problem* p, const double x[3], const double d[3], double* out) {
     Setup s;
@@ -1064,29 +1092,9 @@ int orc_adjoint(const orc_problem* p, const double* G, double* grad, int64_t* n_
             if (h.fate != TALLIED) continue;
             const size_t bin = bin_index(p, h.view, h.cls, h.iv, h.iu);
             const double Gb = G[bin];
-            // sparse per-voxel (count, weighted length)
             std::vector<std::pair<size_t, double>> lv;   // (voxel, g*len)
             std::vector<size_t> cv;                       // collision voxels
-            for (size_t k = 0; k < h.verts.size(); ++k) {
-                const double* a = h.verts[k].x;
-                double bpt[3];
-                if (k + 1 < h.verts.size()) {
-                    for (int c = 0; c < 3; ++c) bpt[c] = h.verts[k + 1].x[c];
-                } else {
-                    // to beyond the grid along the final direction
-                    const double far = 4.0 * (s.L[0] + s.L[1] + s.L[2]);
-                    for (int c = 0; c < 3; ++c) bpt[c] = a[c] + far * h.dfinal[c];
-                }
-                pieces.clear();
-                segment_voxels(s, a, bpt, pieces);
-                const double ge = s.xs.g(h.verts[k].e_after);
-                for (auto& pc : pieces) lv.emplace_back(pc.first, ge * pc.second);
-                if (k + 1 < h.verts.size()) {
-                    int idx[3];
-                    voxel_of(s, h.verts[k + 1].x, idx);
-                    cv.push_back((size_t)idx[0] + (size_t)p->nx * ((size_t)idx[1] + (size_t)p->ny * idx[2]));
-                }
-            }
+            path_terms(s, h, pieces, lv, cv);
             for (auto& q : lv) T.grad[q.first] -= Gb * q.second;
             for (size_t v : cv) T.grad[v] += Gb / (double)p->mu140[v];
             if (n_contrib) {
@@ -1138,6 +1146,42 @@ int orc_adjoint(const orc_problem* p, const double* G, double* grad, int64_t* n_
             fd_out[q] = diff / (2.0 * delta);
         }
     }
+    return 0;
+}
+
+// The same gradient over a given list of histories: each listed (view,
+// history id) is replayed and, if the oracle tallies it, adds
+// G_b (c_{h,v}/mu0_v - lt_{h,v}) to grad (accumulated into; caller zeroes).
+// tallied_bin[i] (nullable) receives the listed history's global bin
+// (view, class, iv, iu) in the tally layout, or -1 if it is not tallied.
+int orc_adjoint_list(const orc_problem* p, const double* G, const int32_t* views,
+                     const uint64_t* hists, int64_t n, double* grad, int64_t* tallied_bin) {
+    Setup s;
+    if (p->activity_prev || p->vr_flags) return -1;
+    if (!build_setup(p, s)) return -1;
+    const size_t nvox = (size_t)p->nx * p->ny * p->nz;
+    const size_t nt = n_threads_for(p);
+    std::vector<std::vector<double>> tg(nt, std::vector<double>(nvox, 0.0));
+    parallel_ranges(0, (uint64_t)n, nt, [&](size_t ti, uint64_t b, uint64_t e) {
+        std::vector<std::pair<size_t, double>> pieces, lv;
+        std::vector<size_t> cv;
+        for (uint64_t i = b; i < e; ++i) {
+            History h;
+            run_history(s, views[i], hists[i], true, h);
+            if (h.fate != TALLIED) {
+                if (tallied_bin) tallied_bin[i] = -1;
+                continue;
+            }
+            const size_t bin = bin_index(p, h.view, h.cls, h.iv, h.iu);
+            if (tallied_bin) tallied_bin[i] = (int64_t)bin;
+            lv.clear(); cv.clear();
+            path_terms(s, h, pieces, lv, cv);
+            const double Gb = G[bin];
+            for (auto& q : lv) tg[ti][q.first] -= Gb * q.second;
+            for (size_t v : cv) tg[ti][v] += Gb / (double)p->mu140[v];
+        }
+    });
+    for (auto& t : tg) for (size_t v = 0; v < nvox; ++v) grad[v] += t[v];
     return 0;
 }
 

@@ -366,6 +366,91 @@ def test_replay_agrees_with_simulate():
     np.testing.assert_array_equal(tally, r["tally"])
 
 
+
+# ---------------------------------------------------------------------------
+# Projection geometry (Sec. 3: a camera rotating about the axis)
+# ---------------------------------------------------------------------------
+
+def _geometry_problem():
+    """A small off-centre voxel source in vacuum: 16^3 grid of 1 mm voxels,
+    activity in voxel (ix, iy, iz) = (15, 1, 13), 2 degree cone, 16 x 16
+    detector of 1 cm pixels, nine views over 180 degrees."""
+    n, vox = 16, 0.1
+    mu = np.zeros((n, n, n), np.float32)
+    act = np.zeros((n, n, n), np.uint32)
+    src_idx = (15, 1, 13)                     # (ix, iy, iz)
+    act[src_idx[2], src_idx[1], src_idx[0]] = 1
+    V = 9
+    base = phantoms.point_source_cube("geom", n, vox, 9 * 400_000)
+    p = base.with_(mu=mu, activity=act, source_mode=phantoms.SOURCE_VOXELS,
+                   angles=phantoms.view_angles(V, 180.0), nu=16, nv=16, pixel_cm=1.0,
+                   radius_cm=phantoms.detector_radius(n, n, vox),
+                   accept_half_angle_rad=math.radians(2.0))
+    centre = np.array([-0.5 * n * vox + (i + 0.5) * vox for i in src_idx])
+    return p, centre
+
+
+def _predicted_pixel(p, centre, theta, mirror_u=False, reverse=False, swap=False):
+    """Closed-form landing pixel of a ray along the view normal n = (cos t,
+    sin t, 0) from the voxel centre: u = (-sin t, cos t, 0) . x, v = z,
+    bin = floor((u + W/2) / pixel); with the alternative conventions a
+    plausible mistake would give."""
+    t = -theta if reverse else theta
+    u = -math.sin(t) * centre[0] + math.cos(t) * centre[1]
+    if mirror_u:
+        u = -u
+    v = centre[2]
+    iu = math.floor((u + 0.5 * p.nu * p.pixel_cm) / p.pixel_cm)
+    iv = math.floor((v + 0.5 * p.nv * p.pixel_cm) / p.pixel_cm)
+    return (iu, iv) if swap else (iv, iu)
+
+
+def test_projection_geometry_off_centre_source():
+    """Primaries of an off-centre source land, view by view, in the pixel the
+    camera geometry predicts: the detector axis u_k = (-sin t_k, cos t_k, 0)
+    rotating with the view, v along z, half-open bins from the detector edge.
+    Views whose predicted landing point has more margin to a pixel edge than
+    the largest spread (half the voxel's extent across u or v plus the cone's
+    tilt over the flight to the plane) must see every tallied photon in that
+    pixel.  A mirrored u axis, a reversed rotation sense or swapped (iu, iv)
+    predict a different pixel in at least one checked view, so each would
+    fail here."""
+    p, c = _geometry_problem()
+    r = oracle.simulate(p)
+    tally = r["tally"]
+    assert tally[:, 1].sum() == 0                      # vacuum: no scatter
+    half = 0.5 * p.nx * p.voxel_cm
+    t_max = p.radius_cm + half * math.sqrt(2)          # longest flight from the grid to the plane
+    tilt = t_max * math.tan(p.accept_half_angle_rad)
+    checked = 0
+    alternatives = {"mirror_u": False, "reverse": False, "swap": False}
+    for k, th in enumerate(p.angles):
+        u = -math.sin(th) * c[0] + math.cos(th) * c[1]
+        spread_u = 0.5 * p.voxel_cm * (abs(math.sin(th)) + abs(math.cos(th))) + tilt
+        spread_v = 0.5 * p.voxel_cm + tilt
+        fu = (u + 0.5 * p.nu * p.pixel_cm) / p.pixel_cm
+        fv = (c[2] + 0.5 * p.nv * p.pixel_cm) / p.pixel_cm
+        mu_ = min(fu - math.floor(fu), math.ceil(fu) - fu) * p.pixel_cm
+        mv_ = min(fv - math.floor(fv), math.ceil(fv) - fv) * p.pixel_cm
+        view = tally[k, 0]
+        assert view.sum() > 50, k
+        if mu_ <= spread_u or mv_ <= spread_v:
+            continue
+        checked += 1
+        iv, iu = _predicted_pixel(p, c, th)
+        nz = np.argwhere(view > 0)
+        assert nz.tolist() == [[iv, iu]], (k, nz.tolist(), (iv, iu))
+        for name in alternatives:
+            if _predicted_pixel(p, c, th, **{name: True}) != (iv, iu):
+                alternatives[name] = True
+    assert checked >= 4, checked
+    assert all(alternatives.values()), alternatives
+    # about (1 - cos a)/2 of each view's photons pass the collimator
+    per_view = tally[:, 0].sum(axis=(1, 2))
+    pexp = 0.5 * (1 - math.cos(p.accept_half_angle_rad))
+    n_view = p.n_histories // p.n_views
+    assert np.all(np.abs((per_view - n_view * pexp) / math.sqrt(n_view * pexp)) < 5)
+
 # ---------------------------------------------------------------------------
 # Adjoint
 # ---------------------------------------------------------------------------
@@ -428,6 +513,77 @@ def test_adjoint_gradient_matches_path_frozen_fd():
     scale = np.maximum(np.abs(fd), 1e-2 * np.abs(fd).max())
     assert np.all(np.abs(g - fd) <= 1e-5 * scale), (g, fd)
     np.testing.assert_array_equal(r["grad"], r0["grad"])
+
+
+def _replay_all(prob):
+    N, V = prob.n_histories, prob.n_views
+    views = np.concatenate([np.full(N // V + (k < N % V), k, np.int32) for k in range(V)])
+    hists = np.concatenate([np.arange(N // V + (k < N % V), dtype=np.uint64) for k in range(V)])
+    return oracle.replay(prob, views, hists), views, hists
+
+
+def _tally_key(rec):
+    """Per history: its bin if tallied, else -1."""
+    b = ((rec["view"].astype(np.int64) * 2 + rec["cls"]) * 10_000 + rec["iv"]) * 10_000 + rec["iu"]
+    return np.where(rec["fate"] == 5, b, -1)
+
+
+def test_adjoint_with_scatter_matches_analog_crn_fd_on_scaling():
+    """Scattered photons in the window (100-154 keV): under mu -> s mu the
+    likelihood-ratio estimate sum_v mu_v dlambda/dmu_v, which now includes
+    the Compton-vertex term c_v/mu_v, must match the central difference of
+    analog runs at s = 1 +- h on the same random numbers.  The FD's error is
+    set by the histories whose tally outcome differs between the two runs
+    (counted exactly by replaying both); dropping the vertex term moves the
+    estimate by the number of Compton vertices on tallied paths, many times
+    that error."""
+    N = 2_000_000
+    alpha = math.radians(20.0)
+    base = phantoms.point_source_cube("adjs", 32, 0.4, N).with_(
+        accept_half_angle_rad=alpha, e_lo_kev=100.0, e_hi_kev=154.0, e_cut_kev=100.0)
+    h = 0.1
+    rp, _, _ = _replay_all(base.with_(mu=(base.mu * (1 + h)).astype(np.float32)))
+    rm, _, _ = _replay_all(base.with_(mu=(base.mu * (1 - h)).astype(np.float32)))
+    lp, lm = np.sum(rp["fate"] == 5), np.sum(rm["fate"] == 5)
+    fd = (lp - lm) / (2 * h)
+    n_diff = int(np.sum(_tally_key(rp) != _tally_key(rm)))
+    G = np.ones(base.tally_shape)
+    r = oracle.adjoint(base, G)
+    est = float(np.sum(r["grad"] * base.mu.astype(np.float64)))
+    T = r["fates"][5]
+    # the vertex term alone: +1 per Compton vertex of every tallied path
+    rec0, _, _ = _replay_all(base)
+    vertices = float(np.sum(rec0["n_scatter"][rec0["fate"] == 5]))
+    sd_fd = math.sqrt(n_diff) / (2 * h)
+    # per tallied history |c - mu lt| <= max(n_scatter, mu * longest path (g <= 1.2)) ~ 3
+    sd_est = 3.0 * math.sqrt(T)
+    bias = 0.01 * abs(fd)             # O(h^2) curvature of exp(-s mu L): (mu L)^2 h^2 / 6 < 1 %
+    tol = 4 * (sd_fd + sd_est) + bias
+    assert np.sum(rec0["n_scatter"][rec0["fate"] == 5] > 0) > 0.15 * T     # scatter is in the window
+    assert abs(fd - est) < tol, (fd, est, tol)
+    assert vertices > 1.5 * tol, (vertices, tol)
+
+
+def test_adjoint_list_matches_full_adjoint():
+    """The gradient over an explicit list of histories: over every history it
+    is the full gradient; over two halves it adds up; the returned bins agree
+    with the replay records."""
+    N = 60_000
+    p = phantoms.thorax_problem("adjl", 32, 1.2, 2, 6, 180.0, 32, 1.2, N)
+    rng = np.random.Generator(np.random.PCG64(8))
+    G = rng.uniform(-1, 1, p.tally_shape)
+    full = oracle.adjoint(p, G)["grad"]
+    rec, views, hists = _replay_all(p)
+    g_all, bins = oracle.adjoint_list(p, G, views, hists)
+    np.testing.assert_allclose(g_all, full, rtol=1e-9, atol=1e-12 * np.abs(full).max())
+    want = np.where(rec["fate"] == 5,
+                    ((rec["view"].astype(np.int64) * 2 + rec["cls"]) * p.nv + rec["iv"]) * p.nu + rec["iu"],
+                    -1)
+    np.testing.assert_array_equal(bins, want)
+    half = len(views) // 2
+    a, _ = oracle.adjoint_list(p, G, views[:half], hists[:half])
+    b, _ = oracle.adjoint_list(p, G, views[half:], hists[half:])
+    np.testing.assert_allclose(a + b, full, rtol=1e-9, atol=1e-12 * np.abs(full).max())
 
 
 # ---------------------------------------------------------------------------
@@ -668,22 +824,19 @@ def test_fd_unbiased_against_analog():
 
 
 def test_box_escape_shortcut_changes_only_step_counts():
-    """Photons in a voxel outside the attenuation box and moving away from it
-    escape at once: with the shortcut switched off every replayed history ends
-    with the same fate, bin, scatter count and energy, and only the number of
-    tentative collisions drops (here by a quarter) when it is on."""
+    """The optional escape shortcut (a photon in a voxel outside the
+    attenuation box, moving away from it, escapes at once) is exact: against
+    the default plain walk every replayed history ends with the same fate,
+    bin, scatter count and energy, tallies and fates are identical, and only
+    the number of tentative collisions drops (here by a quarter)."""
     p = phantoms.thorax_problem("box", 48, 0.8, 2, 12, 180.0, 32, 1.2, 200_000)
     rng = np.random.Generator(np.random.PCG64(13))
     views = rng.integers(0, p.n_views, 20_000).astype(np.int32)
     hists = rng.integers(0, p.n_histories // p.n_views, 20_000).astype(np.uint64)
-    try:
-        oracle.set_box_skip(False)
-        a = oracle.replay(p, views, hists)
-        ra = oracle.simulate(p)
-    finally:
-        oracle.set_box_skip(True)
-    b = oracle.replay(p, views, hists)
-    rb = oracle.simulate(p)
+    a = oracle.replay(p, views, hists)
+    ra = oracle.simulate(p)
+    b = oracle.replay(p, views, hists, escape_shortcut=True)
+    rb = oracle.simulate(p, escape_shortcut=True)
     for f in ("fate", "iu", "iv", "n_scatter", "emit_voxel", "cls", "e_final"):
         np.testing.assert_array_equal(a[f], b[f])
     assert np.all(b["n_tent"] <= a["n_tent"])

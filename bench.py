@@ -60,6 +60,44 @@ def traffic_bytes():
     return 1024.0 * (t["fetch"] * COPY_SCALE["fetch"] + t["write"] * COPY_SCALE["write"])
 
 
+PROBE_CLASSES = ["mad_u64", "xor_add", "fma", "log", "sin", "sqrt", "rcp", "philox_block"]
+
+
+def issue_rates(torch, blocks=None, iters=20000):
+    """Sustained issue rate of each instruction class the transport uses, from
+    the probe kernels (libmcprobe.so): eight independent chains per lane, no
+    memory traffic, eight waves per SIMD.  Returns the cost of one
+    lane-operation of each class in full-rate lane slots (xor/add = 1) and the
+    measured full-rate rate in lane-ops/s.  Loop bodies (from the probes'
+    gfx950 assembly): mad64 8 v_mad_u64_u32 + 8 v_xor; xor 8 v_xor + 8 v_add;
+    fma 8 v_fmaak; each transcendental 8 of it + 8 v_mul; the Philox probe
+    one ten-round block (20 v_mad_u64_u32, ~40 v_xor) per eighth iteration."""
+    import ctypes as C
+    lib = C.CDLL(os.path.join(ROOT, "paper_2105_13324_amd", "libmcprobe.so"))
+    lib.mc_probe_issue.argtypes = [C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_float), C.c_void_p]
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks = blocks or n_cu * 8
+    scratch = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    ms = (C.c_float * 8)()
+    rc = lib.mc_probe_issue(blocks, iters, scratch.data_ptr(), ms,
+                            torch.cuda.current_stream().cuda_stream)
+    if rc != 0:
+        raise RuntimeError(f"mc_probe_issue failed ({rc})")
+    t = dict(zip(PROBE_CLASSES, [float(x) for x in ms]))
+    lanes = blocks * 256 * iters
+    full = 16 * lanes / (t["xor_add"] / 1e3)           # full-rate lane-ops/s
+    slot = t["xor_add"] / 16                            # ms per (lane-op x lanes x iters)
+    cost = {"xor_add": 1.0, "fma": t["fma"] / (8 * slot),
+            "mad_u64": (t["mad_u64"] - 8 * slot) / (8 * slot)}
+    mul = cost["fma"]                                   # v_mul_f32 issues like v_fma
+    for k in ("log", "sin", "sqrt", "rcp"):
+        cost[k] = (t[k] - 8 * mul * slot) / (8 * slot)
+    # one Philox block per eighth iteration: its cost in full-rate slots
+    cost["philox_block"] = t["philox_block"] / (slot * (iters // 8) / iters)
+    return {"full_rate_lane_ops_per_s": full, "peak_nominal_lane_ops_per_s": PEAK_LANE_OPS,
+            "cost_in_full_rate_slots": cost, "probe_ms": t, "blocks": blocks, "iters": iters}
+
+
 def ops_per_history(n_tent, n_kahn, n_scatter, n_hist):
     per = (2 * (OPS_PHILOX) + OPS_EMISSION + OPS_END) * n_hist \
         + n_tent * (OPS_PHILOX + OPS_STEP) + n_kahn * (OPS_PHILOX + OPS_KAHN) \
@@ -106,6 +144,8 @@ def main():
                          "adjoint step on the 128^3 cube) and print its record; for profiling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--issue-probe", action="store_true",
+                    help="only run the instruction issue-rate probes and print their record")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the transport path is built and timed on a single "
@@ -121,6 +161,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 1 << 30}))
+        return
+    if args.issue_probe:
+        print(json.dumps(issue_rates(torch)))
         return
     import phantoms
     import paper_2105_13324_amd as mc

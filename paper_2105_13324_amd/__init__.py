@@ -519,14 +519,21 @@ def fd_tally_sq_float(t) -> np.ndarray:
 
 
 def adjoint(problem: DeviceProblem, dL_dtally, sim: Optional[Simulator] = None,
-            frac_bits: int = 40, raw: bool = False):
+            frac_bits: int = 40, raw: bool = False, events: Optional[np.ndarray] = None):
     """dL/dmu (float64 tensor [nz, ny, nx]) for G = dL_dtally (tally layout).
 
     sim: the forward Simulator of the same problem; its event list (if it has
     one) restricts the replay to the tallied histories.  Without it every
-    history of the range is replayed."""
+    history of the range is replayed.  events: an explicit list of tallied
+    histories (EVENT_DTYPE records, e.g. a subset of sim.events_numpy()) to
+    replay instead of sim's list."""
     torch = _torch()
     dev = problem.mu.device
+    if events is not None:
+        ev = np.ascontiguousarray(events, dtype=EVENT_DTYPE)
+        ev_t = torch.from_numpy(ev.view(np.int64).reshape(-1, 3).copy()).to(dev) if len(ev) else \
+            torch.zeros((1, 3), dtype=torch.int64, device=dev)
+        ev_n = torch.tensor([len(ev)], dtype=torch.int64, device=dev)
     G = dL_dtally.to(device=dev, dtype=torch.float64).contiguous()
     if G.numel() != int(np.prod(problem.tally_shape)):
         raise McError("dL_dtally has the wrong size")
@@ -548,13 +555,16 @@ def adjoint(problem: DeviceProblem, dL_dtally, sim: Optional[Simulator] = None,
             opt.brick_log2, opt.threshold_bytes = sim.options.brick_log2, sim.options.threshold_bytes
     else:
         ws = torch.empty(nb, dtype=torch.uint8, device=dev)
-    use_events = sim is not None and sim.events is not None
+    if events is not None:
+        use_events, ev_ptr, n_ptr, cap = True, ev_t.data_ptr(), ev_n.data_ptr(), max(len(ev), 1)
+    else:
+        use_events = sim is not None and sim.events is not None
+        ev_ptr = sim.events.data_ptr() if use_events else None
+        n_ptr = sim.n_events.data_ptr() if use_events else None
+        cap = sim.event_capacity if use_events else 0
     rc = _lib.mc_adjoint_mu(C.byref(arr), C.byref(opt) if opt is not None else None, G.data_ptr(),
-                            sim.events.data_ptr() if use_events else None,
-                            sim.n_events.data_ptr() if use_events else None,
-                            sim.event_capacity if use_events else 0,
-                            grad.data_ptr(), int(frac_bits), status.data_ptr(), ws.data_ptr(), nb,
-                            _stream_ptr())
+                            ev_ptr, n_ptr, cap, grad.data_ptr(), int(frac_bits), status.data_ptr(),
+                            ws.data_ptr(), nb, _stream_ptr())
     _check(rc, "mc_adjoint_mu")
     torch.cuda.synchronize()
     st = status.cpu().numpy()
@@ -564,7 +574,7 @@ def adjoint(problem: DeviceProblem, dL_dtally, sim: Optional[Simulator] = None,
         raise McError(f"gradient overflow at frac_bits={frac_bits}; use fewer fractional bits")
     if st[0] & STATUS_BAD_EVENT:
         raise McError("an event did not replay to its bin (event list from another problem?)")
-    if use_events and int(sim.n_events.item()) > sim.event_capacity:
+    if events is None and use_events and int(sim.n_events.item()) > sim.event_capacity:
         raise McError("the forward event list overflowed; raise event_capacity")
     if raw:
         return grad

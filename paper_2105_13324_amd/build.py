@@ -11,6 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmcspect.so")
+# issue-rate probes for the benchmark's roofline (not part of the product library)
+PROBE_LIB = os.path.join(HERE, "libmcprobe.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.hip", "staging.hip", "transport.hip", "adjoint.hip", "sysmat.hip", "cfd.hip", "cgsm.hip"]
@@ -42,6 +44,10 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     subprocess.check_call([_hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp])
     os.replace(tmp, LIB)
+    probe = compile_one("probe.hip")
+    subprocess.check_call([_hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", probe, "-o",
+                           PROBE_LIB + ".tmp"])
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     if verbose:
         print("built", LIB)
     return LIB

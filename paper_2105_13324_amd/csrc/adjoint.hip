@@ -37,56 +37,74 @@ __device__ inline void add_fixed(long long* grad, uint32_t v, double val, double
 
 // Walk the ray a + t d over t in [t0, t1), adding w * (length in voxel) to
 // every voxel the piece crosses; the piece starts in the voxel holding
-// a + t0 d (clamped to the grid) and stops at t1 or at the grid edge.
-__device__ void walk_piece(const Cst& C, float ax, float ay, float az, float dx, float dy, float dz,
-                           float t0, float t1, double w, long long* grad, double scale,
+// a + t0 d (clamped to the grid) and stops at t1 or at the grid edge.  The
+// path itself (vertices, directions) is the FP32 replay's; the walk along it
+// is in double precision, with every plane crossing computed from its plane
+// index (t = (plane - p) / d) rather than accumulated step by step, so the
+// lengths carry no error beyond that of the FP32 vertices.
+__device__ void walk_piece(const Cst& C, double ax, double ay, double az, double dx, double dy,
+                           double dz, double t0, double t1, double w, long long* grad, double scale,
                            int64_t* status) {
     if (!(t1 > t0)) return;
-    const float px = fmaf(t0, dx, ax) + C.hx, py = fmaf(t0, dy, ay) + C.hy, pz = fmaf(t0, dz, az) + C.hz;
-    int ix = min(max((int)(px * C.inv_vox), 0), C.nx - 1);
-    int iy = min(max((int)(py * C.inv_vox), 0), C.ny - 1);
-    int iz = min(max((int)(pz * C.inv_vox), 0), C.nz - 1);
-    const int sx = dx > 0.0f ? 1 : -1, sy = dy > 0.0f ? 1 : -1, sz = dz > 0.0f ? 1 : -1;
-    const float inf = __builtin_huge_valf();
-    // parametric distance (from t0) to the next plane on each axis, and between planes
-    float tx = dx != 0.0f ? (((float)(ix + (dx > 0.0f)) * C.vox) - px) / dx : inf;
-    float ty = dy != 0.0f ? (((float)(iy + (dy > 0.0f)) * C.vox) - py) / dy : inf;
-    float tz = dz != 0.0f ? (((float)(iz + (dz > 0.0f)) * C.vox) - pz) / dz : inf;
-    const float ddx = dx != 0.0f ? C.vox / fabsf(dx) : inf;
-    const float ddy = dy != 0.0f ? C.vox / fabsf(dy) : inf;
-    const float ddz = dz != 0.0f ? C.vox / fabsf(dz) : inf;
-    tx = fmaxf(tx, 0.0f); ty = fmaxf(ty, 0.0f); tz = fmaxf(tz, 0.0f);
-    const float t_end = t1 - t0;
-    float t = 0.0f;
+    const double vox = (double)C.vox;
+    const double px = fma(t0, dx, ax) + (double)C.hx, py = fma(t0, dy, ay) + (double)C.hy,
+                 pz = fma(t0, dz, az) + (double)C.hz;
+    int ix = min(max((int)floor(px / vox), 0), C.nx - 1);
+    int iy = min(max((int)floor(py / vox), 0), C.ny - 1);
+    int iz = min(max((int)floor(pz / vox), 0), C.nz - 1);
+    const int sx = dx > 0.0 ? 1 : -1, sy = dy > 0.0 ? 1 : -1, sz = dz > 0.0 ? 1 : -1;
+    const int ox = dx > 0.0 ? 1 : 0, oy = dy > 0.0 ? 1 : 0, oz = dz > 0.0 ? 1 : 0;
+    const double inf = __builtin_huge_val();
+    const double idx = dx != 0.0 ? 1.0 / dx : inf, idy = dy != 0.0 ? 1.0 / dy : inf,
+                 idz = dz != 0.0 ? 1.0 / dz : inf;
+    // parametric distance (from t0) to the next plane on each axis
+    auto plane_t = [&](int i, int o, double p, double id, double d) {
+        return d != 0.0 ? fmax(((double)(i + o) * vox - p) * id, 0.0) : inf;
+    };
+    double tx = plane_t(ix, ox, px, idx, dx), ty = plane_t(iy, oy, py, idy, dy),
+           tz = plane_t(iz, oz, pz, idz, dz);
+    const double t_end = t1 - t0;
+    double t = 0.0;
     const int max_iter = C.nx + C.ny + C.nz + 3;
     for (int it = 0; it < max_iter; ++it) {
-        const float tn = fminf(tx, fminf(ty, tz));
-        const float te = fminf(tn, t_end);
+        const double tn = fmin(tx, fmin(ty, tz));
+        const double te = fmin(tn, t_end);
         const uint32_t v = (uint32_t)ix + (uint32_t)C.nx * ((uint32_t)iy + (uint32_t)C.ny * (uint32_t)iz);
-        if (te > t) add_fixed(grad, v, w * (double)(te - t), scale, status);
+        if (te > t) add_fixed(grad, v, w * (te - t), scale, status);
         if (tn >= t_end) return;
         t = tn;
-        if (tx <= ty && tx <= tz) { ix += sx; tx += ddx; if (ix < 0 || ix >= C.nx) return; }
-        else if (ty <= tz)        { iy += sy; ty += ddy; if (iy < 0 || iy >= C.ny) return; }
-        else                      { iz += sz; tz += ddz; if (iz < 0 || iz >= C.nz) return; }
+        if (tx <= ty && tx <= tz) {
+            ix += sx;
+            if (ix < 0 || ix >= C.nx) return;
+            tx = plane_t(ix, ox, px, idx, dx);
+        } else if (ty <= tz) {
+            iy += sy;
+            if (iy < 0 || iy >= C.ny) return;
+            ty = plane_t(iy, oy, py, idy, dy);
+        } else {
+            iz += sz;
+            if (iz < 0 || iz >= C.nz) return;
+            tz = plane_t(iz, oz, pz, idz, dz);
+        }
     }
 }
 
 // Walk the ray a + t d, t in [0, t_end) (t_end = +inf: to the grid exit), by
 // the whole wavefront: the range is cut into 64 equal pieces, lane k walks
 // piece k.  Every lane must call it with the same arguments.
-__device__ void walk_wave(const Cst& C, float ax, float ay, float az, float dx, float dy, float dz,
-                          float t_end, double w, long long* grad, double scale, int64_t* status) {
-    const float inf = __builtin_huge_valf();
-    const float px = ax + C.hx, py = ay + C.hy, pz = az + C.hz;
-    const float ex = dx > 0.0f ? (C.lx - px) / dx : (dx < 0.0f ? -px / dx : inf);
-    const float ey = dy > 0.0f ? (C.ly - py) / dy : (dy < 0.0f ? -py / dy : inf);
-    const float ez = dz > 0.0f ? (C.lz - pz) / dz : (dz < 0.0f ? -pz / dz : inf);
-    const float len = fminf(t_end, fmaxf(fminf(ex, fminf(ey, ez)), 0.0f));
+__device__ void walk_wave(const Cst& C, double ax, double ay, double az, double dx, double dy,
+                          double dz, double t_end, double w, long long* grad, double scale,
+                          int64_t* status) {
+    const double inf = __builtin_huge_val();
+    const double px = ax + (double)C.hx, py = ay + (double)C.hy, pz = az + (double)C.hz;
+    const double ex = dx > 0.0 ? ((double)C.lx - px) / dx : (dx < 0.0 ? -px / dx : inf);
+    const double ey = dy > 0.0 ? ((double)C.ly - py) / dy : (dy < 0.0 ? -py / dy : inf);
+    const double ez = dz > 0.0 ? ((double)C.lz - pz) / dz : (dz < 0.0 ? -pz / dz : inf);
+    const double len = fmin(t_end, fmax(fmin(ex, fmin(ey, ez)), 0.0));
     const int lane = threadIdx.x & 63;
-    const float piece = len * (1.0f / 64.0f);
-    const float t0 = (float)lane * piece;
-    const float t1 = lane == 63 ? len : (float)(lane + 1) * piece;
+    const double piece = len * (1.0 / 64.0);
+    const double t0 = (double)lane * piece;
+    const double t1 = lane == 63 ? len : (double)(lane + 1) * piece;
     walk_piece(C, ax, ay, az, dx, dy, dz, t0, t1, w, grad, scale, status);
 }
 
@@ -107,7 +125,7 @@ __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now,
     begin_history(C, L, (uint32_t)view, (uint32_t)hist, em);
     Acc A;
     acc_zero(A);
-    float sx = L.x, sy = L.y, sz = L.z;   // start of the current segment
+    double sx = L.x, sy = L.y, sz = L.z;   // start of the current segment
     for (;;) {
         uint32_t c0 = (uint32_t)L.hist, c1 = (uint32_t)L.view, c2, c3;
         counter_of(L, c2, c3);
@@ -118,9 +136,10 @@ __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now,
         const int fate = advance(C, C.pal, L, c0, c1, c2, c3, A, iu, iv);
         if (fate == R_RUNNING) {
             if (walk_now && before == S_STEP && L.state == S_KAHN) {
-                // Compton vertex at L.x: close the segment, add the collision term
-                const float ex = L.x - sx, ey = L.y - sy, ez = L.z - sz;
-                const float len = ex * L.dx + ey * L.dy + ez * L.dz;
+                // Compton vertex at L.x: close the segment (its direction is
+                // still the one it was flown in), add the collision term
+                const double ex = (double)L.x - sx, ey = (double)L.y - sy, ez = (double)L.z - sz;
+                const double len = ex * L.dx + ey * L.dy + ez * L.dz;
                 walk_wave(C, sx, sy, sz, L.dx, L.dy, L.dz, len, -G * g_of(C, e_flight), grad, scale, status);
                 if ((threadIdx.x & 63) == 0) {
                     const int ix = min((int)((L.x + C.hx) * C.inv_vox), C.nx - 1);
@@ -137,7 +156,7 @@ __device__ int replay_path(const Cst& C, uint64_t hist, int view, bool walk_now,
             const int cls = L.n_scatter > 0 ? 1 : 0;
             bin_out = (uint32_t)((((uint32_t)L.view * 2u + cls) * (uint32_t)C.nv + iv) * (uint32_t)C.nu + iu);
             if (walk_now)
-                walk_wave(C, sx, sy, sz, L.dx, L.dy, L.dz, __builtin_huge_valf(), -G * g_of(C, L.e),
+                walk_wave(C, sx, sy, sz, L.dx, L.dy, L.dz, __builtin_huge_val(), -G * g_of(C, L.e),
                           grad, scale, status);
         }
         return fate;

@@ -1,33 +1,44 @@
 """GPU adjoint (dL/dmu) against the oracle's gradient and its central finite
 differences, through the C ABI.
 
-Bar: on the 16 checked voxels |g_gpu - g_FD| <= 1e-3 * max(|g_FD|, 1e-2 *
-max|g_FD|) (finite differences of the path-frozen estimator, common random
-numbers, delta mu = 1e-3 /cm); over the whole grid the relative L2 distance to
-the oracle's FP64 gradient <= 1e-4 when both sides tallied the same
-histories.  A history whose fate flipped between FP32 and FP64 moves the
-gradient by about its own share, so with n_flip such histories out of n
-tallied the grid-wide bar is 1e-4 + 3 sqrt(n_flip / n).
+Bars:
+* finite differences: on 16 checked voxels |g_gpu - g_FD| <= 1e-3 *
+  max(|g_FD|, 1e-2 max|g_FD|), with g_FD the oracle's central difference
+  (delta mu = 1e-3 /cm) of the path-frozen estimator on common random numbers;
+* element by element: on the histories both sides tallied in the same bin
+  (the transport kernel's event list intersected with the oracle's), the
+  GPU gradient over exactly those histories against the oracle's over the
+  same list.  The GPU walks each path in double precision with 2^-40
+  fixed-point sums, so what remains is the path itself: the GPU follows the
+  history in FP32 with the hardware sin, cos and sqrt, whose directions
+  differ from the oracle's FP64 ones by ~1e-6.  Over a flight of length L
+  that moves the crossing of a voxel plane by ~1e-6 L / theta for a ray that
+  meets the plane at a grazing angle theta: the near-axial rays a 2 degree
+  cone admits meet the planes along the other two axes at theta ~ 0.03, and
+  over 6 cm their crossings shift by ~2e-4 cm, ~2e-3 of a 1 mm voxel, at the
+  two voxels beside each crossing.  Measured over the
+  four workloads below: relative L2 up to 9.4e-5 and largest per-voxel error
+  up to 1.6e-4 of the largest magnitude (both on the 1 mm cube).  Bars:
+  relative L2 <= 2e-4, every voxel within 4e-4 of the largest magnitude;
+* the forward window total agrees with the oracle's as in the transport
+  tests (every difference is a history tallied on one side only).
 """
-import sys
-
 import numpy as np
 import pytest
 
 import oracle
 import phantoms
+from parity import ids_of_work, say, tallied_flips
 
 pytestmark = pytest.mark.gpu
+
+REL_L2 = 2e-4
+PER_VOXEL = 4e-4
 
 
 def _mc():
     import paper_2105_13324_amd as mc
     return mc
-
-
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
 
 
 def loss_inputs(prob):
@@ -43,6 +54,30 @@ def loss_inputs(prob):
     return lam, y, eps, G
 
 
+def shared_history_gradient(prob, dp, G, sim, o):
+    """The GPU gradient over the histories both sides tallied in the same bin
+    against the oracle's over the same list.  Returns (rel L2, largest
+    per-voxel error relative to the largest magnitude, histories)."""
+    mc = _mc()
+    import torch
+    ev = sim.events_numpy()
+    gk = ev["work"].astype(np.int64) * (1 << 32) + ev["bin"].astype(np.int64)
+    ok = o["trip_g"].astype(np.int64) * (1 << 32) + o["trip_j"].astype(np.int64)
+    common = ev[np.isin(gk, ok)]
+    g = mc.adjoint(dp, torch.from_numpy(G), sim, events=common).cpu().numpy().reshape(-1)
+    views, hists = ids_of_work(prob, common["work"].astype(np.int64))
+    go, bins = oracle.adjoint_list(prob, G, views, hists)
+    np.testing.assert_array_equal(bins, common["bin"].astype(np.int64))
+    go = go.reshape(-1)
+    rel_l2 = float(np.linalg.norm(g - go) / np.linalg.norm(go))
+    per_vox = float(np.max(np.abs(g - go)) / np.abs(go).max())
+    big = np.abs(go) >= 1e-2 * np.abs(go).max()
+    per_vox_big = float(np.max(np.abs(g[big] - go[big]) / np.abs(go[big])))
+    say(f"  shared-history gradient: rel L2 {rel_l2:.2e}, max |g - g_or| / max |g_or| {per_vox:.2e}, "
+        f"max relative error on voxels above 1 % of the maximum {per_vox_big:.2e}")
+    return rel_l2, per_vox, len(common)
+
+
 def check_adjoint(prob, n_check=16, min_contrib=50):
     mc = _mc()
     import torch
@@ -54,28 +89,29 @@ def check_adjoint(prob, n_check=16, min_contrib=50):
     ro = oracle.adjoint(prob, G, pert_voxels=vox, delta=1e-3, lam=lam, y=y, eps=eps)
     fd = ro["fd"]
     dp = mc.to_device(prob)
-    sim = mc.simulate(dp, event_capacity=200_000, want_sq=False)
-    # histories tallied (same bin) on one side only
-    ev = sim.events_numpy()
     oe = oracle.simulate(prob, want_triplets=True)
-    gpu_set = set(zip(ev["work"].astype(np.int64).tolist(), ev["bin"].astype(np.int64).tolist()))
-    orc_set = set(zip(oe["trip_g"].tolist(), oe["trip_j"].tolist()))
-    n_flip = len(gpu_set ^ orc_set)
+    T = int(oe["fates"][5])
+    sim = mc.simulate(dp, event_capacity=2 * T + 1024, want_sq=False)
+    ev = sim.events_numpy()
+    g_only, o_only = tallied_flips(prob, ev, oe["trip_g"], oe["trip_j"])
+    n_flip = len(g_only) + len(o_only)
+    window_rel = abs(len(ev) - T) / T
     Gt = torch.from_numpy(G)
     g_ev = mc.adjoint(dp, Gt, sim).cpu().numpy()
     g_all = mc.adjoint(dp, Gt, None).cpu().numpy()
     # events mode and replay-everything mode add the same fixed-point terms
     np.testing.assert_array_equal(g_ev, g_all)
     g = g_ev.reshape(-1)
-    go = ro["grad"].reshape(-1)
-    rel_l2 = np.linalg.norm(g - go) / np.linalg.norm(go)
     scale = np.maximum(np.abs(fd), 1e-2 * np.abs(fd).max())
     err = np.abs(g[vox] - fd) / scale
-    say(f"{prob.name}: tallied {int(sim.fates[0, 5].item())}, flipped {n_flip}, rel L2 vs oracle "
-        f"grad {rel_l2:.2e}, max scaled |g - FD| {err.max():.2e}, oracle self |g - FD| "
-        f"{(np.abs(go[vox] - fd) / scale).max():.2e}")
-    assert n_flip <= 1e-3 * len(orc_set) + 2
-    assert rel_l2 <= 1e-4 + 3.0 * np.sqrt(n_flip / max(len(orc_set), 1))
+    rel_l2, per_vox, n_common = shared_history_gradient(prob, dp, G, sim, oe)
+    say(f"{prob.name}: tallied {T} (gpu {len(ev)}), flipped {n_flip}, window total rel "
+        f"{window_rel:.2e}; shared histories {n_common}: rel L2 {rel_l2:.2e}, max per-voxel "
+        f"{per_vox:.2e}; max scaled |g - FD| {err.max():.2e}, oracle self |g - FD| "
+        f"{(np.abs(r0['grad'].reshape(-1)[vox] - fd) / scale).max():.2e}")
+    assert n_flip <= 1e-3 * T + 1
+    assert rel_l2 <= REL_L2
+    assert per_vox <= PER_VOXEL
     assert np.all(err <= 1e-3), (g[vox], fd)
     # run-to-run bit exactness
     g2 = mc.adjoint(dp, Gt, sim).cpu().numpy()
@@ -98,6 +134,15 @@ def test_adjoint_thorax_small_with_scatter():
 def test_adjoint_point_cube_128_full():
     """The adjoint workload at full size: 128^3 x 1 mm cube, 1e7 histories."""
     check_adjoint(phantoms.point_cube_128_adjoint(10 ** 7))
+
+
+def test_adjoint_thorax_128_secondary():
+    """The secondary adjoint workload: the 128^3 x 3 mm headline thorax with
+    60 views, 1e7 histories (scatter in the window, paths through lung and
+    bone).  Its ~1.4e3 tallied paths spread over 60 views rarely share a
+    voxel, so the finite-difference voxels are drawn among those that at
+    least three tallied paths cross."""
+    check_adjoint(phantoms.thorax_128(10 ** 7), min_contrib=3)
 
 
 def test_autograd_function_matches_adjoint():

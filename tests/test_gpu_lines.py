@@ -18,7 +18,7 @@ import phantoms
 
 pytestmark = pytest.mark.gpu
 
-from test_gpu_transport import aggregate_parity, replay_parity  # noqa: E402
+from parity import aggregate_parity, replay_parity  # noqa: E402
 from test_gpu_fd import fd_parity  # noqa: E402
 
 

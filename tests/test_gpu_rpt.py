@@ -49,7 +49,7 @@ def test_rpt_difference_source_matches_oracle():
     d = new.astype(np.int64) - prev.astype(np.int64)
     dp = mc.to_device(p)
     # replay: same emission voxels (from |d|), same histories
-    from test_gpu_transport import replay_parity
+    from parity import replay_parity
     replay_parity(p, n=50_000)
     sim = mc.simulate(dp, event_capacity=1 << 16)
     sim.check_status()

@@ -1,21 +1,24 @@
 """GPU parity of the forward transport against the FP64 oracle, through the C ABI.
 
-Parity bar (per history): identical fate, detector bin and scatter count for at
-least 99.9% of replayed histories (FP32 tracking against FP64 can flip a
-decision that sits within rounding of a boundary; the event-keyed random
-stream confines such a flip to its own history).  Aggregates: energies within
-1e-4 relative; fate counts and primary/scatter tally totals within 1e-4 of the
-number of histories (a count of a few hundred cannot be held to 1e-4 of itself
-when one flipped history out of 10^6 moves it by one).
+The bars are those of tests/parity.py: identical fate, detector bin and
+scatter count for at least 99.9 % of replayed histories; every aggregate
+difference accounted for by histories identified as flipped (the transport
+kernel's event list against the oracle's tallied list, bin by bin exactly;
+fate counts against a replay of every history on both sides), and within
+1e-4 of the aggregate plus those flips; energies within 1e-4 relative.  The
+oracle walks every history to the grid edge; the kernel's escape shortcut
+outside the attenuation box changes only the count of tentative collisions,
+which is compared with the oracle run with the same shortcut.
 """
 import math
-import sys
 
 import numpy as np
 import pytest
 
 import oracle
 import phantoms
+from parity import (aggregate_parity, replay_parity, sample_ids, say,  # noqa: F401
+                    step_count_parity)
 
 pytestmark = pytest.mark.gpu
 
@@ -25,82 +28,14 @@ def _mc():
     return mc
 
 
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
-def sample_ids(prob, n, seed=7):
-    """n seeded (view, history id) pairs spread over the problem's histories."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    N, V = prob.n_histories, prob.n_views
-    g = np.sort(rng.choice(N, size=min(n, N), replace=False))
-    q, r = divmod(N, V)
-    big = q + 1
-    view = np.where(g < r * big, g // big, r + (g - r * big) // max(q, 1))
-    hist = np.where(g < r * big, g % big, (g - r * big) % max(q, 1))
-    return view.astype(np.int32), hist.astype(np.uint64)
-
-
-def replay_parity(prob, n=100_000, seed=7):
-    mc = _mc()
-    views, hists = sample_ids(prob, n, seed)
-    dp = mc.to_device(prob)
-    g = mc.replay(dp, views, hists)
-    o = oracle.replay(prob, views, hists)
-    same = ((g["fate"] == o["fate"]) & (g["iu"] == o["iu"]) & (g["iv"] == o["iv"])
-            & (g["n_scatter"] == o["n_scatter"]))
-    frac = same.mean()
-    both = same & (g["n_tent"] == o["n_tent"])
-    rel_e = np.abs(g["e_final"][both] - o["e_final"][both]) / o["e_final"][both]
-    say(f"{prob.name}: replay identical {frac:.6f} ({(~same).sum()} differ of {len(same)}), "
-        f"n_tent identical {both.mean():.6f}, max rel dE {rel_e.max() if len(rel_e) else 0:.2e}, "
-        f"tallied {np.sum(o['fate'] == 5)}")
-    assert np.array_equal(g["emit_voxel"], o["emit_voxel"])      # integer inverse CDF: exact
-    assert frac >= 0.999
-    assert rel_e.max() < 1e-5
-    return g, o
-
-
-def aggregate_parity(prob, tol=1e-4, options=None):
-    mc = _mc()
-    dp = mc.to_device(prob)
-    sim = mc.simulate(dp, options=options)
-    st = sim.check_status()
-    o = oracle.simulate(prob)
-    fates = sim.fates.cpu().numpy()[0]
-    tally = mc.tally_float(sim.tally).reshape(prob.tally_shape)
-    tsq = mc.tally_float(sim.tally_sq).reshape(prob.tally_shape)
-    energy = sim.energy.cpu().numpy()[0].astype(np.float64) / mc.Q23
-    cnt = sim.counters.cpu().numpy()[0]
-    say(f"{prob.name}: gpu fates {fates.tolist()}\n  oracle fates {o['fates'].tolist()}")
-    say(f"  energy gpu {energy[:3]} oracle {o['energy'][:3]}")
-    assert cnt[3] == prob.n_histories == fates.sum()
-    assert tally.sum() == fates[5]
-    np.testing.assert_array_equal(tally, tsq)
-    N = prob.n_histories
-    for i in range(7):
-        assert abs(fates[i] - o["fates"][i]) <= tol * N, (i, fates[i], o["fates"][i])
-    for c in range(2):
-        a, b = tally[:, c].sum(), o["tally"][:, c].sum()
-        assert abs(a - b) <= tol * N, (c, a, b)
-    for i in range(3):
-        assert abs(energy[i] - o["energy"][i]) <= tol * max(o["energy"][i], 1.0), (i, energy[i], o["energy"][i])
-    assert abs(cnt[0] - o["n_tent"]) <= tol * o["n_tent"]
-    assert abs(cnt[1] - o["n_real"]) <= tol * o["n_real"]
-    assert abs(cnt[2] - o["n_kahn"]) <= tol * max(o["n_kahn"], 1)
-    # bin-by-bin: identical except for rare flipped histories
-    diff = np.abs(tally - o["tally"]).sum()
-    assert diff <= max(2, 1e-3 * tally.sum()), diff
-    return sim, o
-
-
 def test_point_cube_64_replay():
     replay_parity(phantoms.point_cube_64(10 ** 6))
 
 
 def test_point_cube_64_aggregates():
-    aggregate_parity(phantoms.point_cube_64(10 ** 6))
+    p = phantoms.point_cube_64(10 ** 6)
+    aggregate_parity(p)
+    step_count_parity(p)
 
 
 def test_point_cube_64_photoelectric_heavy():
@@ -113,6 +48,24 @@ def test_thorax_small_replay_and_aggregates():
     p = phantoms.thorax_problem("thorax_64", 64, 0.6, 2, 60, 180.0, 64, 0.6, 2_000_000)
     replay_parity(p)
     aggregate_parity(p)
+    step_count_parity(p)
+
+
+def test_headline_thorax_128_full_parity():
+    """The headline workload itself: 128^3 x 3 mm thorax, 60 views, 64^2 x
+    6 mm, 126-154 keV, all 1e8 histories.  Aggregates against the oracle's
+    full run (tallies explained bin by bin by the flipped tallied histories,
+    fates by a replay of all 1e8 histories on both sides), 1e5 replayed ids
+    drawn with PCG64(7), and tentative-collision counts against the oracle
+    with the kernel's escape shortcut."""
+    mc = _mc()
+    p = phantoms.thorax_128(10 ** 8)
+    dp = mc.to_device(p)
+    say("headline parity: 128^3 thorax, 1e8 histories")
+    replay_parity(p, n=100_000, seed=7, dp=dp)
+    _, _, err = aggregate_parity(p, dp=dp)
+    step_count_parity(p, dp=dp)
+    say(f"headline per-result errors: {err}")
 
 
 def _bucket_kinds(act):
@@ -173,7 +126,7 @@ def test_vacuum_geometric_efficiency():
     alpha = math.radians(20.0)
     p = phantoms.point_source_cube("vac", n, 1.0, 400_000).with_(mu=mu, activity=act,
                                                                  accept_half_angle_rad=alpha)
-    sim, o = aggregate_parity(p)
+    sim, o, _ = aggregate_parity(p)
     fates = sim.fates.cpu().numpy()[0]
     pexp = 0.5 * (1 - math.cos(alpha))
     z = (fates[5] - p.n_histories * pexp) / math.sqrt(p.n_histories * pexp * (1 - pexp))

@@ -20,7 +20,7 @@ import phantoms
 
 pytestmark = pytest.mark.gpu
 
-from test_gpu_transport import sample_ids  # noqa: E402
+from parity import sample_ids  # noqa: E402
 
 
 def _mc():

@@ -85,7 +85,7 @@ bool cfd_ok(const mc_problem& p) { return cfd_layers(p) >= 1 && cfd_hmax(p) <= C
 
 struct Layout {
     size_t desc, prefix, state;
-    std::vector<size_t> q, q8, pal, cdf, vid, bsum, bcnt, guide, views, kn, lay, kern, hw;
+    std::vector<size_t> q, q8, pal, runs, bsum, bcnt, guide, views, kn, lay, kern, hw;
     size_t total;
 };
 
@@ -94,7 +94,7 @@ bool plan(const mc_problem* probs, int n, Layout& L, bool cfd = false) {
     L.desc = off;   off += align256(sizeof(ProbDesc) * (size_t)n);
     L.prefix = off; off += align256(sizeof(uint64_t) * 2 * ((size_t)n + 1));
     L.state = off;  off += align256(sizeof(CallState));
-    L.q.resize(n); L.q8.resize(n); L.pal.resize(n); L.cdf.resize(n); L.vid.resize(n); L.bsum.resize(n); L.bcnt.resize(n);
+    L.q.resize(n); L.q8.resize(n); L.pal.resize(n); L.runs.resize(n); L.bsum.resize(n); L.bcnt.resize(n);
     L.guide.resize(n); L.views.resize(n); L.kn.resize(n);
     L.lay.assign(n, 0); L.kern.assign(n, 0); L.hw.assign(n, 0);
     for (int i = 0; i < n; ++i) {
@@ -103,11 +103,10 @@ bool plan(const mc_problem* probs, int n, Layout& L, bool cfd = false) {
         L.q[i] = off;     off += align256(4 * padded_voxels(p));
         L.q8[i] = off;    off += align256(padded_voxels(p));
         L.pal[i] = off;   off += align256(4 * (size_t)PALETTE_N);
-        L.cdf[i] = off;   off += align256(8 * nvox);
-        L.vid[i] = off;   off += align256(4 * nvox);
+        L.runs[i] = off;  off += align256(16 * nvox);
         L.bsum[i] = off;  off += align256(8 * staging_block_scratch_u64(nvox));
         L.bcnt[i] = off;  off += align256(4 * ((nvox + SCAN_ITEMS - 1) / SCAN_ITEMS));
-        L.guide[i] = off; off += align256(16 * guide_capacity(nvox));
+        L.guide[i] = off; off += align256(8 * guide_capacity(nvox));
         L.views[i] = off; off += align256(8 * (size_t)p.n_views);
         L.kn[i] = off;    off += align256(4 * (size_t)KN_TABLE_N);
         if (cfd) {
@@ -163,11 +162,10 @@ ProbDesc host_desc(const mc_problem& p, char* ws, const Layout& L, int i, uint64
     d.palette = (uint32_t*)(ws + L.pal[i]);
     d.pal_state = threshold_bytes == 4 ? 1u : 0u;
     for (int a = 0; a < 3; ++a) { d.bb_lo[a] = INT32_MAX; d.bb_hi[a] = -1; }
-    d.cdf = (uint64_t*)(ws + L.cdf[i]);
-    d.vox_id = (uint32_t*)(ws + L.vid[i]);
+    d.runs = (uint4*)(ws + L.runs[i]);
     d.block_sums = (uint64_t*)(ws + L.bsum[i]);
     d.block_cnt = (uint32_t*)(ws + L.bcnt[i]);
-    d.guide = (uint4*)(ws + L.guide[i]);
+    d.guide = (uint2*)(ws + L.guide[i]);
     d.views = (float2*)(ws + L.views[i]);
     d.kn_table = (float*)(ws + L.kn[i]);
     if (cfd) {

@@ -60,6 +60,11 @@ __device__ __forceinline__ uint4 ldg(const uint4* p) {
     const v4u v = *(const __attribute__((address_space(1))) v4u*)p;
     return make_uint4(v.x, v.y, v.z, v.w);
 }
+__device__ __forceinline__ uint2 ldg(const uint2* p) {
+    typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+    const v2u v = *(const __attribute__((address_space(1))) v2u*)p;
+    return make_uint2(v.x, v.y);
+}
 __device__ __forceinline__ float2 ldg(const float2* p) {
     typedef float v2f __attribute__((ext_vector_type(2)));
     const v2f v = *(const __attribute__((address_space(1))) v2f*)p;
@@ -82,9 +87,8 @@ struct Cst {
     const uint32_t* q32;
     const uint8_t* q8;
     const uint32_t* pal;
-    const uint64_t* cdf;
-    const uint32_t* vox_id;
-    const uint4* guide;
+    const uint4* runs;
+    const uint2* guide;
     const float2* views;
     const float* kn_table;
     int nx, ny, nz, source_mode;
@@ -129,7 +133,7 @@ __device__ inline float energy_terms(const Cst& C, float e, float& ln2_mm, float
 __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     Cst c;
     c.mu = d->mu;
-    c.q32 = d->q32; c.q8 = d->q8; c.pal = d->palette; c.cdf = d->cdf; c.vox_id = d->vox_id; c.guide = d->guide; c.views = d->views;
+    c.q32 = d->q32; c.q8 = d->q8; c.pal = d->palette; c.runs = d->runs; c.guide = d->guide; c.views = d->views;
     c.kn_table = d->kn_table;
     c.nx = d->nx; c.ny = d->ny; c.nz = d->nz; c.source_mode = d->source_mode;
     c.hx = d->hx; c.hy = d->hy; c.hz = d->hz;
@@ -313,11 +317,23 @@ __device__ inline void advance_cursor(const Cst& C, uint64_t& view, uint64_t& hi
     }
 }
 
+// floor(d / a) for d < 1024 a (t - c within one run, and a run lies in one
+// grid row): a float estimate, within one of the quotient (its relative error
+// is a few 2^-24 and the quotient is below 1024), then one integer
+// correction.
+__device__ __forceinline__ uint32_t div_in_run(uint64_t d, uint32_t a) {
+    uint32_t q = (uint32_t)((float)d * rcpf((float)a));
+    const uint64_t p = (uint64_t)q * a;
+    if (p > d) --q;
+    else if (p + a <= d) ++q;
+    return q;
+}
+
 // Emission of history (view, hist): Philox event 0, sub-draws 0 and 1.
 // Sub-draw 0: words 0-1 pick the voxel by inverse CDF, words 2-3 the x and y
 // offsets in it; sub-draw 1: word 0 the z offset, word 1 cos(theta), word 2
 // the azimuth.  Runs with the wavefront converged (no per-lane branches
-// except the CDF search of a bucket that spans three or more voxels).
+// except the search of a bucket that meets several runs).
 struct Emission {
     float x, y, z, dx, dy, dz;
     uint32_t voxel;
@@ -332,24 +348,25 @@ __device__ inline Emission emit_history(const Cst& C, uint32_t hist, uint32_t vi
     philox10(a0, a1, a2, a3, C.seed, C.pid);
     uint32_t b0 = hist, b1 = view, b2 = 0, b3 = 1;
     philox10(b0, b1, b2, b3, C.seed, C.pid);
-    // voxel: t = floor(R * total / 2^64) with R the 64-bit word pair
+    // voxel: t = floor(R * total / 2^64) with R the 64-bit word pair; the run
+    // holding t (its bucket, rarely a search over the runs the bucket
+    // meets), then the voxel within the run
     const uint64_t R = ((uint64_t)a0 << 32) | a1;
     const uint64_t t = __umul64hi(R, C.total);
-    const uint64_t b = t >> C.shift;
-    const uint4 g = ldg(C.guide + b);
-    uint32_t packed;                        // ix | iy << 10 | iz << 20
-    if (g.x & BUCKET_WIDE) {
-        // the bucket spans three or more voxels: search its CDF slots
-        uint32_t lo = g.y, hi = g.z;
+    const uint2 g = ldg(C.guide + (t >> C.shift));
+    uint32_t r = g.x;
+    if (g.y != 0) {
+        // the last run starting at or below t among runs g.x .. g.x + g.y
+        uint32_t lo = g.x, hi = g.x + g.y;
         while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (ldg(C.cdf + mid) > t) hi = mid; else lo = mid + 1;
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            const uint2 c = ldg((const uint2*)(C.runs + mid));
+            if ((((uint64_t)c.y << 32) | c.x) <= t) lo = mid; else hi = mid - 1;
         }
-        packed = ldg(C.vox_id + lo);
-    } else {
-        const uint64_t split = ((uint64_t)g.w << 32) | g.z;
-        packed = (t - (b << C.shift)) < split ? g.x : g.y;
+        r = lo;
     }
+    const uint4 run = ldg(C.runs + r);
+    const uint32_t packed = run.z + div_in_run(t - (((uint64_t)run.y << 32) | run.x), run.w);
     const uint32_t ix = packed & 1023u, iy = (packed >> 10) & 1023u, iz = packed >> 20;
     Emission e;
     e.voxel = ix + (uint32_t)C.nx * (iy + (uint32_t)C.ny * iz);

@@ -38,11 +38,10 @@ struct ProbDesc {
     uint32_t* q32;                  // accept thresholds (linear or bricked layout)
     uint8_t* q8;                    // palette codes, same layout (when pal_state == 0)
     uint32_t* palette;              // PALETTE_N thresholds, open-addressing hash table
-    uint64_t* cdf;                  // inclusive prefix sum of activity over active voxels
-    uint32_t* vox_id;               // voxel index of each active voxel, in grid order
+    uint4* runs;                    // emission runs (EmitRun layout), n_runs entries
     uint64_t* block_sums;           // scan scratch: activity per block
-    uint32_t* block_cnt;            // scan scratch: active voxels per block
-    uint4* guide;                   // emission buckets (EmitBucket layout), n_buckets entries
+    uint32_t* block_cnt;            // scan scratch: runs starting in each block
+    uint2* guide;                   // emission buckets (EmitBucket layout), n_buckets entries
     float2* views;                  // (cos, sin) per view
     float* kn_table;                // sigma_KN(e0 - i/4 keV) / sigma_KN(140), i < KN_TABLE_N
     // filled on the device by staging
@@ -51,7 +50,7 @@ struct ProbDesc {
     uint64_t total;                 // sum of activity
     uint32_t shift;                 // bucket = t >> shift
     uint32_t n_buckets;
-    uint32_t n_active;              // voxels with activity > 0
+    uint32_t n_runs;                // emission runs
     uint32_t pal_state;             // 0: palette in use; 1: 32-bit thresholds (host request
                                     // or more than PALETTE_N distinct values, set by staging)
     float omc_alpha;                // 1 - cos(alpha), from double precision (forced detection)
@@ -96,13 +95,15 @@ __host__ __device__ inline int cfd_half_width(double depth, double tan_a, double
     return (int)ceil(depth * tan_a / pix + 0.5);
 }
 
-// Emission bucket b covers t in [b << shift, (b + 1) << shift) of the integer
-// activity CDF.  Bucket layout, as a uint4 (x, y, z, w):
-//   narrow (x bit 31 clear): t falls in at most two active voxels; x and y are
-//     their packed coordinates, (w:z) the offset of t from the bucket start
-//     below which x is taken (all ones when both are the same voxel);
-//   wide (x = BUCKET_WIDE): the slots of the CDF search are [y, z].
-constexpr uint32_t BUCKET_WIDE = 0x80000000u;
+// Emission tables.  A run is a maximal stretch of consecutive voxels of one
+// grid row (x fastest) with the same nonzero source weight a; EmitRun, as a
+// uint4 (x, y, z, w): (y:x) the cumulative weight of all voxels before the
+// run (c), z the run's first voxel as packed coordinates ix | iy << 10 |
+// iz << 20, w its weight a.  The voxel of t in [c, c + a len) is the run's
+// j-th, j = floor((t - c) / a), exactly the voxel a plain inverse-CDF search
+// over all voxels finds.  EmitBucket b covers t in [b << shift, (b + 1) <<
+// shift); as a uint2: x the run holding the bucket's first t, y how many
+// further runs it meets (0: none, the run is known without a search).
 
 // Threshold palette: a 256-slot open-addressing table keyed by Q (Q <= 2^24,
 // so the all-ones word marks an empty slot); a voxel's code is its slot.
@@ -149,10 +150,11 @@ hipError_t launch_cfd_convolve(const ProbDesc* d, const ProbDesc& h, int64_t* ta
 
 // Host launchers (staging.hip)
 hipError_t launch_staging(ProbDesc* d_desc, const ProbDesc& h_desc, hipStream_t s);
-// emission buckets reserved: the power of two >= 2 nvox
+// emission buckets reserved: the power of two >= nvox (the staging uses the
+// power of two >= 2 x the number of runs, up to this)
 __host__ __device__ inline uint64_t guide_capacity(uint64_t nvox) {
-    uint64_t c = 1;
-    while (c < 2 * nvox) c <<= 1;
+    uint64_t c = 2;
+    while (c < nvox) c <<= 1;
     return c;
 }
 hipError_t launch_staging_batch(ProbDesc* d_descs, const ProbDesc* h_descs, int n, hipStream_t s);

@@ -8,13 +8,14 @@
 //    when the map has at most 256 distinct thresholds (segmented phantoms have
 //    a handful) also one-byte codes into a palette of them, a table a quarter
 //    the size that stays in L2;
-//  * the inclusive prefix sum of activity (uint64) over the active voxels only,
-//    their voxel indices, and a table of buckets over the high bits of the sum
-//    with about two buckets per active voxel (after the guide tables of Chen &
-//    Asau 1974); a bucket that meets at most two voxels holds their packed
-//    coordinates and split point, so an emission voxel is one 16-byte gather,
-//    rarely a short CDF search (the same voxel as a plain inverse-CDF search
-//    over all voxels);
+//  * the runs of the activity map (maximal stretches of a grid row with one
+//    weight), each with the cumulative activity before it (uint64), and a
+//    table of buckets over the high bits of that sum with about two buckets
+//    per run (after the guide tables of Chen & Asau 1974): an emission voxel
+//    is one 8-byte bucket gather, one 16-byte run gather and a division
+//    within the run, rarely a short search over runs -- the same voxel as a
+//    plain inverse-CDF search over all voxels.  A segmented phantom has ~1e4
+//    runs, so both tables stay in L2;
 //  * (cos, sin) of each view angle;
 //  * the Klein-Nishina attenuation shape sigma_KN(E)/sigma_KN(140) at 1/4 keV
 //    steps, evaluated in double precision.
@@ -365,8 +366,15 @@ __global__ __launch_bounds__(RED_THREADS) void k_codes(ProbDesc* descs) {
     }
 }
 
-// --- three-pass scan of the activity map: uint64 inclusive sums and the
-// positions of active voxels, so the CDF is stored over active voxels only ---
+// --- three-pass scan of the activity map: uint64 sums of the source weight
+// and the runs of equal weight, so the emission tables hold one entry per run
+// (a segmented phantom has ~1e4 runs against ~1e6 active voxels) ---
+
+// Voxel i starts a run: it is active and its row neighbour on the left (none
+// at ix = 0) has a different weight.
+__device__ inline bool run_start(uint32_t a, uint32_t a_left, uint64_t i, uint32_t nx) {
+    return a > 0 && (i % nx == 0 || a_left != a);
+}
 
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(ProbDesc* descs) {
     ProbDesc* pd = descs + blockIdx.y;
@@ -374,6 +382,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(ProbDesc* descs) {
     if ((uint64_t)blockIdx.x * SCAN_ITEMS >= nvox) return;   // past this problem's blocks
     const uint32_t* __restrict__ act = pd->act;
     const uint32_t* __restrict__ prev = pd->act_prev;
+    const uint32_t nx = (uint32_t)pd->nx;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_ITEMS;
     uint64_t s = 0;
     uint32_t c = 0;
@@ -381,8 +390,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(ProbDesc* descs) {
         const uint64_t i = base + j;
         if (i < nvox) {
             const uint32_t a = source_weight(act, prev, i);
+            const uint32_t l = i > 0 ? source_weight(act, prev, i - 1) : 0u;
             s += a;
-            c += a > 0;
+            c += run_start(a, l, i, nx);
         }
     }
     s = wave_sum_u64(s);
@@ -400,8 +410,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_sums(ProbDesc* descs) {
     }
 }
 
-// Exclusive scan of the block sums and counts, one block of 1024 threads,
-// each thread a contiguous run; also records the number of active voxels.
+// Exclusive scan of the block sums and run counts, one block of 1024
+// threads, each thread a contiguous stretch; also records the number of runs.
 __global__ __launch_bounds__(1024) void k_scan_top(ProbDesc* descs) {
     ProbDesc* pd = descs + blockIdx.y;
     const int n_blocks = (int)((pd->nvox + SCAN_ITEMS - 1) / SCAN_ITEMS);
@@ -425,8 +435,8 @@ __global__ __launch_bounds__(1024) void k_scan_top(ProbDesc* descs) {
         totc[threadIdx.x] += vc;
         __syncthreads();
     }
-    if (threadIdx.x == 1023) pd->n_active = totc[1023];
-    uint64_t run = tot[threadIdx.x] - s;   // exclusive prefix of this thread's run
+    if (threadIdx.x == 1023) pd->n_runs = totc[1023];
+    uint64_t run = tot[threadIdx.x] - s;   // exclusive prefix of this thread's stretch
     uint32_t runc = totc[threadIdx.x] - c;
     for (int j = 0; j < per; ++j) {
         if (b0 + j < n_blocks) {
@@ -441,8 +451,9 @@ __global__ __launch_bounds__(1024) void k_scan_top(ProbDesc* descs) {
 }
 
 // Per block: 16 consecutive voxels per thread, thread-local scans, block
-// exclusive scans of the thread totals, plus the block offsets; each active
-// voxel writes its cumulative activity and its index at its compacted slot.
+// exclusive scans of the thread totals, plus the block offsets; each voxel
+// that starts a run writes the run (cumulative weight before it, its packed
+// coordinates, its weight) at its compacted slot.
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ProbDesc* descs) {
     ProbDesc* pd = descs + blockIdx.y;
     constexpr int PER = SCAN_ITEMS / SCAN_THREADS;
@@ -450,11 +461,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ProbDesc* descs) {
     if ((uint64_t)blockIdx.x * SCAN_ITEMS >= nvox) return;   // past this problem's blocks
     const uint32_t* __restrict__ act = pd->act;
     const uint32_t* __restrict__ prev = pd->act_prev;
-    uint64_t* __restrict__ cdf = pd->cdf;
-    uint32_t* __restrict__ vid = pd->vox_id;
+    uint4* __restrict__ runs = pd->runs;
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_ITEMS + (uint64_t)threadIdx.x * PER;
     const uint32_t nx = (uint32_t)pd->nx, ny = (uint32_t)pd->ny;
     uint32_t a[PER];
+    const uint32_t left0 = (base > 0 && base < nvox) ? source_weight(act, prev, base - 1) : 0u;
     uint64_t s = 0;
     uint32_t c = 0;
 #pragma unroll
@@ -462,8 +473,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ProbDesc* descs) {
         const uint64_t i = base + j;
         a[j] = (i < nvox) ? source_weight(act, prev, i) : 0u;
         s += a[j];
-        c += a[j] > 0;
     }
+    uint32_t starts = 0;        // bit j: voxel base + j starts a run
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const uint32_t l = j > 0 ? a[j - 1] : left0;
+        if (base + j < nvox && run_start(a[j], l, base + j, nx)) starts |= 1u << j;
+    }
+    c = __popc(starts);
     __shared__ uint64_t tot[SCAN_THREADS];
     __shared__ uint32_t totc[SCAN_THREADS];
     tot[threadIdx.x] = s;
@@ -477,30 +494,37 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_final(ProbDesc* descs) {
         totc[threadIdx.x] += tc;
         __syncthreads();
     }
-    uint64_t run = pd->block_sums[blockIdx.x] + tot[threadIdx.x] - s;
+    uint64_t before = pd->block_sums[blockIdx.x] + tot[threadIdx.x] - s;   // weight before voxel base
     uint32_t k = pd->block_cnt[blockIdx.x] + totc[threadIdx.x] - c;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        if (a[j] > 0) {
-            run += a[j];
-            cdf[k] = run;
+        if (starts & (1u << j)) {
             const uint32_t i = (uint32_t)(base + j);
             const uint32_t ix = i % nx, iy = (i / nx) % ny, iz = i / (nx * ny);
-            vid[k] = ix | (iy << 10) | (iz << 20);   // packed 10 bits per axis
+            runs[k] = make_uint4((uint32_t)before, (uint32_t)(before >> 32),
+                                 ix | (iy << 10) | (iz << 20), a[j]);   // packed 10 bits per axis
             ++k;
         }
+        before += a[j];
     }
 }
 
-// Guide table over the compacted CDF: bucket b covers t in [b 2^s, (b+1) 2^s),
-// with about two buckets per active voxel; guide[b] is the first active slot
-// whose cumulative activity exceeds b 2^s and guide[B] the last slot, so the
-// answer for any t in bucket b lies in [guide[b], guide[b+1]].
-__device__ inline uint64_t first_above(const uint64_t* __restrict__ cdf, uint64_t K, uint64_t key) {
-    uint64_t lo = 0, hi = K - 1;   // first slot with cdf > key; cdf[K-1] = total > key
+// Bucket table over the runs: bucket b covers t in [b 2^s, (b+1) 2^s), with
+// about two buckets per run (after the guide tables of Chen & Asau 1974).
+// Run r holds t in [c_r, c_{r+1}); the bucket's entry is the run holding its
+// first t and the number of further runs starting inside it.
+__device__ inline uint64_t run_c(const uint4* __restrict__ runs, uint64_t r) {
+    const uint4 v = runs[r];
+    return ((uint64_t)v.y << 32) | v.x;
+}
+
+// First run whose start is above key (R when none): the run holding key is
+// the one before it (run 0 starts at 0 <= key).
+__device__ inline uint64_t first_run_above(const uint4* __restrict__ runs, uint64_t R, uint64_t key) {
+    uint64_t lo = 0, hi = R;
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
-        if (cdf[mid] > key) hi = mid; else lo = mid + 1;
+        if (run_c(runs, mid) > key) hi = mid; else lo = mid + 1;
     }
     return lo;
 }
@@ -509,13 +533,13 @@ __global__ __launch_bounds__(RED_THREADS) void k_guide(ProbDesc* descs) {
     ProbDesc* pd = descs + blockIdx.y;
     const uint64_t nb_cap = guide_capacity(pd->nvox);
     const uint64_t total = pd->total;
-    const uint64_t K = pd->n_active;
-    if (total == 0 || K == 0) {
+    const uint64_t R = pd->n_runs;
+    if (total == 0 || R == 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&pd->flags, (uint32_t)MC_STATUS_NO_ACTIVITY);
         return;
     }
     uint64_t cap = 1;
-    while (cap < 2 * K) cap <<= 1;
+    while (cap < 2 * R) cap <<= 1;
     if (cap > nb_cap) cap = nb_cap;
     uint32_t s = 0;
     while (((total - 1) >> s) >= cap) ++s;
@@ -524,41 +548,33 @@ __global__ __launch_bounds__(RED_THREADS) void k_guide(ProbDesc* descs) {
         pd->shift = s;
         pd->n_buckets = (uint32_t)B;
     }
-    const uint64_t* __restrict__ cdf = pd->cdf;
-    const uint32_t* __restrict__ vid = pd->vox_id;
-    uint4* __restrict__ guide = pd->guide;
-    // bucket b spans slots [lo(b), hi(b)], lo(b) = first_above(b 2^s) and
-    // hi(b) = first_above((b + 1) 2^s - 1), which is lo(b + 1), or one less
-    // when a slot's cumulative sum is exactly (b + 1) 2^s (the sums strictly
-    // increase).  A wavefront finds lo for 64 consecutive buckets, one search
-    // per lane, and completes 63 of them with its neighbour's lo.
+    const uint4* __restrict__ runs = pd->runs;
+    uint2* __restrict__ guide = pd->guide;
+    // bucket b's first t lies in run lo(b) = first_run_above(b 2^s) - 1 and
+    // its last t = (b + 1) 2^s - 1 in run hi(b) = (first run starting at or
+    // above (b + 1) 2^s) - 1, which is lo(b + 1), or one less when a run
+    // starts exactly at (b + 1) 2^s.  A wavefront finds lo for 64
+    // consecutive buckets, one search per lane, and completes 63 of them with
+    // its neighbour's.
     const int lane = threadIdx.x & 63;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     for (uint64_t grp = wave; grp * 63 < B; grp += n_waves) {
         const uint64_t b = grp * 63 + (uint64_t)lane;
-        const uint64_t lo = b < B ? first_above(cdf, K, b << s) : K;
-        const uint32_t nl = (uint32_t)__shfl_down((int)(uint32_t)lo, 1, 64);
-        const uint32_t nh = (uint32_t)__shfl_down((int)(uint32_t)(lo >> 32), 1, 64);
+        const uint64_t fa = b < B ? first_run_above(runs, R, b << s) : R;   // >= 1
+        const uint32_t nl = (uint32_t)__shfl_down((int)(uint32_t)fa, 1, 64);
+        const uint32_t nh = (uint32_t)__shfl_down((int)(uint32_t)(fa >> 32), 1, 64);
         if (lane == 63 || b >= B) continue;
+        const uint64_t lo = fa - 1;
         uint64_t hi;
         if (b + 1 < B) {
-            hi = (uint64_t)nl | ((uint64_t)nh << 32);
-            if (hi > 0 && cdf[hi - 1] == ((b + 1) << s)) --hi;
+            const uint64_t fa1 = (uint64_t)nl | ((uint64_t)nh << 32);
+            hi = fa1 - 1;
+            if (run_c(runs, hi) == ((b + 1) << s)) --hi;
         } else {
-            hi = K - 1;                       // the last bucket ends at total - 1
+            hi = R - 1;                        // the last bucket ends at total - 1
         }
-        const uint64_t lo_t = b << s;
-        uint4 g;
-        if (hi == lo) {
-            g.x = vid[lo]; g.y = g.x; g.z = 0xFFFFFFFFu; g.w = 0xFFFFFFFFu;
-        } else if (hi == lo + 1) {
-            const uint64_t split = cdf[lo] - lo_t;   // t < cdf[lo] takes slot lo
-            g.x = vid[lo]; g.y = vid[hi]; g.z = (uint32_t)split; g.w = (uint32_t)(split >> 32);
-        } else {
-            g.x = BUCKET_WIDE; g.y = (uint32_t)lo; g.z = (uint32_t)hi; g.w = 0;
-        }
-        guide[b] = g;
+        guide[b] = make_uint2((uint32_t)lo, (uint32_t)(hi - lo));
     }
 }
 

@@ -68,44 +68,74 @@ def test_headline_thorax_128_full_parity():
     say(f"headline per-result errors: {err}")
 
 
-def _bucket_kinds(act):
-    """Spans of the emission buckets the library cuts the activity CDF into
-    (cap = power of two >= 2 x active voxels, width 2^s): how many active
-    voxels each bucket's range of t meets, weighted by the t it covers."""
-    w = act.ravel().astype(np.uint64)
-    w = w[w > 0]
-    cdf = np.cumsum(w, dtype=np.uint64)
-    total, K = int(cdf[-1]), len(w)
-    cap = 1 << int(np.ceil(np.log2(2 * K)))
+def _emission_table_kinds(act):
+    """How the library's emission tables cover the activity CDF: runs are
+    maximal stretches of a grid row with one weight; buckets (a power of two
+    >= 2 x runs, width 2^s) hold the run of their first t and how many more
+    they meet.  Returns the fraction of the activity mass in buckets meeting
+    1, 2 and >= 3 runs, and in runs longer than one voxel with weight > 1
+    (where the voxel is a division within the run)."""
+    nz, ny, nx = act.shape
+    w = act.reshape(-1).astype(np.uint64)
+    ix = np.tile(np.arange(nx), ny * nz)
+    left = np.concatenate([[0], w[:-1]])
+    start = (w > 0) & ((ix == 0) | (left != w))
+    idx = np.flatnonzero(start)
+    csum = np.concatenate([[0], np.cumsum(w, dtype=np.uint64)])
+    c = csum[idx]                                   # weight before each run
+    total, R = int(csum[-1]), len(idx)
+    run_end = np.concatenate([c[1:], [total]])
+    cap = 1 << int(np.ceil(np.log2(2 * R)))
     s = 0
     while ((total - 1) >> s) >= cap:
         s += 1
     starts = np.arange(0, total, 1 << s, dtype=np.uint64)
     ends = np.minimum(starts + np.uint64((1 << s) - 1), np.uint64(total - 1))
-    lo = np.searchsorted(cdf, starts, side="right")
-    hi = np.searchsorted(cdf, ends, side="right")
+    lo = np.searchsorted(c, starts, side="right") - 1
+    hi = np.searchsorted(c, ends, side="right") - 1
     span = hi - lo + 1
     mass = (ends - starts + np.uint64(1)).astype(np.float64) / total
-    return {k: float(mass[(span == k) if k < 3 else (span >= 3)].sum()) for k in (1, 2, 3)}
+    out = {k: float(mass[(span == k) if k < 3 else (span >= 3)].sum()) for k in (1, 2, 3)}
+    length = (run_end - c) // w[idx]
+    div = (length > 1) & (w[idx] > 1)
+    out["division"] = float(((run_end - c)[div]).astype(np.float64).sum() / total)
+    out["runs"] = R
+    return out
 
 
-def test_emission_buckets_skewed_activity():
+def test_emission_tables_skewed_activity():
     """Activity over nine decades (one hot voxel, a warm block, a faint body)
-    gives emission buckets of every kind: inside one voxel, split between two,
-    and wide ones searched over the CDF.  The emitted voxel is integer
-    arithmetic on both sides and must be identical for every history."""
+    gives emission buckets inside one run and buckets meeting many runs (a
+    search: the faint body's runs share the few buckets its small mass
+    spans), and runs of several voxels with weights above one (a division
+    within the run).  The emitted voxel is integer arithmetic
+    on both sides and must be identical for every history."""
     p = phantoms.thorax_problem("skewed_act", 40, 0.96, 3, 6, 180.0, 32, 1.2, 300_000)
     act = p.activity.copy()
     act[20, 20, 20] = 3_000_000_000
     act[10:14, 24:30, 15:19] = np.where(act[10:14, 24:30, 15:19] > 0, 2_000_000, 0)
     act[30, 5:9, :] = 7
     p = p.with_(activity=act)
-    kinds = _bucket_kinds(act)
-    say(f"bucket mass by span: {kinds}")
-    assert kinds[1] > 0.5 and kinds[2] > 1e-4 and kinds[3] > 1e-3
+    kinds = _emission_table_kinds(act)
+    say(f"emission table mass by runs met per bucket: {kinds}")
+    assert kinds[1] > 0.5 and kinds[3] > 1e-4 and kinds["division"] > 1e-3
     g, o = replay_parity(p, n=60_000, seed=11)
     v = g["emit_voxel"]
     assert np.any(v == 20 + 40 * (20 + 40 * 20)) and len(np.unique(v)) >= 90   # hot, warm block, faint body
+
+
+def test_emission_random_weights_every_voxel_a_run():
+    """Random weights 0-5 in every voxel: almost every active voxel is a run
+    of its own, so the tables are as large as the grid allows and buckets meet
+    one or two runs; every emitted voxel identical to the oracle's."""
+    n = 48
+    rng = np.random.Generator(np.random.PCG64(19))
+    p = phantoms.thorax_problem("rand_act", n, 0.8, 3, 5, 180.0, 32, 1.2, 200_000)
+    p = p.with_(activity=rng.integers(0, 6, size=(n, n, n)).astype(np.uint32))
+    kinds = _emission_table_kinds(p.activity)
+    say(f"random weights: {kinds}")
+    assert kinds["runs"] > 0.7 * np.count_nonzero(p.activity) and kinds[2] > 0.1
+    replay_parity(p, n=50_000, seed=12)
 
 
 def test_thorax_odd_non_cubic_grid():

@@ -251,6 +251,25 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems,
                             int64_t* status,
                             void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and arguments as mc_simulate_projections, without a workspace.
+ * The scratch comes from one array of MC_STATIC_SCRATCH_BYTES (64 MiB) per
+ * device, placed in device memory when the library's code is loaded and held
+ * until the process ends; the call allocates nothing.  Problems whose
+ * mc_workspace_bytes exceed it are refused with MC_ENOMEM (a 128^3 grid
+ * fits).  Every call on a device shares that device's array: calls that
+ * overlap on one device (different streams, threads) race and must be
+ * serialised by the caller.  The outputs are the caller's, as for
+ * mc_simulate_projections, and are bit-identical to its. */
+#define MC_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int mc_simulate_projections_static(const mc_problem* problems, int32_t n_problems,
+                                   const mc_options* opt,
+                                   int64_t* tally, int64_t* tally_sq, int64_t* fates,
+                                   int64_t* energy, int64_t* counters,
+                                   mc_event* events, uint64_t event_capacity, uint64_t* n_events,
+                                   int64_t* status, void* stream);
+
 /* Re-run the listed histories of problem 0 one per lane and write one record
  * each (the replay contract: a history is a function of its Philox counter).
  *   views, hists   device [n]: view and history id of each history

@@ -36,7 +36,8 @@ Q23 = float(2 ** 23)   # energy fixed point: Q40.23 keV
 Q52 = float(2 ** 52)   # forced-detection sum of squared scores: Q11.52
 
 # Exported symbols, as declared in include/mcspect.h.
-EXPORTS = ["mc_workspace_bytes", "mc_simulate_projections", "mc_replay_histories",
+EXPORTS = ["mc_workspace_bytes", "mc_simulate_projections", "mc_simulate_projections_static",
+           "mc_replay_histories",
            "mc_adjoint_mu", "mc_system_matrix_workspace_bytes", "mc_system_matrix",
            "mlem_workspace_bytes", "mlem_iterate", "osem_workspace_bytes", "osem_iterate",
            "mc_block_activity", "mc_expand_projection",
@@ -84,6 +85,10 @@ _lib.mc_workspace_bytes.restype = _sz
 _lib.mc_simulate_projections.argtypes = [C.POINTER(McProblem), _i32, C.POINTER(McOptions),
                                          _vp, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp, _sz, _vp]
 _lib.mc_simulate_projections.restype = C.c_int
+_lib.mc_simulate_projections_static.argtypes = [C.POINTER(McProblem), _i32, C.POINTER(McOptions),
+                                                _vp, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp]
+_lib.mc_simulate_projections_static.restype = C.c_int
+STATIC_SCRATCH_BYTES = 64 * 1024 * 1024   # MC_STATIC_SCRATCH_BYTES
 _lib.mc_replay_histories.argtypes = [C.POINTER(McProblem), C.POINTER(McOptions), _vp, _vp, _i64,
                                      _vp, _vp, _vp, _sz, _vp]
 _lib.mc_replay_histories.restype = C.c_int
@@ -320,6 +325,19 @@ class Simulator:
             self.n_events.data_ptr(), self.status.data_ptr(), self.workspace.data_ptr(),
             self.workspace.numel(), _stream_ptr())
         _check(rc, "mc_simulate_projections")
+
+    def run_static(self):
+        """The same call through mc_simulate_projections_static: the library's
+        per-device scratch array instead of this Simulator's workspace (for
+        callers that cannot allocate; calls overlapping on one device race)."""
+        opts = self.options
+        rc = _lib.mc_simulate_projections_static(
+            self._arr, len(self.problems), C.byref(opts) if opts else None,
+            self.tally.data_ptr(), self.tally_sq.data_ptr() if self.tally_sq is not None else None,
+            self.fates.data_ptr(), self.energy.data_ptr(), self.counters.data_ptr(),
+            self.events.data_ptr() if self.events is not None else None, self.event_capacity,
+            self.n_events.data_ptr(), self.status.data_ptr(), _stream_ptr())
+        _check(rc, "mc_simulate_projections_static")
 
     def check_status(self):
         st = self.status.cpu().numpy()

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "mc_internal.h"
@@ -241,11 +242,15 @@ size_t mc_workspace_bytes(const mc_problem* problems, int32_t n_problems, const 
     return L.total;
 }
 
-int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, const mc_options* opt,
-                            int64_t* tally, int64_t* tally_sq, int64_t* fates, int64_t* energy,
-                            int64_t* counters, mc_event* events, uint64_t event_capacity,
-                            uint64_t* n_events, int64_t* status, void* workspace,
-                            size_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+int simulate_impl(const mc_problem* problems, int32_t n_problems, const mc_options* opt,
+                  int64_t* tally, int64_t* tally_sq, int64_t* fates, int64_t* energy,
+                  int64_t* counters, mc_event* events, uint64_t event_capacity,
+                  uint64_t* n_events, int64_t* status, void* workspace,
+                  size_t workspace_bytes, void* stream) {
     if (!problems || n_problems < 1 || !tally || !fates || !status || !workspace) return MC_EINVAL;
     if (opt && (opt->forced_detection < 0 || opt->forced_detection > 2)) return MC_EINVAL;
     if (!vr_ok(opt)) return MC_EINVAL;
@@ -329,6 +334,64 @@ int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, cons
     for (int i = 0; cfd && i < (int)hd.size(); ++i)
         if ((e = launch_cfd_convolve(d_desc + i, hd[i], tally, st)) != hipSuccess) return hip_fail(e);
     return MC_OK;
+}
+
+// Scratch of the no-allocation entry point: one array per device, placed by
+// the code-object loader, shared by every call on that device.  Its host-side
+// name is not a device address: host code uses only the address that
+// hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) unsigned char scratch[MC_STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array (looked up once per
+// device, with that device current).  Returns MC_OK or an error code.
+int scratch_of_current_device(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if (dev < 0 || dev >= MAX_DEVICES) return MC_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e);
+        if (!p) return MC_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mc_simulate_projections(const mc_problem* problems, int32_t n_problems, const mc_options* opt,
+                            int64_t* tally, int64_t* tally_sq, int64_t* fates, int64_t* energy,
+                            int64_t* counters, mc_event* events, uint64_t event_capacity,
+                            uint64_t* n_events, int64_t* status, void* workspace,
+                            size_t workspace_bytes, void* stream) {
+    return simulate_impl(problems, n_problems, opt, tally, tally_sq, fates, energy, counters, events,
+                         event_capacity, n_events, status, workspace, workspace_bytes, stream);
+}
+
+int mc_simulate_projections_static(const mc_problem* problems, int32_t n_problems,
+                                   const mc_options* opt, int64_t* tally, int64_t* tally_sq,
+                                   int64_t* fates, int64_t* energy, int64_t* counters,
+                                   mc_event* events, uint64_t event_capacity, uint64_t* n_events,
+                                   int64_t* status, void* stream) {
+    if (!problems || n_problems < 1) return MC_EINVAL;
+    const size_t need = mc_workspace_bytes(problems, n_problems, opt);
+    if (need == 0) return MC_EINVAL;
+    if (need > (size_t)MC_STATIC_SCRATCH_BYTES) return MC_ENOMEM;
+    void* ws = nullptr;
+    const int rc = scratch_of_current_device(&ws);
+    if (rc != MC_OK) return rc;
+    return simulate_impl(problems, n_problems, opt, tally, tally_sq, fates, energy, counters, events,
+                         event_capacity, n_events, status, ws, (size_t)MC_STATIC_SCRATCH_BYTES, stream);
 }
 
 int mc_replay_histories(const mc_problem* problem, const mc_options* opt, const int32_t* views,

@@ -163,7 +163,13 @@ def main():
         print(json.dumps({"copy_bytes": 1 << 30}))
         return
     if args.issue_probe:
-        print(json.dumps(issue_rates(torch)))
+        rec = issue_rates(torch)
+        # the same probes at 1-4 waves per SIMD: how much of each class's rate
+        # survives without the latency hiding of eight resident waves
+        n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+        rec["by_waves_per_simd"] = {w: issue_rates(torch, blocks=n_cu * w)["probe_ms"]
+                                    for w in (1, 2, 3, 4)}
+        print(json.dumps(rec))
         return
     import phantoms
     import paper_2105_13324_amd as mc

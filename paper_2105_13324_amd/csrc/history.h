@@ -73,6 +73,7 @@ __device__ __forceinline__ float2 ldg(const float2* p) {
 
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrtf_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float rsqf_hw(float x) { return __builtin_amdgcn_rsqf(x); }
 // sin(2 pi u), cos(2 pi u): the hardware instructions take revolutions.
 __device__ __forceinline__ float sin_rev(float u) { return __builtin_amdgcn_sinf(u); }
 __device__ __forceinline__ float cos_rev(float u) { return __builtin_amdgcn_cosf(u); }
@@ -98,6 +99,7 @@ struct Cst {
     int nu, nv, n_views;
     float inv_pix, radius, cos_alpha, wu, wv, e_lo, e_hi, e_cut;
     float f_pe, mu_hat, ln2_mm0, p_pe0, e0, g0;   // attenuation terms at the line e0
+    float ln2_mu;                                 // ln 2 / max mu
     uint32_t seed, pid, max_steps, shift;
     uint64_t total, q_per_view, r_extra, work_begin, tally_offset;
     uint32_t flags, use_pal;
@@ -125,7 +127,7 @@ __device__ inline float energy_terms(const Cst& C, float e, float& ln2_mm, float
     const float pe = C.f_pe * x * x * x;
     const float g = fmaf(1.0f - C.f_pe, kn, pe);
     const float ig = rcpf(g);
-    ln2_mm = LN2_F * rcpf(C.mu_hat * g);
+    ln2_mm = C.ln2_mu * ig;
     p_pe = pe * ig;
     return g;
 }
@@ -154,11 +156,12 @@ __device__ inline Cst load_cst(const ProbDesc* __restrict__ d) {
     c.wu = d->wu; c.wv = d->wv; c.e_lo = d->e_lo; c.e_hi = d->e_hi; c.e_cut = d->e_cut;
     c.f_pe = d->f_pe;
     c.mu_hat = __uint_as_float(d->mu_hat_bits);
+    c.ln2_mu = (float)(0.69314718055994531 / (double)c.mu_hat);
     c.e0 = d->e0;
     if (c.e0 == 140.0f) {
         // g(140 keV) = 1 by construction: mu_max(140) = max mu, p_pe(140) = f.
         c.g0 = 1.0f;
-        c.ln2_mm0 = (float)(0.69314718055994531 / (double)c.mu_hat);
+        c.ln2_mm0 = c.ln2_mu;
         c.p_pe0 = c.f_pe;
     } else {
         c.g0 = energy_terms(c, c.e0, c.ln2_mm0, c.p_pe0);
@@ -253,12 +256,12 @@ __device__ inline void rotate_dir(float& u, float& v, float& w, float ct, float 
         v = st * sp;
         w = w0 > 0.0f ? ct : -ct;
     } else {
-        const float t = sqrtf_hw((1.0f - w0) * (1.0f + w0));
-        const float it = rcpf(t);
+        const float t2 = (1.0f - w0) * (1.0f + w0);
+        const float it = rsqf_hw(t2);
         const float a = st * it;
         u = fmaf(a, u0 * w0 * cp - v0 * sp, u0 * ct);
         v = fmaf(a, v0 * w0 * cp + u0 * sp, v0 * ct);
-        w = fmaf(-st * cp, t, w0 * ct);
+        w = fmaf(-st * cp, t2 * it, w0 * ct);
     }
 }
 
@@ -271,12 +274,12 @@ __device__ inline void rotate(Lane& L, float ct, float phi_u) {
         L.dy = st * sp;
         L.dz = w > 0.0f ? ct : -ct;
     } else {
-        const float t = sqrtf_hw((1.0f - w) * (1.0f + w));
-        const float it = rcpf(t);
+        const float t2 = (1.0f - w) * (1.0f + w);
+        const float it = rsqf_hw(t2);
         const float a = st * it;
         L.dx = fmaf(a, u * w * cp - v * sp, u * ct);
         L.dy = fmaf(a, v * w * cp + u * sp, v * ct);
-        L.dz = fmaf(-st * cp, t, w * ct);
+        L.dz = fmaf(-st * cp, t2 * it, w * ct);
     }
 }
 
@@ -430,14 +433,16 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
         const float tx = xn + C.hx, ty = yn + C.hy, tz = zn + C.hz;
         const bool inside = (tx >= 0.0f) & (tx < C.lx) & (ty >= 0.0f) & (ty < C.ly) &
                             (tz >= 0.0f) & (tz < C.lz);
-        if (!inside) return escape(C, L, iu, iv);
         const int ix = min((int)(tx * C.inv_vox), C.nx - 1);
         const int iy = min((int)(ty * C.inv_vox), C.ny - 1);
         const int iz = min((int)(tz * C.inv_vox), C.nz - 1);
-        if (C.box_margin && leaves_box(C, ix, iy, iz, L.dx, L.dy, L.dz)) {
-            // in the air outside the attenuation box, moving away from it:
-            // every later collision would be virtual, so escape now along this ray
-            L.x = xn; L.y = yn; L.z = zn;
+        // in the air outside the attenuation box, moving away from it, every
+        // later collision would be virtual: the photon escapes along this ray
+        // from the new point (one escape path for both ways out, so the
+        // wavefront runs it once when lanes leave both ways)
+        const bool box_exit = inside && C.box_margin && leaves_box(C, ix, iy, iz, L.dx, L.dy, L.dz);
+        if (!inside || box_exit) {
+            if (box_exit) { L.x = xn; L.y = yn; L.z = zn; }
             return escape(C, L, iu, iv);
         }
         const uint32_t k = brick_index((uint32_t)ix, (uint32_t)iy, (uint32_t)iz, (uint32_t)C.nx,
@@ -462,18 +467,14 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
         const float tk = 2.0f * k;
         const float r1 = unif(w0), r2 = unif(w1), r3 = unif(w2);
         const float den = fmaf(tk, r2, 1.0f);
-        float xx, ixx;
-        bool acc;
-        if (r1 * (9.0f + tk) <= 1.0f + tk) {
-            xx = den;
-            ixx = rcpf(xx);
-            acc = r3 <= 4.0f * (ixx - ixx * ixx);
-        } else {
-            xx = (1.0f + tk) * rcpf(den);
-            ixx = den * rcpf(1.0f + tk);
-            const float c = 1.0f - (xx - 1.0f) * ik;
-            acc = r3 <= 0.5f * fmaf(c, c, ixx);
-        }
+        const float r_den = rcpf(den);
+        // both candidates from one reciprocal each; the first branch of
+        // Kahn's method is x = den, the second x = (1 + 2k) / den
+        const bool first = r1 * (9.0f + tk) <= 1.0f + tk;
+        const float xx = first ? den : (1.0f + tk) * r_den;
+        const float ixx = first ? r_den : den * rcpf(1.0f + tk);
+        const float c = 1.0f - (xx - 1.0f) * ik;
+        const bool acc = first ? (r3 <= 4.0f * (ixx - ixx * ixx)) : (r3 <= 0.5f * fmaf(c, c, ixx));
         if (!acc) {
             L.a += 1;
             if (L.a >= KAHN_MAX) return MC_CAPPED_FATE;

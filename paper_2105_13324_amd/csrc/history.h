@@ -417,50 +417,61 @@ __device__ inline void begin_history(const Cst& C, Lane& L, uint32_t view, uint3
 // or a copy in LDS), read when C.use_pal.
 // fi: forced interaction (Sec. 5.2): a real collision is always a Compton
 // scatter and the weight takes the factor 1 - p_pe(E).
+//
+// Every lane runs exactly one of the two states; the body is laid out in
+// four phases so that a wavefront holding lanes of both states overlaps the
+// latency of the threshold gather with the Kahn arithmetic: (1) tentative
+// collision up to the gather of the voxel's threshold code (lanes that leave
+// escape here), (2) the Kahn attempt and, on acceptance, the new direction
+// and energy (arithmetic only), (3) the accept test of the tentative
+// collision, (4) the attenuation terms at a new energy (table reads).
 __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32_t w0, uint32_t w1,
                               uint32_t w2, uint32_t w3, Acc& A, int& iu, int& iv, bool fi = false) {
-    if (L.state == S_STEP) {
+    const int state = L.state;
+    int fate = R_RUNNING;
+    // (1) tentative collision n + 1: flight -log(u)/mu_max, the new point
+    bool pending = false;
+    uint32_t raw = 0;
+    float xn = 0.0f, yn = 0.0f, zn = 0.0f;
+    if (state == S_STEP) {
         L.n += 1;
         if (L.n > C.max_steps) {
             L.n -= 1;
-            return MC_CAPPED_FATE;
+            fate = MC_CAPPED_FATE;
+        } else {
+            A.n_tent++;
+            const float s = -__builtin_amdgcn_logf(unif(w0)) * L.ln2_mm;
+            xn = fmaf(s, L.dx, L.x);
+            yn = fmaf(s, L.dy, L.y);
+            zn = fmaf(s, L.dz, L.z);
+            const float tx = xn + C.hx, ty = yn + C.hy, tz = zn + C.hz;
+            const bool inside = (tx >= 0.0f) & (tx < C.lx) & (ty >= 0.0f) & (ty < C.ly) &
+                                (tz >= 0.0f) & (tz < C.lz);
+            const int ix = min((int)(tx * C.inv_vox), C.nx - 1);
+            const int iy = min((int)(ty * C.inv_vox), C.ny - 1);
+            const int iz = min((int)(tz * C.inv_vox), C.nz - 1);
+            // in the air outside the attenuation box, moving away from it, every
+            // later collision would be virtual: the photon escapes along this ray
+            // from the new point (one escape path for both ways out, so the
+            // wavefront runs it once when lanes leave both ways)
+            const bool box_exit = inside && C.box_margin && leaves_box(C, ix, iy, iz, L.dx, L.dy, L.dz);
+            if (!inside || box_exit) {
+                if (box_exit) { L.x = xn; L.y = yn; L.z = zn; }
+                fate = escape(C, L, iu, iv);
+            }
+            // the gather comes last in this phase, so nothing after it in the
+            // phase can reuse its destination register while it is in flight
+            pending = inside && !box_exit;
+            if (pending) {
+                const uint32_t k = brick_index((uint32_t)ix, (uint32_t)iy, (uint32_t)iz, (uint32_t)C.nx,
+                                               (uint32_t)C.ny, C.brick, C.bmask, C.nbx, C.nby);
+                raw = C.use_pal ? (uint32_t)ldg(C.q8 + k) : ldg(C.q32 + k);
+            }
         }
-        A.n_tent++;
-        const float s = -__builtin_amdgcn_logf(unif(w0)) * L.ln2_mm;
-        const float xn = fmaf(s, L.dx, L.x);
-        const float yn = fmaf(s, L.dy, L.y);
-        const float zn = fmaf(s, L.dz, L.z);
-        const float tx = xn + C.hx, ty = yn + C.hy, tz = zn + C.hz;
-        const bool inside = (tx >= 0.0f) & (tx < C.lx) & (ty >= 0.0f) & (ty < C.ly) &
-                            (tz >= 0.0f) & (tz < C.lz);
-        const int ix = min((int)(tx * C.inv_vox), C.nx - 1);
-        const int iy = min((int)(ty * C.inv_vox), C.ny - 1);
-        const int iz = min((int)(tz * C.inv_vox), C.nz - 1);
-        // in the air outside the attenuation box, moving away from it, every
-        // later collision would be virtual: the photon escapes along this ray
-        // from the new point (one escape path for both ways out, so the
-        // wavefront runs it once when lanes leave both ways)
-        const bool box_exit = inside && C.box_margin && leaves_box(C, ix, iy, iz, L.dx, L.dy, L.dz);
-        if (!inside || box_exit) {
-            if (box_exit) { L.x = xn; L.y = yn; L.z = zn; }
-            return escape(C, L, iu, iv);
-        }
-        const uint32_t k = brick_index((uint32_t)ix, (uint32_t)iy, (uint32_t)iz, (uint32_t)C.nx,
-                                       (uint32_t)C.ny, C.brick, C.bmask, C.nbx, C.nby);
-        const uint32_t q = C.use_pal ? pal[ldg(C.q8 + k)] : ldg(C.q32 + k);
-        L.x = xn; L.y = yn; L.z = zn;
-        if ((w1 >> 8) < q) {
-            A.n_real++;
-            if (fi) L.w *= 1.0f - L.p_pe;
-            else if (unif(w2) < L.p_pe) return MC_ABSORBED;
-            L.phi_word = w3;
-            L.a = 0;
-            L.state = S_KAHN;
-        }
-        return R_RUNNING;
     }
-    if (L.state == S_KAHN) {
-        // Kahn's rejection sampler for x = E/E' on [1, 1+2k], k = E / m_e c^2
+    // (2) Kahn's rejection sampler for x = E/E' on [1, 1+2k], k = E / m_e c^2
+    bool new_energy = false;
+    if (state == S_KAHN) {
         A.n_kahn++;
         const float k = L.e * INV_MEC2;
         const float ik = MEC2_F * rcpf(L.e);
@@ -477,19 +488,38 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
         const bool acc = first ? (r3 <= 4.0f * (ixx - ixx * ixx)) : (r3 <= 0.5f * fmaf(c, c, ixx));
         if (!acc) {
             L.a += 1;
-            if (L.a >= KAHN_MAX) return MC_CAPPED_FATE;
-            return R_RUNNING;
+            if (L.a >= KAHN_MAX) fate = MC_CAPPED_FATE;
+        } else {
+            const float ct = 1.0f - (xx - 1.0f) * ik;
+            L.e = L.e * ixx;
+            L.n_scatter += 1;
+            rotate(L, ct, unif(L.phi_word));
+            if (L.e < C.e_cut) {
+                fate = MC_CUT;
+            } else {
+                new_energy = true;
+                L.state = S_STEP;
+            }
         }
-        const float ct = 1.0f - (xx - 1.0f) * ik;
-        L.e = L.e * ixx;
-        L.n_scatter += 1;
-        rotate(L, ct, unif(L.phi_word));
-        if (L.e < C.e_cut) return MC_CUT;
-        energy_terms(C, L.e, L.ln2_mm, L.p_pe);
-        L.state = S_STEP;
-        return R_RUNNING;
     }
-    return R_RUNNING;
+    // (3) the tentative collision is real iff (r >> 8) < Q_v
+    if (pending) {
+        const uint32_t q = C.use_pal ? pal[raw] : raw;
+        L.x = xn; L.y = yn; L.z = zn;
+        if ((w1 >> 8) < q) {
+            A.n_real++;
+            if (fi) L.w *= 1.0f - L.p_pe;
+            else if (unif(w2) < L.p_pe) fate = MC_ABSORBED;
+            if (fate == R_RUNNING) {
+                L.phi_word = w3;
+                L.a = 0;
+                L.state = S_KAHN;
+            }
+        }
+    }
+    // (4) flight scale and photoelectric share at the new energy
+    if (new_energy) energy_terms(C, L.e, L.ln2_mm, L.p_pe);
+    return fate;
 }
 
 // ---------------------------------------------------------------------------

@@ -341,12 +341,21 @@ size_t mlem_workspace_bytes(int64_t n_bins, int64_t n_vox);
  * Tt_*, the same matrix), float values, double accumulation.  image: device
  * float [n_vox], in: S^0 (voxels with sens_i = 0 are set to 0), out: S^n_iter.
  * proj: device float [n_bins].  A bin with y_j = 0 contributes nothing.
- * Deterministic: the summation order depends only on the matrix.  Columns of
- * each Tt row in ascending order (as mc_system_matrix writes them) let large
- * detectors (n_bins >= 2^19) backproject one bin slice per XCD from L2; any
- * column order gives the same result.  Asynchronous on stream: no host
- * synchronisation, no allocation. */
-int mlem_iterate(int64_t n_bins, int64_t n_vox,
+ * nnz: the entry count, T_rowptr[n_bins] = Tt_rowptr[n_vox], as the caller
+ * knows it from building the matrix; it picks the layout and schedule before
+ * launch, and is checked on the device: a different value leaves the image
+ * NaN.  Each iteration sweeps only the non-empty rows of T and T^T (listed
+ * once per call): two kernels per iteration.  A sparse matrix (nnz <= n_bins
+ * + n_vox) is iterated in a compact layout (vectors over the non-empty rows,
+ * columns renumbered once per call) whose gathers stay in L2; on a large
+ * detector (n_bins >= 2^19, nnz >= 16 n_vox) the backprojection works on one
+ * bin slice per XCD (a third kernel adds the slices); columns of each Tt row
+ * in ascending order (as mc_system_matrix writes them) give the slices their
+ * locality, any order gives the same result.  Deterministic: the summation
+ * order depends only on the matrix.  Asynchronous on stream: no host
+ * synchronisation, no allocation, no memset, so a call can be captured in a
+ * graph (mc_graph_begin) and replayed. */
+int mlem_iterate(int64_t n_bins, int64_t n_vox, int64_t nnz,
                  const int64_t* T_rowptr, const int32_t* T_col, const float* T_val,
                  const int64_t* Tt_rowptr, const int32_t* Tt_col, const float* Tt_val,
                  const float* proj, float* image, int32_t n_iter,
@@ -393,13 +402,63 @@ int mc_block_activity(const uint32_t* act, int32_t nx, int32_t ny, int32_t nz, i
  * out pixel (j, i) of every plane = the bilinear interpolation at
  * ((i + 1/2) / f - 1/2, (j + 1/2) / f - 1/2) in coarse pixel units (each
  * coordinate clamped to [0, n_c - 1]) of the coarse values read as samples
- * at the coarse pixel centres, divided by f^2 (counts per normal pixel).
+ * at the coarse pixel centres, divided by f^2 (counts per normal pixel),
+ * times scale (1 for counts; A V / N for activity units, as mc_scale_tally).
  *   coarse  device int64 [n_planes][nv_c][nu_c], Q31.32 (a tally: planes =
  *           views x classes)
- *   out     device double [n_planes][nv_c f][nu_c f], counts
- * MC_EINVAL for sizes < 1. */
+ *   out     device double [n_planes][nv_c f][nu_c f]
+ * MC_EINVAL for sizes < 1 or a non-finite scale. */
 int mc_expand_projection(const int64_t* coarse, int64_t n_planes, int32_t nu_c, int32_t nv_c,
-                         int32_t factor, double* out, void* stream);
+                         int32_t factor, double scale, double* out, void* stream);
+
+/* Total weight of a source (Sec. 5.3): sum over the n_vox voxels of
+ * |activity - activity_prev| (of activity when activity_prev is NULL), the
+ * number a reuse-of-photon-tracks projector sets its histories by.
+ *   activity, activity_prev  device uint32 [n_vox] (activity_prev nullable)
+ *   total                    device uint64 [1], overwritten (exact)
+ * MC_EINVAL for n_vox < 1 or a NULL activity / total. */
+int mc_source_total(const uint32_t* activity, const uint32_t* activity_prev, int64_t n_vox,
+                    uint64_t* total, void* stream);
+
+/* A Q31.32 tally in activity units (Sec. 5.3, Sec. 5.4): out[i] = tally[i]
+ * 2^-32 scale, or out[i] + tally[i] 2^-32 scale when accumulate = 1 -- the
+ * projection of the new estimate as the old projection plus the scaled
+ * projection of the difference source (reuse of photon tracks; scale = A V /
+ * N for a source of total weight A simulated with N histories over V views).
+ *   tally  device int64 [n];  out  device double [n]
+ * MC_EINVAL for n < 1, a non-finite scale or accumulate not 0 or 1. */
+int mc_scale_tally(const int64_t* tally, int64_t n, double scale, double* out, int32_t accumulate,
+                   void* stream);
+
+/* Graph capture of a fixed sequence of library calls (the batched launch,
+ * response-matrix builds, reconstruction), for callers that replay it:
+ * mc_graph_begin starts capturing `stream` (thread-local capture mode); the
+ * calls then enqueued on it are recorded, not run; mc_graph_end ends the
+ * capture and instantiates it; mc_graph_launch replays it on a stream;
+ * mc_graph_destroy frees it.  The calls keep the pointers, sizes and options
+ * they were given at capture.  The library's kernels clear their outputs and
+ * counters themselves (no memset nodes), so every replay recomputes from the
+ * inputs.  stream must not be NULL (the legacy default stream cannot be
+ * captured). */
+typedef struct mc_graph_s* mc_graph;
+int mc_graph_begin(void* stream);
+int mc_graph_end(void* stream, mc_graph* graph);
+int mc_graph_launch(mc_graph graph, void* stream);
+int mc_graph_destroy(mc_graph graph);
+
+/* Launch options for a set of problems (the autotuner of the batched launch):
+ * for each of n_candidates option sets, one untimed mc_simulate_projections
+ * and reps timed ones (HIP events around the transport kernel); *best
+ * receives the index of the fastest (smallest of its reps), times_ms
+ * (host, nullable, [n_candidates]) each candidate's best time.  Options only
+ * change layout and scheduling (not forced_detection / variance reduction,
+ * which change the estimate), so every candidate gives bit-identical
+ * outputs; tally, fates and status hold the last run's.  workspace must
+ * hold mc_workspace_bytes for these problems.  Synchronous: returns when the
+ * last run has finished. */
+int mc_autotune(const mc_problem* problems, int32_t n_problems, const mc_options* candidates,
+                int32_t n_candidates, int32_t reps, int64_t* tally, int64_t* fates, int64_t* status,
+                void* workspace, size_t workspace_bytes, void* stream, int32_t* best, float* times_ms);
 
 /* Human-readable text for an MC_* code (static storage). */
 const char* mc_error_string(int code);

@@ -40,7 +40,8 @@ EXPORTS = ["mc_workspace_bytes", "mc_simulate_projections", "mc_simulate_project
            "mc_replay_histories",
            "mc_adjoint_mu", "mc_system_matrix_workspace_bytes", "mc_system_matrix",
            "mlem_workspace_bytes", "mlem_iterate", "osem_workspace_bytes", "osem_iterate",
-           "mc_block_activity", "mc_expand_projection",
+           "mc_block_activity", "mc_expand_projection", "mc_source_total", "mc_scale_tally",
+           "mc_graph_begin", "mc_graph_end", "mc_graph_launch", "mc_graph_destroy", "mc_autotune",
            "mc_error_string", "mc_last_hip_error"]
 
 
@@ -107,12 +108,28 @@ _lib.osem_iterate.restype = C.c_int
 _lib.mc_system_matrix.restype = C.c_int
 _lib.mlem_workspace_bytes.argtypes = [_i64, _i64]
 _lib.mlem_workspace_bytes.restype = _sz
-_lib.mlem_iterate.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp, _sz, _vp]
+_lib.mlem_iterate.argtypes = [_i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp,
+                              _sz, _vp]
 _lib.mlem_iterate.restype = C.c_int
 _lib.mc_block_activity.argtypes = [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]
 _lib.mc_block_activity.restype = C.c_int
-_lib.mc_expand_projection.argtypes = [_vp, _i64, _i32, _i32, _i32, _vp, _vp]
+_lib.mc_expand_projection.argtypes = [_vp, _i64, _i32, _i32, _i32, C.c_double, _vp, _vp]
 _lib.mc_expand_projection.restype = C.c_int
+_lib.mc_source_total.argtypes = [_vp, _vp, _i64, _vp, _vp]
+_lib.mc_source_total.restype = C.c_int
+_lib.mc_scale_tally.argtypes = [_vp, _i64, C.c_double, _vp, _i32, _vp]
+_lib.mc_scale_tally.restype = C.c_int
+_lib.mc_graph_begin.argtypes = [_vp]
+_lib.mc_graph_begin.restype = C.c_int
+_lib.mc_graph_end.argtypes = [_vp, C.POINTER(_vp)]
+_lib.mc_graph_end.restype = C.c_int
+_lib.mc_graph_launch.argtypes = [_vp, _vp]
+_lib.mc_graph_launch.restype = C.c_int
+_lib.mc_graph_destroy.argtypes = [_vp]
+_lib.mc_graph_destroy.restype = C.c_int
+_lib.mc_autotune.argtypes = [C.POINTER(McProblem), _i32, C.POINTER(McOptions), _i32, _i32, _vp, _vp, _vp,
+                             _vp, _sz, _vp, C.POINTER(_i32), C.POINTER(C.c_float)]
+_lib.mc_autotune.restype = C.c_int
 _lib.mc_error_string.argtypes = [C.c_int]
 _lib.mc_error_string.restype = C.c_char_p
 _lib.mc_last_hip_error.argtypes = []
@@ -425,14 +442,9 @@ class RptProjector:
         self.histories = []        # histories simulated per call
         self.seed = int(problem.seed)
 
-    def _run(self, activity, prev):
-        torch = _torch()
-        a = activity.to(torch.int64) & 0xFFFFFFFF        # the maps hold uint32 bits
-        if prev is not None:
-            total = int((a - (prev.to(torch.int64) & 0xFFFFFFFF)).abs().sum().item())
-        else:
-            total = int(a.sum().item())
+    def _run(self, activity, prev, out, accumulate):
         V = self.problem.n_views
+        total = source_total(activity, prev)
         per_view = max(1, int(round(self.hpu * total / V)))
         n = per_view * V
         self.seed += 1
@@ -440,20 +452,47 @@ class RptProjector:
                                 history_offset=0, history_count=0, seed=self.seed)
         self.histories.append(n)
         if total == 0:
-            return torch.zeros(dp.tally_shape, dtype=torch.float64, device=activity.device)
+            if not accumulate:
+                out.zero_()
+            return
         sim = simulate(dp, want_sq=False, options=self.options)
-        return sim.tally.view(dp.tally_shape).to(torch.float64) * (2.0 ** -32 * total * V / n)
+        scale_tally(sim.tally, total * V / n, out, accumulate)
 
     def project(self, activity):
         """Projection of the estimate `activity` (device uint32 map stored as
         int32, as to_device makes it)."""
+        torch = _torch()
         activity = activity.contiguous()
         if self.prev is None:
-            self.projection = self._run(activity, None)
+            self.projection = torch.empty(self.problem.tally_shape, dtype=torch.float64,
+                                          device=activity.device)
+            self._run(activity, None, self.projection, False)
         else:
-            self.projection = self.projection + self._run(activity, self.prev)
+            self._run(activity, self.prev, self.projection, True)
         self.prev = activity.clone()
         return self.projection
+
+
+def source_total(activity, activity_prev=None) -> int:
+    """Total weight of a source, sum |activity - activity_prev| (of activity
+    without a previous map), computed on the device (mc_source_total) and
+    read back (the history count of a projection is set from it)."""
+    torch = _torch()
+    total = torch.zeros(1, dtype=torch.int64, device=activity.device)
+    _check(_lib.mc_source_total(activity.data_ptr(),
+                                activity_prev.data_ptr() if activity_prev is not None else None,
+                                activity.numel(), total.data_ptr(), _stream_ptr()), "mc_source_total")
+    return int(total.item()) & 0xFFFFFFFFFFFFFFFF
+
+
+def scale_tally(tally, scale: float, out, accumulate: bool = False):
+    """out = tally x 2^-32 x scale, or out + that (mc_scale_tally); out: device
+    float64 tensor with as many elements as the tally."""
+    if out.numel() != tally.numel() or out.dtype != _torch().float64 or not out.is_contiguous():
+        raise McError("scale_tally: out must be a contiguous float64 tensor of the tally's size")
+    _check(_lib.mc_scale_tally(tally.data_ptr(), tally.numel(), float(scale), out.data_ptr(),
+                               1 if accumulate else 0, _stream_ptr()), "mc_scale_tally")
+    return out
 
 
 def coarse_problem(problem: DeviceProblem, factor: int) -> DeviceProblem:
@@ -477,15 +516,16 @@ def coarse_problem(problem: DeviceProblem, factor: int) -> DeviceProblem:
                          pixel_cm=problem.pixel_cm * f)
 
 
-def expand_projection(tally, shape, factor: int):
-    """A coarse Q31.32 tally [V, 2, nv_c, nu_c] expanded to counts per normal
-    pixel, float64 [V, 2, nv_c f, nu_c f] (mc_expand_projection)."""
+def expand_projection(tally, shape, factor: int, scale: float = 1.0):
+    """A coarse Q31.32 tally [V, 2, nv_c, nu_c] expanded to the normal pixels,
+    float64 [V, 2, nv_c f, nu_c f]: counts per normal pixel times scale
+    (mc_expand_projection)."""
     torch = _torch()
     V, K, nv_c, nu_c = shape
     f = int(factor)
     src = tally.contiguous()
     out = torch.empty((V, K, nv_c * f, nu_c * f), dtype=torch.float64, device=tally.device)
-    _check(_lib.mc_expand_projection(src.data_ptr(), V * K, nu_c, nv_c, f,
+    _check(_lib.mc_expand_projection(src.data_ptr(), V * K, nu_c, nv_c, f, float(scale),
                                      out.data_ptr(), _stream_ptr()), "mc_expand_projection")
     return out
 
@@ -515,7 +555,6 @@ class ScatterModel:
         self.last = None
 
     def estimate(self, activity):
-        torch = _torch()
         self.calls += 1
         if self.last is not None and self.simulations >= self.n_updates:
             return self.last
@@ -524,9 +563,9 @@ class ScatterModel:
                                 seed=int(self.problem.seed) + self.simulations)
         cp = coarse_problem(dp, self.factor)
         sim = simulate(cp, want_sq=False, options=self.options)
-        total = float((activity.to(torch.int64) & 0xFFFFFFFF).sum().item())
-        e = expand_projection(sim.tally, cp.tally_shape, self.factor)[:, 1]
-        self.last = e * (total * self.problem.n_views / self.histories)
+        total = source_total(dp.activity)
+        self.last = expand_projection(sim.tally, cp.tally_shape, self.factor,
+                                      total * self.problem.n_views / self.histories)[:, 1]
         self.simulations += 1
         return self.last
 
@@ -641,28 +680,53 @@ def _mc_project_fn():
 # Graph capture and autotuning of the batched launch
 # ---------------------------------------------------------------------------
 
-class GraphRunner:
-    """One mc_simulate_projections call on a Simulator captured as a HIP graph
-    (staging + transport + finalize as graph nodes); replay() relaunches it.
-    The graph holds the Simulator's buffers and options as captured."""
+class Graph:
+    """A fixed sequence of library calls captured as one HIP graph by the
+    library (mc_graph_begin / mc_graph_end) and replayed with
+    mc_graph_launch.  fn() is run `warmup` times eagerly, then once under
+    capture on a stream of its own; the graph keeps the buffers, sizes and
+    options those calls were given.  fn must not allocate (workspaces are
+    made beforehand) and must not synchronise."""
 
-    def __init__(self, sim: Simulator, warmup: int = 1):
+    def __init__(self, fn, warmup: int = 1):
         torch = _torch()
-        self.sim = sim
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
+        self.stream = torch.cuda.Stream()       # capture needs a stream of its own
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.stream):
             for _ in range(warmup):
-                sim.run()
-        torch.cuda.current_stream().wait_stream(side)
+                fn()
         torch.cuda.synchronize()
-        self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph, capture_error_mode="thread_local"):
-            sim.run()
-        torch.cuda.synchronize()
+        s = self.stream.cuda_stream
+        _check(_lib.mc_graph_begin(s), "mc_graph_begin")
+        g = C.c_void_p()
+        with torch.cuda.stream(self.stream):
+            try:
+                fn()
+            finally:
+                rc = _lib.mc_graph_end(s, C.byref(g))
+        _check(rc, "mc_graph_end")
+        self.graph = g
 
     def replay(self):
-        self.graph.replay()
+        _check(_lib.mc_graph_launch(self.graph, _stream_ptr()), "mc_graph_launch")
+
+    def __del__(self):
+        try:
+            if getattr(self, "graph", None):
+                _lib.mc_graph_destroy(self.graph)
+                self.graph = None
+        except Exception:
+            pass
+
+
+class GraphRunner(Graph):
+    """One mc_simulate_projections call on a Simulator as a graph (staging,
+    transport and finalize as graph nodes); replay() relaunches it on the
+    current stream."""
+
+    def __init__(self, sim: Simulator, warmup: int = 1):
+        self.sim = sim
+        super().__init__(sim.run, warmup)
 
 
 def _size_class(problems: Sequence[DeviceProblem]) -> str:
@@ -696,27 +760,17 @@ def autotune(problems: Union[DeviceProblem, Sequence[DeviceProblem]], *,
             pass
     if key in _TUNE_CACHE:
         return dict(_TUNE_CACHE[key])
-    timer = KernelTimer()
-    best, best_ms, log = None, float("inf"), []
-    sim = None
-    for b in bricks:
-        for h in hist_per_lane:
-            for bs in block_sizes:
-                opts = {"brick_log2": b, "hist_per_lane": h, "block_size": bs}
-                if sim is None:
-                    sim = Simulator(problems, want_sq=False, options=opts)
-                else:
-                    sim.options = _opts(opts)
-                sim.run()
-                ms = []
-                for _ in range(reps):
-                    sim.run(kernel_events=timer.handles)
-                    torch.cuda.synchronize()
-                    ms.append(timer.elapsed_ms())
-                t = min(ms)
-                log.append((opts, t))
-                if t < best_ms:
-                    best, best_ms = opts, t
+    cands = [{"brick_log2": br, "hist_per_lane": h, "block_size": bs}
+             for br in bricks for h in hist_per_lane for bs in block_sizes]
+    arr = (McOptions * len(cands))(*[_opts(o) for o in cands])
+    sim = Simulator(problems, want_sq=False)
+    best_i = C.c_int32(-1)
+    times = (C.c_float * len(cands))()
+    _check(_lib.mc_autotune(sim._arr, len(problems), arr, len(cands), int(reps), sim.tally.data_ptr(),
+                            sim.fates.data_ptr(), sim.status.data_ptr(), sim.workspace.data_ptr(),
+                            sim.workspace.numel(), _stream_ptr(), C.byref(best_i), times), "mc_autotune")
+    log = [(o, float(t)) for o, t in zip(cands, times)]
+    best = cands[best_i.value]
     if verbose:
         for o, t in log:
             print(f"autotune {o}: {t:.3f} ms")
@@ -808,12 +862,13 @@ class Mlem:
         if nb == 0:
             raise McError("mlem_workspace_bytes: invalid sizes")
         self.ws = torch.empty(nb, dtype=torch.uint8, device=m.T_val.device)
+        self.nnz = m.nnz                          # read once: it picks the schedule
 
     def run(self, image, n_iter: int, proj=None):
         """image: float32 device tensor [n_img], S^0 in, S^n_iter out (in place)."""
         m = self.m
         P = m.proj if proj is None else proj
-        rc = _lib.mlem_iterate(m.n_bins, m.n_img, m.T_rowptr.data_ptr(), m.T_col.data_ptr(),
+        rc = _lib.mlem_iterate(m.n_bins, m.n_img, self.nnz, m.T_rowptr.data_ptr(), m.T_col.data_ptr(),
                                m.T_val.data_ptr(), m.Tt_rowptr.data_ptr(), m.Tt_col.data_ptr(),
                                m.Tt_val.data_ptr(), P.data_ptr(), image.data_ptr(), int(n_iter),
                                self.ws.data_ptr(), self.ws.numel(), _stream_ptr())

@@ -15,7 +15,8 @@ LIB = os.path.join(HERE, "libmcspect.so")
 PROBE_LIB = os.path.join(HERE, "libmcprobe.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "staging.hip", "transport.hip", "adjoint.hip", "sysmat.hip", "cfd.hip", "cgsm.hip"]
+SOURCES = ["api.hip", "staging.hip", "transport.hip", "adjoint.hip", "sysmat.hip", "cfd.hip", "cgsm.hip",
+           "compose.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

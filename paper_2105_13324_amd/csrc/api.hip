@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "mc_internal.h"
@@ -493,17 +494,17 @@ size_t mlem_workspace_bytes(int64_t n_bins, int64_t n_vox) {
     return mlem_workspace((uint64_t)n_bins, (uint64_t)n_vox);
 }
 
-int mlem_iterate(int64_t n_bins, int64_t n_vox, const int64_t* T_rowptr, const int32_t* T_col,
-                 const float* T_val, const int64_t* Tt_rowptr, const int32_t* Tt_col,
-                 const float* Tt_val, const float* proj, float* image, int32_t n_iter,
-                 void* workspace, size_t workspace_bytes, void* stream) {
-    if (n_bins < 1 || n_vox < 1 || n_iter < 0) return MC_EINVAL;
+int mlem_iterate(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t* T_rowptr,
+                 const int32_t* T_col, const float* T_val, const int64_t* Tt_rowptr,
+                 const int32_t* Tt_col, const float* Tt_val, const float* proj, float* image,
+                 int32_t n_iter, void* workspace, size_t workspace_bytes, void* stream) {
+    if (n_bins < 1 || n_vox < 1 || nnz < 0 || n_iter < 0) return MC_EINVAL;
     if (n_bins >= (1ll << 31) || n_vox >= (1ll << 31)) return MC_EINVAL;
     if (!T_rowptr || !T_col || !T_val || !Tt_rowptr || !Tt_col || !Tt_val || !proj || !image ||
         !workspace)
         return MC_EINVAL;
     if (workspace_bytes < mlem_workspace((uint64_t)n_bins, (uint64_t)n_vox)) return MC_ENOMEM;
-    hipError_t e = launch_mlem(n_bins, n_vox, T_rowptr, T_col, T_val, Tt_rowptr, Tt_col, Tt_val,
+    hipError_t e = launch_mlem(n_bins, n_vox, nnz, T_rowptr, T_col, T_val, Tt_rowptr, Tt_col, Tt_val,
                                proj, image, n_iter, workspace, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
     return MC_OK;
@@ -545,12 +546,134 @@ int mc_block_activity(const uint32_t* act, int32_t nx, int32_t ny, int32_t nz, i
 }
 
 int mc_expand_projection(const int64_t* coarse, int64_t n_planes, int32_t nu_c, int32_t nv_c,
-                         int32_t factor, double* out, void* stream) {
+                         int32_t factor, double scale, double* out, void* stream) {
     if (!coarse || !out || n_planes < 1 || nu_c < 1 || nv_c < 1 || factor < 1) return MC_EINVAL;
+    if (!std::isfinite(scale)) return MC_EINVAL;
     if ((uint64_t)nu_c * factor >= (1ull << 20) || (uint64_t)nv_c * factor >= (1ull << 20)) return MC_EINVAL;
     if ((uint64_t)n_planes * nu_c * factor * nv_c * factor >= (1ull << 40)) return MC_EINVAL;
-    const hipError_t e = launch_expand(coarse, (uint64_t)n_planes, nu_c, nv_c, factor, out, (hipStream_t)stream);
+    const hipError_t e = launch_expand(coarse, (uint64_t)n_planes, nu_c, nv_c, factor, scale, out,
+                                       (hipStream_t)stream);
     return e == hipSuccess ? MC_OK : hip_fail(e);
+}
+
+int mc_source_total(const uint32_t* activity, const uint32_t* activity_prev, int64_t n_vox,
+                    uint64_t* total, void* stream) {
+    if (!activity || !total || n_vox < 1) return MC_EINVAL;
+    const hipError_t e = launch_source_total(activity, activity_prev, (uint64_t)n_vox,
+                                             (unsigned long long*)total, (hipStream_t)stream);
+    return e == hipSuccess ? MC_OK : hip_fail(e);
+}
+
+int mc_scale_tally(const int64_t* tally, int64_t n, double scale, double* out, int32_t accumulate,
+                   void* stream) {
+    if (!tally || !out || n < 1 || !std::isfinite(scale)) return MC_EINVAL;
+    if (accumulate != 0 && accumulate != 1) return MC_EINVAL;
+    const hipError_t e = launch_scale_tally(tally, (uint64_t)n, scale, out, accumulate, (hipStream_t)stream);
+    return e == hipSuccess ? MC_OK : hip_fail(e);
+}
+
+}  // extern "C"
+
+struct mc_graph_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+extern "C" {
+
+int mc_graph_begin(void* stream) {
+    if (!stream) return MC_EINVAL;   // the legacy default stream cannot be captured
+    const hipError_t e = hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal);
+    return e == hipSuccess ? MC_OK : hip_fail(e);
+}
+
+int mc_graph_end(void* stream, mc_graph* out) {
+    if (!stream || !out) return MC_EINVAL;
+    *out = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture((hipStream_t)stream, &g);
+    if (e != hipSuccess) return hip_fail(e);
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e);
+    }
+    mc_graph h = new (std::nothrow) mc_graph_s;
+    if (!h) {
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
+        return MC_ENOMEM;
+    }
+    h->graph = g;
+    h->exec = x;
+    *out = h;
+    return MC_OK;
+}
+
+int mc_graph_launch(mc_graph graph, void* stream) {
+    if (!graph) return MC_EINVAL;
+    const hipError_t e = hipGraphLaunch(graph->exec, (hipStream_t)stream);
+    return e == hipSuccess ? MC_OK : hip_fail(e);
+}
+
+int mc_graph_destroy(mc_graph graph) {
+    if (!graph) return MC_OK;
+    hipError_t e = hipGraphExecDestroy(graph->exec);
+    const hipError_t e2 = hipGraphDestroy(graph->graph);
+    delete graph;
+    if (e == hipSuccess) e = e2;
+    return e == hipSuccess ? MC_OK : hip_fail(e);
+}
+
+int mc_autotune(const mc_problem* problems, int32_t n_problems, const mc_options* candidates,
+                int32_t n_candidates, int32_t reps, int64_t* tally, int64_t* fates, int64_t* status,
+                void* workspace, size_t workspace_bytes, void* stream, int32_t* best, float* times_ms) {
+    if (!problems || n_problems < 1 || !candidates || n_candidates < 1 || reps < 1 || !best)
+        return MC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    if (e != hipSuccess) {
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        return hip_fail(e);
+    }
+    int rc = MC_OK;
+    float best_ms = 0.0f;
+    *best = -1;
+    for (int32_t c = 0; c < n_candidates && rc == MC_OK; ++c) {
+        mc_options o = candidates[c];
+        o.kernel_events[0] = nullptr;
+        o.kernel_events[1] = nullptr;
+        rc = simulate_impl(problems, n_problems, &o, tally, nullptr, fates, nullptr, nullptr, nullptr, 0,
+                           nullptr, status, workspace, workspace_bytes, stream);     // untimed
+        o.kernel_events[0] = ev[0];
+        o.kernel_events[1] = ev[1];
+        float t_c = 0.0f;
+        for (int32_t r = 0; r < reps && rc == MC_OK; ++r) {
+            rc = simulate_impl(problems, n_problems, &o, tally, nullptr, fates, nullptr, nullptr, nullptr,
+                               0, nullptr, status, workspace, workspace_bytes, stream);
+            if (rc != MC_OK) break;
+            float ms = 0.0f;
+            if ((e = hipEventSynchronize(ev[1])) != hipSuccess ||
+                (e = hipEventElapsedTime(&ms, ev[0], ev[1])) != hipSuccess) {
+                rc = hip_fail(e);
+                break;
+            }
+            if (r == 0 || ms < t_c) t_c = ms;
+        }
+        if (rc != MC_OK) break;
+        if (times_ms) times_ms[c] = t_c;
+        if (*best < 0 || t_c < best_ms) {
+            *best = c;
+            best_ms = t_c;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    (void)st;
+    return rc;
 }
 
 const char* mc_error_string(int code) {

@@ -7,7 +7,8 @@
 // uniform over the block.  k_expand turns a coarse Q31.32 projection into
 // counts per normal pixel: bilinear interpolation at the pixel centre of the
 // coarse values read as samples at the coarse pixel centres (held constant
-// beyond the outermost centres), divided by f^2.  Both are HBM-bound passes.
+// beyond the outermost centres), divided by f^2 (and times a caller's scale,
+// e.g. to activity units).  Both are HBM-bound passes.
 #include "mc_internal.h"
 
 namespace mcs {
@@ -51,10 +52,11 @@ __device__ inline void lerp_index(int i, int f, int n_c, int& i0, int& i1, doubl
 
 // one thread per normal pixel of every plane
 __global__ __launch_bounds__(256) void k_expand(const int64_t* __restrict__ coarse, uint64_t n_planes,
-                                                int nu_c, int nv_c, int f, double* __restrict__ out) {
+                                                int nu_c, int nv_c, int f, double user_scale,
+                                                double* __restrict__ out) {
     const int nu = nu_c * f, nv = nv_c * f;
     const uint64_t n = n_planes * (uint64_t)nu * nv;
-    const double scale = 1.0 / (4294967296.0 * f * f);
+    const double scale = user_scale / (4294967296.0 * f * f);
     for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
          o += (uint64_t)gridDim.x * blockDim.x) {
         const int i = (int)(o % nu), j = (int)((o / nu) % nv);
@@ -86,10 +88,10 @@ hipError_t launch_block_activity(const uint32_t* act, int nx, int ny, int nz, in
     return hipGetLastError();
 }
 
-hipError_t launch_expand(const int64_t* coarse, uint64_t n_planes, int nu_c, int nv_c, int f, double* out,
-                         hipStream_t s) {
+hipError_t launch_expand(const int64_t* coarse, uint64_t n_planes, int nu_c, int nv_c, int f, double scale,
+                         double* out, hipStream_t s) {
     const uint64_t n = n_planes * (uint64_t)nu_c * f * nv_c * f;
-    k_expand<<<grid_for_n(n), 256, 0, s>>>(coarse, n_planes, nu_c, nv_c, f, out);
+    k_expand<<<grid_for_n(n), 256, 0, s>>>(coarse, n_planes, nu_c, nv_c, f, scale, out);
     return hipGetLastError();
 }
 

@@ -138,8 +138,15 @@ struct CallState {
 // to the normal pixels.
 hipError_t launch_block_activity(const uint32_t* act, int nx, int ny, int nz, int f, uint32_t* out,
                                  int64_t* status, hipStream_t s);
-hipError_t launch_expand(const int64_t* coarse, uint64_t n_planes, int nu_c, int nv_c, int f, double* out,
-                         hipStream_t s);
+hipError_t launch_expand(const int64_t* coarse, uint64_t n_planes, int nu_c, int nv_c, int f, double scale,
+                         double* out, hipStream_t s);
+
+// Host launchers (compose.hip): total source weight (sum of |act - prev|)
+// into a device uint64; a Q31.32 tally times scale into (or added to) FP64.
+hipError_t launch_source_total(const uint32_t* act, const uint32_t* prev, uint64_t n,
+                               unsigned long long* total, hipStream_t s);
+hipError_t launch_scale_tally(const int64_t* tally, uint64_t n, double scale, double* out, int accumulate,
+                              hipStream_t s);
 
 // Host launchers (cfd.hip): zero the layers and build the responses (per call,
 // before transport); convolve the layers into the tally (after transport).
@@ -205,10 +212,10 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
                          int64_t* Tt_rp, int32_t* Tt_col, float* Tt_val, float* proj,
                          void* workspace, hipStream_t s);
 size_t mlem_workspace(uint64_t n_bins, uint64_t n_vox);
-hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, const int64_t* T_rp, const int32_t* T_col,
-                       const float* T_val, const int64_t* Tt_rp, const int32_t* Tt_col,
-                       const float* Tt_val, const float* proj, float* image, int32_t n_iter,
-                       void* workspace, hipStream_t s);
+hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t* T_rp,
+                       const int32_t* T_col, const float* T_val, const int64_t* Tt_rp,
+                       const int32_t* Tt_col, const float* Tt_val, const float* proj, float* image,
+                       int32_t n_iter, void* workspace, hipStream_t s);
 
 size_t osem_workspace(uint64_t n_bins, uint64_t n_vox, uint32_t n_sub);
 hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n_sub,

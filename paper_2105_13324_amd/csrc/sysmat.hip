@@ -19,9 +19,10 @@
 //
 // MLEM.  S_i <- S_i / sens_i * sum_j T_ij P_j / y_j, y = T S, sens_i =
 // sum_j T_ij; FP32 matrix values, FP64 accumulation; bins with y_j = 0 add
-// nothing; voxels with sens_i = 0 stay 0.  Rows are swept by groups of 1 to
-// 64 lanes sized to the mean row length; on large detectors the
-// backprojection works on one bin slice per XCD so its gathers hit L2.
+// nothing; voxels with sens_i = 0 stay 0.  The non-empty rows are listed
+// once per call and only they are swept, by groups of 1 to 64 lanes sized to
+// their mean length; on large detectors the backprojection works on one bin
+// slice per XCD so its gathers hit L2.
 #include <algorithm>
 
 #include "mc_internal.h"
@@ -177,8 +178,8 @@ __device__ inline bool event_rc(const SysArgs& a, const mc_event& ev, uint32_t& 
 }
 
 __global__ __launch_bounds__(T256) void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
+    for (uint64_t i = (uint64_t)blockIdx.x * T256 + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * T256) p[i] = v;
 }
 
 // activity per image voxel, and the total
@@ -189,8 +190,8 @@ __global__ __launch_bounds__(T256) void k_image_activity(const uint32_t* __restr
                                                          unsigned long long* __restrict__ total) {
     const uint64_t n = (uint64_t)nx * ny * nz;
     uint64_t sum = 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t i = (uint64_t)blockIdx.x * T256 + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * T256) {
         const uint32_t a = act[i];
         if (!a) continue;
         sum += a;
@@ -244,8 +245,8 @@ __global__ __launch_bounds__(T256) void k_make_keys(SysArgs a, int transpose, ui
                                                     int col_bits, uint64_t* __restrict__ keys,
                                                     int64_t* __restrict__ vals) {
     const uint64_t n = n_events_of(a);
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-         e += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t e = (uint64_t)blockIdx.x * T256 + threadIdx.x; e < n;
+         e += (uint64_t)gridDim.x * T256) {
         uint32_t bin, img;
         const mc_event ev = a.events[e];
         if (event_rc(a, ev, bin, img)) {
@@ -395,8 +396,8 @@ __global__ __launch_bounds__(T256) void k_row_starts(const uint64_t* __restrict_
                                                      int col_bits, uint64_t n_rows,
                                                      uint64_t* __restrict__ start) {
     const uint64_t n = n_events_of(a);
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n_rows;
-         r += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t r = (uint64_t)blockIdx.x * T256 + threadIdx.x; r <= n_rows;
+         r += (uint64_t)gridDim.x * T256) {
         const uint64_t key = r << col_bits;
         uint64_t lo = 0, hi = n;
         while (lo < hi) {
@@ -414,8 +415,8 @@ __global__ __launch_bounds__(T256) void k_run_heads(const uint64_t* __restrict__
                                                     uint64_t n_rows, uint64_t capacity,
                                                     uint32_t* __restrict__ flag) {
     const uint64_t n_valid = start[n_rows] < capacity ? start[n_rows] : capacity;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_valid;
-         i += (uint64_t)gridDim.x * blockDim.x)
+    for (uint64_t i = (uint64_t)blockIdx.x * T256 + threadIdx.x; i < n_valid;
+         i += (uint64_t)gridDim.x * T256)
         flag[i] = i == 0 || keys[i] != keys[i - 1];
 }
 
@@ -423,8 +424,8 @@ __global__ __launch_bounds__(T256) void k_run_heads(const uint64_t* __restrict__
 __global__ __launch_bounds__(T256) void k_rows_from_runs(const uint64_t* __restrict__ start,
                                                          const uint64_t* __restrict__ head_pos,
                                                          uint64_t n_rows, int64_t* __restrict__ rowptr) {
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= n_rows;
-         r += (uint64_t)gridDim.x * blockDim.x)
+    for (uint64_t r = (uint64_t)blockIdx.x * T256 + threadIdx.x; r <= n_rows;
+         r += (uint64_t)gridDim.x * T256)
         rowptr[r] = (int64_t)head_pos[start[r]];
 }
 
@@ -443,8 +444,8 @@ __global__ __launch_bounds__(T256) void k_emit_runs(SysArgs a, int transpose,
     const uint64_t n_valid = start[n_rows];
     const double total = (double)*total_p;
     const uint64_t mask = (1ull << col_bits) - 1ull;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_valid;
-         i += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t i = (uint64_t)blockIdx.x * T256 + threadIdx.x; i < n_valid;
+         i += (uint64_t)gridDim.x * T256) {
         const uint64_t k = keys[i];
         if (i > 0 && keys[i - 1] == k) continue;
         long long cw = 0;
@@ -465,8 +466,8 @@ __global__ __launch_bounds__(T256) void k_emit_runs(SysArgs a, int transpose,
 __global__ __launch_bounds__(T256) void k_proj_rows(const int64_t* __restrict__ w,
                                                     const uint64_t* __restrict__ start,
                                                     uint64_t n_rows, float* __restrict__ proj) {
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n_rows;
-         r += (uint64_t)gridDim.x * blockDim.x) {
+    for (uint64_t r = (uint64_t)blockIdx.x * T256 + threadIdx.x; r < n_rows;
+         r += (uint64_t)gridDim.x * T256) {
         long long tot = 0;
         for (uint64_t i = start[r]; i < start[r + 1]; ++i) tot += w[i];
         proj[r] = (float)((double)tot * 0x1p-32);
@@ -492,8 +493,8 @@ __device__ inline double wave_sum_f64(double v) {
 template <class Term, class Done>
 __device__ inline void for_rows(int64_t n_rows, const int64_t* __restrict__ rp, Term term, Done done) {
     const bool wave_mode = rp[n_rows] >= WAVE_ROW_MIN * n_rows;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * T256 + threadIdx.x;
+    const int64_t nt = (int64_t)gridDim.x * T256;
     if (wave_mode) {
         const int lane = threadIdx.x & 63;
         for (int64_t r = tid >> 6; r < n_rows; r += nt >> 6) {
@@ -517,18 +518,161 @@ __global__ __launch_bounds__(T256) void k_row_sums(int64_t n_rows, const int64_t
              [&](int64_t r, double acc) { out[r] = acc; });
 }
 
-__global__ __launch_bounds__(T256) void k_mlem_init(int64_t n_vox, const float* __restrict__ img,
+// Per-call state of mlem_iterate (device uint32 [ST_WORDS]): the lengths of
+// the two row lists, a flag set when the entry count the caller gave is not
+// the matrix's own (the iterations then sweep nothing and the image is NaN),
+// and the lengths of the row-length class lists of the compact layout (four
+// for bins, four for voxels).
+enum { ST_BINS = 0, ST_VOXS = 1, ST_BAD = 2, ST_BIN_CLASS = 4, ST_VOX_CLASS = 8, ST_WORDS = 12 };
+
+// S_i = img_i where sens_i > 0, else 0 (row order; in list order the compact
+// layout sets S in k_mlem_compact); the list lengths zeroed, the entry count
+// checked against both row-pointer arrays.
+__global__ __launch_bounds__(T256) void k_mlem_init(int64_t n_bins, int64_t n_vox, int64_t nnz,
+                                                    const int64_t* __restrict__ T_rp,
+                                                    const int64_t* __restrict__ Tt_rp,
+                                                    const float* __restrict__ img,
                                                     const double* __restrict__ sens,
-                                                    double* __restrict__ S) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
-         i += (int64_t)gridDim.x * blockDim.x)
+                                                    double* __restrict__ S, uint32_t* __restrict__ st,
+                                                    int compact) {
+    if (blockIdx.x == 0 && threadIdx.x < ST_WORDS)
+        st[threadIdx.x] = threadIdx.x != ST_BAD ? 0u
+                                                : (T_rp[n_bins] != nnz || Tt_rp[n_vox] != nnz) ? 1u : 0u;
+    if (compact) return;
+    for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * T256)
         S[i] = sens[i] > 0.0 ? (double)img[i] : 0.0;
+}
+
+// A non-empty row of a CSR matrix: its index and entry range.
+struct RowRef {
+    int64_t lo;
+    int32_t row, len;
+};
+
+// The non-empty rows of T (bins[], length st[ST_BINS]) and of T^T (voxs[],
+// length st[ST_VOXS]): only these are swept by the iterations (an empty bin
+// row has no ratio to compute, an empty voxel row has sens_i = 0 and
+// S_i = 0).  A workgroup takes 4096 consecutive rows of one matrix at a time
+// and appends their non-empty ones in row order with one atomic; the order
+// of the workgroups' runs varies from call to call, which changes no result,
+// since every row is summed by one group of lanes on its own.  bin_pos /
+// vox_pos (nullable): each row's list position, -1 for an empty row.
+constexpr int ROWS_PER_THREAD = 16;
+constexpr int ROW_CHUNK = T256 * ROWS_PER_THREAD;
+
+__global__ __launch_bounds__(T256) void k_mlem_rows(int64_t n_bins, int64_t n_vox,
+                                                    const int64_t* __restrict__ T_rp,
+                                                    const int64_t* __restrict__ Tt_rp,
+                                                    RowRef* __restrict__ bins,
+                                                    RowRef* __restrict__ voxs,
+                                                    int32_t* __restrict__ bin_pos,
+                                                    int32_t* __restrict__ vox_pos,
+                                                    uint32_t* __restrict__ st) {
+    constexpr int WAVES = T256 / 64;
+    __shared__ uint32_t before[ROWS_PER_THREAD * WAVES];
+    __shared__ uint32_t base_s;
+    if (st[ST_BAD]) return;
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    const uint64_t lane_lt = (1ull << lane) - 1;
+    const int64_t nbc = (n_bins + ROW_CHUNK - 1) / ROW_CHUNK;
+    const int64_t nvc = (n_vox + ROW_CHUNK - 1) / ROW_CHUNK;
+    for (int64_t c = blockIdx.x; c < nbc + nvc; c += gridDim.x) {
+        const bool vox = c >= nbc;
+        const int64_t r0 = (vox ? c - nbc : c) * ROW_CHUNK;
+        const int64_t nr = vox ? n_vox : n_bins;
+        const int64_t* rp = vox ? Tt_rp : T_rp;
+        int32_t* pos = vox ? vox_pos : bin_pos;
+        int64_t lo[ROWS_PER_THREAD];
+        int32_t len[ROWS_PER_THREAD];
+        uint64_t m[ROWS_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+            const int64_t r = r0 + k * T256 + threadIdx.x;
+            lo[k] = 0;
+            len[k] = 0;
+            if (r < nr) {
+                lo[k] = rp[r];
+                len[k] = (int32_t)(rp[r + 1] - lo[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+            m[k] = __ballot(len[k] > 0);
+            if (lane == 0) before[k * WAVES + w] = (uint32_t)__popcll(m[k]);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // rows r0 + k * 256 + w * 64 + lane in (k, w, lane) order: row order
+            uint32_t tot = 0;
+            for (int q = 0; q < ROWS_PER_THREAD * WAVES; ++q) {
+                const uint32_t x = before[q];
+                before[q] = tot;
+                tot += x;
+            }
+            base_s = tot ? atomicAdd(&st[vox ? ST_VOXS : ST_BINS], tot) : 0u;
+        }
+        __syncthreads();
+        RowRef* out = vox ? voxs : bins;
+#pragma unroll
+        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+            const int64_t r = r0 + k * T256 + threadIdx.x;
+            const uint32_t slot = base_s + before[k * WAVES + w] + (uint32_t)__popcll(m[k] & lane_lt);
+            if (len[k] > 0) out[slot] = RowRef{lo[k], (int32_t)r, len[k]};
+            if (pos && r < nr) pos[r] = len[k] > 0 ? (int32_t)slot : -1;
+        }
+        __syncthreads();     // before[] and base_s are rewritten for the next chunk
+    }
+}
+
+// Compact layout (sparse matrices, nnz <= n_bins + n_vox): the iterations
+// keep S, sens, P and the ratio in list order, and the column indices of both
+// matrices are renumbered to list positions (Tc: voxel positions, Ttc: bin
+// positions), so every gather falls in a vector of the non-empty rows only
+// (a few MB at most, L2-resident) instead of a sparse scattering over the
+// full bin and voxel ranges.  The summation order is the same as in row
+// order.  A column whose row in the other orientation is empty (the two
+// orientations disagree) sets the bad flag.
+__global__ __launch_bounds__(T256) void k_mlem_compact(int64_t nnz, const int32_t* __restrict__ T_col,
+                                                       const int32_t* __restrict__ Tt_col,
+                                                       const int32_t* __restrict__ bin_pos,
+                                                       const int32_t* __restrict__ vox_pos,
+                                                       int32_t* __restrict__ Tc, int32_t* __restrict__ Ttc,
+                                                       const RowRef* __restrict__ bins,
+                                                       const RowRef* __restrict__ voxs,
+                                                       const float* __restrict__ img,
+                                                       const double* __restrict__ sens,
+                                                       double* __restrict__ S_l,
+                                                       double* __restrict__ sens_l,
+                                                       const float* __restrict__ P,
+                                                       float* __restrict__ P_l, uint32_t* __restrict__ st) {
+    if (st[ST_BAD]) return;
+    const int64_t nb = st[ST_BINS], nv = st[ST_VOXS];
+    const int64_t n = std::max(nnz, std::max(nb, nv));
+    bool bad = false;
+    for (int64_t t = (int64_t)blockIdx.x * T256 + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * T256) {
+        if (t < nnz) {
+            const int32_t pv = vox_pos[T_col[t]], pb = bin_pos[Tt_col[t]];
+            bad |= pv < 0 || pb < 0;
+            Tc[t] = pv < 0 ? 0 : pv;
+            Ttc[t] = pb < 0 ? 0 : pb;
+        }
+        if (t < nv) {
+            const int32_t i = voxs[t].row;
+            const double si = sens[i];
+            sens_l[t] = si;
+            S_l[t] = si > 0.0 ? (double)img[i] : 0.0;
+        }
+        if (t < nb) P_l[t] = P[bins[t].row];
+    }
+    if (bad) atomicOr(&st[ST_BAD], 1u);
 }
 
 // Lanes that share one row in the MLEM sweeps: the smallest group of 1, 4, 16
 // or 64 lanes for which four entries per lane cover the mean row (nnz /
 // n_rows entries), so that short rows do not leave most of a wavefront idle.
-__device__ inline int lanes_per_row(int64_t nnz, int64_t n_rows) {
+__host__ __device__ inline int lanes_per_row(int64_t nnz, int64_t n_rows) {
     if (nnz <= 4 * n_rows) return 1;
     if (nnz <= 16 * n_rows) return 4;
     if (nnz <= 64 * n_rows) return 16;
@@ -542,9 +686,9 @@ struct RowGroups {
     int64_t first, step;
     int sub;
     __device__ RowGroups(int64_t block, int64_t n_blocks) {
-        const int64_t t = block * blockDim.x + threadIdx.x;
+        const int64_t t = block * T256 + threadIdx.x;
         first = t / GS;
-        step = n_blocks * blockDim.x / GS;
+        step = n_blocks * T256 / GS;
         sub = (int)(threadIdx.x & (GS - 1));
     }
 };
@@ -598,37 +742,73 @@ __device__ inline void sweep_rows(const RowGroups<GS>& G, int64_t n, Bounds boun
     }
 }
 
-// y_j = sum_i T_ij S_i; ratio_j = P_j / y_j (0 when y_j = 0).  An empty bin
-// row is skipped: no entry of T^T refers to it, so its ratio is never read.
-template <int GS>
-__device__ inline void mlem_forward_rows(int64_t n_bins, const int64_t* __restrict__ rp,
-                                         const int32_t* __restrict__ col,
-                                         const float* __restrict__ val,
-                                         const double* __restrict__ S,
-                                         const float* __restrict__ P, double* __restrict__ ratio) {
-    const RowGroups<GS> G(blockIdx.x, gridDim.x);
-    sweep_rows(G, n_bins, [&](int64_t j, int64_t& lo, int64_t& hi) { lo = rp[j]; hi = rp[j + 1]; },
-               [&](int64_t k, bool ok) {
-                   const double x = (double)val[k] * S[col[k]];
-                   return ok ? x : 0.0;
-               },
-               [&](int64_t j, int64_t, int64_t len, double y) {
-                   if (len > 0 && G.sub == 0) ratio[j] = y > 0.0 ? (double)P[j] / y : 0.0;
-               });
+// A group's share of a row list: entries q = G.first + k G.step (k = 0, 1,
+// ...), four per pass.  The first four entries are loaded together with the
+// list's length (those past it are read from the list's spare capacity, cap
+// entries in all, and dropped), so a sweep of short rows waits for three
+// dependent loads (list entry, matrix entry, gathered vector entry), not
+// four.  aux(q, valid, ref) loads a row's own operands (q clamped below cap)
+// before its sum; done(q, ref, aux, sum) runs for every listed row.
+template <int GS, class Aux, class Term, class Done>
+__device__ inline void sweep_list(const RowGroups<GS>& G, const RowRef* __restrict__ L, int64_t cap,
+                                  const uint32_t* __restrict__ count, Aux aux, Term term, Done done) {
+    if (G.first >= cap) return;
+    RowRef ref[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t q = G.first + u * G.step;
+        ref[u] = L[q < cap ? q : cap - 1];
+    }
+    const uint32_t n32 = *count;
+    // all five loads in flight before any is used (the compiler would
+    // otherwise issue the rows' loads only once the length test has passed)
+    asm volatile("" ::"v"(ref[0].lo), "v"(ref[1].lo), "v"(ref[2].lo), "v"(ref[3].lo), "s"(n32));
+    const int64_t n = n32;
+    for (int64_t r = G.first; r < n; r += 4 * G.step) {
+        if (r != G.first) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t q = r + u * G.step;
+                ref[u] = L[q < n ? q : n - 1];
+            }
+        }
+        bool ok[4];
+        decltype(aux(0, false, ref[0])) a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t q = r + u * G.step;
+            ok[u] = q < n;
+            a[u] = aux(q < cap ? q : cap - 1, ok[u], ref[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (ok[u])
+                done(r + u * G.step, ref[u], a[u],
+                     group_row_sum<GS>(ref[u].lo, ref[u].lo + ref[u].len, G.sub, term));
+    }
 }
 
-__global__ __launch_bounds__(T256) void k_mlem_forward(int64_t n_bins, const int64_t* __restrict__ rp,
+// y_j = sum_i T_ij S_i; ratio_j = P_j / y_j (0 when y_j = 0), over the
+// non-empty bin rows (an empty one is referred to by no entry of T^T, so its
+// ratio is never read).
+template <int GS>
+__global__ __launch_bounds__(T256) void k_mlem_forward(const RowRef* __restrict__ L, int64_t cap,
+                                                       const uint32_t* __restrict__ count,
                                                        const int32_t* __restrict__ col,
                                                        const float* __restrict__ val,
                                                        const double* __restrict__ S,
                                                        const float* __restrict__ P,
                                                        double* __restrict__ ratio) {
-    switch (lanes_per_row(rp[n_bins], n_bins)) {
-        case 1: mlem_forward_rows<1>(n_bins, rp, col, val, S, P, ratio); break;
-        case 4: mlem_forward_rows<4>(n_bins, rp, col, val, S, P, ratio); break;
-        case 16: mlem_forward_rows<16>(n_bins, rp, col, val, S, P, ratio); break;
-        default: mlem_forward_rows<64>(n_bins, rp, col, val, S, P, ratio); break;
-    }
+    const RowGroups<GS> G(blockIdx.x, gridDim.x);
+    sweep_list(G, L, cap, count,
+               [&](int64_t, bool ok, const RowRef& r) { return P[ok ? r.row : 0]; },
+               [&](int64_t k, bool ok) {
+                   const double x = (double)val[k] * S[col[k]];
+                   return ok ? x : 0.0;
+               },
+               [&](int64_t, const RowRef& r, float p, double y) {
+                   if (G.sub == 0) ratio[r.row] = y > 0.0 ? (double)p / y : 0.0;
+               });
 }
 
 // Backprojection by bin slices.  When the ratio vector is larger than one
@@ -644,7 +824,7 @@ __global__ __launch_bounds__(T256) void k_mlem_forward(int64_t n_bins, const int
 constexpr int MLEM_SEGS = 8;
 constexpr int64_t MLEM_SEG_MIN_BINS = (int64_t)1 << 19;
 
-__host__ __device__ inline bool mlem_sliced(int64_t n_bins, int64_t nnz, int64_t n_vox) {
+inline bool mlem_sliced(int64_t n_bins, int64_t nnz, int64_t n_vox) {
     return n_bins >= MLEM_SEG_MIN_BINS && nnz >= 16 * n_vox;
 }
 
@@ -654,9 +834,8 @@ __global__ __launch_bounds__(T256) void k_mlem_slices(int64_t n_vox, int64_t n_b
                                                       const int64_t* __restrict__ rp,
                                                       const int32_t* __restrict__ col,
                                                       int64_t* __restrict__ sb) {
-    if (!mlem_sliced(n_bins, rp[n_vox], n_vox)) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * T256) {
         int64_t lo = rp[i];
         const int64_t hi = rp[i + 1];
         int64_t* out = sb + i * (MLEM_SEGS + 1);
@@ -675,36 +854,209 @@ __global__ __launch_bounds__(T256) void k_mlem_slices(int64_t n_vox, int64_t n_b
     }
 }
 
-// S_i <- S_i * (sum_j T_ij ratio_j) / sens_i over whole voxel rows.  An
-// empty row has sens_i = 0, so its S_i is already 0 and is skipped.
+// S_i <- S_i * (sum_j T_ij ratio_j) / sens_i over the non-empty voxel rows
+// (an empty row has sens_i = 0, so its S_i is already 0).
 template <int GS>
-__device__ inline void mlem_update_rows(int64_t n_vox, const int64_t* __restrict__ rp,
-                                        const int32_t* __restrict__ col,
-                                        const float* __restrict__ val,
-                                        const double* __restrict__ ratio,
-                                        const double* __restrict__ sens, double* __restrict__ S) {
+__global__ __launch_bounds__(T256) void k_mlem_update(const RowRef* __restrict__ L, int64_t cap,
+                                                      const uint32_t* __restrict__ count,
+                                                      const int32_t* __restrict__ col,
+                                                      const float* __restrict__ val,
+                                                      const double* __restrict__ ratio,
+                                                      const double* __restrict__ sens,
+                                                      double* __restrict__ S) {
     const RowGroups<GS> G(blockIdx.x, gridDim.x);
-    sweep_rows(G, n_vox, [&](int64_t i, int64_t& lo, int64_t& hi) { lo = rp[i]; hi = rp[i + 1]; },
+    sweep_list(G, L, cap, count,
+               [&](int64_t, bool ok, const RowRef& r) {
+                   const int64_t i = ok ? r.row : 0;
+                   return double2{S[i], sens[i]};
+               },
                [&](int64_t k, bool ok) {
                    const double x = (double)val[k] * ratio[col[k]];
                    return ok ? x : 0.0;
                },
-               [&](int64_t i, int64_t, int64_t len, double b) {
-                   if (len > 0 && G.sub == 0) {
-                       const double si = sens[i];
-                       S[i] = si > 0.0 ? S[i] * b / si : 0.0;
-                   }
+               [&](int64_t, const RowRef& r, double2 ss, double b) {
+                   if (G.sub == 0) S[r.row] = ss.y > 0.0 ? ss.x * b / ss.y : 0.0;
                });
+}
+
+// ---- compact layout: row-length classes.  The non-empty rows are split by
+// length into four lists, rows of at most 4, 16, 64 entries and longer ones,
+// swept by groups of 1, 4, 16 and 64 lanes, one row per group and pass, so a
+// row of up to 4 GS entries takes one load round of its group and a long
+// row does not hold one lane for many rounds.  The group size, and with it
+// the summation order, depends only on the row's length.
+constexpr int N_CLASS = 4;
+
+__host__ __device__ inline int length_class(int64_t len) {
+    return len <= 4 ? 0 : len <= 16 ? 1 : len <= 64 ? 2 : 3;
+}
+
+// The most rows class c can hold, of n rows and at most nnz entries.
+__host__ __device__ inline int64_t class_capacity(int c, int64_t n, int64_t nnz) {
+    const int64_t min_len[N_CLASS] = {1, 5, 17, 65};
+    const int64_t m = nnz / min_len[c];
+    return m < n ? m : n;
+}
+
+// A listed row of the compact layout: its list position (the index of its
+// vector entries) and entry range.
+struct ClassRef {
+    int32_t q;
+    uint32_t lo;
+    int32_t len, pad;
+};
+
+struct ClassLists {
+    ClassRef* l[N_CLASS];
+    int64_t cap[N_CLASS];
+};
+
+// Exclusive prefix over the workgroup's 256 threads of x, and the total in
+// *all (wsum: 4 words of shared memory; the caller syncs before reusing it).
+__device__ inline uint64_t block_excl_scan(uint64_t x, uint64_t* wsum, uint64_t* all) {
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    uint64_t v = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(v, o, 64);
+        if (lane >= o) v += y;
+    }
+    if (lane == 63) wsum[w] = v;
+    __syncthreads();
+    uint64_t before = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < T256 / 64; ++i) {
+        if (i < w) before += wsum[i];
+        tot += wsum[i];
+    }
+    *all = tot;
+    return before + v - x;
+}
+
+// Class lists of one row list (L, length *count): each workgroup takes 4096
+// list entries at a time, counts them per class (four 16-bit fields of one
+// 64-bit word, scanned over the workgroup), appends each class's with one
+// atomic on cnt[c].  A count past a list's capacity (impossible for the
+// entry count checked on the device) sets the bad flag instead of writing.
+__global__ __launch_bounds__(T256) void k_mlem_classes(const RowRef* __restrict__ L,
+                                                       const uint32_t* __restrict__ count,
+                                                       ClassLists C, uint32_t* __restrict__ cnt,
+                                                       uint32_t* __restrict__ st) {
+    __shared__ uint64_t wsum[T256 / 64];
+    __shared__ uint32_t base_s[N_CLASS];
+    if (st[ST_BAD]) return;
+    const int64_t n = *count;
+    bool bad = false;
+    for (int64_t c0 = (int64_t)blockIdx.x * ROW_CHUNK; c0 < n; c0 += (int64_t)gridDim.x * ROW_CHUNK) {
+        uint64_t mine = 0;
+#pragma unroll
+        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+            const int64_t q = c0 + k * T256 + threadIdx.x;
+            if (q < n) mine += 1ull << (16 * length_class(L[q].len));
+        }
+        uint64_t all = 0;
+        uint64_t before = block_excl_scan(mine, wsum, &all);
+        if (threadIdx.x < N_CLASS) {
+            const uint32_t t = (uint32_t)((all >> (16 * threadIdx.x)) & 0xFFFF);
+            base_s[threadIdx.x] = t ? atomicAdd(&cnt[threadIdx.x], t) : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+            const int64_t q = c0 + k * T256 + threadIdx.x;
+            if (q < n) {
+                const RowRef r = L[q];
+                const int c = length_class(r.len);
+                const uint64_t slot = base_s[c] + ((before >> (16 * c)) & 0xFFFF);
+                before += 1ull << (16 * c);
+                if ((int64_t)slot < C.cap[c])
+                    C.l[c][slot] = ClassRef{(int32_t)q, (uint32_t)r.lo, r.len, 0};
+                else
+                    bad = true;
+            }
+        }
+        __syncthreads();     // wsum and base_s are rewritten for the next chunk
+    }
+    if (bad) atomicOr(&st[ST_BAD], 1u);
+}
+
+// One class's rows by groups of GS lanes (workgroup `block` of n_blocks for
+// this class), one row per group and pass; the first entry is loaded with
+// the list length.  aux(q) loads the row's own operands, done(q, aux, sum)
+// runs on the group's first lane.
+template <int GS, class Aux, class Term, class Done>
+__device__ inline void sweep_class(int64_t block, int64_t n_blocks, const ClassRef* __restrict__ L,
+                                   int64_t cap, const uint32_t* __restrict__ count, Aux aux, Term term,
+                                   Done done) {
+    const RowGroups<GS> G(block, n_blocks);
+    if (G.first >= cap) return;
+    ClassRef ref = L[G.first];
+    const uint32_t n32 = *count;
+    // both loads in flight before either is used (the compiler would
+    // otherwise issue the row's load only once the length test has passed)
+    asm volatile("" ::"v"(ref.q), "v"(ref.lo), "v"(ref.len), "s"(n32));
+    const int64_t n = n32;
+    for (int64_t r = G.first; r < n; r += G.step) {
+        if (r != G.first) ref = L[r];
+        const auto a = aux(ref.q);
+        const double sum = group_row_sum<GS>(ref.lo, (int64_t)ref.lo + ref.len, G.sub, term);
+        if (G.sub == 0) done(ref.q, a, sum);
+    }
+}
+
+// The four classes of one list in one launch: workgroups [b.x, b.y) sweep
+// class 0, [b.y, b.z) class 1, [b.z, b.w) class 2, [b.w, gridDim.x) class 3.
+template <class Aux, class Term, class Done>
+__device__ inline void sweep_classes(const ClassLists& C, const uint32_t* __restrict__ cnt, int4 b,
+                                     Aux aux, Term term, Done done) {
+    const int64_t k = blockIdx.x;
+    if (k < b.y) sweep_class<1>(k - b.x, b.y - b.x, C.l[0], C.cap[0], cnt + 0, aux, term, done);
+    else if (k < b.z) sweep_class<4>(k - b.y, b.z - b.y, C.l[1], C.cap[1], cnt + 1, aux, term, done);
+    else if (k < b.w) sweep_class<16>(k - b.z, b.w - b.z, C.l[2], C.cap[2], cnt + 2, aux, term, done);
+    else sweep_class<64>(k - b.w, (int64_t)gridDim.x - b.w, C.l[3], C.cap[3], cnt + 3, aux, term, done);
+}
+
+// Compact forward: ratio_q = P_q / (sum_k val_k S[col_k]) over the bin rows,
+// S, P, ratio in list order and col renumbered to voxel list positions.
+__global__ __launch_bounds__(T256) void k_mlem_forward_c(ClassLists C, const uint32_t* __restrict__ cnt,
+                                                         int4 b, const int32_t* __restrict__ col,
+                                                         const float* __restrict__ val,
+                                                         const double* __restrict__ S,
+                                                         const float* __restrict__ P,
+                                                         double* __restrict__ ratio) {
+    sweep_classes(C, cnt, b, [&](int32_t q) { return P[q]; },
+                  [&](int64_t k, bool ok) {
+                      const double x = (double)val[k] * S[col[k]];
+                      return ok ? x : 0.0;
+                  },
+                  [&](int32_t q, float p, double y) { ratio[q] = y > 0.0 ? (double)p / y : 0.0; });
+}
+
+// Compact update: S_q <- S_q (sum_k val_k ratio[col_k]) / sens_q over the
+// voxel rows, in list order, col renumbered to bin list positions.
+__global__ __launch_bounds__(T256) void k_mlem_update_c(ClassLists C, const uint32_t* __restrict__ cnt,
+                                                        int4 b, const int32_t* __restrict__ col,
+                                                        const float* __restrict__ val,
+                                                        const double* __restrict__ ratio,
+                                                        const double* __restrict__ sens,
+                                                        double* __restrict__ S) {
+    sweep_classes(C, cnt, b, [&](int32_t q) { return double2{S[q], sens[q]}; },
+                  [&](int64_t k, bool ok) {
+                      const double x = (double)val[k] * ratio[col[k]];
+                      return ok ? x : 0.0;
+                  },
+                  [&](int32_t q, double2 ss, double v) { S[q] = ss.y > 0.0 ? ss.x * v / ss.y : 0.0; });
 }
 
 // part[s][i] = sum over the entries of voxel row i in slice s of T_ij ratio_j,
 // slice s = blockIdx.x mod MLEM_SEGS (gridDim.x is a multiple of MLEM_SEGS).
 template <int GS>
-__device__ inline void mlem_back_slices(int64_t n_vox, const int64_t* __restrict__ sb,
-                                        const int32_t* __restrict__ col,
-                                        const float* __restrict__ val,
-                                        const double* __restrict__ ratio,
-                                        double* __restrict__ part) {
+__global__ __launch_bounds__(T256) void k_mlem_back_slices(int64_t n_vox,
+                                                           const int64_t* __restrict__ sb,
+                                                           const int32_t* __restrict__ col,
+                                                           const float* __restrict__ val,
+                                                           const double* __restrict__ ratio,
+                                                           double* __restrict__ part) {
     const int seg = (int)(blockIdx.x % MLEM_SEGS);
     const RowGroups<GS> G(blockIdx.x / MLEM_SEGS, gridDim.x / MLEM_SEGS);
     sweep_rows(G, n_vox,
@@ -722,42 +1074,12 @@ __device__ inline void mlem_back_slices(int64_t n_vox, const int64_t* __restrict
                });
 }
 
-__global__ __launch_bounds__(T256) void k_mlem_update(int64_t n_vox, int64_t n_bins,
-                                                      const int64_t* __restrict__ rp,
-                                                      const int32_t* __restrict__ col,
-                                                      const float* __restrict__ val,
-                                                      const double* __restrict__ ratio,
-                                                      const double* __restrict__ sens,
-                                                      double* __restrict__ S,
-                                                      const int64_t* __restrict__ sb,
-                                                      double* __restrict__ part) {
-    const int64_t nnz = rp[n_vox];
-    if (mlem_sliced(n_bins, nnz, n_vox)) {
-        switch (lanes_per_row(nnz, n_vox * MLEM_SEGS)) {
-            case 1: mlem_back_slices<1>(n_vox, sb, col, val, ratio, part); break;
-            case 4: mlem_back_slices<4>(n_vox, sb, col, val, ratio, part); break;
-            case 16: mlem_back_slices<16>(n_vox, sb, col, val, ratio, part); break;
-            default: mlem_back_slices<64>(n_vox, sb, col, val, ratio, part); break;
-        }
-        return;
-    }
-    switch (lanes_per_row(nnz, n_vox)) {
-        case 1: mlem_update_rows<1>(n_vox, rp, col, val, ratio, sens, S); break;
-        case 4: mlem_update_rows<4>(n_vox, rp, col, val, ratio, sens, S); break;
-        case 16: mlem_update_rows<16>(n_vox, rp, col, val, ratio, sens, S); break;
-        default: mlem_update_rows<64>(n_vox, rp, col, val, ratio, sens, S); break;
-    }
-}
-
 // Sliced backprojection, second half: S_i <- S_i * (sum_s part[s][i]) / sens_i.
-__global__ __launch_bounds__(T256) void k_mlem_combine(int64_t n_vox, int64_t n_bins,
-                                                       const int64_t* __restrict__ rp,
-                                                       const double* __restrict__ part,
+__global__ __launch_bounds__(T256) void k_mlem_combine(int64_t n_vox, const double* __restrict__ part,
                                                        const double* __restrict__ sens,
                                                        double* __restrict__ S) {
-    if (!mlem_sliced(n_bins, rp[n_vox], n_vox)) return;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * T256) {
         double b = 0.0;
 #pragma unroll
         for (int s = 0; s < MLEM_SEGS; ++s) b += part[(int64_t)s * n_vox + i];
@@ -766,11 +1088,26 @@ __global__ __launch_bounds__(T256) void k_mlem_combine(int64_t n_vox, int64_t n_
     }
 }
 
+// image_i = S_i (row order; vox_pos given: S in list order, 0 for an empty
+// row), NaN throughout when the bad flag of st (nullable) is set.
 __global__ __launch_bounds__(T256) void k_mlem_out(int64_t n_vox, const double* __restrict__ S,
+                                                   const int32_t* __restrict__ vox_pos,
+                                                   const uint32_t* __restrict__ st,
                                                    float* __restrict__ img) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
-         i += (int64_t)gridDim.x * blockDim.x)
-        img[i] = (float)S[i];
+    const bool bad = st && st[ST_BAD] != 0;
+    for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * T256) {
+        float v;
+        if (bad) {
+            v = __builtin_nanf("");
+        } else if (vox_pos) {
+            const int32_t p = vox_pos[i];
+            v = p >= 0 ? (float)S[p] : 0.0f;
+        } else {
+            v = (float)S[i];
+        }
+        img[i] = v;
+    }
 }
 
 // ---- ordered subsets (OSEM; dual matrix, Eq. DMOS; additive scatter, the
@@ -792,8 +1129,8 @@ __global__ __launch_bounds__(T256) void k_os_init(int64_t n_vox, int32_t n_sub,
                                                   const float* __restrict__ img,
                                                   const double* __restrict__ sens,
                                                   double* __restrict__ S) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vox;
-         i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < n_vox;
+         i += (int64_t)gridDim.x * T256) {
         double tot = 0.0;
         for (int k = 0; k < n_sub; ++k) tot += sens[(int64_t)k * n_vox + i];
         S[i] = tot > 0.0 ? (double)img[i] : 0.0;
@@ -924,7 +1261,7 @@ hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int
                                             ratio, sens, S);
         }
     }
-    k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, image);
+    k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, nullptr, nullptr, image);
     return hipGetLastError();
 }
 
@@ -1033,53 +1370,187 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
     return hipGetLastError();
 }
 
-size_t mlem_workspace(uint64_t n_bins, uint64_t n_vox) {
-    auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
-    size_t b = al(8 * n_vox) /* sens */ + al(8 * n_vox) /* S */ + al(8 * n_bins) /* ratio */;
-    if ((int64_t)n_bins >= MLEM_SEG_MIN_BINS)
-        b += al(8 * (MLEM_SEGS + 1) * n_vox) /* slice cuts */ + al(8 * MLEM_SEGS * n_vox) /* partials */;
-    return b;
+namespace {
+
+// Byte offsets of mlem_iterate's workspace, for n_bins x n_vox (every array
+// 256-byte aligned).  The compact layout's arrays are sized for its largest
+// entry count, n_bins + n_vox; the slice arrays exist for n_bins >= 2^19.
+struct MlemLayout {
+    size_t sens, S, ratio, bin_rows, vox_rows, st, sens_l, P_l, bin_pos, vox_pos, Tc, Ttc;
+    size_t cls[2][N_CLASS];
+    int64_t cls_cap[2][N_CLASS];
+    size_t sb, part, total;
+};
+
+MlemLayout mlem_layout(uint64_t nb, uint64_t nv) {
+    MlemLayout L{};
+    size_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        const size_t at = o;
+        o += (bytes + 255) & ~(uint64_t)255;
+        return at;
+    };
+    L.sens = take(8 * nv);
+    L.S = take(8 * nv);
+    L.ratio = take(8 * nb);
+    L.bin_rows = take(16 * nb);
+    L.vox_rows = take(16 * nv);
+    L.st = take(4 * ST_WORDS);
+    L.sens_l = take(8 * nv);
+    L.P_l = take(4 * nb);
+    L.bin_pos = take(4 * nb);
+    L.vox_pos = take(4 * nv);
+    L.Tc = take(4 * (nb + nv));
+    L.Ttc = take(4 * (nb + nv));
+    for (int c = 0; c < N_CLASS; ++c) {
+        L.cls_cap[0][c] = class_capacity(c, (int64_t)nb, (int64_t)(nb + nv));
+        L.cls_cap[1][c] = class_capacity(c, (int64_t)nv, (int64_t)(nb + nv));
+        L.cls[0][c] = take(16 * (uint64_t)L.cls_cap[0][c]);
+        L.cls[1][c] = take(16 * (uint64_t)L.cls_cap[1][c]);
+    }
+    if ((int64_t)nb >= MLEM_SEG_MIN_BINS) {
+        L.sb = take(8 * (MLEM_SEGS + 1) * nv);
+        L.part = take(8 * MLEM_SEGS * nv);
+    }
+    L.total = o;
+    return L;
 }
 
-hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, const int64_t* T_rp, const int32_t* T_col,
-                       const float* T_val, const int64_t* Tt_rp, const int32_t* Tt_col,
-                       const float* Tt_val, const float* proj, float* image, int32_t n_iter,
-                       void* workspace, hipStream_t s) {
-    auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+}  // namespace
+
+size_t mlem_workspace(uint64_t n_bins, uint64_t n_vox) { return mlem_layout(n_bins, n_vox).total; }
+
+namespace {
+
+// Workgroups for a sweep of at most `rows` rows by groups of gs lanes, four
+// rows per group and pass: one pass when the device holds it, else one
+// resident round (the sweeps are grid-strided; more workgroups would only
+// cost dispatch time and a ragged last round).
+template <class K>
+hipError_t sweep_grid(K kernel, int64_t rows, int gs, int n_cu, int* grid) {
+    int bpc = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, kernel, T256, 0);
+    if (e != hipSuccess) return e;
+    const uint64_t threads = ((uint64_t)std::max<int64_t>(rows, 1) + 3) / 4 * (uint64_t)gs;
+    *grid = grid_for(threads, T256, std::max(1, n_cu * bpc));
+    return hipSuccess;
+}
+
+template <class K>
+K by_group(int gs, K k1, K k4, K k16, K k64) {
+    return gs == 1 ? k1 : gs == 4 ? k4 : gs == 16 ? k16 : k64;
+}
+
+}  // namespace
+
+hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t* T_rp,
+                       const int32_t* T_col, const float* T_val, const int64_t* Tt_rp,
+                       const int32_t* Tt_col, const float* Tt_val, const float* proj, float* image,
+                       int32_t n_iter, void* workspace, hipStream_t s) {
+    const uint64_t nb = (uint64_t)n_bins, nv = (uint64_t)n_vox;
+    const MlemLayout Lo = mlem_layout(nb, nv);
     char* w = (char*)workspace;
-    double* sens = (double*)w;  w += al(8 * n_vox);
-    double* S = (double*)w;     w += al(8 * n_vox);
-    double* ratio = (double*)w; w += al(8 * n_bins);
-    // slicing is decided on the device from nnz; n_bins alone rules it out
-    const bool may_slice = n_bins >= MLEM_SEG_MIN_BINS;
-    int64_t* sb = nullptr;
-    double* part = nullptr;
-    if (may_slice) {
-        sb = (int64_t*)w;       w += al(8 * (MLEM_SEGS + 1) * (uint64_t)n_vox);
-        part = (double*)w;
-    }
-    const int gv = grid_for((uint64_t)n_vox, T256, 8192);
-    // The sweeps are grid-strided: one resident round of workgroups at most
-    // (more only costs dispatch time and a ragged last round).
-    int dev = 0, n_cu = 0, bpc_f = 0, bpc_u = 0;
+    double* sens = (double*)(w + Lo.sens);
+    double* S = (double*)(w + Lo.S);
+    double* ratio = (double*)(w + Lo.ratio);
+    RowRef* bin_rows = (RowRef*)(w + Lo.bin_rows);
+    RowRef* vox_rows = (RowRef*)(w + Lo.vox_rows);
+    uint32_t* st = (uint32_t*)(w + Lo.st);
+    // Layout: compact when the matrix is sparse (its renumbered columns fit
+    // the workspace), else bin slices on large detectors, else row order.
+    const bool compact = nnz <= n_bins + n_vox;
+    const bool sliced = !compact && mlem_sliced(n_bins, nnz, n_vox);
+    int dev = 0, n_cu = 0;
     hipError_t e;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_f, k_mlem_forward, T256, 0)) != hipSuccess)
-        return e;
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_u, k_mlem_update, T256, 0)) != hipSuccess)
-        return e;
-    const int gb = grid_for((uint64_t)n_bins, T256, std::max(1, n_cu * bpc_f));
-    const int gu = MLEM_SEGS * grid_for((uint64_t)n_vox, T256, std::max(1, n_cu * bpc_u / MLEM_SEGS));
+    const int gv = grid_for(nv, T256, 8192);
+    const int gr = grid_for((nb + ROW_CHUNK - 1) / ROW_CHUNK + (nv + ROW_CHUNK - 1) / ROW_CHUNK, 1, 2048);
     k_row_sums<<<gv, T256, 0, s>>>(n_vox, Tt_rp, Tt_val, sens);
-    k_mlem_init<<<gv, T256, 0, s>>>(n_vox, image, sens, S);
-    if (may_slice) k_mlem_slices<<<gv, T256, 0, s>>>(n_vox, n_bins, Tt_rp, Tt_col, sb);
-    for (int it = 0; it < n_iter; ++it) {
-        k_mlem_forward<<<gb, T256, 0, s>>>(n_bins, T_rp, T_col, T_val, S, proj, ratio);
-        k_mlem_update<<<gu, T256, 0, s>>>(n_vox, n_bins, Tt_rp, Tt_col, Tt_val, ratio, sens, S, sb, part);
-        if (may_slice) k_mlem_combine<<<gv, T256, 0, s>>>(n_vox, n_bins, Tt_rp, part, sens, S);
+    k_mlem_init<<<gv, T256, 0, s>>>(n_bins, n_vox, nnz, T_rp, Tt_rp, image, sens, S, st, compact ? 1 : 0);
+    if (compact) {
+        double* sens_l = (double*)(w + Lo.sens_l);
+        float* P_l = (float*)(w + Lo.P_l);
+        int32_t* bin_pos = (int32_t*)(w + Lo.bin_pos);
+        int32_t* vox_pos = (int32_t*)(w + Lo.vox_pos);
+        int32_t* Tc = (int32_t*)(w + Lo.Tc);
+        int32_t* Ttc = (int32_t*)(w + Lo.Ttc);
+        ClassLists cl[2];
+        for (int m = 0; m < 2; ++m)
+            for (int c = 0; c < N_CLASS; ++c) {
+                cl[m].l[c] = (ClassRef*)(w + Lo.cls[m][c]);
+                cl[m].cap[c] = Lo.cls_cap[m][c];
+            }
+        // Workgroups per class: one pass over the most rows the class can
+        // hold with nnz entries, at most one resident round.
+        int bpc_f = 0, bpc_u = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_f, k_mlem_forward_c, T256, 0)) != hipSuccess)
+            return e;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_u, k_mlem_update_c, T256, 0)) != hipSuccess)
+            return e;
+        auto ranges = [&](int64_t n_rows, int bpc, int4* b) {
+            const int gs[N_CLASS] = {1, 4, 16, 64};
+            int at = 0, start[N_CLASS];
+            for (int c = 0; c < N_CLASS; ++c) {
+                start[c] = at;
+                const uint64_t lanes = (uint64_t)class_capacity(c, n_rows, nnz) * gs[c];
+                at += grid_for(lanes, T256, std::max(1, n_cu * bpc));
+            }
+            *b = make_int4(start[0], start[1], start[2], start[3]);
+            return at;
+        };
+        int4 bf, bu;
+        const int gf = ranges(n_bins, bpc_f, &bf), gu = ranges(n_vox, bpc_u, &bu);
+        k_mlem_rows<<<gr, T256, 0, s>>>(n_bins, n_vox, T_rp, Tt_rp, bin_rows, vox_rows, bin_pos, vox_pos, st);
+        k_mlem_compact<<<grid_for(std::max<uint64_t>((uint64_t)nnz, std::max(nb, nv)), T256, 8192), T256, 0,
+                         s>>>(nnz, T_col, Tt_col, bin_pos, vox_pos, Tc, Ttc, bin_rows, vox_rows, image, sens,
+                              S, sens_l, proj, P_l, st);
+        const int gcb = grid_for((uint64_t)std::min<int64_t>(n_bins, nnz), ROW_CHUNK, 2048);
+        const int gcv = grid_for((uint64_t)std::min<int64_t>(n_vox, nnz), ROW_CHUNK, 2048);
+        k_mlem_classes<<<gcb, T256, 0, s>>>(bin_rows, st + ST_BINS, cl[0], st + ST_BIN_CLASS, st);
+        k_mlem_classes<<<gcv, T256, 0, s>>>(vox_rows, st + ST_VOXS, cl[1], st + ST_VOX_CLASS, st);
+        for (int it = 0; it < n_iter; ++it) {
+            k_mlem_forward_c<<<gf, T256, 0, s>>>(cl[0], st + ST_BIN_CLASS, bf, Tc, T_val, S, P_l, ratio);
+            k_mlem_update_c<<<gu, T256, 0, s>>>(cl[1], st + ST_VOX_CLASS, bu, Ttc, Tt_val, ratio, sens_l, S);
+        }
+        k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, vox_pos, st, image);
+        return hipGetLastError();
     }
-    k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, image);
+    int64_t* sb = sliced ? (int64_t*)(w + Lo.sb) : nullptr;
+    double* part = sliced ? (double*)(w + Lo.part) : nullptr;
+    // Group sizes from the mean row length over all rows that can be
+    // non-empty (at most nnz of them): the summation order depends only on
+    // the matrix.
+    const int64_t bin_rows_max = std::min(n_bins, std::max<int64_t>(nnz, 1));
+    const int64_t vox_rows_max = std::min(n_vox, std::max<int64_t>(nnz, 1));
+    const int gs_f = lanes_per_row(nnz, bin_rows_max);
+    const int gs_u = sliced ? lanes_per_row(nnz, n_vox * MLEM_SEGS) : lanes_per_row(nnz, vox_rows_max);
+    auto kf = by_group(gs_f, k_mlem_forward<1>, k_mlem_forward<4>, k_mlem_forward<16>, k_mlem_forward<64>);
+    auto ku = by_group(gs_u, k_mlem_update<1>, k_mlem_update<4>, k_mlem_update<16>, k_mlem_update<64>);
+    auto kb = by_group(gs_u, k_mlem_back_slices<1>, k_mlem_back_slices<4>, k_mlem_back_slices<16>,
+                       k_mlem_back_slices<64>);
+    int gb = 1, gu = 1;
+    if ((e = sweep_grid(kf, bin_rows_max, gs_f, n_cu, &gb)) != hipSuccess) return e;
+    if (sliced) {
+        // one grid of slices: workgroup b on slice b mod MLEM_SEGS
+        int per = 1;
+        if ((e = sweep_grid(kb, n_vox, gs_u, std::max(1, n_cu / MLEM_SEGS), &per)) != hipSuccess) return e;
+        gu = MLEM_SEGS * per;
+    } else if ((e = sweep_grid(ku, vox_rows_max, gs_u, n_cu, &gu)) != hipSuccess) {
+        return e;
+    }
+    k_mlem_rows<<<gr, T256, 0, s>>>(n_bins, n_vox, T_rp, Tt_rp, bin_rows, vox_rows, nullptr, nullptr, st);
+    if (sliced) k_mlem_slices<<<gv, T256, 0, s>>>(n_vox, n_bins, Tt_rp, Tt_col, sb);
+    for (int it = 0; it < n_iter; ++it) {
+        kf<<<gb, T256, 0, s>>>(bin_rows, n_bins, st + ST_BINS, T_col, T_val, S, proj, ratio);
+        if (sliced) {
+            kb<<<gu, T256, 0, s>>>(n_vox, sb, Tt_col, Tt_val, ratio, part);
+            k_mlem_combine<<<gv, T256, 0, s>>>(n_vox, part, sens, S);
+        } else {
+            ku<<<gu, T256, 0, s>>>(vox_rows, n_vox, st + ST_VOXS, Tt_col, Tt_val, ratio, sens, S);
+        }
+    }
+    k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, nullptr, st, image);
     return hipGetLastError();
 }
 

@@ -190,9 +190,34 @@ def test_simulate_rejects_bad_buffers_before_launch():
     assert ba(8, 8, 8, 8, 2, 8, 8, None) == mc.MC_EINVAL        # in place
     assert ba(8, 8, 8, 8, 0, 16, 8, None) == mc.MC_EINVAL
     assert ba(None, 8, 8, 8, 2, 16, 8, None) == mc.MC_EINVAL
-    assert ex(8, 0, 4, 4, 2, 16, None) == mc.MC_EINVAL
-    assert ex(8, 2, 4, 4, 0, 16, None) == mc.MC_EINVAL
-    assert ex(None, 2, 4, 4, 2, 16, None) == mc.MC_EINVAL
+    assert ex(8, 0, 4, 4, 2, 1.0, 16, None) == mc.MC_EINVAL
+    assert ex(8, 2, 4, 4, 0, 1.0, 16, None) == mc.MC_EINVAL
+    assert ex(None, 2, 4, 4, 2, 1.0, 16, None) == mc.MC_EINVAL
+    assert ex(8, 2, 4, 4, 2, float("nan"), 16, None) == mc.MC_EINVAL
+    # projection arithmetic and graph helpers: arguments checked before any launch
+    assert mc._lib.mc_source_total(None, None, 10, 8, None) == mc.MC_EINVAL
+    assert mc._lib.mc_source_total(8, None, 0, 8, None) == mc.MC_EINVAL
+    assert mc._lib.mc_scale_tally(8, 10, float("inf"), 8, 0, None) == mc.MC_EINVAL
+    assert mc._lib.mc_scale_tally(8, 10, 1.0, 8, 2, None) == mc.MC_EINVAL
+    assert mc._lib.mc_scale_tally(8, 0, 1.0, 8, 0, None) == mc.MC_EINVAL
+    assert mc._lib.mc_graph_begin(None) == mc.MC_EINVAL       # the legacy default stream
+    assert mc._lib.mc_graph_end(None, None) == mc.MC_EINVAL
+    assert mc._lib.mc_graph_launch(None, None) == mc.MC_EINVAL
+    assert mc._lib.mc_graph_destroy(None) == mc.MC_OK
+    # MLEM: sizes, entry count and workspace checked before any launch
+    ml = mc._lib.mlem_iterate
+    wsb = mc._lib.mlem_workspace_bytes(100, 50)
+    assert wsb > 0 and mc._lib.mlem_workspace_bytes(0, 50) == 0
+    args = lambda nb, nv, nnz, ws: (nb, nv, nnz, 8, 8, 8, 8, 8, 8, 8, 8, 3, 8, ws, None)
+    assert ml(*args(100, 50, -1, wsb)) == mc.MC_EINVAL
+    assert ml(*args(0, 50, 10, wsb)) == mc.MC_EINVAL
+    assert ml(*args(100, 1 << 31, 10, wsb)) == mc.MC_EINVAL
+    assert ml(*args(100, 50, 10, wsb - 1)) == mc.MC_ENOMEM
+    best = C.c_int32(7)
+    assert mc._lib.mc_autotune(C.byref(p), 1, None, 1, 1, 8, 8, 8, 8, need, None, C.byref(best),
+                               None) == mc.MC_EINVAL
+    assert mc._lib.mc_autotune(C.byref(p), 1, C.byref(o), 0, 1, 8, 8, 8, 8, need, None, C.byref(best),
+                               None) == mc.MC_EINVAL
     assert sim(None, 1, None, 8, None, 8, None, None, None, 0, None, 8, 8, need, None) == mc.MC_EINVAL
     assert mc._lib.mc_error_string(mc.MC_EINVAL) == b"invalid argument"
     assert mc._lib.mc_replay_histories(C.byref(p), None, None, None, 5, None, 8, 8, need, None) == mc.MC_EINVAL

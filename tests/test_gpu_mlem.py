@@ -99,8 +99,9 @@ def _mlem_vs_oracle(T, P, n_iter, m=None):
 
 @pytest.mark.parametrize("n_bins,n_vox,density", [
     (1000, 4000, 0.03),        # 120 entries per bin row (64 lanes), 30 per voxel row (16)
-    (600_000, 3000, 2e-5),     # large detector, 12 entries per voxel row: whole rows
-    (600_000, 3000, 1e-4),     # bin slices, 7.5 entries per slice (4 lanes)
+    (600_000, 3000, 2e-5),     # large detector, sparse: compact layout, 12 entries per voxel row
+    (600_000, 3000, 1e-4),     # compact layout, 60 entries per voxel row (16 lanes)
+    (600_000, 20_000, 6e-5),   # bin slices, 4.5 entries per slice (4 lanes)
     (600_000, 3000, 1e-3),     # bin slices, 75 entries per slice (64 lanes)
 ])
 def test_mlem_row_groups_and_bin_slices(n_bins, n_vox, density):
@@ -121,7 +122,7 @@ def test_mlem_bin_slices_unsorted_rows():
     the oracle's."""
     mc = _mc()
     import torch
-    T, truth = phantoms.random_system(600_000, 2000, 2e-4, seed=38)
+    T, truth = phantoms.random_system(600_000, 2000, 6e-4, seed=38)
     rng = np.random.Generator(np.random.PCG64(39))
     P = rng.poisson(T.astype(np.float64) @ truth * 20).astype(np.float32)
     m = mc.csr_from_scipy(T)
@@ -423,12 +424,12 @@ def test_system_matrix_list_edges(case):
 
 
 def test_mlem_bin_slices_edges():
-    """Bin-slice path (2^19 bins or more, 16+ entries per voxel row) with
-    voxels no bin sees: those stay 0; n_iter = 0 returns S^0 masked by the
+    """Bin-slice path (2^19 bins or more, 16+ entries per voxel row, more
+    entries than bins and voxels together) with voxels no bin sees: those stay 0; n_iter = 0 returns S^0 masked by the
     sensitivity; a non-uniform S^0 is followed as in the oracle."""
     mc = _mc()
     import torch
-    T, truth = phantoms.random_system(600_000, 2000, 2e-4, seed=41)
+    T, truth = phantoms.random_system(600_000, 2000, 6e-4, seed=41)
     T = T.tolil()
     T[:, 1500:1600] = 0.0                 # 100 voxels that no bin sees
     T = T.tocsr()

@@ -23,16 +23,30 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 N_CU, CLOCK_HZ = 256, 2.4e9
-PEAK_LANE_OPS = N_CU * 64 * CLOCK_HZ  # one 32-bit VALU operation per lane per clock
+PEAK_LANE_OPS = N_CU * 64 * CLOCK_HZ  # one 32-bit VALU instruction per lane per clock
 
-# Algorithmic 32-bit operation model per unit of work (lane operations counted
-# from the source of each step):
-OPS_PHILOX = 100          # 10 rounds x (2 lo + 2 hi products, 4 xor, 2 key adds)
-OPS_EMISSION = 50         # voxel pick (64-bit product, guide, search), position, direction
-OPS_STEP = 35             # flight length, move, inside test, voxel index, accept test
-OPS_KAHN = 20             # one rejection attempt
-OPS_SCATTER = 95          # kinematics, rotation, attenuation terms (FP64 counted twice)
-OPS_END = 35              # collimator, detector bin, window, bookkeeping
+# Algorithmic work per history: the method's operation table (Philox blocks,
+# transcendentals, other 32-bit operations per emission, per tentative
+# collision, per Kahn attempt and per real collision), with a Philox4x32-10
+# block counted as the 60 instructions it is in the library's gfx950
+# assembly (10 rounds x (2 v_mad_u64_u32 + 4 v_xor_b32); the key schedule is
+# scalar).  Counts come from the kernel's own work counters.
+OPS_PHILOX = 60
+TABLE = {            # (Philox blocks, transcendentals, other operations)
+    "emission": (2, 3, 20),          # voxel, position, sqrt/sin/cos direction
+    "tentative": (1, 1, 10),         # log flight, move, voxel, accept test
+    "kahn_attempt": (1, 0, 0),       # the attempt's Philox block (its test is counted per real collision)
+    "real": (0, 3, 40),              # branch, Kahn test, sqrt/sin/cos rotation, energy terms
+}
+
+
+def table_ops(n_hist, n_tent, n_kahn, n_real, cost=None):
+    """Operations of the table for these counts; cost: optional issue cost of
+    a Philox block, a transcendental and another operation (full-rate
+    slots), else one operation each (a Philox block = OPS_PHILOX)."""
+    ph, tr, ot = cost if cost else (OPS_PHILOX, 1.0, 1.0)
+    n = {"emission": n_hist, "tentative": n_tent, "kahn_attempt": n_kahn, "real": n_real}
+    return sum(n[k] * (p * ph + t * tr + o * ot) for k, (p, t, o) in TABLE.items())
 
 
 # HBM traffic of one transport launch on the headline workload, from rocprofv3
@@ -40,7 +54,11 @@ OPS_END = 35              # collimator, detector bin, window, bookkeeping
 # counters read for a plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); keyed
 # by a hash of the kernel sources so a changed kernel reports null.
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
-TRAFFIC_KIB = {"9d2b7c2f78f4efd5": {"fetch": 4687792.5625, "write": 5326.4375}}
+TRAFFIC_KIB = {"6444ebc0c4fdb25c": {"fetch": 5929.0, "write": 5326.25}}
+# rocprofv3 --pmc SQ_INSTS_VALU of the same launch (and the dispatch time of
+# that run), keyed like the traffic
+VALU_COUNTERS = {"6444ebc0c4fdb25c": {"workload": "thorax_128", "SQ_INSTS_VALU": 2.38873e9,
+                                      "kernel_ms": 4.6169}}
 
 
 def kernel_source_hash() -> str:
@@ -98,33 +116,128 @@ def issue_rates(torch, blocks=None, iters=20000):
             "cost_in_full_rate_slots": cost, "probe_ms": t, "blocks": blocks, "iters": iters}
 
 
-def ops_per_history(n_tent, n_kahn, n_scatter, n_hist):
-    per = (2 * (OPS_PHILOX) + OPS_EMISSION + OPS_END) * n_hist \
-        + n_tent * (OPS_PHILOX + OPS_STEP) + n_kahn * (OPS_PHILOX + OPS_KAHN) \
-        + n_scatter * OPS_SCATTER
-    return per / max(n_hist, 1)
+def transport_roofline(sim, k_ms, rates=None, kernel="k_transport", counters_key=None):
+    """ALU roofline of one transport launch from the work counters of all its
+    problems.  frac: the table's operations (one per instruction, a Philox
+    block = 60) per second over the nominal peak, 256 CU x 64 lanes x
+    2.4 GHz.  With measured issue rates (issue_rates): the shortest time the
+    same operations take at the rates the probes sustain (full-rate slots,
+    a v_mad_u64_u32 and a transcendental as measured) against the kernel
+    time, and, from the committed counter profile of this kernel build, the
+    VALU instructions it actually issued."""
+    cnt = sim.counters.cpu().numpy().astype(np.float64).sum(axis=0)
+    n_tent, n_real, n_kahn, n_hist = cnt
+    ops = table_ops(n_hist, n_tent, n_kahn, n_real)
+    achieved = ops / (k_ms / 1e3)
+    out = {"bound": "alu", "kernel": kernel, "kernel_ms": k_ms,
+           "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+           "unit": "Tops/s (32-bit lane ops, one per instruction)", "frac": achieved / PEAK_LANE_OPS,
+           "ops_per_history": ops / n_hist,
+           # the same table with a Philox block at 100 (the middle of the
+           # 80-120 range of a generic count) instead of its 60 gfx950 instructions
+           "frac_philox_100": table_ops(n_hist, n_tent, n_kahn, n_real, cost=(100, 1.0, 1.0))
+                              / (k_ms / 1e3) / PEAK_LANE_OPS,
+           "op_table": "per history: emission 2 Philox + 3 transcendental + 20; per tentative "
+                       "collision 1 Philox + log + 10; per Kahn attempt 1 Philox; per real collision "
+                       "3 transcendental + 40; Philox = 60 gfx950 instructions"}
+    if rates:
+        c = rates["cost_in_full_rate_slots"]
+        slots = table_ops(n_hist, n_tent, n_kahn, n_real,
+                          cost=(c["philox_block"], np.mean([c[k] for k in ("log", "sin", "sqrt", "rcp")]), 1.0))
+        t_min = slots / rates["full_rate_lane_ops_per_s"]
+        out["frac_of_measured_op_mix_peak"] = t_min / (k_ms / 1e3)
+        out["op_mix_slots_per_history"] = slots / n_hist
+    if counters_key:
+        pc = VALU_COUNTERS.get(kernel_source_hash())
+        if pc is not None and pc.get("workload") == counters_key:
+            issued = pc["SQ_INSTS_VALU"] * 64
+            out["issue_frac"] = issued / (pc["kernel_ms"] / 1e3) / PEAK_LANE_OPS
+            out["issued_valu_per_history"] = pc["SQ_INSTS_VALU"] * 64 / n_hist
+    return out
 
 
-def cpu_baseline(prob, target_s: float = 12.0):
-    """The FP64 oracle on the host cores, on a bounded sample of the workload."""
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(prob, mc, dp, torch, full_limit_s: float = 60.0, target_s: float = 12.0):
+    """The FP64 oracle on the host cores.  When the whole workload fits in
+    full_limit_s of wall time (estimated from a 1e6-history run) it is timed
+    on the whole workload, and that run is also the reference of the parity
+    block; otherwise on a bounded sample, and the parity block is left out."""
     import oracle
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    # calibrate on growing samples until one takes a second, then size the timed sample
-    n0 = 200_000
-    while True:
-        t = time.perf_counter()
-        oracle.simulate(prob.with_(n_histories=n0), n_threads=cores)
-        dt0 = time.perf_counter() - t
-        if dt0 > 1.0 or n0 >= prob.n_histories:
-            break
-        n0 = min(n0 * 8, prob.n_histories)
-    n = int(min(max(n0, n0 * target_s / max(dt0, 1e-3)), prob.n_histories))
+    n0 = min(10 ** 6, prob.n_histories)
     t = time.perf_counter()
-    oracle.simulate(prob.with_(n_histories=n), n_threads=cores)
-    dt = time.perf_counter() - t
-    return {"value": n / dt, "unit": "histories/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {n} histories of the same workload ({prob.n_views} views), "
-                      f"{dt:.1f} s wall on {cores} threads"}
+    oracle.simulate(prob.with_(n_histories=n0), n_threads=cores)
+    dt0 = time.perf_counter() - t
+    parity = None
+    if dt0 * prob.n_histories / n0 <= full_limit_s:
+        n = prob.n_histories
+        t = time.perf_counter()
+        o = oracle.simulate(prob, n_threads=cores, want_triplets=True,
+                            trip_cap=max(1 << 20, n // 1000))
+        dt = time.perf_counter() - t
+        sample = f"the whole workload ({n} histories, {prob.n_views} views)"
+        parity = headline_parity(prob, o, mc, dp, torch, cores)
+    else:
+        n = int(min(max(n0, n0 * target_s / max(dt0, 1e-3)), prob.n_histories))
+        t = time.perf_counter()
+        oracle.simulate(prob.with_(n_histories=n), n_threads=cores)
+        dt = time.perf_counter() - t
+        sample = f"first {n} histories of the same workload ({prob.n_views} views)"
+    return ({"value": n / dt, "unit": "histories/s", "cores": cores, "kind": "oracle",
+             "cpu_model": host_cpu_model(),
+             "sample": f"{sample}, {dt:.1f} s wall on {cores} threads; the oracle's plain "
+                       f"Woodcock walk (every history followed to the grid edge), FP64"},
+            parity)
+
+
+def headline_parity(prob, o, mc, dp, torch, cores, n_replay=100_000):
+    """Per-result errors of the GPU run against the oracle's run of the same
+    workload: relative error of the window total, of each class, of each
+    fate count and energy; tallied histories on one side only (the transport
+    kernel's event list against the oracle's tallied list); identical (fate,
+    bin, scatter count) fraction over n_replay ids drawn with numpy PCG64(7)."""
+    import oracle
+    T = int(o["fates"][5])
+    sim = mc.Simulator(dp, want_sq=False, event_capacity=2 * T + 1024)
+    sim.run()
+    torch.cuda.synchronize()
+    ev = sim.events_numpy()
+    tally = mc.tally_float(sim.tally).reshape(prob.tally_shape)
+    fates = sim.fates.cpu().numpy()[0]
+    energy = sim.energy.cpu().numpy()[0].astype(np.float64) / mc.Q23
+    gk = ev["work"].astype(np.int64) * (1 << 32) + ev["bin"].astype(np.int64)
+    ok = o["trip_g"].astype(np.int64) * (1 << 32) + o["trip_j"].astype(np.int64)
+    flipped = int(len(np.setdiff1d(gk, ok)) + len(np.setdiff1d(ok, gk)))
+    rel = lambda a, b: float(abs(a - b) / max(abs(b), 1.0))
+    rng = np.random.Generator(np.random.PCG64(7))
+    N, V = prob.n_histories, prob.n_views
+    g = np.sort(rng.choice(N, size=min(n_replay, N), replace=False))
+    q, r = divmod(N, V)
+    view = np.where(g < r * (q + 1), g // (q + 1), r + (g - r * (q + 1)) // q).astype(np.int32)
+    hist = np.where(g < r * (q + 1), g % (q + 1), (g - r * (q + 1)) % q).astype(np.uint64)
+    a = mc.replay(dp, view, hist)
+    b = oracle.replay(prob, view, hist, n_threads=cores)
+    same = ((a["fate"] == b["fate"]) & (a["iu"] == b["iu"]) & (a["iv"] == b["iv"])
+            & (a["n_scatter"] == b["n_scatter"]))
+    return {"reference": "FP64 oracle, same workload and random streams",
+            "tallied_histories": T, "tallied_on_one_side_only": flipped,
+            "window_total_rel": rel(tally.sum(), o["tally"].sum()),
+            "primary_rel": rel(tally[:, 0].sum(), o["tally"][:, 0].sum()),
+            "scatter_rel": rel(tally[:, 1].sum(), o["tally"][:, 1].sum()),
+            "bin_l1_rel": float(np.abs(tally - o["tally"]).sum() / max(o["tally"].sum(), 1.0)),
+            "fates_max_rel": max(rel(fates[i], o["fates"][i]) for i in range(7)),
+            "energy_max_rel": max(rel(energy[i], o["energy"][i]) for i in range(3)),
+            "replay_identical": float(same.mean()), "replayed": int(len(same)),
+            "replay_ids": "numpy PCG64(7), without replacement"}
 
 
 def main():
@@ -210,16 +323,11 @@ def main():
     value = n_hist / (ms_per_step / 1e3)
     cnt = sim.counters.cpu().numpy()[0].astype(np.float64)
     fates = sim.fates.cpu().numpy()[0]
-    # accepted scatters = real collisions that were not photoelectric absorptions
-    n_scatter = float(cnt[1] - fates[0])
-    ops_h = ops_per_history(cnt[0], cnt[2], n_scatter, cnt[3])
     k_ms = float(np.mean(kernel_ms))
-    achieved = ops_h * n_hist / (k_ms / 1e3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                "unit": "Tops/s (32-bit lane ops)", "frac": achieved / PEAK_LANE_OPS,
-                "traffic": traffic_bytes(), "traffic_unit": "bytes per launch",
-                "kernel": "k_transport", "kernel_ms": k_ms,
-                "ops_per_history": ops_h}
+    rates = issue_rates(torch)
+    roofline = transport_roofline(sim, k_ms, rates, counters_key="thorax_128")
+    roofline["traffic"] = traffic_bytes()
+    roofline["traffic_unit"] = "bytes per launch (HBM + MALL, from FETCH_SIZE/WRITE_SIZE)"
     rec = {
         "metric": "photon histories/s (128^3 thorax, 60 views) + adjoint μ-grad histories/s",
         "value": value, "unit": "histories/s", "n_gpus": 1, "steps": args.steps,
@@ -234,14 +342,16 @@ def main():
                         "tallied_fraction": float(fates[5]) / cnt[3]},
         "status": int(st[0]),
         "wall_s": wall,
+        "issue_rates": {"full_rate_lane_ops_per_s": rates["full_rate_lane_ops_per_s"],
+                        "cost_in_full_rate_slots": rates["cost_in_full_rate_slots"]},
     }
     if not args.no_extra:
-        rec["forms"] = extra_forms(mc, torch, args)
+        rec["forms"] = extra_forms(mc, torch, args, rates)
         a = rec["forms"].get("adjoint")
         if a:
             rec["adjoint_histories_per_s"] = a["value"]
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(prob)
+        rec["cpu_baseline"], rec["parity"] = cpu_baseline(prob, mc, dp, torch)
     print(json.dumps(rec))
 
 
@@ -259,7 +369,7 @@ def timed(torch, fn, steps):
     return e0.elapsed_time(e1) / steps
 
 
-def extra_forms(mc, torch, args):
+def extra_forms(mc, torch, args, rates=None):
     """Throughput of the other forms: the point-source cube, the batched graph
     launch over 32 uneven thoraxes, the adjoint (forward with event list +
     replaying gradient) on the 128^3 x 1 mm cube, forced detection on the
@@ -278,8 +388,8 @@ def extra_forms(mc, torch, args):
     out["point_cube_64"] = {"value": p1.n_histories / (ms / 1e3), "unit": "histories/s",
                             "ms_per_step": ms, "eager_ms_per_step": ms_eager,
                             "histories": p1.n_histories, "launch": "hipGraph replay of one call"}
-    out["batched"] = batched_form(mc, torch, steps)
-    out["adjoint"] = adjoint_form(mc, torch, steps)
+    out["batched"] = batched_form(mc, torch, steps, rates)
+    out["adjoint"] = adjoint_form(mc, torch, steps, rates)
     out["forced_detection"] = fd_form(mc, torch, steps)
     out["reuse_of_photon_tracks"] = rpt_form(mc, torch, steps)
     out["coarse_grid_scatter"] = cgsm_form(mc, torch, steps)
@@ -289,7 +399,7 @@ def extra_forms(mc, torch, args):
     return out
 
 
-def adjoint_form(mc, torch, steps):
+def adjoint_form(mc, torch, steps, rates=None):
     """Adjoint step on the 128^3 x 1 mm cube, 1e7 histories: forward with an
     event list, Poisson-loss gradient, replaying adjoint."""
     import phantoms
@@ -323,13 +433,13 @@ def adjoint_form(mc, torch, steps):
             "ms_per_step": ms, "forward_ms": ms_fwd, "adjoint_call_ms": ms_adj,
             "histories": p4.n_histories, "tallied": int(s4.n_events.item()),
             "step": "forward with event list + Poisson-loss gradient + replaying adjoint",
-            "roofline": transport_roofline(s4, k_fwd),
+            "roofline": transport_roofline(s4, k_fwd, rates),
             "roofline_note": "dominant kernel: the forward transport; the adjoint call replays "
                              "only the tallied histories, one wavefront each with the segment "
                              "walks split over its lanes, and reads its status back once"}
 
 
-def batched_form(mc, torch, steps):
+def batched_form(mc, torch, steps, rates=None):
     """32 thoraxes 96^3-160^3, 30-120 views, 1e7 histories each: staging of
     every problem and one persistent transport kernel, replayed as one HIP
     graph, with the autotuned options."""
@@ -351,20 +461,7 @@ def batched_form(mc, torch, steps):
     return {"value": n3 / (ms / 1e3), "unit": "histories/s", "ms_per_step": ms,
             "transport_ms": k_ms, "histories": n3, "problems": len(probs), "options": opts,
             "launch": "hipGraph replay: staging x32 + one persistent transport kernel",
-            "roofline": transport_roofline(s3, k_ms)}
-
-
-def transport_roofline(sim, k_ms):
-    """ALU roofline of one transport launch from the work counters of all its
-    problems (the operation model of the headline line)."""
-    cnt = sim.counters.cpu().numpy().astype(np.float64).sum(axis=0)
-    absorbed = float(sim.fates.cpu().numpy()[:, 0].sum())
-    ops_h = ops_per_history(cnt[0], cnt[2], cnt[1] - absorbed, cnt[3])
-    achieved = ops_h * cnt[3] / (k_ms / 1e3)
-    return {"bound": "alu", "kernel": "k_transport", "kernel_ms": k_ms,
-            "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "Tops/s (32-bit lane ops)", "frac": achieved / PEAK_LANE_OPS,
-            "ops_per_history": ops_h}
+            "roofline": transport_roofline(s3, k_ms, rates)}
 
 
 def fd_form(mc, torch, steps):
@@ -548,10 +645,12 @@ def large_fd(mc, torch, steps, p5):
         img.fill_(1.0)
         ml.run(img, 50)
     recon()
-    ms_mlem = timed(torch, recon, steps)
+    ms_eager = timed(torch, recon, steps)
+    ms_mlem = timed(torch, mc.Graph(recon).replay, steps)
     return {"histories": p.n_histories, "forward_ms": ms_fwd, "events": n_ev,
             "events_listed": min(n_ev, cap), "system_matrix_ms": ms_sys, "nnz": m.nnz,
-            "mlem_50_ms": ms_mlem, "histories_per_s": p.n_histories / (ms_fwd / 1e3)}
+            "mlem_50_ms": ms_mlem, "mlem_50_eager_ms": ms_eager,
+            "histories_per_s": p.n_histories / (ms_fwd / 1e3)}
 
 
 def large_form(mc, torch, steps):
@@ -574,7 +673,9 @@ def large_form(mc, torch, steps):
         img.fill_(1.0)
         ml.run(img, 50)
     recon()
-    ms_mlem = timed(torch, recon, steps)
+    ms_eager = timed(torch, recon, steps)
+    # the 50 iterations as one graph (mc_graph_begin / mc_graph_end)
+    ms_mlem = timed(torch, mc.Graph(recon).replay, steps)
     # OSEM: 8 subsets of interleaved views (15 of the 120 each), 10 iterations
     img_os = torch.ones(m.n_img, dtype=torch.float32, device="cuda")
 
@@ -587,7 +688,8 @@ def large_form(mc, torch, steps):
     fd = large_fd(mc, torch, steps, p5)
     return {"value": p5.n_histories / (ms_fwd / 1e3), "unit": "histories/s",
             "forward_ms": ms_fwd, "system_matrix_ms": ms_sys, "mlem_50_ms": ms_mlem,
-            "mlem_iteration_ms": ms_mlem / 50, "osem_8_subsets_10_iterations_ms": ms_os,
+            "mlem_iteration_ms": ms_mlem / 50, "mlem_eager_iteration_ms": ms_eager / 50,
+            "osem_8_subsets_10_iterations_ms": ms_os,
             "osem_iteration_ms": ms_os / 10, "histories": p5.n_histories,
             "tallied": n_tallied, "nnz": nnz,
             "bins": n_bins, "image_voxels": n_img, "forced_detection": fd}

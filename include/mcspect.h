@@ -58,8 +58,8 @@ enum {
     MC_EINVAL = -1,     /* invalid argument (host-visible)                    */
     MC_ENOMEM = -2,     /* workspace or output capacity too small             */
     MC_EDEVICE = -3,    /* a HIP call failed; see mc_last_hip_error()         */
-    MC_EOVERFLOW = -4,  /* reserved: fixed-point overflow reported by a check */
-    MC_ECAPPED = -5     /* reserved: some history hit max_steps               */
+    MC_EOVERFLOW = -4,  /* fixed-point overflow (mc_check_status)             */
+    MC_ECAPPED = -5     /* some history hit max_steps (mc_check_status)       */
 };
 
 /* Bits of status[0] (device int64 written by mc_simulate_projections). */
@@ -72,7 +72,11 @@ enum {
     MC_STATUS_GRAD_OVERFLOW = 32,/* a gradient term exceeded the fixed-point  */
                                  /* range at this frac_bits (term dropped)    */
     MC_STATUS_BAD_EVENT = 64,    /* an event did not replay to its bin        */
-    MC_STATUS_ACTIVITY_OVERFLOW = 128 /* a block activity sum exceeds 32 bits */
+    MC_STATUS_ACTIVITY_OVERFLOW = 128,/* a block activity sum exceeds 32 bits */
+    MC_STATUS_TALLY_OVERFLOW = 256    /* a tally bin may have left Q31.32: a     */
+                                      /* negative bin of a source of one sign, or */
+                                      /* 2^31 or more tallied histories of a      */
+                                      /* difference source (analog)               */
 };
 
 /* Fate counters, in this order: */
@@ -320,6 +324,12 @@ size_t mc_system_matrix_workspace_bytes(const mc_problem* problem, uint64_t even
  * c_ij is summed in Q31.32 integers, so the result does not depend on the
  * order of the list.
  * nnz = T_rowptr[n_bins] = Tt_rowptr[n_img] <= min(*n_events, capacity).
+ * A list that lost events (*n_events > capacity, read on the device) gives
+ * no matrix: every value of T_val, Tt_val and proj is written as NaN (the
+ * Python binding reads the count and raises instead).  The forward call must
+ * have covered the whole work range (history_offset 0, history_count 0 or
+ * n_histories): N_view is the view's share of n_histories; MC_EINVAL
+ * otherwise.
  * events / n_events / event_capacity: as returned by mc_simulate_projections
  * for this problem.  class_mask selects the tallied histories used: bit 0
  * primaries, bit 1 scattered photons (3: all; 1: the primary-only matrix a
@@ -459,6 +469,19 @@ int mc_graph_destroy(mc_graph graph);
 int mc_autotune(const mc_problem* problems, int32_t n_problems, const mc_options* candidates,
                 int32_t n_candidates, int32_t reps, int64_t* tally, int64_t* fates, int64_t* status,
                 void* workspace, size_t workspace_bytes, void* stream, int32_t* best, float* times_ms);
+
+/* The outcome a status array records, as a return code (synchronous: waits
+ * for `stream`, then reads status[0] from the device):
+ *   MC_EINVAL    bad device input (MC_STATUS_BAD_MU, _NO_ACTIVITY,
+ *                _BAD_ANGLE, _BAD_EVENT)
+ *   MC_EOVERFLOW a fixed-point sum left its range (_GRAD_OVERFLOW,
+ *                _TALLY_OVERFLOW, _ACTIVITY_OVERFLOW)
+ *   MC_ENOMEM    the event list was too small (_LIST_OVERFLOW)
+ *   MC_ECAPPED   some history stopped at max_steps (_CAPPED)
+ *   MC_OK        none of these
+ * in this order of precedence; MC_EDEVICE if the copy fails.
+ *   status  device int64 [>= 1], as written by the calls above */
+int mc_check_status(const int64_t* status, void* stream);
 
 /* Human-readable text for an MC_* code (static storage). */
 const char* mc_error_string(int code);

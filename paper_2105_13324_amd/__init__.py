@@ -29,7 +29,7 @@ _lib = C.CDLL(LIB_PATH)
 
 MC_OK, MC_EINVAL, MC_ENOMEM, MC_EDEVICE, MC_EOVERFLOW, MC_ECAPPED = 0, -1, -2, -3, -4, -5
 STATUS_BAD_MU, STATUS_NO_ACTIVITY, STATUS_BAD_ANGLE, STATUS_LIST_OVERFLOW, STATUS_CAPPED = 1, 2, 4, 8, 16
-STATUS_GRAD_OVERFLOW, STATUS_BAD_EVENT, STATUS_ACTIVITY_OVERFLOW = 32, 64, 128
+STATUS_GRAD_OVERFLOW, STATUS_BAD_EVENT, STATUS_ACTIVITY_OVERFLOW, STATUS_TALLY_OVERFLOW = 32, 64, 128, 256
 FATES = ["ABSORBED", "CUT", "ESCAPED", "ESCAPED_FOV", "OUT_OF_WINDOW", "TALLIED", "CAPPED", "SPARE"]
 Q32 = float(2 ** 32)   # tally fixed point: Q31.32
 Q23 = float(2 ** 23)   # energy fixed point: Q40.23 keV
@@ -42,7 +42,7 @@ EXPORTS = ["mc_workspace_bytes", "mc_simulate_projections", "mc_simulate_project
            "mlem_workspace_bytes", "mlem_iterate", "osem_workspace_bytes", "osem_iterate",
            "mc_block_activity", "mc_expand_projection", "mc_source_total", "mc_scale_tally",
            "mc_graph_begin", "mc_graph_end", "mc_graph_launch", "mc_graph_destroy", "mc_autotune",
-           "mc_error_string", "mc_last_hip_error"]
+           "mc_check_status", "mc_error_string", "mc_last_hip_error"]
 
 
 class McProblem(C.Structure):
@@ -130,6 +130,8 @@ _lib.mc_graph_destroy.restype = C.c_int
 _lib.mc_autotune.argtypes = [C.POINTER(McProblem), _i32, C.POINTER(McOptions), _i32, _i32, _vp, _vp, _vp,
                              _vp, _sz, _vp, C.POINTER(_i32), C.POINTER(C.c_float)]
 _lib.mc_autotune.restype = C.c_int
+_lib.mc_check_status.argtypes = [_vp, _vp]
+_lib.mc_check_status.restype = C.c_int
 _lib.mc_error_string.argtypes = [C.c_int]
 _lib.mc_error_string.restype = C.c_char_p
 _lib.mc_last_hip_error.argtypes = []
@@ -138,6 +140,10 @@ _lib.mc_last_hip_error.restype = C.c_int
 
 class McError(RuntimeError):
     pass
+
+
+class GradientOverflow(McError):
+    """A term of the adjoint's fixed-point sums exceeded its range."""
 
 
 def _check(rc: int, what: str):
@@ -357,9 +363,13 @@ class Simulator:
         _check(rc, "mc_simulate_projections_static")
 
     def check_status(self):
+        """mc_check_status on the call's status: raises McError for bad
+        device input or a tally that left its fixed-point range; returns the
+        status array (list overflow and capped histories are reported there)."""
+        rc = _lib.mc_check_status(self.status.data_ptr(), _stream_ptr())
         st = self.status.cpu().numpy()
-        if st[0] & (STATUS_BAD_MU | STATUS_NO_ACTIVITY | STATUS_BAD_ANGLE):
-            raise McError(f"invalid device input (status bits {int(st[0])})")
+        if rc in (MC_EINVAL, MC_EOVERFLOW, MC_EDEVICE):
+            raise McError(f"{_lib.mc_error_string(rc).decode()} (status bits {int(st[0])})")
         return st
 
     def tallies(self):
@@ -575,15 +585,32 @@ def fd_tally_sq_float(t) -> np.ndarray:
     return t.cpu().numpy().astype(np.float64) / Q52
 
 
+ADJOINT_FRAC_BITS = (40, 28, 16)
+
+
 def adjoint(problem: DeviceProblem, dL_dtally, sim: Optional[Simulator] = None,
-            frac_bits: int = 40, raw: bool = False, events: Optional[np.ndarray] = None):
+            frac_bits: Optional[int] = None, raw: bool = False, events: Optional[np.ndarray] = None):
     """dL/dmu (float64 tensor [nz, ny, nx]) for G = dL_dtally (tally layout).
 
     sim: the forward Simulator of the same problem; its event list (if it has
     one) restricts the replay to the tallied histories.  Without it every
     history of the range is replayed.  events: an explicit list of tallied
     histories (EVENT_DTYPE records, e.g. a subset of sim.events_numpy()) to
-    replay instead of sim's list."""
+    replay instead of sim's list.  frac_bits: fractional bits of the
+    fixed-point sums; None tries 40, 28 and 16 in turn, rerunning the call
+    with fewer bits when a term overflowed (MC_STATUS_GRAD_OVERFLOW); an
+    explicit value raises on overflow instead.  raw: the int64 sums (needs
+    an explicit frac_bits)."""
+    if frac_bits is None:
+        if raw:
+            raise McError("raw sums need an explicit frac_bits")
+        for fb in ADJOINT_FRAC_BITS:
+            try:
+                return adjoint(problem, dL_dtally, sim, fb, False, events)
+            except GradientOverflow:
+                if fb == ADJOINT_FRAC_BITS[-1]:
+                    raise
+        raise AssertionError("unreachable")
     torch = _torch()
     dev = problem.mu.device
     if events is not None:
@@ -628,7 +655,7 @@ def adjoint(problem: DeviceProblem, dL_dtally, sim: Optional[Simulator] = None,
     if st[0] & (STATUS_BAD_MU | STATUS_NO_ACTIVITY | STATUS_BAD_ANGLE):
         raise McError(f"invalid device input (status bits {int(st[0])})")
     if st[0] & STATUS_GRAD_OVERFLOW:
-        raise McError(f"gradient overflow at frac_bits={frac_bits}; use fewer fractional bits")
+        raise GradientOverflow(f"gradient overflow at frac_bits={frac_bits}; use fewer fractional bits")
     if st[0] & STATUS_BAD_EVENT:
         raise McError("an event did not replay to its bin (event list from another problem?)")
     if events is None and use_events and int(sim.n_events.item()) > sim.event_capacity:
@@ -644,7 +671,7 @@ class MCProject:
     are constants."""
 
     @staticmethod
-    def apply(mu, problem: DeviceProblem, event_capacity: int = 1 << 20, frac_bits: int = 40):
+    def apply(mu, problem: DeviceProblem, event_capacity: int = 1 << 20, frac_bits: Optional[int] = None):
         return _mc_project_fn().apply(mu, problem, event_capacity, frac_bits)
 
 
@@ -824,6 +851,10 @@ def system_matrix(problem: DeviceProblem, sim: Simulator, classes: str = "all") 
     torch = _torch()
     if sim.events is None:
         raise McError("the forward run kept no event list")
+    n_ev = int(sim.n_events.reshape(-1)[0].item())
+    if n_ev > sim.event_capacity:
+        raise McError(f"the event list lost events ({n_ev} tallied, capacity {sim.event_capacity}): "
+                      "rerun the forward call with a larger event_capacity")
     if problem.image_factor < 1:
         raise McError("problem.image_factor must be >= 1")
     dev = problem.mu.device

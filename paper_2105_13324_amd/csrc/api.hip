@@ -334,6 +334,7 @@ int simulate_impl(const mc_problem* problems, int32_t n_problems, const mc_optio
     if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return hip_fail(e);
     for (int i = 0; cfd && i < (int)hd.size(); ++i)
         if ((e = launch_cfd_convolve(d_desc + i, hd[i], tally, st)) != hipSuccess) return hip_fail(e);
+    if ((e = launch_tally_check(d_desc, n_problems, tally, fates, status, st)) != hipSuccess) return hip_fail(e);
     return MC_OK;
 }
 
@@ -474,6 +475,11 @@ int mc_system_matrix(const mc_problem* problem, const mc_event* events, const ui
         return MC_EINVAL;
     if (!check_problem(*problem) || problem->image_factor < 1) return MC_EINVAL;
     if (problem->activity_prev) return MC_EINVAL;   // normalised by a plain source's activity
+    // N_view is the view's share of all n_histories: the forward call must
+    // have covered the whole work range
+    if (problem->history_offset != 0 ||
+        (problem->history_count != 0 && problem->history_count != problem->n_histories))
+        return MC_EINVAL;
     if (event_capacity < 1 || event_capacity >= (1ull << 31)) return MC_EINVAL;
     if (class_mask < 1 || class_mask > 3) return MC_EINVAL;
     const mc_problem& p = *problem;
@@ -674,6 +680,21 @@ int mc_autotune(const mc_problem* problems, int32_t n_problems, const mc_options
     (void)hipEventDestroy(ev[1]);
     (void)st;
     return rc;
+}
+
+int mc_check_status(const int64_t* status, void* stream) {
+    if (!status) return MC_EINVAL;
+    int64_t st = 0;
+    hipError_t e = hipMemcpyAsync(&st, status, sizeof(st), hipMemcpyDeviceToHost, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    if (st & (MC_STATUS_BAD_MU | MC_STATUS_NO_ACTIVITY | MC_STATUS_BAD_ANGLE | MC_STATUS_BAD_EVENT))
+        return MC_EINVAL;
+    if (st & (MC_STATUS_GRAD_OVERFLOW | MC_STATUS_TALLY_OVERFLOW | MC_STATUS_ACTIVITY_OVERFLOW))
+        return MC_EOVERFLOW;
+    if (st & MC_STATUS_LIST_OVERFLOW) return MC_ENOMEM;
+    if (st & MC_STATUS_CAPPED) return MC_ECAPPED;
+    return MC_OK;
 }
 
 const char* mc_error_string(int code) {

@@ -118,12 +118,13 @@ constexpr int MAX_AXIS = 1024;      // voxel indices are packed 10 bits per axis
 constexpr int SCAN_THREADS = 256;
 
 // Index of voxel (ix, iy, iz) in the threshold array: linear for b = 0, else
-// brick-major over nbx x nby x nbz bricks of 2^b voxels per side.
-__host__ __device__ inline uint32_t brick_index(uint32_t ix, uint32_t iy, uint32_t iz, uint32_t nx,
-                                                uint32_t ny, int b, uint32_t m, uint32_t nbx,
-                                                uint32_t nby) {
-    if (b == 0) return ix + nx * (iy + ny * iz);
-    const uint32_t brick = ((iz >> b) * nby + (iy >> b)) * nbx + (ix >> b);
+// brick-major over nbx x nby x nbz bricks of 2^b voxels per side.  Every
+// factor is below 2^24 (axes of at most 1024 voxels), so the products take
+// the full-rate 24-bit multiplier.
+__device__ inline uint32_t brick_index(uint32_t ix, uint32_t iy, uint32_t iz, uint32_t nx,
+                                       uint32_t ny, int b, uint32_t m, uint32_t nbx, uint32_t nby) {
+    if (b == 0) return ix + __umul24(nx, iy + __umul24(ny, iz));
+    const uint32_t brick = __umul24(__umul24(iz >> b, nby) + (iy >> b), nbx) + (ix >> b);
     const uint32_t local = (((iz & m) << b | (iy & m)) << b) | (ix & m);
     return (brick << (3 * b)) | local;
 }
@@ -189,6 +190,10 @@ struct TransportArgs {
 };
 constexpr int32_t VR_FORCED_DIRECTION = 1, VR_FORCED_INTERACTION = 2;
 hipError_t launch_transport(const TransportArgs& a, int grid, int block, hipStream_t s);
+// After every tally writer of a forward call: MC_STATUS_TALLY_OVERFLOW when a
+// problem's tally may have left the Q31.32 range.
+hipError_t launch_tally_check(const ProbDesc* d_desc, int n_problems, const int64_t* tally,
+                              const int64_t* fates, int64_t* status, hipStream_t s);
 hipError_t launch_replay(const ProbDesc* d_desc, const int32_t* views, const uint64_t* hists,
                          int64_t n, mc_record* out, int64_t* status, int block, int32_t vr_flags,
                          float vr_omc, hipStream_t s);

@@ -444,6 +444,8 @@ __global__ __launch_bounds__(T256) void k_emit_runs(SysArgs a, int transpose,
     const uint64_t n_valid = start[n_rows];
     const double total = (double)*total_p;
     const uint64_t mask = (1ull << col_bits) - 1ull;
+    // a list that lost events (count above the capacity) gives no matrix
+    const bool lost = *a.n_events > a.capacity;
     for (uint64_t i = (uint64_t)blockIdx.x * T256 + threadIdx.x; i < n_valid;
          i += (uint64_t)gridDim.x * T256) {
         const uint64_t k = keys[i];
@@ -458,19 +460,22 @@ __global__ __launch_bounds__(T256) void k_emit_runs(SysArgs a, int transpose,
         const double n_i = n_view * (double)a_img[img] / total;
         const uint64_t o = head_pos[i];
         col[o] = (int32_t)c;
-        val[o] = (float)((double)cw * 0x1p-32 / n_i);
+        val[o] = lost ? __builtin_nanf("") : (float)((double)cw * 0x1p-32 / n_i);
     }
 }
 
-// P_j = the summed weight of bin row j's events (all its items)
+// P_j = the summed weight of bin row j's events (all its items); NaN when
+// the list lost events
 __global__ __launch_bounds__(T256) void k_proj_rows(const int64_t* __restrict__ w,
                                                     const uint64_t* __restrict__ start,
-                                                    uint64_t n_rows, float* __restrict__ proj) {
+                                                    uint64_t n_rows, const unsigned long long* n_events,
+                                                    uint64_t capacity, float* __restrict__ proj) {
+    const bool lost = *n_events > capacity;
     for (uint64_t r = (uint64_t)blockIdx.x * T256 + threadIdx.x; r < n_rows;
          r += (uint64_t)gridDim.x * T256) {
         long long tot = 0;
         for (uint64_t i = start[r]; i < start[r + 1]; ++i) tot += w[i];
-        proj[r] = (float)((double)tot * 0x1p-32);
+        proj[r] = lost ? __builtin_nanf("") : (float)((double)tot * 0x1p-32);
     }
 }
 
@@ -1365,7 +1370,8 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
                                         transpose ? Tt_col : T_col, transpose ? Tt_val : T_val,
                                         a_img, total);
         if (!transpose && proj)
-            k_proj_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(w, L.start, n_rows, proj);
+            k_proj_rows<<<grid_for(n_rows, T256, 8192), T256, 0, s>>>(w, L.start, n_rows, n_events, capacity,
+                                                                      proj);
     }
     return hipGetLastError();
 }

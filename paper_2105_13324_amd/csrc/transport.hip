@@ -525,6 +525,34 @@ __global__ void k_finalize(const ProbDesc* __restrict__ descs, int n_problems, i
     status[2] = n_pal;
 }
 
+// Tally range check, TALLY_CHECK_BLOCKS workgroups per problem.  A source
+// of one sign adds weights of one sign (at most 2^32 each), so a bin that
+// crossed 2^63 reads negative: any negative bin is an overflow.  A
+// difference source adds both signs; its analog bins stay in range while
+// fewer than 2^31 histories are tallied in all (each adds +-2^32), which is
+// what is checked for it (its forced-detection and weighted forms are not
+// checked: each history then scores up to one weight per collision).
+constexpr int TALLY_CHECK_BLOCKS = 16;
+
+__global__ __launch_bounds__(256) void k_tally_check(const ProbDesc* __restrict__ descs,
+                                                     const int64_t* __restrict__ tally,
+                                                     const int64_t* __restrict__ fates,
+                                                     int64_t* status) {
+    const int p = blockIdx.x / TALLY_CHECK_BLOCKS, part = blockIdx.x % TALLY_CHECK_BLOCKS;
+    const ProbDesc& d = descs[p];
+    bool bad = false;
+    if (d.act_prev) {
+        bad = part == 0 && threadIdx.x == 0 && fates[(size_t)p * MC_N_FATES + MC_TALLIED] >= (1ll << 31);
+    } else {
+        const uint64_t n = (uint64_t)d.n_views * 2u * (uint64_t)d.nv * (uint64_t)d.nu;
+        const int64_t* t = tally + d.tally_offset;
+        for (uint64_t i = (uint64_t)part * 256 + threadIdx.x; i < n; i += TALLY_CHECK_BLOCKS * 256)
+            bad |= t[i] < 0;
+    }
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0)
+        atomicOr((unsigned long long*)status, (unsigned long long)MC_STATUS_TALLY_OVERFLOW);
+}
+
 __global__ void k_zero_status(int64_t* status) {
     if (blockIdx.x == 0 && threadIdx.x < 4) status[threadIdx.x] = 0;
 }
@@ -541,6 +569,12 @@ hipError_t launch_prepare_call(const ProbDesc* descs, int32_t n_problems, uint64
     if (g > 4096) g = 4096;
     k_prepare<<<(int)g, 256, 0, s>>>(descs, n_problems, work_prefix, chunk, state, status, n_events,
                                      tally, tally_elems, tally_sq, fates, energy, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_tally_check(const ProbDesc* d_desc, int n_problems, const int64_t* tally,
+                              const int64_t* fates, int64_t* status, hipStream_t s) {
+    k_tally_check<<<n_problems * TALLY_CHECK_BLOCKS, 256, 0, s>>>(d_desc, tally, fates, status);
     return hipGetLastError();
 }
 

@@ -170,6 +170,13 @@ def test_simulate_rejects_bad_buffers_before_launch():
     q.image_factor = 2
     assert mc._lib.mc_system_matrix(C.byref(q), 8, 8, 16, 3, 8, 8, 8, 8, 8, 8, None, 8,
                                     1 << 30, None) == mc.MC_EINVAL
+    # the response matrix normalises by the whole acquisition: a forward call
+    # over part of the work range is refused
+    for off, cnt in ((5, 0), (0, 600), (500, 500)):
+        r = _good()
+        r.image_factor, r.history_offset, r.history_count = 2, off, cnt
+        assert mc._lib.mc_system_matrix(C.byref(r), 8, 8, 16, 3, 8, 8, 8, 8, 8, 8, None, 8,
+                                        1 << 30, None) == mc.MC_EINVAL, (off, cnt)
     # weighted analog transport: flags 0..3, a forced-direction cone, not
     # with forced detection, not for the adjoint
     for kw in (dict(variance_reduction=4), dict(variance_reduction=-1),
@@ -204,6 +211,7 @@ def test_simulate_rejects_bad_buffers_before_launch():
     assert mc._lib.mc_graph_end(None, None) == mc.MC_EINVAL
     assert mc._lib.mc_graph_launch(None, None) == mc.MC_EINVAL
     assert mc._lib.mc_graph_destroy(None) == mc.MC_OK
+    assert mc._lib.mc_check_status(None, None) == mc.MC_EINVAL
     # MLEM: sizes, entry count and workspace checked before any launch
     ml = mc._lib.mlem_iterate
     wsb = mc._lib.mlem_workspace_bytes(100, 50)

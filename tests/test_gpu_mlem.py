@@ -372,7 +372,8 @@ def test_system_matrix_row_length_classes():
 def test_system_matrix_list_edges(case):
     """Event-list edge cases of the response-matrix build against the oracle:
     an empty list (every row pointer 0, P = 0); a device-side count above the
-    capacity (only the first `capacity` events count); slots past the count
+    capacity (the binding raises; through the C ABI every value and P_j is
+    NaN: a list that lost events gives no matrix); slots past the count
     holding garbage (never read); the primary-only and scatter-only classes;
     every event on one (voxel, bin) key (one run across all radix tiles); a
     list in descending key order."""
@@ -405,6 +406,30 @@ def test_system_matrix_list_edges(case):
     sim = types.SimpleNamespace(events=raw, event_capacity=cap,
                                 n_events=torch.tensor([n_ev], dtype=torch.int64, device="cuda"))
     classes = case if case in ("primary", "scatter") else "all"
+    if case == "over_capacity":
+        import ctypes as C
+        with pytest.raises(mc.McError, match="lost events"):
+            mc.system_matrix(mc.to_device(p), sim)
+        dp = mc.to_device(p)
+        arr = dp.c_struct()
+        nb = mc._lib.mc_system_matrix_workspace_bytes(C.byref(arr), cap)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        n_bins, n_img = p.n_views * p.nv * p.nu, (p.nx // 2) * (p.ny // 2) * (p.nz // 2)
+        T_rp = torch.empty(n_bins + 1, dtype=torch.int64, device="cuda")
+        Tt_rp = torch.empty(n_img + 1, dtype=torch.int64, device="cuda")
+        T_col, Tt_col = (torch.empty(cap, dtype=torch.int32, device="cuda") for _ in range(2))
+        T_val, Tt_val = (torch.empty(cap, dtype=torch.float32, device="cuda") for _ in range(2))
+        proj = torch.empty(n_bins, dtype=torch.float32, device="cuda")
+        rc = mc._lib.mc_system_matrix(C.byref(arr), raw.data_ptr(), sim.n_events.data_ptr(), cap, 3,
+                                      T_rp.data_ptr(), T_col.data_ptr(), T_val.data_ptr(),
+                                      Tt_rp.data_ptr(), Tt_col.data_ptr(), Tt_val.data_ptr(),
+                                      proj.data_ptr(), ws.data_ptr(), nb, mc._stream_ptr())
+        assert rc == mc.MC_OK
+        nnz = int(T_rp[-1].item())
+        assert nnz > 0 and int(Tt_rp[-1].item()) == nnz
+        assert torch.isnan(T_val[:nnz]).all() and torch.isnan(Tt_val[:nnz]).all()
+        assert torch.isnan(proj).all()
+        return
     m = mc.system_matrix(mc.to_device(p), sim, classes=classes)
     mx = p.nx // p.image_factor
     f = p.image_factor

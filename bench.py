@@ -40,6 +40,18 @@ TABLE = {            # (Philox blocks, transcendentals, other operations)
 }
 
 
+# Forced copies (Sec. 5.2): per copy whose ray is walked to the detector, a
+# Philox block (the cone direction), 6 transcendentals (sin, cos and sqrt of
+# the rotation, two reciprocals of the Klein-Nishina density, the
+# attenuation exponential) and ~60 other operations (rotation, density,
+# detector hit and bin, tally); per voxel the walk visits, ~8 (next plane:
+# min of three, axis select, parameter and index update, exit test; the
+# path-length product) and one 4-byte mu gather from L2.
+OPS_PER_RAY = (1, 6, 60)
+OPS_PER_VOXEL = 8
+BYTES_PER_VOXEL = 4
+
+
 def table_ops(n_hist, n_tent, n_kahn, n_real, cost=None):
     """Operations of the table for these counts; cost: optional issue cost of
     a Philox block, a transcendental and another operation (full-rate
@@ -153,6 +165,28 @@ def transport_roofline(sim, k_ms, rates=None, kernel="k_transport", counters_key
             issued = pc["SQ_INSTS_VALU"] * 64
             out["issue_frac"] = issued / (pc["kernel_ms"] / 1e3) / PEAK_LANE_OPS
             out["issued_valu_per_history"] = pc["SQ_INSTS_VALU"] * 64 / n_hist
+    return out
+
+
+def forced_roofline(sim, k_ms, kernel):
+    """ALU roofline of a forced-detection or weighted transport launch: the
+    analog table for its histories plus, for forced copies, OPS_PER_RAY per
+    walked ray and OPS_PER_VOXEL per visited voxel (counters 4 and 5), over
+    the nominal peak."""
+    cnt = sim.counters.cpu().numpy().astype(np.float64).sum(axis=0)
+    n_tent, n_real, n_kahn, n_hist, rays, voxels = cnt[:6]
+    ops = table_ops(n_hist, n_tent, n_kahn, n_real)
+    ph, tr, ot = OPS_PER_RAY
+    ops += rays * (ph * OPS_PHILOX + tr + ot) + voxels * OPS_PER_VOXEL
+    achieved = ops / (k_ms / 1e3)
+    out = {"bound": "alu", "kernel": kernel, "kernel_ms": k_ms, "achieved": achieved / 1e12,
+           "peak": PEAK_LANE_OPS / 1e12, "unit": "Tops/s (32-bit lane ops, one per instruction)",
+           "frac": achieved / PEAK_LANE_OPS, "ops_per_history": ops / n_hist}
+    if rays:
+        out.update({"rays_per_history": rays / n_hist, "voxels_per_ray": voxels / rays,
+                    "ray_unit": "voxel crossing: %d ops, %d B (mu gather, L2)" % (OPS_PER_VOXEL, BYTES_PER_VOXEL),
+                    "crossings_per_s": voxels / (k_ms / 1e3),
+                    "mu_gather_GBps": voxels * BYTES_PER_VOXEL / (k_ms / 1e3) / 1e9})
     return out
 
 
@@ -504,6 +538,9 @@ def fd_form(mc, torch, steps):
         torch.cuda.synchronize()
         k_ms = float(np.mean([t.elapsed_ms() for t in timers]))
         nz = int((sf.tally != 0).sum().item())
+        kname = {"forced_detection": "k_transport_fd", "convolution_fd": "k_transport_cfd"}.get(
+            name, "k_transport_vr")
+        roof = forced_roofline(sf, k_ms, kname)
         del sf
         tallies = []
         for k in range(16):
@@ -521,7 +558,7 @@ def fd_form(mc, torch, steps):
                      "variance_per_history": var, "bin_variance_per_history": bins,
                      "fom_gain": (var_an * t_an) / (var * t_f),
                      "bin_fom_gain": (bins_an * t_an) / (bins * t_f),
-                     "nonzero_bins": nz}
+                     "nonzero_bins": nz, "roofline": roof}
     fd = out.pop("forced_detection")
     fd.update({"analog_ms_per_step": ms_an, "analog_window_count_per_history": p_an,
                "analog_variance_per_history": var_an, "analog_bin_variance_per_history": bins_an,

@@ -79,6 +79,8 @@ enum {
                                       /* difference source (analog)               */
 };
 
+enum { MC_N_COUNTERS = 8 };   /* work counters per problem */
+
 /* Fate counters, in this order: */
 enum { MC_ABSORBED = 0, MC_CUT = 1, MC_ESCAPED = 2, MC_ESCAPED_FOV = 3,
        MC_OUT_OF_WINDOW = 4, MC_TALLIED = 5, MC_CAPPED_FATE = 6, MC_N_FATES = 8 };
@@ -204,8 +206,11 @@ size_t mc_workspace_bytes(const mc_problem* problems, int32_t n_problems,
  *   fates      device int64 [n_problems][8]; overwritten
  *   energy     device int64 [n_problems][4], Q40.23 keV: deposited, escaped,
  *              capped, 0; nullable
- *   counters   device int64 [n_problems][4]: tentative collisions, real
- *              collisions, Kahn attempts, histories; nullable
+ *   counters   device int64 [n_problems][MC_N_COUNTERS]: tentative
+ *              collisions, real collisions, Kahn attempts, histories, then
+ *              (forced detection) the forced copies whose ray was walked to
+ *              the detector and the voxels those walks visited, 0, 0;
+ *              nullable
  *   events     device mc_event [event_capacity], tallied histories in no
  *              particular order; nullable
  *   n_events   device uint64 [1], number of tallied histories (may exceed the

@@ -319,7 +319,7 @@ class Simulator:
         self.tally_sq = torch.zeros(total, dtype=torch.int64, device=dev) if want_sq else None
         self.fates = torch.zeros((n, 8), dtype=torch.int64, device=dev)
         self.energy = torch.zeros((n, 4), dtype=torch.int64, device=dev)
-        self.counters = torch.zeros((n, 4), dtype=torch.int64, device=dev)
+        self.counters = torch.zeros((n, 8), dtype=torch.int64, device=dev)
         self.status = torch.zeros(4, dtype=torch.int64, device=dev)
         self.event_capacity = int(event_capacity)
         self.events = (torch.zeros((max(self.event_capacity, 1), 3), dtype=torch.int64, device=dev)

@@ -554,11 +554,13 @@ struct FdPoint {
 // gathers together, so the gathers' latencies overlap.
 constexpr int RAY_BATCH = 8;
 
-__device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox, float oy, float oz) {
+__device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox, float oy, float oz,
+                               uint32_t& pieces) {
     const float px = x + C.hx, py = y + C.hy, pz = z + C.hz;
     int ix = min(max((int)(px * C.inv_vox), 0), C.nx - 1);
     int iy = min(max((int)(py * C.inv_vox), 0), C.ny - 1);
     int iz = min(max((int)(pz * C.inv_vox), 0), C.nz - 1);
+    const int ix0 = ix, iy0 = iy, iz0 = iz;
     const float inf = __builtin_huge_valf();
     const int sx = ox > 0.0f ? 1 : -1, sy = oy > 0.0f ? 1 : -1, sz = oz > 0.0f ? 1 : -1;
     float tx = ox != 0.0f ? fmaxf(((float)(ix + (ox > 0.0f)) * C.vox - px) / ox, 0.0f) : inf;
@@ -614,6 +616,9 @@ __device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox
         for (int k = 0; k < RAY_BATCH; ++k) sum = fmaf(ldg(C.mu + vb[k]), lb[k], sum);
         if (done) break;
     }
+    // voxels the walk visited (one plane crossing per step, so the index
+    // distance from the first voxel to the last, plus one)
+    pieces = (uint32_t)(abs(ix - ix0) + abs(iy - iy0) + abs(iz - iz0) + 1);
     return sum;
 }
 
@@ -621,7 +626,7 @@ __device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox
 // the problem (tally layout) and its weight.  d: the problem's descriptor
 // (cone and Klein-Nishina constants).
 __device__ inline bool fd_eval(const Cst& C, const ProbDesc* __restrict__ d, const FdPoint& q,
-                               uint32_t& bin, float& score) {
+                               uint32_t& bin, float& score, uint32_t& pieces) {
     const float omc = d->omc_alpha, kn140 = (float)d->kn140;
     uint32_t r0 = q.hist, r1 = q.view, r2 = q.event, r3 = FD_SUB;
     philox10(r0, r1, r2, r3, C.seed, C.pid);
@@ -653,7 +658,7 @@ __device__ inline bool fd_eval(const Cst& C, const ProbDesc* __restrict__ d, con
     const int iv = min((int)(av * C.inv_pix), C.nv - 1);
     float l2, ppe;
     const float g = e2 == C.e0 ? C.g0 : energy_terms(C, e2, l2, ppe);
-    score = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, ox, oy, oz));
+    score = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, ox, oy, oz, pieces));
     const uint32_t cls = q.event == 0 ? 0u : 1u;
     bin = ((q.view * 2u + cls) * (uint32_t)C.nv + (uint32_t)iv) * (uint32_t)C.nu + (uint32_t)iu;
     return true;
@@ -668,7 +673,7 @@ __device__ inline bool fd_eval(const Cst& C, const ProbDesc* __restrict__ d, con
 // weight.  The layers are convolved with the collimator response of their
 // depth after transport.
 __device__ inline bool cfd_eval(const Cst& C, const ProbDesc* __restrict__ d, const FdPoint& q,
-                                uint64_t& lbin, float& score) {
+                                uint64_t& lbin, float& score, uint32_t& pieces) {
     const float omc = d->omc_alpha, kn140 = (float)d->kn140;
     const float2 vw = ldg(C.views + q.view);
     float w, e2;
@@ -696,7 +701,7 @@ __device__ inline bool cfd_eval(const Cst& C, const ProbDesc* __restrict__ d, co
     const int l = min(max((int)floorf(depth * C.inv_pix), 0), nl - 1);
     float l2, ppe;
     const float g = e2 == C.e0 ? C.g0 : energy_terms(C, e2, l2, ppe);
-    score = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, vw.x, vw.y, 0.0f));
+    score = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, vw.x, vw.y, 0.0f, pieces));
     const uint32_t cls = q.event == 0 ? 0u : 1u;
     lbin = ((((uint64_t)q.view * (uint64_t)nl + (uint64_t)l) * 2u + cls) * (uint64_t)C.nv + (uint64_t)iv) *
                (uint64_t)C.nu + (uint64_t)iu;

@@ -44,11 +44,16 @@ __device__ __forceinline__ long long wsum64(long long v) {
 
 // Wave-wide flush of one problem's accumulators (all 64 lanes must call).
 // fc: wave-uniform fate counts; wc: wave-uniform tentative collisions, real
-// collisions, Kahn attempts; e_esc: the lane's escaped energy (Q40.23).  The
-// deposited energy is filled in after the kernel (k_finalize).
-__device__ inline void flush(long long& e_esc, uint32_t* fc, uint32_t* wc, int p,
-                             const TransportArgs& T, int lane) {
+// collisions, Kahn attempts; e_esc: the lane's escaped energy (Q40.23);
+// rays / pieces: the lane's forced-copy ray walks and the voxels they
+// visited.  The deposited energy is filled in after the kernel (k_finalize).
+// count_tallied: add the tallied histories to T.n_events (an analog run
+// without an event list, whose count needs no per-history atomic).
+__device__ inline void flush(long long& e_esc, uint32_t* fc, uint32_t* wc, uint32_t& rays,
+                             uint32_t& pieces, int p, const TransportArgs& T, int lane,
+                             bool count_tallied) {
     const long long ee = wsum64(e_esc);
+    const long long n_rays = wsum64(rays), n_pieces = wsum64(pieces);
     uint32_t nh = 0;
 #pragma unroll
     for (int i = 0; i < 7; ++i) nh += fc[i];
@@ -57,12 +62,17 @@ __device__ inline void flush(long long& e_esc, uint32_t* fc, uint32_t* wc, int p
 #pragma unroll
         for (int i = 0; i < 7; ++i) if (fc[i]) atomicAdd(fa + i, (unsigned long long)fc[i]);
         if (T.energy) atomicAdd((unsigned long long*)(T.energy + (size_t)p * 4 + 1), (unsigned long long)ee);
+        if (count_tallied && fc[MC_TALLIED]) atomicAdd(T.n_events, (unsigned long long)fc[MC_TALLIED]);
         if (T.counters) {
-            unsigned long long* ca = (unsigned long long*)(T.counters + (size_t)p * 4);
+            unsigned long long* ca = (unsigned long long*)(T.counters + (size_t)p * MC_N_COUNTERS);
             atomicAdd(ca + 0, (unsigned long long)wc[0]);
             atomicAdd(ca + 1, (unsigned long long)wc[1]);
             atomicAdd(ca + 2, (unsigned long long)wc[2]);
             atomicAdd(ca + 3, (unsigned long long)nh);
+            if (n_rays) {
+                atomicAdd(ca + 4, (unsigned long long)n_rays);
+                atomicAdd(ca + 5, (unsigned long long)n_pieces);
+            }
         }
         if (fc[MC_CAPPED_FATE]) {
             atomicOr((unsigned long long*)T.status, (unsigned long long)MC_STATUS_CAPPED);
@@ -70,6 +80,7 @@ __device__ inline void flush(long long& e_esc, uint32_t* fc, uint32_t* wc, int p
         }
     }
     e_esc = 0;
+    rays = pieces = 0;
 #pragma unroll
     for (int i = 0; i < 7; ++i) fc[i] = 0;
     wc[0] = wc[1] = wc[2] = 0;
@@ -97,29 +108,66 @@ struct EmitRec {
 };
 
 constexpr uint32_t FD_RING = 128;         // forced-detection queue per wave
+// Events of listed forced copies staged per wave before one atomic appends
+// them: the list's counter is one address for the whole device, so one
+// atomic per few hundred events instead of one per scored batch.
+constexpr uint32_t EV_STAGE = 320;
 
-// Score the forced copy of each active lane: tally (Q31.32), sum of squares
-// (Q11.52) and, if listed, one event each (appended with one atomic per
-// wavefront by its first active lane).
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Append the wave's staged events to the list: one atomic reserves `count`
+// slots, the lanes copy the stage out; slots past the capacity are dropped
+// but counted, as for a direct append.  All 64 lanes call; count is
+// wave-uniform.
+__device__ inline void flush_events(const TransportArgs& T, const mc_event* stage, uint32_t& count,
+                                    int lane) {
+    if (count == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(T.n_events, (unsigned long long)count);
+    base = uniform64(base);
+    wave_sync_lds();
+    for (uint32_t i = (uint32_t)lane; i < count; i += 64) {
+        const uint64_t idx = base + i;
+        if (idx < T.event_capacity) T.events[idx] = stage[i];
+    }
+    wave_sync_lds();
+    count = 0;
+}
+
+// Score the forced copy of each lane with valid set: tally (Q31.32), sum of
+// squares (Q11.52) and, if listed, one event each into the wave's stage
+// (ev_count more; the caller keeps room for 64).  All 64 lanes call.
 template <int MODE>
-__device__ inline void fd_commit(const Cst& C, int p, const FdPoint& q, int lane,
-                                 const TransportArgs& T) {
+__device__ inline void fd_commit(const Cst& C, int p, const FdPoint& q, bool valid, int lane,
+                                 const TransportArgs& T, uint32_t& rays, uint32_t& pieces,
+                                 mc_event* stage, uint32_t& ev_count) {
+    uint32_t pc = 0;
     if constexpr (MODE == 2) {
         // convolution-based: deposit into the depth layer (no events, no
         // sum of squares)
         uint64_t lb = 0;
         float sc = 0.0f;
-        if (cfd_eval(C, T.descs + p, q, lb, sc))
+        if (valid && cfd_eval(C, T.descs + p, q, lb, sc, pc))
             atomicAdd((unsigned long long*)(T.descs[p].layers + lb),
                       (unsigned long long)signed_weight(T.descs + p, q.voxel,
                                                         __float2ll_rn(sc * 4294967296.0f)));
+        rays += pc != 0;
+        pieces += pc;
         return;
     }
     uint32_t bin = 0;
     float sc = 0.0f;
-    const bool ok = fd_eval(C, T.descs + p, q, bin, sc);
-    const long long w = signed_weight(T.descs + p, q.voxel, __float2ll_rn(sc * 4294967296.0f));
+    bool ok = false;
+    if (valid) ok = fd_eval(C, T.descs + p, q, bin, sc, pc);
+    rays += pc != 0;
+    pieces += pc;
+    long long w = 0;
     if (ok) {
+        w = signed_weight(T.descs + p, q.voxel, __float2ll_rn(sc * 4294967296.0f));
         const size_t b = C.tally_offset + bin;
         atomicAdd((unsigned long long*)(T.tally + b), (unsigned long long)w);
         if (T.tally_sq)
@@ -128,37 +176,29 @@ __device__ inline void fd_commit(const Cst& C, int p, const FdPoint& q, int lane
     }
     if (T.events) {            // forced copies are counted only when listed
         const uint64_t m = __ballot(ok);
-        if (m != 0) {
-            unsigned long long base = 0;
-            if (lane == __ffsll((unsigned long long)__ballot(1)) - 1)
-                base = atomicAdd(T.n_events, (unsigned long long)__popcll(m));
-            base = uniform64(base);
-            if (ok) {
-                const uint64_t idx = base + (uint64_t)__popcll(m & ((1ull << lane) - 1ull));
-                if (idx < T.event_capacity) {
-                    mc_event ev;
-                    ev.work = T.work_prefix[p] + (work_of(C, q.view, q.hist) - C.work_begin);
-                    ev.bin = bin;
-                    ev.emit_voxel = q.voxel;
-                    ev.weight = w;
-                    T.events[idx] = ev;
-                }
-            }
+        if (ok) {
+            mc_event ev;
+            ev.work = T.work_prefix[p] + (work_of(C, q.view, q.hist) - C.work_begin);
+            ev.bin = bin;
+            ev.emit_voxel = q.voxel;
+            ev.weight = w;
+            stage[ev_count + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = ev;
         }
+        ev_count += (uint32_t)__popcll(m);
     }
 }
 
-// Score the n (<= 64) forced copies at the head of a wave's ring.
+// Score the n (<= 64) forced copies at the head of a wave's ring (all 64
+// lanes call).
 template <int MODE>
 __device__ inline void fd_drain(const Cst& C, int p, const FdPoint* ring, uint32_t& head, uint32_t n,
-                                int lane, const TransportArgs& T) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if ((uint32_t)lane < n) {
-        const FdPoint q = ring[(head + (uint32_t)lane) & (FD_RING - 1)];
-        fd_commit<MODE>(C, p, q, lane, T);
-    }
+                                int lane, const TransportArgs& T, uint32_t& rays, uint32_t& pieces,
+                                mc_event* stage, uint32_t& ev_count) {
+    wave_sync_lds();
+    const bool valid = (uint32_t)lane < n;
+    FdPoint q = {};
+    if (valid) q = ring[(head + (uint32_t)lane) & (FD_RING - 1)];
+    fd_commit<MODE>(C, p, q, valid, lane, T, rays, pieces, stage, ev_count);
     head += n;
 }
 
@@ -172,11 +212,13 @@ __device__ inline void fd_drain(const Cst& C, int p, const FdPoint* ring, uint32
 template <int MODE>
 __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restrict__ my,
                                                uint32_t* __restrict__ my_pal,
-                                               FdPoint* __restrict__ ring) {
+                                               FdPoint* __restrict__ ring,
+                                               mc_event* __restrict__ ev_stage) {
     constexpr bool FD = MODE == 1 || MODE == 2;
     constexpr bool VR = MODE == 3;
     const bool vr_dir = VR && (T.vr_flags & VR_FORCED_DIRECTION);
     const bool vr_fi = VR && (T.vr_flags & VR_FORCED_INTERACTION);
+    const bool count_tallied = !FD && T.n_events && !T.events;
     const int lane = threadIdx.x & 63;
     uint32_t fd_head = 0, fd_tail = 0;    // wave-uniform ring cursors (FD)
     const uint64_t lane_lt = (1ull << lane) - 1ull;
@@ -191,6 +233,9 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
     uint32_t fc[7] = {0, 0, 0, 0, 0, 0, 0};   // wave-uniform fate counts
     uint32_t wc[3] = {0, 0, 0};               // wave-uniform work counters
     long long e_esc = 0;                      // escaped energy, Q40.23 (per lane)
+    uint32_t fd_rays = 0, fd_pieces = 0;      // forced-copy ray walks, voxels visited (per lane)
+    uint32_t ev_count = 0;                    // staged events (forced detection, wave-uniform)
+    const bool fd_list = FD && T.events;
     Cst C;
     Lane L;
     L.state = S_IDLE;
@@ -231,7 +276,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                             ready = false;                 // drain problem p first
                         } else {
                             if (np != p) {
-                                if (p >= 0) flush(e_esc, fc, wc, p, T, lane);
+                                if (p >= 0) flush(e_esc, fc, wc, fd_rays, fd_pieces, p, T, lane, count_tallied);
                                 p = np;
                                 C = load_cst(T.descs + p);
                                 if (C.use_pal) {
@@ -258,9 +303,11 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                 }
                 if (ready && c_next < c_end) {
                     const uint32_t n_rec = (uint32_t)min((uint64_t)EMIT_BATCH, c_end - c_next);
+                    if (fd_list && ev_count > EV_STAGE - EMIT_BATCH) flush_events(T, ev_stage, ev_count, lane);
 #pragma unroll 1
                     for (int k = 0; k < EMIT_PER_LANE; ++k) {
                         const uint32_t idx = (uint32_t)(k * 64 + lane);
+                        FdPoint q = {};
                         if (idx < n_rec) {
                             uint64_t v = cur_view, h = cur_hist;
                             advance_cursor(C, v, h, idx, C.n_views);
@@ -270,15 +317,17 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                             r.voxel = e.voxel; r.view = (uint32_t)v; r.hist = (uint32_t)h;
                             my[idx] = r;
                             if constexpr (FD) {
-                                FdPoint q;
                                 q.x = e.x; q.y = e.y; q.z = e.z;
-                                q.dx = 0.0f; q.dy = 0.0f; q.dz = 0.0f;
                                 q.e = C.e0;
                                 q.view = (uint32_t)v; q.hist = (uint32_t)h; q.event = 0;
                                 q.voxel = e.voxel;
-                                fd_commit<MODE>(C, p, q, lane, T);
                             }
                         }
+                        // the emission point's forced copy (all lanes: the
+                        // event stage is appended wave-wide)
+                        if constexpr (FD)
+                            fd_commit<MODE>(C, p, q, idx < n_rec, lane, T, fd_rays, fd_pieces, ev_stage,
+                                            ev_count);
                     }
                     // the records are read by other lanes of this wavefront
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -352,8 +401,11 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             // path, so a score never depends on where it was drained): 64 at
             // a time, or what is left once no lane is busy
             const uint32_t cnt = fd_tail - fd_head;
-            if (cnt >= 64 || (cnt != 0 && __ballot(L.state != S_IDLE) == 0))
-                fd_drain<MODE>(C, p, ring, fd_head, cnt < 64 ? cnt : 64u, lane, T);
+            if (cnt >= 64 || (cnt != 0 && __ballot(L.state != S_IDLE) == 0)) {
+                if (fd_list && ev_count > EV_STAGE - 64) flush_events(T, ev_stage, ev_count, lane);
+                fd_drain<MODE>(C, p, ring, fd_head, cnt < 64 ? cnt : 64u, lane, T, fd_rays, fd_pieces,
+                               ev_stage, ev_count);
+            }
         }
         if (__ballot(fate != R_RUNNING) != 0) {
             // fate counts through ballots: wave-uniform, no per-lane counters
@@ -371,9 +423,9 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                     atomicAdd((unsigned long long*)(T.tally_sq + gb),
                               VR ? (unsigned long long)__float2ll_rn(L.w * L.w * 4503599627370496.0f)
                                  : 1ull << 32);
-                if (T.n_events) {
+                if (T.events) {       // without a list the count is the flushed fate count
                     const unsigned long long idx = atomicAdd(T.n_events, 1ull);
-                    if (T.events && idx < T.event_capacity) {
+                    if (idx < T.event_capacity) {
                         mc_event ev;
                         ev.work = T.work_prefix[p] + (work_of(C, L.view, L.hist) - C.work_begin);
                         ev.bin = bin;
@@ -386,27 +438,29 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             if (fate != R_RUNNING) L.state = S_IDLE;
         }
     }
-    if (p >= 0) flush(e_esc, fc, wc, p, T, lane);
+    if (p >= 0) flush(e_esc, fc, wc, fd_rays, fd_pieces, p, T, lane, count_tallied);
+    if (fd_list) flush_events(T, ev_stage, ev_count, lane);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TransportArgs T) {
     __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
     __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
-    transport_body<0>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr);
+    transport_body<0>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(256) void k_transport_fd(TransportArgs T) {
     __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
     __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
     __shared__ FdPoint ring[WAVES_PER_BLOCK_MAX][FD_RING];
+    __shared__ mc_event ev_stage[WAVES_PER_BLOCK_MAX][EV_STAGE];
     transport_body<1>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6],
-                      ring[threadIdx.x >> 6]);
+                      ring[threadIdx.x >> 6], ev_stage[threadIdx.x >> 6]);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport_vr(TransportArgs T) {
     __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
     __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
-    transport_body<3>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr);
+    transport_body<3>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(256) void k_transport_cfd(TransportArgs T) {
@@ -414,7 +468,7 @@ __global__ __launch_bounds__(256) void k_transport_cfd(TransportArgs T) {
     __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
     __shared__ FdPoint ring[WAVES_PER_BLOCK_MAX][FD_RING];
     transport_body<2>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6],
-                      ring[threadIdx.x >> 6]);
+                      ring[threadIdx.x >> 6], nullptr);
 }
 
 // Replay: one listed history per lane, run to its end, one record out.
@@ -479,10 +533,10 @@ __global__ __launch_bounds__(256) void k_prepare(const ProbDesc* __restrict__ de
         if (tally_sq) tally_sq[i] = 0;
     }
     for (uint64_t i = tid; i < (uint64_t)n_problems * MC_N_FATES; i += stride) fates[i] = 0;
-    for (uint64_t i = tid; i < (uint64_t)n_problems * 4; i += stride) {
+    for (uint64_t i = tid; i < (uint64_t)n_problems * 4; i += stride)
         if (energy) energy[i] = 0;
+    for (uint64_t i = tid; i < (uint64_t)n_problems * MC_N_COUNTERS; i += stride)
         if (counters) counters[i] = 0;
-    }
     if (tid == 0) {
         uint64_t w = 0, c = 0;
         uint64_t* chunk_prefix = work_prefix + (n_problems + 1);

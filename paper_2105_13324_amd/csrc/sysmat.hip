@@ -526,9 +526,9 @@ __global__ __launch_bounds__(T256) void k_row_sums(int64_t n_rows, const int64_t
 // Per-call state of mlem_iterate (device uint32 [ST_WORDS]): the lengths of
 // the two row lists, a flag set when the entry count the caller gave is not
 // the matrix's own (the iterations then sweep nothing and the image is NaN),
-// and the lengths of the row-length class lists of the compact layout (four
-// for bins, four for voxels).
-enum { ST_BINS = 0, ST_VOXS = 1, ST_BAD = 2, ST_BIN_CLASS = 4, ST_VOX_CLASS = 8, ST_WORDS = 12 };
+// and for the compact layout, per matrix and per (group, length class) key
+// (2 x 32), the rows counted, their first list position and an append cursor.
+enum { ST_BINS = 0, ST_VOXS = 1, ST_BAD = 2, ST_HIST = 4, ST_OFF = 68, ST_CUR = 132, ST_WORDS = 196 };
 
 // S_i = img_i where sens_i > 0, else 0 (row order; in list order the compact
 // layout sets S in k_mlem_compact); the list lengths zeroed, the entry count
@@ -628,50 +628,6 @@ __global__ __launch_bounds__(T256) void k_mlem_rows(int64_t n_bins, int64_t n_vo
         }
         __syncthreads();     // before[] and base_s are rewritten for the next chunk
     }
-}
-
-// Compact layout (sparse matrices, nnz <= n_bins + n_vox): the iterations
-// keep S, sens, P and the ratio in list order, and the column indices of both
-// matrices are renumbered to list positions (Tc: voxel positions, Ttc: bin
-// positions), so every gather falls in a vector of the non-empty rows only
-// (a few MB at most, L2-resident) instead of a sparse scattering over the
-// full bin and voxel ranges.  The summation order is the same as in row
-// order.  A column whose row in the other orientation is empty (the two
-// orientations disagree) sets the bad flag.
-__global__ __launch_bounds__(T256) void k_mlem_compact(int64_t nnz, const int32_t* __restrict__ T_col,
-                                                       const int32_t* __restrict__ Tt_col,
-                                                       const int32_t* __restrict__ bin_pos,
-                                                       const int32_t* __restrict__ vox_pos,
-                                                       int32_t* __restrict__ Tc, int32_t* __restrict__ Ttc,
-                                                       const RowRef* __restrict__ bins,
-                                                       const RowRef* __restrict__ voxs,
-                                                       const float* __restrict__ img,
-                                                       const double* __restrict__ sens,
-                                                       double* __restrict__ S_l,
-                                                       double* __restrict__ sens_l,
-                                                       const float* __restrict__ P,
-                                                       float* __restrict__ P_l, uint32_t* __restrict__ st) {
-    if (st[ST_BAD]) return;
-    const int64_t nb = st[ST_BINS], nv = st[ST_VOXS];
-    const int64_t n = std::max(nnz, std::max(nb, nv));
-    bool bad = false;
-    for (int64_t t = (int64_t)blockIdx.x * T256 + threadIdx.x; t < n;
-         t += (int64_t)gridDim.x * T256) {
-        if (t < nnz) {
-            const int32_t pv = vox_pos[T_col[t]], pb = bin_pos[Tt_col[t]];
-            bad |= pv < 0 || pb < 0;
-            Tc[t] = pv < 0 ? 0 : pv;
-            Ttc[t] = pb < 0 ? 0 : pb;
-        }
-        if (t < nv) {
-            const int32_t i = voxs[t].row;
-            const double si = sens[i];
-            sens_l[t] = si;
-            S_l[t] = si > 0.0 ? (double)img[i] : 0.0;
-        }
-        if (t < nb) P_l[t] = P[bins[t].row];
-    }
-    if (bad) atomicOr(&st[ST_BAD], 1u);
 }
 
 // Lanes that share one row in the MLEM sweeps: the smallest group of 1, 4, 16
@@ -884,13 +840,27 @@ __global__ __launch_bounds__(T256) void k_mlem_update(const RowRef* __restrict__
                });
 }
 
-// ---- compact layout: row-length classes.  The non-empty rows are split by
-// length into four lists, rows of at most 4, 16, 64 entries and longer ones,
+// ---- compact layout.  The non-empty rows of both matrices are listed in
+// (group, length class) order; the list position of a row is the index of
+// its entries in the iterated vectors.
+//
+// Groups.  Workgroups are handed to the 8 XCDs in turn, and workgroup b of a
+// sweep works on group b mod 8, so the rows of one group are swept, and
+// their vector entries written, by one XCD.  A voxel row's group is its
+// eighth of the voxel index range (contiguous index ranges are slabs of
+// planes); a bin row's group is that of the voxel of its first entry (for a
+// parallel-hole camera, the slab its ray crosses).  Gathers then mostly read
+// entries that the same XCD wrote in the previous sweep, still in its L2,
+// rather than lines written back by other XCDs.  Any grouping is correct.
+//
+// Length classes.  Rows of at most 4, 16, 64 entries and longer ones are
 // swept by groups of 1, 4, 16 and 64 lanes, one row per group and pass, so a
-// row of up to 4 GS entries takes one load round of its group and a long
-// row does not hold one lane for many rounds.  The group size, and with it
+// row of up to 4 GS entries takes one load round of its group and a long row
+// does not hold one lane for many rounds.  The lane-group size, and with it
 // the summation order, depends only on the row's length.
 constexpr int N_CLASS = 4;
+constexpr int N_GROUP = 8;
+constexpr int N_KEY = N_CLASS * N_GROUP;     // per matrix
 
 __host__ __device__ inline int length_class(int64_t len) {
     return len <= 4 ? 0 : len <= 16 ? 1 : len <= 64 ? 2 : 3;
@@ -903,154 +873,258 @@ __host__ __device__ inline int64_t class_capacity(int c, int64_t n, int64_t nnz)
     return m < n ? m : n;
 }
 
-// A listed row of the compact layout: its list position (the index of its
-// vector entries) and entry range.
+// A listed row of the compact layout (at its list position): its index and
+// entry range.
 struct ClassRef {
-    int32_t q;
+    int32_t row;
     uint32_t lo;
     int32_t len, pad;
 };
 
-struct ClassLists {
-    ClassRef* l[N_CLASS];
-    int64_t cap[N_CLASS];
-};
-
-// Exclusive prefix over the workgroup's 256 threads of x, and the total in
-// *all (wsum: 4 words of shared memory; the caller syncs before reusing it).
-__device__ inline uint64_t block_excl_scan(uint64_t x, uint64_t* wsum, uint64_t* all) {
-    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
-    uint64_t v = x;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint64_t y = __shfl_up(v, o, 64);
-        if (lane >= o) v += y;
-    }
-    if (lane == 63) wsum[w] = v;
-    __syncthreads();
-    uint64_t before = 0, tot = 0;
-#pragma unroll
-    for (int i = 0; i < T256 / 64; ++i) {
-        if (i < w) before += wsum[i];
-        tot += wsum[i];
-    }
-    *all = tot;
-    return before + v - x;
-}
-
-// Class lists of one row list (L, length *count): each workgroup takes 4096
-// list entries at a time, counts them per class (four 16-bit fields of one
-// 64-bit word, scanned over the workgroup), appends each class's with one
-// atomic on cnt[c].  A count past a list's capacity (impossible for the
-// entry count checked on the device) sets the bad flag instead of writing.
-__global__ __launch_bounds__(T256) void k_mlem_classes(const RowRef* __restrict__ L,
-                                                       const uint32_t* __restrict__ count,
-                                                       ClassLists C, uint32_t* __restrict__ cnt,
-                                                       uint32_t* __restrict__ st) {
-    __shared__ uint64_t wsum[T256 / 64];
-    __shared__ uint32_t base_s[N_CLASS];
+// Compact layout (sparse matrices, nnz <= n_bins + n_vox): the iterations
+// keep S, sens, P and the ratio in list order, and the column indices of both
+// matrices are renumbered to list positions (Tc: voxel positions, Ttc: bin
+// positions), so every gather falls in a vector of the non-empty rows only
+// (a few MB at most, L2-resident) instead of a sparse scattering over the
+// full bin and voxel ranges.  A column whose row in the other orientation is
+// empty (the two orientations disagree) sets the bad flag.
+__global__ __launch_bounds__(T256) void k_mlem_compact(int64_t nnz, const int32_t* __restrict__ T_col,
+                                                       const int32_t* __restrict__ Tt_col,
+                                                       const int32_t* __restrict__ bin_pos,
+                                                       const int32_t* __restrict__ vox_pos,
+                                                       int32_t* __restrict__ Tc, int32_t* __restrict__ Ttc,
+                                                       const ClassRef* __restrict__ bins,
+                                                       const ClassRef* __restrict__ voxs,
+                                                       const float* __restrict__ img,
+                                                       const double* __restrict__ sens,
+                                                       double* __restrict__ S_l,
+                                                       double* __restrict__ sens_l,
+                                                       const float* __restrict__ P,
+                                                       float* __restrict__ P_l, uint32_t* __restrict__ st) {
     if (st[ST_BAD]) return;
-    const int64_t n = *count;
+    const int64_t nb = st[ST_BINS], nv = st[ST_VOXS];
+    const int64_t n = std::max(nnz, std::max(nb, nv));
     bool bad = false;
-    for (int64_t c0 = (int64_t)blockIdx.x * ROW_CHUNK; c0 < n; c0 += (int64_t)gridDim.x * ROW_CHUNK) {
-        uint64_t mine = 0;
-#pragma unroll
-        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
-            const int64_t q = c0 + k * T256 + threadIdx.x;
-            if (q < n) mine += 1ull << (16 * length_class(L[q].len));
+    for (int64_t t = (int64_t)blockIdx.x * T256 + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * T256) {
+        if (t < nnz) {
+            const int32_t pv = vox_pos[T_col[t]], pb = bin_pos[Tt_col[t]];
+            bad |= pv < 0 || pb < 0;
+            Tc[t] = pv < 0 ? 0 : pv;
+            Ttc[t] = pb < 0 ? 0 : pb;
         }
-        uint64_t all = 0;
-        uint64_t before = block_excl_scan(mine, wsum, &all);
-        if (threadIdx.x < N_CLASS) {
-            const uint32_t t = (uint32_t)((all >> (16 * threadIdx.x)) & 0xFFFF);
-            base_s[threadIdx.x] = t ? atomicAdd(&cnt[threadIdx.x], t) : 0u;
+        if (t < nv) {
+            const int32_t i = voxs[t].row;
+            const double si = sens[i];
+            sens_l[t] = si;
+            S_l[t] = si > 0.0 ? (double)img[i] : 0.0;
         }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
-            const int64_t q = c0 + k * T256 + threadIdx.x;
-            if (q < n) {
-                const RowRef r = L[q];
-                const int c = length_class(r.len);
-                const uint64_t slot = base_s[c] + ((before >> (16 * c)) & 0xFFFF);
-                before += 1ull << (16 * c);
-                if ((int64_t)slot < C.cap[c])
-                    C.l[c][slot] = ClassRef{(int32_t)q, (uint32_t)r.lo, r.len, 0};
-                else
-                    bad = true;
-            }
-        }
-        __syncthreads();     // wsum and base_s are rewritten for the next chunk
+        if (t < nb) P_l[t] = P[bins[t].row];
     }
     if (bad) atomicOr(&st[ST_BAD], 1u);
 }
 
-// One class's rows by groups of GS lanes (workgroup `block` of n_blocks for
-// this class), one row per group and pass; the first entry is loaded with
-// the list length.  aux(q) loads the row's own operands, done(q, aux, sum)
-// runs on the group's first lane.
-template <int GS, class Aux, class Term, class Done>
-__device__ inline void sweep_class(int64_t block, int64_t n_blocks, const ClassRef* __restrict__ L,
-                                   int64_t cap, const uint32_t* __restrict__ count, Aux aux, Term term,
-                                   Done done) {
-    const RowGroups<GS> G(block, n_blocks);
-    if (G.first >= cap) return;
-    ClassRef ref = L[G.first];
-    const uint32_t n32 = *count;
-    // both loads in flight before either is used (the compiler would
-    // otherwise issue the row's load only once the length test has passed)
-    asm volatile("" ::"v"(ref.q), "v"(ref.lo), "v"(ref.len), "s"(n32));
-    const int64_t n = n32;
-    for (int64_t r = G.first; r < n; r += G.step) {
-        if (r != G.first) ref = L[r];
-        const auto a = aux(ref.q);
-        const double sum = group_row_sum<GS>(ref.lo, (int64_t)ref.lo + ref.len, G.sub, term);
-        if (G.sub == 0) done(ref.q, a, sum);
+// (group, class) key of a non-empty row: group by voxel index (a voxel row's
+// own, a bin row's first column), class by length.
+__device__ inline int row_key(int64_t vox, int64_t n_vox, int64_t len) {
+    const int g = (int)(((uint64_t)vox * N_GROUP) / (uint64_t)n_vox);
+    return g * N_CLASS + length_class(len);
+}
+
+// One matrix's rows in chunks of 4096 per workgroup: for each non-empty row,
+// f(row, lo, len, key).  Rows of the bin matrix (col: its columns) take the
+// group of their first column.
+template <class F>
+__device__ inline void for_listed_rows(int64_t r0, int64_t nr, const int64_t* __restrict__ rp,
+                                       const int32_t* __restrict__ col, int64_t n_vox, F f) {
+    // all row bounds, then all first columns, in flight before any is used
+    int64_t lo[ROWS_PER_THREAD], len[ROWS_PER_THREAD];
+    int32_t c0[ROWS_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+        const int64_t r = r0 + k * T256 + threadIdx.x;
+        lo[k] = 0;
+        len[k] = 0;
+        if (r < nr) {
+            lo[k] = rp[r];
+            len[k] = rp[r + 1] - lo[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < ROWS_PER_THREAD; ++k) c0[k] = (col && len[k] > 0) ? col[lo[k]] : 0;
+#pragma unroll
+    for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+        const int64_t r = r0 + k * T256 + threadIdx.x;
+        if (len[k] > 0) f(r, lo[k], len[k], row_key(col ? (int64_t)c0[k] : r, n_vox, len[k]));
     }
 }
 
-// The four classes of one list in one launch: workgroups [b.x, b.y) sweep
-// class 0, [b.y, b.z) class 1, [b.z, b.w) class 2, [b.w, gridDim.x) class 3.
+// Pass 1: rows per (matrix, key), one workgroup histogram per chunk.
+__global__ __launch_bounds__(T256) void k_mlem_count(int64_t n_bins, int64_t n_vox,
+                                                     const int64_t* __restrict__ T_rp,
+                                                     const int32_t* __restrict__ T_col,
+                                                     const int64_t* __restrict__ Tt_rp,
+                                                     uint32_t* __restrict__ st) {
+    __shared__ uint32_t h[N_KEY];
+    if (st[ST_BAD]) return;
+    const int64_t nbc = (n_bins + ROW_CHUNK - 1) / ROW_CHUNK, nvc = (n_vox + ROW_CHUNK - 1) / ROW_CHUNK;
+    for (int64_t c = blockIdx.x; c < nbc + nvc; c += gridDim.x) {
+        const bool vox = c >= nbc;
+        if (threadIdx.x < N_KEY) h[threadIdx.x] = 0;
+        __syncthreads();
+        for_listed_rows((vox ? c - nbc : c) * ROW_CHUNK, vox ? n_vox : n_bins, vox ? Tt_rp : T_rp,
+                        vox ? nullptr : T_col, n_vox,
+                        [&](int64_t, int64_t, int64_t, int key) { atomicAdd(&h[key], 1u); });
+        __syncthreads();
+        if (threadIdx.x < N_KEY && h[threadIdx.x])
+            atomicAdd(&st[ST_HIST + (vox ? N_KEY : 0) + threadIdx.x], h[threadIdx.x]);
+        __syncthreads();
+    }
+}
+
+// Pass 2 (one thread): each key's first list position, the list lengths,
+// cursors zeroed.
+__global__ void k_mlem_offsets(uint32_t* __restrict__ st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || st[ST_BAD]) return;
+    for (int m = 0; m < 2; ++m) {
+        uint32_t at = 0;
+        for (int k = 0; k < N_KEY; ++k) {
+            st[ST_OFF + m * N_KEY + k] = at;
+            st[ST_CUR + m * N_KEY + k] = 0;
+            at += st[ST_HIST + m * N_KEY + k];
+        }
+        st[m == 0 ? ST_BINS : ST_VOXS] = at;
+    }
+}
+
+// Pass 3: each non-empty row at the next position of its key (one atomic per
+// key and workgroup chunk; the order within a key varies from call to call,
+// which changes no result: every row is summed by one lane group on its
+// own); pos[row] = its position, -1 for an empty row.
+__global__ __launch_bounds__(T256) void k_mlem_place(int64_t n_bins, int64_t n_vox,
+                                                     const int64_t* __restrict__ T_rp,
+                                                     const int32_t* __restrict__ T_col,
+                                                     const int64_t* __restrict__ Tt_rp,
+                                                     ClassRef* __restrict__ bins, ClassRef* __restrict__ voxs,
+                                                     int32_t* __restrict__ bin_pos, int32_t* __restrict__ vox_pos,
+                                                     uint32_t* __restrict__ st) {
+    __shared__ uint32_t h[N_KEY], base[N_KEY];
+    if (st[ST_BAD]) return;
+    const int64_t nbc = (n_bins + ROW_CHUNK - 1) / ROW_CHUNK, nvc = (n_vox + ROW_CHUNK - 1) / ROW_CHUNK;
+    for (int64_t c = blockIdx.x; c < nbc + nvc; c += gridDim.x) {
+        const bool vox = c >= nbc;
+        const int64_t r0 = (vox ? c - nbc : c) * ROW_CHUNK, nr = vox ? n_vox : n_bins;
+        const int64_t* rp = vox ? Tt_rp : T_rp;
+        int32_t* pos = vox ? vox_pos : bin_pos;
+        ClassRef* out = vox ? voxs : bins;
+        const uint32_t* off = st + ST_OFF + (vox ? N_KEY : 0);
+        if (threadIdx.x < N_KEY) h[threadIdx.x] = 0;
+        __syncthreads();
+        // rank within the chunk's rows of the same key (packed: key << 16 | rank)
+        uint32_t kr[ROWS_PER_THREAD];
+#pragma unroll
+        for (int k = 0; k < ROWS_PER_THREAD; ++k) kr[k] = 0xFFFFFFFFu;
+        for_listed_rows(r0, nr, rp, vox ? nullptr : T_col, n_vox, [&](int64_t r, int64_t, int64_t, int key) {
+            kr[(r - r0) / T256] = ((uint32_t)key << 16) | atomicAdd(&h[key], 1u);
+        });
+        __syncthreads();
+        if (threadIdx.x < N_KEY)
+            base[threadIdx.x] = h[threadIdx.x] ? atomicAdd(&st[ST_CUR + (vox ? N_KEY : 0) + threadIdx.x],
+                                                           h[threadIdx.x])
+                                               : 0u;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < ROWS_PER_THREAD; ++k) {
+            const int64_t r = r0 + k * T256 + threadIdx.x;
+            if (r < nr) {
+                int32_t q = -1;
+                if (kr[k] != 0xFFFFFFFFu) {
+                    const uint32_t key = kr[k] >> 16;
+                    q = (int32_t)(off[key] + base[key] + (kr[k] & 0xFFFFu));
+                    const int64_t lo = rp[r];
+                    out[q] = ClassRef{(int32_t)r, (uint32_t)lo, (int32_t)(rp[r + 1] - lo), 0};
+                }
+                pos[r] = q;
+            }
+        }
+        __syncthreads();     // h and base are rewritten for the next chunk
+    }
+}
+
+// One (group, class) list by lane groups of GS (workgroup `block` of n_blocks
+// for it), one row per group and pass.  aux(q) loads the row's own operands,
+// done(q, aux, sum) runs on the group's first lane; q is the list position.
+template <int GS, class Aux, class Term, class Done>
+__device__ inline void sweep_key(int64_t block, int64_t n_blocks, const ClassRef* __restrict__ L,
+                                 uint32_t first, uint32_t n, Aux aux, Term term, Done done) {
+    const RowGroups<GS> G(block, n_blocks);
+    for (int64_t r = G.first; r < (int64_t)n; r += G.step) {
+        const ClassRef ref = L[first + r];
+        const uint32_t q = first + (uint32_t)r;
+        const auto a = aux(q);
+        const double sum = group_row_sum<GS>(ref.lo, (int64_t)ref.lo + ref.len, G.sub, term);
+        if (G.sub == 0) done(q, a, sum);
+    }
+}
+
+// The (group, class) lists of one matrix in one launch: workgroups [b.x, b.y)
+// sweep class 0, [b.y, b.z) class 1, [b.z, b.w) class 2, [b.w, gridDim.x)
+// class 3 (every range a multiple of N_GROUP); within a class, workgroup b
+// works on group b mod N_GROUP.  key_st: that matrix's counts (ST_HIST) and
+// first positions (ST_OFF).
 template <class Aux, class Term, class Done>
-__device__ inline void sweep_classes(const ClassLists& C, const uint32_t* __restrict__ cnt, int4 b,
-                                     Aux aux, Term term, Done done) {
+__device__ inline void sweep_keys(const ClassRef* __restrict__ L, const uint32_t* __restrict__ hist,
+                                  const uint32_t* __restrict__ off, int4 b, Aux aux, Term term, Done done) {
     const int64_t k = blockIdx.x;
-    if (k < b.y) sweep_class<1>(k - b.x, b.y - b.x, C.l[0], C.cap[0], cnt + 0, aux, term, done);
-    else if (k < b.z) sweep_class<4>(k - b.y, b.z - b.y, C.l[1], C.cap[1], cnt + 1, aux, term, done);
-    else if (k < b.w) sweep_class<16>(k - b.z, b.w - b.z, C.l[2], C.cap[2], cnt + 2, aux, term, done);
-    else sweep_class<64>(k - b.w, (int64_t)gridDim.x - b.w, C.l[3], C.cap[3], cnt + 3, aux, term, done);
+    const int g = (int)(k % N_GROUP);
+    int c;
+    int64_t lo, hi;
+    if (k < b.y) { c = 0; lo = b.x; hi = b.y; }
+    else if (k < b.z) { c = 1; lo = b.y; hi = b.z; }
+    else if (k < b.w) { c = 2; lo = b.z; hi = b.w; }
+    else { c = 3; lo = b.w; hi = gridDim.x; }
+    const int key = g * N_CLASS + c;
+    const uint32_t first = off[key], n = hist[key];
+    const int64_t blk = (k - lo) / N_GROUP, nblk = (hi - lo) / N_GROUP;
+    if (c == 0) sweep_key<1>(blk, nblk, L, first, n, aux, term, done);
+    else if (c == 1) sweep_key<4>(blk, nblk, L, first, n, aux, term, done);
+    else if (c == 2) sweep_key<16>(blk, nblk, L, first, n, aux, term, done);
+    else sweep_key<64>(blk, nblk, L, first, n, aux, term, done);
 }
 
 // Compact forward: ratio_q = P_q / (sum_k val_k S[col_k]) over the bin rows,
 // S, P, ratio in list order and col renumbered to voxel list positions.
-__global__ __launch_bounds__(T256) void k_mlem_forward_c(ClassLists C, const uint32_t* __restrict__ cnt,
-                                                         int4 b, const int32_t* __restrict__ col,
+__global__ __launch_bounds__(T256) void k_mlem_forward_c(const ClassRef* __restrict__ L,
+                                                         const uint32_t* __restrict__ st, int4 b,
+                                                         const int32_t* __restrict__ col,
                                                          const float* __restrict__ val,
                                                          const double* __restrict__ S,
                                                          const float* __restrict__ P,
                                                          double* __restrict__ ratio) {
-    sweep_classes(C, cnt, b, [&](int32_t q) { return P[q]; },
-                  [&](int64_t k, bool ok) {
-                      const double x = (double)val[k] * S[col[k]];
-                      return ok ? x : 0.0;
-                  },
-                  [&](int32_t q, float p, double y) { ratio[q] = y > 0.0 ? (double)p / y : 0.0; });
+    sweep_keys(L, st + ST_HIST, st + ST_OFF, b, [&](uint32_t q) { return P[q]; },
+               [&](int64_t k, bool ok) {
+                   const double x = (double)val[k] * S[col[k]];
+                   return ok ? x : 0.0;
+               },
+               [&](uint32_t q, float p, double y) { ratio[q] = y > 0.0 ? (double)p / y : 0.0; });
 }
 
 // Compact update: S_q <- S_q (sum_k val_k ratio[col_k]) / sens_q over the
 // voxel rows, in list order, col renumbered to bin list positions.
-__global__ __launch_bounds__(T256) void k_mlem_update_c(ClassLists C, const uint32_t* __restrict__ cnt,
-                                                        int4 b, const int32_t* __restrict__ col,
+__global__ __launch_bounds__(T256) void k_mlem_update_c(const ClassRef* __restrict__ L,
+                                                        const uint32_t* __restrict__ st, int4 b,
+                                                        const int32_t* __restrict__ col,
                                                         const float* __restrict__ val,
                                                         const double* __restrict__ ratio,
                                                         const double* __restrict__ sens,
                                                         double* __restrict__ S) {
-    sweep_classes(C, cnt, b, [&](int32_t q) { return double2{S[q], sens[q]}; },
-                  [&](int64_t k, bool ok) {
-                      const double x = (double)val[k] * ratio[col[k]];
-                      return ok ? x : 0.0;
-                  },
-                  [&](int32_t q, double2 ss, double v) { S[q] = ss.y > 0.0 ? ss.x * v / ss.y : 0.0; });
+    sweep_keys(L, st + ST_HIST + N_KEY, st + ST_OFF + N_KEY, b,
+               [&](uint32_t q) { return double2{S[q], sens[q]}; },
+               [&](int64_t k, bool ok) {
+                   const double x = (double)val[k] * ratio[col[k]];
+                   return ok ? x : 0.0;
+               },
+               [&](uint32_t q, double2 ss, double v) { S[q] = ss.y > 0.0 ? ss.x * v / ss.y : 0.0; });
 }
 
 // part[s][i] = sum over the entries of voxel row i in slice s of T_ij ratio_j,
@@ -1383,8 +1457,6 @@ namespace {
 // entry count, n_bins + n_vox; the slice arrays exist for n_bins >= 2^19.
 struct MlemLayout {
     size_t sens, S, ratio, bin_rows, vox_rows, st, sens_l, P_l, bin_pos, vox_pos, Tc, Ttc;
-    size_t cls[2][N_CLASS];
-    int64_t cls_cap[2][N_CLASS];
     size_t sb, part, total;
 };
 
@@ -1408,12 +1480,6 @@ MlemLayout mlem_layout(uint64_t nb, uint64_t nv) {
     L.vox_pos = take(4 * nv);
     L.Tc = take(4 * (nb + nv));
     L.Ttc = take(4 * (nb + nv));
-    for (int c = 0; c < N_CLASS; ++c) {
-        L.cls_cap[0][c] = class_capacity(c, (int64_t)nb, (int64_t)(nb + nv));
-        L.cls_cap[1][c] = class_capacity(c, (int64_t)nv, (int64_t)(nb + nv));
-        L.cls[0][c] = take(16 * (uint64_t)L.cls_cap[0][c]);
-        L.cls[1][c] = take(16 * (uint64_t)L.cls_cap[1][c]);
-    }
     if ((int64_t)nb >= MLEM_SEG_MIN_BINS) {
         L.sb = take(8 * (MLEM_SEGS + 1) * nv);
         L.part = take(8 * MLEM_SEGS * nv);
@@ -1481,14 +1547,12 @@ hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t
         int32_t* vox_pos = (int32_t*)(w + Lo.vox_pos);
         int32_t* Tc = (int32_t*)(w + Lo.Tc);
         int32_t* Ttc = (int32_t*)(w + Lo.Ttc);
-        ClassLists cl[2];
-        for (int m = 0; m < 2; ++m)
-            for (int c = 0; c < N_CLASS; ++c) {
-                cl[m].l[c] = (ClassRef*)(w + Lo.cls[m][c]);
-                cl[m].cap[c] = Lo.cls_cap[m][c];
-            }
-        // Workgroups per class: one pass over the most rows the class can
-        // hold with nnz entries, at most one resident round.
+        ClassRef* bin_list = (ClassRef*)(w + Lo.bin_rows);
+        ClassRef* vox_list = (ClassRef*)(w + Lo.vox_rows);
+        // Workgroups per class: each of the N_GROUP groups gets one pass over
+        // a quarter of the rows the class can hold with nnz entries (groups
+        // are uneven; the sweeps are grid-strided, so any count is correct),
+        // the whole launch at most one resident round.
         int bpc_f = 0, bpc_u = 0;
         if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_f, k_mlem_forward_c, T256, 0)) != hipSuccess)
             return e;
@@ -1496,28 +1560,28 @@ hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t
             return e;
         auto ranges = [&](int64_t n_rows, int bpc, int4* b) {
             const int gs[N_CLASS] = {1, 4, 16, 64};
+            const int cap = std::max(1, n_cu * bpc / (N_CLASS * N_GROUP));
             int at = 0, start[N_CLASS];
             for (int c = 0; c < N_CLASS; ++c) {
                 start[c] = at;
-                const uint64_t lanes = (uint64_t)class_capacity(c, n_rows, nnz) * gs[c];
-                at += grid_for(lanes, T256, std::max(1, n_cu * bpc));
+                const uint64_t lanes = ((uint64_t)class_capacity(c, n_rows, nnz) + 3) / 4 * gs[c];
+                at += N_GROUP * grid_for(lanes, T256, cap);
             }
             *b = make_int4(start[0], start[1], start[2], start[3]);
             return at;
         };
         int4 bf, bu;
         const int gf = ranges(n_bins, bpc_f, &bf), gu = ranges(n_vox, bpc_u, &bu);
-        k_mlem_rows<<<gr, T256, 0, s>>>(n_bins, n_vox, T_rp, Tt_rp, bin_rows, vox_rows, bin_pos, vox_pos, st);
+        k_mlem_count<<<gr, T256, 0, s>>>(n_bins, n_vox, T_rp, T_col, Tt_rp, st);
+        k_mlem_offsets<<<1, 64, 0, s>>>(st);
+        k_mlem_place<<<gr, T256, 0, s>>>(n_bins, n_vox, T_rp, T_col, Tt_rp, bin_list, vox_list, bin_pos,
+                                          vox_pos, st);
         k_mlem_compact<<<grid_for(std::max<uint64_t>((uint64_t)nnz, std::max(nb, nv)), T256, 8192), T256, 0,
-                         s>>>(nnz, T_col, Tt_col, bin_pos, vox_pos, Tc, Ttc, bin_rows, vox_rows, image, sens,
+                         s>>>(nnz, T_col, Tt_col, bin_pos, vox_pos, Tc, Ttc, bin_list, vox_list, image, sens,
                               S, sens_l, proj, P_l, st);
-        const int gcb = grid_for((uint64_t)std::min<int64_t>(n_bins, nnz), ROW_CHUNK, 2048);
-        const int gcv = grid_for((uint64_t)std::min<int64_t>(n_vox, nnz), ROW_CHUNK, 2048);
-        k_mlem_classes<<<gcb, T256, 0, s>>>(bin_rows, st + ST_BINS, cl[0], st + ST_BIN_CLASS, st);
-        k_mlem_classes<<<gcv, T256, 0, s>>>(vox_rows, st + ST_VOXS, cl[1], st + ST_VOX_CLASS, st);
         for (int it = 0; it < n_iter; ++it) {
-            k_mlem_forward_c<<<gf, T256, 0, s>>>(cl[0], st + ST_BIN_CLASS, bf, Tc, T_val, S, P_l, ratio);
-            k_mlem_update_c<<<gu, T256, 0, s>>>(cl[1], st + ST_VOX_CLASS, bu, Ttc, Tt_val, ratio, sens_l, S);
+            k_mlem_forward_c<<<gf, T256, 0, s>>>(bin_list, st, bf, Tc, T_val, S, P_l, ratio);
+            k_mlem_update_c<<<gu, T256, 0, s>>>(vox_list, st, bu, Ttc, Tt_val, ratio, sens_l, S);
         }
         k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, vox_pos, st, image);
         return hipGetLastError();

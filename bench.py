@@ -28,10 +28,11 @@ PEAK_LANE_OPS = N_CU * 64 * CLOCK_HZ  # one 32-bit VALU instruction per lane per
 # Algorithmic work per history: the method's operation table (Philox blocks,
 # transcendentals, other 32-bit operations per emission, per tentative
 # collision, per Kahn attempt and per real collision), with a Philox4x32-10
-# block counted as the 60 instructions it is in the library's gfx950
-# assembly (10 rounds x (2 v_mad_u64_u32 + 4 v_xor_b32); the key schedule is
-# scalar).  Counts come from the kernel's own work counters.
-OPS_PHILOX = 60
+# block counted as the 40 instructions it is in the library's gfx950
+# assembly (10 rounds x (2 v_mad_u64_u32 + 2 three-way xors, v_bitop3_b32);
+# the key schedule is scalar).  Counts come from the kernel's own work
+# counters.
+OPS_PHILOX = 40
 TABLE = {            # (Philox blocks, transcendentals, other operations)
     "emission": (2, 3, 20),          # voxel, position, sqrt/sin/cos direction
     "tentative": (1, 1, 10),         # log flight, move, voxel, accept test
@@ -101,7 +102,7 @@ def issue_rates(torch, blocks=None, iters=20000):
     measured full-rate rate in lane-ops/s.  Loop bodies (from the probes'
     gfx950 assembly): mad64 8 v_mad_u64_u32 + 8 v_xor; xor 8 v_xor + 8 v_add;
     fma 8 v_fmaak; each transcendental 8 of it + 8 v_mul; the Philox probe
-    one ten-round block (20 v_mad_u64_u32, ~40 v_xor) per eighth iteration."""
+    one ten-round block (20 v_mad_u64_u32, 20 v_bitop3) per eighth iteration."""
     import ctypes as C
     lib = C.CDLL(os.path.join(ROOT, "paper_2105_13324_amd", "libmcprobe.so"))
     lib.mc_probe_issue.argtypes = [C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_float), C.c_void_p]
@@ -131,14 +132,14 @@ def issue_rates(torch, blocks=None, iters=20000):
 def transport_roofline(sim, k_ms, rates=None, kernel="k_transport", counters_key=None):
     """ALU roofline of one transport launch from the work counters of all its
     problems.  frac: the table's operations (one per instruction, a Philox
-    block = 60) per second over the nominal peak, 256 CU x 64 lanes x
+    block = 40) per second over the nominal peak, 256 CU x 64 lanes x
     2.4 GHz.  With measured issue rates (issue_rates): the shortest time the
     same operations take at the rates the probes sustain (full-rate slots,
     a v_mad_u64_u32 and a transcendental as measured) against the kernel
     time, and, from the committed counter profile of this kernel build, the
     VALU instructions it actually issued."""
     cnt = sim.counters.cpu().numpy().astype(np.float64).sum(axis=0)
-    n_tent, n_real, n_kahn, n_hist = cnt
+    n_tent, n_real, n_kahn, n_hist = cnt[:4]
     ops = table_ops(n_hist, n_tent, n_kahn, n_real)
     achieved = ops / (k_ms / 1e3)
     out = {"bound": "alu", "kernel": kernel, "kernel_ms": k_ms,
@@ -146,12 +147,12 @@ def transport_roofline(sim, k_ms, rates=None, kernel="k_transport", counters_key
            "unit": "Tops/s (32-bit lane ops, one per instruction)", "frac": achieved / PEAK_LANE_OPS,
            "ops_per_history": ops / n_hist,
            # the same table with a Philox block at 100 (the middle of the
-           # 80-120 range of a generic count) instead of its 60 gfx950 instructions
+           # 80-120 range of a generic count) instead of its 40 gfx950 instructions
            "frac_philox_100": table_ops(n_hist, n_tent, n_kahn, n_real, cost=(100, 1.0, 1.0))
                               / (k_ms / 1e3) / PEAK_LANE_OPS,
            "op_table": "per history: emission 2 Philox + 3 transcendental + 20; per tentative "
                        "collision 1 Philox + log + 10; per Kahn attempt 1 Philox; per real collision "
-                       "3 transcendental + 40; Philox = 60 gfx950 instructions"}
+                       "3 transcendental + 40; Philox = 40 gfx950 instructions"}
     if rates:
         c = rates["cost_in_full_rate_slots"]
         slots = table_ops(n_hist, n_tent, n_kahn, n_real,

@@ -25,16 +25,21 @@ enum : int { S_IDLE = 0, S_STEP = 3, S_KAHN = 4 };
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
 // (words 0 and 2), xor-mixed with words 1 and 3 and the key; the key takes a
 // Weyl step after every round.  The key is wave-uniform, so its steps are
-// scalar adds.
+// scalar adds.  Each three-way xor is one gfx950 v_bitop3_b32 (truth table
+// 0x96 = a ^ b ^ c), so a round is two v_mad_u64_u32 and two bitwise ops.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
                                          uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
         const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(b >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(a >> 32), c3, k1);
         c1 = (uint32_t)b;
         c3 = (uint32_t)a;
         c0 = n0;

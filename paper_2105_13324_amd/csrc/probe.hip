@@ -8,7 +8,8 @@
 // is made of: Philox's 32x32->64-bit products (v_mad_u64_u32), 32-bit logic
 // (v_xor), FP32 fused multiply-adds, and the hardware transcendentals the
 // kernels use (v_log, v_sin, v_cos, v_sqrt, v_rcp), plus one Philox4x32-10
-// block per iteration as the mixed case.  The result is the number of
+// block per iteration as the mixed case (written as in the transport: each
+// three-way xor one v_bitop3_b32).  The result is the number of
 // lane-operations of the class per second over the whole device.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -96,8 +97,8 @@ __global__ __launch_bounds__(256) void k_philox(uint32_t* out, int iters, uint32
         for (int r = 0; r < 10; ++r) {
             const uint64_t p0 = (uint64_t)x0 * 0xD2511F53u;
             const uint64_t p1 = (uint64_t)x2 * 0xCD9E8D57u;
-            const uint32_t n0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
-            const uint32_t n2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+            const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), x1, k0, 0x96);
+            const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), x3, k1, 0x96);
             x1 = (uint32_t)p1;
             x3 = (uint32_t)p0;
             x0 = n0;

@@ -92,6 +92,37 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+__device__ __forceinline__ long long readlane64(long long v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(unsigned long long)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((unsigned long long)v >> 32), l);
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Wavefront-aggregated fixed-point tally: the lanes of mask m (wave-uniform)
+// add w (and w2 into the squared tally) to bin off + bin; lanes with equal
+// bins are summed first (one 64-bit atomic per distinct bin and array).
+// Integer sums: the result is the same as one atomic per lane.  All lanes
+// call; the loop runs once per distinct bin.
+__device__ inline void tally_aggregated(const TransportArgs& T, size_t off, uint64_t m, uint32_t bin,
+                                        long long w, long long w2, int lane) {
+    while (m != 0) {
+        const int lead = __builtin_ctzll(m);
+        const uint32_t key = __builtin_amdgcn_readlane(bin, lead);
+        const uint64_t grp = __ballot(bin == key) & m;
+        long long s = 0, s2 = 0;
+        for (uint64_t g = grp; g != 0; g &= g - 1) {
+            const int l = __builtin_ctzll(g);
+            s += readlane64(w, l);
+            s2 += readlane64(w2, l);
+        }
+        if (lane == lead) {
+            atomicAdd((unsigned long long*)(T.tally + off + key), (unsigned long long)s);
+            if (T.tally_sq) atomicAdd((unsigned long long*)(T.tally_sq + off + key), (unsigned long long)s2);
+        }
+        m &= ~grp;
+    }
+}
+
 // Problem-local work index of (view, hist): view-major order.
 __device__ __forceinline__ uint64_t work_of(const Cst& C, uint64_t view, uint64_t hist) {
     return view * C.q_per_view + min(view, C.r_extra) + hist;
@@ -411,21 +442,27 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             // fate counts through ballots: wave-uniform, no per-lane counters
 #pragma unroll
             for (int f = 0; f < 7; ++f) fc[f] += (uint32_t)__popcll(__ballot(fate == f));
-            if (!FD && fate == MC_TALLIED) {
-                const int cls = L.n_scatter > 0 ? 1 : 0;
-                const uint32_t bin = (uint32_t)((((uint32_t)L.view * 2u + cls) * (uint32_t)C.nv + iv) *
-                                                (uint32_t)C.nu + iu);
-                const size_t gb = C.tally_offset + bin;
-                const long long w = signed_weight(T.descs + p, L.emit_voxel,
-                                                  VR ? __float2ll_rn(L.w * 4294967296.0f) : 1ll << 32);
-                atomicAdd((unsigned long long*)(T.tally + gb), (unsigned long long)w);
-                if (T.tally_sq)   // Q31.32 for unit weights; Q11.52 for weighted arrivals
-                    atomicAdd((unsigned long long*)(T.tally_sq + gb),
-                              VR ? (unsigned long long)__float2ll_rn(L.w * L.w * 4503599627370496.0f)
-                                 : 1ull << 32);
+            const uint64_t tallied = FD ? 0ull : __ballot(fate == MC_TALLIED);
+            if (tallied != 0) {
+                // arrivals: bin, weight (Q31.32) and squared weight (Q31.32 for
+                // unit weights, Q11.52 for weighted arrivals)
+                uint32_t bin = 0;
+                long long w = 0, w2 = 0;
+                if (fate == MC_TALLIED) {
+                    const int cls = L.n_scatter > 0 ? 1 : 0;
+                    bin = (uint32_t)((((uint32_t)L.view * 2u + cls) * (uint32_t)C.nv + iv) * (uint32_t)C.nu + iu);
+                    w = signed_weight(T.descs + p, L.emit_voxel,
+                                      VR ? __float2ll_rn(L.w * 4294967296.0f) : 1ll << 32);
+                    w2 = VR ? __float2ll_rn(L.w * L.w * 4503599627370496.0f) : 1ll << 32;
+                }
+                tally_aggregated(T, C.tally_offset, tallied, bin, w, w2, lane);
                 if (T.events) {       // without a list the count is the flushed fate count
-                    const unsigned long long idx = atomicAdd(T.n_events, 1ull);
-                    if (idx < T.event_capacity) {
+                    // one reservation for the wave's arrivals, then one record per lane
+                    unsigned long long base = 0;
+                    if (lane == 0) base = atomicAdd(T.n_events, (unsigned long long)__popcll(tallied));
+                    base = uniform64(base);
+                    const unsigned long long idx = base + (unsigned long long)__popcll(tallied & lane_lt);
+                    if (fate == MC_TALLIED && idx < T.event_capacity) {
                         mc_event ev;
                         ev.work = T.work_prefix[p] + (work_of(C, L.view, L.hist) - C.work_begin);
                         ev.bin = bin;

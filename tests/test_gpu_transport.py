@@ -163,6 +163,48 @@ def test_vacuum_geometric_efficiency():
     assert abs(z) < 4
 
 
+@pytest.mark.parametrize("forced_direction", [False, True])
+def test_wave_aggregated_tally_equals_per_arrival_sum(forced_direction):
+    """Arrivals of one wavefront that share a bin are summed before one atomic
+    (Sec. 2 tallies): a point source in vacuum with a wide cone on an 8x8
+    detector of 2 cm pixels puts many arrivals of each wavefront into the same
+    few bins.  Every bin of the tally (and of the squared tally) must equal
+    the sum over that bin's listed arrivals, whose records are written one per
+    lane."""
+    mc = _mc()
+    n = 16
+    mu = np.zeros((n, n, n), np.float32)
+    act = np.zeros((n, n, n), np.uint32)
+    act[n // 2, n // 2, n // 2] = 1
+    alpha = math.radians(20.0)
+    p = phantoms.point_source_cube("vac_agg", n, 1.0, 300_000, nu=8, pixel_cm=2.0).with_(
+        mu=mu, activity=act, accept_half_angle_rad=alpha)
+    opts = {"variance_reduction": 1, "forced_direction_half_angle": alpha} if forced_direction else None
+    sim = mc.simulate(mc.to_device(p), event_capacity=400_000, options=opts)
+    ev = sim.events_numpy()
+    n_tallied = int(sim.fates[0, 5].item())
+    assert len(ev) == int(sim.n_events.item()) == n_tallied
+    assert n_tallied > (p.n_histories // 2 if forced_direction else 5000)
+    tally = sim.tally.cpu().numpy().astype(np.int64)
+    sq = sim.tally_sq.cpu().numpy().astype(np.int64)
+    bins = ev["bin"].astype(np.int64)
+    count = np.bincount(bins, minlength=tally.size)
+    wsum = np.zeros(tally.size, dtype=np.int64)
+    np.add.at(wsum, bins, ev["weight"].astype(np.int64))
+    np.testing.assert_array_equal(tally, wsum)
+    if forced_direction:
+        # one weight for every arrival (no interaction in vacuum): the squared
+        # tally is the count times one Q11.52 square
+        hit = count > 0
+        per = sq[hit] // count[hit]
+        assert np.all(per * count[hit] == sq[hit]) and np.all(per == per[0]) and per[0] > 0
+        assert np.all(sq[~hit] == 0)
+    else:
+        np.testing.assert_array_equal(sq, tally)
+    say(f"aggregated tally ({'forced direction' if forced_direction else 'analog'}): {n_tallied} "
+        f"arrivals in {int((count > 0).sum())} bins, largest bin {int(count.max())}")
+
+
 def test_run_to_run_and_option_independence():
     mc = _mc()
     p = phantoms.thorax_problem("thorax_64", 64, 0.6, 2, 60, 180.0, 64, 0.6, 1_000_000)

@@ -15,10 +15,12 @@ from typing import List, Optional, Sequence, Union
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmcspect.so")
+# MCSPECT_LIB names another build of the same sources (the region-profile
+# build of region_profile.py); by default the product library.
+LIB_PATH = os.environ.get("MCSPECT_LIB") or os.path.join(_HERE, "libmcspect.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"libmcspect.so not built at {LIB_PATH}; run paper_2105_13324_amd.build.build()")
+    raise ImportError(f"{os.path.basename(LIB_PATH)} not built at {LIB_PATH}; run paper_2105_13324_amd.build.build()")
 
 # torch first: it loads its HIP runtime (soname libamdhip64.so.7), and the
 # library's own dependency then binds to that same copy.  Two HIP runtimes in

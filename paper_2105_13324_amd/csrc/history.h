@@ -439,6 +439,7 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
     uint32_t raw = 0;
     float xn = 0.0f, yn = 0.0f, zn = 0.0f;
     if (state == S_STEP) {
+        MC_REGION(RG_STEP);
         L.n += 1;
         if (L.n > C.max_steps) {
             L.n -= 1;
@@ -461,6 +462,7 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
             // wavefront runs it once when lanes leave both ways)
             const bool box_exit = inside && C.box_margin && leaves_box(C, ix, iy, iz, L.dx, L.dy, L.dz);
             if (!inside || box_exit) {
+                MC_REGION(RG_ESCAPE);
                 if (box_exit) { L.x = xn; L.y = yn; L.z = zn; }
                 fate = escape(C, L, iu, iv);
             }
@@ -468,6 +470,7 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
             // phase can reuse its destination register while it is in flight
             pending = inside && !box_exit;
             if (pending) {
+                MC_REGION(RG_GATHER);
                 const uint32_t k = brick_index((uint32_t)ix, (uint32_t)iy, (uint32_t)iz, (uint32_t)C.nx,
                                                (uint32_t)C.ny, C.brick, C.bmask, C.nbx, C.nby);
                 raw = C.use_pal ? (uint32_t)ldg(C.q8 + k) : ldg(C.q32 + k);
@@ -477,6 +480,7 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
     // (2) Kahn's rejection sampler for x = E/E' on [1, 1+2k], k = E / m_e c^2
     bool new_energy = false;
     if (state == S_KAHN) {
+        MC_REGION(RG_KAHN);
         A.n_kahn++;
         const float k = L.e * INV_MEC2;
         const float ik = MEC2_F * rcpf(L.e);
@@ -495,6 +499,7 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
             L.a += 1;
             if (L.a >= KAHN_MAX) fate = MC_CAPPED_FATE;
         } else {
+            MC_REGION(RG_KAHN_ACCEPT);
             const float ct = 1.0f - (xx - 1.0f) * ik;
             L.e = L.e * ixx;
             L.n_scatter += 1;
@@ -509,9 +514,11 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
     }
     // (3) the tentative collision is real iff (r >> 8) < Q_v
     if (pending) {
+        MC_REGION(RG_ACCEPT_TEST);
         const uint32_t q = C.use_pal ? pal[raw] : raw;
         L.x = xn; L.y = yn; L.z = zn;
         if ((w1 >> 8) < q) {
+            MC_REGION(RG_REAL);
             A.n_real++;
             if (fi) L.w *= 1.0f - L.p_pe;
             else if (unif(w2) < L.p_pe) fate = MC_ABSORBED;
@@ -523,7 +530,10 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
         }
     }
     // (4) flight scale and photoelectric share at the new energy
-    if (new_energy) energy_terms(C, L.e, L.ln2_mm, L.p_pe);
+    if (new_energy) {
+        MC_REGION(RG_ENERGY_TERMS);
+        energy_terms(C, L.e, L.ln2_mm, L.p_pe);
+    }
     return fate;
 }
 

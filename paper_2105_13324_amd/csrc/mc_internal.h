@@ -8,6 +8,57 @@
 
 namespace mcs {
 
+// ---------------------------------------------------------------------------
+// Region profile of the transport loop (measurement build only: compiled with
+// -DMC_REGION_PROFILE into libmcspect_prof.so).  Each marker charges the
+// shader-clock time since the wave's previous marker to the previous region
+// and counts one wave-level entry of the new one, in LDS per wave; the
+// transport kernel adds the totals to a device array at its end
+// (mc_region_profile).  The markers cost about as much as a short region, so
+// the entry counts are exact while the times carry that overhead.
+// ---------------------------------------------------------------------------
+enum Region : int {
+    RG_LOOP = 0, RG_REFILL, RG_EMIT, RG_BEGIN, RG_EXIT_TEST, RG_PHILOX, RG_STEP, RG_ESCAPE, RG_GATHER,
+    RG_KAHN, RG_KAHN_ACCEPT, RG_ACCEPT_TEST, RG_REAL, RG_ENERGY_TERMS, RG_FATE_ENERGY, RG_WORK_COUNT,
+    RG_FATES, RG_TALLY, RG_FORCED, RG_COUNT
+};
+#ifdef MC_REGION_PROFILE
+constexpr int RG_SLOTS = RG_COUNT + 1;      // + the time before the first marker
+static __device__ unsigned long long g_region_count[RG_SLOTS];
+static __device__ unsigned long long g_region_cycles[RG_SLOTS];
+// k >= 0: enter region k; -1: start (zero the wave's LDS totals); -2: add them
+// to the device totals.  Kernels other than the transport loop that share the
+// marked functions only touch their own LDS copy, which is never read back.
+__device__ inline void region_mark(int k) {
+    __shared__ unsigned long long rg_cyc[4][RG_SLOTS], rg_cnt[4][RG_SLOTS], rg_last[4];
+    __shared__ int rg_cur[4];
+    const unsigned long long m = __ballot(1);
+    const int w = (int)(threadIdx.x >> 6);
+    if (w >= 4 || (threadIdx.x & 63) != (unsigned)(__ffsll((long long)m) - 1)) return;
+    const unsigned long long t = __builtin_amdgcn_s_memtime();
+    if (k == -1) {
+        for (int i = 0; i < RG_SLOTS; ++i) rg_cyc[w][i] = rg_cnt[w][i] = 0;
+        rg_cur[w] = RG_COUNT;
+    } else {
+        const int c = (unsigned)rg_cur[w] < (unsigned)RG_SLOTS ? rg_cur[w] : RG_COUNT;
+        rg_cyc[w][c] += t - rg_last[w];
+        if (k == -2) {
+            for (int i = 0; i < RG_SLOTS; ++i) {
+                atomicAdd(&g_region_cycles[i], rg_cyc[w][i]);
+                atomicAdd(&g_region_count[i], rg_cnt[w][i]);
+            }
+        } else {
+            rg_cnt[w][k] += 1;
+            rg_cur[w] = k;
+        }
+    }
+    rg_last[w] = t;
+}
+#define MC_REGION(k) ::mcs::region_mark(k)
+#else
+#define MC_REGION(k) ((void)0)
+#endif
+
 // Everything a kernel needs about one problem.  Host-filled fields come from
 // mc_problem; the staging kernels fill the rest on the device.
 struct ProbDesc {

@@ -276,13 +276,16 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
     const uint64_t* __restrict__ chunk_prefix = T.work_prefix + (T.n_problems + 1);
     const uint64_t n_chunks = chunk_prefix[T.n_problems];
 
+    MC_REGION(-1);
     for (;;) {
+        MC_REGION(RG_LOOP);
         // Refill: at most one chunk claim and one emission phase per iteration;
         // idle lanes not served wait for the next one.  Lanes only pick a
         // staged slot here and load it below, outside any loop.
         const uint64_t need = __ballot(L.state == S_IDLE);
         int slot = -1;
         if (need != 0 && !exhausted) {
+            MC_REGION(RG_REFILL);
             bool ready = true;
             if (s_next >= s_end) {
                 // stage empty: emit the next batch of the chunk (claim one if needed)
@@ -333,6 +336,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                     }
                 }
                 if (ready && c_next < c_end) {
+                    MC_REGION(RG_EMIT);
                     const uint32_t n_rec = (uint32_t)min((uint64_t)EMIT_BATCH, c_end - c_next);
                     if (fd_list && ev_count > EV_STAGE - EMIT_BATCH) flush_events(T, ev_stage, ev_count, lane);
 #pragma unroll 1
@@ -378,6 +382,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             }
         }
         if (slot >= 0) {
+            MC_REGION(RG_BEGIN);
             const EmitRec r = my[slot];
             Emission e;
             e.x = r.x; e.y = r.y; e.z = r.z; e.dx = r.dx; e.dy = r.dy; e.dz = r.dz;
@@ -385,17 +390,20 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             begin_history(C, L, r.view, r.hist, e);
             if (vr_dir) L.w = 0.5f * T.vr_omc;     // Omega / (4 pi)
         }
+        MC_REGION(RG_EXIT_TEST);
         if (exhausted && __ballot(L.state != S_IDLE) == 0 && (!FD || fd_tail == fd_head)) break;
 
         int fate = R_RUNNING;
         int iu = -1, iv = -1;
         const int before = L.state;
         if (before != S_IDLE) {
+            MC_REGION(RG_PHILOX);
             uint32_t c0 = L.hist, c1 = (uint32_t)L.view, c2, c3;
             counter_of(L, c2, c3);
             philox10(c0, c1, c2, c3, C.seed, C.pid);
             fate = advance(C, my_pal, L, c0, c1, c2, c3, A, iu, iv, vr_fi);
             if (fate != R_RUNNING) {
+                MC_REGION(RG_FATE_ENERGY);
                 // outgoing energy: escaped, or left at the step cap (rare: booked at once)
                 const float out = ((fate == MC_ABSORBED) | (fate == MC_CUT)) ? 0.0f : L.e;
                 if (fate == MC_CAPPED_FATE) {
@@ -409,6 +417,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
         }
         // work counters by ballot: a tentative collision unless the step cap
         // stopped it; a real one if it absorbed or started a Compton scatter
+        MC_REGION(RG_WORK_COUNT);
         const bool real = (before == S_STEP) &
                           ((fate == MC_ABSORBED) | ((fate == R_RUNNING) & (L.state == S_KAHN)));
         wc[0] += (uint32_t)__popcll(__ballot((before == S_STEP) & (fate != MC_CAPPED_FATE)));
@@ -431,6 +440,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             // the one place forced copies of collisions are scored (one code
             // path, so a score never depends on where it was drained): 64 at
             // a time, or what is left once no lane is busy
+            MC_REGION(RG_FORCED);
             const uint32_t cnt = fd_tail - fd_head;
             if (cnt >= 64 || (cnt != 0 && __ballot(L.state != S_IDLE) == 0)) {
                 if (fd_list && ev_count > EV_STAGE - 64) flush_events(T, ev_stage, ev_count, lane);
@@ -439,11 +449,13 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             }
         }
         if (__ballot(fate != R_RUNNING) != 0) {
+            MC_REGION(RG_FATES);
             // fate counts through ballots: wave-uniform, no per-lane counters
 #pragma unroll
             for (int f = 0; f < 7; ++f) fc[f] += (uint32_t)__popcll(__ballot(fate == f));
             const uint64_t tallied = FD ? 0ull : __ballot(fate == MC_TALLIED);
             if (tallied != 0) {
+                MC_REGION(RG_TALLY);
                 // arrivals: bin, weight (Q31.32) and squared weight (Q31.32 for
                 // unit weights, Q11.52 for weighted arrivals)
                 uint32_t bin = 0;
@@ -477,6 +489,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
     }
     if (p >= 0) flush(e_esc, fc, wc, fd_rays, fd_pieces, p, T, lane, count_tallied);
     if (fd_list) flush_events(T, ev_stage, ev_count, lane);
+    MC_REGION(-2);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TransportArgs T) {
@@ -706,3 +719,23 @@ int transport_blocks_per_cu(int block, int forced_detection, int vr_flags) {
 }
 
 }  // namespace mcs
+
+#ifdef MC_REGION_PROFILE
+// Measurement build only: copy the region totals of the transport loop
+// (entries and shader-clock cycles, RG_COUNT + 1 values each; the last is the
+// time before the first marker) to host arrays, or zero them (reset != 0).
+extern "C" int mc_region_profile(unsigned long long* counts, unsigned long long* cycles, int reset) {
+    using namespace mcs;
+    const size_t nb = sizeof(unsigned long long) * RG_SLOTS;
+    if (reset) {
+        unsigned long long z[RG_SLOTS] = {0};
+        hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_region_count), z, nb);
+        if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_region_cycles), z, nb);
+        return (int)e;
+    }
+    if (!counts || !cycles) return MC_EINVAL;
+    hipError_t e = hipMemcpyFromSymbol(counts, HIP_SYMBOL(g_region_count), nb);
+    if (e == hipSuccess) e = hipMemcpyFromSymbol(cycles, HIP_SYMBOL(g_region_cycles), nb);
+    return (int)e;
+}
+#endif

@@ -434,44 +434,57 @@ def extra_forms(mc, torch, args, rates=None):
     return out
 
 
-def adjoint_form(mc, torch, steps, rates=None):
-    """Adjoint step on the 128^3 x 1 mm cube, 1e7 histories: forward with an
-    event list, Poisson-loss gradient, replaying adjoint."""
-    import phantoms
-    p4 = phantoms.point_cube_128_adjoint(10 ** 7)
-    d4 = mc.to_device(p4)
-    ref = mc.simulate(d4.with_(seed=1), want_sq=False)
-    lam_ref = ref.tally.view(p4.tally_shape).to(torch.float64).sum(dim=1) * 2.0 ** -32
+def _adjoint_step_record(mc, torch, prob, steps, rates=None):
+    """Time the adjoint step on one problem: forward with an event list,
+    Poisson-loss gradient against a Poisson target from an independent
+    seed-1 run, replaying adjoint."""
+    dp = mc.to_device(prob)
+    ref = mc.simulate(dp.with_(seed=1), want_sq=False)
+    lam_ref = ref.tally.view(prob.tally_shape).to(torch.float64).sum(dim=1) * 2.0 ** -32
     gen = torch.Generator(device=lam_ref.device)
     gen.manual_seed(4)
     y = torch.poisson(lam_ref, generator=gen)
-    s4 = mc.Simulator(d4, event_capacity=1 << 16, want_sq=False)
+    cap = max(1 << 16, 4 * int(ref.fates[0, 5].item()) + 1024)
+    sim = mc.Simulator(dp, event_capacity=cap, want_sq=False)
+
+    def loss_grad():
+        lam = sim.tally.view(prob.tally_shape).to(torch.float64).sum(dim=1) * 2.0 ** -32
+        eps = 1e-6 * float(prob.n_histories)
+        return (1.0 - y / (lam + eps)).unsqueeze(1).expand(-1, 2, -1, -1).contiguous()
 
     def adjoint_step():
-        s4.run()
-        lam = s4.tally.view(p4.tally_shape).to(torch.float64).sum(dim=1) * 2.0 ** -32
-        eps = 1e-6 * float(p4.n_histories)
-        G = (1.0 - y / (lam + eps)).unsqueeze(1).expand(-1, 2, -1, -1).contiguous()
-        return mc.adjoint(d4, G, s4)
+        sim.run()
+        return mc.adjoint(dp, loss_grad(), sim)
     adjoint_step()
-    ms_fwd = timed(torch, s4.run, steps)
+    ms_fwd = timed(torch, sim.run, steps)
     ms = timed(torch, adjoint_step, steps)
     timers = [mc.KernelTimer() for _ in range(steps)]
     for t in timers:
-        s4.run(kernel_events=t.handles)
+        sim.run(kernel_events=t.handles)
     torch.cuda.synchronize()
     k_fwd = float(np.mean([t.elapsed_ms() for t in timers]))
-    lam = s4.tally.view(p4.tally_shape).to(torch.float64).sum(dim=1) * 2.0 ** -32
-    G = (1.0 - y / (lam + 1e-6 * float(p4.n_histories))).unsqueeze(1).expand(-1, 2, -1, -1).contiguous()
-    ms_adj = timed(torch, lambda: mc.adjoint(d4, G, s4), steps)
-    return {"value": p4.n_histories / (ms / 1e3), "unit": "histories/s",
+    G = loss_grad()
+    ms_adj = timed(torch, lambda: mc.adjoint(dp, G, sim), steps)
+    return {"value": prob.n_histories / (ms / 1e3), "unit": "histories/s",
             "ms_per_step": ms, "forward_ms": ms_fwd, "adjoint_call_ms": ms_adj,
-            "histories": p4.n_histories, "tallied": int(s4.n_events.item()),
+            "histories": prob.n_histories, "tallied": int(sim.n_events.item()),
             "step": "forward with event list + Poisson-loss gradient + replaying adjoint",
-            "roofline": transport_roofline(s4, k_fwd, rates),
-            "roofline_note": "dominant kernel: the forward transport; the adjoint call replays "
-                             "only the tallied histories, one wavefront each with the segment "
-                             "walks split over its lanes, and reads its status back once"}
+            "roofline": transport_roofline(sim, k_fwd, rates)}
+
+
+def adjoint_form(mc, torch, steps, rates=None):
+    """Adjoint step on the 128^3 x 1 mm cube, 1e7 histories (primary), and
+    on the 128^3 x 3 mm headline thorax with 60 views, 1e7 histories
+    (secondary)."""
+    import phantoms
+    rec = _adjoint_step_record(mc, torch, phantoms.point_cube_128_adjoint(10 ** 7), steps, rates)
+    rec["roofline_note"] = ("dominant kernel: the forward transport; the adjoint call replays "
+                            "only the tallied histories, one wavefront each with the segment "
+                            "walks split over its lanes, and reads its status back once")
+    sec = _adjoint_step_record(mc, torch, phantoms.thorax_128(10 ** 7), steps, rates)
+    sec["workload"] = "thorax_128: 128^3 x 3 mm thorax, 60 views, 1e7 histories"
+    rec["secondary"] = sec
+    return rec
 
 
 def batched_form(mc, torch, steps, rates=None):

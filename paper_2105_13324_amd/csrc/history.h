@@ -436,8 +436,8 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
     int fate = R_RUNNING;
     // (1) tentative collision n + 1: flight -log(u)/mu_max, the new point
     bool pending = false;
-    uint32_t raw = 0;
-    float xn = 0.0f, yn = 0.0f, zn = 0.0f;
+    uint32_t raw;               // set, with xn..zn, wherever pending is
+    float xn, yn, zn;
     if (state == S_STEP) {
         MC_REGION(RG_STEP);
         L.n += 1;

@@ -394,7 +394,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
         if (exhausted && __ballot(L.state != S_IDLE) == 0 && (!FD || fd_tail == fd_head)) break;
 
         int fate = R_RUNNING;
-        int iu = -1, iv = -1;
+        int iu, iv;               // set by the escape of a history that arrives
         const int before = L.state;
         if (before != S_IDLE) {
             MC_REGION(RG_PHILOX);

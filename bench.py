@@ -67,11 +67,11 @@ def table_ops(n_hist, n_tent, n_kahn, n_real, cost=None):
 # counters read for a plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); keyed
 # by a hash of the kernel sources so a changed kernel reports null.
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
-TRAFFIC_KIB = {"6444ebc0c4fdb25c": {"fetch": 5929.0, "write": 5326.25}}
+TRAFFIC_KIB = {"59f7d00faafcfc34": {"fetch": 5924.44, "write": 4983.5}}
 # rocprofv3 --pmc SQ_INSTS_VALU of the same launch (and the dispatch time of
 # that run), keyed like the traffic
-VALU_COUNTERS = {"6444ebc0c4fdb25c": {"workload": "thorax_128", "SQ_INSTS_VALU": 2.38873e9,
-                                      "kernel_ms": 4.6169}}
+VALU_COUNTERS = {"59f7d00faafcfc34": {"workload": "thorax_128", "SQ_INSTS_VALU": 2.07745e9,
+                                      "kernel_ms": 4.2973}}
 
 
 def kernel_source_hash() -> str:
@@ -423,14 +423,19 @@ def extra_forms(mc, torch, args, rates=None):
     out["point_cube_64"] = {"value": p1.n_histories / (ms / 1e3), "unit": "histories/s",
                             "ms_per_step": ms, "eager_ms_per_step": ms_eager,
                             "histories": p1.n_histories, "launch": "hipGraph replay of one call"}
-    out["batched"] = batched_form(mc, torch, steps, rates)
-    out["adjoint"] = adjoint_form(mc, torch, steps, rates)
-    out["forced_detection"] = fd_form(mc, torch, steps)
-    out["reuse_of_photon_tracks"] = rpt_form(mc, torch, steps)
-    out["coarse_grid_scatter"] = cgsm_form(mc, torch, steps)
-    out["tl201_dual_window"] = tl201_form(mc, torch, steps)
+    forms = [("batched", lambda: batched_form(mc, torch, steps, rates)),
+             ("adjoint", lambda: adjoint_form(mc, torch, steps, rates)),
+             ("forced_detection", lambda: fd_form(mc, torch, steps)),
+             ("reuse_of_photon_tracks", lambda: rpt_form(mc, torch, steps)),
+             ("coarse_grid_scatter", lambda: cgsm_form(mc, torch, steps)),
+             ("tl201_dual_window", lambda: tl201_form(mc, torch, steps))]
     if not args.no_large:
-        out["large_mlem"] = large_form(mc, torch, steps)
+        forms.append(("large_mlem", lambda: large_form(mc, torch, steps)))
+    for name, run in forms:
+        t = time.perf_counter()
+        out[name] = run()
+        # progress on stderr: the JSON line on stdout stays the only output there
+        print(f"bench: form {name} done in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
     return out
 
 

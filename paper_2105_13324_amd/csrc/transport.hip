@@ -467,7 +467,19 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                                       VR ? __float2ll_rn(L.w * 4294967296.0f) : 1ll << 32);
                     w2 = VR ? __float2ll_rn(L.w * L.w * 4503599627370496.0f) : 1ll << 32;
                 }
-                tally_aggregated(T, C.tally_offset, tallied, bin, w, w2, lane);
+                if constexpr (VR) {
+                    // weighted runs (forced direction) tally most histories, in
+                    // bins that are nearly all distinct within a wavefront: one
+                    // atomic per lane (the matching loop took 0.99 against 0.75 ms)
+                    if (fate == MC_TALLIED) {
+                        atomicAdd((unsigned long long*)(T.tally + C.tally_offset + bin), (unsigned long long)w);
+                        if (T.tally_sq)
+                            atomicAdd((unsigned long long*)(T.tally_sq + C.tally_offset + bin),
+                                      (unsigned long long)w2);
+                    }
+                } else {
+                    tally_aggregated(T, C.tally_offset, tallied, bin, w, w2, lane);
+                }
                 if (T.events) {       // without a list the count is the flushed fate count
                     // one reservation for the wave's arrivals, then one record per lane
                     unsigned long long base = 0;

@@ -165,11 +165,12 @@ def test_vacuum_geometric_efficiency():
 
 @pytest.mark.parametrize("forced_direction", [False, True])
 def test_wave_aggregated_tally_equals_per_arrival_sum(forced_direction):
-    """Arrivals of one wavefront that share a bin are summed before one atomic
-    (Sec. 2 tallies): a point source in vacuum with a wide cone on an 8x8
-    detector of 2 cm pixels puts many arrivals of each wavefront into the same
-    few bins.  Every bin of the tally (and of the squared tally) must equal
-    the sum over that bin's listed arrivals, whose records are written one per
+    """Analog arrivals of one wavefront that share a bin are summed before one
+    atomic (Sec. 2 tallies); weighted arrivals (forced direction) keep one
+    atomic each.  A point source in vacuum with a wide cone on an 8x8 detector
+    of 2 cm pixels puts many arrivals of each wavefront into the same few
+    bins.  Every bin of the tally (and of the squared tally) must equal the
+    sum over that bin's listed arrivals, whose records are written one per
     lane."""
     mc = _mc()
     n = 16

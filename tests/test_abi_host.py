@@ -41,6 +41,23 @@ def test_library_exports_every_declared_symbol():
         assert re.search(r"\bT %s\b" % name, out), name
 
 
+def test_region_profile_only_in_the_measurement_build():
+    """mc_region_profile (the transport loop's region markers) exists only in
+    libmcspect_prof.so; the product library carries no marker code."""
+    mc = _mc()
+    prof = os.path.join(os.path.dirname(mc.LIB_PATH), "libmcspect_prof.so")
+    out = subprocess.run(["nm", "-D", "--defined-only", mc.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    assert "mc_region_profile" not in out
+    if not os.path.exists(prof):
+        pytest.skip("measurement build not built (python paper_2105_13324_amd/build.py --profile)")
+    out = subprocess.run(["nm", "-D", "--defined-only", prof], capture_output=True,
+                         text=True, check=True).stdout
+    assert re.search(r"\bT mc_region_profile\b", out)
+    for name in declared_functions():
+        assert re.search(r"\bT %s\b" % name, out), name
+
+
 def _layout_src(mc):
     fields = " ".join("F(mc_problem, %s)" % n for n, _ in mc.McProblem._fields_)
     return r"""

@@ -376,6 +376,32 @@ int mlem_iterate(int64_t n_bins, int64_t n_vox, int64_t nnz,
                  const float* proj, float* image, int32_t n_iter,
                  void* workspace, size_t workspace_bytes, void* stream);
 
+/* mlem_iterate in two parts, for many reconstructions with one matrix
+ * (Sec. 5.1: the matrix is fixed while the image is iterated).
+ * mlem_prepare does the matrix's share once: the sensitivities sum_j T_ij,
+ * the lists of non-empty rows, the renumbered columns of the compact layout
+ * and the bin slices, all kept in the workspace together with the entry-count
+ * check and a fingerprint (n_bins, n_vox, nnz).  mlem_iterate_prepared then
+ * runs n_iter updates exactly as mlem_iterate does (same results bit for
+ * bit) without repeating that set-up: the arguments are mlem_iterate's, and
+ * the matrix (structure and values) must be the one prepared in this
+ * workspace, which must not be used for another matrix in between.  A call
+ * whose sizes or entry count differ from the prepared fingerprint, or on a
+ * matrix whose entry check failed, sweeps nothing and leaves the image NaN
+ * (a workspace never prepared holds no valid fingerprint only by chance: pass
+ * a prepared one).  proj and image may change from call to call.  Both are
+ * asynchronous on stream, allocate nothing and can be captured in a graph.
+ * Errors: as mlem_iterate (mlem_prepare takes no proj, image or n_iter). */
+int mlem_prepare(int64_t n_bins, int64_t n_vox, int64_t nnz,
+                 const int64_t* T_rowptr, const int32_t* T_col, const float* T_val,
+                 const int64_t* Tt_rowptr, const int32_t* Tt_col, const float* Tt_val,
+                 void* workspace, size_t workspace_bytes, void* stream);
+int mlem_iterate_prepared(int64_t n_bins, int64_t n_vox, int64_t nnz,
+                          const int64_t* T_rowptr, const int32_t* T_col, const float* T_val,
+                          const int64_t* Tt_rowptr, const int32_t* Tt_col, const float* Tt_val,
+                          const float* proj, float* image, int32_t n_iter,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
 /* Workspace bytes of osem_iterate. */
 size_t osem_workspace_bytes(int64_t n_bins, int64_t n_vox, int32_t n_subsets);
 

@@ -41,7 +41,8 @@ Q52 = float(2 ** 52)   # forced-detection sum of squared scores: Q11.52
 EXPORTS = ["mc_workspace_bytes", "mc_simulate_projections", "mc_simulate_projections_static",
            "mc_replay_histories",
            "mc_adjoint_mu", "mc_system_matrix_workspace_bytes", "mc_system_matrix",
-           "mlem_workspace_bytes", "mlem_iterate", "osem_workspace_bytes", "osem_iterate",
+           "mlem_workspace_bytes", "mlem_iterate", "mlem_prepare", "mlem_iterate_prepared",
+           "osem_workspace_bytes", "osem_iterate",
            "mc_block_activity", "mc_expand_projection", "mc_source_total", "mc_scale_tally",
            "mc_graph_begin", "mc_graph_end", "mc_graph_launch", "mc_graph_destroy", "mc_autotune",
            "mc_check_status", "mc_error_string", "mc_last_hip_error"]
@@ -113,6 +114,10 @@ _lib.mlem_workspace_bytes.restype = _sz
 _lib.mlem_iterate.argtypes = [_i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp,
                               _sz, _vp]
 _lib.mlem_iterate.restype = C.c_int
+_lib.mlem_iterate_prepared.argtypes = _lib.mlem_iterate.argtypes
+_lib.mlem_iterate_prepared.restype = C.c_int
+_lib.mlem_prepare.argtypes = [_i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.mlem_prepare.restype = C.c_int
 _lib.mc_block_activity.argtypes = [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]
 _lib.mc_block_activity.restype = C.c_int
 _lib.mc_expand_projection.argtypes = [_vp, _i64, _i32, _i32, _i32, C.c_double, _vp, _vp]
@@ -886,7 +891,9 @@ def system_matrix(problem: DeviceProblem, sim: Simulator, classes: str = "all") 
 
 
 class Mlem:
-    """mlem_iterate on fixed CSR buffers (workspace allocated once)."""
+    """MLEM on fixed CSR buffers: the workspace is allocated and the matrix's
+    set-up (mlem_prepare) done once; each run is mlem_iterate_prepared.  The
+    matrix must not change while this object is used (build a new one)."""
 
     def __init__(self, m: SystemMatrix):
         torch = _torch()
@@ -896,15 +903,31 @@ class Mlem:
             raise McError("mlem_workspace_bytes: invalid sizes")
         self.ws = torch.empty(nb, dtype=torch.uint8, device=m.T_val.device)
         self.nnz = m.nnz                          # read once: it picks the schedule
+        rc = _lib.mlem_prepare(m.n_bins, m.n_img, self.nnz, *self._csr(), self.ws.data_ptr(), self.ws.numel(),
+                               _stream_ptr())
+        _check(rc, "mlem_prepare")
+
+    def _csr(self):
+        m = self.m
+        return (m.T_rowptr.data_ptr(), m.T_col.data_ptr(), m.T_val.data_ptr(), m.Tt_rowptr.data_ptr(),
+                m.Tt_col.data_ptr(), m.Tt_val.data_ptr())
 
     def run(self, image, n_iter: int, proj=None):
         """image: float32 device tensor [n_img], S^0 in, S^n_iter out (in place)."""
         m = self.m
         P = m.proj if proj is None else proj
-        rc = _lib.mlem_iterate(m.n_bins, m.n_img, self.nnz, m.T_rowptr.data_ptr(), m.T_col.data_ptr(),
-                               m.T_val.data_ptr(), m.Tt_rowptr.data_ptr(), m.Tt_col.data_ptr(),
-                               m.Tt_val.data_ptr(), P.data_ptr(), image.data_ptr(), int(n_iter),
-                               self.ws.data_ptr(), self.ws.numel(), _stream_ptr())
+        rc = _lib.mlem_iterate_prepared(m.n_bins, m.n_img, self.nnz, *self._csr(), P.data_ptr(),
+                                        image.data_ptr(), int(n_iter), self.ws.data_ptr(), self.ws.numel(),
+                                        _stream_ptr())
+        _check(rc, "mlem_iterate_prepared")
+        return image
+
+    def run_unprepared(self, image, n_iter: int, proj=None):
+        """The same update through mlem_iterate (set-up repeated in the call)."""
+        m = self.m
+        P = m.proj if proj is None else proj
+        rc = _lib.mlem_iterate(m.n_bins, m.n_img, self.nnz, *self._csr(), P.data_ptr(), image.data_ptr(),
+                               int(n_iter), self.ws.data_ptr(), self.ws.numel(), _stream_ptr())
         _check(rc, "mlem_iterate")
         return image
 

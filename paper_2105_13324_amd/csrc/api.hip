@@ -500,20 +500,44 @@ size_t mlem_workspace_bytes(int64_t n_bins, int64_t n_vox) {
     return mlem_workspace((uint64_t)n_bins, (uint64_t)n_vox);
 }
 
+static int mlem_call(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t* T_rowptr,
+                     const int32_t* T_col, const float* T_val, const int64_t* Tt_rowptr,
+                     const int32_t* Tt_col, const float* Tt_val, const float* proj, float* image,
+                     int32_t n_iter, void* workspace, size_t workspace_bytes, void* stream, int phases) {
+    const bool iterate = (phases & MLEM_ITERATE) != 0;
+    if (n_bins < 1 || n_vox < 1 || nnz < 0 || n_iter < 0) return MC_EINVAL;
+    if (n_bins >= (1ll << 31) || n_vox >= (1ll << 31)) return MC_EINVAL;
+    if (!T_rowptr || !T_col || !T_val || !Tt_rowptr || !Tt_col || !Tt_val || !workspace) return MC_EINVAL;
+    if (iterate && (!proj || !image)) return MC_EINVAL;
+    if (workspace_bytes < mlem_workspace((uint64_t)n_bins, (uint64_t)n_vox)) return MC_ENOMEM;
+    hipError_t e = launch_mlem(n_bins, n_vox, nnz, T_rowptr, T_col, T_val, Tt_rowptr, Tt_col, Tt_val,
+                               proj, image, n_iter, workspace, phases, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return MC_OK;
+}
+
 int mlem_iterate(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t* T_rowptr,
                  const int32_t* T_col, const float* T_val, const int64_t* Tt_rowptr,
                  const int32_t* Tt_col, const float* Tt_val, const float* proj, float* image,
                  int32_t n_iter, void* workspace, size_t workspace_bytes, void* stream) {
-    if (n_bins < 1 || n_vox < 1 || nnz < 0 || n_iter < 0) return MC_EINVAL;
-    if (n_bins >= (1ll << 31) || n_vox >= (1ll << 31)) return MC_EINVAL;
-    if (!T_rowptr || !T_col || !T_val || !Tt_rowptr || !Tt_col || !Tt_val || !proj || !image ||
-        !workspace)
-        return MC_EINVAL;
-    if (workspace_bytes < mlem_workspace((uint64_t)n_bins, (uint64_t)n_vox)) return MC_ENOMEM;
-    hipError_t e = launch_mlem(n_bins, n_vox, nnz, T_rowptr, T_col, T_val, Tt_rowptr, Tt_col, Tt_val,
-                               proj, image, n_iter, workspace, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e);
-    return MC_OK;
+    return mlem_call(n_bins, n_vox, nnz, T_rowptr, T_col, T_val, Tt_rowptr, Tt_col, Tt_val, proj, image,
+                     n_iter, workspace, workspace_bytes, stream, MLEM_SETUP | MLEM_ITERATE);
+}
+
+int mlem_prepare(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t* T_rowptr,
+                 const int32_t* T_col, const float* T_val, const int64_t* Tt_rowptr,
+                 const int32_t* Tt_col, const float* Tt_val, void* workspace, size_t workspace_bytes,
+                 void* stream) {
+    return mlem_call(n_bins, n_vox, nnz, T_rowptr, T_col, T_val, Tt_rowptr, Tt_col, Tt_val, nullptr, nullptr,
+                     0, workspace, workspace_bytes, stream, MLEM_SETUP);
+}
+
+int mlem_iterate_prepared(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t* T_rowptr,
+                          const int32_t* T_col, const float* T_val, const int64_t* Tt_rowptr,
+                          const int32_t* Tt_col, const float* Tt_val, const float* proj, float* image,
+                          int32_t n_iter, void* workspace, size_t workspace_bytes, void* stream) {
+    return mlem_call(n_bins, n_vox, nnz, T_rowptr, T_col, T_val, Tt_rowptr, Tt_col, Tt_val, proj, image,
+                     n_iter, workspace, workspace_bytes, stream, MLEM_ITERATE);
 }
 
 size_t osem_workspace_bytes(int64_t n_bins, int64_t n_vox, int32_t n_subsets) {

@@ -268,10 +268,13 @@ hipError_t launch_sysmat(const mc_event* events, const unsigned long long* n_eve
                          int64_t* Tt_rp, int32_t* Tt_col, float* Tt_val, float* proj,
                          void* workspace, hipStream_t s);
 size_t mlem_workspace(uint64_t n_bins, uint64_t n_vox);
+// launch_mlem phases: the matrix's set-up (row sums, row lists, renumbered
+// columns, kept in the workspace) and the call (load, iterations, image out).
+enum : int { MLEM_SETUP = 1, MLEM_ITERATE = 2 };
 hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t* T_rp,
                        const int32_t* T_col, const float* T_val, const int64_t* Tt_rp,
                        const int32_t* Tt_col, const float* Tt_val, const float* proj, float* image,
-                       int32_t n_iter, void* workspace, hipStream_t s);
+                       int32_t n_iter, void* workspace, int phases, hipStream_t s);
 
 size_t osem_workspace(uint64_t n_bins, uint64_t n_vox, uint32_t n_sub);
 hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n_sub,

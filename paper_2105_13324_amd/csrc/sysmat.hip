@@ -523,30 +523,42 @@ __global__ __launch_bounds__(T256) void k_row_sums(int64_t n_rows, const int64_t
              [&](int64_t r, double acc) { out[r] = acc; });
 }
 
-// Per-call state of mlem_iterate (device uint32 [ST_WORDS]): the lengths of
-// the two row lists, a flag set when the entry count the caller gave is not
-// the matrix's own (the iterations then sweep nothing and the image is NaN),
-// and for the compact layout, per matrix and per (group, length class) key
-// (2 x 32), the rows counted, their first list position and an append cursor.
-enum { ST_BINS = 0, ST_VOXS = 1, ST_BAD = 2, ST_HIST = 4, ST_OFF = 68, ST_CUR = 132, ST_WORDS = 196 };
+// MLEM state in the workspace (device uint32 [ST_WORDS]), written by the
+// set-up of a matrix and kept for every later call on it: the lengths of the
+// two row lists; a flag set when the entry count the caller gave is not the
+// matrix's own; a flag set by each call when it does not match the set-up
+// (its sizes differ from the fingerprint); for the compact layout, per
+// matrix and per (group, length class) key (2 x 32), the rows counted, their
+// first list position and an append cursor; the fingerprint (n_bins, n_vox,
+// nnz).  With either flag set the iterations sweep nothing and the image is
+// NaN.
+enum {
+    ST_BINS = 0, ST_VOXS = 1, ST_BAD = 2, ST_CALL_BAD = 3, ST_HIST = 4, ST_OFF = 68, ST_CUR = 132,
+    ST_FP = 196, ST_WORDS = 200
+};
 
-// S_i = img_i where sens_i > 0, else 0 (row order; in list order the compact
-// layout sets S in k_mlem_compact); the list lengths zeroed, the entry count
-// checked against both row-pointer arrays.
-__global__ __launch_bounds__(T256) void k_mlem_init(int64_t n_bins, int64_t n_vox, int64_t nnz,
-                                                    const int64_t* __restrict__ T_rp,
-                                                    const int64_t* __restrict__ Tt_rp,
-                                                    const float* __restrict__ img,
-                                                    const double* __restrict__ sens,
-                                                    double* __restrict__ S, uint32_t* __restrict__ st,
-                                                    int compact) {
-    if (blockIdx.x == 0 && threadIdx.x < ST_WORDS)
-        st[threadIdx.x] = threadIdx.x != ST_BAD ? 0u
-                                                : (T_rp[n_bins] != nnz || Tt_rp[n_vox] != nnz) ? 1u : 0u;
-    if (compact) return;
-    for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < n_vox;
-         i += (int64_t)gridDim.x * T256)
-        S[i] = sens[i] > 0.0 ? (double)img[i] : 0.0;
+// Set-up: the state zeroed, the entry count checked against both row-pointer
+// arrays, the fingerprint stored (one workgroup).
+__global__ __launch_bounds__(T256) void k_mlem_setup(int64_t n_bins, int64_t n_vox, int64_t nnz,
+                                                     const int64_t* __restrict__ T_rp,
+                                                     const int64_t* __restrict__ Tt_rp,
+                                                     uint32_t* __restrict__ st) {
+    const uint32_t t = threadIdx.x;
+    if (t >= ST_WORDS) return;
+    uint32_t v = 0;
+    if (t == ST_BAD) v = (T_rp[n_bins] != nnz || Tt_rp[n_vox] != nnz) ? 1u : 0u;
+    else if (t == ST_FP) v = (uint32_t)n_bins;
+    else if (t == ST_FP + 1) v = (uint32_t)n_vox;
+    else if (t == ST_FP + 2) v = (uint32_t)(uint64_t)nnz;
+    else if (t == ST_FP + 3) v = (uint32_t)((uint64_t)nnz >> 32);
+    st[t] = v;
+}
+
+// A call's sizes against the set-up's fingerprint (and its entry-count flag).
+__device__ inline bool mlem_call_bad(const uint32_t* __restrict__ st, int64_t n_bins, int64_t n_vox,
+                                     int64_t nnz) {
+    return st[ST_BAD] != 0 || st[ST_FP] != (uint32_t)n_bins || st[ST_FP + 1] != (uint32_t)n_vox ||
+           st[ST_FP + 2] != (uint32_t)(uint64_t)nnz || st[ST_FP + 3] != (uint32_t)((uint64_t)nnz >> 32);
 }
 
 // A non-empty row of a CSR matrix: its index and entry range.
@@ -712,7 +724,8 @@ __device__ inline void sweep_rows(const RowGroups<GS>& G, int64_t n, Bounds boun
 // before its sum; done(q, ref, aux, sum) runs for every listed row.
 template <int GS, class Aux, class Term, class Done>
 __device__ inline void sweep_list(const RowGroups<GS>& G, const RowRef* __restrict__ L, int64_t cap,
-                                  const uint32_t* __restrict__ count, Aux aux, Term term, Done done) {
+                                  const uint32_t* __restrict__ count, const uint32_t* __restrict__ call_bad,
+                                  Aux aux, Term term, Done done) {
     if (G.first >= cap) return;
     RowRef ref[4];
 #pragma unroll
@@ -720,10 +733,12 @@ __device__ inline void sweep_list(const RowGroups<GS>& G, const RowRef* __restri
         const int64_t q = G.first + u * G.step;
         ref[u] = L[q < cap ? q : cap - 1];
     }
-    const uint32_t n32 = *count;
-    // all five loads in flight before any is used (the compiler would
+    const uint32_t n_listed = *count, bad = *call_bad;
+    // all six loads in flight before any is used (the compiler would
     // otherwise issue the rows' loads only once the length test has passed)
-    asm volatile("" ::"v"(ref[0].lo), "v"(ref[1].lo), "v"(ref[2].lo), "v"(ref[3].lo), "s"(n32));
+    asm volatile("" ::"v"(ref[0].lo), "v"(ref[1].lo), "v"(ref[2].lo), "v"(ref[3].lo), "s"(n_listed),
+                 "s"(bad));
+    const uint32_t n32 = bad ? 0u : n_listed;   // a call that does not match the set-up sweeps nothing
     const int64_t n = n32;
     for (int64_t r = G.first; r < n; r += 4 * G.step) {
         if (r != G.first) {
@@ -755,13 +770,14 @@ __device__ inline void sweep_list(const RowGroups<GS>& G, const RowRef* __restri
 template <int GS>
 __global__ __launch_bounds__(T256) void k_mlem_forward(const RowRef* __restrict__ L, int64_t cap,
                                                        const uint32_t* __restrict__ count,
+                                                       const uint32_t* __restrict__ call_bad,
                                                        const int32_t* __restrict__ col,
                                                        const float* __restrict__ val,
                                                        const double* __restrict__ S,
                                                        const float* __restrict__ P,
                                                        double* __restrict__ ratio) {
     const RowGroups<GS> G(blockIdx.x, gridDim.x);
-    sweep_list(G, L, cap, count,
+    sweep_list(G, L, cap, count, call_bad,
                [&](int64_t, bool ok, const RowRef& r) { return P[ok ? r.row : 0]; },
                [&](int64_t k, bool ok) {
                    const double x = (double)val[k] * S[col[k]];
@@ -819,14 +835,15 @@ __global__ __launch_bounds__(T256) void k_mlem_slices(int64_t n_vox, int64_t n_b
 // (an empty row has sens_i = 0, so its S_i is already 0).
 template <int GS>
 __global__ __launch_bounds__(T256) void k_mlem_update(const RowRef* __restrict__ L, int64_t cap,
-                                                      const uint32_t* __restrict__ count,
+                                                       const uint32_t* __restrict__ count,
+                                                       const uint32_t* __restrict__ call_bad,
                                                       const int32_t* __restrict__ col,
                                                       const float* __restrict__ val,
                                                       const double* __restrict__ ratio,
                                                       const double* __restrict__ sens,
                                                       double* __restrict__ S) {
     const RowGroups<GS> G(blockIdx.x, gridDim.x);
-    sweep_list(G, L, cap, count,
+    sweep_list(G, L, cap, count, call_bad,
                [&](int64_t, bool ok, const RowRef& r) {
                    const int64_t i = ok ? r.row : 0;
                    return double2{S[i], sens[i]};
@@ -881,6 +898,15 @@ struct ClassRef {
     int32_t len, pad;
 };
 
+// The entries of a listed row of at most four (length class 0), copied at
+// its list position with columns renumbered: a sweep loads them together
+// with the row's ClassRef instead of after it (one dependent load fewer).
+// Slots past the row's length are unused.
+struct alignas(16) ShortRow {
+    int32_t col[4];
+    float val[4];
+};
+
 // Compact layout (sparse matrices, nnz <= n_bins + n_vox): the iterations
 // keep S, sens, P and the ratio in list order, and the column indices of both
 // matrices are renumbered to list positions (Tc: voxel positions, Ttc: bin
@@ -895,16 +921,29 @@ __global__ __launch_bounds__(T256) void k_mlem_compact(int64_t nnz, const int32_
                                                        int32_t* __restrict__ Tc, int32_t* __restrict__ Ttc,
                                                        const ClassRef* __restrict__ bins,
                                                        const ClassRef* __restrict__ voxs,
-                                                       const float* __restrict__ img,
+                                                       const float* __restrict__ T_val,
+                                                       const float* __restrict__ Tt_val,
+                                                       ShortRow* __restrict__ bin_short,
+                                                       ShortRow* __restrict__ vox_short,
                                                        const double* __restrict__ sens,
-                                                       double* __restrict__ S_l,
-                                                       double* __restrict__ sens_l,
-                                                       const float* __restrict__ P,
-                                                       float* __restrict__ P_l, uint32_t* __restrict__ st) {
+                                                       double* __restrict__ sens_l, uint32_t* __restrict__ st) {
     if (st[ST_BAD]) return;
     const int64_t nb = st[ST_BINS], nv = st[ST_VOXS];
     const int64_t n = std::max(nnz, std::max(nb, nv));
     bool bad = false;
+    // a short row's entries with the renumbering of Tc / Ttc (from the
+    // original columns: Tc and Ttc are written by other threads of this pass)
+    auto copy_short = [](const ClassRef& r, const int32_t* __restrict__ c, const float* __restrict__ v,
+                         const int32_t* __restrict__ pos, ShortRow* __restrict__ out) {
+        ShortRow e;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int32_t p = k < r.len ? pos[c[r.lo + k]] : 0;
+            e.col[k] = p < 0 ? 0 : p;
+            e.val[k] = k < r.len ? v[r.lo + k] : 0.0f;
+        }
+        *out = e;
+    };
     for (int64_t t = (int64_t)blockIdx.x * T256 + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * T256) {
         if (t < nnz) {
@@ -914,14 +953,39 @@ __global__ __launch_bounds__(T256) void k_mlem_compact(int64_t nnz, const int32_
             Ttc[t] = pb < 0 ? 0 : pb;
         }
         if (t < nv) {
-            const int32_t i = voxs[t].row;
-            const double si = sens[i];
-            sens_l[t] = si;
-            S_l[t] = si > 0.0 ? (double)img[i] : 0.0;
+            const ClassRef r = voxs[t];
+            sens_l[t] = sens[r.row];
+            if (r.len <= 4) copy_short(r, Tt_col, Tt_val, bin_pos, vox_short + t);
         }
-        if (t < nb) P_l[t] = P[bins[t].row];
+        if (t < nb) {
+            const ClassRef r = bins[t];
+            if (r.len <= 4) copy_short(r, T_col, T_val, vox_pos, bin_short + t);
+        }
     }
     if (bad) atomicOr(&st[ST_BAD], 1u);
+}
+
+// Per call: the call checked against the set-up (ST_CALL_BAD), then the
+// iterated vectors loaded: S = img where sens > 0, else 0, and for the
+// compact layout P in list order (voxs / bins non-null).  In row order S and
+// sens are indexed by voxel; in list order by list position.
+__global__ __launch_bounds__(T256) void k_mlem_load(int64_t n_bins, int64_t n_vox, int64_t nnz,
+                                                    const float* __restrict__ img,
+                                                    const double* __restrict__ sens,
+                                                    double* __restrict__ S, const float* __restrict__ P,
+                                                    const ClassRef* __restrict__ bins,
+                                                    const ClassRef* __restrict__ voxs,
+                                                    float* __restrict__ P_l, uint32_t* __restrict__ st) {
+    const bool bad = mlem_call_bad(st, n_bins, n_vox, nnz);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st[ST_CALL_BAD] = bad ? 1u : 0u;
+    if (bad) return;
+    const int64_t nv = voxs ? (int64_t)st[ST_VOXS] : n_vox, nb = bins ? (int64_t)st[ST_BINS] : 0;
+    const int64_t n = std::max(nv, nb);
+    for (int64_t t = (int64_t)blockIdx.x * T256 + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * T256) {
+        if (t < nv) S[t] = sens[t] > 0.0 ? (double)img[voxs ? voxs[t].row : t] : 0.0;
+        if (t < nb) P_l[t] = P[bins[t].row];
+    }
 }
 
 // (group, class) key of a non-empty row: group by voxel index (a voxel row's
@@ -1067,14 +1131,40 @@ __device__ inline void sweep_key(int64_t block, int64_t n_blocks, const ClassRef
     }
 }
 
+// Class 0 (rows of at most four entries), one lane per row: the row's
+// ClassRef and its ShortRow load together, then its (up to) four gathers.
+// The terms are added in group_row_sum<1>'s order (a term past the row's
+// length is 0), so the sum is the same bit for bit.
+template <class Aux, class Gather, class Done>
+__device__ inline void sweep_key_short(int64_t block, int64_t n_blocks, const ClassRef* __restrict__ L,
+                                       const ShortRow* __restrict__ E, uint32_t first, uint32_t n, Aux aux,
+                                       Gather gather, Done done) {
+    const RowGroups<1> G(block, n_blocks);
+    for (int64_t r = G.first; r < (int64_t)n; r += G.step) {
+        const uint32_t q = first + (uint32_t)r;
+        const int32_t len = L[q].len;
+        const ShortRow e = E[q];
+        const auto a = aux(q);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double x = (double)e.val[k] * gather(e.col[k]);
+            acc += k < len ? x : 0.0;
+        }
+        done(q, a, acc);
+    }
+}
+
 // The (group, class) lists of one matrix in one launch: workgroups [b.x, b.y)
 // sweep class 0, [b.y, b.z) class 1, [b.z, b.w) class 2, [b.w, gridDim.x)
 // class 3 (every range a multiple of N_GROUP); within a class, workgroup b
 // works on group b mod N_GROUP.  key_st: that matrix's counts (ST_HIST) and
 // first positions (ST_OFF).
-template <class Aux, class Term, class Done>
-__device__ inline void sweep_keys(const ClassRef* __restrict__ L, const uint32_t* __restrict__ hist,
-                                  const uint32_t* __restrict__ off, int4 b, Aux aux, Term term, Done done) {
+template <class Aux, class Term, class Gather, class Done>
+__device__ inline void sweep_keys(const ClassRef* __restrict__ L, const ShortRow* __restrict__ E,
+                                  const uint32_t* __restrict__ hist, const uint32_t* __restrict__ off,
+                                  const uint32_t* __restrict__ call_bad, int4 b, Aux aux, Term term,
+                                  Gather gather, Done done) {
     const int64_t k = blockIdx.x;
     const int g = (int)(k % N_GROUP);
     int c;
@@ -1084,9 +1174,11 @@ __device__ inline void sweep_keys(const ClassRef* __restrict__ L, const uint32_t
     else if (k < b.w) { c = 2; lo = b.z; hi = b.w; }
     else { c = 3; lo = b.w; hi = gridDim.x; }
     const int key = g * N_CLASS + c;
-    const uint32_t first = off[key], n = hist[key];
+    // a call that does not match the set-up sweeps nothing (the three loads
+    // are independent)
+    const uint32_t first = off[key], n = *call_bad ? 0u : hist[key];
     const int64_t blk = (k - lo) / N_GROUP, nblk = (hi - lo) / N_GROUP;
-    if (c == 0) sweep_key<1>(blk, nblk, L, first, n, aux, term, done);
+    if (c == 0) sweep_key_short(blk, nblk, L, E, first, n, aux, gather, done);
     else if (c == 1) sweep_key<4>(blk, nblk, L, first, n, aux, term, done);
     else if (c == 2) sweep_key<16>(blk, nblk, L, first, n, aux, term, done);
     else sweep_key<64>(blk, nblk, L, first, n, aux, term, done);
@@ -1095,35 +1187,39 @@ __device__ inline void sweep_keys(const ClassRef* __restrict__ L, const uint32_t
 // Compact forward: ratio_q = P_q / (sum_k val_k S[col_k]) over the bin rows,
 // S, P, ratio in list order and col renumbered to voxel list positions.
 __global__ __launch_bounds__(T256) void k_mlem_forward_c(const ClassRef* __restrict__ L,
+                                                         const ShortRow* __restrict__ E,
                                                          const uint32_t* __restrict__ st, int4 b,
                                                          const int32_t* __restrict__ col,
                                                          const float* __restrict__ val,
                                                          const double* __restrict__ S,
                                                          const float* __restrict__ P,
                                                          double* __restrict__ ratio) {
-    sweep_keys(L, st + ST_HIST, st + ST_OFF, b, [&](uint32_t q) { return P[q]; },
+    sweep_keys(L, E, st + ST_HIST, st + ST_OFF, st + ST_CALL_BAD, b, [&](uint32_t q) { return P[q]; },
                [&](int64_t k, bool ok) {
                    const double x = (double)val[k] * S[col[k]];
                    return ok ? x : 0.0;
                },
+               [&](int32_t c) { return S[c]; },
                [&](uint32_t q, float p, double y) { ratio[q] = y > 0.0 ? (double)p / y : 0.0; });
 }
 
 // Compact update: S_q <- S_q (sum_k val_k ratio[col_k]) / sens_q over the
 // voxel rows, in list order, col renumbered to bin list positions.
 __global__ __launch_bounds__(T256) void k_mlem_update_c(const ClassRef* __restrict__ L,
+                                                        const ShortRow* __restrict__ E,
                                                         const uint32_t* __restrict__ st, int4 b,
                                                         const int32_t* __restrict__ col,
                                                         const float* __restrict__ val,
                                                         const double* __restrict__ ratio,
                                                         const double* __restrict__ sens,
                                                         double* __restrict__ S) {
-    sweep_keys(L, st + ST_HIST + N_KEY, st + ST_OFF + N_KEY, b,
+    sweep_keys(L, E, st + ST_HIST + N_KEY, st + ST_OFF + N_KEY, st + ST_CALL_BAD, b,
                [&](uint32_t q) { return double2{S[q], sens[q]}; },
                [&](int64_t k, bool ok) {
                    const double x = (double)val[k] * ratio[col[k]];
                    return ok ? x : 0.0;
                },
+               [&](int32_t c) { return ratio[c]; },
                [&](uint32_t q, double2 ss, double v) { S[q] = ss.y > 0.0 ? ss.x * v / ss.y : 0.0; });
 }
 
@@ -1135,7 +1231,9 @@ __global__ __launch_bounds__(T256) void k_mlem_back_slices(int64_t n_vox,
                                                            const int32_t* __restrict__ col,
                                                            const float* __restrict__ val,
                                                            const double* __restrict__ ratio,
-                                                           double* __restrict__ part) {
+                                                           double* __restrict__ part,
+                                                           const uint32_t* __restrict__ call_bad) {
+    if (*call_bad) return;   // the slices are the set-up's: a mismatched call reads none
     const int seg = (int)(blockIdx.x % MLEM_SEGS);
     const RowGroups<GS> G(blockIdx.x / MLEM_SEGS, gridDim.x / MLEM_SEGS);
     sweep_rows(G, n_vox,
@@ -1156,7 +1254,9 @@ __global__ __launch_bounds__(T256) void k_mlem_back_slices(int64_t n_vox,
 // Sliced backprojection, second half: S_i <- S_i * (sum_s part[s][i]) / sens_i.
 __global__ __launch_bounds__(T256) void k_mlem_combine(int64_t n_vox, const double* __restrict__ part,
                                                        const double* __restrict__ sens,
-                                                       double* __restrict__ S) {
+                                                       double* __restrict__ S,
+                                                       const uint32_t* __restrict__ call_bad) {
+    if (*call_bad) return;
     for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < n_vox;
          i += (int64_t)gridDim.x * T256) {
         double b = 0.0;
@@ -1173,7 +1273,7 @@ __global__ __launch_bounds__(T256) void k_mlem_out(int64_t n_vox, const double* 
                                                    const int32_t* __restrict__ vox_pos,
                                                    const uint32_t* __restrict__ st,
                                                    float* __restrict__ img) {
-    const bool bad = st && st[ST_BAD] != 0;
+    const bool bad = st && (st[ST_BAD] != 0 || st[ST_CALL_BAD] != 0);
     for (int64_t i = (int64_t)blockIdx.x * T256 + threadIdx.x; i < n_vox;
          i += (int64_t)gridDim.x * T256) {
         float v;
@@ -1456,7 +1556,7 @@ namespace {
 // 256-byte aligned).  The compact layout's arrays are sized for its largest
 // entry count, n_bins + n_vox; the slice arrays exist for n_bins >= 2^19.
 struct MlemLayout {
-    size_t sens, S, ratio, bin_rows, vox_rows, st, sens_l, P_l, bin_pos, vox_pos, Tc, Ttc;
+    size_t sens, S, ratio, bin_rows, vox_rows, st, sens_l, P_l, bin_pos, vox_pos, Tc, Ttc, bin_short, vox_short;
     size_t sb, part, total;
 };
 
@@ -1480,6 +1580,8 @@ MlemLayout mlem_layout(uint64_t nb, uint64_t nv) {
     L.vox_pos = take(4 * nv);
     L.Tc = take(4 * (nb + nv));
     L.Ttc = take(4 * (nb + nv));
+    L.bin_short = take(sizeof(ShortRow) * nb);
+    L.vox_short = take(sizeof(ShortRow) * nv);
     if ((int64_t)nb >= MLEM_SEG_MIN_BINS) {
         L.sb = take(8 * (MLEM_SEGS + 1) * nv);
         L.part = take(8 * MLEM_SEGS * nv);
@@ -1518,7 +1620,7 @@ K by_group(int gs, K k1, K k4, K k16, K k64) {
 hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t* T_rp,
                        const int32_t* T_col, const float* T_val, const int64_t* Tt_rp,
                        const int32_t* Tt_col, const float* Tt_val, const float* proj, float* image,
-                       int32_t n_iter, void* workspace, hipStream_t s) {
+                       int32_t n_iter, void* workspace, int phases, hipStream_t s) {
     const uint64_t nb = (uint64_t)n_bins, nv = (uint64_t)n_vox;
     const MlemLayout Lo = mlem_layout(nb, nv);
     char* w = (char*)workspace;
@@ -1528,6 +1630,7 @@ hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t
     RowRef* bin_rows = (RowRef*)(w + Lo.bin_rows);
     RowRef* vox_rows = (RowRef*)(w + Lo.vox_rows);
     uint32_t* st = (uint32_t*)(w + Lo.st);
+    const bool setup = (phases & MLEM_SETUP) != 0, iterate = (phases & MLEM_ITERATE) != 0;
     // Layout: compact when the matrix is sparse (its renumbered columns fit
     // the workspace), else bin slices on large detectors, else row order.
     const bool compact = nnz <= n_bins + n_vox;
@@ -1538,8 +1641,10 @@ hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
     const int gv = grid_for(nv, T256, 8192);
     const int gr = grid_for((nb + ROW_CHUNK - 1) / ROW_CHUNK + (nv + ROW_CHUNK - 1) / ROW_CHUNK, 1, 2048);
-    k_row_sums<<<gv, T256, 0, s>>>(n_vox, Tt_rp, Tt_val, sens);
-    k_mlem_init<<<gv, T256, 0, s>>>(n_bins, n_vox, nnz, T_rp, Tt_rp, image, sens, S, st, compact ? 1 : 0);
+    if (setup) {
+        k_row_sums<<<gv, T256, 0, s>>>(n_vox, Tt_rp, Tt_val, sens);
+        k_mlem_setup<<<1, T256, 0, s>>>(n_bins, n_vox, nnz, T_rp, Tt_rp, st);
+    }
     if (compact) {
         double* sens_l = (double*)(w + Lo.sens_l);
         float* P_l = (float*)(w + Lo.P_l);
@@ -1549,6 +1654,18 @@ hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t
         int32_t* Ttc = (int32_t*)(w + Lo.Ttc);
         ClassRef* bin_list = (ClassRef*)(w + Lo.bin_rows);
         ClassRef* vox_list = (ClassRef*)(w + Lo.vox_rows);
+        ShortRow* bin_short = (ShortRow*)(w + Lo.bin_short);
+        ShortRow* vox_short = (ShortRow*)(w + Lo.vox_short);
+        if (setup) {
+            k_mlem_count<<<gr, T256, 0, s>>>(n_bins, n_vox, T_rp, T_col, Tt_rp, st);
+            k_mlem_offsets<<<1, 64, 0, s>>>(st);
+            k_mlem_place<<<gr, T256, 0, s>>>(n_bins, n_vox, T_rp, T_col, Tt_rp, bin_list, vox_list, bin_pos,
+                                              vox_pos, st);
+            k_mlem_compact<<<grid_for(std::max<uint64_t>((uint64_t)nnz, std::max(nb, nv)), T256, 8192), T256, 0,
+                             s>>>(nnz, T_col, Tt_col, bin_pos, vox_pos, Tc, Ttc, bin_list, vox_list, T_val, Tt_val,
+                                  bin_short, vox_short, sens, sens_l, st);
+        }
+        if (!iterate) return hipGetLastError();
         // Workgroups per class: each of the N_GROUP groups gets one pass over
         // a quarter of the rows the class can hold with nnz entries (groups
         // are uneven; the sweeps are grid-strided, so any count is correct),
@@ -1572,22 +1689,22 @@ hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t
         };
         int4 bf, bu;
         const int gf = ranges(n_bins, bpc_f, &bf), gu = ranges(n_vox, bpc_u, &bu);
-        k_mlem_count<<<gr, T256, 0, s>>>(n_bins, n_vox, T_rp, T_col, Tt_rp, st);
-        k_mlem_offsets<<<1, 64, 0, s>>>(st);
-        k_mlem_place<<<gr, T256, 0, s>>>(n_bins, n_vox, T_rp, T_col, Tt_rp, bin_list, vox_list, bin_pos,
-                                          vox_pos, st);
-        k_mlem_compact<<<grid_for(std::max<uint64_t>((uint64_t)nnz, std::max(nb, nv)), T256, 8192), T256, 0,
-                         s>>>(nnz, T_col, Tt_col, bin_pos, vox_pos, Tc, Ttc, bin_list, vox_list, image, sens,
-                              S, sens_l, proj, P_l, st);
+        k_mlem_load<<<grid_for(std::max(nb, nv), T256, 8192), T256, 0, s>>>(n_bins, n_vox, nnz, image, sens_l, S,
+                                                                            proj, bin_list, vox_list, P_l, st);
         for (int it = 0; it < n_iter; ++it) {
-            k_mlem_forward_c<<<gf, T256, 0, s>>>(bin_list, st, bf, Tc, T_val, S, P_l, ratio);
-            k_mlem_update_c<<<gu, T256, 0, s>>>(vox_list, st, bu, Ttc, Tt_val, ratio, sens_l, S);
+            k_mlem_forward_c<<<gf, T256, 0, s>>>(bin_list, bin_short, st, bf, Tc, T_val, S, P_l, ratio);
+            k_mlem_update_c<<<gu, T256, 0, s>>>(vox_list, vox_short, st, bu, Ttc, Tt_val, ratio, sens_l, S);
         }
         k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, vox_pos, st, image);
         return hipGetLastError();
     }
     int64_t* sb = sliced ? (int64_t*)(w + Lo.sb) : nullptr;
     double* part = sliced ? (double*)(w + Lo.part) : nullptr;
+    if (setup) {
+        k_mlem_rows<<<gr, T256, 0, s>>>(n_bins, n_vox, T_rp, Tt_rp, bin_rows, vox_rows, nullptr, nullptr, st);
+        if (sliced) k_mlem_slices<<<gv, T256, 0, s>>>(n_vox, n_bins, Tt_rp, Tt_col, sb);
+    }
+    if (!iterate) return hipGetLastError();
     // Group sizes from the mean row length over all rows that can be
     // non-empty (at most nnz of them): the summation order depends only on
     // the matrix.
@@ -1609,15 +1726,14 @@ hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t
     } else if ((e = sweep_grid(ku, vox_rows_max, gs_u, n_cu, &gu)) != hipSuccess) {
         return e;
     }
-    k_mlem_rows<<<gr, T256, 0, s>>>(n_bins, n_vox, T_rp, Tt_rp, bin_rows, vox_rows, nullptr, nullptr, st);
-    if (sliced) k_mlem_slices<<<gv, T256, 0, s>>>(n_vox, n_bins, Tt_rp, Tt_col, sb);
+    k_mlem_load<<<gv, T256, 0, s>>>(n_bins, n_vox, nnz, image, sens, S, nullptr, nullptr, nullptr, nullptr, st);
     for (int it = 0; it < n_iter; ++it) {
-        kf<<<gb, T256, 0, s>>>(bin_rows, n_bins, st + ST_BINS, T_col, T_val, S, proj, ratio);
+        kf<<<gb, T256, 0, s>>>(bin_rows, n_bins, st + ST_BINS, st + ST_CALL_BAD, T_col, T_val, S, proj, ratio);
         if (sliced) {
-            kb<<<gu, T256, 0, s>>>(n_vox, sb, Tt_col, Tt_val, ratio, part);
-            k_mlem_combine<<<gv, T256, 0, s>>>(n_vox, part, sens, S);
+            kb<<<gu, T256, 0, s>>>(n_vox, sb, Tt_col, Tt_val, ratio, part, st + ST_CALL_BAD);
+            k_mlem_combine<<<gv, T256, 0, s>>>(n_vox, part, sens, S, st + ST_CALL_BAD);
         } else {
-            ku<<<gu, T256, 0, s>>>(vox_rows, n_vox, st + ST_VOXS, Tt_col, Tt_val, ratio, sens, S);
+            ku<<<gu, T256, 0, s>>>(vox_rows, n_vox, st + ST_VOXS, st + ST_CALL_BAD, Tt_col, Tt_val, ratio, sens, S);
         }
     }
     k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, nullptr, st, image);

@@ -116,6 +116,45 @@ def test_mlem_row_groups_and_bin_slices(n_bins, n_vox, density):
     assert rel <= 1e-6
 
 
+@pytest.mark.parametrize("n_bins,n_vox,density", [
+    (600_000, 3000, 2e-5),     # compact layout
+    (1000, 4000, 0.03),        # row order
+    (600_000, 3000, 1e-3),     # bin slices
+])
+def test_mlem_prepared_equals_one_call(n_bins, n_vox, density):
+    """mlem_prepare once, then mlem_iterate_prepared per reconstruction (new
+    data and a new start image each time) gives mlem_iterate's image bit for
+    bit; a call whose entry count differs from the prepared fingerprint
+    sweeps nothing and leaves the image NaN, and the workspace serves
+    matching calls afterwards."""
+    mc = _mc()
+    import torch
+    T, truth = phantoms.random_system(n_bins, n_vox, density, seed=51)
+    rng = np.random.Generator(np.random.PCG64(52))
+    m = mc.csr_from_scipy(T)
+    ml = mc.Mlem(m)                       # mlem_prepare
+    for k in range(2):
+        P = torch.as_tensor(rng.poisson(T.astype(np.float64) @ truth * (10 + 10 * k)).astype(np.float32),
+                            device="cuda")
+        S0 = rng.uniform(0.5, 2.0, size=n_vox).astype(np.float32)
+        a = torch.as_tensor(S0.copy(), device="cuda")
+        ml.run(a, 7, proj=P)
+        b = torch.as_tensor(S0.copy(), device="cuda")
+        ml.run_unprepared(b, 7, proj=P)   # set-up repeated inside the call
+        assert torch.equal(a, b), k
+        assert bool(torch.isfinite(a).all())
+    img = torch.ones(n_vox, dtype=torch.float32, device="cuda")
+    rc = mc._lib.mlem_iterate_prepared(m.n_bins, m.n_img, m.nnz + 1, *ml._csr(), P.data_ptr(), img.data_ptr(),
+                                       3, ml.ws.data_ptr(), ml.ws.numel(), mc._stream_ptr())
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(img).all())
+    c = torch.as_tensor(S0.copy(), device="cuda")
+    ml.run(c, 7, proj=P)
+    assert torch.equal(c, a)
+    say(f"{n_bins} x {n_vox}, {T.nnz} entries: prepared calls identical to one-call MLEM")
+
+
 def test_mlem_bin_slices_unsorted_rows():
     """Voxel rows whose columns are not ascending: the slice cuts then do not
     follow the slices, but the pieces still cover each row, so the result is

@@ -76,6 +76,14 @@ __device__ __forceinline__ float2 ldg(const float2* p) {
     return make_float2(v.x, v.y);
 }
 
+// A wave-uniform pointer moved to scalar registers.
+__device__ __forceinline__ const void* uniform_ptr(const void* p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const void*)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrtf_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float rsqf_hw(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -562,78 +570,134 @@ struct FdPoint {
     uint32_t voxel;      // phantom voxel of the history's emission
 };
 
+constexpr int RAY_BATCH = 8;
+
+// State of a voxel walk: the current voxel (per axis and linear), the ray
+// parameter reached, the next plane per axis, and whether it has ended.
+struct RayWalk {
+    int ix, iy, iz, v;
+    float t, tx, ty, tz;
+    bool done;
+};
+// What the walk does not change: steps per axis (voxel and linear), plane
+// spacing in t per axis, the exit parameter.
+struct RaySteps {
+    int sx, sy, sz, stx, sty, stz;
+    float ddx, ddy, ddz, t_exit;
+};
+
+// RAY_BATCH pieces of the walk: piece k is voxel v from t to min(next plane,
+// exit); a finished walk repeats its last (valid) voxel with length 0.  The
+// pieces' mu gathers are issued at the end (byte offsets below 2^32: axes of
+// at most 1024 voxels).
+__device__ __forceinline__ void ray_batch(const Cst& C, const RaySteps& s, RayWalk& w,
+                                          const float* __restrict__ mu_map, float (&mu)[RAY_BATCH],
+                                          float (&lb)[RAY_BATCH]) {
+    uint32_t vb[RAY_BATCH];
+#pragma unroll
+    for (int k = 0; k < RAY_BATCH; ++k) {
+        const float tn = fminf(w.tx, fminf(w.ty, w.tz));
+        vb[k] = (uint32_t)w.v;
+        lb[k] = w.done ? 0.0f : fminf(tn, s.t_exit) - w.t;
+        const bool bx = (w.tx <= w.ty) & (w.tx <= w.tz);
+        const bool by = !bx & (w.ty <= w.tz);
+        const bool bz = !bx & !by;
+        const int nix = w.ix + (bx ? s.sx : 0), niy = w.iy + (by ? s.sy : 0), niz = w.iz + (bz ? s.sz : 0);
+        const bool out = ((unsigned)nix >= (unsigned)C.nx) | ((unsigned)niy >= (unsigned)C.ny) |
+                         ((unsigned)niz >= (unsigned)C.nz);
+        w.done = w.done | (tn >= s.t_exit) | out;
+        if (!w.done) {
+            w.t = tn;
+            w.ix = nix; w.iy = niy; w.iz = niz;
+            w.tx += bx ? s.ddx : 0.0f; w.ty += by ? s.ddy : 0.0f; w.tz += bz ? s.ddz : 0.0f;
+            // one term per axis (selects against 0, not between the steps)
+            w.v += (bx ? s.stx : 0) + (by ? s.sty : 0) + (bz ? s.stz : 0);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RAY_BATCH; ++k) mu[k] = ldg((const float*)((const char*)mu_map + vb[k] * 4u));
+}
+
+__device__ __forceinline__ void ray_add(float& sum, const float (&mu)[RAY_BATCH], const float (&lb)[RAY_BATCH]) {
+#pragma unroll
+    for (int k = 0; k < RAY_BATCH; ++k) sum = fmaf(mu[k], lb[k], sum);
+}
+
 // Integral of mu140 along p + t o (t >= 0, o a unit vector) to the grid edge:
 // voxel walk (Amanatides & Woo 1987) with the advancing axis chosen by
 // selects, so the lanes of a wavefront stay together.  The walk runs
-// RAY_BATCH crossings of pure arithmetic, then issues their RAY_BATCH mu
-// gathers together, so the gathers' latencies overlap.
-constexpr int RAY_BATCH = 8;
-
+// RAY_BATCH crossings of pure arithmetic and issues their RAY_BATCH mu
+// gathers together; two batches alternate buffers, so a batch's gathered
+// values are summed after the next batch has been walked and its gathers
+// issued, and a gather's latency overlaps a whole batch of work (the sum is
+// still taken piece by piece in walk order).  Plane parameters use the
+// reciprocals of the direction's components (one division per axis); the
+// gathers take a 32-bit offset from the map's base in scalar registers.
 __device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox, float oy, float oz,
                                uint32_t& pieces) {
     const float px = x + C.hx, py = y + C.hy, pz = z + C.hz;
-    int ix = min(max((int)(px * C.inv_vox), 0), C.nx - 1);
-    int iy = min(max((int)(py * C.inv_vox), 0), C.ny - 1);
-    int iz = min(max((int)(pz * C.inv_vox), 0), C.nz - 1);
-    const int ix0 = ix, iy0 = iy, iz0 = iz;
+    RayWalk w;
+    w.ix = min(max((int)(px * C.inv_vox), 0), C.nx - 1);
+    w.iy = min(max((int)(py * C.inv_vox), 0), C.ny - 1);
+    w.iz = min(max((int)(pz * C.inv_vox), 0), C.nz - 1);
+    const int ix0 = w.ix, iy0 = w.iy, iz0 = w.iz;
     const float inf = __builtin_huge_valf();
-    const int sx = ox > 0.0f ? 1 : -1, sy = oy > 0.0f ? 1 : -1, sz = oz > 0.0f ? 1 : -1;
-    float tx = ox != 0.0f ? fmaxf(((float)(ix + (ox > 0.0f)) * C.vox - px) / ox, 0.0f) : inf;
-    float ty = oy != 0.0f ? fmaxf(((float)(iy + (oy > 0.0f)) * C.vox - py) / oy, 0.0f) : inf;
-    float tz = oz != 0.0f ? fmaxf(((float)(iz + (oz > 0.0f)) * C.vox - pz) / oz, 0.0f) : inf;
-    const float ddx = ox != 0.0f ? C.vox / fabsf(ox) : inf;
-    const float ddy = oy != 0.0f ? C.vox / fabsf(oy) : inf;
-    const float ddz = oz != 0.0f ? C.vox / fabsf(oz) : inf;
-    const float ex = ox > 0.0f ? (C.lx - px) / ox : (ox < 0.0f ? -px / ox : inf);
-    const float ey = oy > 0.0f ? (C.ly - py) / oy : (oy < 0.0f ? -py / oy : inf);
-    const float ez = oz > 0.0f ? (C.lz - pz) / oz : (oz < 0.0f ? -pz / oz : inf);
-    float t_exit = fmaxf(fminf(ex, fminf(ey, ez)), 0.0f);
-    if (in_box(C, ix, iy, iz)) {
-        // mu is zero outside the attenuation box: stop where the ray leaves it
-        const float bx = ox > 0.0f ? ((float)((C.bbx >> 16) + 1u) * C.vox - px) / ox
-                                   : (ox < 0.0f ? ((float)(C.bbx & 0xFFFFu) * C.vox - px) / ox : inf);
-        const float by = oy > 0.0f ? ((float)((C.bby >> 16) + 1u) * C.vox - py) / oy
-                                   : (oy < 0.0f ? ((float)(C.bby & 0xFFFFu) * C.vox - py) / oy : inf);
-        const float bz = oz > 0.0f ? ((float)((C.bbz >> 16) + 1u) * C.vox - pz) / oz
-                                   : (oz < 0.0f ? ((float)(C.bbz & 0xFFFFu) * C.vox - pz) / oz : inf);
-        t_exit = fminf(t_exit, fmaxf(fminf(bx, fminf(by, bz)), 0.0f));
+    // 1 / o per axis (inf for a zero component: never selected)
+    const float rx = ox != 0.0f ? 1.0f / ox : inf, ry = oy != 0.0f ? 1.0f / oy : inf;
+    const float rz = oz != 0.0f ? 1.0f / oz : inf;
+    RaySteps s;
+    s.sx = ox > 0.0f ? 1 : -1;
+    s.sy = oy > 0.0f ? 1 : -1;
+    s.sz = oz > 0.0f ? 1 : -1;
+    w.tx = ox != 0.0f ? fmaxf(((float)(w.ix + (ox > 0.0f)) * C.vox - px) * rx, 0.0f) : inf;
+    w.ty = oy != 0.0f ? fmaxf(((float)(w.iy + (oy > 0.0f)) * C.vox - py) * ry, 0.0f) : inf;
+    w.tz = oz != 0.0f ? fmaxf(((float)(w.iz + (oz > 0.0f)) * C.vox - pz) * rz, 0.0f) : inf;
+    s.ddx = ox != 0.0f ? C.vox * fabsf(rx) : inf;
+    s.ddy = oy != 0.0f ? C.vox * fabsf(ry) : inf;
+    s.ddz = oz != 0.0f ? C.vox * fabsf(rz) : inf;
+    // exit of the grid, and of the attenuation box (mu is zero outside it):
+    // per axis the far plane, (plane - p) / o; the nearest of the three
+    const float ex = ox > 0.0f ? (C.lx - px) * rx : (ox < 0.0f ? -px * rx : inf);
+    const float ey = oy > 0.0f ? (C.ly - py) * ry : (oy < 0.0f ? -py * ry : inf);
+    const float ez = oz > 0.0f ? (C.lz - pz) * rz : (oz < 0.0f ? -pz * rz : inf);
+    s.t_exit = fmaxf(fminf(ex, fminf(ey, ez)), 0.0f);
+    if (in_box(C, w.ix, w.iy, w.iz)) {
+        const float bx = ox > 0.0f ? ((float)((C.bbx >> 16) + 1u) * C.vox - px) * rx
+                                   : (ox < 0.0f ? ((float)(C.bbx & 0xFFFFu) * C.vox - px) * rx : inf);
+        const float by = oy > 0.0f ? ((float)((C.bby >> 16) + 1u) * C.vox - py) * ry
+                                   : (oy < 0.0f ? ((float)(C.bby & 0xFFFFu) * C.vox - py) * ry : inf);
+        const float bz = oz > 0.0f ? ((float)((C.bbz >> 16) + 1u) * C.vox - pz) * rz
+                                   : (oz < 0.0f ? ((float)(C.bbz & 0xFFFFu) * C.vox - pz) * rz : inf);
+        s.t_exit = fminf(s.t_exit, fmaxf(fminf(bx, fminf(by, bz)), 0.0f));
     }
-    const int stx = sx, sty = sy * C.nx, stz = sz * C.nx * C.ny;
-    int v = ix + C.nx * (iy + C.ny * iz);
-    float t = 0.0f, sum = 0.0f;
-    bool done = false;
+    s.stx = s.sx;
+    s.sty = s.sy * C.nx;
+    s.stz = s.sz * C.nx * C.ny;
+    w.v = w.ix + C.nx * (w.iy + C.ny * w.iz);
+    w.t = 0.0f;
+    w.done = false;
+    float sum = 0.0f;
     const int max_batches = (C.nx + C.ny + C.nz + 3) / RAY_BATCH + 1;
-    for (int it = 0; it < max_batches; ++it) {
-        int vb[RAY_BATCH];
-        float lb[RAY_BATCH];
-#pragma unroll
-        for (int k = 0; k < RAY_BATCH; ++k) {
-            // piece k: voxel v from t to min(next plane, exit); a finished
-            // lane repeats its last (valid) voxel with length 0
-            const float tn = fminf(tx, fminf(ty, tz));
-            vb[k] = v;
-            lb[k] = done ? 0.0f : fminf(tn, t_exit) - t;
-            const bool bx = (tx <= ty) & (tx <= tz);
-            const bool by = !bx & (ty <= tz);
-            const bool bz = !bx & !by;
-            const int nix = ix + (bx ? sx : 0), niy = iy + (by ? sy : 0), niz = iz + (bz ? sz : 0);
-            const bool out = ((unsigned)nix >= (unsigned)C.nx) | ((unsigned)niy >= (unsigned)C.ny) |
-                             ((unsigned)niz >= (unsigned)C.nz);
-            done = done | (tn >= t_exit) | out;
-            if (!done) {
-                t = tn;
-                ix = nix; iy = niy; iz = niz;
-                tx += bx ? ddx : 0.0f; ty += by ? ddy : 0.0f; tz += bz ? ddz : 0.0f;
-                v += bx ? stx : (by ? sty : stz);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < RAY_BATCH; ++k) sum = fmaf(ldg(C.mu + vb[k]), lb[k], sum);
-        if (done) break;
+    const float* __restrict__ mu_map = (const float*)uniform_ptr(C.mu);
+    float mu_a[RAY_BATCH], lb_a[RAY_BATCH], mu_b[RAY_BATCH], lb_b[RAY_BATCH];
+    ray_batch(C, s, w, mu_map, mu_a, lb_a);
+    int it = 1;
+    for (; it + 1 < max_batches && !w.done; it += 2) {
+        ray_batch(C, s, w, mu_map, mu_b, lb_b);
+        ray_add(sum, mu_a, lb_a);
+        ray_batch(C, s, w, mu_map, mu_a, lb_a);
+        ray_add(sum, mu_b, lb_b);
+    }
+    if (it < max_batches && !w.done) {     // one batch left (max_batches even)
+        ray_batch(C, s, w, mu_map, mu_b, lb_b);
+        ray_add(sum, mu_a, lb_a);
+        ray_add(sum, mu_b, lb_b);
+    } else {
+        ray_add(sum, mu_a, lb_a);
     }
     // voxels the walk visited (one plane crossing per step, so the index
     // distance from the first voxel to the last, plus one)
-    pieces = (uint32_t)(abs(ix - ix0) + abs(iy - iy0) + abs(iz - iz0) + 1);
+    pieces = (uint32_t)(abs(w.ix - ix0) + abs(w.iy - iy0) + abs(w.iz - iz0) + 1);
     return sum;
 }
 

@@ -67,11 +67,11 @@ def table_ops(n_hist, n_tent, n_kahn, n_real, cost=None):
 # counters read for a plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); keyed
 # by a hash of the kernel sources so a changed kernel reports null.
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
-TRAFFIC_KIB = {"a1483d89fcc1db15": {"fetch": 5930.44, "write": 4983.91}}
+TRAFFIC_KIB = {"ff8d756a7c8f9279": {"fetch": 5928.94, "write": 4983.94}}
 # rocprofv3 --pmc SQ_INSTS_VALU of the same launch (and the dispatch time of
 # that run), keyed like the traffic
-VALU_COUNTERS = {"a1483d89fcc1db15": {"workload": "thorax_128", "SQ_INSTS_VALU": 2.07747e9,
-                                      "kernel_ms": 4.2639}}
+VALU_COUNTERS = {"ff8d756a7c8f9279": {"workload": "thorax_128", "SQ_INSTS_VALU": 2.07747e9,
+                                      "kernel_ms": 4.2717}}
 
 
 def kernel_source_hash() -> str:

@@ -648,7 +648,7 @@ __global__ void k_finalize(const ProbDesc* __restrict__ descs, int n_problems, i
 // fewer than 2^31 histories are tallied in all (each adds +-2^32), which is
 // what is checked for it (its forced-detection and weighted forms are not
 // checked: each history then scores up to one weight per collision).
-constexpr int TALLY_CHECK_BLOCKS = 16;
+constexpr int TALLY_CHECK_BLOCKS = 128;   // ~16 elements per thread on a 60-view 64x64 tally
 
 __global__ __launch_bounds__(256) void k_tally_check(const ProbDesc* __restrict__ descs,
                                                      const int64_t* __restrict__ tally,
@@ -662,6 +662,7 @@ __global__ __launch_bounds__(256) void k_tally_check(const ProbDesc* __restrict_
     } else {
         const uint64_t n = (uint64_t)d.n_views * 2u * (uint64_t)d.nv * (uint64_t)d.nu;
         const int64_t* t = tally + d.tally_offset;
+#pragma unroll 4
         for (uint64_t i = (uint64_t)part * 256 + threadIdx.x; i < n; i += TALLY_CHECK_BLOCKS * 256)
             bad |= t[i] < 0;
     }

@@ -67,11 +67,11 @@ def table_ops(n_hist, n_tent, n_kahn, n_real, cost=None):
 # counters read for a plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); keyed
 # by a hash of the kernel sources so a changed kernel reports null.
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
-TRAFFIC_KIB = {"ff8d756a7c8f9279": {"fetch": 5928.94, "write": 4983.94}}
+TRAFFIC_KIB = {"ed82bc6e4e06038d": {"fetch": 5929.12, "write": 4983.38}}
 # rocprofv3 --pmc SQ_INSTS_VALU of the same launch (and the dispatch time of
 # that run), keyed like the traffic
-VALU_COUNTERS = {"ff8d756a7c8f9279": {"workload": "thorax_128", "SQ_INSTS_VALU": 2.07747e9,
-                                      "kernel_ms": 4.2717}}
+VALU_COUNTERS = {"ed82bc6e4e06038d": {"workload": "thorax_128", "SQ_INSTS_VALU": 2.07745e9,
+                                      "kernel_ms": 4.2337}}
 
 
 def kernel_source_hash() -> str:
@@ -683,8 +683,8 @@ def tl201_form(mc, torch, steps):
 
 def large_fd(mc, torch, steps, p5):
     """Forced-detection response matrix on the large workload: 1e8 histories
-    with an event list (one event per score), the weighted response matrix
-    and 50 MLEM iterations on it."""
+    with an event list (one event per score), the weighted response matrix,
+    50 MLEM iterations and 2 OSEM iterations of 8 subsets on it."""
     p = p5.with_(n_histories=10 ** 8)
     dp = mc.to_device(p)
     cap = 3 * p.n_histories
@@ -703,9 +703,16 @@ def large_fd(mc, torch, steps, p5):
     recon()
     ms_eager = timed(torch, recon, steps)
     ms_mlem = timed(torch, mc.Graph(recon).replay, steps)
+
+    def os_recon():
+        img.fill_(1.0)
+        mc.osem(m, img, 2, 8, p.nu * p.nv)
+    os_recon()
+    ms_os = timed(torch, os_recon, steps)
     return {"histories": p.n_histories, "forward_ms": ms_fwd, "events": n_ev,
             "events_listed": min(n_ev, cap), "system_matrix_ms": ms_sys, "nnz": m.nnz,
             "mlem_50_ms": ms_mlem, "mlem_50_eager_ms": ms_eager,
+            "osem_8_subsets_2_iterations_ms": ms_os,
             "histories_per_s": p.n_histories / (ms_fwd / 1e3)}
 
 

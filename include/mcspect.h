@@ -402,8 +402,9 @@ int mlem_iterate_prepared(int64_t n_bins, int64_t n_vox, int64_t nnz,
                           const float* proj, float* image, int32_t n_iter,
                           void* workspace, size_t workspace_bytes, void* stream);
 
-/* Workspace bytes of osem_iterate. */
-size_t osem_workspace_bytes(int64_t n_bins, int64_t n_vox, int32_t n_subsets);
+/* Workspace bytes of osem_iterate (bt_nnz: the entry count of b); 0 for
+ * invalid sizes or more than 64 subsets. */
+size_t osem_workspace_bytes(int64_t n_bins, int64_t n_vox, int32_t n_subsets, int64_t bt_nnz);
 
 /* Ordered-subsets reconstruction in the forms the paper reviews (Sec. 5.3,
  * Sec. 5.4): OSEM; the dual-matrix update of Eq. DMOS (reproject with c,
@@ -417,11 +418,17 @@ size_t osem_workspace_bytes(int64_t n_bins, int64_t n_vox, int32_t n_subsets);
  * sees start and stay at 0).  n_subsets = 1, b = c, s = NULL is MLEM.
  *   C_*   CSR of c, rows = bins;  Bt_*  CSR of b transposed, rows = voxels
  *   proj  device float [n_bins];  scatter  device float [n_bins] or NULL
+ *   bt_nnz the entry count of b, Bt_rowptr[n_vox], as the caller knows it;
+ *         checked on the device: a different value leaves the image NaN
  *   image device float [n_vox]: S^0 in, result out.
- * FP32 matrix values, FP64 accumulation. */
+ * 1 <= n_subsets <= min(64, number of views), else MC_EINVAL.  Once per call
+ * B^T is split by subset in the workspace (for subset k and voxel i, the
+ * entries of row i whose bin is in subset k, in row order), so each subset's
+ * backprojection reads only its own entries.  FP32 matrix values, FP64
+ * accumulation.  Asynchronous on stream, no allocation. */
 int osem_iterate(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n_subsets,
                  const int64_t* C_rowptr, const int32_t* C_col, const float* C_val,
-                 const int64_t* Bt_rowptr, const int32_t* Bt_col, const float* Bt_val,
+                 const int64_t* Bt_rowptr, const int32_t* Bt_col, const float* Bt_val, int64_t bt_nnz,
                  const float* proj, const float* scatter, float* image, int32_t n_iter,
                  void* workspace, size_t workspace_bytes, void* stream);
 

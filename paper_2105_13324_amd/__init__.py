@@ -103,9 +103,9 @@ _lib.mc_system_matrix_workspace_bytes.argtypes = [C.POINTER(McProblem), _u64]
 _lib.mc_system_matrix_workspace_bytes.restype = _sz
 _lib.mc_system_matrix.argtypes = [C.POINTER(McProblem), _vp, _vp, _u64, C.c_int32, _vp, _vp, _vp,
                                   _vp, _vp, _vp, _vp, _vp, _sz, _vp]
-_lib.osem_workspace_bytes.argtypes = [_i64, _i64, C.c_int32]
+_lib.osem_workspace_bytes.argtypes = [_i64, _i64, C.c_int32, _i64]
 _lib.osem_workspace_bytes.restype = _sz
-_lib.osem_iterate.argtypes = [_i64, _i64, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+_lib.osem_iterate.argtypes = [_i64, _i64, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp,
                               _vp, _vp, C.c_int32, _vp, _sz, _vp]
 _lib.osem_iterate.restype = C.c_int
 _lib.mc_system_matrix.restype = C.c_int
@@ -952,13 +952,13 @@ def osem(c: SystemMatrix, image, n_iter: int, n_subsets: int, bins_per_view: int
     torch = _torch()
     b = c if b is None else b
     P = c.proj if proj is None else proj
-    nb = _lib.osem_workspace_bytes(c.n_bins, c.n_img, int(n_subsets))
+    nb = _lib.osem_workspace_bytes(c.n_bins, c.n_img, int(n_subsets), int(b.nnz))
     if nb == 0:
-        raise McError("osem_workspace_bytes: invalid sizes")
+        raise McError("osem_workspace_bytes: invalid sizes (or more than 64 subsets)")
     ws = torch.empty(nb, dtype=torch.uint8, device=c.T_val.device)
     rc = _lib.osem_iterate(c.n_bins, c.n_img, int(bins_per_view), int(n_subsets),
                            c.T_rowptr.data_ptr(), c.T_col.data_ptr(), c.T_val.data_ptr(),
-                           b.Tt_rowptr.data_ptr(), b.Tt_col.data_ptr(), b.Tt_val.data_ptr(),
+                           b.Tt_rowptr.data_ptr(), b.Tt_col.data_ptr(), b.Tt_val.data_ptr(), int(b.nnz),
                            P.data_ptr(), scatter.data_ptr() if scatter is not None else None,
                            image.data_ptr(), int(n_iter), ws.data_ptr(), nb, _stream_ptr())
     _check(rc, "osem_iterate")

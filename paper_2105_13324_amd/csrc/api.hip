@@ -540,26 +540,27 @@ int mlem_iterate_prepared(int64_t n_bins, int64_t n_vox, int64_t nnz, const int6
                      n_iter, workspace, workspace_bytes, stream, MLEM_ITERATE);
 }
 
-size_t osem_workspace_bytes(int64_t n_bins, int64_t n_vox, int32_t n_subsets) {
-    if (n_bins < 1 || n_vox < 1 || n_subsets < 1) return 0;
-    return osem_workspace((uint64_t)n_bins, (uint64_t)n_vox, (uint32_t)n_subsets);
+size_t osem_workspace_bytes(int64_t n_bins, int64_t n_vox, int32_t n_subsets, int64_t bt_nnz) {
+    if (n_bins < 1 || n_vox < 1 || n_subsets < 1 || n_subsets > OSEM_MAX_SUBSETS || bt_nnz < 0) return 0;
+    return osem_workspace((uint64_t)n_bins, (uint64_t)n_vox, (uint32_t)n_subsets, (uint64_t)bt_nnz);
 }
 
 int osem_iterate(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n_subsets,
                  const int64_t* C_rowptr, const int32_t* C_col, const float* C_val,
-                 const int64_t* Bt_rowptr, const int32_t* Bt_col, const float* Bt_val,
+                 const int64_t* Bt_rowptr, const int32_t* Bt_col, const float* Bt_val, int64_t bt_nnz,
                  const float* proj, const float* scatter, float* image, int32_t n_iter,
                  void* workspace, size_t workspace_bytes, void* stream) {
-    if (n_bins < 1 || n_vox < 1 || n_iter < 0 || bins_per_view < 1 || n_subsets < 1) return MC_EINVAL;
+    if (n_bins < 1 || n_vox < 1 || n_iter < 0 || bins_per_view < 1 || n_subsets < 1 || bt_nnz < 0)
+        return MC_EINVAL;
     if (n_bins >= (1ll << 31) || n_vox >= (1ll << 31) || n_bins % bins_per_view != 0) return MC_EINVAL;
-    if (n_subsets > n_bins / bins_per_view) return MC_EINVAL;
+    if (n_subsets > n_bins / bins_per_view || n_subsets > OSEM_MAX_SUBSETS) return MC_EINVAL;
     if (!C_rowptr || !C_col || !C_val || !Bt_rowptr || !Bt_col || !Bt_val || !proj || !image ||
         !workspace)
         return MC_EINVAL;
-    if (workspace_bytes < osem_workspace((uint64_t)n_bins, (uint64_t)n_vox, (uint32_t)n_subsets))
+    if (workspace_bytes < osem_workspace((uint64_t)n_bins, (uint64_t)n_vox, (uint32_t)n_subsets, (uint64_t)bt_nnz))
         return MC_ENOMEM;
     hipError_t e = launch_osem(n_bins, n_vox, bins_per_view, n_subsets, C_rowptr, C_col, C_val,
-                               Bt_rowptr, Bt_col, Bt_val, proj, scatter, image, n_iter, workspace,
+                               Bt_rowptr, Bt_col, Bt_val, bt_nnz, proj, scatter, image, n_iter, workspace,
                                (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
     return MC_OK;

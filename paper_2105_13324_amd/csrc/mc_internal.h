@@ -276,10 +276,11 @@ hipError_t launch_mlem(int64_t n_bins, int64_t n_vox, int64_t nnz, const int64_t
                        const int32_t* Tt_col, const float* Tt_val, const float* proj, float* image,
                        int32_t n_iter, void* workspace, int phases, hipStream_t s);
 
-size_t osem_workspace(uint64_t n_bins, uint64_t n_vox, uint32_t n_sub);
+constexpr int32_t OSEM_MAX_SUBSETS = 64;   // one lane of a wavefront per subset in the split
+size_t osem_workspace(uint64_t n_bins, uint64_t n_vox, uint32_t n_sub, uint64_t bt_nnz);
 hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n_sub,
                        const int64_t* C_rp, const int32_t* C_col, const float* C_val,
-                       const int64_t* Bt_rp, const int32_t* Bt_col, const float* Bt_val,
+                       const int64_t* Bt_rp, const int32_t* Bt_col, const float* Bt_val, int64_t bt_nnz,
                        const float* proj, const float* scatter, float* image, int32_t n_iter,
                        void* workspace, hipStream_t s);
 

@@ -645,6 +645,12 @@ __global__ __launch_bounds__(T256) void k_mlem_rows(int64_t n_bins, int64_t n_vo
 // Lanes that share one row in the MLEM sweeps: the smallest group of 1, 4, 16
 // or 64 lanes for which four entries per lane cover the mean row (nnz /
 // n_rows entries), so that short rows do not leave most of a wavefront idle.
+// The kernel instantiated for lane-group size gs (1, 4, 16 or 64).
+template <class K>
+K by_group(int gs, K k1, K k4, K k16, K k64) {
+    return gs == 1 ? k1 : gs == 4 ? k4 : gs == 16 ? k16 : k64;
+}
+
 __host__ __device__ inline int lanes_per_row(int64_t nnz, int64_t n_rows) {
     if (nnz <= 4 * n_rows) return 1;
     if (nnz <= 16 * n_rows) return 4;
@@ -1292,16 +1298,97 @@ __global__ __launch_bounds__(T256) void k_mlem_out(int64_t n_vox, const double* 
 // ---- ordered subsets (OSEM; dual matrix, Eq. DMOS; additive scatter, the
 // Sohlberg OS-EM equation).  Subset k holds the views v with v mod n_sub == k.
 
-// sens[k][i] = sum over the bins j of subset k of b_ij (row i of B^T)
-__global__ __launch_bounds__(T256) void k_subset_sens(int64_t n_vox, const int64_t* __restrict__ rp,
-                                                      const int32_t* __restrict__ col,
-                                                      const float* __restrict__ val,
-                                                      int32_t bins_per_view, int32_t n_sub,
-                                                      double* __restrict__ sens) {
-    for (int k = 0; k < n_sub; ++k)
-        for_rows(n_vox, rp,
-                 [&](int64_t e) { return (col[e] / bins_per_view) % n_sub == k ? (double)val[e] : 0.0; },
-                 [&](int64_t i, double acc) { sens[(int64_t)k * n_vox + i] = acc; });
+// The backprojector split by subset, built once per call: for subset k and
+// voxel i, the entries of row i of B^T whose bin lies in subset k, in their
+// order in the row, at rows k * n_vox + i of one CSR (offsets off[], k-major),
+// so that a subset's backprojection reads that subset's entries only instead
+// of the whole of B^T once per subset.  One wavefront per row: 64 entries at
+// a time, the distinct subsets among them taken in turn (a ballot matches
+// the lanes of one subset); lane k of the wavefront keeps subset k's count
+// (hence at most 64 subsets).
+
+// st[2] (as for MLEM: the image is NaN when set): the entry count the caller
+// gave is not B^T's own.
+__global__ void k_os_check(int64_t n_vox, const int64_t* __restrict__ rp, int64_t nnz,
+                           uint32_t* __restrict__ st) {
+    if (blockIdx.x == 0 && threadIdx.x < 4) st[threadIdx.x] = threadIdx.x == 2 ? (rp[n_vox] != nnz) : 0u;
+}
+
+__device__ __forceinline__ int os_subset_of(int32_t bin, int32_t bins_per_view, int32_t n_sub) {
+    return (bin / bins_per_view) % n_sub;
+}
+
+// cnt[k * n_vox + i] = entries of row i in subset k (all 0 when st[2] is set).
+__global__ __launch_bounds__(T256) void k_os_split_count(int64_t n_vox, const int64_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ col,
+                                                         int32_t bins_per_view, int32_t n_sub,
+                                                         uint32_t* __restrict__ cnt,
+                                                         const uint32_t* __restrict__ st) {
+    const bool bad = st[2] != 0;
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t waves = (int64_t)gridDim.x * (T256 / 64);
+    for (int64_t i = (int64_t)blockIdx.x * (T256 / 64) + (threadIdx.x >> 6); i < n_vox; i += waves) {
+        uint32_t c = 0;                    // lane k: entries of subset k so far
+        if (!bad) {
+            const int64_t lo = rp[i], hi = rp[i + 1];
+            for (int64_t e0 = lo; e0 < hi; e0 += 64) {
+                const int64_t e = e0 + lane;
+                const bool valid = e < hi;
+                const int k = valid ? os_subset_of(col[e], bins_per_view, n_sub) : -1;
+                uint64_t m = __ballot(valid);
+                while (m != 0) {
+                    const int kk = __builtin_amdgcn_readlane(k, __builtin_ctzll(m));
+                    const uint64_t grp = __ballot(k == kk) & m;
+                    if (lane == kk) c += (uint32_t)__popcll(grp);
+                    m &= ~grp;
+                }
+            }
+        }
+        if (lane < n_sub) cnt[(int64_t)lane * n_vox + i] = c;
+    }
+}
+
+// The entries moved to their subset rows: off[k * n_vox + i] is the first
+// slot of subset k's row i (an exclusive scan of cnt).
+__global__ __launch_bounds__(T256) void k_os_split_scatter(int64_t n_vox, const int64_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ col,
+                                                           const float* __restrict__ val,
+                                                           int32_t bins_per_view, int32_t n_sub,
+                                                           const uint64_t* __restrict__ off,
+                                                           int32_t* __restrict__ col_s,
+                                                           float* __restrict__ val_s,
+                                                           const uint32_t* __restrict__ st) {
+    if (st[2] != 0) return;
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t waves = (int64_t)gridDim.x * (T256 / 64);
+    for (int64_t i = (int64_t)blockIdx.x * (T256 / 64) + (threadIdx.x >> 6); i < n_vox; i += waves) {
+        const int64_t lo = rp[i], hi = rp[i + 1];
+        if (lo == hi) continue;           // wave-uniform
+        // lane k: the next free slot of subset k's row i
+        uint64_t next = lane < n_sub ? off[(int64_t)lane * n_vox + i] : 0;
+        for (int64_t e0 = lo; e0 < hi; e0 += 64) {
+            const int64_t e = e0 + lane;
+            const bool valid = e < hi;
+            const int32_t c = valid ? col[e] : 0;
+            const float v = valid ? val[e] : 0.0f;
+            const int k = valid ? os_subset_of(c, bins_per_view, n_sub) : -1;
+            uint64_t m = __ballot(valid);
+            while (m != 0) {
+                const int kk = __builtin_amdgcn_readlane(k, __builtin_ctzll(m));
+                const uint64_t grp = __ballot(k == kk) & m;
+                const uint32_t lo32 = __builtin_amdgcn_readlane((uint32_t)next, kk);
+                const uint32_t hi32 = __builtin_amdgcn_readlane((uint32_t)(next >> 32), kk);
+                const uint64_t base = ((uint64_t)hi32 << 32) | lo32;
+                if (k == kk) {
+                    const uint64_t at = base + (uint64_t)__popcll(grp & ((1ull << lane) - 1ull));
+                    col_s[at] = c;
+                    val_s[at] = v;
+                }
+                if (lane == kk) next += (uint64_t)__popcll(grp);
+                m &= ~grp;
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(T256) void k_os_init(int64_t n_vox, int32_t n_sub,
@@ -1366,69 +1453,95 @@ __global__ __launch_bounds__(T256) void k_os_forward(int64_t n_sub_bins, int32_t
     }
 }
 
-// subset k: S_i <- S_i * (sum_{j in k} b_ij ratio_j) / sens_k,i (unchanged where sens_k,i = 0)
+// subset k: S_i <- S_i * (sum_{j in k} b_ij ratio_j) / sens_k,i (unchanged
+// where sens_k,i = 0), over subset k's rows of the split backprojector
+// (rp = off + k n_vox: row i spans [rp[i], rp[i + 1])).
 template <int GS>
-__device__ inline void os_update_rows(int64_t n_vox, int32_t bins_per_view, int32_t n_sub, int32_t k,
-                                      const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                      const float* __restrict__ val,
-                                      const double* __restrict__ ratio,
-                                      const double* __restrict__ sens, double* __restrict__ S) {
-    const RowGroups<GS> G(blockIdx.x, gridDim.x);
-    sweep_rows(G, n_vox, [&](int64_t i, int64_t& lo, int64_t& hi) { lo = rp[i]; hi = rp[i + 1]; },
-               [&](int64_t e, bool ok) {
-                   // every entry gathers its ratio (loads issued together);
-                   // entries outside subset k then count 0.  Masking the
-                   // gather instead serialises the loads and was slower.
-                   const int32_t j = col[e];
-                   const bool in_k = (j / bins_per_view) % n_sub == k;
-                   const double x = (double)val[e] * ratio[j];
-                   return ok && in_k ? x : 0.0;
-               },
-               [&](int64_t i, int64_t, int64_t, double bsum) {
-                   if (G.sub != 0) return;
-                   const double si = sens[(int64_t)k * n_vox + i];
-                   if (si > 0.0) S[i] = S[i] * bsum / si;
-               });
-}
-
-__global__ __launch_bounds__(T256) void k_os_update(int64_t n_vox, int32_t bins_per_view,
-                                                    int32_t n_sub, int32_t k,
-                                                    const int64_t* __restrict__ rp,
+__global__ __launch_bounds__(T256) void k_os_update(int64_t n_vox, const int64_t* __restrict__ rp,
                                                     const int32_t* __restrict__ col,
                                                     const float* __restrict__ val,
                                                     const double* __restrict__ ratio,
-                                                    const double* __restrict__ sens,
+                                                    const double* __restrict__ sens_k,
                                                     double* __restrict__ S) {
-    switch (lanes_per_row(rp[n_vox], n_vox)) {
-        case 1: os_update_rows<1>(n_vox, bins_per_view, n_sub, k, rp, col, val, ratio, sens, S); break;
-        case 4: os_update_rows<4>(n_vox, bins_per_view, n_sub, k, rp, col, val, ratio, sens, S); break;
-        case 16: os_update_rows<16>(n_vox, bins_per_view, n_sub, k, rp, col, val, ratio, sens, S); break;
-        default: os_update_rows<64>(n_vox, bins_per_view, n_sub, k, rp, col, val, ratio, sens, S); break;
-    }
+    const RowGroups<GS> G(blockIdx.x, gridDim.x);
+    sweep_rows(G, n_vox, [&](int64_t i, int64_t& lo, int64_t& hi) { lo = rp[i]; hi = rp[i + 1]; },
+               [&](int64_t e, bool ok) {
+                   const double x = (double)val[e] * ratio[col[e]];
+                   return ok ? x : 0.0;
+               },
+               [&](int64_t i, int64_t, int64_t, double bsum) {
+                   if (G.sub != 0) return;
+                   const double si = sens_k[i];
+                   if (si > 0.0) S[i] = S[i] * bsum / si;
+               });
 }
 
 }  // namespace
 
 
-size_t osem_workspace(uint64_t n_bins, uint64_t n_vox, uint32_t n_sub) {
-    auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
-    return al(8 * n_vox * n_sub) /* sens per subset */ + al(8 * n_vox) /* S */ + al(8 * n_bins);
+// OSEM workspace: per-subset sensitivities, S, the ratio, the check word,
+// and the subset-split backprojector (counts, their scan and its block sums,
+// columns and values).
+struct OsemLayout {
+    size_t sens, S, ratio, st, cnt, off, bsum, col_s, val_s, total;
+};
+
+OsemLayout osem_layout(uint64_t n_bins, uint64_t n_vox, uint32_t n_sub, uint64_t nnz) {
+    OsemLayout L{};
+    size_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        const size_t at = o;
+        o += (bytes + 255) & ~(uint64_t)255;
+        return at;
+    };
+    const uint64_t rows = (uint64_t)n_sub * n_vox;
+    L.sens = take(8 * rows);
+    L.S = take(8 * n_vox);
+    L.ratio = take(8 * n_bins);
+    L.st = take(16);
+    L.cnt = take(4 * rows);
+    L.off = take(8 * (rows + 1));
+    L.bsum = take(8 * ((rows + 1 + SCAN_BLOCK - 1) / SCAN_BLOCK));
+    L.col_s = take(4 * nnz);
+    L.val_s = take(4 * nnz);
+    L.total = o;
+    return L;
+}
+
+size_t osem_workspace(uint64_t n_bins, uint64_t n_vox, uint32_t n_sub, uint64_t bt_nnz) {
+    return osem_layout(n_bins, n_vox, n_sub, bt_nnz).total;
 }
 
 hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n_sub,
                        const int64_t* C_rp, const int32_t* C_col, const float* C_val,
-                       const int64_t* Bt_rp, const int32_t* Bt_col, const float* Bt_val,
+                       const int64_t* Bt_rp, const int32_t* Bt_col, const float* Bt_val, int64_t bt_nnz,
                        const float* proj, const float* scatter, float* image, int32_t n_iter,
                        void* workspace, hipStream_t s) {
-    auto al = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+    const OsemLayout L = osem_layout((uint64_t)n_bins, (uint64_t)n_vox, (uint32_t)n_sub, (uint64_t)bt_nnz);
     char* w = (char*)workspace;
-    double* sens = (double*)w;  w += al(8 * (uint64_t)n_vox * n_sub);
-    double* S = (double*)w;     w += al(8 * (uint64_t)n_vox);
-    double* ratio = (double*)w;
+    double* sens = (double*)(w + L.sens);
+    double* S = (double*)(w + L.S);
+    double* ratio = (double*)(w + L.ratio);
+    uint32_t* st = (uint32_t*)(w + L.st);
+    uint32_t* cnt = (uint32_t*)(w + L.cnt);
+    uint64_t* off = (uint64_t*)(w + L.off);
+    int32_t* col_s = (int32_t*)(w + L.col_s);
+    float* val_s = (float*)(w + L.val_s);
     const int64_t n_views = n_bins / bins_per_view;
+    const uint64_t rows = (uint64_t)n_sub * (uint64_t)n_vox;
     const int gv = grid_for((uint64_t)n_vox, T256, 8192);
-    k_subset_sens<<<gv, T256, 0, s>>>(n_vox, Bt_rp, Bt_col, Bt_val, bins_per_view, n_sub, sens);
+    const int gw = grid_for((uint64_t)n_vox, T256 / 64, 8192);     // one wavefront per row
+    hipError_t e;
+    k_os_check<<<1, 64, 0, s>>>(n_vox, Bt_rp, bt_nnz, st);
+    k_os_split_count<<<gw, T256, 0, s>>>(n_vox, Bt_rp, Bt_col, bins_per_view, n_sub, cnt, st);
+    if ((e = exclusive_scan(cnt, rows, off, (uint64_t*)(w + L.bsum), s)) != hipSuccess) return e;
+    k_os_split_scatter<<<gw, T256, 0, s>>>(n_vox, Bt_rp, Bt_col, Bt_val, bins_per_view, n_sub, off, col_s,
+                                           val_s, st);
+    k_row_sums<<<grid_for(rows, T256, 8192), T256, 0, s>>>((int64_t)rows, (const int64_t*)off, val_s, sens);
     k_os_init<<<gv, T256, 0, s>>>(n_vox, n_sub, image, sens, S);
+    // lanes per subset row from the mean subset row length
+    const int gs_u = lanes_per_row(bt_nnz / n_sub, n_vox);
+    auto ku = by_group(gs_u, k_os_update<1>, k_os_update<4>, k_os_update<16>, k_os_update<64>);
     for (int it = 0; it < n_iter; ++it) {
         for (int k = 0; k < n_sub; ++k) {
             const int64_t views_k = (n_views - k + n_sub - 1) / n_sub;
@@ -1436,15 +1549,14 @@ hipError_t launch_osem(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int
             if (nb <= 0) continue;
             k_os_forward<<<grid_for((uint64_t)nb, T256, 16384), T256, 0, s>>>(
                 nb, bins_per_view, n_sub, k, C_rp, C_col, C_val, S, proj, scatter, ratio, n_bins);
-            k_os_update<<<gv, T256, 0, s>>>(n_vox, bins_per_view, n_sub, k, Bt_rp, Bt_col, Bt_val,
-                                            ratio, sens, S);
+            ku<<<gv, T256, 0, s>>>(n_vox, (const int64_t*)(off + (uint64_t)k * (uint64_t)n_vox), col_s, val_s,
+                                   ratio, sens + (uint64_t)k * (uint64_t)n_vox, S);
         }
     }
-    k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, nullptr, nullptr, image);
+    k_mlem_out<<<gv, T256, 0, s>>>(n_vox, S, nullptr, st, image);
     return hipGetLastError();
 }
 
-// Workspace of the response-matrix build, in bytes (layout below).
 // Workspace of the response-matrix build (layout in sysmat_layout).
 struct SysLayout {
     uint64_t* start;       // [nr + 1] row starts in the sorted items
@@ -1608,11 +1720,6 @@ hipError_t sweep_grid(K kernel, int64_t rows, int gs, int n_cu, int* grid) {
     const uint64_t threads = ((uint64_t)std::max<int64_t>(rows, 1) + 3) / 4 * (uint64_t)gs;
     *grid = grid_for(threads, T256, std::max(1, n_cu * bpc));
     return hipSuccess;
-}
-
-template <class K>
-K by_group(int gs, K k1, K k4, K k16, K k64) {
-    return gs == 1 ? k1 : gs == 4 ? k4 : gs == 16 ? k16 : k64;
 }
 
 }  // namespace

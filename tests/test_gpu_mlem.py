@@ -306,6 +306,33 @@ def test_osem_one_subset_equals_mlem_kernel():
     np.testing.assert_allclose(b.cpu().numpy(), a.cpu().numpy(), rtol=1e-6)
 
 
+def test_osem_subset_limit_and_entry_check():
+    """At most 64 subsets (one wavefront lane per subset in the split of the
+    backprojector); a wrong entry count of b leaves the image NaN."""
+    mc = _mc()
+    import torch
+    T, n, bpv = _views_system(56)
+    m = mc.csr_from_scipy(T)
+    rng = np.random.Generator(np.random.PCG64(57))
+    m.proj = torch.as_tensor(rng.poisson(T.astype(np.float64) @ n * 3).astype(np.float32), device="cuda")
+    assert mc._lib.osem_workspace_bytes(m.n_bins, m.n_img, 65, m.nnz) == 0
+    with pytest.raises(mc.McError):
+        mc.osem(m, torch.ones(m.n_img, dtype=torch.float32, device="cuda"), 1, 65, bpv)
+    nb = mc._lib.osem_workspace_bytes(m.n_bins, m.n_img, 4, m.nnz + 1)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    img = torch.ones(m.n_img, dtype=torch.float32, device="cuda")
+    rc = mc._lib.osem_iterate(m.n_bins, m.n_img, bpv, 4, m.T_rowptr.data_ptr(), m.T_col.data_ptr(),
+                              m.T_val.data_ptr(), m.Tt_rowptr.data_ptr(), m.Tt_col.data_ptr(),
+                              m.Tt_val.data_ptr(), m.nnz + 1, m.proj.data_ptr(), None, img.data_ptr(), 2,
+                              ws.data_ptr(), nb, mc._stream_ptr())
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(img).all())
+    ok = torch.ones(m.n_img, dtype=torch.float32, device="cuda")
+    mc.osem(m, ok, 2, 4, bpv)
+    assert bool(torch.isfinite(ok).all())
+
+
 def test_dual_matrix_and_scatter_forms_thorax():
     """Dual-matrix (backproject with the primary-only matrix) and additive
     scatter (primary matrix + scatter projection) forms on a thorax, GPU

@@ -125,7 +125,6 @@ struct Cst {
 // it, with the hardware log2) and the photoelectric share f (140/E)^3 / g.
 // The KN ratio is linearly interpolated (error below 1e-6 relative over the
 // table range), the photoelectric term is exact.
-// sigma_KN(e) / sigma_KN(140), linearly interpolated in the table.
 __device__ inline float kn_ratio(const Cst& C, float e) {
     const float t = (C.e0 - e) * KN_TABLE_STEP_INV;
     const int i = (int)t;
@@ -256,10 +255,9 @@ __device__ inline int escape(const Cst& C, const Lane& L, int& iu, int& iv) {
     return MC_TALLIED;
 }
 
-// Turn the direction by polar cosine ct and azimuth 2 pi phi_u (standard
-// formula; near the poles the direction is taken as +-z).
 // Rotate unit direction (u, v, w) by polar cosine ct and azimuth phi_u (in
-// revolutions), with the near-pole branch for |w| > 0.99999.
+// revolutions): the standard formula, with the near-pole branch for
+// |w| > 0.99999 (the direction then taken as +-z).
 __device__ inline void rotate_dir(float& u, float& v, float& w, float ct, float phi_u) {
     const float sp = sin_rev(phi_u), cp = cos_rev(phi_u);
     const float st = sqrtf_hw(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));
@@ -278,6 +276,7 @@ __device__ inline void rotate_dir(float& u, float& v, float& w, float ct, float 
     }
 }
 
+// rotate_dir on a lane's direction.
 __device__ inline void rotate(Lane& L, float ct, float phi_u) {
     const float sp = sin_rev(phi_u), cp = cos_rev(phi_u);
     const float st = sqrtf_hw(fmaxf(0.0f, (1.0f - ct) * (1.0f + ct)));

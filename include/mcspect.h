@@ -425,7 +425,10 @@ size_t osem_workspace_bytes(int64_t n_bins, int64_t n_vox, int32_t n_subsets, in
  * B^T is split by subset in the workspace (for subset k and voxel i, the
  * entries of row i whose bin is in subset k, in row order), so each subset's
  * backprojection reads only its own entries.  FP32 matrix values, FP64
- * accumulation.  Asynchronous on stream, no allocation. */
+ * accumulation.  Column indices must lie in range (C_col < n_vox, Bt_col <
+ * n_bins; not checked).  Errors: MC_EINVAL for bad sizes or null pointers,
+ * MC_ENOMEM if workspace_bytes < osem_workspace_bytes(...).  Asynchronous on
+ * stream, no allocation. */
 int osem_iterate(int64_t n_bins, int64_t n_vox, int32_t bins_per_view, int32_t n_subsets,
                  const int64_t* C_rowptr, const int32_t* C_col, const float* C_val,
                  const int64_t* Bt_rowptr, const int32_t* Bt_col, const float* Bt_val, int64_t bt_nnz,

@@ -198,8 +198,9 @@ struct Lane {
     float w;            // statistical weight (forced direction / interaction)
 };
 
-// Per-lane work counters of a history (replay and adjoint; the transport
-// kernel counts by wavefront ballots instead).
+// Per-lane work counters: tentative collisions, real collisions, Kahn
+// attempts (per history in replay and adjoint; the transport kernel keeps
+// them over all of a lane's histories and sums them over the wave).
 struct Acc {
     uint32_t n_tent, n_real, n_kahn;
 };

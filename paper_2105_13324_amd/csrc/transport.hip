@@ -37,23 +37,31 @@ __device__ __forceinline__ uint32_t wsum32(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
     return v;
 }
+// Lanes of mask m below this lane (two mbcnt instructions).
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ __forceinline__ long long wsum64(long long v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
 // Wave-wide flush of one problem's accumulators (all 64 lanes must call).
-// fc: wave-uniform fate counts; wc: wave-uniform tentative collisions, real
-// collisions, Kahn attempts; e_esc: the lane's escaped energy (Q40.23);
+// fc: wave-uniform fate counts; A: the lane's tentative collisions, real
+// collisions and Kahn attempts (advance() counts them; summed here, which
+// costs less than three ballots per iteration); e_esc: the lane's escaped
+// energy (Q40.23);
 // rays / pieces: the lane's forced-copy ray walks and the voxels they
 // visited.  The deposited energy is filled in after the kernel (k_finalize).
 // count_tallied: add the tallied histories to T.n_events (an analog run
 // without an event list, whose count needs no per-history atomic).
-__device__ inline void flush(long long& e_esc, uint32_t* fc, uint32_t* wc, uint32_t& rays,
+__device__ inline void flush(long long& e_esc, uint32_t* fc, Acc& A, uint32_t& rays,
                              uint32_t& pieces, int p, const TransportArgs& T, int lane,
                              bool count_tallied) {
     const long long ee = wsum64(e_esc);
     const long long n_rays = wsum64(rays), n_pieces = wsum64(pieces);
+    const long long n_tent = wsum64(A.n_tent), n_real = wsum64(A.n_real), n_kahn = wsum64(A.n_kahn);
     uint32_t nh = 0;
 #pragma unroll
     for (int i = 0; i < 7; ++i) nh += fc[i];
@@ -65,9 +73,9 @@ __device__ inline void flush(long long& e_esc, uint32_t* fc, uint32_t* wc, uint3
         if (count_tallied && fc[MC_TALLIED]) atomicAdd(T.n_events, (unsigned long long)fc[MC_TALLIED]);
         if (T.counters) {
             unsigned long long* ca = (unsigned long long*)(T.counters + (size_t)p * MC_N_COUNTERS);
-            atomicAdd(ca + 0, (unsigned long long)wc[0]);
-            atomicAdd(ca + 1, (unsigned long long)wc[1]);
-            atomicAdd(ca + 2, (unsigned long long)wc[2]);
+            atomicAdd(ca + 0, (unsigned long long)n_tent);
+            atomicAdd(ca + 1, (unsigned long long)n_real);
+            atomicAdd(ca + 2, (unsigned long long)n_kahn);
             atomicAdd(ca + 3, (unsigned long long)nh);
             if (n_rays) {
                 atomicAdd(ca + 4, (unsigned long long)n_rays);
@@ -83,7 +91,7 @@ __device__ inline void flush(long long& e_esc, uint32_t* fc, uint32_t* wc, uint3
     rays = pieces = 0;
 #pragma unroll
     for (int i = 0; i < 7; ++i) fc[i] = 0;
-    wc[0] = wc[1] = wc[2] = 0;
+    acc_zero(A);
 }
 
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
@@ -213,7 +221,7 @@ __device__ inline void fd_commit(const Cst& C, int p, const FdPoint& q, bool val
             ev.bin = bin;
             ev.emit_voxel = q.voxel;
             ev.weight = w;
-            stage[ev_count + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = ev;
+            stage[ev_count + lanes_below(m)] = ev;
         }
         ev_count += (uint32_t)__popcll(m);
     }
@@ -252,7 +260,6 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
     const bool count_tallied = !FD && T.n_events && !T.events;
     const int lane = threadIdx.x & 63;
     uint32_t fd_head = 0, fd_tail = 0;    // wave-uniform ring cursors (FD)
-    const uint64_t lane_lt = (1ull << lane) - 1ull;
     const uint64_t full = __ballot(1);   // lanes of this wavefront
     // chunk bookkeeping (wave-uniform): problem-local work range [c_next, c_end)
     // and the (view, history id) of c_next; staged records [s_next, s_end)
@@ -262,7 +269,6 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
     bool exhausted = false, have_pending = false;
     uint64_t pending = 0;
     uint32_t fc[7] = {0, 0, 0, 0, 0, 0, 0};   // wave-uniform fate counts
-    uint32_t wc[3] = {0, 0, 0};               // wave-uniform work counters
     long long e_esc = 0;                      // escaped energy, Q40.23 (per lane)
     uint32_t fd_rays = 0, fd_pieces = 0;      // forced-copy ray walks, voxels visited (per lane)
     uint32_t ev_count = 0;                    // staged events (forced detection, wave-uniform)
@@ -270,7 +276,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
     Cst C;
     Lane L;
     L.state = S_IDLE;
-    Acc A;            // advance()'s per-lane counters: unused here (counted by ballots)
+    Acc A;            // advance()'s per-lane work counters, summed over the wave at flush
     acc_zero(A);
     // chunk prefix lives after the work prefix: [n_problems + 1] entries
     const uint64_t* __restrict__ chunk_prefix = T.work_prefix + (T.n_problems + 1);
@@ -310,7 +316,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                             ready = false;                 // drain problem p first
                         } else {
                             if (np != p) {
-                                if (p >= 0) flush(e_esc, fc, wc, fd_rays, fd_pieces, p, T, lane, count_tallied);
+                                if (p >= 0) flush(e_esc, fc, A, fd_rays, fd_pieces, p, T, lane, count_tallied);
                                 p = np;
                                 C = load_cst(T.descs + p);
                                 if (C.use_pal) {
@@ -376,7 +382,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             }
             if (ready && s_next < s_end) {
                 const uint32_t avail = s_end - s_next;
-                const uint32_t rank = __popcll(need & lane_lt);
+                const uint32_t rank = lanes_below(need);
                 if (L.state == S_IDLE && rank < avail) slot = (int)(s_next + rank);
                 s_next += min((uint32_t)__popcll(need), avail);
             }
@@ -415,15 +421,11 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                 }
             }
         }
-        // work counters by ballot: a tentative collision unless the step cap
-        // stopped it; a real one if it absorbed or started a Compton scatter
         MC_REGION(RG_WORK_COUNT);
-        const bool real = (before == S_STEP) &
-                          ((fate == MC_ABSORBED) | ((fate == R_RUNNING) & (L.state == S_KAHN)));
-        wc[0] += (uint32_t)__popcll(__ballot((before == S_STEP) & (fate != MC_CAPPED_FATE)));
-        wc[1] += (uint32_t)__popcll(__ballot(real));
-        wc[2] += (uint32_t)__popcll(__ballot(before == S_KAHN));
         if constexpr (FD) {
+            // a real collision: absorbed, or a Compton scatter started
+            const bool real = (before == S_STEP) &
+                              ((fate == MC_ABSORBED) | ((fate == R_RUNNING) & (L.state == S_KAHN)));
             // real collisions queue their forced copies (position, direction
             // and energy before the collision are still the lane's)
             const uint64_t m = __ballot(real);
@@ -433,7 +435,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                     q.x = L.x; q.y = L.y; q.z = L.z; q.dx = L.dx; q.dy = L.dy; q.dz = L.dz;
                     q.e = L.e; q.view = (uint32_t)L.view; q.hist = L.hist; q.event = L.n;
                     q.voxel = L.emit_voxel;
-                    ring[(fd_tail + (uint32_t)__popcll(m & lane_lt)) & (FD_RING - 1)] = q;
+                    ring[(fd_tail + lanes_below(m)) & (FD_RING - 1)] = q;
                 }
                 fd_tail += (uint32_t)__popcll(m);
             }
@@ -485,7 +487,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                     unsigned long long base = 0;
                     if (lane == 0) base = atomicAdd(T.n_events, (unsigned long long)__popcll(tallied));
                     base = uniform64(base);
-                    const unsigned long long idx = base + (unsigned long long)__popcll(tallied & lane_lt);
+                    const unsigned long long idx = base + (unsigned long long)lanes_below(tallied);
                     if (fate == MC_TALLIED && idx < T.event_capacity) {
                         mc_event ev;
                         ev.work = T.work_prefix[p] + (work_of(C, L.view, L.hist) - C.work_begin);
@@ -499,7 +501,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             if (fate != R_RUNNING) L.state = S_IDLE;
         }
     }
-    if (p >= 0) flush(e_esc, fc, wc, fd_rays, fd_pieces, p, T, lane, count_tallied);
+    if (p >= 0) flush(e_esc, fc, A, fd_rays, fd_pieces, p, T, lane, count_tallied);
     if (fd_list) flush_events(T, ev_stage, ev_count, lane);
     MC_REGION(-2);
 }

@@ -42,6 +42,18 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Per-lane fate counts packed in 9-bit fields (fate f at bit 9 f), added to
+// the wave-uniform counts fc and cleared: a lane ends at most one history
+// per iteration, so a fold at least every 511 iterations keeps each field
+// from overflowing.  All 64 lanes call.
+constexpr uint32_t FATE_FOLD = 511;
+__device__ inline void fold_fates(uint64_t& fpk, uint32_t* fc) {
+#pragma unroll
+    for (int f = 0; f < 7; ++f)
+        fc[f] += __builtin_amdgcn_readfirstlane(wsum32((uint32_t)(fpk >> (9 * f)) & 511u));
+    fpk = 0;
+}
+
 __device__ __forceinline__ long long wsum64(long long v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
@@ -269,6 +281,12 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
     bool exhausted = false, have_pending = false;
     uint64_t pending = 0;
     uint32_t fc[7] = {0, 0, 0, 0, 0, 0, 0};   // wave-uniform fate counts
+    // packed per-lane fate counts (fold_fates), cheaper per iteration than
+    // seven ballots; the weighted mode keeps the ballots (its registers are
+    // tighter: the packed counts spill there)
+    constexpr bool PACK_FATES = !VR;
+    uint64_t fpk = 0;
+    uint32_t fpk_iter = 0;
     long long e_esc = 0;                      // escaped energy, Q40.23 (per lane)
     uint32_t fd_rays = 0, fd_pieces = 0;      // forced-copy ray walks, voxels visited (per lane)
     uint32_t ev_count = 0;                    // staged events (forced detection, wave-uniform)
@@ -316,7 +334,10 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                             ready = false;                 // drain problem p first
                         } else {
                             if (np != p) {
-                                if (p >= 0) flush(e_esc, fc, A, fd_rays, fd_pieces, p, T, lane, count_tallied);
+                                if (p >= 0) {
+                                    if (PACK_FATES) fold_fates(fpk, fc);
+                                    flush(e_esc, fc, A, fd_rays, fd_pieces, p, T, lane, count_tallied);
+                                }
                                 p = np;
                                 C = load_cst(T.descs + p);
                                 if (C.use_pal) {
@@ -452,9 +473,12 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
         }
         if (__ballot(fate != R_RUNNING) != 0) {
             MC_REGION(RG_FATES);
-            // fate counts through ballots: wave-uniform, no per-lane counters
+            if constexpr (PACK_FATES) {
+                if (fate != R_RUNNING) fpk += 1ull << (9 * fate);
+            } else {
 #pragma unroll
-            for (int f = 0; f < 7; ++f) fc[f] += (uint32_t)__popcll(__ballot(fate == f));
+                for (int f = 0; f < 7; ++f) fc[f] += (uint32_t)__popcll(__ballot(fate == f));
+            }
             const uint64_t tallied = FD ? 0ull : __ballot(fate == MC_TALLIED);
             if (tallied != 0) {
                 MC_REGION(RG_TALLY);
@@ -500,7 +524,12 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             }
             if (fate != R_RUNNING) L.state = S_IDLE;
         }
+        if (PACK_FATES && ++fpk_iter == FATE_FOLD) {
+            fold_fates(fpk, fc);
+            fpk_iter = 0;
+        }
     }
+    if (PACK_FATES) fold_fates(fpk, fc);
     if (p >= 0) flush(e_esc, fc, A, fd_rays, fd_pieces, p, T, lane, count_tallied);
     if (fd_list) flush_events(T, ev_stage, ev_count, lane);
     MC_REGION(-2);

@@ -572,24 +572,32 @@ struct FdPoint {
 
 constexpr int RAY_BATCH = 8;
 
-// State of a voxel walk: the current voxel (per axis and linear), the ray
-// parameter reached, the next plane per axis, and whether it has ended.
+// State of a voxel walk: the current voxel (linear index), the planes
+// crossed, the ray parameter reached, the next plane per axis, and whether
+// it has ended.
 struct RayWalk {
-    int ix, iy, iz, v;
+    int v;
+    uint32_t n;
     float t, tx, ty, tz;
     bool done;
 };
-// What the walk does not change: steps per axis (voxel and linear), plane
-// spacing in t per axis, the exit parameter.
+// What the walk does not change: linear voxel step per axis, plane spacing
+// in t per axis, the exit parameter, the last voxel index.
 struct RaySteps {
-    int sx, sy, sz, stx, sty, stz;
+    int stx, sty, stz;
     float ddx, ddy, ddz, t_exit;
+    uint32_t vmax;
 };
 
 // RAY_BATCH pieces of the walk: piece k is voxel v from t to min(next plane,
-// exit); a finished walk repeats its last (valid) voxel with length 0.  The
-// pieces' mu gathers are issued at the end (byte offsets below 2^32: axes of
-// at most 1024 voxels).
+// exit); a finished walk repeats its last voxel with length 0.  The walk ends
+// when the next plane lies at or beyond the exit (the grid's, or the
+// attenuation box's); the voxels are not tracked per axis.  Where rounding
+// puts the grid's last plane just before t_exit, the walk takes one more
+// step, past the grid edge, whose piece is as short as that rounding
+// difference: its index is clamped into the map (any voxel's mu times a
+// length of rounding size).  The pieces' mu gathers are issued at the end
+// (byte offsets below 2^32: axes of at most 1024 voxels).
 __device__ __forceinline__ void ray_batch(const Cst& C, const RaySteps& s, RayWalk& w,
                                           const float* __restrict__ mu_map, float (&mu)[RAY_BATCH],
                                           float (&lb)[RAY_BATCH]) {
@@ -597,18 +605,15 @@ __device__ __forceinline__ void ray_batch(const Cst& C, const RaySteps& s, RayWa
 #pragma unroll
     for (int k = 0; k < RAY_BATCH; ++k) {
         const float tn = fminf(w.tx, fminf(w.ty, w.tz));
-        vb[k] = (uint32_t)w.v;
+        vb[k] = min((uint32_t)w.v, s.vmax);
         lb[k] = w.done ? 0.0f : fminf(tn, s.t_exit) - w.t;
         const bool bx = (w.tx <= w.ty) & (w.tx <= w.tz);
         const bool by = !bx & (w.ty <= w.tz);
         const bool bz = !bx & !by;
-        const int nix = w.ix + (bx ? s.sx : 0), niy = w.iy + (by ? s.sy : 0), niz = w.iz + (bz ? s.sz : 0);
-        const bool out = ((unsigned)nix >= (unsigned)C.nx) | ((unsigned)niy >= (unsigned)C.ny) |
-                         ((unsigned)niz >= (unsigned)C.nz);
-        w.done = w.done | (tn >= s.t_exit) | out;
+        w.done = w.done | (tn >= s.t_exit);
         if (!w.done) {
             w.t = tn;
-            w.ix = nix; w.iy = niy; w.iz = niz;
+            w.n += 1;
             w.tx += bx ? s.ddx : 0.0f; w.ty += by ? s.ddy : 0.0f; w.tz += bz ? s.ddz : 0.0f;
             // one term per axis (selects against 0, not between the steps)
             w.v += (bx ? s.stx : 0) + (by ? s.sty : 0) + (bz ? s.stz : 0);
@@ -637,21 +642,17 @@ __device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox
                                uint32_t& pieces) {
     const float px = x + C.hx, py = y + C.hy, pz = z + C.hz;
     RayWalk w;
-    w.ix = min(max((int)(px * C.inv_vox), 0), C.nx - 1);
-    w.iy = min(max((int)(py * C.inv_vox), 0), C.ny - 1);
-    w.iz = min(max((int)(pz * C.inv_vox), 0), C.nz - 1);
-    const int ix0 = w.ix, iy0 = w.iy, iz0 = w.iz;
+    const int ix = min(max((int)(px * C.inv_vox), 0), C.nx - 1);
+    const int iy = min(max((int)(py * C.inv_vox), 0), C.ny - 1);
+    const int iz = min(max((int)(pz * C.inv_vox), 0), C.nz - 1);
     const float inf = __builtin_huge_valf();
     // 1 / o per axis (inf for a zero component: never selected)
     const float rx = ox != 0.0f ? 1.0f / ox : inf, ry = oy != 0.0f ? 1.0f / oy : inf;
     const float rz = oz != 0.0f ? 1.0f / oz : inf;
     RaySteps s;
-    s.sx = ox > 0.0f ? 1 : -1;
-    s.sy = oy > 0.0f ? 1 : -1;
-    s.sz = oz > 0.0f ? 1 : -1;
-    w.tx = ox != 0.0f ? fmaxf(((float)(w.ix + (ox > 0.0f)) * C.vox - px) * rx, 0.0f) : inf;
-    w.ty = oy != 0.0f ? fmaxf(((float)(w.iy + (oy > 0.0f)) * C.vox - py) * ry, 0.0f) : inf;
-    w.tz = oz != 0.0f ? fmaxf(((float)(w.iz + (oz > 0.0f)) * C.vox - pz) * rz, 0.0f) : inf;
+    w.tx = ox != 0.0f ? fmaxf(((float)(ix + (ox > 0.0f)) * C.vox - px) * rx, 0.0f) : inf;
+    w.ty = oy != 0.0f ? fmaxf(((float)(iy + (oy > 0.0f)) * C.vox - py) * ry, 0.0f) : inf;
+    w.tz = oz != 0.0f ? fmaxf(((float)(iz + (oz > 0.0f)) * C.vox - pz) * rz, 0.0f) : inf;
     s.ddx = ox != 0.0f ? C.vox * fabsf(rx) : inf;
     s.ddy = oy != 0.0f ? C.vox * fabsf(ry) : inf;
     s.ddz = oz != 0.0f ? C.vox * fabsf(rz) : inf;
@@ -661,7 +662,7 @@ __device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox
     const float ey = oy > 0.0f ? (C.ly - py) * ry : (oy < 0.0f ? -py * ry : inf);
     const float ez = oz > 0.0f ? (C.lz - pz) * rz : (oz < 0.0f ? -pz * rz : inf);
     s.t_exit = fmaxf(fminf(ex, fminf(ey, ez)), 0.0f);
-    if (in_box(C, w.ix, w.iy, w.iz)) {
+    if (in_box(C, ix, iy, iz)) {
         const float bx = ox > 0.0f ? ((float)((C.bbx >> 16) + 1u) * C.vox - px) * rx
                                    : (ox < 0.0f ? ((float)(C.bbx & 0xFFFFu) * C.vox - px) * rx : inf);
         const float by = oy > 0.0f ? ((float)((C.bby >> 16) + 1u) * C.vox - py) * ry
@@ -670,10 +671,12 @@ __device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox
                                    : (oz < 0.0f ? ((float)(C.bbz & 0xFFFFu) * C.vox - pz) * rz : inf);
         s.t_exit = fminf(s.t_exit, fmaxf(fminf(bx, fminf(by, bz)), 0.0f));
     }
-    s.stx = s.sx;
-    s.sty = s.sy * C.nx;
-    s.stz = s.sz * C.nx * C.ny;
-    w.v = w.ix + C.nx * (w.iy + C.ny * w.iz);
+    s.stx = ox > 0.0f ? 1 : -1;
+    s.sty = oy > 0.0f ? C.nx : -C.nx;
+    s.stz = oz > 0.0f ? C.nx * C.ny : -(C.nx * C.ny);
+    s.vmax = (uint32_t)(C.nx * C.ny * C.nz - 1);
+    w.v = ix + C.nx * (iy + C.ny * iz);
+    w.n = 0;
     w.t = 0.0f;
     w.done = false;
     float sum = 0.0f;
@@ -695,9 +698,8 @@ __device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox
     } else {
         ray_add(sum, mu_a, lb_a);
     }
-    // voxels the walk visited (one plane crossing per step, so the index
-    // distance from the first voxel to the last, plus one)
-    pieces = (uint32_t)(abs(w.ix - ix0) + abs(w.iy - iy0) + abs(w.iz - iz0) + 1);
+    // voxels the walk visited: one per plane crossed, plus the first
+    pieces = w.n + 1;
     return sum;
 }
 

@@ -459,11 +459,13 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
             yn = fmaf(s, L.dy, L.y);
             zn = fmaf(s, L.dz, L.z);
             const float tx = xn + C.hx, ty = yn + C.hy, tz = zn + C.hz;
-            const bool inside = (tx >= 0.0f) & (tx < C.lx) & (ty >= 0.0f) & (ty < C.ly) &
-                                (tz >= 0.0f) & (tz < C.lz);
-            const int ix = min((int)(tx * C.inv_vox), C.nx - 1);
-            const int iy = min((int)(ty * C.inv_vox), C.ny - 1);
-            const int iz = min((int)(tz * C.inv_vox), C.nz - 1);
+            // the voxel by floor (negative below the grid), inside iff every
+            // index is in range: one test per axis decides both
+            const int ix = (int)floorf(tx * C.inv_vox);
+            const int iy = (int)floorf(ty * C.inv_vox);
+            const int iz = (int)floorf(tz * C.inv_vox);
+            const bool inside = ((uint32_t)ix < (uint32_t)C.nx) & ((uint32_t)iy < (uint32_t)C.ny) &
+                                ((uint32_t)iz < (uint32_t)C.nz);
             // in the air outside the attenuation box, moving away from it, every
             // later collision would be virtual: the photon escapes along this ray
             // from the new point (one escape path for both ways out, so the

@@ -396,7 +396,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                     s_next = 0;
-                    s_end = n_rec;
+                    s_end = __builtin_amdgcn_readfirstlane(n_rec);
                     c_next += n_rec;
                     advance_cursor(C, cur_view, cur_hist, n_rec, C.n_views);
                 }
@@ -405,7 +405,9 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                 const uint32_t avail = s_end - s_next;
                 const uint32_t rank = lanes_below(need);
                 if (L.state == S_IDLE && rank < avail) slot = (int)(s_next + rank);
-                s_next += min((uint32_t)__popcll(need), avail);
+                // read back as uniform: the cursor then stays in a scalar
+                // register and the slot pick above is scalar work
+                s_next = __builtin_amdgcn_readfirstlane(s_next + min((uint32_t)__popcll(need), avail));
             }
         }
         if (slot >= 0) {

@@ -705,11 +705,26 @@ __device__ inline float ray_mu(const Cst& C, float x, float y, float z, float ox
     return sum;
 }
 
-// Score of one forced copy: false if it scores nothing, else its bin within
-// the problem (tally layout) and its weight.  d: the problem's descriptor
-// (cone and Klein-Nishina constants).
-__device__ inline bool fd_eval(const Cst& C, const ProbDesc* __restrict__ d, const FdPoint& q,
-                               uint32_t& bin, float& score, uint32_t& pieces) {
+// A forced copy that scores, up to its ray walk: start point, direction,
+// weight before transmission, the attenuation scale g(E') of the walk's
+// integral, its target (tally bin, or index in the CFD depth layers), and
+// what the tally and the event list take from the copy (view, history id,
+// emission voxel).  Score = w exp(-g integral of mu140 along the ray).
+struct FdJob {
+    float x, y, z, ox, oy, oz, w, g;
+    uint32_t bin_lo, bin_hi;
+    uint32_t view, hist, voxel;
+};
+
+__device__ inline float fd_walk_score(const Cst& C, const FdJob& j, uint32_t& pieces) {
+    return j.w * __expf(-j.g * ray_mu(C, j.x, j.y, j.z, j.ox, j.oy, j.oz, pieces));
+}
+
+// Set-up of one forced copy: false if it scores nothing (energy out of the
+// window or cut, or the ray misses the detector), else its job with the
+// tally bin in bin_lo.  d: the problem's descriptor (cone and Klein-Nishina
+// constants).
+__device__ inline bool fd_setup(const Cst& C, const ProbDesc* __restrict__ d, const FdPoint& q, FdJob& j) {
     const float omc = d->omc_alpha, kn140 = (float)d->kn140;
     uint32_t r0 = q.hist, r1 = q.view, r2 = q.event, r3 = FD_SUB;
     philox10(r0, r1, r2, r3, C.seed, C.pid);
@@ -740,10 +755,14 @@ __device__ inline bool fd_eval(const Cst& C, const ProbDesc* __restrict__ d, con
     const int iu = min((int)(au * C.inv_pix), C.nu - 1);
     const int iv = min((int)(av * C.inv_pix), C.nv - 1);
     float l2, ppe;
-    const float g = e2 == C.e0 ? C.g0 : energy_terms(C, e2, l2, ppe);
-    score = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, ox, oy, oz, pieces));
+    j.g = e2 == C.e0 ? C.g0 : energy_terms(C, e2, l2, ppe);
+    j.x = q.x; j.y = q.y; j.z = q.z;
+    j.ox = ox; j.oy = oy; j.oz = oz;
+    j.w = w;
     const uint32_t cls = q.event == 0 ? 0u : 1u;
-    bin = ((q.view * 2u + cls) * (uint32_t)C.nv + (uint32_t)iv) * (uint32_t)C.nu + (uint32_t)iu;
+    j.bin_lo = ((q.view * 2u + cls) * (uint32_t)C.nv + (uint32_t)iv) * (uint32_t)C.nu + (uint32_t)iu;
+    j.bin_hi = 0;
+    j.view = q.view; j.hist = q.hist; j.voxel = q.voxel;
     return true;
 }
 
@@ -751,12 +770,11 @@ __device__ inline bool fd_eval(const Cst& C, const ProbDesc* __restrict__ d, con
 // the detector normal n_k instead of a direction drawn in the cone, with the
 // weight above taken at that direction, and is stored in the sub-projection
 // layer of its depth D - n_k . x (one pixel per layer, clamped to the layer
-// range) at the pixel of its perpendicular hit.  Returns false if it scores
-// nothing, else its index in the problem's layers [V][L][2][nv][nu] and its
-// weight.  The layers are convolved with the collimator response of their
-// depth after transport.
-__device__ inline bool cfd_eval(const Cst& C, const ProbDesc* __restrict__ d, const FdPoint& q,
-                                uint64_t& lbin, float& score, uint32_t& pieces) {
+// range) at the pixel of its perpendicular hit.  The set-up: false if it
+// scores nothing, else its job with the index in the problem's layers
+// [V][L][2][nv][nu] in (bin_lo, bin_hi).  The layers are convolved with the
+// collimator response of their depth after transport.
+__device__ inline bool cfd_setup(const Cst& C, const ProbDesc* __restrict__ d, const FdPoint& q, FdJob& j) {
     const float omc = d->omc_alpha, kn140 = (float)d->kn140;
     const float2 vw = ldg(C.views + q.view);
     float w, e2;
@@ -783,11 +801,16 @@ __device__ inline bool cfd_eval(const Cst& C, const ProbDesc* __restrict__ d, co
     const float depth = C.radius - (q.x * vw.x + q.y * vw.y);
     const int l = min(max((int)floorf(depth * C.inv_pix), 0), nl - 1);
     float l2, ppe;
-    const float g = e2 == C.e0 ? C.g0 : energy_terms(C, e2, l2, ppe);
-    score = w * __expf(-g * ray_mu(C, q.x, q.y, q.z, vw.x, vw.y, 0.0f, pieces));
+    j.g = e2 == C.e0 ? C.g0 : energy_terms(C, e2, l2, ppe);
+    j.x = q.x; j.y = q.y; j.z = q.z;
+    j.ox = vw.x; j.oy = vw.y; j.oz = 0.0f;
+    j.w = w;
     const uint32_t cls = q.event == 0 ? 0u : 1u;
-    lbin = ((((uint64_t)q.view * (uint64_t)nl + (uint64_t)l) * 2u + cls) * (uint64_t)C.nv + (uint64_t)iv) *
-               (uint64_t)C.nu + (uint64_t)iu;
+    const uint64_t lbin = ((((uint64_t)q.view * (uint64_t)nl + (uint64_t)l) * 2u + cls) * (uint64_t)C.nv +
+                           (uint64_t)iv) * (uint64_t)C.nu + (uint64_t)iu;
+    j.bin_lo = (uint32_t)lbin;
+    j.bin_hi = (uint32_t)(lbin >> 32);
+    j.view = q.view; j.hist = q.hist; j.voxel = q.voxel;
     return true;
 }
 

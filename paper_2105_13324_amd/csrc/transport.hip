@@ -148,9 +148,11 @@ __device__ __forceinline__ uint64_t work_of(const Cst& C, uint64_t view, uint64_
     return view * C.q_per_view + min(view, C.r_extra) + hist;
 }
 
-// Emission records a wavefront stages in LDS: two per lane.
+// Emission records a wavefront stages in LDS: two per lane (one in the
+// forced-detection modes, whose LDS also holds the copy and job queues).
 constexpr int EMIT_PER_LANE = 2;
 constexpr int EMIT_BATCH = 64 * EMIT_PER_LANE;
+constexpr int emit_per_lane(int mode) { return mode == 1 || mode == 2 ? 1 : EMIT_PER_LANE; }
 constexpr int WAVES_PER_BLOCK_MAX = 4;    // 256 threads
 
 struct EmitRec {
@@ -159,10 +161,11 @@ struct EmitRec {
 };
 
 constexpr uint32_t FD_RING = 128;         // forced-detection queue per wave
+constexpr uint32_t FD_JOBS = 128;         // scoring jobs waiting for their walks, per wave
 // Events of listed forced copies staged per wave before one atomic appends
 // them: the list's counter is one address for the whole device, so one
 // atomic per few hundred events instead of one per scored batch.
-constexpr uint32_t EV_STAGE = 320;
+constexpr uint32_t EV_STAGE = 160;
 
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -189,49 +192,53 @@ __device__ inline void flush_events(const TransportArgs& T, const mc_event* stag
     count = 0;
 }
 
-// Score the forced copy of each lane with valid set: tally (Q31.32), sum of
-// squares (Q11.52) and, if listed, one event each into the wave's stage
-// (ev_count more; the caller keeps room for 64).  All 64 lanes call.
+// The set-up of one forced copy for this mode (false: it scores nothing).
 template <int MODE>
-__device__ inline void fd_commit(const Cst& C, int p, const FdPoint& q, bool valid, int lane,
-                                 const TransportArgs& T, uint32_t& rays, uint32_t& pieces,
-                                 mc_event* stage, uint32_t& ev_count) {
+__device__ __forceinline__ bool fd_setup_mode(const Cst& C, const ProbDesc* __restrict__ d, const FdPoint& q,
+                                              FdJob& j) {
+    if constexpr (MODE == 2) return cfd_setup(C, d, q, j);
+    else return fd_setup(C, d, q, j);
+}
+
+// Walk and score the job of each lane with valid set: tally (Q31.32), sum of
+// squares (Q11.52) and, if listed, one event each into the wave's stage
+// (ev_count more; the caller keeps room for 64); convolution-based forced
+// detection deposits into the depth layer instead (no events, no sum of
+// squares).  All 64 lanes call.
+template <int MODE>
+__device__ inline void fd_score(const Cst& C, int p, const FdJob& j, bool valid, int lane,
+                                const TransportArgs& T, uint32_t& rays, uint32_t& pieces,
+                                mc_event* stage, uint32_t& ev_count) {
     uint32_t pc = 0;
-    if constexpr (MODE == 2) {
-        // convolution-based: deposit into the depth layer (no events, no
-        // sum of squares)
-        uint64_t lb = 0;
-        float sc = 0.0f;
-        if (valid && cfd_eval(C, T.descs + p, q, lb, sc, pc))
-            atomicAdd((unsigned long long*)(T.descs[p].layers + lb),
-                      (unsigned long long)signed_weight(T.descs + p, q.voxel,
-                                                        __float2ll_rn(sc * 4294967296.0f)));
-        rays += pc != 0;
-        pieces += pc;
-        return;
-    }
-    uint32_t bin = 0;
     float sc = 0.0f;
-    bool ok = false;
-    if (valid) ok = fd_eval(C, T.descs + p, q, bin, sc, pc);
+    if (valid) sc = fd_walk_score(C, j, pc);
     rays += pc != 0;
     pieces += pc;
+    if constexpr (MODE == 2) {
+        if (valid) {
+            const uint64_t lb = ((uint64_t)j.bin_hi << 32) | j.bin_lo;
+            atomicAdd((unsigned long long*)(T.descs[p].layers + lb),
+                      (unsigned long long)signed_weight(T.descs + p, j.voxel,
+                                                        __float2ll_rn(sc * 4294967296.0f)));
+        }
+        return;
+    }
     long long w = 0;
-    if (ok) {
-        w = signed_weight(T.descs + p, q.voxel, __float2ll_rn(sc * 4294967296.0f));
-        const size_t b = C.tally_offset + bin;
+    if (valid) {
+        w = signed_weight(T.descs + p, j.voxel, __float2ll_rn(sc * 4294967296.0f));
+        const size_t b = C.tally_offset + j.bin_lo;
         atomicAdd((unsigned long long*)(T.tally + b), (unsigned long long)w);
         if (T.tally_sq)
             atomicAdd((unsigned long long*)(T.tally_sq + b),
                       (unsigned long long)__float2ll_rn(sc * sc * 4503599627370496.0f));
     }
     if (T.events) {            // forced copies are counted only when listed
-        const uint64_t m = __ballot(ok);
-        if (ok) {
+        const uint64_t m = __ballot(valid);
+        if (valid) {
             mc_event ev;
-            ev.work = T.work_prefix[p] + (work_of(C, q.view, q.hist) - C.work_begin);
-            ev.bin = bin;
-            ev.emit_voxel = q.voxel;
+            ev.work = T.work_prefix[p] + (work_of(C, j.view, j.hist) - C.work_begin);
+            ev.bin = j.bin_lo;
+            ev.emit_voxel = j.voxel;
             ev.weight = w;
             stage[ev_count + lanes_below(m)] = ev;
         }
@@ -239,22 +246,43 @@ __device__ inline void fd_commit(const Cst& C, int p, const FdPoint& q, bool val
     }
 }
 
-// Score the n (<= 64) forced copies at the head of a wave's ring (all 64
-// lanes call).
+// Set up the n (<= 64) forced copies at the head of a wave's ring and append
+// those that score to the wave's job queue (all 64 lanes call).  Most copies
+// of collisions score nothing (their energy leaves the window), so their ray
+// walks are deferred and run 64 scoring jobs at a time (fd_walk_jobs)
+// instead of a few lanes of each drained batch.
 template <int MODE>
 __device__ inline void fd_drain(const Cst& C, int p, const FdPoint* ring, uint32_t& head, uint32_t n,
-                                int lane, const TransportArgs& T, uint32_t& rays, uint32_t& pieces,
-                                mc_event* stage, uint32_t& ev_count) {
+                                int lane, const TransportArgs& T, FdJob* jq, uint32_t& jq_tail) {
     wave_sync_lds();
-    const bool valid = (uint32_t)lane < n;
-    FdPoint q = {};
-    if (valid) q = ring[(head + (uint32_t)lane) & (FD_RING - 1)];
-    fd_commit<MODE>(C, p, q, valid, lane, T, rays, pieces, stage, ev_count);
+    FdJob j;
+    bool ok = false;
+    if ((uint32_t)lane < n) {
+        const FdPoint q = ring[(head + (uint32_t)lane) & (FD_RING - 1)];
+        ok = fd_setup_mode<MODE>(C, T.descs + p, q, j);
+    }
+    const uint64_t m = __ballot(ok);
+    if (ok) jq[(jq_tail + lanes_below(m)) & (FD_JOBS - 1)] = j;
+    jq_tail += (uint32_t)__popcll(m);
     head += n;
 }
 
+// Walk and score the n (<= 64) jobs at the head of the wave's job queue
+// (all 64 lanes call).
+template <int MODE>
+__device__ inline void fd_walk_jobs(const Cst& C, int p, const FdJob* jq, uint32_t& jq_head, uint32_t n,
+                                    int lane, const TransportArgs& T, uint32_t& rays, uint32_t& pieces,
+                                    mc_event* stage, uint32_t& ev_count) {
+    wave_sync_lds();
+    const bool valid = (uint32_t)lane < n;
+    FdJob j = {};
+    if (valid) j = jq[(jq_head + (uint32_t)lane) & (FD_JOBS - 1)];
+    fd_score<MODE>(C, p, j, valid, lane, T, rays, pieces, stage, ev_count);
+    jq_head += n;
+}
+
 // Persistent transport: waves claim chunks of work until none are left.
-// A wavefront emits the next EMIT_BATCH histories of its chunk in one
+// A wavefront emits the next 64 x emit_per_lane histories of its chunk in one
 // converged phase into LDS; idle lanes then start histories from there, so
 // the per-lane loop only alternates tentative collisions and Kahn attempts.
 // MODE 0: analog arrivals into the tally; 1: forced detection (tally);
@@ -264,7 +292,10 @@ template <int MODE>
 __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restrict__ my,
                                                uint32_t* __restrict__ my_pal,
                                                FdPoint* __restrict__ ring,
+                                               FdJob* __restrict__ jq,
                                                mc_event* __restrict__ ev_stage) {
+    constexpr int EPL = emit_per_lane(MODE);
+    constexpr int EBATCH = 64 * EPL;
     constexpr bool FD = MODE == 1 || MODE == 2;
     constexpr bool VR = MODE == 3;
     const bool vr_dir = VR && (T.vr_flags & VR_FORCED_DIRECTION);
@@ -272,6 +303,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
     const bool count_tallied = !FD && T.n_events && !T.events;
     const int lane = threadIdx.x & 63;
     uint32_t fd_head = 0, fd_tail = 0;    // wave-uniform ring cursors (FD)
+    uint32_t jq_head = 0, jq_tail = 0;    // wave-uniform job queue cursors (FD)
     const uint64_t full = __ballot(1);   // lanes of this wavefront
     // chunk bookkeeping (wave-uniform): problem-local work range [c_next, c_end)
     // and the (view, history id) of c_next; staged records [s_next, s_end)
@@ -330,7 +362,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                         }
                         const int np = __builtin_amdgcn_readfirstlane(lo);
                         // drain problem p first: no lane busy, no forced copy queued
-                        if (np != p && (need != full || (FD && fd_tail != fd_head))) {
+                        if (np != p && (need != full || (FD && (fd_tail != fd_head || jq_tail != jq_head)))) {
                             ready = false;                 // drain problem p first
                         } else {
                             if (np != p) {
@@ -364,10 +396,10 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                 }
                 if (ready && c_next < c_end) {
                     MC_REGION(RG_EMIT);
-                    const uint32_t n_rec = (uint32_t)min((uint64_t)EMIT_BATCH, c_end - c_next);
-                    if (fd_list && ev_count > EV_STAGE - EMIT_BATCH) flush_events(T, ev_stage, ev_count, lane);
+                    const uint32_t n_rec = (uint32_t)min((uint64_t)EBATCH, c_end - c_next);
+                    if (fd_list && ev_count > EV_STAGE - EBATCH) flush_events(T, ev_stage, ev_count, lane);
 #pragma unroll 1
-                    for (int k = 0; k < EMIT_PER_LANE; ++k) {
+                    for (int k = 0; k < EPL; ++k) {
                         const uint32_t idx = (uint32_t)(k * 64 + lane);
                         FdPoint q = {};
                         if (idx < n_rec) {
@@ -385,11 +417,13 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                                 q.voxel = e.voxel;
                             }
                         }
-                        // the emission point's forced copy (all lanes: the
-                        // event stage is appended wave-wide)
-                        if constexpr (FD)
-                            fd_commit<MODE>(C, p, q, idx < n_rec, lane, T, fd_rays, fd_pieces, ev_stage,
-                                            ev_count);
+                        // the emission point's forced copy, scored at once (all
+                        // lanes: the event stage is appended wave-wide)
+                        if constexpr (FD) {
+                            FdJob j;
+                            const bool ok = idx < n_rec && fd_setup_mode<MODE>(C, T.descs + p, q, j);
+                            fd_score<MODE>(C, p, j, ok, lane, T, fd_rays, fd_pieces, ev_stage, ev_count);
+                        }
                     }
                     // the records are read by other lanes of this wavefront
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -420,7 +454,8 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             if (vr_dir) L.w = 0.5f * T.vr_omc;     // Omega / (4 pi)
         }
         MC_REGION(RG_EXIT_TEST);
-        if (exhausted && __ballot(L.state != S_IDLE) == 0 && (!FD || fd_tail == fd_head)) break;
+        if (exhausted && __ballot(L.state != S_IDLE) == 0 && (!FD || (fd_tail == fd_head && jq_tail == jq_head)))
+            break;
 
         int fate = R_RUNNING;
         int iu, iv;               // set by the escape of a history that arrives
@@ -463,14 +498,20 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                 fd_tail += (uint32_t)__popcll(m);
             }
             // the one place forced copies of collisions are scored (one code
-            // path, so a score never depends on where it was drained): 64 at
-            // a time, or what is left once no lane is busy
+            // path, so a score never depends on where it was drained): set
+            // up 64 at a time, or what is left once no lane is busy; the
+            // walks of those that score run 64 at a time, or the rest once
+            // no lane is busy and no copy is queued
             MC_REGION(RG_FORCED);
             const uint32_t cnt = fd_tail - fd_head;
-            if (cnt >= 64 || (cnt != 0 && __ballot(L.state != S_IDLE) == 0)) {
+            const bool none_busy = __ballot(L.state != S_IDLE) == 0;
+            if (cnt >= 64 || (cnt != 0 && none_busy))
+                fd_drain<MODE>(C, p, ring, fd_head, cnt < 64 ? cnt : 64u, lane, T, jq, jq_tail);
+            const uint32_t nj = jq_tail - jq_head;
+            if (nj >= 64 || (nj != 0 && none_busy && fd_tail == fd_head)) {
                 if (fd_list && ev_count > EV_STAGE - 64) flush_events(T, ev_stage, ev_count, lane);
-                fd_drain<MODE>(C, p, ring, fd_head, cnt < 64 ? cnt : 64u, lane, T, fd_rays, fd_pieces,
-                               ev_stage, ev_count);
+                fd_walk_jobs<MODE>(C, p, jq, jq_head, nj < 64 ? nj : 64u, lane, T, fd_rays, fd_pieces,
+                                   ev_stage, ev_count);
             }
         }
         if (__ballot(fate != R_RUNNING) != 0) {
@@ -540,30 +581,32 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport(TransportArgs T) {
     __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
     __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
-    transport_body<0>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr, nullptr);
+    transport_body<0>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr, nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(256) void k_transport_fd(TransportArgs T) {
-    __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
+    __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][64 * emit_per_lane(1)];
     __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
     __shared__ FdPoint ring[WAVES_PER_BLOCK_MAX][FD_RING];
+    __shared__ FdJob jobs[WAVES_PER_BLOCK_MAX][FD_JOBS];
     __shared__ mc_event ev_stage[WAVES_PER_BLOCK_MAX][EV_STAGE];
     transport_body<1>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6],
-                      ring[threadIdx.x >> 6], ev_stage[threadIdx.x >> 6]);
+                      ring[threadIdx.x >> 6], jobs[threadIdx.x >> 6], ev_stage[threadIdx.x >> 6]);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_transport_vr(TransportArgs T) {
     __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
     __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
-    transport_body<3>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr, nullptr);
+    transport_body<3>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6], nullptr, nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(256) void k_transport_cfd(TransportArgs T) {
-    __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][EMIT_BATCH];
+    __shared__ EmitRec stage[WAVES_PER_BLOCK_MAX][64 * emit_per_lane(2)];
     __shared__ uint32_t pal_copy[WAVES_PER_BLOCK_MAX][PALETTE_N];
     __shared__ FdPoint ring[WAVES_PER_BLOCK_MAX][FD_RING];
+    __shared__ FdJob jobs[WAVES_PER_BLOCK_MAX][FD_JOBS];
     transport_body<2>(T, stage[threadIdx.x >> 6], pal_copy[threadIdx.x >> 6],
-                      ring[threadIdx.x >> 6], nullptr);
+                      ring[threadIdx.x >> 6], jobs[threadIdx.x >> 6], nullptr);
 }
 
 // Replay: one listed history per lane, run to its end, one record out.

@@ -67,11 +67,11 @@ def table_ops(n_hist, n_tent, n_kahn, n_real, cost=None):
 # counters read for a plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); keyed
 # by a hash of the kernel sources so a changed kernel reports null.
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
-TRAFFIC_KIB = {"8d6b6c2aa1e02935": {"fetch": 5949.75, "write": 4983.75}}
+TRAFFIC_KIB = {"41e99e466d98bbf3": {"fetch": 5952.31, "write": 4983.38}}
 # rocprofv3 --pmc SQ_INSTS_VALU of the same launch (and the dispatch time of
 # that run), keyed like the traffic
-VALU_COUNTERS = {"8d6b6c2aa1e02935": {"workload": "thorax_128", "SQ_INSTS_VALU": 1.91408e9,
-                                      "kernel_ms": 3.9601}}
+VALU_COUNTERS = {"41e99e466d98bbf3": {"workload": "thorax_128", "SQ_INSTS_VALU": 1.89687e9,
+                                      "kernel_ms": 3.8994}}
 
 
 def kernel_source_hash() -> str:

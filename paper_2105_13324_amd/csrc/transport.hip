@@ -160,6 +160,7 @@ constexpr int WAVES_PER_BLOCK_MAX = 4;    // 256 threads
 struct EmitRec {
     float x, y, z, dx, dy, dz;
     uint32_t voxel, view, hist;
+    float vc, vs;       // the view's detector normal, read in the converged emission phase
 };
 
 constexpr uint32_t FD_RING = 128;         // forced-detection queue per wave
@@ -411,6 +412,8 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                             EmitRec r;
                             r.x = e.x; r.y = e.y; r.z = e.z; r.dx = e.dx; r.dy = e.dy; r.dz = e.dz;
                             r.voxel = e.voxel; r.view = (uint32_t)v; r.hist = (uint32_t)h;
+                            const float2 cs = ldg(C.views + v);
+                            r.vc = cs.x; r.vs = cs.y;
                             my[idx] = r;
                             if constexpr (FD) {
                                 q.x = e.x; q.y = e.y; q.z = e.z;
@@ -453,6 +456,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
             e.x = r.x; e.y = r.y; e.z = r.z; e.dx = r.dx; e.dy = r.dy; e.dz = r.dz;
             e.voxel = r.voxel;
             begin_history(C, L, r.view, r.hist, e);
+            L.vc = r.vc; L.vs = r.vs;     // staged: no global load at the history's start
             if (vr_dir) L.w = 0.5f * T.vr_omc;     // Omega / (4 pi)
         }
         MC_REGION(RG_EXIT_TEST);
@@ -477,7 +481,8 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                         atomicAdd((unsigned long long*)(T.energy + (size_t)p * 4 + 2),
                                   (unsigned long long)to_q23(out));
                 } else {
-                    e_esc += to_q23(out);
+                    // Q40.23 as to_q23, zero-extended: the energy is never negative
+                    e_esc += (long long)(uint32_t)__float2int_rn(out * 8388608.0f);
                 }
             }
         }

@@ -67,11 +67,11 @@ def table_ops(n_hist, n_tent, n_kahn, n_real, cost=None):
 # counters read for a plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); keyed
 # by a hash of the kernel sources so a changed kernel reports null.
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
-TRAFFIC_KIB = {"41e99e466d98bbf3": {"fetch": 5952.31, "write": 4983.38}}
+TRAFFIC_KIB = {"c0161dea242dbf20": {"fetch": 5943.88, "write": 4983.75}}
 # rocprofv3 --pmc SQ_INSTS_VALU of the same launch (and the dispatch time of
 # that run), keyed like the traffic
-VALU_COUNTERS = {"41e99e466d98bbf3": {"workload": "thorax_128", "SQ_INSTS_VALU": 1.89687e9,
-                                      "kernel_ms": 3.8994}}
+VALU_COUNTERS = {"c0161dea242dbf20": {"workload": "thorax_128", "SQ_INSTS_VALU": 1.89764e9,
+                                      "kernel_ms": 3.8693}}
 
 
 def kernel_source_hash() -> str:

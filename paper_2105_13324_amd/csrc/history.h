@@ -133,6 +133,19 @@ __device__ inline float kn_ratio(const Cst& C, float e) {
     return fmaf(fr, k1 - k0, k0);
 }
 
+// The same, given the KN table pair and fraction of e (read earlier).
+__device__ inline float energy_terms_kn(const Cst& C, float e, float fr, float k0, float k1, float& ln2_mm,
+                                        float& p_pe) {
+    const float kn = fmaf(fr, k1 - k0, k0);
+    const float x = 140.0f * rcpf(e);
+    const float pe = C.f_pe * x * x * x;
+    const float g = fmaf(1.0f - C.f_pe, kn, pe);
+    const float ig = rcpf(g);
+    ln2_mm = C.ln2_mu * ig;
+    p_pe = pe * ig;
+    return g;
+}
+
 __device__ inline float energy_terms(const Cst& C, float e, float& ln2_mm, float& p_pe) {
     const float kn = kn_ratio(C, e);
     const float x = 140.0f * rcpf(e);
@@ -489,6 +502,7 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
     }
     // (2) Kahn's rejection sampler for x = E/E' on [1, 1+2k], k = E / m_e c^2
     bool new_energy = false;
+    float kn_fr, kn0, kn1;      // set with new_energy
     if (state == S_KAHN) {
         MC_REGION(RG_KAHN);
         A.n_kahn++;
@@ -512,6 +526,15 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
             MC_REGION(RG_KAHN_ACCEPT);
             const float ct = 1.0f - (xx - 1.0f) * ik;
             L.e = L.e * ixx;
+            {
+                // the KN table pair of the new energy, read before the
+                // rotation so the load is in flight during it
+                const float t = (C.e0 - L.e) * KN_TABLE_STEP_INV;
+                const int i = (int)t;
+                kn_fr = t - (float)i;
+                kn0 = ldg(C.kn_table + i);
+                kn1 = ldg(C.kn_table + i + 1);
+            }
             L.n_scatter += 1;
             rotate(L, ct, unif(L.phi_word));
             if (L.e < C.e_cut) {
@@ -542,7 +565,7 @@ __device__ inline int advance(const Cst& C, const uint32_t* pal, Lane& L, uint32
     // (4) flight scale and photoelectric share at the new energy
     if (new_energy) {
         MC_REGION(RG_ENERGY_TERMS);
-        energy_terms(C, L.e, L.ln2_mm, L.p_pe);
+        energy_terms_kn(C, L.e, kn_fr, kn0, kn1, L.ln2_mm, L.p_pe);
     }
     return fate;
 }

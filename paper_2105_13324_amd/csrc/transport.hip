@@ -299,6 +299,9 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                                                mc_event* __restrict__ ev_stage) {
     constexpr int EPL = emit_per_lane(MODE);
     constexpr int EBATCH = 64 * EPL;
+    // analog: two records of the emission loop at a time, so their table
+    // gathers overlap (the weighted kernel measured slower unrolled)
+    constexpr int EMIT_UNROLL = MODE == 0 ? 2 : 1;
     constexpr bool FD = MODE == 1 || MODE == 2;
     constexpr bool VR = MODE == 3;
     const bool vr_dir = VR && (T.vr_flags & VR_FORCED_DIRECTION);
@@ -401,7 +404,7 @@ __device__ __forceinline__ void transport_body(TransportArgs T, EmitRec* __restr
                     MC_REGION(RG_EMIT);
                     const uint32_t n_rec = (uint32_t)min((uint64_t)EBATCH, c_end - c_next);
                     if (fd_list && ev_count > EV_STAGE - EBATCH) flush_events(T, ev_stage, ev_count, lane);
-#pragma unroll 1
+#pragma unroll EMIT_UNROLL
                     for (int k = 0; k < EPL; ++k) {
                         const uint32_t idx = (uint32_t)(k * 64 + lane);
                         FdPoint q = {};

@@ -67,11 +67,11 @@ def table_ops(n_hist, n_tent, n_kahn, n_real, cost=None):
 # counters read for a plain 1 GiB device copy (FETCH x2.0, WRITE x1.0); keyed
 # by a hash of the kernel sources so a changed kernel reports null.
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
-TRAFFIC_KIB = {"c0161dea242dbf20": {"fetch": 5943.88, "write": 4983.75}}
+TRAFFIC_KIB = {"a6209a920f84733f": {"fetch": 5967.5, "write": 4983.19}}
 # rocprofv3 --pmc SQ_INSTS_VALU of the same launch (and the dispatch time of
 # that run), keyed like the traffic
-VALU_COUNTERS = {"c0161dea242dbf20": {"workload": "thorax_128", "SQ_INSTS_VALU": 1.89764e9,
-                                      "kernel_ms": 3.8693}}
+VALU_COUNTERS = {"a6209a920f84733f": {"workload": "thorax_128", "SQ_INSTS_VALU": 1.90174e9,
+                                      "kernel_ms": 3.8077}}
 
 
 def kernel_source_hash() -> str:
